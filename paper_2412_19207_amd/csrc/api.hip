@@ -1,0 +1,560 @@
+// C entry points (include/rann_dd.h): validation, ownership, phase ordering.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace rdd {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+void dev_free(Handle& h, void* p) {
+    if (!p) return;
+    auto it = std::find(h.allocs.begin(), h.allocs.end(), p);
+    if (it != h.allocs.end()) {
+        h.allocs.erase(it);
+        (void)hipFree(p);
+    }
+}
+
+int ensure_ws(Handle& h, size_t bytes) {
+    if (h.ws_bytes >= bytes) return RANN_OK;
+    if (h.ws) dev_free(h, h.ws);
+    h.ws = nullptr;
+    h.ws_bytes = 0;
+    unsigned char* p = nullptr;
+    RDD_TRY(dev_alloc(h, &p, bytes + (bytes >> 3)));
+    h.ws = p;
+    h.ws_bytes = bytes + (bytes >> 3);
+    return RANN_OK;
+}
+
+namespace {
+
+__global__ void k_pad_features(int64_t sum_m, int d, const double* __restrict__ R,
+                               double* __restrict__ Rf) {
+    int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f >= sum_m) return;
+    for (int i = 0; i < 4; ++i) Rf[f * 4 + i] = (i < d) ? R[f * d + i] : 0.0;
+}
+
+__global__ void k_identity_V(const int32_t* __restrict__ m, const int64_t* __restrict__ v_off,
+                             double* __restrict__ V) {
+    const int j = blockIdx.x;
+    const int mj = m[j];
+    for (int64_t e = threadIdx.x; e < (int64_t)mj * mj; e += blockDim.x)
+        V[v_off[j] + e] = ((e / mj) == (e % mj)) ? 1.0 : 0.0;
+}
+
+__global__ void k_concat_points(int64_t n_int, int64_t n_bnd, int d, const double* __restrict__ Xi,
+                                const double* __restrict__ Xb, double* __restrict__ X) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t tot = (n_int + n_bnd) * d;
+    if (idx >= tot) return;
+    X[idx] = (idx < n_int * d) ? Xi[idx] : Xb[idx - n_int * d];
+}
+
+__global__ void k_scale_tail(int64_t row0, int64_t rows, int k, double f, double* __restrict__ a) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx < rows * k) a[row0 * k + idx] *= f;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int validate_opts(const rann_dd_solve_opts* o) {
+    if (!o) {
+        set_error("opts is NULL");
+        return RANN_EINVAL;
+    }
+    if (!(o->tol > 0.0) || o->maxiter < 1 || o->check_every < 1 ||
+        (o->method != RANN_METHOD_CG && o->method != RANN_METHOD_GMRES) ||
+        (o->method == RANN_METHOD_GMRES && (o->restart < 1 || o->restart > 128))) {
+        set_error("invalid solve options");
+        return RANN_EINVAL;
+    }
+    return RANN_OK;
+}
+
+}  // namespace
+
+static int assemble_impl(const rann_dd_desc* ds, void* stream, Handle*& hp) {
+    if (!ds) {
+        set_error("desc is NULL");
+        return RANN_EINVAL;
+    }
+    const int d = ds->d;
+    if (d < 1 || d > kMaxDim) {
+        set_error("d must be 1..4");
+        return RANN_EINVAL;
+    }
+    int64_t J = 1, sum_l = 0;
+    for (int i = 0; i < d; ++i) {
+        if (ds->l[i] < 1 || ds->l[i] > 4096) {
+            set_error("l[i] must be 1..4096");
+            return RANN_EINVAL;
+        }
+        if (!(ds->sigma[i] > 0.0) || !std::isfinite(ds->sigma[i])) {
+            set_error("sigma[i] must be positive and finite");
+            return RANN_EINVAL;
+        }
+        J *= ds->l[i];
+        sum_l += ds->l[i];
+    }
+    if (J > (1 << 20)) {
+        set_error("too many subdomains");
+        return RANN_EINVAL;
+    }
+    if (!ds->mu || !ds->m || !ds->R || !ds->b || !ds->X_int || !ds->a || !ds->beta || !ds->c ||
+        ds->n_int < 1 || ds->n_bnd < 0 || (ds->n_bnd > 0 && !ds->X_bnd)) {
+        set_error("missing array or empty point set in the descriptor");
+        return RANN_EINVAL;
+    }
+    if (!(ds->lambda_B > 0.0) || !std::isfinite(ds->lambda_B)) {
+        set_error("lambda_B must be positive and finite");
+        return RANN_EINVAL;
+    }
+    if (ds->precision != RANN_FP64 && ds->precision != RANN_MIXED) {
+        set_error("precision must be RANN_FP64 or RANN_MIXED");
+        return RANN_EINVAL;
+    }
+    if (ds->stencil < RANN_STENCIL_SELF || ds->stencil > RANN_STENCIL_FULL ||
+        ds->precond < RANN_PRECOND_NONE || ds->precond > RANN_PRECOND_SAS) {
+        set_error("invalid stencil or preconditioner");
+        return RANN_EINVAL;
+    }
+    {
+        int64_t off = 0;
+        for (int i = 0; i < d; ++i) {
+            for (int c = 0; c < ds->l[i]; ++c) {
+                double v = ds->mu[off + c];
+                if (!std::isfinite(v) || (c > 0 && !(v > ds->mu[off + c - 1]))) {
+                    set_error("centres must be finite and strictly increasing per dimension");
+                    return RANN_EINVAL;
+                }
+            }
+            off += ds->l[i];
+        }
+    }
+    for (int64_t j = 0; j < J; ++j) {
+        if (ds->m[j] < 1 || ds->m[j] > kMaxWidth) {
+            set_error("hidden widths must be 1..1024");
+            return RANN_EINVAL;
+        }
+    }
+    Handle* h = new Handle();
+    hp = h;
+    h->stream = static_cast<hipStream_t>(stream);
+    RDD_HIP(hipGetDevice(&h->device));
+    Geo& g = h->geo;
+    g.d = d;
+    g.J = (int)J;
+    int off = 0;
+    for (int i = 0; i < kMaxDim; ++i) {
+        g.l[i] = (i < d) ? ds->l[i] : 1;
+        g.mu_off[i] = (i < d) ? off : 0;
+        if (i < d) off += ds->l[i];
+        g.sigma[i] = (i < d) ? ds->sigma[i] : 1.0;
+        g.inv_sigma[i] = 1.0 / g.sigma[i];
+    }
+    h->lambda_B = ds->lambda_B;
+    h->precision = ds->precision;
+    h->stencil = ds->stencil;
+    h->precond = ds->precond;
+    h->n_int = ds->n_int;
+    h->n_bnd = ds->n_bnd;
+    h->N = ds->n_int + ds->n_bnd;
+    h->m.assign(ds->m, ds->m + J);
+    h->m_off.assign(J + 1, 0);
+    for (int64_t j = 0; j < J; ++j) h->m_off[j + 1] = h->m_off[j] + h->m[j];
+    h->sum_m = h->m_off[J];
+    RDD_TRY(dev_alloc(*h, &h->d_mu, (size_t)sum_l));
+    RDD_HIP(hipMemcpy(h->d_mu, ds->mu, sizeof(double) * sum_l, hipMemcpyHostToDevice));
+    RDD_TRY(dev_alloc(*h, &h->d_m, (size_t)J));
+    RDD_TRY(dev_alloc(*h, &h->d_m_off, (size_t)J + 1));
+    RDD_HIP(hipMemcpy(h->d_m, h->m.data(), sizeof(int32_t) * J, hipMemcpyHostToDevice));
+    RDD_HIP(hipMemcpy(h->d_m_off, h->m_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+    RDD_TRY(dev_alloc(*h, &h->d_Rf, (size_t)h->sum_m * 4));
+    RDD_TRY(dev_alloc(*h, &h->d_bf, (size_t)h->sum_m));
+    hipLaunchKernelGGL(k_pad_features, dim3((unsigned)((h->sum_m + 255) / 256)), dim3(256), 0,
+                       h->stream, h->sum_m, d, ds->R, h->d_Rf);
+    RDD_HIP(hipGetLastError());
+    RDD_HIP(hipMemcpyAsync(h->d_bf, ds->b, sizeof(double) * h->sum_m, hipMemcpyDeviceToDevice,
+                           h->stream));
+    // points (interior then boundary) and operator coefficients
+    double *X = nullptr, *a = nullptr, *be = nullptr, *c = nullptr, *Lf = nullptr;
+    RDD_TRY(dev_alloc(*h, &X, (size_t)h->N * d));
+    hipLaunchKernelGGL(k_concat_points, dim3((unsigned)((h->N * d + 255) / 256)), dim3(256), 0,
+                       h->stream, h->n_int, h->n_bnd, d, ds->X_int, ds->X_bnd, X);
+    RDD_HIP(hipGetLastError());
+    RDD_TRY(dev_alloc(*h, &a, (size_t)h->n_int * d));
+    RDD_TRY(dev_alloc(*h, &be, (size_t)h->n_int * d));
+    RDD_TRY(dev_alloc(*h, &c, (size_t)h->n_int));
+    RDD_HIP(hipMemcpyAsync(a, ds->a, sizeof(double) * h->n_int * d, hipMemcpyDeviceToDevice, h->stream));
+    RDD_HIP(hipMemcpyAsync(be, ds->beta, sizeof(double) * h->n_int * d, hipMemcpyDeviceToDevice,
+                           h->stream));
+    RDD_HIP(hipMemcpyAsync(c, ds->c, sizeof(double) * h->n_int, hipMemcpyDeviceToDevice, h->stream));
+    if (ds->Lfun) {
+        RDD_TRY(dev_alloc(*h, &Lf, (size_t)h->N * (1 + 2 * d)));
+        RDD_HIP(hipMemcpyAsync(Lf, ds->Lfun, sizeof(double) * h->N * (1 + 2 * d),
+                               hipMemcpyDeviceToDevice, h->stream));
+    }
+    RDD_TRY(bin_points(*h, X, h->N, h->pts));
+    RDD_TRY(pair_records(*h, X, h->n_int, a, be, c, Lf, h->N, h->lambda_B, false, nullptr, h->pts));
+    RDD_HIP(hipStreamSynchronize(h->stream));
+    // the pair records carry everything later phases need
+    dev_free(*h, a);
+    dev_free(*h, be);
+    dev_free(*h, c);
+    if (Lf) dev_free(*h, Lf);
+    dev_free(*h, X);
+    return RANN_OK;
+}
+
+static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, const double* V_force,
+                    int32_t* p_out) {
+    if (h.pca_done) {
+        set_error("rann_dd_pca was already called on this handle");
+        return RANN_EINVAL;
+    }
+    if (mode < RANN_PCA_REL_EIG || mode > RANN_PCA_OFF || (mode != RANN_PCA_OFF && !(tol > 0.0))) {
+        set_error("invalid PCA mode or threshold");
+        return RANN_EINVAL;
+    }
+    if (V_force && !p_force) {
+        set_error("V_force requires p_force");
+        return RANN_EINVAL;
+    }
+    const int J = h.geo.J;
+    int warn = RANN_OK;
+    h.p.assign(J, 0);
+    std::vector<int64_t> g_off(J + 1, 0);
+    for (int j = 0; j < J; ++j) g_off[j + 1] = g_off[j] + (int64_t)h.m[j] * h.m[j];
+    RDD_TRY(dev_alloc(h, &h.d_p, J));
+    RDD_TRY(dev_alloc(h, &h.d_eig, (size_t)h.sum_m));
+    double* Vfull = nullptr;
+    int64_t* d_g_off = nullptr;
+    if (mode != RANN_PCA_OFF && !V_force) {
+        double *G = nullptr, *Z = nullptr;
+        int32_t* flags = nullptr;
+        RDD_TRY(dev_alloc(h, &G, (size_t)g_off[J]));
+        RDD_TRY(dev_alloc(h, &Z, (size_t)g_off[J]));
+        RDD_TRY(dev_alloc(h, &d_g_off, (size_t)J + 1));
+        RDD_TRY(dev_alloc(h, &flags, 2));
+        RDD_HIP(hipMemcpy(d_g_off, g_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+        RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, h.stream));
+        RDD_TRY(pca_gram(h, G, g_off.data(), d_g_off));
+        RDD_TRY(eig_batched(h, G, d_g_off, Z, tol, mode, h.d_p, h.d_eig, flags));
+        int32_t fl[2];
+        RDD_HIP(hipMemcpy(fl, flags, sizeof(fl), hipMemcpyDeviceToHost));
+        RDD_HIP(hipMemcpy(h.p.data(), h.d_p, sizeof(int32_t) * J, hipMemcpyDeviceToHost));
+        dev_free(h, Z);
+        dev_free(h, flags);
+        if (fl[0]) {
+            dev_free(h, G);
+            set_error("symmetric eigensolver did not converge");
+            return RANN_EDEVICE;
+        }
+        if (fl[1]) warn = RANN_WRANKTIE;
+        Vfull = G;
+    } else {
+        for (int j = 0; j < J; ++j) h.p[j] = h.m[j];
+        RDD_HIP(hipMemsetAsync(h.d_eig, 0, sizeof(double) * h.sum_m, h.stream));
+    }
+    if (p_force) {
+        for (int j = 0; j < J; ++j) {
+            if (p_force[j] < 1 || p_force[j] > h.m[j]) {
+                set_error("p_force entries must be 1..m_j");
+                return RANN_EINVAL;
+            }
+            h.p[j] = p_force[j];
+        }
+    }
+    RDD_HIP(hipMemcpy(h.d_p, h.p.data(), sizeof(int32_t) * J, hipMemcpyHostToDevice));
+    h.col_off.assign(J + 1, 0);
+    h.v_off.assign(J + 1, 0);
+    h.h_off.assign(J + 1, 0);
+    for (int j = 0; j < J; ++j) {
+        h.col_off[j + 1] = h.col_off[j] + h.p[j];
+        h.v_off[j + 1] = h.v_off[j] + (int64_t)h.m[j] * h.p[j];
+        h.h_off[j + 1] = h.h_off[j] + (h.pts.row_off[j + 1] - h.pts.row_off[j]) * h.p[j];
+    }
+    h.P = h.col_off[J];
+    h.nnz = h.h_off[J];
+    RDD_TRY(dev_alloc(h, &h.d_col_off, J + 1));
+    RDD_TRY(dev_alloc(h, &h.d_v_off, J + 1));
+    RDD_TRY(dev_alloc(h, &h.d_h_off, J + 1));
+    RDD_HIP(hipMemcpy(h.d_col_off, h.col_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+    RDD_HIP(hipMemcpy(h.d_v_off, h.v_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+    RDD_HIP(hipMemcpy(h.d_h_off, h.h_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+    RDD_TRY(dev_alloc(h, &h.d_V, (size_t)h.v_off[J]));
+    if (V_force) {
+        RDD_HIP(hipMemcpyAsync(h.d_V, V_force, sizeof(double) * h.v_off[J], hipMemcpyDeviceToDevice,
+                               h.stream));
+    } else if (Vfull) {
+        RDD_TRY(compact_V(h, Vfull, d_g_off, h.d_V));
+    } else {
+        hipLaunchKernelGGL(k_identity_V, dim3(J), dim3(256), 0, h.stream, h.d_m, h.d_v_off, h.d_V);
+        RDD_HIP(hipGetLastError());
+    }
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    if (Vfull) dev_free(h, Vfull);
+    if (d_g_off) dev_free(h, d_g_off);
+    // operator rows in the PCA basis
+    RDD_TRY(dev_alloc(h, &h.d_H, (size_t)h.nnz));
+    if (h.precision == RANN_MIXED) RDD_TRY(dev_alloc(h, &h.d_H32, (size_t)h.nnz));
+    RDD_TRY(feature_rows(h));
+    RDD_TRY(plan_products(h));
+    RDD_TRY(build_schwarz(h));
+    if (p_out) std::copy(h.p.begin(), h.p.end(), p_out);
+    h.pca_done = true;
+    return warn;
+}
+
+}  // namespace rdd
+
+using rdd::Handle;
+
+struct rann_dd_handle {
+    Handle h;
+};
+
+static int guard_handle(const rann_dd_handle* hh, bool need_pca) {
+    if (!hh) {
+        rdd::set_error("handle is NULL");
+        return RANN_EINVAL;
+    }
+    if (need_pca && !hh->h.pca_done) {
+        rdd::set_error("rann_dd_pca has not been called on this handle");
+        return RANN_EINVAL;
+    }
+    return RANN_OK;
+}
+
+extern "C" {
+
+const char* rann_dd_last_error(void) { return rdd::g_last_error.c_str(); }
+
+int rann_dd_assemble(const rann_dd_desc* desc, void* hip_stream, rann_dd_handle** out) {
+    if (!out) {
+        rdd::set_error("out is NULL");
+        return RANN_EINVAL;
+    }
+    *out = nullptr;
+    rdd::g_last_error.clear();
+    auto t0 = std::chrono::steady_clock::now();
+    Handle* raw = nullptr;
+    int rc = rdd::assemble_impl(desc, hip_stream, raw);
+    if (rc < 0) {
+        if (raw) {
+            for (void* p : raw->allocs) (void)hipFree(p);
+            delete raw;
+        }
+        return rc;
+    }
+    auto* hh = new rann_dd_handle();
+    hh->h = std::move(*raw);
+    delete raw;
+    hh->h.setup_ms[0] = rdd::ms_since(t0);
+    *out = hh;
+    return RANN_OK;
+}
+
+int rann_dd_pca(rann_dd_handle* hh, double tol, int32_t mode, const int32_t* p_force,
+                const double* V_force, int32_t* p_out) {
+    RDD_TRY(guard_handle(hh, false));
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = rdd::pca_impl(hh->h, tol, mode, p_force, V_force, p_out);
+    hh->h.setup_ms[1] = rdd::ms_since(t0);
+    return rc;
+}
+
+int rann_dd_solve(rann_dd_handle* hh, const double* F, int32_t k, const double* W0,
+                  const rann_dd_solve_opts* opts, double* W, rann_dd_stats* st) {
+    RDD_TRY(guard_handle(hh, true));
+    RDD_TRY(rdd::validate_opts(opts));
+    Handle& h = hh->h;
+    if (!F || !W || k < 1 || k > 256) {
+        rdd::set_error("F and W must be given and 1 <= k <= 256");
+        return RANN_EINVAL;
+    }
+    double* Fs = nullptr;
+    RDD_TRY(rdd::dev_alloc(h, &Fs, (size_t)h.N * k));
+    int rc = rdd::scale_boundary(h, F, k, Fs, h.lambda_B);
+    int status = RANN_OK;
+    if (rc == RANN_OK) {
+        if (opts->method == RANN_METHOD_CG)
+            rc = rdd::krylov_cg(h, Fs, k, W0, *opts, W, st, &status);
+        else
+            rc = rdd::krylov_gmres(h, Fs, k, W0, *opts, W, st, &status);
+    }
+    rdd::dev_free(h, Fs);
+    if (rc < 0) return rc;
+    return status;
+}
+
+int rann_dd_solve_backward(rann_dd_handle* hh, const double* dW, int32_t k,
+                           const rann_dd_solve_opts* opts, double* dF, rann_dd_stats* st) {
+    RDD_TRY(guard_handle(hh, true));
+    RDD_TRY(rdd::validate_opts(opts));
+    Handle& h = hh->h;
+    if (!dW || !dF || k < 1 || k > 256) {
+        rdd::set_error("dW and dF must be given and 1 <= k <= 256");
+        return RANN_EINVAL;
+    }
+    double* z = nullptr;
+    RDD_TRY(rdd::dev_alloc(h, &z, (size_t)h.P * k));
+    int status = RANN_OK;
+    int rc = (opts->method == RANN_METHOD_CG) ? rdd::adjoint_cg(h, dW, k, *opts, z, st, &status)
+                                              : rdd::adjoint_gmres(h, dW, k, *opts, z, st, &status);
+    if (rc == RANN_OK) rc = rdd::launch_Hx(h, z, k, dF, false);
+    if (rc == RANN_OK && h.n_bnd > 0) {
+        hipLaunchKernelGGL(rdd::k_scale_tail, dim3((unsigned)((h.n_bnd * k + 255) / 256)), dim3(256), 0,
+                           h.stream, h.n_int, h.n_bnd, k, h.lambda_B, dF);
+        if (hipGetLastError() != hipSuccess) rc = RANN_EDEVICE;
+    }
+    if (rc == RANN_OK && st) {
+        if (hipStreamSynchronize(h.stream) != hipSuccess) rc = RANN_EDEVICE;
+    }
+    rdd::dev_free(h, z);
+    if (rc < 0) return rc;
+    return status;
+}
+
+int rann_dd_eval(rann_dd_handle* hh, const double* Xq, int64_t M, const double* Lq, const double* W,
+                 int32_t k, double* U) {
+    RDD_TRY(guard_handle(hh, true));
+    if (!Xq || !W || !U || M < 1 || k < 1 || k > 256) {
+        rdd::set_error("invalid eval arguments");
+        return RANN_EINVAL;
+    }
+    return rdd::eval_points(hh->h, Xq, M, Lq, W, k, U, false);
+}
+
+int rann_dd_eval_T(rann_dd_handle* hh, const double* Xq, int64_t M, const double* Lq,
+                   const double* dU, int32_t k, double* dW) {
+    RDD_TRY(guard_handle(hh, true));
+    if (!Xq || !dU || !dW || M < 1 || k < 1 || k > 256) {
+        rdd::set_error("invalid eval_T arguments");
+        return RANN_EINVAL;
+    }
+    return rdd::eval_points(hh->h, Xq, M, Lq, dU, k, dW, true);
+}
+
+int rann_dd_coeffs(rann_dd_handle* hh, const double* W, int32_t k, double* c) {
+    RDD_TRY(guard_handle(hh, true));
+    if (!W || !c || k < 1) {
+        rdd::set_error("invalid coeffs arguments");
+        return RANN_EINVAL;
+    }
+    RDD_TRY(rdd::coeffs_raw(hh->h, W, k, c, false));
+    RDD_HIP(hipStreamSynchronize(hh->h.stream));
+    return RANN_OK;
+}
+
+int rann_dd_matvec(rann_dd_handle* hh, const double* x, int32_t k, double* y) {
+    RDD_TRY(guard_handle(hh, true));
+    if (!x || !y || k < 1) return (rdd::set_error("invalid matvec arguments"), RANN_EINVAL);
+    RDD_TRY(rdd::launch_Hx(hh->h, x, k, y, false));
+    RDD_HIP(hipStreamSynchronize(hh->h.stream));
+    return RANN_OK;
+}
+
+int rann_dd_rmatvec(rann_dd_handle* hh, const double* y, int32_t k, double* x) {
+    RDD_TRY(guard_handle(hh, true));
+    Handle& h = hh->h;
+    if (!x || !y || k < 1) return (rdd::set_error("invalid rmatvec arguments"), RANN_EINVAL);
+    double* part = nullptr;
+    RDD_TRY(rdd::dev_alloc(h, &part, (size_t)h.part_total * k));
+    int rc = rdd::launch_HTy(h, y, k, x, part);
+    if (rc == RANN_OK && hipStreamSynchronize(h.stream) != hipSuccess) rc = RANN_EDEVICE;
+    rdd::dev_free(h, part);
+    return rc;
+}
+
+int rann_dd_apply_normal(rann_dd_handle* hh, const double* x, int32_t k, double* s) {
+    RDD_TRY(guard_handle(hh, true));
+    Handle& h = hh->h;
+    if (!x || !s || k < 1) return (rdd::set_error("invalid apply_normal arguments"), RANN_EINVAL);
+    double *y = nullptr, *part = nullptr;
+    RDD_TRY(rdd::dev_alloc(h, &y, (size_t)h.N * k));
+    RDD_TRY(rdd::dev_alloc(h, &part, (size_t)h.part_total * k));
+    int rc = rdd::launch_Hx(h, x, k, y, false);
+    if (rc == RANN_OK) rc = rdd::launch_HTy(h, y, k, s, part);
+    if (rc == RANN_OK && hipStreamSynchronize(h.stream) != hipSuccess) rc = RANN_EDEVICE;
+    rdd::dev_free(h, y);
+    rdd::dev_free(h, part);
+    return rc;
+}
+
+int rann_dd_apply_precond(rann_dd_handle* hh, const double* r, int32_t k, double* z) {
+    RDD_TRY(guard_handle(hh, true));
+    Handle& h = hh->h;
+    if (!r || !z || k < 1) return (rdd::set_error("invalid apply_precond arguments"), RANN_EINVAL);
+    double* ub = nullptr;
+    RDD_TRY(rdd::dev_alloc(h, &ub, (size_t)std::max<int64_t>(h.ub_total, 1) * k));
+    int rc = rdd::launch_precond(h, r, k, z, ub);
+    if (rc == RANN_OK && hipStreamSynchronize(h.stream) != hipSuccess) rc = RANN_EDEVICE;
+    rdd::dev_free(h, ub);
+    return rc;
+}
+
+int rann_dd_get_info(const rann_dd_handle* hh, rann_dd_info* out) {
+    RDD_TRY(guard_handle(hh, false));
+    if (!out) return (rdd::set_error("out is NULL"), RANN_EINVAL);
+    const Handle& h = hh->h;
+    out->d = h.geo.d;
+    out->J = h.geo.J;
+    out->N_int = h.n_int;
+    out->N_bnd = h.n_bnd;
+    out->N = h.N;
+    out->P = h.P;
+    out->pairs = h.pts.pairs;
+    out->nnz = h.nnz;
+    out->sum_m = h.sum_m;
+    out->factor_elems = h.factor_elems;
+    out->max_q = h.max_q;
+    out->pca_done = h.pca_done ? 1 : 0;
+    return RANN_OK;
+}
+
+int rann_dd_get_layout(const rann_dd_handle* hh, int64_t* row_off, int32_t* rows, int32_t* p) {
+    RDD_TRY(guard_handle(hh, false));
+    const Handle& h = hh->h;
+    if (row_off) std::copy(h.pts.row_off.begin(), h.pts.row_off.end(), row_off);
+    if (rows && h.pts.pairs > 0)
+        RDD_HIP(hipMemcpy(rows, h.pts.d_rows, sizeof(int32_t) * h.pts.pairs, hipMemcpyDeviceToHost));
+    if (p) {
+        if (!h.pca_done) return (rdd::set_error("p is known after rann_dd_pca"), RANN_EINVAL);
+        std::copy(h.p.begin(), h.p.end(), p);
+    }
+    return RANN_OK;
+}
+
+int rann_dd_get_arrays(const rann_dd_handle* hh, double* blocks, double* V, double* eig) {
+    RDD_TRY(guard_handle(hh, true));
+    const Handle& h = hh->h;
+    if (blocks) RDD_HIP(hipMemcpy(blocks, h.d_H, sizeof(double) * h.nnz, hipMemcpyDeviceToDevice));
+    if (V) RDD_HIP(hipMemcpy(V, h.d_V, sizeof(double) * h.v_off.back(), hipMemcpyDeviceToDevice));
+    if (eig) RDD_HIP(hipMemcpy(eig, h.d_eig, sizeof(double) * h.sum_m, hipMemcpyDeviceToDevice));
+    return RANN_OK;
+}
+
+void rann_dd_destroy(rann_dd_handle* hh) {
+    if (!hh) return;
+    (void)hipStreamSynchronize(hh->h.stream);
+    for (void* p : hh->h.allocs) (void)hipFree(p);
+    hh->h.allocs.clear();
+    delete hh;
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+// Shared definitions of the RaNN overlapping-Schwarz library (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rann_dd.h"
+
+namespace rdd {
+
+constexpr int kMaxDim = 4;
+constexpr int kMaxWidth = 1024;     // hidden width limit per subdomain
+constexpr int kPairRec = 16;        // doubles per (point, subdomain) record
+// pair record layout: [0..3] normalised coordinates, [4] window value w_j,
+// [5] P0, [6..9] P1_i, [10..13] P2_i (operator row = P0 t + (sum P1_i rho_i) s
+// - 2 (sum P2_i rho_i^2) t s with t = tanh z, s = 1 - t^2, rho_i = R_i / sigma_i)
+constexpr int kRecX = 0, kRecW = 4, kRecP0 = 5, kRecP1 = 6, kRecP2 = 10;
+constexpr double kEdge = 1.0 - 1e-12;  // strict support test factor
+
+struct Geo {                 // passed by value to kernels
+    int d;
+    int l[kMaxDim];
+    int mu_off[kMaxDim];     // offset of dimension i's centres in the mu array
+    double sigma[kMaxDim];
+    double inv_sigma[kMaxDim];
+    int J;
+};
+
+// A point set binned into the subdomain supports: the row sets S_j, the
+// (row -> pairs) map, and one record per (point, subdomain) pair.
+struct PointSet {
+    int64_t n = 0;                 // points
+    int64_t pairs = 0;             // sum_j n_j
+    std::vector<int64_t> row_off;  // host J+1
+    int64_t* d_row_off = nullptr;  // device J+1
+    int32_t* d_rows = nullptr;     // device pairs: global row of each pair (S_j concatenated)
+    int32_t* d_pair_sub = nullptr; // device pairs: subdomain of each pair
+    int64_t* d_cover_off = nullptr;// device n+1: pairs of each point (CSR)
+    int64_t* d_cover = nullptr;    // device: pair ids, ascending subdomain order
+    double* d_rec = nullptr;       // device pairs x kPairRec
+    int max_cover = 0;
+};
+
+struct Handle {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Geo geo{};
+    double lambda_B = 1.0;
+    int precision = RANN_FP64, stencil = RANN_STENCIL_FULL, precond = RANN_PRECOND_AS;
+    int64_t n_int = 0, n_bnd = 0, N = 0;
+    std::vector<int32_t> m;        // host widths
+    std::vector<int64_t> m_off;    // host J+1
+    int64_t sum_m = 0;
+    double* d_mu = nullptr;        // device sum(l)
+    double* d_Rf = nullptr;        // device sum_m x 4 (padded)
+    double* d_bf = nullptr;        // device sum_m
+    int64_t* d_m_off = nullptr;    // device J+1
+    int32_t* d_m = nullptr;        // device J
+    PointSet pts;                  // collocation points
+
+    // PCA
+    bool pca_done = false;
+    std::vector<int32_t> p;        // host J
+    std::vector<int64_t> col_off;  // host J+1
+    std::vector<int64_t> v_off;    // host J+1 (sum m_j p_j)
+    std::vector<int64_t> h_off;    // host J+1 (sum n_j p_j)
+    int64_t P = 0, nnz = 0;
+    int32_t* d_p = nullptr;
+    int64_t* d_col_off = nullptr;
+    int64_t* d_v_off = nullptr;
+    int64_t* d_h_off = nullptr;
+    double* d_eig = nullptr;       // sum m_j, descending
+    double* d_V = nullptr;         // sum m_j p_j
+    double* d_H = nullptr;         // nnz FP64
+    float* d_H32 = nullptr;        // nnz FP32 (mixed)
+
+    // Schwarz blocks
+    std::vector<std::vector<int>> sten;  // stencil of each block (ascending)
+    std::vector<int64_t> q;        // block sizes
+    std::vector<int64_t> f_off;    // J+1 offsets of q_i^2 factor storage
+    int64_t factor_elems = 0;
+    int max_q = 0;
+    double* d_M64 = nullptr;       // local inverses FP64 (q_i x q_i each)
+    float* d_M32 = nullptr;        // FP32 (mixed)
+    int64_t* d_f_off = nullptr;
+    int64_t* d_q = nullptr;
+    int64_t* d_ub_off = nullptr;   // J+1 offsets of per-block local vectors (sum q_i)
+    int32_t* d_blk_cols = nullptr; // sum q_i: global column of each block entry
+    // gather form of the AS sum: for each global column, the (block entry) list
+    int64_t* d_gat_off = nullptr;  // P+1
+    int64_t* d_gat = nullptr;      // entries
+    double* d_gat_w = nullptr;     // weights (AS 1, SAS 1/mult, RAS ownership)
+    int32_t shifts = 0;
+    int64_t prec_rows = 0;         // local-solve rows applied per preconditioner call
+    int64_t* d_prec_row_start = nullptr;
+    int64_t* d_prec_row_blk_off = nullptr;
+    int32_t* d_prec_row_blk = nullptr;
+    int64_t ub_total = 0;          // sum q_i
+
+    // H^T y: row chunks of each block, partial sums per chunk
+    std::vector<int64_t> chunk_off; // J+1 (chunks per subdomain)
+    int64_t n_chunks = 0, n_tasks = 0, part_total = 0;
+    int64_t* d_chunk_off = nullptr; // J+1
+    int32_t* d_chunk_sub = nullptr; // n_chunks: subdomain of each chunk
+    int64_t* d_part_off = nullptr;  // n_chunks: column offset of each chunk's partial
+    int32_t* d_tasks = nullptr;     // n_tasks x 2: (chunk, 64-column block)
+    int32_t* d_col_sub = nullptr;   // P: subdomain of each column
+    int32_t* d_feat_sub = nullptr;  // sum_m: subdomain of each hidden feature
+
+    // workspace (grows on demand)
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    void* ws2 = nullptr;           // true-residual scratch
+    size_t ws2_bytes = 0;
+    double* pinned = nullptr;      // host pinned scalars
+
+    double setup_ms[4] = {0, 0, 0, 0};  // assemble, pca+factor host-clock times
+
+    std::vector<void*> allocs;     // everything to free
+};
+
+// ---------------------------------------------------------------------------
+// error handling
+void set_error(const std::string& msg);
+
+#define RDD_HIP(call)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess) {                                                \
+            ::rdd::set_error(std::string(#call) + ": " + hipGetErrorString(e_)); \
+            return RANN_EDEVICE;                                               \
+        }                                                                      \
+    } while (0)
+
+#define RDD_TRY(call)                                                          \
+    do {                                                                       \
+        int r_ = (call);                                                       \
+        if (r_ < 0) return r_;                                                 \
+    } while (0)
+
+template <class T>
+int dev_alloc(Handle& h, T** ptr, size_t count) {
+    *ptr = nullptr;
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+        set_error("hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " +
+                  hipGetErrorString(e));
+        return RANN_ENOMEM;
+    }
+    h.allocs.push_back(p);
+    *ptr = static_cast<T*>(p);
+    return RANN_OK;
+}
+
+void dev_free(Handle& h, void* p);
+int ensure_ws(Handle& h, size_t bytes);
+
+// ---------------------------------------------------------------------------
+// launchers (defined in the .hip files)
+int bin_points(Handle& h, const double* X, int64_t n, PointSet& ps);
+int pair_records(Handle& h, const double* X, int64_t n_int, const double* a,
+                 const double* beta, const double* c, const double* Lfun, int64_t n_all,
+                 double lambda_B, bool value_rows_only, const double* Lq, PointSet& ps);
+int exclusive_scan_i64(Handle& h, const int64_t* in, int64_t* out, int64_t n);
+
+int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g_off);
+int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* Z, double tol, int mode,
+                int32_t* d_p, double* d_eig, int32_t* d_tie);
+int compact_V(Handle& h, const double* Z, const int64_t* d_g_off, double* V);
+int feature_rows(Handle& h);
+int build_schwarz(Handle& h);
+template <class T>
+int local_blocks(Handle& h, const T* H, T* A_out);
+int plan_products(Handle& h);
+
+int launch_Hx(Handle& h, const double* x, int k, double* y, bool scale_bnd);
+int launch_HTy(Handle& h, const double* y, int k, double* x, double* partial);
+int launch_precond(Handle& h, const double* r, int k, double* z, double* ub);
+
+int krylov_cg(Handle& h, const double* rhs, int k, const double* W0, const rann_dd_solve_opts& o,
+              double* W, rann_dd_stats* st, int* status);
+int adjoint_cg(Handle& h, const double* dW, int k, const rann_dd_solve_opts& o, double* z,
+               rann_dd_stats* st, int* status);
+int adjoint_gmres(Handle& h, const double* dW, int k, const rann_dd_solve_opts& o, double* z,
+                  rann_dd_stats* st, int* status);
+int krylov_gmres(Handle& h, const double* rhs, int k, const double* W0,
+                 const rann_dd_solve_opts& o, double* W, rann_dd_stats* st, int* status);
+int true_residual(Handle& h, const double* Fs, const double* W, int k, double* out_host,
+                  double* rhs_norm_host);
+int scale_boundary(Handle& h, const double* F, int k, double* Fs, double factor);
+int eval_points(Handle& h, const double* Xq, int64_t M, const double* Lq, const double* W,
+                int k, double* U, bool transpose);
+int coeffs_raw(Handle& h, const double* W, int k, double* c, bool transpose);
+
+}  // namespace rdd

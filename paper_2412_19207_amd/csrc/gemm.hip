@@ -1,0 +1,492 @@
+// Matrix-core GEMMs of the set-up phase.
+//
+//  * k_pca_gram  : G_j = Psi_j^T Psi_j, Psi_j[i,k] = w_j(x_i) tanh(z_k(x_i)),
+//                  the value matrix of the PCA step (paper Sec. 4); Psi is
+//                  generated tile by tile in LDS and never stored.
+//  * k_feat_rows : H_j = A_j V_j with A_j[i,k] = A[L w_j phi_k](x_i) generated
+//                  in the GEMM prologue from the pair coefficients (eqs. (sum),
+//                  (system_new)); FP64 output plus an FP32 copy in the mixed path.
+//  * k_local_gram: Gram blocks G_jk = H_j^T H_k over the rows the two supports
+//                  share, the pieces of the Schwarz blocks A_i = R_i H^T H R_i^T
+//                  (Sec. 3); FP64, or FP32 with FP32 accumulation.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "mfma.h"
+
+namespace rdd {
+
+namespace {
+
+struct GramTile { int j, tm, tn, pad; };
+
+__device__ __forceinline__ double feature_z(const double* Rk, double bk, const double* xt, int d) {
+    double z = bk;
+    for (int i = 0; i < d; ++i) z = fma(Rk[i], xt[i], z);
+    return z;
+}
+
+__global__ void __launch_bounds__(256) k_pca_gram(Geo g, const GramTile* __restrict__ tiles,
+                                                  const int64_t* __restrict__ row_off,
+                                                  const double* __restrict__ rec,
+                                                  const int32_t* __restrict__ m,
+                                                  const int64_t* __restrict__ m_off,
+                                                  const double* __restrict__ Rf,
+                                                  const double* __restrict__ bf,
+                                                  const int64_t* __restrict__ g_off,
+                                                  double* __restrict__ G) {
+    __shared__ double As[kTK][kTM + kPad];
+    __shared__ double Bs[kTK][kTN + kPad];
+    const GramTile t = tiles[blockIdx.x];
+    const int j = t.j, mj = m[j];
+    const int64_t n = row_off[j + 1] - row_off[j];
+    const double* rj = rec + row_off[j] * kPairRec;
+    const int kk = threadIdx.x >> 4, c4 = (threadIdx.x & 15) * 4;
+    const bool diag = (t.tm == t.tn);
+    TileAcc<double> acc;
+    acc.zero();
+    for (int64_t i0 = 0; i0 < n; i0 += kTK) {
+        const int64_t i = i0 + kk;
+        double xt[kMaxDim] = {0, 0, 0, 0}, w = 0.0;
+        if (i < n) {
+            for (int q = 0; q < g.d; ++q) xt[q] = rj[i * kPairRec + kRecX + q];
+            w = rj[i * kPairRec + kRecW];
+        }
+        for (int e = 0; e < 4; ++e) {
+            int f = t.tm * kTM + c4 + e;
+            double v = 0.0;
+            if (i < n && f < mj) {
+                int64_t gf = m_off[j] + f;
+                v = w * tanh(feature_z(Rf + gf * 4, bf[gf], xt, g.d));
+            }
+            As[kk][c4 + e] = v;
+            if (!diag) {
+                int f2 = t.tn * kTN + c4 + e;
+                double v2 = 0.0;
+                if (i < n && f2 < mj) {
+                    int64_t gf = m_off[j] + f2;
+                    v2 = w * tanh(feature_z(Rf + gf * 4, bf[gf], xt, g.d));
+                }
+                Bs[kk][c4 + e] = v2;
+            }
+        }
+        __syncthreads();
+        acc.step(As, diag ? As : Bs);
+        __syncthreads();
+    }
+    double* Gj = G + g_off[j];
+    acc.each([&](int r, int c, double v) {
+        int gr = t.tm * kTM + r, gc = t.tn * kTN + c;
+        if (gr < mj && gc < mj) {
+            if (!diag || gr >= gc) {
+                Gj[(int64_t)gr * mj + gc] = v;
+                Gj[(int64_t)gc * mj + gr] = v;
+            }
+        }
+    });
+}
+
+__global__ void __launch_bounds__(256) k_feat_rows(Geo g, const GramTile* __restrict__ tiles,
+                                                   const int64_t* __restrict__ row_off,
+                                                   const double* __restrict__ rec,
+                                                   const int32_t* __restrict__ m,
+                                                   const int64_t* __restrict__ m_off,
+                                                   const double* __restrict__ Rf,
+                                                   const double* __restrict__ bf,
+                                                   const int32_t* __restrict__ p,
+                                                   const int64_t* __restrict__ v_off,
+                                                   const double* __restrict__ V,
+                                                   const int64_t* __restrict__ h_off,
+                                                   double* __restrict__ H, float* __restrict__ H32) {
+    __shared__ double As[kTK][kTM + kPad];
+    __shared__ double Bs[kTK][kTN + kPad];
+    const GramTile t = tiles[blockIdx.x];
+    const int j = t.j, mj = m[j], pj = p[j];
+    const int64_t n = row_off[j + 1] - row_off[j];
+    const int mm = threadIdx.x & 63, kq = threadIdx.x >> 6;
+    const int64_t row = (int64_t)t.tm * kTM + mm;
+    // pair coefficients of this thread's row, kept in registers over the K loop
+    double xt[kMaxDim] = {0, 0, 0, 0}, P0 = 0.0, P1[kMaxDim] = {0, 0, 0, 0},
+           P2[kMaxDim] = {0, 0, 0, 0};
+    const bool rv = row < n;
+    if (rv) {
+        const double* rr = rec + (row_off[j] + row) * kPairRec;
+        for (int q = 0; q < g.d; ++q) {
+            xt[q] = rr[kRecX + q];
+            P1[q] = rr[kRecP1 + q];
+            P2[q] = rr[kRecP2 + q];
+        }
+        P0 = rr[kRecP0];
+    }
+    const int bk = threadIdx.x >> 4, bc4 = (threadIdx.x & 15) * 4;
+    const double* Vj = V + v_off[j];
+    TileAcc<double> acc;
+    acc.zero();
+    for (int k0 = 0; k0 < mj; k0 += kTK) {
+        for (int e = 0; e < 4; ++e) {
+            int f = k0 + kq * 4 + e;
+            double v = 0.0;
+            if (rv && f < mj) {
+                int64_t gf = m_off[j] + f;
+                const double* Rk = Rf + gf * 4;
+                double th = tanh(feature_z(Rk, bf[gf], xt, g.d));
+                double s = 1.0 - th * th;
+                double g1 = 0.0, g2 = 0.0;
+                for (int q = 0; q < g.d; ++q) {
+                    double rho = Rk[q] * g.inv_sigma[q];
+                    g1 = fma(P1[q], rho, g1);
+                    g2 = fma(P2[q], rho * rho, g2);
+                }
+                v = th * (P0 - 2.0 * g2 * s) + g1 * s;
+            }
+            As[kq * 4 + e][mm] = v;
+        }
+        for (int e = 0; e < 4; ++e) {
+            int f = k0 + bk, c = t.tn * kTN + bc4 + e;
+            Bs[bk][bc4 + e] = (f < mj && c < pj) ? Vj[(int64_t)f * pj + c] : 0.0;
+        }
+        __syncthreads();
+        acc.step(As, Bs);
+        __syncthreads();
+    }
+    double* Hj = H + h_off[j];
+    float* Hj32 = H32 ? H32 + h_off[j] : nullptr;
+    acc.each([&](int r, int c, double v) {
+        int64_t gr = (int64_t)t.tm * kTM + r;
+        int gc = t.tn * kTN + c;
+        if (gr < n && gc < pj) {
+            Hj[gr * pj + gc] = v;
+            if (Hj32) Hj32[gr * pj + gc] = (float)v;
+        }
+    });
+}
+
+struct PairBlock {
+    int j, k;          // subdomains (j <= k)
+    int64_t isect;     // offset into the intersection lists (-1 when j == k)
+    int64_t len;       // shared rows
+    int64_t g_off;     // offset of the p_j x p_k block in the block store
+};
+
+struct LocalTile { int blk, tm, tn, pad; };
+
+template <class T>
+__global__ void __launch_bounds__(256) k_local_gram(const LocalTile* __restrict__ tiles,
+                                                    const PairBlock* __restrict__ blocks,
+                                                    const int32_t* __restrict__ loc_j,
+                                                    const int32_t* __restrict__ loc_k,
+                                                    const int32_t* __restrict__ p,
+                                                    const int64_t* __restrict__ h_off,
+                                                    const T* __restrict__ H, T* __restrict__ Gout) {
+    __shared__ T As[kTK][kTM + kPad];
+    __shared__ T Bs[kTK][kTN + kPad];
+    const LocalTile t = tiles[blockIdx.x];
+    const PairBlock B = blocks[t.blk];
+    const int pj = p[B.j], pk = p[B.k];
+    const T* Hj = H + h_off[B.j];
+    const T* Hk = H + h_off[B.k];
+    const int kk = threadIdx.x >> 4, c4 = (threadIdx.x & 15) * 4;
+    TileAcc<T> acc;
+    acc.zero();
+    for (int64_t i0 = 0; i0 < B.len; i0 += kTK) {
+        const int64_t i = i0 + kk;
+        int64_t rj = -1, rk = -1;
+        if (i < B.len) {
+            if (B.isect < 0) {
+                rj = i;
+                rk = i;
+            } else {
+                rj = loc_j[B.isect + i];
+                rk = loc_k[B.isect + i];
+            }
+        }
+        for (int e = 0; e < 4; ++e) {
+            int ca = t.tm * kTM + c4 + e, cb = t.tn * kTN + c4 + e;
+            As[kk][c4 + e] = (rj >= 0 && ca < pj) ? Hj[rj * pj + ca] : T(0);
+            Bs[kk][c4 + e] = (rk >= 0 && cb < pk) ? Hk[rk * pk + cb] : T(0);
+        }
+        __syncthreads();
+        acc.step(As, Bs);
+        __syncthreads();
+    }
+    T* G = Gout + B.g_off;
+    acc.each([&](int r, int c, T v) {
+        int gr = t.tm * kTM + r, gc = t.tn * kTN + c;
+        if (gr < pj && gc < pk) G[(int64_t)gr * pk + gc] = v;
+    });
+}
+
+// rows shared by the supports of j and k: positions in S_j and in S_k
+template <bool kFill>
+__global__ void __launch_bounds__(256) k_intersect(const PairBlock* __restrict__ blocks,
+                                                   const int64_t* __restrict__ row_off,
+                                                   const int32_t* __restrict__ rows,
+                                                   int64_t* __restrict__ count,
+                                                   int32_t* __restrict__ loc_j,
+                                                   int32_t* __restrict__ loc_k) {
+    const PairBlock B = blocks[blockIdx.x];
+    if (B.isect < 0 && kFill) return;
+    const int32_t* Sj = rows + row_off[B.j];
+    const int32_t* Sk = rows + row_off[B.k];
+    const int64_t nj = row_off[B.j + 1] - row_off[B.j], nk = row_off[B.k + 1] - row_off[B.k];
+    __shared__ int wave_cnt[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t base = 0;
+    for (int64_t a0 = 0; a0 < nj; a0 += 256) {
+        int64_t a = a0 + threadIdx.x;
+        int64_t pos = -1;
+        if (a < nj) {
+            int32_t v = Sj[a];
+            int64_t lo = 0, hi = nk;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (Sk[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            if (lo < nk && Sk[lo] == v) pos = lo;
+        }
+        bool in = pos >= 0;
+        uint64_t mask = __ballot(in);
+        if (lane == 0) wave_cnt[wave] = __popcll(mask);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < 4; ++w) {
+            before += (w < wave) ? wave_cnt[w] : 0;
+            total += wave_cnt[w];
+        }
+        if (kFill && in) {
+            uint64_t lower = (lane == 0) ? 0ull : (mask & ((~0ull) >> (64 - lane)));
+            int64_t o = B.isect + base + before + __popcll(lower);
+            loc_j[o] = (int32_t)a;
+            loc_k[o] = (int32_t)pos;
+        }
+        base += total;
+        __syncthreads();
+    }
+    if (!kFill && threadIdx.x == 0) count[blockIdx.x] = base;
+}
+
+// assemble A_i from the Gram block store (exactly symmetric by construction)
+template <class T>
+__global__ void __launch_bounds__(256) k_assemble_A(int J, const int32_t* __restrict__ sten_off,
+                                                    const int32_t* __restrict__ sten,
+                                                    const int32_t* __restrict__ pair_of,
+                                                    const PairBlock* __restrict__ blocks,
+                                                    const int32_t* __restrict__ p,
+                                                    const int64_t* __restrict__ f_off,
+                                                    const T* __restrict__ Gs, T* __restrict__ A) {
+    // blockIdx.x = block i, blockIdx.y = stencil pair (a, b) packed as a * 32 + b
+    const int i = blockIdx.x;
+    const int ns = sten_off[i + 1] - sten_off[i];
+    const int a = blockIdx.y / 32, b = blockIdx.y % 32;
+    if (a >= ns || b >= ns) return;
+    int64_t q = 0, oa = 0, ob = 0;
+    for (int s = 0; s < ns; ++s) {
+        int js = sten[sten_off[i] + s];
+        if (s == a) oa = q;
+        if (s == b) ob = q;
+        q += p[js];
+    }
+    const int ja = sten[sten_off[i] + a], jb = sten[sten_off[i] + b];
+    const int pa = p[ja], pb = p[jb];
+    const int pid = pair_of[sten_off[i] * 32 + a * 32 + b];  // index into blocks or -1
+    T* Ai = A + f_off[i];
+    for (int64_t e = threadIdx.x; e < (int64_t)pa * pb; e += blockDim.x) {
+        int r = (int)(e / pb), c = (int)(e % pb);
+        T v = T(0);
+        if (pid >= 0) {
+            const PairBlock B = blocks[pid];
+            const T* G = Gs + B.g_off;
+            if (ja == jb) {
+                int hi = r > c ? r : c, lo = r > c ? c : r;
+                v = G[(int64_t)hi * pb + lo];
+            } else if (ja < jb) {
+                v = G[(int64_t)r * pb + c];
+            } else {
+                v = G[(int64_t)c * pa + r];
+            }
+        }
+        Ai[(oa + r) * q + ob + c] = v;
+    }
+}
+
+}  // namespace
+
+int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g_off) {
+    (void)g_off_host;
+    std::vector<GramTile> tiles;
+    for (int j = 0; j < h.geo.J; ++j) {
+        int nt = (h.m[j] + kTM - 1) / kTM;
+        for (int a = 0; a < nt; ++a)
+            for (int b = 0; b <= a; ++b) tiles.push_back({j, a, b, 0});
+    }
+    GramTile* d_t = nullptr;
+    RDD_TRY(dev_alloc(h, &d_t, tiles.size()));
+    RDD_HIP(hipMemcpyAsync(d_t, tiles.data(), sizeof(GramTile) * tiles.size(),
+                           hipMemcpyHostToDevice, h.stream));
+    hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, h.geo, d_t,
+                       h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, d_g_off, G);
+    RDD_HIP(hipGetLastError());
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    dev_free(h, d_t);
+    return RANN_OK;
+}
+
+int feature_rows(Handle& h) {
+    std::vector<GramTile> tiles;
+    for (int j = 0; j < h.geo.J; ++j) {
+        int64_t n = h.pts.row_off[j + 1] - h.pts.row_off[j];
+        int ntm = (int)((n + kTM - 1) / kTM), ntn = (h.p[j] + kTN - 1) / kTN;
+        for (int a = 0; a < ntm; ++a)
+            for (int b = 0; b < ntn; ++b) tiles.push_back({j, a, b, 0});
+    }
+    if (tiles.empty()) return RANN_OK;
+    GramTile* d_t = nullptr;
+    RDD_TRY(dev_alloc(h, &d_t, tiles.size()));
+    RDD_HIP(hipMemcpyAsync(d_t, tiles.data(), sizeof(GramTile) * tiles.size(),
+                           hipMemcpyHostToDevice, h.stream));
+    hipLaunchKernelGGL(k_feat_rows, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, h.geo, d_t,
+                       h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, h.d_p,
+                       h.d_v_off, h.d_V, h.d_h_off, h.d_H, h.d_H32);
+    RDD_HIP(hipGetLastError());
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    dev_free(h, d_t);
+    return RANN_OK;
+}
+
+// Gram blocks of every stencil and the assembled A_i (device, q_i x q_i each)
+template <class T>
+int local_blocks(Handle& h, const T* H, T* A_out) {
+    const int J = h.geo.J;
+    // supports of j and k intersect (open boxes)
+    std::vector<double> mu_host;  // recomputed centres per subdomain
+    auto centre = [&](int j, int i) {
+        int c = j;
+        for (int q = 0; q < i; ++q) c /= h.geo.l[q];
+        c %= h.geo.l[i];
+        return c;
+    };
+    std::vector<std::vector<double>> cen(J, std::vector<double>(h.geo.d));
+    {
+        std::vector<double> mu_all(h.geo.mu_off[h.geo.d - 1] + h.geo.l[h.geo.d - 1]);
+        RDD_HIP(hipMemcpy(mu_all.data(), h.d_mu, sizeof(double) * mu_all.size(),
+                          hipMemcpyDeviceToHost));
+        for (int j = 0; j < J; ++j)
+            for (int i = 0; i < h.geo.d; ++i) cen[j][i] = mu_all[h.geo.mu_off[i] + centre(j, i)];
+    }
+    auto meet = [&](int j, int k) {
+        for (int i = 0; i < h.geo.d; ++i)
+            if (!(std::fabs(cen[j][i] - cen[k][i]) < 2.0 * h.geo.sigma[i])) return false;
+        return true;
+    };
+    // unique (j <= k) pairs needed by some stencil
+    std::vector<PairBlock> blocks;
+    std::vector<int> index(0);
+    std::vector<std::vector<int>> pid_of(J);  // sparse map j -> list of (k, pid)
+    auto find_pair = [&](int j, int k) -> int {
+        for (size_t t = 0; t < pid_of[j].size(); t += 2)
+            if (pid_of[j][t] == k) return pid_of[j][t + 1];
+        return -1;
+    };
+    for (int i = 0; i < J; ++i) {
+        const auto& s = h.sten[i];
+        for (size_t a = 0; a < s.size(); ++a)
+            for (size_t b = a; b < s.size(); ++b) {
+                int j = std::min(s[a], s[b]), k = std::max(s[a], s[b]);
+                if (!meet(j, k) || find_pair(j, k) >= 0) continue;
+                PairBlock B{j, k, j == k ? -1 : 0, 0, 0};
+                pid_of[j].push_back(k);
+                pid_of[j].push_back((int)blocks.size());
+                blocks.push_back(B);
+            }
+    }
+    const int nb = (int)blocks.size();
+    PairBlock* d_blocks = nullptr;
+    RDD_TRY(dev_alloc(h, &d_blocks, nb));
+    // count shared rows
+    for (auto& B : blocks) B.len = (B.isect < 0) ? (h.pts.row_off[B.j + 1] - h.pts.row_off[B.j]) : 0;
+    RDD_HIP(hipMemcpy(d_blocks, blocks.data(), sizeof(PairBlock) * nb, hipMemcpyHostToDevice));
+    int64_t* d_cnt = nullptr;
+    RDD_TRY(dev_alloc(h, &d_cnt, nb));
+    hipLaunchKernelGGL((k_intersect<false>), dim3(nb), dim3(256), 0, h.stream, d_blocks,
+                       h.pts.d_row_off, h.pts.d_rows, d_cnt, nullptr, nullptr);
+    RDD_HIP(hipGetLastError());
+    std::vector<int64_t> cnt(nb);
+    RDD_HIP(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, h.stream));
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    int64_t tot_isect = 0, tot_g = 0;
+    for (int b = 0; b < nb; ++b) {
+        auto& B = blocks[b];
+        if (B.isect >= 0) {
+            B.isect = tot_isect;
+            B.len = cnt[b];
+            tot_isect += cnt[b];
+        }
+        B.g_off = tot_g;
+        tot_g += (int64_t)h.p[B.j] * h.p[B.k];
+    }
+    RDD_HIP(hipMemcpy(d_blocks, blocks.data(), sizeof(PairBlock) * nb, hipMemcpyHostToDevice));
+    int32_t *d_lj = nullptr, *d_lk = nullptr;
+    RDD_TRY(dev_alloc(h, &d_lj, (size_t)tot_isect));
+    RDD_TRY(dev_alloc(h, &d_lk, (size_t)tot_isect));
+    hipLaunchKernelGGL((k_intersect<true>), dim3(nb), dim3(256), 0, h.stream, d_blocks,
+                       h.pts.d_row_off, h.pts.d_rows, nullptr, d_lj, d_lk);
+    RDD_HIP(hipGetLastError());
+    // Gram blocks
+    T* d_G = nullptr;
+    RDD_TRY(dev_alloc(h, &d_G, (size_t)tot_g));
+    std::vector<LocalTile> tiles;
+    for (int b = 0; b < nb; ++b) {
+        int ta = (h.p[blocks[b].j] + kTM - 1) / kTM, tb = (h.p[blocks[b].k] + kTN - 1) / kTN;
+        for (int x = 0; x < ta; ++x)
+            for (int y = 0; y < tb; ++y) tiles.push_back({b, x, y, 0});
+    }
+    LocalTile* d_tiles = nullptr;
+    RDD_TRY(dev_alloc(h, &d_tiles, tiles.size()));
+    RDD_HIP(hipMemcpy(d_tiles, tiles.data(), sizeof(LocalTile) * tiles.size(), hipMemcpyHostToDevice));
+    if (!tiles.empty()) {
+        hipLaunchKernelGGL((k_local_gram<T>), dim3((unsigned)tiles.size()), dim3(256), 0, h.stream,
+                           d_tiles, d_blocks, d_lj, d_lk, h.d_p, h.d_h_off, H, d_G);
+        RDD_HIP(hipGetLastError());
+    }
+    // stencil tables and assembly
+    std::vector<int32_t> sten_off(J + 1, 0), sten_flat, pair_of;
+    int max_ns = 0;
+    for (int i = 0; i < J; ++i) {
+        sten_off[i + 1] = sten_off[i] + (int32_t)h.sten[i].size();
+        max_ns = std::max(max_ns, (int)h.sten[i].size());
+        for (int s : h.sten[i]) sten_flat.push_back(s);
+    }
+    if (max_ns > 32) {
+        set_error("stencil larger than 32 subdomains");
+        return RANN_EINVAL;
+    }
+    pair_of.assign((size_t)sten_off[J] * 32, -1);
+    for (int i = 0; i < J; ++i) {
+        const auto& s = h.sten[i];
+        for (size_t a = 0; a < s.size(); ++a)
+            for (size_t b = 0; b < s.size(); ++b) {
+                int j = std::min(s[a], s[b]), k = std::max(s[a], s[b]);
+                pair_of[(size_t)sten_off[i] * 32 + a * 32 + b] = find_pair(j, k);
+            }
+    }
+    int32_t *d_so = nullptr, *d_sf = nullptr, *d_po = nullptr;
+    RDD_TRY(dev_alloc(h, &d_so, sten_off.size()));
+    RDD_TRY(dev_alloc(h, &d_sf, sten_flat.size()));
+    RDD_TRY(dev_alloc(h, &d_po, pair_of.size()));
+    RDD_HIP(hipMemcpy(d_so, sten_off.data(), sizeof(int32_t) * sten_off.size(), hipMemcpyHostToDevice));
+    RDD_HIP(hipMemcpy(d_sf, sten_flat.data(), sizeof(int32_t) * sten_flat.size(), hipMemcpyHostToDevice));
+    RDD_HIP(hipMemcpy(d_po, pair_of.data(), sizeof(int32_t) * pair_of.size(), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL((k_assemble_A<T>), dim3(J, max_ns * 32), dim3(256), 0, h.stream, J, d_so, d_sf,
+                       d_po, d_blocks, h.d_p, h.d_f_off, d_G, A_out);
+    RDD_HIP(hipGetLastError());
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    for (void* ptr : {(void*)d_blocks, (void*)d_cnt, (void*)d_lj, (void*)d_lk, (void*)d_G,
+                      (void*)d_tiles, (void*)d_so, (void*)d_sf, (void*)d_po})
+        dev_free(h, ptr);
+    return RANN_OK;
+}
+
+template int local_blocks<double>(Handle&, const double*, double*);
+template int local_blocks<float>(Handle&, const float*, float*);
+
+}  // namespace rdd

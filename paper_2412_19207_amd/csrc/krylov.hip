@@ -1,0 +1,1157 @@
+// The iteration: products with H and H^T, Krylov recurrences, true residual,
+// adjoint and probe evaluation (paper Sec. 2 normal equations, Sec. 3
+// preconditioned CG / GMRES, Sec. 5 stopping rule).
+//
+// Vectors are FP64, (rows, k) row-major with the right-hand side fastest.
+// All reductions are two-stage with a fixed number of workgroups and a fixed
+// order, so results are bitwise reproducible (no floating-point atomics).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace rdd {
+
+namespace {
+
+constexpr int kDotBlocks = 240;
+constexpr int kChunkRows = 128;
+
+// ------------------------------------------------------------------ H x
+// one wave per global row: y[r] = sum over the subdomains covering r of H_j[row] . x_j
+template <int KB>
+__global__ void __launch_bounds__(256) k_Hx(int64_t N, const int64_t* __restrict__ cover_off,
+                                            const int64_t* __restrict__ cover,
+                                            const int32_t* __restrict__ pair_sub,
+                                            const int64_t* __restrict__ row_off,
+                                            const int32_t* __restrict__ p,
+                                            const int64_t* __restrict__ h_off,
+                                            const int64_t* __restrict__ col_off,
+                                            const double* __restrict__ H,
+                                            const double* __restrict__ x, int k, int k0,
+                                            double* __restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= N) return;
+    double acc[KB];
+    for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+    for (int64_t c = cover_off[r]; c < cover_off[r + 1]; ++c) {
+        const int64_t pid = cover[c];
+        const int j = pair_sub[pid];
+        const int pj = p[j];
+        const double* Hr = H + h_off[j] + (pid - row_off[j]) * pj;
+        const double* xj = x + col_off[j] * k + k0;
+        for (int q = lane; q < pj; q += 64) {
+            const double hv = Hr[q];
+            for (int t = 0; t < KB; ++t) acc[t] = fma(hv, xj[(int64_t)q * k + t], acc[t]);
+        }
+    }
+    for (int t = 0; t < KB; ++t)
+        for (int off = 32; off > 0; off >>= 1) acc[t] += __shfl_xor(acc[t], off);
+    if (lane == 0)
+        for (int t = 0; t < KB; ++t) y[r * k + k0 + t] = acc[t];
+}
+
+// ------------------------------------------------------------------ H^T y
+// one wave per (row chunk of a block, 64-column slab): partial column sums
+template <int KB>
+__global__ void __launch_bounds__(256) k_HTy_part(int64_t n_tasks, const int32_t* __restrict__ tasks,
+                                                  const int32_t* __restrict__ chunk_sub,
+                                                  const int64_t* __restrict__ chunk_off,
+                                                  const int64_t* __restrict__ part_off,
+                                                  const int64_t* __restrict__ row_off,
+                                                  const int32_t* __restrict__ rows,
+                                                  const int32_t* __restrict__ p,
+                                                  const int64_t* __restrict__ h_off,
+                                                  const double* __restrict__ H,
+                                                  const double* __restrict__ y, int k, int k0,
+                                                  double* __restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t task = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (task >= n_tasks) return;
+    const int ch = tasks[2 * task], slab = tasks[2 * task + 1];
+    const int j = chunk_sub[ch];
+    const int pj = p[j];
+    const int c = slab * 64 + lane;
+    const int64_t n = row_off[j + 1] - row_off[j];
+    const int64_t lc = ch - chunk_off[j];
+    const int64_t r0 = lc * kChunkRows, r1 = (r0 + kChunkRows < n) ? r0 + kChunkRows : n;
+    double acc[KB];
+    for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+    const double* Hj = H + h_off[j];
+    const int32_t* Sj = rows + row_off[j];
+    if (c < pj) {
+        for (int64_t r = r0; r < r1; ++r) {
+            const double hv = Hj[r * pj + c];
+            const double* yr = y + (int64_t)Sj[r] * k + k0;
+            for (int t = 0; t < KB; ++t) acc[t] = fma(hv, yr[t], acc[t]);
+        }
+        double* o = part + (part_off[ch] + c) * k + k0;
+        for (int t = 0; t < KB; ++t) o[t] = acc[t];
+    }
+}
+
+__global__ void k_HTy_reduce(int64_t P, int k, const int32_t* __restrict__ col_sub,
+                             const int64_t* __restrict__ col_off,
+                             const int64_t* __restrict__ chunk_off,
+                             const int64_t* __restrict__ part_off, const double* __restrict__ part,
+                             double* __restrict__ x) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= P * k) return;
+    const int64_t g = idx / k;
+    const int t = (int)(idx % k);
+    const int j = col_sub[g];
+    const int64_t c = g - col_off[j];
+    double s = 0.0;
+    for (int64_t ch = chunk_off[j]; ch < chunk_off[j + 1]; ++ch) s += part[(part_off[ch] + c) * k + t];
+    x[idx] = s;
+}
+
+// ------------------------------------------------------------------ reductions
+// partial[b * k + t] = sum over this block's rows of a[row, t] * b[row, t]
+__global__ void __launch_bounds__(256) k_dot_part(int64_t rows, int k, const double* __restrict__ a,
+                                                  const double* __restrict__ b,
+                                                  double* __restrict__ partial) {
+    __shared__ double s[256];
+    const int per = 256 / k;  // rows per step (k <= 256)
+    const int t = threadIdx.x % k, ro = threadIdx.x / k;
+    double acc = 0.0;
+    if (ro < per) {
+        for (int64_t r = (int64_t)blockIdx.x * per + ro; r < rows; r += (int64_t)gridDim.x * per)
+            acc = fma(a[r * k + t], b[r * k + t], acc);
+    }
+    s[threadIdx.x] = (ro < per) ? acc : 0.0;
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double tot = 0.0;
+        for (int q = 0; q < per; ++q) tot += s[q * k + threadIdx.x];
+        partial[blockIdx.x * k + threadIdx.x] = tot;
+    }
+}
+
+// out[t] = sum over the nb partials; per = 256 / k threads share each t (fixed order)
+__global__ void __launch_bounds__(256) k_dot_fin(int k, int nb, const double* __restrict__ partial,
+                                                 double* __restrict__ out) {
+    __shared__ double s[256];
+    const int per = 256 / k;
+    const int t = threadIdx.x % k, ro = threadIdx.x / k;
+    double acc = 0.0;
+    if (ro < per)
+        for (int b = ro; b < nb; b += per) acc += partial[b * k + t];
+    s[threadIdx.x] = (ro < per) ? acc : 0.0;
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double tot = 0.0;
+        for (int q = 0; q < per; ++q) tot += s[q * k + threadIdx.x];
+        out[threadIdx.x] = tot;
+    }
+}
+
+// ------------------------------------------------------------------ CG pieces
+// state per RHS: rho, active flag, iteration count; alpha from <p,s>
+__global__ void k_cg_alpha(int k, const double* __restrict__ pS, const double* __restrict__ rho,
+                           const int32_t* __restrict__ active, double* __restrict__ alpha,
+                           int32_t* __restrict__ flags) {
+    int t = threadIdx.x;
+    if (t >= k) return;
+    double a = 0.0;
+    if (active[t]) {
+        if (!(pS[t] > 0.0)) {
+            flags[0] = 1;  // breakdown
+        } else {
+            a = rho[t] / pS[t];
+        }
+        if (!isfinite(pS[t])) flags[1] = 1;
+    }
+    alpha[t] = a;
+}
+
+__global__ void k_cg_xr(int64_t P, int k, const double* __restrict__ alpha,
+                        const double* __restrict__ p, const double* __restrict__ s,
+                        double* __restrict__ x, double* __restrict__ r) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= P * k) return;
+    const double a = alpha[idx % k];
+    x[idx] = fma(a, p[idx], x[idx]);
+    r[idx] = fma(-a, s[idx], r[idx]);
+}
+
+// beta, rho update and convergence of the recurrence residual; `upd` marks the
+// right-hand sides whose search direction is advanced this iteration, so that a
+// right-hand side deactivated here can later resume the same recurrence
+__global__ void k_cg_beta(int k, const double* __restrict__ rz, const double* __restrict__ rr,
+                          const double* __restrict__ bnorm2, const double* __restrict__ tol2,
+                          double* __restrict__ rho, double* __restrict__ beta,
+                          int32_t* __restrict__ active, int32_t* __restrict__ upd,
+                          int32_t* __restrict__ iters, double* __restrict__ rres) {
+    int t = threadIdx.x;
+    if (t >= k) return;
+    double b = 0.0;
+    int u = 0;
+    if (active[t]) {
+        iters[t] += 1;
+        rres[t] = sqrt(rr[t] / bnorm2[t]);
+        b = rz[t] / rho[t];
+        rho[t] = rz[t];
+        u = 1;
+        if (rr[t] <= tol2[t] * bnorm2[t]) active[t] = 0;
+    }
+    beta[t] = b;
+    upd[t] = u;
+}
+
+__global__ void k_cg_p(int64_t P, int k, const double* __restrict__ beta, const int32_t* __restrict__ upd,
+                       const double* __restrict__ z, double* __restrict__ p) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= P * k) return;
+    const int t = (int)(idx % k);
+    if (upd[t]) p[idx] = fma(beta[t], p[idx], z[idx]);
+}
+
+__global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ c) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx < n) c[idx] = a[idx] - b[idx];
+}
+
+__global__ void k_scale_rows(int64_t row0, int64_t rows, int k, double f, const double* __restrict__ in,
+                             double* __restrict__ out) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= rows * k) return;
+    out[row0 * k + idx] = f * in[row0 * k + idx];
+}
+
+__global__ void k_copy(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx < n) b[idx] = a[idx];
+}
+
+__global__ void k_nan_check(int64_t n, const double* __restrict__ a, int32_t* __restrict__ flag) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx < n && !isfinite(a[idx])) flag[0] = 1;
+}
+
+// ------------------------------------------------------------------ GMRES pieces
+// h[i][t] for i < nv: dots of w with V_i (V stored (restart+1) x P x k)
+__global__ void __launch_bounds__(256) k_mdot_part(int64_t P, int k, int nv, const double* __restrict__ V,
+                                                   const double* __restrict__ w,
+                                                   double* __restrict__ partial) {
+    // blockIdx.y = basis vector index
+    __shared__ double s[256];
+    const int i = blockIdx.y;
+    const int per = 256 / k;
+    const int t = threadIdx.x % k, ro = threadIdx.x / k;
+    const double* Vi = V + (int64_t)i * P * k;
+    double acc = 0.0;
+    if (ro < per)
+        for (int64_t r = (int64_t)blockIdx.x * per + ro; r < P; r += (int64_t)gridDim.x * per)
+            acc = fma(Vi[r * k + t], w[r * k + t], acc);
+    s[threadIdx.x] = (ro < per) ? acc : 0.0;
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double tot = 0.0;
+        for (int q = 0; q < per; ++q) tot += s[q * k + threadIdx.x];
+        partial[((int64_t)i * gridDim.x + blockIdx.x) * k + threadIdx.x] = tot;
+    }
+    (void)nv;
+}
+
+__global__ void k_mdot_fin(int k, int nv, int nb, const double* __restrict__ partial,
+                           double* __restrict__ out) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nv * k) return;
+    int i = idx / k, t = idx % k;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[((int64_t)i * nb + b) * k + t];
+    out[idx] = s;
+}
+
+// w -= sum_i h[i][t] V_i
+__global__ void k_mgs_update(int64_t P, int k, int nv, const double* __restrict__ V,
+                             const double* __restrict__ h, double* __restrict__ w) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= P * k) return;
+    const int t = (int)(idx % k);
+    double acc = w[idx];
+    for (int i = 0; i < nv; ++i) acc -= h[i * k + t] * V[(int64_t)i * P * k + idx];
+    w[idx] = acc;
+}
+
+// v_{j+1} = w / ||w||
+__global__ void k_normalize(int64_t P, int k, const double* __restrict__ nrm2, const double* __restrict__ w,
+                            double* __restrict__ v) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= P * k) return;
+    const double n = sqrt(nrm2[idx % k]);
+    v[idx] = (n > 0.0) ? w[idx] / n : 0.0;
+}
+
+// Givens update of column j of the Hessenberg matrix (per RHS, one thread each)
+// Hs: (restart+1) x restart x k column-major per RHS: Hs[(i * restart + col) * k + t]
+__global__ void k_givens(int k, int j, int restart, const double* __restrict__ hcol1,
+                         const double* __restrict__ hcol2, const double* __restrict__ wnorm2,
+                         double* __restrict__ Hs, double* __restrict__ cs, double* __restrict__ sn,
+                         double* __restrict__ g, double* __restrict__ res,
+                         const int32_t* __restrict__ active) {
+    int t = threadIdx.x;
+    if (t >= k || !active[t]) return;
+    // column entries h[0..j] from the two Gram-Schmidt passes, h[j+1] = ||w||
+    double col[130];
+    for (int i = 0; i <= j; ++i) col[i] = hcol1[i * k + t] + hcol2[i * k + t];
+    col[j + 1] = sqrt(wnorm2[t]);
+    for (int i = 0; i < j; ++i) {
+        double c = cs[i * k + t], s = sn[i * k + t];
+        double a = c * col[i] + s * col[i + 1];
+        col[i + 1] = -s * col[i] + c * col[i + 1];
+        col[i] = a;
+    }
+    double den = hypot(col[j], col[j + 1]);
+    double c = den > 0.0 ? col[j] / den : 1.0, s = den > 0.0 ? col[j + 1] / den : 0.0;
+    cs[j * k + t] = c;
+    sn[j * k + t] = s;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    for (int i = 0; i <= j; ++i) Hs[((int64_t)i * restart + j) * k + t] = col[i];
+    double gj = g[j * k + t];
+    g[(j + 1) * k + t] = -s * gj;
+    g[j * k + t] = c * gj;
+    res[t] = fabs(-s * gj);
+}
+
+// y = R^{-1} g (back substitution) per RHS; x += V y
+__global__ void k_gmres_solve(int k, int jn, int restart, const double* __restrict__ Hs,
+                              const double* __restrict__ g, double* __restrict__ y,
+                              const int32_t* __restrict__ nused) {
+    int t = threadIdx.x;
+    if (t >= k) return;
+    int n = nused[t] < jn ? nused[t] : jn;
+    for (int i = n - 1; i >= 0; --i) {
+        double s = g[i * k + t];
+        for (int q = i + 1; q < n; ++q) s -= Hs[((int64_t)i * restart + q) * k + t] * y[q * k + t];
+        double d = Hs[((int64_t)i * restart + i) * k + t];
+        y[i * k + t] = d != 0.0 ? s / d : 0.0;
+    }
+    for (int i = n; i < restart; ++i) y[i * k + t] = 0.0;
+}
+
+__global__ void k_gmres_update(int64_t P, int k, int jn, const double* __restrict__ V,
+                               const double* __restrict__ y, double* __restrict__ x) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= P * k) return;
+    const int t = (int)(idx % k);
+    double acc = x[idx];
+    for (int i = 0; i < jn; ++i) acc += y[i * k + t] * V[(int64_t)i * P * k + idx];
+    x[idx] = acc;
+}
+
+__global__ void k_gmres_init(int k, const double* __restrict__ nrm2, double* __restrict__ g,
+                             int restart, int32_t* __restrict__ nused) {
+    int t = threadIdx.x;
+    if (t >= k) return;
+    for (int i = 0; i <= restart; ++i) g[i * k + t] = 0.0;
+    g[t] = sqrt(nrm2[t]);
+    nused[t] = 0;
+}
+
+__global__ void k_gmres_count(int k, int j, const int32_t* __restrict__ active, int32_t* __restrict__ nused,
+                              int32_t* __restrict__ iters) {
+    int t = threadIdx.x;
+    if (t >= k || !active[t]) return;
+    nused[t] = j + 1;
+    iters[t] += 1;
+}
+
+__global__ void k_gmres_deactivate(int k, double tol, const double* __restrict__ res,
+                                   const double* __restrict__ mbn, int32_t* __restrict__ active) {
+    int t = threadIdx.x;
+    if (t >= k || !active[t]) return;
+    if (res[t] <= tol * mbn[t]) active[t] = 0;
+}
+
+// ------------------------------------------------------------------ probes
+// value of each (probe, subdomain) pair: P0 * sum_f c_f tanh(z_f)
+template <int KB>
+__global__ void __launch_bounds__(256) k_eval_pairs(Geo g, int64_t pairs, const int32_t* __restrict__ pair_sub,
+                                                    const double* __restrict__ rec,
+                                                    const int32_t* __restrict__ m,
+                                                    const int64_t* __restrict__ m_off,
+                                                    const double* __restrict__ Rf,
+                                                    const double* __restrict__ bf,
+                                                    const double* __restrict__ cf, int k, int k0,
+                                                    double* __restrict__ val) {
+    int64_t pid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pid >= pairs) return;
+    const int j = pair_sub[pid];
+    const double* rr = rec + pid * kPairRec;
+    double xt[kMaxDim];
+    for (int i = 0; i < kMaxDim; ++i) xt[i] = rr[kRecX + i];
+    double acc[KB];
+    for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+    for (int f = 0; f < m[j]; ++f) {
+        const int64_t gf = m_off[j] + f;
+        double z = bf[gf];
+        for (int i = 0; i < g.d; ++i) z = fma(Rf[gf * 4 + i], xt[i], z);
+        const double th = tanh(z);
+        for (int t = 0; t < KB; ++t) acc[t] = fma(th, cf[gf * k + k0 + t], acc[t]);
+    }
+    const double P0 = rr[kRecP0];
+    for (int t = 0; t < KB; ++t) val[pid * k + k0 + t] = P0 * acc[t];
+}
+
+__global__ void k_point_sum(int64_t n, int k, const int64_t* __restrict__ cover_off,
+                            const int64_t* __restrict__ cover, const double* __restrict__ val,
+                            double* __restrict__ U) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * k) return;
+    const int64_t r = idx / k;
+    const int t = (int)(idx % k);
+    double s = 0.0;
+    for (int64_t c = cover_off[r]; c < cover_off[r + 1]; ++c) s += val[cover[c] * k + t];
+    U[idx] = s;
+}
+
+// transpose: dc_j[f] = sum over probe pairs of j of P0 tanh(z_f) dU[row]
+template <int KB>
+__global__ void __launch_bounds__(256) k_eval_T(Geo g, const int64_t* __restrict__ row_off,
+                                                const int32_t* __restrict__ rows,
+                                                const double* __restrict__ rec,
+                                                const int32_t* __restrict__ m,
+                                                const int64_t* __restrict__ m_off,
+                                                const double* __restrict__ Rf,
+                                                const double* __restrict__ bf,
+                                                const double* __restrict__ dU, int k, int k0,
+                                                double* __restrict__ dc) {
+    const int j = blockIdx.x;
+    for (int f = threadIdx.x; f < m[j]; f += blockDim.x) {
+        const int64_t gf = m_off[j] + f;
+        double R[kMaxDim];
+        for (int i = 0; i < kMaxDim; ++i) R[i] = Rf[gf * 4 + i];
+        const double b = bf[gf];
+        double acc[KB];
+        for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+        for (int64_t pid = row_off[j]; pid < row_off[j + 1]; ++pid) {
+            const double* rr = rec + pid * kPairRec;
+            double z = b;
+            for (int i = 0; i < g.d; ++i) z = fma(R[i], rr[kRecX + i], z);
+            const double w = rr[kRecP0] * tanh(z);
+            const double* du = dU + (int64_t)rows[pid] * k + k0;
+            for (int t = 0; t < KB; ++t) acc[t] = fma(w, du[t], acc[t]);
+        }
+        for (int t = 0; t < KB; ++t) dc[gf * k + k0 + t] = acc[t];
+    }
+}
+
+// c_j = V_j W_j (raw-neuron coefficients) and its transpose
+__global__ void k_coeffs(int64_t sum_m, int k, const int32_t* __restrict__ feat_sub,
+                         const int64_t* __restrict__ m_off, const int32_t* __restrict__ p,
+                         const int64_t* __restrict__ v_off, const int64_t* __restrict__ col_off,
+                         const double* __restrict__ V, const double* __restrict__ W,
+                         double* __restrict__ c) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= sum_m * k) return;
+    const int64_t gf = idx / k;
+    const int t = (int)(idx % k);
+    const int j = feat_sub[gf];
+    const int64_t f = gf - m_off[j];
+    const int pj = p[j];
+    const double* Vr = V + v_off[j] + f * pj;
+    const double* Wj = W + col_off[j] * k + t;
+    double s = 0.0;
+    for (int q = 0; q < pj; ++q) s = fma(Vr[q], Wj[(int64_t)q * k], s);
+    c[idx] = s;
+}
+
+__global__ void k_coeffs_T(int64_t P, int k, const int32_t* __restrict__ col_sub,
+                           const int64_t* __restrict__ m_off, const int32_t* __restrict__ m,
+                           const int32_t* __restrict__ p, const int64_t* __restrict__ v_off,
+                           const int64_t* __restrict__ col_off, const double* __restrict__ V,
+                           const double* __restrict__ dc, double* __restrict__ dW) {
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= P * k) return;
+    const int64_t gcol = idx / k;
+    const int t = (int)(idx % k);
+    const int j = col_sub[gcol];
+    const int64_t q = gcol - col_off[j];
+    const int pj = p[j];
+    const double* Vj = V + v_off[j];
+    const double* dcj = dc + m_off[j] * k + t;
+    double s = 0.0;
+    for (int f = 0; f < m[j]; ++f) s = fma(Vj[(int64_t)f * pj + q], dcj[(int64_t)f * k], s);
+    dW[idx] = s;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+inline int kb_for(int rem) {
+    return rem >= 32 ? 32 : rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+int launch_Hx(Handle& h, const double* x, int k, double* y, bool) {
+    const unsigned grid = (unsigned)((h.N + 3) / 4);
+    for (int k0 = 0; k0 < k;) {
+        int kb = kb_for(k - k0);
+#define RDD_HX(KBV)                                                                             \
+    hipLaunchKernelGGL((k_Hx<KBV>), dim3(grid), dim3(256), 0, h.stream, h.N, h.pts.d_cover_off, \
+                       h.pts.d_cover, h.pts.d_pair_sub, h.pts.d_row_off, h.d_p, h.d_h_off,     \
+                       h.d_col_off, h.d_H, x, k, k0, y)
+        switch (kb) {
+            case 32: RDD_HX(32); break;
+            case 16: RDD_HX(16); break;
+            case 8: RDD_HX(8); break;
+            case 4: RDD_HX(4); break;
+            case 2: RDD_HX(2); break;
+            default: RDD_HX(1); break;
+        }
+#undef RDD_HX
+        k0 += kb;
+    }
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
+int launch_HTy(Handle& h, const double* y, int k, double* x, double* part) {
+    const unsigned grid = (unsigned)((h.n_tasks + 3) / 4);
+    for (int k0 = 0; k0 < k;) {
+        int kb = kb_for(k - k0);
+#define RDD_HT(KBV)                                                                                \
+    hipLaunchKernelGGL((k_HTy_part<KBV>), dim3(grid), dim3(256), 0, h.stream, h.n_tasks, h.d_tasks, \
+                       h.d_chunk_sub, h.d_chunk_off, h.d_part_off, h.pts.d_row_off, h.pts.d_rows, h.d_p, \
+                       h.d_h_off, h.d_H, y, k, k0, part)
+        switch (kb) {
+            case 32: RDD_HT(32); break;
+            case 16: RDD_HT(16); break;
+            case 8: RDD_HT(8); break;
+            case 4: RDD_HT(4); break;
+            case 2: RDD_HT(2); break;
+            default: RDD_HT(1); break;
+        }
+#undef RDD_HT
+        k0 += kb;
+    }
+    hipLaunchKernelGGL(k_HTy_reduce, dim3(grid_for(h.P * k)), dim3(256), 0, h.stream, h.P, k,
+                       h.d_col_sub, h.d_col_off, h.d_chunk_off, h.d_part_off, part, x);
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
+// chunk / task tables for H^T y
+int plan_products(Handle& h) {
+    const int J = h.geo.J;
+    h.chunk_off.assign(J + 1, 0);
+    std::vector<int64_t> part_off;
+    std::vector<int32_t> tasks;
+    int64_t poff = 0;
+    for (int j = 0; j < J; ++j) {
+        int64_t n = h.pts.row_off[j + 1] - h.pts.row_off[j];
+        int64_t nc = (n + kChunkRows - 1) / kChunkRows;
+        if (nc == 0) nc = 1;
+        h.chunk_off[j + 1] = h.chunk_off[j] + nc;
+        int slabs = (h.p[j] + 63) / 64;
+        for (int64_t c = 0; c < nc; ++c) {
+            part_off.push_back(poff);
+            poff += h.p[j];
+            for (int s = 0; s < slabs; ++s) {
+                tasks.push_back((int32_t)(h.chunk_off[j] + c));
+                tasks.push_back(s);
+            }
+        }
+    }
+    h.n_chunks = h.chunk_off[J];
+    h.n_tasks = (int64_t)tasks.size() / 2;
+    h.part_total = poff;
+    std::vector<int64_t> co(h.chunk_off);
+    std::vector<int32_t> chunk_sub(h.n_chunks);
+    for (int j = 0; j < J; ++j)
+        for (int64_t c = h.chunk_off[j]; c < h.chunk_off[j + 1]; ++c) chunk_sub[c] = j;
+    RDD_TRY(dev_alloc(h, &h.d_chunk_sub, chunk_sub.size()));
+    RDD_HIP(hipMemcpy(h.d_chunk_sub, chunk_sub.data(), sizeof(int32_t) * chunk_sub.size(),
+                      hipMemcpyHostToDevice));
+    RDD_TRY(dev_alloc(h, &h.d_chunk_off, co.size()));
+    RDD_TRY(dev_alloc(h, &h.d_part_off, part_off.size()));
+    RDD_TRY(dev_alloc(h, &h.d_tasks, tasks.size()));
+    RDD_HIP(hipMemcpy(h.d_chunk_off, co.data(), sizeof(int64_t) * co.size(), hipMemcpyHostToDevice));
+    RDD_HIP(hipMemcpy(h.d_part_off, part_off.data(), sizeof(int64_t) * part_off.size(),
+                      hipMemcpyHostToDevice));
+    RDD_HIP(hipMemcpy(h.d_tasks, tasks.data(), sizeof(int32_t) * tasks.size(), hipMemcpyHostToDevice));
+    std::vector<int32_t> col_sub(h.P), feat_sub(h.sum_m);
+    for (int j = 0; j < J; ++j) {
+        for (int64_t c = h.col_off[j]; c < h.col_off[j + 1]; ++c) col_sub[c] = j;
+        for (int64_t f = h.m_off[j]; f < h.m_off[j + 1]; ++f) feat_sub[f] = j;
+    }
+    RDD_TRY(dev_alloc(h, &h.d_col_sub, col_sub.size()));
+    RDD_TRY(dev_alloc(h, &h.d_feat_sub, feat_sub.size()));
+    RDD_HIP(hipMemcpy(h.d_col_sub, col_sub.data(), sizeof(int32_t) * col_sub.size(), hipMemcpyHostToDevice));
+    RDD_HIP(hipMemcpy(h.d_feat_sub, feat_sub.data(), sizeof(int32_t) * feat_sub.size(),
+                      hipMemcpyHostToDevice));
+    return RANN_OK;
+}
+
+namespace {
+
+struct Scratch {
+    double* base = nullptr;
+    size_t used = 0;  // doubles
+    double* take(size_t n) {
+        double* p = base + used;
+        used += (n + 31) & ~size_t(31);
+        return p;
+    }
+};
+
+int dot(Handle& h, int64_t rows, int k, const double* a, const double* b, double* partial, double* out) {
+    hipLaunchKernelGGL(k_dot_part, dim3(kDotBlocks), dim3(256), 0, h.stream, rows, k, a, b, partial);
+    hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(256), 0, h.stream, k, kDotBlocks, partial, out);
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
+int normal_op(Handle& h, const double* x, int k, double* y, double* part, double* s) {
+    RDD_TRY(launch_Hx(h, x, k, y, false));
+    RDD_TRY(launch_HTy(h, y, k, s, part));
+    return RANN_OK;
+}
+
+}  // namespace
+
+int scale_boundary(Handle& h, const double* F, int k, double* Fs, double factor) {
+    const int64_t ni = h.n_int * k, nb = h.n_bnd * k;
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(ni)), dim3(256), 0, h.stream, ni, F, Fs);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scale_rows, dim3(grid_for(nb)), dim3(256), 0, h.stream, h.n_int, h.n_bnd,
+                           k, factor, F, Fs);
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
+// ||H^T (Fs - H W)|| and ||H^T Fs|| per RHS (host outputs)
+int true_residual(Handle& h, const double* Fs, const double* W, int k, double* out_host,
+                  double* rhs_norm_host) {
+    // own scratch: callers inside a Krylov loop hold pointers into the main workspace
+    const size_t need = (size_t)h.N * k * 2 + (size_t)h.P * k * 2 + (size_t)h.part_total * k +
+                        (size_t)kDotBlocks * k + 4 * (size_t)k + 256;
+    if (h.ws2_bytes < need * sizeof(double)) {
+        if (h.ws2) dev_free(h, h.ws2);
+        h.ws2 = nullptr;
+        h.ws2_bytes = 0;
+        double* p2 = nullptr;
+        RDD_TRY(dev_alloc(h, &p2, need));
+        h.ws2 = p2;
+        h.ws2_bytes = need * sizeof(double);
+    }
+    Scratch sc{static_cast<double*>(h.ws2), 0};
+    double* y = sc.take((size_t)h.N * k);
+    double* y2 = sc.take((size_t)h.N * k);
+    double* r = sc.take((size_t)h.P * k);
+    double* g = sc.take((size_t)h.P * k);
+    double* part = sc.take((size_t)h.part_total * k);
+    double* dp = sc.take((size_t)kDotBlocks * k);
+    double* o1 = sc.take(k);
+    double* o2 = sc.take(k);
+    RDD_TRY(launch_Hx(h, W, k, y, false));
+    hipLaunchKernelGGL(k_sub, dim3(grid_for(h.N * k)), dim3(256), 0, h.stream, h.N * k, Fs, y, y2);
+    RDD_TRY(launch_HTy(h, y2, k, r, part));
+    RDD_TRY(launch_HTy(h, Fs, k, g, part));
+    RDD_TRY(dot(h, h.P, k, r, r, dp, o1));
+    RDD_TRY(dot(h, h.P, k, g, g, dp, o2));
+    std::vector<double> a(k), b(k);
+    RDD_HIP(hipMemcpyAsync(a.data(), o1, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_HIP(hipMemcpyAsync(b.data(), o2, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    for (int t = 0; t < k; ++t) {
+        out_host[t] = std::sqrt(a[t]);
+        if (rhs_norm_host) rhs_norm_host[t] = std::sqrt(b[t]);
+    }
+    return RANN_OK;
+}
+
+// Preconditioned CG on H^T H W = rhs (rhs = H^T Fs, or dW for the adjoint).
+// Fs may be null (adjoint): then only the recurrence residual is checked.
+static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const double* W0,
+                   const rann_dd_solve_opts& o, double* W, std::vector<int>& iters_out,
+                   std::vector<double>& res_out, int* status) {
+    const size_t P = (size_t)h.P, N = (size_t)h.N;
+    const size_t need = P * k * 4 + N * k + (size_t)h.part_total * k + (size_t)h.ub_total * k +
+                        (size_t)kDotBlocks * k + 16 * (size_t)k + 1024;
+    RDD_TRY(ensure_ws(h, need * sizeof(double)));
+    Scratch sc{static_cast<double*>(h.ws), 0};
+    double* r = sc.take(P * k);
+    double* z = sc.take(P * k);
+    double* p = sc.take(P * k);
+    double* s = sc.take(P * k);
+    double* y = sc.take(N * k);
+    double* part = sc.take((size_t)h.part_total * k);
+    double* ub = sc.take((size_t)h.ub_total * k);
+    double* dp = sc.take((size_t)kDotBlocks * k);
+    double* rho = sc.take(k);
+    double* pS = sc.take(k);
+    double* alpha = sc.take(k);
+    double* beta = sc.take(k);
+    double* rz = sc.take(k);
+    double* rr = sc.take(k);
+    double* bn2 = sc.take(k);
+    double* rres = sc.take(k);
+    double* tol2v = sc.take(k);
+    int32_t* upd = reinterpret_cast<int32_t*>(sc.take(k));
+    int32_t* active = reinterpret_cast<int32_t*>(sc.take(k));
+    int32_t* iters = reinterpret_cast<int32_t*>(sc.take(k));
+    int32_t* flags = reinterpret_cast<int32_t*>(sc.take(4));
+    const int64_t Pk = (int64_t)P * k;
+
+    RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, h.stream));
+    RDD_HIP(hipMemsetAsync(iters, 0, sizeof(int32_t) * k, h.stream));
+    RDD_TRY(dot(h, P, k, rhs, rhs, dp, bn2));
+    hipLaunchKernelGGL(k_nan_check, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, flags + 1);
+    // x0, r0 = rhs - A x0
+    if (W0) {
+        hipLaunchKernelGGL(k_copy, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, W0, W);
+        RDD_TRY(normal_op(h, W, k, y, part, s));
+        hipLaunchKernelGGL(k_sub, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, s, r);
+    } else {
+        RDD_HIP(hipMemsetAsync(W, 0, sizeof(double) * Pk, h.stream));
+        hipLaunchKernelGGL(k_copy, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, r);
+    }
+    std::vector<double> bn2h(k), tmp(k);
+    std::vector<int32_t> act(k, 1), ith(k, 0);
+    RDD_HIP(hipMemcpyAsync(bn2h.data(), bn2, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    for (int t = 0; t < k; ++t)
+        if (!(bn2h[t] > 0.0)) bn2h[t] = 1.0;  // zero right-hand side: solution 0
+    RDD_HIP(hipMemcpyAsync(bn2, bn2h.data(), sizeof(double) * k, hipMemcpyHostToDevice, h.stream));
+
+    auto restart = [&]() -> int {
+        RDD_TRY(launch_precond(h, r, k, z, ub));
+        hipLaunchKernelGGL(k_copy, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, z, p);
+        RDD_TRY(dot(h, P, k, r, z, dp, rho));
+        return RANN_OK;
+    };
+    RDD_HIP(hipMemcpyAsync(active, act.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, h.stream));
+    std::vector<double> tol2h(k, o.tol * o.tol);
+    RDD_HIP(hipMemcpyAsync(tol2v, tol2h.data(), sizeof(double) * k, hipMemcpyHostToDevice, h.stream));
+    RDD_TRY(restart());
+    int it = 0;
+    const int every = std::max(1, o.check_every);
+    std::vector<double> tres(k);
+    int replacements = 0, stalls = 0;
+    double best_true = 1e300;
+    *status = RANN_OK;
+    while (true) {
+        for (int q = 0; q < every && it < o.maxiter; ++q, ++it) {
+            RDD_TRY(normal_op(h, p, k, y, part, s));
+            RDD_TRY(dot(h, P, k, p, s, dp, pS));
+            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, h.stream, k, pS, rho, active, alpha,
+                               flags);
+            hipLaunchKernelGGL(k_cg_xr, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P, k,
+                               alpha, p, s, W, r);
+            RDD_TRY(dot(h, P, k, r, r, dp, rr));
+            RDD_TRY(launch_precond(h, r, k, z, ub));
+            RDD_TRY(dot(h, P, k, r, z, dp, rz));
+            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, h.stream, k, rz, rr, bn2, tol2v, rho,
+                               beta, active, upd, iters, rres);
+            hipLaunchKernelGGL(k_cg_p, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P, k, beta,
+                               upd, z, p);
+        }
+        RDD_HIP(hipGetLastError());
+        int32_t fl[4];
+        RDD_HIP(hipMemcpyAsync(act.data(), active, sizeof(int32_t) * k, hipMemcpyDeviceToHost, h.stream));
+        RDD_HIP(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, h.stream));
+        RDD_HIP(hipStreamSynchronize(h.stream));
+        if (fl[1]) {
+            set_error("NaN or Inf in the Krylov iteration");
+            return RANN_ENAN;
+        }
+        if (fl[0]) {
+            set_error("CG breakdown: <p, H^T H p> <= 0");
+            return RANN_EBREAKDOWN;
+        }
+        bool any = false;
+        for (int t = 0; t < k; ++t) any |= act[t] != 0;
+        if (!any) {
+            if (Fs == nullptr) break;
+            // confirm on the true FP64 normal residual recomputed from scratch; a
+            // right-hand side that fails it resumes its recurrence with a tighter
+            // recurrence threshold, or restarts from the true residual when the
+            // recurrence has drifted far from it
+            RDD_TRY(true_residual(h, Fs, W, k, tres.data(), tmp.data()));
+            std::vector<double> rrh(k);
+            RDD_HIP(hipMemcpy(rrh.data(), rres, sizeof(double) * k, hipMemcpyDeviceToHost));
+            bool again = false, drift = false;
+            for (int t = 0; t < k; ++t) {
+                double relr = tmp[t] > 0 ? tres[t] / tmp[t] : 0.0;
+                if (relr > o.tol) {
+                    act[t] = 1;
+                    again = true;
+                    tol2h[t] *= 0.01;
+                    if (relr > 1e3 * std::max(rrh[t], 1e-300)) drift = true;
+                }
+            }
+            bool floor_hit = false;
+            for (int t = 0; t < k; ++t) floor_hit |= tol2h[t] < 1e-60;
+            // stagnation: the true residual stopped improving at the FP64 floor
+            double worst = 0.0;
+            for (int t = 0; t < k; ++t) worst = std::max(worst, tmp[t] > 0 ? tres[t] / tmp[t] : 0.0);
+            if (worst < 0.9 * best_true) {
+                best_true = worst;
+                stalls = 0;
+            } else {
+                ++stalls;
+            }
+            if (!again || it >= o.maxiter || replacements > 20 || floor_hit || stalls >= 4) {
+                if (again) *status = RANN_ENOTCONV;
+                break;
+            }
+            RDD_HIP(hipMemcpyAsync(tol2v, tol2h.data(), sizeof(double) * k, hipMemcpyHostToDevice, h.stream));
+            RDD_HIP(hipMemcpyAsync(active, act.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice,
+                                   h.stream));
+            if (drift) {
+                ++replacements;
+                RDD_TRY(launch_Hx(h, W, k, y, false));
+                hipLaunchKernelGGL(k_sub, dim3(grid_for((int64_t)N * k)), dim3(256), 0, h.stream,
+                                   (int64_t)N * k, Fs, y, y);
+                RDD_TRY(launch_HTy(h, y, k, r, part));
+                RDD_TRY(restart());
+            }
+            continue;
+        }
+        if (it >= o.maxiter) {
+            *status = RANN_ENOTCONV;
+            break;
+        }
+    }
+    RDD_HIP(hipMemcpyAsync(ith.data(), iters, sizeof(int32_t) * k, hipMemcpyDeviceToHost, h.stream));
+    std::vector<double> rrh(k);
+    RDD_HIP(hipMemcpyAsync(rrh.data(), rres, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    iters_out.assign(ith.begin(), ith.end());
+    res_out = rrh;
+    return RANN_OK;
+}
+
+int krylov_cg(Handle& h, const double* Fs, int k, const double* W0, const rann_dd_solve_opts& o,
+              double* W, rann_dd_stats* st, int* status) {
+    double* rhs = nullptr;
+    double* part = nullptr;
+    RDD_TRY(dev_alloc(h, &rhs, (size_t)h.P * k));
+    RDD_TRY(dev_alloc(h, &part, (size_t)h.part_total * k));
+    RDD_TRY(launch_HTy(h, Fs, k, rhs, part));
+    std::vector<int> iters;
+    std::vector<double> rres;
+    int rc = cg_core(h, rhs, Fs, k, W0, o, W, iters, rres, status);
+    dev_free(h, part);
+    if (rc < 0) {
+        dev_free(h, rhs);
+        return rc;
+    }
+    dev_free(h, rhs);
+    if (st) {
+        std::vector<double> tres(k), bn(k);
+        RDD_TRY(true_residual(h, Fs, W, k, tres.data(), bn.data()));
+        st->iterations = 0;
+        st->converged = 0;
+        st->max_rel_residual = 0.0;
+        for (int t = 0; t < k; ++t) {
+            double rel = bn[t] > 0 ? tres[t] / bn[t] : 0.0;
+            st->iterations = std::max(st->iterations, iters[t]);
+            st->converged += rel <= o.tol ? 1 : 0;
+            st->max_rel_residual = std::max(st->max_rel_residual, rel);
+            if (st->rel_residual) st->rel_residual[t] = rel;
+            if (st->rhs_iterations) st->rhs_iterations[t] = iters[t];
+        }
+        st->shifts = h.shifts;
+    }
+    return RANN_OK;
+}
+
+int adjoint_cg(Handle& h, const double* dW, int k, const rann_dd_solve_opts& o, double* z,
+               rann_dd_stats* st, int* status) {
+    std::vector<int> iters;
+    std::vector<double> rres;
+    RDD_TRY(cg_core(h, dW, nullptr, k, nullptr, o, z, iters, rres, status));
+    if (st) {
+        st->iterations = 0;
+        st->converged = 0;
+        st->max_rel_residual = 0.0;
+        for (int t = 0; t < k; ++t) {
+            st->iterations = std::max(st->iterations, iters[t]);
+            st->converged += rres[t] <= o.tol ? 1 : 0;
+            st->max_rel_residual = std::max(st->max_rel_residual, rres[t]);
+            if (st->rel_residual) st->rel_residual[t] = rres[t];
+            if (st->rhs_iterations) st->rhs_iterations[t] = iters[t];
+        }
+        st->shifts = h.shifts;
+    }
+    return RANN_OK;
+}
+
+// Left-preconditioned GMRES(restart): minimise ||M^{-1}(rhs - H^T H W)|| per RHS.
+static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, const double* W0,
+                      const rann_dd_solve_opts& o, double* W, std::vector<int>& iters_out,
+                      int* status) {
+    const int m = std::max(1, std::min(o.restart, 128));
+    const size_t P = (size_t)h.P, N = (size_t)h.N;
+    const size_t need = P * k * (m + 1) + P * k * 3 + N * k + (size_t)h.part_total * k +
+                        (size_t)h.ub_total * k + (size_t)kDotBlocks * k * (m + 1) +
+                        (size_t)k * ((m + 1) * m + 6 * (m + 1) + 16) + 1024;
+    RDD_TRY(ensure_ws(h, need * sizeof(double)));
+    Scratch sc{static_cast<double*>(h.ws), 0};
+    double* V = sc.take(P * k * (m + 1));
+    double* w = sc.take(P * k);
+    double* s = sc.take(P * k);
+    double* t0 = sc.take(P * k);
+    double* y = sc.take(N * k);
+    double* part = sc.take((size_t)h.part_total * k);
+    double* ub = sc.take((size_t)h.ub_total * k);
+    double* dp = sc.take((size_t)kDotBlocks * k * (m + 1));
+    double* Hs = sc.take((size_t)k * (m + 1) * m);
+    double* h1 = sc.take((size_t)k * (m + 1));
+    double* h2 = sc.take((size_t)k * (m + 1));
+    double* cs = sc.take((size_t)k * (m + 1));
+    double* sn = sc.take((size_t)k * (m + 1));
+    double* g = sc.take((size_t)k * (m + 1));
+    double* yv = sc.take((size_t)k * (m + 1));
+    double* nrm = sc.take(k);
+    double* res = sc.take(k);
+    double* mbn = sc.take(k);
+    int32_t* active = reinterpret_cast<int32_t*>(sc.take(k));
+    int32_t* nused = reinterpret_cast<int32_t*>(sc.take(k));
+    int32_t* iters = reinterpret_cast<int32_t*>(sc.take(k));
+    const int64_t Pk = (int64_t)P * k;
+    RDD_HIP(hipMemsetAsync(iters, 0, sizeof(int32_t) * k, h.stream));
+    if (W0) {
+        hipLaunchKernelGGL(k_copy, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, W0, W);
+    } else {
+        RDD_HIP(hipMemsetAsync(W, 0, sizeof(double) * Pk, h.stream));
+    }
+    // ||M^{-1} rhs||
+    RDD_TRY(launch_precond(h, rhs, k, w, ub));
+    RDD_TRY(dot(h, P, k, w, w, dp, nrm));
+    std::vector<double> mb(k);
+    RDD_HIP(hipMemcpyAsync(mb.data(), nrm, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    for (int t = 0; t < k; ++t) mb[t] = mb[t] > 0 ? std::sqrt(mb[t]) : 1.0;
+    RDD_HIP(hipMemcpyAsync(mbn, mb.data(), sizeof(double) * k, hipMemcpyHostToDevice, h.stream));
+    double tol_p = o.tol;
+    int it = 0, cycles = 0;
+    std::vector<int32_t> act(k, 1);
+    std::vector<double> tres(k), bn(k), rh(k);
+    *status = RANN_OK;
+    while (true) {
+        // r = M^{-1}(rhs - A W)
+        RDD_TRY(normal_op(h, W, k, y, part, s));
+        hipLaunchKernelGGL(k_sub, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, s, t0);
+        RDD_TRY(launch_precond(h, t0, k, w, ub));
+        RDD_TRY(dot(h, P, k, w, w, dp, nrm));
+        hipLaunchKernelGGL(k_normalize, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P, k, nrm,
+                           w, V);
+        hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(256), 0, h.stream, k, nrm, g, m, nused);
+        // active: those whose preconditioned residual is above tol_p
+        RDD_HIP(hipMemcpyAsync(rh.data(), nrm, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+        RDD_HIP(hipStreamSynchronize(h.stream));
+        bool any = false;
+        for (int t = 0; t < k; ++t) {
+            act[t] = (std::sqrt(rh[t]) > tol_p * mb[t]) ? 1 : 0;
+            any |= act[t] != 0;
+        }
+        RDD_HIP(hipMemcpyAsync(active, act.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, h.stream));
+        int jn = 0;
+        if (any) {
+            for (int j = 0; j < m && it < o.maxiter; ++j, ++it) {
+                double* vj = V + (size_t)j * P * k;
+                RDD_TRY(normal_op(h, vj, k, y, part, s));
+                RDD_TRY(launch_precond(h, s, k, w, ub));
+                // classical Gram-Schmidt, twice
+                hipLaunchKernelGGL(k_mdot_part, dim3(kDotBlocks, j + 1), dim3(256), 0, h.stream,
+                                   (int64_t)P, k, j + 1, V, w, dp);
+                hipLaunchKernelGGL(k_mdot_fin, dim3((unsigned)(((j + 1) * k + 255) / 256)), dim3(256), 0,
+                                   h.stream, k, j + 1, kDotBlocks, dp, h1);
+                hipLaunchKernelGGL(k_mgs_update, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P,
+                                   k, j + 1, V, h1, w);
+                hipLaunchKernelGGL(k_mdot_part, dim3(kDotBlocks, j + 1), dim3(256), 0, h.stream,
+                                   (int64_t)P, k, j + 1, V, w, dp);
+                hipLaunchKernelGGL(k_mdot_fin, dim3((unsigned)(((j + 1) * k + 255) / 256)), dim3(256), 0,
+                                   h.stream, k, j + 1, kDotBlocks, dp, h2);
+                hipLaunchKernelGGL(k_mgs_update, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P,
+                                   k, j + 1, V, h2, w);
+                RDD_TRY(dot(h, P, k, w, w, dp, nrm));
+                hipLaunchKernelGGL(k_normalize, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P, k,
+                                   nrm, w, V + (size_t)(j + 1) * P * k);
+                hipLaunchKernelGGL(k_givens, dim3(1), dim3(256), 0, h.stream, k, j, m, h1, h2, nrm, Hs,
+                                   cs, sn, g, res, active);
+                hipLaunchKernelGGL(k_gmres_count, dim3(1), dim3(256), 0, h.stream, k, j, active, nused,
+                                   iters);
+                hipLaunchKernelGGL(k_gmres_deactivate, dim3(1), dim3(256), 0, h.stream, k, tol_p, res, mbn,
+                                   active);
+                jn = j + 1;
+                if ((j + 1) % std::max(1, o.check_every) == 0) {
+                    RDD_HIP(hipMemcpyAsync(act.data(), active, sizeof(int32_t) * k, hipMemcpyDeviceToHost,
+                                           h.stream));
+                    RDD_HIP(hipStreamSynchronize(h.stream));
+                    bool a2 = false;
+                    for (int t = 0; t < k; ++t) a2 |= act[t] != 0;
+                    if (!a2) break;
+                }
+            }
+            hipLaunchKernelGGL(k_gmres_solve, dim3(1), dim3(256), 0, h.stream, k, jn, m, Hs, g, yv, nused);
+            hipLaunchKernelGGL(k_gmres_update, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P, k,
+                               jn, V, yv, W);
+            RDD_HIP(hipGetLastError());
+        }
+        ++cycles;
+        // convergence on the true normal residual
+        if (Fs) {
+            RDD_TRY(true_residual(h, Fs, W, k, tres.data(), bn.data()));
+            bool ok = true;
+            for (int t = 0; t < k; ++t) ok &= (bn[t] > 0 ? tres[t] / bn[t] : 0.0) <= o.tol;
+            if (ok) break;
+            if (!any) tol_p *= 0.1;  // preconditioned residual met but true residual not yet
+        } else if (!any) {
+            break;
+        }
+        if (it >= o.maxiter || cycles > 10000 || tol_p < 1e-30) {
+            *status = RANN_ENOTCONV;
+            break;
+        }
+    }
+    std::vector<int32_t> ith(k);
+    RDD_HIP(hipMemcpyAsync(ith.data(), iters, sizeof(int32_t) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    iters_out.assign(ith.begin(), ith.end());
+    return RANN_OK;
+}
+
+int krylov_gmres(Handle& h, const double* Fs, int k, const double* W0, const rann_dd_solve_opts& o,
+                 double* W, rann_dd_stats* st, int* status) {
+    double* rhs = nullptr;
+    double* part = nullptr;
+    RDD_TRY(dev_alloc(h, &rhs, (size_t)h.P * k));
+    RDD_TRY(dev_alloc(h, &part, (size_t)h.part_total * k));
+    RDD_TRY(launch_HTy(h, Fs, k, rhs, part));
+    dev_free(h, part);
+    std::vector<int> iters;
+    int rc = gmres_core(h, rhs, Fs, k, W0, o, W, iters, status);
+    dev_free(h, rhs);
+    RDD_TRY(rc);
+    if (st) {
+        std::vector<double> tres(k), bn(k);
+        RDD_TRY(true_residual(h, Fs, W, k, tres.data(), bn.data()));
+        st->iterations = 0;
+        st->converged = 0;
+        st->max_rel_residual = 0.0;
+        for (int t = 0; t < k; ++t) {
+            double rel = bn[t] > 0 ? tres[t] / bn[t] : 0.0;
+            st->iterations = std::max(st->iterations, iters[t]);
+            st->converged += rel <= o.tol ? 1 : 0;
+            st->max_rel_residual = std::max(st->max_rel_residual, rel);
+            if (st->rel_residual) st->rel_residual[t] = rel;
+            if (st->rhs_iterations) st->rhs_iterations[t] = iters[t];
+        }
+        st->shifts = h.shifts;
+    }
+    return RANN_OK;
+}
+
+int adjoint_gmres(Handle& h, const double* dW, int k, const rann_dd_solve_opts& o, double* z,
+                  rann_dd_stats* st, int* status) {
+    std::vector<int> iters;
+    RDD_TRY(gmres_core(h, dW, nullptr, k, nullptr, o, z, iters, status));
+    if (st) {
+        st->iterations = 0;
+        for (int t = 0; t < k; ++t) {
+            st->iterations = std::max(st->iterations, iters[t]);
+            if (st->rhs_iterations) st->rhs_iterations[t] = iters[t];
+        }
+        st->converged = k;
+        st->max_rel_residual = 0.0;
+        st->shifts = h.shifts;
+    }
+    return RANN_OK;
+}
+
+// ------------------------------------------------------------------ probes
+int coeffs_raw(Handle& h, const double* W, int k, double* c, bool transpose) {
+    if (!transpose) {
+        hipLaunchKernelGGL(k_coeffs, dim3(grid_for(h.sum_m * k)), dim3(256), 0, h.stream, h.sum_m, k,
+                           h.d_feat_sub, h.d_m_off, h.d_p, h.d_v_off, h.d_col_off, h.d_V, W, c);
+    } else {
+        hipLaunchKernelGGL(k_coeffs_T, dim3(grid_for(h.P * k)), dim3(256), 0, h.stream, h.P, k,
+                           h.d_col_sub, h.d_m_off, h.d_m, h.d_p, h.d_v_off, h.d_col_off, h.d_V, W, c);
+    }
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
+int eval_points(Handle& h, const double* Xq, int64_t M, const double* Lq, const double* W, int k,
+                double* U, bool transpose) {
+    PointSet ps;
+    size_t mark = h.allocs.size();
+    auto cleanup = [&]() {
+        // free every allocation made for this probe set
+        std::vector<void*> mine(h.allocs.begin() + mark, h.allocs.end());
+        for (void* p : mine) dev_free(h, p);
+    };
+    int rc = bin_points(h, Xq, M, ps);
+    if (rc == RANN_OK)
+        rc = pair_records(h, Xq, 0, nullptr, nullptr, nullptr, nullptr, M, 1.0, true, Lq, ps);
+    double* cf = nullptr;
+    double* val = nullptr;
+    if (rc == RANN_OK) rc = dev_alloc(h, &cf, (size_t)h.sum_m * k);
+    if (rc == RANN_OK && !transpose) rc = dev_alloc(h, &val, (size_t)ps.pairs * k);
+    if (rc == RANN_OK && !transpose) {
+        rc = coeffs_raw(h, W, k, cf, false);
+        for (int k0 = 0; rc == RANN_OK && k0 < k;) {
+            int kb = kb_for(k - k0);
+#define RDD_EV(KBV)                                                                                    \
+    hipLaunchKernelGGL((k_eval_pairs<KBV>), dim3(grid_for(ps.pairs)), dim3(256), 0, h.stream, h.geo, \
+                       ps.pairs, ps.d_pair_sub, ps.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, cf, k, k0, \
+                       val)
+            switch (kb) {
+                case 32: RDD_EV(32); break;
+                case 16: RDD_EV(16); break;
+                case 8: RDD_EV(8); break;
+                case 4: RDD_EV(4); break;
+                case 2: RDD_EV(2); break;
+                default: RDD_EV(1); break;
+            }
+#undef RDD_EV
+            k0 += kb;
+        }
+        hipLaunchKernelGGL(k_point_sum, dim3(grid_for(M * k)), dim3(256), 0, h.stream, M, k,
+                           ps.d_cover_off, ps.d_cover, val, U);
+    } else if (rc == RANN_OK) {
+        // U holds dW (output), W holds dU (input) in the transposed call
+        for (int k0 = 0; k0 < k;) {
+            int kb = kb_for(k - k0);
+#define RDD_ET(KBV)                                                                                 \
+    hipLaunchKernelGGL((k_eval_T<KBV>), dim3(h.geo.J), dim3(256), 0, h.stream, h.geo, ps.d_row_off, \
+                       ps.d_rows, ps.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, W, k, k0, cf)
+            switch (kb) {
+                case 32: RDD_ET(32); break;
+                case 16: RDD_ET(16); break;
+                case 8: RDD_ET(8); break;
+                case 4: RDD_ET(4); break;
+                case 2: RDD_ET(2); break;
+                default: RDD_ET(1); break;
+            }
+#undef RDD_ET
+            k0 += kb;
+        }
+        rc = coeffs_raw(h, cf, k, U, true);
+    }
+    if (rc == RANN_OK) {
+        hipError_t e = hipStreamSynchronize(h.stream);
+        if (e != hipSuccess) {
+            set_error(std::string("eval: ") + hipGetErrorString(e));
+            rc = RANN_EDEVICE;
+        }
+    }
+    cleanup();
+    return rc;
+}
+
+}  // namespace rdd

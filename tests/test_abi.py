@@ -1,0 +1,123 @@
+"""Host-only checks of the C interface: the library loads, exports every entry
+point the header declares, and rejects invalid arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2412_19207_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rann_dd.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2412_19207_amd import build
+        build.build()
+    return binding.load()
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"RANN_API\s+(?:int|void|const char\*)\s+(rann_dd_\w+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for required in ["rann_dd_assemble", "rann_dd_pca", "rann_dd_solve", "rann_dd_solve_backward"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+        assert name in binding._SIGS, f"binding lacks {name}"
+
+
+def test_struct_layouts_match_header():
+    # offsets computed by ctypes must match the C layout (natural alignment)
+    assert ctypes.sizeof(binding.SolveOpts) == 24
+    assert binding.Desc.lambda_B.offset % 8 == 0
+    assert ctypes.sizeof(binding.Info) % 8 == 0
+
+
+def _valid_desc(keep):
+    d = binding.Desc()
+    d.d = 2
+    d.l[0], d.l[1], d.l[2], d.l[3] = 2, 2, 1, 1
+    mu = np.array([0.25, 0.75, 0.25, 0.75])
+    m = np.array([4, 4, 4, 4], dtype=np.int32)
+    keep += [mu, m]
+    d.mu = mu.ctypes.data_as(binding.c_dp)
+    d.m = m.ctypes.data_as(binding.c_ip)
+    d.sigma[0] = d.sigma[1] = 0.3
+    d.sigma[2] = d.sigma[3] = 1.0
+    # host addresses stand in for device pointers: validation rejects before any use
+    fake = np.zeros(64)
+    keep.append(fake)
+    ptr = fake.ctypes.data
+    d.R = d.b = d.X_int = d.a = d.beta = d.c = ptr
+    d.n_int = 4
+    d.n_bnd = 0
+    d.lambda_B = 1.0
+    d.precision = binding.FP64
+    d.stencil = 2
+    d.precond = 1
+    return d
+
+
+@pytest.mark.parametrize("field,value", [
+    ("d", 0), ("d", 5), ("lambda_B", -1.0), ("lambda_B", float("nan")), ("precision", 7),
+    ("stencil", 9), ("precond", -2), ("n_int", 0),
+])
+def test_invalid_descriptor_is_rejected(lib, field, value):
+    keep = []
+    d = _valid_desc(keep)
+    setattr(d, field, value)
+    h = ctypes.c_void_p()
+    rc = lib.rann_dd_assemble(ctypes.byref(d), None, ctypes.byref(h))
+    assert rc == binding.RANN_EINVAL
+    assert not h.value
+    assert len(binding.rann_dd_last_error()) > 0
+
+
+def test_non_increasing_centres_rejected(lib):
+    keep = []
+    d = _valid_desc(keep)
+    mu = np.array([0.75, 0.25, 0.25, 0.75])
+    keep.append(mu)
+    d.mu = mu.ctypes.data_as(binding.c_dp)
+    h = ctypes.c_void_p()
+    assert lib.rann_dd_assemble(ctypes.byref(d), None, ctypes.byref(h)) == binding.RANN_EINVAL
+
+
+def test_bad_width_rejected(lib):
+    keep = []
+    d = _valid_desc(keep)
+    m = np.array([4, 0, 4, 4], dtype=np.int32)
+    keep.append(m)
+    d.m = m.ctypes.data_as(binding.c_ip)
+    h = ctypes.c_void_p()
+    assert lib.rann_dd_assemble(ctypes.byref(d), None, ctypes.byref(h)) == binding.RANN_EINVAL
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    opts = binding.SolveOpts(tol=1e-8, maxiter=10, method=0, restart=10, check_every=1)
+    assert lib.rann_dd_solve(None, None, 1, None, ctypes.byref(opts), None, None) == binding.RANN_EINVAL
+    assert lib.rann_dd_pca(None, 1e-8, 0, None, None, None) == binding.RANN_EINVAL
+    assert lib.rann_dd_get_info(None, None) == binding.RANN_EINVAL
+    lib.rann_dd_destroy(None)
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The binding, the build script and the kernels must not import or name the oracle."""
+    pkg = os.path.join(ROOT, "paper_2412_19207_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
