@@ -30,7 +30,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # dense FP64 (matrix cores and vector ALUs)
+FP32_PEAK_TFLOPS = 157.3
+KERNELS = ["k_eig", "k_factor_inverse", "k_pca_gram", "k_feat_rows", "k_local_gram", "k_Hx",
+           "k_HTy_part", "k_local_apply"]
 
 
 def parse():
@@ -59,12 +63,44 @@ class Inputs:
         self.binding = binding
 
 
-def run_step(inp, precision, stencil, tol, torch, timings=None):
-    """One pass of the path; returns (solve info, adjoint info)."""
+def work_model(s, prob, k):
+    """Algorithmic work per launch of each timed kernel (bytes the method must
+    move, or flops it must do), from the handle's sizes."""
+    row_off, _, p = s.layout()
+    n = np.diff(row_off).astype(np.float64)
+    m = np.asarray(prob.m, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    q = s.blocks().astype(np.float64)
+    nnz, N, P = float(s.info.nnz), float(s.info.N), float(s.info.P)
+    f_bytes = 4.0 if s.precision == "mixed" else 8.0
+    return {
+        # nominal count of a dense symmetric eigendecomposition with vectors
+        "k_eig": ("alu", float(np.sum(9.0 * m ** 3)), "flop", FP64_PEAK_TFLOPS),
+        # Cholesky q^3/3 + triangular inverse q^3/3 + X^T X q^3/3
+        "k_factor_inverse": ("mfma", float(np.sum(q ** 3)), "flop",
+                             FP32_PEAK_TFLOPS if s.precision == "mixed" else FP64_PEAK_TFLOPS),
+        # symmetric rank-n update Psi^T Psi
+        "k_pca_gram": ("mfma", float(np.sum(n * m * m)), "flop", FP64_PEAK_TFLOPS),
+        "k_feat_rows": ("mfma", float(np.sum(2.0 * n * m * p)), "flop", FP64_PEAK_TFLOPS),
+        # Gram blocks H_j^T H_k: counted for the diagonal blocks only (a lower bound)
+        "k_local_gram": ("mfma", float(np.sum(2.0 * n * p * p)), "flop",
+                         FP32_PEAK_TFLOPS if s.precision == "mixed" else FP64_PEAK_TFLOPS),
+        # H read once, x read, y written
+        "k_Hx": ("hbm", 8.0 * (nnz + P * k + N * k), "byte", HBM_PEAK_GBS),
+        "k_HTy_part": ("hbm", 8.0 * (nnz + N * k + P * k), "byte", HBM_PEAK_GBS),
+        # local inverses read once, gathered r and local results
+        "k_local_apply": ("hbm", f_bytes * float(np.sum(q * q)) + 16.0 * float(np.sum(q)) * k, "byte",
+                          HBM_PEAK_GBS),
+    }
+
+
+def run_step(inp, precision, stencil, tol, torch, timings=None, want_model=False):
+    """One pass of the path; returns (solve info, adjoint info, work model or None)."""
     b = inp.binding
     sync = torch.cuda.synchronize
     t0 = time.perf_counter()
     s = b.Solver(inp.prob, precision=precision, stencil=stencil, precond="as")
+    s.precision = precision
     if timings is not None:
         sync()
         timings["assemble_ms"] = (time.perf_counter() - t0) * 1e3
@@ -86,8 +122,9 @@ def run_step(inp, precision, stencil, tol, torch, timings=None):
     if timings is not None:
         sync()
         timings["eval_adjoint_ms"] = (time.perf_counter() - t0) * 1e3
+    model = work_model(s, inp.prob, inp.prob.F.shape[1]) if want_model else None
     s.close()
-    return info, ainfo, s
+    return info, ainfo, model
 
 
 def solve_only(inp, precision, stencil, tol, torch, reps=3):
@@ -145,14 +182,38 @@ def main():
     for _ in range(args.warmup):
         run_step(inp, "fp64", args.stencil, args.tol, torch)
     torch.cuda.synchronize()
+    binding.rann_dd_ktime_enable(True)
     t0 = time.perf_counter()
     last = None
     for _ in range(args.steps):
         last = run_step(inp, "fp64", args.stencil, args.tol, torch)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    ktimes = {name: binding.rann_dd_ktime_query(name) for name in KERNELS}
+    binding.rann_dd_ktime_enable(False)
     ms_step = elapsed / args.steps * 1e3
     info, ainfo, _ = last
+    tm = {}
+    _, _, model = run_step(inp, "fp64", args.stencil, args.tol, torch, timings=tm, want_model=True)
+    # dominant kernel over the timed region and its roofline position
+    dom = max(ktimes, key=lambda n: ktimes[n][0])
+    tot_ms, launches = ktimes[dom]
+    avg_s = tot_ms / max(launches, 1) / 1e3
+    bound, work, wunit, peak = model[dom]
+    achieved = work / avg_s / (1e9 if wunit == "byte" else 1e12)
+    roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
+                "unit": "GB/s" if wunit == "byte" else "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "avg_launch_us": avg_s * 1e6, "launches": launches,
+                "algorithmic_work_per_launch": work}
+    kernel_table = {}
+    for name, (ms, cnt) in ktimes.items():
+        if cnt == 0:
+            continue
+        b_, w_, u_, pk_ = model[name]
+        av = ms / cnt / 1e3
+        ach = w_ / av / (1e9 if u_ == "byte" else 1e12)
+        kernel_table[name] = {"ms_per_step": ms / args.steps, "avg_us": av * 1e6, "bound": b_,
+                              "achieved": ach, "frac": ach / pk_}
 
     out = {
         "metric": "time-to-1e-6 residual & solves/s, mixed-batched vs FP64 AS-CG; fwd+bwd ms",
@@ -174,10 +235,10 @@ def main():
         "iterations": int(info["iterations"]),
         "adjoint_iterations": int(ainfo["iterations"]),
         "rel_residual": float(info["max_rel_residual"]),
+        "roofline": roofline,
+        "kernels": kernel_table,
     }
     if not args.quick:
-        tm = {}
-        run_step(inp, "fp64", args.stencil, args.tol, torch, timings=tm)
         out["phases_ms"] = tm
         so = solve_only(inp, "fp64", args.stencil, args.tol, torch)
         out["time_to_1e-6_ms"] = {"end_to_end": tm["assemble_ms"] + tm["pca_factor_ms"] + tm["solve_ms"],

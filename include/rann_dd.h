@@ -202,6 +202,20 @@ RANN_API int rann_dd_get_info(const rann_dd_handle* h, rann_dd_info* out);
 RANN_API int rann_dd_get_layout(const rann_dd_handle* h, int64_t* row_off, int32_t* rows, int32_t* p);
 RANN_API int rann_dd_get_arrays(const rann_dd_handle* h, double* blocks, double* V, double* eig);
 
+/* Host copy of the Schwarz block sizes q_i (J entries; zeros without a
+ * preconditioner).  Valid after rann_dd_pca. */
+RANN_API int rann_dd_get_blocks(const rann_dd_handle* h, int64_t* q);
+
+/* Kernel timing for measurement (process-wide, off by default).  When enabled,
+ * the main kernels are bracketed by HIP events on the stream they run on;
+ * rann_dd_ktime_enable(on) also clears the accumulated times.  Query by kernel
+ * name ("k_eig", "k_factor_inverse", "k_pca_gram", "k_feat_rows",
+ * "k_local_gram", "k_Hx", "k_HTy_part", "k_local_apply"): total milliseconds
+ * and number of launches since the last enable.  Query synchronises on the
+ * recorded events. */
+RANN_API int rann_dd_ktime_enable(int32_t on);
+RANN_API int rann_dd_ktime_query(const char* name, double* total_ms, int64_t* launches);
+
 /* Release the handle and its device memory (NULL is ignored). */
 RANN_API void rann_dd_destroy(rann_dd_handle* h);
 

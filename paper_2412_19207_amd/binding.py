@@ -79,6 +79,10 @@ _SIGS = {
     "rann_dd_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     "rann_dd_get_layout": (ctypes.c_int, [ctypes.c_void_p, c_lp, c_ip, c_ip]),
     "rann_dd_get_arrays": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rann_dd_get_blocks": (ctypes.c_int, [ctypes.c_void_p, c_lp]),
+    "rann_dd_ktime_enable": (ctypes.c_int, [ctypes.c_int32]),
+    "rann_dd_ktime_query": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int64)]),
     "rann_dd_destroy": (None, [ctypes.c_void_p]),
     "rann_dd_last_error": (ctypes.c_char_p, []),
 }
@@ -199,6 +203,23 @@ def rann_dd_get_arrays(h, blocks_ptr=0, V_ptr=0, eig_ptr=0):
     return _check(load().rann_dd_get_arrays(h, ctypes.c_void_p(blocks_ptr) if blocks_ptr else None,
                                             ctypes.c_void_p(V_ptr) if V_ptr else None,
                                             ctypes.c_void_p(eig_ptr) if eig_ptr else None))
+
+
+def rann_dd_get_blocks(h, J):
+    q = np.zeros(J, dtype=np.int64)
+    _check(load().rann_dd_get_blocks(h, q.ctypes.data_as(c_lp)))
+    return q
+
+
+def rann_dd_ktime_enable(on: bool):
+    return _check(load().rann_dd_ktime_enable(1 if on else 0))
+
+
+def rann_dd_ktime_query(name: str):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load().rann_dd_ktime_query(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def rann_dd_destroy(h):
@@ -361,6 +382,9 @@ class Solver:
     # -- internal arrays (verification)
     def layout(self):
         return rann_dd_get_layout(self.handle, self.J, self.info.pairs, with_p=self.info.pca_done == 1)
+
+    def blocks(self):
+        return rann_dd_get_blocks(self.handle, self.J)
 
     def arrays(self):
         torch = self.torch

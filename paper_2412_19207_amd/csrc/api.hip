@@ -2,9 +2,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +18,40 @@ namespace rdd {
 static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+// ------------------------------------------------------------ kernel timing
+namespace {
+std::atomic<int> g_ktime_on{0};
+std::mutex g_ktime_mu;
+struct KRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::vector<KRec> g_ktime_pending;
+std::map<std::string, std::pair<double, int64_t>> g_ktime_acc;
+
+void ktime_flush_locked() {
+    for (auto& r : g_ktime_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto& e = g_ktime_acc[r.name];
+            e.first += ms;
+            e.second += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_ktime_pending.clear();
+}
+}  // namespace
+
+bool ktime_enabled() { return g_ktime_on.load(std::memory_order_relaxed) != 0; }
+
+void ktime_record(const char* name, hipEvent_t a, hipEvent_t b) {
+    std::lock_guard<std::mutex> lk(g_ktime_mu);
+    g_ktime_pending.push_back({name, a, b});
+    if (g_ktime_pending.size() > 4096) ktime_flush_locked();
+}
 
 void dev_free(Handle& h, void* p) {
     if (!p) return;
@@ -244,28 +281,30 @@ static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, con
     double* Vfull = nullptr;
     int64_t* d_g_off = nullptr;
     if (mode != RANN_PCA_OFF && !V_force) {
-        double *G = nullptr, *Z = nullptr;
+        double *G = nullptr, *Z = nullptr, *Y = nullptr;
         int32_t* flags = nullptr;
         RDD_TRY(dev_alloc(h, &G, (size_t)g_off[J]));
         RDD_TRY(dev_alloc(h, &Z, (size_t)g_off[J]));
+        RDD_TRY(dev_alloc(h, &Y, (size_t)g_off[J]));
         RDD_TRY(dev_alloc(h, &d_g_off, (size_t)J + 1));
         RDD_TRY(dev_alloc(h, &flags, 2));
         RDD_HIP(hipMemcpy(d_g_off, g_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
         RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, h.stream));
         RDD_TRY(pca_gram(h, G, g_off.data(), d_g_off));
-        RDD_TRY(eig_batched(h, G, d_g_off, Z, tol, mode, h.d_p, h.d_eig, flags));
+        RDD_TRY(eig_batched(h, G, d_g_off, Z, Y, tol, mode, h.d_p, h.d_eig, flags));
         int32_t fl[2];
         RDD_HIP(hipMemcpy(fl, flags, sizeof(fl), hipMemcpyDeviceToHost));
         RDD_HIP(hipMemcpy(h.p.data(), h.d_p, sizeof(int32_t) * J, hipMemcpyDeviceToHost));
         dev_free(h, Z);
+        dev_free(h, G);
         dev_free(h, flags);
         if (fl[0]) {
-            dev_free(h, G);
+            dev_free(h, Y);
             set_error("symmetric eigensolver did not converge");
             return RANN_EDEVICE;
         }
         if (fl[1]) warn = RANN_WRANKTIE;
-        Vfull = G;
+        Vfull = Y;
     } else {
         for (int j = 0; j < J; ++j) h.p[j] = h.m[j];
         RDD_HIP(hipMemsetAsync(h.d_eig, 0, sizeof(double) * h.sum_m, h.stream));
@@ -343,6 +382,27 @@ static int guard_handle(const rann_dd_handle* hh, bool need_pca) {
 extern "C" {
 
 const char* rann_dd_last_error(void) { return rdd::g_last_error.c_str(); }
+
+int rann_dd_ktime_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(rdd::g_ktime_mu);
+    rdd::ktime_flush_locked();
+    rdd::g_ktime_acc.clear();
+    rdd::g_ktime_on.store(on ? 1 : 0);
+    return RANN_OK;
+}
+
+int rann_dd_ktime_query(const char* name, double* total_ms, int64_t* launches) {
+    if (!name || !total_ms || !launches) {
+        rdd::set_error("invalid ktime_query arguments");
+        return RANN_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(rdd::g_ktime_mu);
+    rdd::ktime_flush_locked();
+    auto it = rdd::g_ktime_acc.find(name);
+    *total_ms = (it == rdd::g_ktime_acc.end()) ? 0.0 : it->second.first;
+    *launches = (it == rdd::g_ktime_acc.end()) ? 0 : it->second.second;
+    return RANN_OK;
+}
 
 int rann_dd_assemble(const rann_dd_desc* desc, void* hip_stream, rann_dd_handle** out) {
     if (!out) {
@@ -546,6 +606,14 @@ int rann_dd_get_arrays(const rann_dd_handle* hh, double* blocks, double* V, doub
     if (blocks) RDD_HIP(hipMemcpy(blocks, h.d_H, sizeof(double) * h.nnz, hipMemcpyDeviceToDevice));
     if (V) RDD_HIP(hipMemcpy(V, h.d_V, sizeof(double) * h.v_off.back(), hipMemcpyDeviceToDevice));
     if (eig) RDD_HIP(hipMemcpy(eig, h.d_eig, sizeof(double) * h.sum_m, hipMemcpyDeviceToDevice));
+    return RANN_OK;
+}
+
+int rann_dd_get_blocks(const rann_dd_handle* hh, int64_t* q) {
+    RDD_TRY(guard_handle(hh, true));
+    if (!q) return (rdd::set_error("q is NULL"), RANN_EINVAL);
+    const Handle& h = hh->h;
+    for (int j = 0; j < h.geo.J; ++j) q[j] = h.q.empty() ? 0 : h.q[j];
     return RANN_OK;
 }
 

@@ -160,6 +160,29 @@ int dev_alloc(Handle& h, T** ptr, size_t count) {
 void dev_free(Handle& h, void* p);
 int ensure_ws(Handle& h, size_t bytes);
 
+// Optional per-kernel timing with HIP events on the launch stream (process-wide,
+// off by default): KTimer t(stream, "k_name"); <launch>; t.stop();
+bool ktime_enabled();
+void ktime_record(const char* name, hipEvent_t a, hipEvent_t b);
+struct KTimer {
+    hipStream_t s;
+    const char* name;
+    hipEvent_t a = nullptr, b = nullptr;
+    KTimer(hipStream_t stream, const char* n) : s(stream), name(n) {
+        if (ktime_enabled() && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, s);
+        else
+            a = b = nullptr;
+    }
+    void stop() {
+        if (a) {
+            (void)hipEventRecord(b, s);
+            ktime_record(name, a, b);
+            a = b = nullptr;
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // launchers (defined in the .hip files)
 int bin_points(Handle& h, const double* X, int64_t n, PointSet& ps);
@@ -169,8 +192,8 @@ int pair_records(Handle& h, const double* X, int64_t n_int, const double* a,
 int exclusive_scan_i64(Handle& h, const int64_t* in, int64_t* out, int64_t n);
 
 int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g_off);
-int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* Z, double tol, int mode,
-                int32_t* d_p, double* d_eig, int32_t* d_tie);
+int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* Z, double* Y, double tol,
+                int mode, int32_t* d_p, double* d_eig, int32_t* d_tie);
 int compact_V(Handle& h, const double* Z, const int64_t* d_g_off, double* V);
 int feature_rows(Handle& h);
 int build_schwarz(Handle& h);

@@ -275,8 +275,10 @@ __global__ void __launch_bounds__(kFT) k_factor_inverse(const int64_t* __restric
 
 template <class T>
 int factor_inverse(Handle& h, T* A, T* M, T* D, int32_t* flags) {
+    KTimer kt_(h.stream, "k_factor_inverse");
     hipLaunchKernelGGL((k_factor_inverse<T>), dim3(h.geo.J), dim3(kFT), 0, h.stream, h.d_f_off, h.d_q,
                        h.d_ub_off, A, M, D, flags, flags + 1);
+    kt_.stop();
     RDD_HIP(hipGetLastError());
     return RANN_OK;
 }

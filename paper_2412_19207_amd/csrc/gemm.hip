@@ -323,8 +323,10 @@ int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g
     RDD_TRY(dev_alloc(h, &d_t, tiles.size()));
     RDD_HIP(hipMemcpyAsync(d_t, tiles.data(), sizeof(GramTile) * tiles.size(),
                            hipMemcpyHostToDevice, h.stream));
+    KTimer kt_(h.stream, "k_pca_gram");
     hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, h.geo, d_t,
                        h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, d_g_off, G);
+    kt_.stop();
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));
     dev_free(h, d_t);
@@ -344,9 +346,11 @@ int feature_rows(Handle& h) {
     RDD_TRY(dev_alloc(h, &d_t, tiles.size()));
     RDD_HIP(hipMemcpyAsync(d_t, tiles.data(), sizeof(GramTile) * tiles.size(),
                            hipMemcpyHostToDevice, h.stream));
+    KTimer kt_(h.stream, "k_feat_rows");
     hipLaunchKernelGGL(k_feat_rows, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, h.geo, d_t,
                        h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, h.d_p,
                        h.d_v_off, h.d_V, h.d_h_off, h.d_H, h.d_H32);
+    kt_.stop();
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));
     dev_free(h, d_t);
@@ -444,8 +448,10 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
     RDD_TRY(dev_alloc(h, &d_tiles, tiles.size()));
     RDD_HIP(hipMemcpy(d_tiles, tiles.data(), sizeof(LocalTile) * tiles.size(), hipMemcpyHostToDevice));
     if (!tiles.empty()) {
+        KTimer kt_(h.stream, "k_local_gram");
         hipLaunchKernelGGL((k_local_gram<T>), dim3((unsigned)tiles.size()), dim3(256), 0, h.stream,
                            d_tiles, d_blocks, d_lj, d_lk, h.d_p, h.d_h_off, H, d_G);
+        kt_.stop();
         RDD_HIP(hipGetLastError());
     }
     // stencil tables and assembly

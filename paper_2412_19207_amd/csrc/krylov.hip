@@ -501,6 +501,7 @@ int launch_Hx(Handle& h, const double* x, int k, double* y, bool) {
     hipLaunchKernelGGL((k_Hx<KBV>), dim3(grid), dim3(256), 0, h.stream, h.N, h.pts.d_cover_off, \
                        h.pts.d_cover, h.pts.d_pair_sub, h.pts.d_row_off, h.d_p, h.d_h_off,     \
                        h.d_col_off, h.d_H, x, k, k0, y)
+        KTimer kt_(h.stream, "k_Hx");
         switch (kb) {
             case 32: RDD_HX(32); break;
             case 16: RDD_HX(16); break;
@@ -509,6 +510,7 @@ int launch_Hx(Handle& h, const double* x, int k, double* y, bool) {
             case 2: RDD_HX(2); break;
             default: RDD_HX(1); break;
         }
+        kt_.stop();
 #undef RDD_HX
         k0 += kb;
     }
@@ -524,6 +526,7 @@ int launch_HTy(Handle& h, const double* y, int k, double* x, double* part) {
     hipLaunchKernelGGL((k_HTy_part<KBV>), dim3(grid), dim3(256), 0, h.stream, h.n_tasks, h.d_tasks, \
                        h.d_chunk_sub, h.d_chunk_off, h.d_part_off, h.pts.d_row_off, h.pts.d_rows, h.d_p, \
                        h.d_h_off, h.d_H, y, k, k0, part)
+        KTimer kt_(h.stream, "k_HTy_part");
         switch (kb) {
             case 32: RDD_HT(32); break;
             case 16: RDD_HT(16); break;
@@ -532,6 +535,7 @@ int launch_HTy(Handle& h, const double* y, int k, double* x, double* part) {
             case 2: RDD_HT(2); break;
             default: RDD_HT(1); break;
         }
+        kt_.stop();
 #undef RDD_HT
         k0 += kb;
     }

@@ -290,11 +290,13 @@ int launch_precond(Handle& h, const double* r, int k, double* z, double* ub) {
         case 2: RDD_LA(T, M, 2); break;      \
         default: RDD_LA(T, M, 1); break;     \
     }
+        KTimer kt_(h.stream, "k_local_apply");
         if (h.precision == RANN_MIXED) {
             RDD_LA_ALL(float, h.d_M32);
         } else {
             RDD_LA_ALL(double, h.d_M64);
         }
+        kt_.stop();
 #undef RDD_LA_ALL
 #undef RDD_LA
         k0 += kb;
