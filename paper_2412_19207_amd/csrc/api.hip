@@ -283,15 +283,21 @@ static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, con
     if (mode != RANN_PCA_OFF && !V_force) {
         double *G = nullptr, *Z = nullptr, *Y = nullptr;
         int32_t* flags = nullptr;
+        int64_t* d_s_off = nullptr;
+        std::vector<int64_t> s_off(J + 1, 0);  // eigensolver scratch: 6 m^2 per subdomain
+        for (int j = 0; j < J; ++j) s_off[j + 1] = s_off[j] + 6 * (int64_t)h.m[j] * h.m[j];
         RDD_TRY(dev_alloc(h, &G, (size_t)g_off[J]));
-        RDD_TRY(dev_alloc(h, &Z, (size_t)g_off[J]));
+        RDD_TRY(dev_alloc(h, &Z, (size_t)s_off[J]));
         RDD_TRY(dev_alloc(h, &Y, (size_t)g_off[J]));
         RDD_TRY(dev_alloc(h, &d_g_off, (size_t)J + 1));
+        RDD_TRY(dev_alloc(h, &d_s_off, (size_t)J + 1));
         RDD_TRY(dev_alloc(h, &flags, 2));
         RDD_HIP(hipMemcpy(d_g_off, g_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+        RDD_HIP(hipMemcpy(d_s_off, s_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
         RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, h.stream));
         RDD_TRY(pca_gram(h, G, g_off.data(), d_g_off));
-        RDD_TRY(eig_batched(h, G, d_g_off, Z, Y, tol, mode, h.d_p, h.d_eig, flags));
+        RDD_TRY(eig_batched(h, G, d_g_off, Z, d_s_off, Y, tol, mode, h.d_p, h.d_eig, flags));
+        dev_free(h, d_s_off);
         int32_t fl[2];
         RDD_HIP(hipMemcpy(fl, flags, sizeof(fl), hipMemcpyDeviceToHost));
         RDD_HIP(hipMemcpy(h.p.data(), h.d_p, sizeof(int32_t) * J, hipMemcpyDeviceToHost));

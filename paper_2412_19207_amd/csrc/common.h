@@ -192,8 +192,8 @@ int pair_records(Handle& h, const double* X, int64_t n_int, const double* a,
 int exclusive_scan_i64(Handle& h, const int64_t* in, int64_t* out, int64_t n);
 
 int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g_off);
-int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* Z, double* Y, double tol,
-                int mode, int32_t* d_p, double* d_eig, int32_t* d_tie);
+int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const int64_t* d_s_off,
+                double* Y, double tol, int mode, int32_t* d_p, double* d_eig, int32_t* d_tie);
 int compact_V(Handle& h, const double* Z, const int64_t* d_g_off, double* V);
 int feature_rows(Handle& h);
 int build_schwarz(Handle& h);
