@@ -100,13 +100,17 @@ struct Handle {
     int32_t* d_prec_row_blk = nullptr;
     int64_t ub_total = 0;          // sum q_i
 
-    // H^T y: row chunks of each block, partial sums per chunk
+    // products with H: row chunks of each block, partial sums per chunk
     std::vector<int64_t> chunk_off; // J+1 (chunks per subdomain)
-    int64_t n_chunks = 0, n_tasks = 0, part_total = 0;
+    int64_t n_chunks = 0, part_total = 0;
     int64_t* d_chunk_off = nullptr; // J+1
     int32_t* d_chunk_sub = nullptr; // n_chunks: subdomain of each chunk
     int64_t* d_part_off = nullptr;  // n_chunks: column offset of each chunk's partial
-    int32_t* d_tasks = nullptr;     // n_tasks x 2: (chunk, 64-column block)
+    int64_t* d_col_pbase = nullptr; // P: first chunk partial of each column
+    int32_t* d_col_pstride = nullptr; // P: distance between its chunk partials (p_j)
+    int32_t* d_col_nch = nullptr;   // P: number of chunk partials
+    double* d_tpair = nullptr;      // per-pair values of H x
+    size_t tpair_elems = 0;
     int32_t* d_col_sub = nullptr;   // P: subdomain of each column
     int32_t* d_feat_sub = nullptr;  // sum_m: subdomain of each hidden feature
 
@@ -204,6 +208,7 @@ int plan_products(Handle& h);
 int launch_Hx(Handle& h, const double* x, int k, double* y, bool scale_bnd);
 int launch_HTy(Handle& h, const double* y, int k, double* x, double* partial);
 int launch_precond(Handle& h, const double* r, int k, double* z, double* ub);
+int launch_precond_local(Handle& h, const double* r, int k, double* ub);
 
 int krylov_cg(Handle& h, const double* rhs, int k, const double* W0, const rann_dd_solve_opts& o,
               double* W, rann_dd_stats* st, int* status);

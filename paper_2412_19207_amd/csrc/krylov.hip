@@ -21,80 +21,6 @@ namespace {
 constexpr int kDotBlocks = 240;
 constexpr int kChunkRows = 128;
 
-// ------------------------------------------------------------------ H x
-// one wave per global row: y[r] = sum over the subdomains covering r of H_j[row] . x_j
-template <int KB>
-__global__ void __launch_bounds__(256) k_Hx(int64_t N, const int64_t* __restrict__ cover_off,
-                                            const int64_t* __restrict__ cover,
-                                            const int32_t* __restrict__ pair_sub,
-                                            const int64_t* __restrict__ row_off,
-                                            const int32_t* __restrict__ p,
-                                            const int64_t* __restrict__ h_off,
-                                            const int64_t* __restrict__ col_off,
-                                            const double* __restrict__ H,
-                                            const double* __restrict__ x, int k, int k0,
-                                            double* __restrict__ y) {
-    const int lane = threadIdx.x & 63;
-    const int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= N) return;
-    double acc[KB];
-    for (int t = 0; t < KB; ++t) acc[t] = 0.0;
-    for (int64_t c = cover_off[r]; c < cover_off[r + 1]; ++c) {
-        const int64_t pid = cover[c];
-        const int j = pair_sub[pid];
-        const int pj = p[j];
-        const double* Hr = H + h_off[j] + (pid - row_off[j]) * pj;
-        const double* xj = x + col_off[j] * k + k0;
-        for (int q = lane; q < pj; q += 64) {
-            const double hv = Hr[q];
-            for (int t = 0; t < KB; ++t) acc[t] = fma(hv, xj[(int64_t)q * k + t], acc[t]);
-        }
-    }
-    for (int t = 0; t < KB; ++t)
-        for (int off = 32; off > 0; off >>= 1) acc[t] += __shfl_xor(acc[t], off);
-    if (lane == 0)
-        for (int t = 0; t < KB; ++t) y[r * k + k0 + t] = acc[t];
-}
-
-// ------------------------------------------------------------------ H^T y
-// one wave per (row chunk of a block, 64-column slab): partial column sums
-template <int KB>
-__global__ void __launch_bounds__(256) k_HTy_part(int64_t n_tasks, const int32_t* __restrict__ tasks,
-                                                  const int32_t* __restrict__ chunk_sub,
-                                                  const int64_t* __restrict__ chunk_off,
-                                                  const int64_t* __restrict__ part_off,
-                                                  const int64_t* __restrict__ row_off,
-                                                  const int32_t* __restrict__ rows,
-                                                  const int32_t* __restrict__ p,
-                                                  const int64_t* __restrict__ h_off,
-                                                  const double* __restrict__ H,
-                                                  const double* __restrict__ y, int k, int k0,
-                                                  double* __restrict__ part) {
-    const int lane = threadIdx.x & 63;
-    const int64_t task = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (task >= n_tasks) return;
-    const int ch = tasks[2 * task], slab = tasks[2 * task + 1];
-    const int j = chunk_sub[ch];
-    const int pj = p[j];
-    const int c = slab * 64 + lane;
-    const int64_t n = row_off[j + 1] - row_off[j];
-    const int64_t lc = ch - chunk_off[j];
-    const int64_t r0 = lc * kChunkRows, r1 = (r0 + kChunkRows < n) ? r0 + kChunkRows : n;
-    double acc[KB];
-    for (int t = 0; t < KB; ++t) acc[t] = 0.0;
-    const double* Hj = H + h_off[j];
-    const int32_t* Sj = rows + row_off[j];
-    if (c < pj) {
-        for (int64_t r = r0; r < r1; ++r) {
-            const double hv = Hj[r * pj + c];
-            const double* yr = y + (int64_t)Sj[r] * k + k0;
-            for (int t = 0; t < KB; ++t) acc[t] = fma(hv, yr[t], acc[t]);
-        }
-        double* o = part + (part_off[ch] + c) * k + k0;
-        for (int t = 0; t < KB; ++t) o[t] = acc[t];
-    }
-}
-
 __global__ void k_HTy_reduce(int64_t P, int k, const int32_t* __restrict__ col_sub,
                              const int64_t* __restrict__ col_off,
                              const int64_t* __restrict__ chunk_off,
@@ -484,6 +410,214 @@ __global__ void k_coeffs_T(int64_t P, int k, const int32_t* __restrict__ col_sub
     dW[idx] = s;
 }
 
+// ------------------------------------------------------------------ fused CG pieces
+// Producers of dot products write per-workgroup partial sums (kRed workgroups,
+// grid-stride, stride a multiple of k so every thread keeps one right-hand
+// side); consumers sum the partials in a fixed order.
+constexpr int kRed = 120;
+
+__device__ inline int64_t rhs_stride(int k) { return ((int64_t)kRed * 256 / k) * k; }
+
+// Per-workgroup partial sums by right-hand side, fixed-order tree.  The grid
+// stride is a multiple of k, so thread x of block b always handles RHS
+// t = (b * 256 + x) % k; threads are grouped by that t.
+__device__ void block_partial_by_rhs(double val, int k, double* sh, double* out) {
+    sh[threadIdx.x] = val;
+    __syncthreads();
+    if (k == 1) {
+        for (int st = 128; st > 0; st >>= 1) {
+            if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+        __syncthreads();
+        return;
+    }
+    // general k: thread x with e = x belongs to t(e) = (base + e) % k; sum the
+    // entries of each t along e = e0, e0 + k, ... with a pairwise tree
+    const int base = (int)(((int64_t)blockIdx.x * 256) % k);
+    const int groups = (256 + k - 1) / k;  // entries per t (at most)
+    for (int st = 1; st < groups; st <<= 1) {
+        const int e = threadIdx.x;
+        // e is the first entry of a pair at this level when its index along
+        // its t-chain is a multiple of 2 st
+        const int t = (base + e) % k;
+        int e0 = (t - base) % k;
+        if (e0 < 0) e0 += k;
+        const int idx = (e - e0) / k;
+        if ((idx % (2 * st)) == 0 && e + st * k < 256) sh[e] += sh[e + st * k];
+        __syncthreads();
+    }
+    if (threadIdx.x < k) {
+        const int t = threadIdx.x;
+        int e0 = (t - base) % k;
+        if (e0 < 0) e0 += k;
+        out[blockIdx.x * k + t] = (e0 < 256) ? sh[e0] : 0.0;
+    }
+    __syncthreads();
+}
+
+// res[t] = sum over the kRed partials (fixed-order tree), for t < k
+__device__ void sum_partials(const double* part, int k, double* res, double* sh) {
+    const int per = 256 / k;
+    const int t = threadIdx.x % k, ro = threadIdx.x / k;
+    double acc = 0.0;
+    if (ro < per)
+        for (int b = ro; b < kRed; b += per) acc += part[b * k + t];
+    sh[threadIdx.x] = (ro < per) ? acc : 0.0;
+    __syncthreads();
+    for (int st = 1; st < per; st <<= 1) {
+        if (ro < per && (ro % (2 * st)) == 0 && ro + st < per) sh[threadIdx.x] += sh[threadIdx.x + st * k];
+        __syncthreads();
+    }
+    if (threadIdx.x < k) res[threadIdx.x] = sh[threadIdx.x];
+    __syncthreads();
+}
+
+// s = H^T y from the chunk partials (column g's partials start at pbase[g]
+// and repeat every pstride[g] columns, nch[g] of them), and partials of <p, s>
+__global__ void __launch_bounds__(256) k_nrm_reduce_dot(int64_t P, int k, const int64_t* __restrict__ pbase,
+                                                        const int32_t* __restrict__ pstride,
+                                                        const int32_t* __restrict__ nch,
+                                                        const double* __restrict__ part,
+                                                        const double* __restrict__ pv,
+                                                        double* __restrict__ s_out,
+                                                        double* __restrict__ partA) {
+    __shared__ double sh[256];
+    const int64_t stride = rhs_stride(k);
+    const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
+    double acc = 0.0;
+    if (i0 < stride) {
+        for (int64_t idx = i0; idx < P * k; idx += stride) {
+            const int64_t g = idx / k;
+            const int t = (int)(idx % k);
+            const int64_t b = pbase[g];
+            const int64_t ps = pstride[g];
+            const int nc = nch[g];
+            double sv = 0.0;
+            for (int q = 0; q < nc; ++q) sv += part[(b + q * ps) * k + t];
+            s_out[idx] = sv;
+            acc = fma(pv[idx], sv, acc);
+        }
+    }
+    block_partial_by_rhs(acc, k, sh, partA);
+}
+
+// alpha = rho / <p, s>; x += alpha p; r -= alpha s; partials of <r, r>
+__global__ void __launch_bounds__(256) k_cg_xr2(int64_t P, int k, const double* __restrict__ partA,
+                                                const double* __restrict__ rho_in,
+                                                const int32_t* __restrict__ active_in,
+                                                const double* __restrict__ p,
+                                                const double* __restrict__ s, double* __restrict__ x,
+                                                double* __restrict__ r, double* __restrict__ partB,
+                                                int32_t* __restrict__ flags) {
+    __shared__ double sh[256];
+    __shared__ double al[256];
+    sum_partials(partA, k, al, sh);
+    if (threadIdx.x < k) {
+        const int t = threadIdx.x;
+        double a = 0.0;
+        if (active_in[t]) {
+            const double pS = al[t];
+            if (!(pS > 0.0)) {
+                if (blockIdx.x == 0) flags[0] = 1;
+            } else {
+                a = rho_in[t] / pS;
+            }
+            if (!isfinite(pS) && blockIdx.x == 0) flags[1] = 1;
+        }
+        al[t] = a;
+    }
+    __syncthreads();
+    const int64_t stride = rhs_stride(k);
+    const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
+    double acc = 0.0;
+    if (i0 < stride) {
+        const double a = al[i0 % k];
+        for (int64_t idx = i0; idx < P * k; idx += stride) {
+            x[idx] = fma(a, p[idx], x[idx]);
+            const double rv = fma(-a, s[idx], r[idx]);
+            r[idx] = rv;
+            acc = fma(rv, rv, acc);
+        }
+    }
+    block_partial_by_rhs(acc, k, sh, partB);
+}
+
+// z = sum of the weighted local solutions (gather form of the Schwarz sum) and
+// partials of <r, z>; without a preconditioner z = r
+__global__ void __launch_bounds__(256) k_gather_dot(int64_t P, int k, int identity,
+                                                    const int64_t* __restrict__ gat_off,
+                                                    const int64_t* __restrict__ gat,
+                                                    const double* __restrict__ gat_w,
+                                                    const double* __restrict__ u,
+                                                    const double* __restrict__ r, double* __restrict__ z,
+                                                    double* __restrict__ partC) {
+    __shared__ double sh[256];
+    const int64_t stride = rhs_stride(k);
+    const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
+    double acc = 0.0;
+    if (i0 < stride) {
+        for (int64_t idx = i0; idx < P * k; idx += stride) {
+            double zv;
+            if (identity) {
+                zv = r[idx];
+            } else {
+                const int64_t g = idx / k;
+                const int t = (int)(idx % k);
+                zv = 0.0;
+                for (int64_t e = gat_off[g]; e < gat_off[g + 1]; ++e) zv += gat_w[e] * u[gat[e] * k + t];
+            }
+            z[idx] = zv;
+            acc = fma(r[idx], zv, acc);
+        }
+    }
+    block_partial_by_rhs(acc, k, sh, partC);
+}
+
+// beta = <r,z> / rho, rho and activity update (workgroup 0 writes the state of
+// the next iteration into the other buffer), p = z + beta p
+__global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, const double* __restrict__ partB,
+                                               const double* __restrict__ partC,
+                                               const double* __restrict__ bn2,
+                                               const double* __restrict__ tol2,
+                                               const double* __restrict__ rho_in,
+                                               double* __restrict__ rho_out,
+                                               const int32_t* __restrict__ active_in,
+                                               int32_t* __restrict__ active_out,
+                                               int32_t* __restrict__ iters, double* __restrict__ rres,
+                                               const double* __restrict__ z, double* __restrict__ p) {
+    __shared__ double sh[256];
+    __shared__ double rr[256];
+    __shared__ double rz[256];
+    sum_partials(partB, k, rr, sh);
+    sum_partials(partC, k, rz, sh);
+    if (threadIdx.x < k) {
+        const int t = threadIdx.x;
+        const int act = active_in[t];
+        const double b = act ? rz[t] / rho_in[t] : 0.0;
+        if (blockIdx.x == 0) {
+            rho_out[t] = act ? rz[t] : rho_in[t];
+            active_out[t] = (act && !(rr[t] <= tol2[t] * bn2[t])) ? 1 : 0;
+            if (act) {
+                iters[t] += 1;
+                rres[t] = sqrt(rr[t] / bn2[t]);
+            }
+        }
+        rz[t] = b;  // reuse as beta
+    }
+    __syncthreads();
+    const int64_t stride = rhs_stride(k);
+    const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
+    if (i0 < stride) {
+        const int t = (int)(i0 % k);
+        if (active_in[t]) {
+            const double b = rz[t];
+            for (int64_t idx = i0; idx < P * k; idx += stride) p[idx] = fma(b, p[idx], z[idx]);
+        }
+    }
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 inline int kb_for(int rem) {
@@ -493,107 +627,31 @@ inline int kb_for(int rem) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-int launch_Hx(Handle& h, const double* x, int k, double* y, bool) {
-    const unsigned grid = (unsigned)((h.N + 3) / 4);
-    for (int k0 = 0; k0 < k;) {
-        int kb = kb_for(k - k0);
-#define RDD_HX(KBV)                                                                             \
-    hipLaunchKernelGGL((k_Hx<KBV>), dim3(grid), dim3(256), 0, h.stream, h.N, h.pts.d_cover_off, \
-                       h.pts.d_cover, h.pts.d_pair_sub, h.pts.d_row_off, h.d_p, h.d_h_off,     \
-                       h.d_col_off, h.d_H, x, k, k0, y)
-        KTimer kt_(h.stream, "k_Hx");
-        switch (kb) {
-            case 32: RDD_HX(32); break;
-            case 16: RDD_HX(16); break;
-            case 8: RDD_HX(8); break;
-            case 4: RDD_HX(4); break;
-            case 2: RDD_HX(2); break;
-            default: RDD_HX(1); break;
-        }
-        kt_.stop();
-#undef RDD_HX
-        k0 += kb;
-    }
-    RDD_HIP(hipGetLastError());
+int launch_Hx_pairs(Handle& h, const double* x, int k, double* y, double* tpair);
+int launch_HTy_part(Handle& h, const double* y, int k, double* part);
+
+// per-pair scratch of H x, grown on demand (kept apart from the Krylov workspace)
+static int ensure_tpair(Handle& h, int k) {
+    const size_t need = (size_t)std::max<int64_t>(h.pts.pairs, 1) * k;
+    if (h.tpair_elems >= need) return RANN_OK;
+    if (h.d_tpair) dev_free(h, h.d_tpair);
+    h.d_tpair = nullptr;
+    h.tpair_elems = 0;
+    RDD_TRY(dev_alloc(h, &h.d_tpair, need));
+    h.tpair_elems = need;
     return RANN_OK;
+}
+
+int launch_Hx(Handle& h, const double* x, int k, double* y, bool) {
+    RDD_TRY(ensure_tpair(h, k));
+    return launch_Hx_pairs(h, x, k, y, h.d_tpair);
 }
 
 int launch_HTy(Handle& h, const double* y, int k, double* x, double* part) {
-    const unsigned grid = (unsigned)((h.n_tasks + 3) / 4);
-    for (int k0 = 0; k0 < k;) {
-        int kb = kb_for(k - k0);
-#define RDD_HT(KBV)                                                                                \
-    hipLaunchKernelGGL((k_HTy_part<KBV>), dim3(grid), dim3(256), 0, h.stream, h.n_tasks, h.d_tasks, \
-                       h.d_chunk_sub, h.d_chunk_off, h.d_part_off, h.pts.d_row_off, h.pts.d_rows, h.d_p, \
-                       h.d_h_off, h.d_H, y, k, k0, part)
-        KTimer kt_(h.stream, "k_HTy_part");
-        switch (kb) {
-            case 32: RDD_HT(32); break;
-            case 16: RDD_HT(16); break;
-            case 8: RDD_HT(8); break;
-            case 4: RDD_HT(4); break;
-            case 2: RDD_HT(2); break;
-            default: RDD_HT(1); break;
-        }
-        kt_.stop();
-#undef RDD_HT
-        k0 += kb;
-    }
+    RDD_TRY(launch_HTy_part(h, y, k, part));
     hipLaunchKernelGGL(k_HTy_reduce, dim3(grid_for(h.P * k)), dim3(256), 0, h.stream, h.P, k,
                        h.d_col_sub, h.d_col_off, h.d_chunk_off, h.d_part_off, part, x);
     RDD_HIP(hipGetLastError());
-    return RANN_OK;
-}
-
-// chunk / task tables for H^T y
-int plan_products(Handle& h) {
-    const int J = h.geo.J;
-    h.chunk_off.assign(J + 1, 0);
-    std::vector<int64_t> part_off;
-    std::vector<int32_t> tasks;
-    int64_t poff = 0;
-    for (int j = 0; j < J; ++j) {
-        int64_t n = h.pts.row_off[j + 1] - h.pts.row_off[j];
-        int64_t nc = (n + kChunkRows - 1) / kChunkRows;
-        if (nc == 0) nc = 1;
-        h.chunk_off[j + 1] = h.chunk_off[j] + nc;
-        int slabs = (h.p[j] + 63) / 64;
-        for (int64_t c = 0; c < nc; ++c) {
-            part_off.push_back(poff);
-            poff += h.p[j];
-            for (int s = 0; s < slabs; ++s) {
-                tasks.push_back((int32_t)(h.chunk_off[j] + c));
-                tasks.push_back(s);
-            }
-        }
-    }
-    h.n_chunks = h.chunk_off[J];
-    h.n_tasks = (int64_t)tasks.size() / 2;
-    h.part_total = poff;
-    std::vector<int64_t> co(h.chunk_off);
-    std::vector<int32_t> chunk_sub(h.n_chunks);
-    for (int j = 0; j < J; ++j)
-        for (int64_t c = h.chunk_off[j]; c < h.chunk_off[j + 1]; ++c) chunk_sub[c] = j;
-    RDD_TRY(dev_alloc(h, &h.d_chunk_sub, chunk_sub.size()));
-    RDD_HIP(hipMemcpy(h.d_chunk_sub, chunk_sub.data(), sizeof(int32_t) * chunk_sub.size(),
-                      hipMemcpyHostToDevice));
-    RDD_TRY(dev_alloc(h, &h.d_chunk_off, co.size()));
-    RDD_TRY(dev_alloc(h, &h.d_part_off, part_off.size()));
-    RDD_TRY(dev_alloc(h, &h.d_tasks, tasks.size()));
-    RDD_HIP(hipMemcpy(h.d_chunk_off, co.data(), sizeof(int64_t) * co.size(), hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h.d_part_off, part_off.data(), sizeof(int64_t) * part_off.size(),
-                      hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h.d_tasks, tasks.data(), sizeof(int32_t) * tasks.size(), hipMemcpyHostToDevice));
-    std::vector<int32_t> col_sub(h.P), feat_sub(h.sum_m);
-    for (int j = 0; j < J; ++j) {
-        for (int64_t c = h.col_off[j]; c < h.col_off[j + 1]; ++c) col_sub[c] = j;
-        for (int64_t f = h.m_off[j]; f < h.m_off[j + 1]; ++f) feat_sub[f] = j;
-    }
-    RDD_TRY(dev_alloc(h, &h.d_col_sub, col_sub.size()));
-    RDD_TRY(dev_alloc(h, &h.d_feat_sub, feat_sub.size()));
-    RDD_HIP(hipMemcpy(h.d_col_sub, col_sub.data(), sizeof(int32_t) * col_sub.size(), hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h.d_feat_sub, feat_sub.data(), sizeof(int32_t) * feat_sub.size(),
-                      hipMemcpyHostToDevice));
     return RANN_OK;
 }
 
@@ -682,7 +740,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
                    std::vector<double>& res_out, int* status) {
     const size_t P = (size_t)h.P, N = (size_t)h.N;
     const size_t need = P * k * 4 + N * k + (size_t)h.part_total * k + (size_t)h.ub_total * k +
-                        (size_t)kDotBlocks * k + 16 * (size_t)k + 1024;
+                        (size_t)kDotBlocks * k + 3 * (size_t)kRed * k + 24 * (size_t)k + 2048;
     RDD_TRY(ensure_ws(h, need * sizeof(double)));
     Scratch sc{static_cast<double*>(h.ws), 0};
     double* r = sc.take(P * k);
@@ -702,10 +760,16 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     double* bn2 = sc.take(k);
     double* rres = sc.take(k);
     double* tol2v = sc.take(k);
-    int32_t* upd = reinterpret_cast<int32_t*>(sc.take(k));
-    int32_t* active = reinterpret_cast<int32_t*>(sc.take(k));
+    double* rhoB = sc.take(2 * (size_t)k);       // rho, double-buffered
+    double* partA = sc.take((size_t)kRed * k);
+    double* partB = sc.take((size_t)kRed * k);
+    double* partC = sc.take((size_t)kRed * k);
+    int32_t* activeB = reinterpret_cast<int32_t*>(sc.take(2 * (size_t)k));  // activity, double-buffered
     int32_t* iters = reinterpret_cast<int32_t*>(sc.take(k));
     int32_t* flags = reinterpret_cast<int32_t*>(sc.take(4));
+    (void)rho; (void)pS; (void)alpha; (void)beta; (void)rz; (void)rr;
+    int par = 0;
+    int32_t* active = activeB;  // current buffer, follows par
     const int64_t Pk = (int64_t)P * k;
 
     RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, h.stream));
@@ -732,7 +796,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     auto restart = [&]() -> int {
         RDD_TRY(launch_precond(h, r, k, z, ub));
         hipLaunchKernelGGL(k_copy, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, z, p);
-        RDD_TRY(dot(h, P, k, r, z, dp, rho));
+        RDD_TRY(dot(h, P, k, r, z, dp, rhoB + (size_t)par * k));
         return RANN_OK;
     };
     RDD_HIP(hipMemcpyAsync(active, act.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, h.stream));
@@ -747,19 +811,26 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     *status = RANN_OK;
     while (true) {
         for (int q = 0; q < every && it < o.maxiter; ++q, ++it) {
-            RDD_TRY(normal_op(h, p, k, y, part, s));
-            RDD_TRY(dot(h, P, k, p, s, dp, pS));
-            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, h.stream, k, pS, rho, active, alpha,
-                               flags);
-            hipLaunchKernelGGL(k_cg_xr, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P, k,
-                               alpha, p, s, W, r);
-            RDD_TRY(dot(h, P, k, r, r, dp, rr));
-            RDD_TRY(launch_precond(h, r, k, z, ub));
-            RDD_TRY(dot(h, P, k, r, z, dp, rz));
-            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, h.stream, k, rz, rr, bn2, tol2v, rho,
-                               beta, active, upd, iters, rres);
-            hipLaunchKernelGGL(k_cg_p, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P, k, beta,
-                               upd, z, p);
+            double* rho_in = rhoB + (size_t)par * k;
+            double* rho_out = rhoB + (size_t)(par ^ 1) * k;
+            int32_t* act_in = activeB + (size_t)par * k;
+            int32_t* act_out = activeB + (size_t)(par ^ 1) * k;
+            // s = H^T H p and <p, s>
+            RDD_TRY(launch_Hx(h, p, k, y, false));
+            RDD_TRY(launch_HTy_part(h, y, k, part));
+            hipLaunchKernelGGL(k_nrm_reduce_dot, dim3(kRed), dim3(256), 0, h.stream, (int64_t)P, k,
+                               h.d_col_pbase, h.d_col_pstride, h.d_col_nch, part, p, s, partA);
+            hipLaunchKernelGGL(k_cg_xr2, dim3(kRed), dim3(256), 0, h.stream, (int64_t)P, k, partA, rho_in,
+                               act_in, p, s, W, r, partB, flags);
+            // z = M^{-1} r and <r, z>
+            const int ident = (h.precond == RANN_PRECOND_NONE) ? 1 : 0;
+            if (!ident) RDD_TRY(launch_precond_local(h, r, k, ub));
+            hipLaunchKernelGGL(k_gather_dot, dim3(kRed), dim3(256), 0, h.stream, (int64_t)P, k, ident,
+                               h.d_gat_off, h.d_gat, h.d_gat_w, ub, r, z, partC);
+            hipLaunchKernelGGL(k_cg_p2, dim3(kRed), dim3(256), 0, h.stream, (int64_t)P, k, partB, partC, bn2,
+                               tol2v, rho_in, rho_out, act_in, act_out, iters, rres, z, p);
+            par ^= 1;
+            active = activeB + (size_t)par * k;
         }
         RDD_HIP(hipGetLastError());
         int32_t fl[4];

@@ -1,0 +1,265 @@
+// Products with the block-sparse collocation matrix H = [H_1 .. H_J] (paper
+// Sec. 3 remark: domain decomposition makes H block sparse).
+//
+// Work is cut into chunks of up to kChunk consecutive rows of one block H_j
+// (stored row-major, n_j x p_j, blocks concatenated), so one workgroup reads
+// one contiguous piece of H:
+//   * y = H x : per chunk, t_pair = H_j[row] . x_j (x_j staged in LDS, one
+//               wave per row, lanes stride the row), then y[r] = sum of the
+//               pair values of row r (the rows two supports share get two);
+//   * x = H^T y: per chunk, column partial sums with the threads laid out as
+//               (row group, column) so consecutive threads read consecutive
+//               addresses, then a fixed-order sum over the chunks of a block.
+// No floating-point atomics: every sum has a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+namespace rdd {
+
+namespace {
+
+constexpr int kChunk = 128;
+constexpr int kHxKB = 8;    // right-hand sides per pass of H x (x_j staged in LDS)
+constexpr int kHTKB = 8;    // right-hand sides per pass of H^T y
+
+template <int KB>
+__global__ void __launch_bounds__(256) k_Hx_chunk(const int32_t* __restrict__ chunk_sub,
+                                                  const int64_t* __restrict__ chunk_off,
+                                                  const int64_t* __restrict__ row_off,
+                                                  const int32_t* __restrict__ p,
+                                                  const int64_t* __restrict__ h_off,
+                                                  const int64_t* __restrict__ col_off,
+                                                  const double* __restrict__ H,
+                                                  const double* __restrict__ x, int k, int k0,
+                                                  double* __restrict__ tpair) {
+    __shared__ double xs[KB][kMaxWidth];
+    const int ch = blockIdx.x;
+    const int j = chunk_sub[ch];
+    const int pj = p[j];
+    const int64_t n = row_off[j + 1] - row_off[j];
+    const int64_t r0 = (ch - chunk_off[j]) * (int64_t)kChunk;
+    const int64_t r1 = (r0 + kChunk < n) ? r0 + kChunk : n;
+    const double* xj = x + col_off[j] * k + k0;
+    for (int e = threadIdx.x; e < pj * KB; e += 256) {
+        const int c = e / KB, t = e % KB;
+        xs[t][c] = xj[(int64_t)c * k + t];
+    }
+    __syncthreads();
+    // L lanes per row (L = 8 .. 64 from the block width), 64 / L rows per wave
+    const int L = pj > 256 ? 64 : pj > 128 ? 32 : pj > 64 ? 16 : 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sub = lane / L, l = lane % L, rpw = 64 / L;
+    const double* Hj = H + h_off[j];
+    for (int64_t rb = r0 + (int64_t)wave * rpw; rb < r1; rb += 4 * rpw) {
+        const int64_t r = rb + sub;
+        double acc[KB];
+        for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+        if (r < r1) {
+            const double* Hr = Hj + r * pj;
+            for (int c = l; c < pj; c += L) {
+                const double hv = Hr[c];
+                for (int t = 0; t < KB; ++t) acc[t] = fma(hv, xs[t][c], acc[t]);
+            }
+        }
+        for (int t = 0; t < KB; ++t)
+            for (int off = L >> 1; off > 0; off >>= 1) acc[t] += __shfl_xor(acc[t], off);
+        if (l == 0 && r < r1) {
+            double* o = tpair + (row_off[j] + r) * k + k0;
+            for (int t = 0; t < KB; ++t) o[t] = acc[t];
+        }
+    }
+}
+
+// y[r][t] = sum over the pairs of point r (ascending subdomain order)
+__global__ void k_pair_to_rows(int64_t n, int k, const int64_t* __restrict__ cover_off,
+                               const int64_t* __restrict__ cover, const double* __restrict__ tpair,
+                               double* __restrict__ y) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * k) return;
+    const int64_t r = idx / k;
+    const int t = (int)(idx % k);
+    double s = 0.0;
+    for (int64_t c = cover_off[r]; c < cover_off[r + 1]; ++c) s += tpair[cover[c] * k + t];
+    y[idx] = s;
+}
+
+template <int KB>
+__global__ void __launch_bounds__(256) k_HTy_chunk(const int32_t* __restrict__ chunk_sub,
+                                                   const int64_t* __restrict__ chunk_off,
+                                                   const int64_t* __restrict__ part_off,
+                                                   const int64_t* __restrict__ row_off,
+                                                   const int32_t* __restrict__ rows,
+                                                   const int32_t* __restrict__ p,
+                                                   const int64_t* __restrict__ h_off,
+                                                   const double* __restrict__ H,
+                                                   const double* __restrict__ y, int k, int k0,
+                                                   double* __restrict__ part) {
+    __shared__ double ys[kChunk][KB];
+    __shared__ double red[256 * KB];
+    const int ch = blockIdx.x;
+    const int j = chunk_sub[ch];
+    const int pj = p[j];
+    const int64_t n = row_off[j + 1] - row_off[j];
+    const int64_t r0 = (ch - chunk_off[j]) * (int64_t)kChunk;
+    const int nr = (int)((r0 + kChunk < n) ? kChunk : n - r0);
+    const int32_t* Sj = rows + row_off[j];
+    for (int e = threadIdx.x; e < nr * KB; e += 256) {
+        const int rr = e / KB, t = e % KB;
+        ys[rr][t] = y[(int64_t)Sj[r0 + rr] * k + k0 + t];
+    }
+    __syncthreads();
+    const double* Hj = H + h_off[j] + r0 * pj;
+    for (int c0 = 0; c0 < pj; c0 += 256) {
+        const int pc = (pj - c0 < 256) ? pj - c0 : 256;   // columns in this pass
+        const int G = 256 / pc;                            // row groups
+        const int g = threadIdx.x / pc, c = threadIdx.x % pc;
+        double acc[KB];
+        for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+        if (g < G) {
+            for (int rr = g; rr < nr; rr += G) {
+                const double hv = Hj[(int64_t)rr * pj + c0 + c];
+                for (int t = 0; t < KB; ++t) acc[t] = fma(hv, ys[rr][t], acc[t]);
+            }
+        }
+        for (int t = 0; t < KB; ++t) red[t * 256 + threadIdx.x] = acc[t];
+        __syncthreads();
+        if (threadIdx.x < pc) {
+            double* o = part + (part_off[ch] + c0 + threadIdx.x) * k + k0;
+            for (int t = 0; t < KB; ++t) {
+                double s = 0.0;
+                for (int gg = 0; gg < G; ++gg) s += red[t * 256 + gg * pc + threadIdx.x];
+                o[t] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+// chunk tables
+int plan_products(Handle& h) {
+    const int J = h.geo.J;
+    h.chunk_off.assign(J + 1, 0);
+    std::vector<int64_t> part_off;
+    std::vector<int32_t> chunk_sub;
+    int64_t poff = 0;
+    for (int j = 0; j < J; ++j) {
+        const int64_t n = h.pts.row_off[j + 1] - h.pts.row_off[j];
+        const int64_t nc = (n + kChunk - 1) / kChunk;
+        h.chunk_off[j + 1] = h.chunk_off[j] + nc;
+        for (int64_t c = 0; c < nc; ++c) {
+            part_off.push_back(poff);
+            poff += h.p[j];
+            chunk_sub.push_back(j);
+        }
+    }
+    h.n_chunks = h.chunk_off[J];
+    h.part_total = poff;
+    RDD_TRY(dev_alloc(h, &h.d_chunk_sub, chunk_sub.size()));
+    RDD_TRY(dev_alloc(h, &h.d_chunk_off, h.chunk_off.size()));
+    RDD_TRY(dev_alloc(h, &h.d_part_off, part_off.size()));
+    if (!chunk_sub.empty()) {
+        RDD_HIP(hipMemcpy(h.d_chunk_sub, chunk_sub.data(), sizeof(int32_t) * chunk_sub.size(),
+                          hipMemcpyHostToDevice));
+        RDD_HIP(hipMemcpy(h.d_part_off, part_off.data(), sizeof(int64_t) * part_off.size(),
+                          hipMemcpyHostToDevice));
+    }
+    RDD_HIP(hipMemcpy(h.d_chunk_off, h.chunk_off.data(), sizeof(int64_t) * h.chunk_off.size(),
+                      hipMemcpyHostToDevice));
+    std::vector<int32_t> col_sub(h.P), feat_sub(h.sum_m);
+    for (int j = 0; j < J; ++j) {
+        for (int64_t c = h.col_off[j]; c < h.col_off[j + 1]; ++c) col_sub[c] = j;
+        for (int64_t f = h.m_off[j]; f < h.m_off[j + 1]; ++f) feat_sub[f] = j;
+    }
+    RDD_TRY(dev_alloc(h, &h.d_col_sub, col_sub.size()));
+    RDD_TRY(dev_alloc(h, &h.d_feat_sub, feat_sub.size()));
+    if (!col_sub.empty())
+        RDD_HIP(hipMemcpy(h.d_col_sub, col_sub.data(), sizeof(int32_t) * col_sub.size(),
+                          hipMemcpyHostToDevice));
+    RDD_HIP(hipMemcpy(h.d_feat_sub, feat_sub.data(), sizeof(int32_t) * feat_sub.size(),
+                      hipMemcpyHostToDevice));
+    // per-column partial metadata for the fused reductions
+    std::vector<int64_t> pbase(h.P);
+    std::vector<int32_t> pstride(h.P), nch(h.P);
+    for (int j = 0; j < J; ++j) {
+        const int64_t ch0 = h.chunk_off[j];
+        const int64_t nc = h.chunk_off[j + 1] - ch0;
+        for (int64_t c = 0; c < h.p[j]; ++c) {
+            const int64_t g = h.col_off[j] + c;
+            pbase[g] = (nc > 0 ? part_off[ch0] : 0) + c;
+            pstride[g] = h.p[j];
+            nch[g] = (int32_t)nc;
+        }
+    }
+    RDD_TRY(dev_alloc(h, &h.d_col_pbase, pbase.size()));
+    RDD_TRY(dev_alloc(h, &h.d_col_pstride, pstride.size()));
+    RDD_TRY(dev_alloc(h, &h.d_col_nch, nch.size()));
+    if (h.P > 0) {
+        RDD_HIP(hipMemcpy(h.d_col_pbase, pbase.data(), sizeof(int64_t) * h.P, hipMemcpyHostToDevice));
+        RDD_HIP(hipMemcpy(h.d_col_pstride, pstride.data(), sizeof(int32_t) * h.P, hipMemcpyHostToDevice));
+        RDD_HIP(hipMemcpy(h.d_col_nch, nch.data(), sizeof(int32_t) * h.P, hipMemcpyHostToDevice));
+    }
+    return RANN_OK;
+}
+
+// y = H x; `tpair` holds pairs x k doubles
+int launch_Hx_pairs(Handle& h, const double* x, int k, double* y, double* tpair) {
+    if (h.n_chunks == 0) {
+        RDD_HIP(hipMemsetAsync(y, 0, sizeof(double) * h.N * k, h.stream));
+        return RANN_OK;
+    }
+    KTimer kt_(h.stream, "k_Hx");
+    for (int k0 = 0; k0 < k;) {
+        const int rem = k - k0;
+        const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+#define RDD_HXC(KBV)                                                                              \
+    hipLaunchKernelGGL((k_Hx_chunk<KBV>), dim3((unsigned)h.n_chunks), dim3(256), 0, h.stream,     \
+                       h.d_chunk_sub, h.d_chunk_off, h.pts.d_row_off, h.d_p, h.d_h_off, h.d_col_off, \
+                       h.d_H, x, k, k0, tpair)
+        switch (kb) {
+            case 8: RDD_HXC(8); break;
+            case 4: RDD_HXC(4); break;
+            case 2: RDD_HXC(2); break;
+            default: RDD_HXC(1); break;
+        }
+#undef RDD_HXC
+        k0 += kb;
+    }
+    hipLaunchKernelGGL(k_pair_to_rows, dim3((unsigned)((h.N * k + 255) / 256)), dim3(256), 0, h.stream,
+                       h.N, k, h.pts.d_cover_off, h.pts.d_cover, tpair, y);
+    kt_.stop();
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
+// part = chunk partial sums of H^T y (part_total x k)
+int launch_HTy_part(Handle& h, const double* y, int k, double* part) {
+    if (h.n_chunks == 0) return RANN_OK;
+    KTimer kt_(h.stream, "k_HTy_part");
+    for (int k0 = 0; k0 < k;) {
+        const int rem = k - k0;
+        const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+#define RDD_HTC(KBV)                                                                               \
+    hipLaunchKernelGGL((k_HTy_chunk<KBV>), dim3((unsigned)h.n_chunks), dim3(256), 0, h.stream,     \
+                       h.d_chunk_sub, h.d_chunk_off, h.d_part_off, h.pts.d_row_off, h.pts.d_rows,  \
+                       h.d_p, h.d_h_off, h.d_H, y, k, k0, part)
+        switch (kb) {
+            case 8: RDD_HTC(8); break;
+            case 4: RDD_HTC(4); break;
+            case 2: RDD_HTC(2); break;
+            default: RDD_HTC(1); break;
+        }
+#undef RDD_HTC
+        k0 += kb;
+    }
+    kt_.stop();
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
+}  // namespace rdd

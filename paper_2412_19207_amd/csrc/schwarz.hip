@@ -268,12 +268,10 @@ int build_schwarz(Handle& h) {
     return RANN_OK;
 }
 
-int launch_precond(Handle& h, const double* r, int k, double* z, double* ub) {
-    if (h.precond == RANN_PRECOND_NONE) {
-        RDD_HIP(hipMemcpyAsync(z, r, sizeof(double) * h.P * k, hipMemcpyDeviceToDevice, h.stream));
-        return RANN_OK;
-    }
+// u_i = A_i^{-1} r_{N(i)} for every block (the local solves only)
+int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
     const unsigned grid = (unsigned)((h.prec_rows + 3) / 4);
+    KTimer kt_(h.stream, "k_local_apply");
     for (int k0 = 0; k0 < k;) {
         int rem = k - k0;
         int kb = rem >= 32 ? 32 : rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
@@ -290,18 +288,26 @@ int launch_precond(Handle& h, const double* r, int k, double* z, double* ub) {
         case 2: RDD_LA(T, M, 2); break;      \
         default: RDD_LA(T, M, 1); break;     \
     }
-        KTimer kt_(h.stream, "k_local_apply");
         if (h.precision == RANN_MIXED) {
             RDD_LA_ALL(float, h.d_M32);
         } else {
             RDD_LA_ALL(double, h.d_M64);
         }
-        kt_.stop();
 #undef RDD_LA_ALL
 #undef RDD_LA
         k0 += kb;
     }
+    kt_.stop();
     RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
+int launch_precond(Handle& h, const double* r, int k, double* z, double* ub) {
+    if (h.precond == RANN_PRECOND_NONE) {
+        RDD_HIP(hipMemcpyAsync(z, r, sizeof(double) * h.P * k, hipMemcpyDeviceToDevice, h.stream));
+        return RANN_OK;
+    }
+    RDD_TRY(launch_precond_local(h, r, k, ub));
     const int64_t tot = h.P * k;
     hipLaunchKernelGGL(k_gather_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h.stream,
                        h.P, k, h.d_gat_off, h.d_gat, h.d_gat_w, ub, z);
