@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # dense FP64 (matrix cores and vector ALUs)
 FP32_PEAK_TFLOPS = 157.3
-KERNELS = ["k_eig", "k_factor_inverse", "k_pca_gram", "k_feat_rows", "k_local_gram", "k_Hx",
+KERNELS = ["k_eig", "k_factor", "k_pca_gram", "k_feat_rows", "k_local_gram", "k_Hx",
            "k_HTy_part", "k_local_apply"]
 
 
@@ -76,21 +76,20 @@ def work_model(s, prob, k):
     return {
         # nominal count of a dense symmetric eigendecomposition with vectors
         "k_eig": ("alu", float(np.sum(9.0 * m ** 3)), "flop", FP64_PEAK_TFLOPS),
-        # Cholesky q^3/3 + triangular inverse q^3/3 + X^T X q^3/3
-        "k_factor_inverse": ("mfma", float(np.sum(q ** 3)), "flop",
-                             FP32_PEAK_TFLOPS if s.precision == "mixed" else FP64_PEAK_TFLOPS),
+        # Cholesky q^3/3 + triangular inverse q^3/3, FP64 on matrix cores
+        "k_factor": ("mfma", float(np.sum(2.0 * q ** 3 / 3.0)), "flop", FP64_PEAK_TFLOPS),
         # symmetric rank-n update Psi^T Psi
         "k_pca_gram": ("mfma", float(np.sum(n * m * m)), "flop", FP64_PEAK_TFLOPS),
         "k_feat_rows": ("mfma", float(np.sum(2.0 * n * m * p)), "flop", FP64_PEAK_TFLOPS),
         # Gram blocks H_j^T H_k: counted for the diagonal blocks only (a lower bound)
-        "k_local_gram": ("mfma", float(np.sum(2.0 * n * p * p)), "flop",
-                         FP32_PEAK_TFLOPS if s.precision == "mixed" else FP64_PEAK_TFLOPS),
+        "k_local_gram": ("mfma", float(np.sum(2.0 * n * p * p)), "flop", FP64_PEAK_TFLOPS),
         # H read once, x read, y written
         "k_Hx": ("hbm", 8.0 * (nnz + P * k + N * k), "byte", HBM_PEAK_GBS),
         "k_HTy_part": ("hbm", 8.0 * (nnz + N * k + P * k), "byte", HBM_PEAK_GBS),
-        # local inverses read once, gathered r and local results
-        "k_local_apply": ("hbm", f_bytes * float(np.sum(q * q)) + 16.0 * float(np.sum(q)) * k, "byte",
-                          HBM_PEAK_GBS),
+        # triangular factors Y_i (q_i (q_i + 1) / 2 entries) read by both passes;
+        # gathered r, the intermediate u (written and read) and the result
+        "k_local_apply": ("hbm", 2.0 * f_bytes * float(np.sum(q * (q + 1) / 2.0))
+                          + 32.0 * float(np.sum(q)) * k, "byte", HBM_PEAK_GBS),
     }
 
 

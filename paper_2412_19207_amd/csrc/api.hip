@@ -356,7 +356,6 @@ static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, con
     if (d_g_off) dev_free(h, d_g_off);
     // operator rows in the PCA basis
     RDD_TRY(dev_alloc(h, &h.d_H, (size_t)h.nnz));
-    if (h.precision == RANN_MIXED) RDD_TRY(dev_alloc(h, &h.d_H32, (size_t)h.nnz));
     RDD_TRY(feature_rows(h));
     RDD_TRY(plan_products(h));
     RDD_TRY(build_schwarz(h));
@@ -567,7 +566,7 @@ int rann_dd_apply_precond(rann_dd_handle* hh, const double* r, int32_t k, double
     Handle& h = hh->h;
     if (!r || !z || k < 1) return (rdd::set_error("invalid apply_precond arguments"), RANN_EINVAL);
     double* ub = nullptr;
-    RDD_TRY(rdd::dev_alloc(h, &ub, (size_t)std::max<int64_t>(h.ub_total, 1) * k));
+    RDD_TRY(rdd::dev_alloc(h, &ub, (size_t)std::max<int64_t>(h.ub_total, 1) * k * 2));
     int rc = rdd::launch_precond(h, r, k, z, ub);
     if (rc == RANN_OK && hipStreamSynchronize(h.stream) != hipSuccess) rc = RANN_EDEVICE;
     rdd::dev_free(h, ub);
@@ -587,7 +586,7 @@ int rann_dd_get_info(const rann_dd_handle* hh, rann_dd_info* out) {
     out->pairs = h.pts.pairs;
     out->nnz = h.nnz;
     out->sum_m = h.sum_m;
-    out->factor_elems = h.factor_elems;
+    out->factor_elems = h.tile_elems;
     out->max_q = h.max_q;
     out->pca_done = h.pca_done ? 1 : 0;
     return RANN_OK;

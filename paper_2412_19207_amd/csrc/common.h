@@ -75,16 +75,22 @@ struct Handle {
     double* d_eig = nullptr;       // sum m_j, descending
     double* d_V = nullptr;         // sum m_j p_j
     double* d_H = nullptr;         // nnz FP64
-    float* d_H32 = nullptr;        // nnz FP32 (mixed)
 
     // Schwarz blocks
     std::vector<std::vector<int>> sten;  // stencil of each block (ascending)
     std::vector<int64_t> q;        // block sizes
-    std::vector<int64_t> f_off;    // J+1 offsets of q_i^2 factor storage
-    int64_t factor_elems = 0;
+    std::vector<int64_t> f_off;    // J+1 offsets of the q_i^2 set-up work arrays
+    int64_t factor_elems = 0;      // sum q_i^2
     int max_q = 0;
-    double* d_M64 = nullptr;       // local inverses FP64 (q_i x q_i each)
-    float* d_M32 = nullptr;        // FP32 (mixed)
+    std::vector<int32_t> nt;       // 64-wide tiles per edge of each block
+    std::vector<int64_t> t_off;    // J+1 offsets of the packed lower tiles
+    int64_t tile_elems = 0;        // sum nt_i (nt_i + 1) / 2 * 4096
+    int64_t* d_t_off = nullptr;
+    double* d_M64 = nullptr;       // Y_i = L_i^{-1} D_i, packed tiles, FP64
+    float* d_M32 = nullptr;        // the same in FP32 (mixed)
+    int2* d_row_tasks = nullptr;   // (block, tile row) of the row pass
+    int2* d_col_tasks = nullptr;   // (block, tile column) of the column pass
+    int64_t n_row_tasks = 0, n_col_tasks = 0;
     int64_t* d_f_off = nullptr;
     int64_t* d_q = nullptr;
     int64_t* d_ub_off = nullptr;   // J+1 offsets of per-block local vectors (sum q_i)
@@ -94,10 +100,6 @@ struct Handle {
     int64_t* d_gat = nullptr;      // entries
     double* d_gat_w = nullptr;     // weights (AS 1, SAS 1/mult, RAS ownership)
     int32_t shifts = 0;
-    int64_t prec_rows = 0;         // local-solve rows applied per preconditioner call
-    int64_t* d_prec_row_start = nullptr;
-    int64_t* d_prec_row_blk_off = nullptr;
-    int32_t* d_prec_row_blk = nullptr;
     int64_t ub_total = 0;          // sum q_i
 
     // products with H: row chunks of each block, partial sums per chunk

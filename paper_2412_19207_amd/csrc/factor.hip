@@ -1,19 +1,28 @@
 // Local inverses of the Schwarz blocks on matrix cores (paper Sec. 3: the
 // local inverse A_i^{-1} of A_i = R_i H^T H R_i^T).
 //
-// One workgroup per block, 64x64 tiles, three blocked phases:
-//   1. right-looking Cholesky of D A D + eps I = L L^T (D = diag(A)^{-1/2}):
-//      diagonal tile factored in LDS, panel = A_ik L_kk^{-T} and trailing
-//      update A_ij -= P_i P_j^T on MFMA;
-//   2. X = L^{-1}: diagonal tiles inverted in LDS, then
-//      X_ik = -X_ii sum_{j=k}^{i-1} L_ij X_jk on MFMA;
-//   3. A^{-1} = D X^T X D, lower tiles on MFMA, mirrored.
-// A pivot that is not positive restarts the factorisation with a diagonal
-// shift eps = 10 u q, growing tenfold (counted in `shifts`).
+// The inverse is kept as a triangular factor: with D = diag(A)^{-1/2} and the
+// Cholesky factorisation D A D + eps I = L L^T,
+//     A^{-1} = Y^T Y,   Y = L^{-1} D,
+// stored as packed lower 64x64 tiles (FP64, or FP32 in the mixed path).  Y^T Y
+// is positive semi-definite by construction whatever the storage precision,
+// so the rounded factor still gives a valid CG preconditioner.
+//
+// All blocks are factorised together, one tile per workgroup, in launches
+// that follow the data dependences of the blocked algorithms:
+//   Cholesky, for each panel step s:  diag(s)  : L_ss = chol(W_ss), L_ss^{-1}
+//                                     panel(s) : L_as = W_as L_ss^{-T}
+//                                     trail(s) : W_ab -= L_as L_bs^T (s < b <= a)
+//   X = L^{-1}, by tile distance t:    X_ab = -L_aa^{-1} sum_{c=b}^{a-1} L_ac X_cb
+//   Y = X D, rounded to the storage type.
+// A pivot that is not positive restarts that block with a diagonal shift
+// eps = 10 u q, growing tenfold (the count is reported as `shifts`).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <vector>
 
 #include "common.h"
 #include "mfma.h"
@@ -21,13 +30,6 @@
 namespace rdd {
 
 namespace {
-
-template <class T>
-struct Unit;
-template <>
-struct Unit<double> { static constexpr double u = DBL_EPSILON; };
-template <>
-struct Unit<float> { static constexpr double u = FLT_EPSILON; };
 
 constexpr int kFT = 256;  // threads
 
@@ -84,206 +86,398 @@ __device__ void tri_inverse_lds(T (*L)[kTM + kPad], T (*X)[kTM + kPad], int n) {
     __syncthreads();
 }
 
-template <class T>
-__global__ void __launch_bounds__(kFT) k_factor_inverse(const int64_t* __restrict__ f_off,
-                                                       const int64_t* __restrict__ qv,
-                                                       const int64_t* __restrict__ ub_off,
-                                                       T* __restrict__ Aall, T* __restrict__ Mall,
-                                                       T* __restrict__ Dall, int32_t* __restrict__ shifts,
-                                                       int32_t* __restrict__ fail) {
-    __shared__ T Ld[kTM][kTM + kPad];
-    __shared__ T Xd[kTM][kTM + kPad];
-    __shared__ T As[kTK][kTM + kPad];
-    __shared__ T Bs[kTK][kTN + kPad];
-    __shared__ int bad;
+
+struct TileTask {
+    int32_t blk, a, b, pad;
+};
+
+__device__ __forceinline__ int tile_dim(int64_t q, int t) {
+    const int64_t r = q - (int64_t)t * kTM;
+    return (int)(r < kTM ? r : kTM);
+}
+
+// D = diag(A)^{-1/2} (1 where the diagonal is not positive)
+__global__ void k_equil(const int64_t* __restrict__ f_off, const int64_t* __restrict__ qv,
+                        const int64_t* __restrict__ ub_off, const double* __restrict__ A,
+                        double* __restrict__ D) {
     const int i = blockIdx.x;
     const int64_t q = qv[i];
-    if (q == 0) return;
-    T* A = Aall + f_off[i];   // original block, later X = L^{-1}
-    T* W = Mall + f_off[i];   // factor workspace, later the inverse
-    T* D = Dall + ub_off[i];
+    const double* Ai = A + f_off[i];
+    for (int64_t r = threadIdx.x; r < q; r += blockDim.x) {
+        const double a = Ai[r * q + r];
+        D[ub_off[i] + r] = (a > 0.0 && isfinite(a)) ? 1.0 / sqrt(a) : 1.0;
+    }
+}
+
+// W = D A D + eps_i I for the listed blocks (grid.y = list index)
+__global__ void k_scale_shift(const int32_t* __restrict__ blks, const int64_t* __restrict__ f_off,
+                              const int64_t* __restrict__ qv, const int64_t* __restrict__ ub_off,
+                              const double* __restrict__ eps, const double* __restrict__ A,
+                              const double* __restrict__ D, double* __restrict__ W,
+                              int32_t* __restrict__ bad) {
+    const int i = blks[blockIdx.y];
+    const int64_t q = qv[i];
+    const double* Ai = A + f_off[i];
+    double* Wi = W + f_off[i];
+    const double* Di = D + ub_off[i];
+    const double e = eps[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) bad[i] = 0;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < q * q;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = x / q, c = x % q;
+        Wi[x] = Di[r] * Ai[x] * Di[c] + (r == c ? e : 0.0);
+    }
+}
+
+// L_ss = chol(W_ss) in LDS (written to W), X_ss = L_ss^{-1} (written to Xd)
+__global__ void __launch_bounds__(kFT) k_chol_diag(const TileTask* __restrict__ tasks,
+                                                   const int64_t* __restrict__ f_off,
+                                                   const int64_t* __restrict__ qv,
+                                                   const int64_t* __restrict__ xd_off,
+                                                   double* __restrict__ Wall,
+                                                   double* __restrict__ Xd,
+                                                   int32_t* __restrict__ bad) {
+    __shared__ double Ld[kTM][kTM + kPad];
+    __shared__ double Xs[kTM][kTM + kPad];
+    __shared__ int bad_s;
+    const TileTask tk = tasks[blockIdx.x];
+    const int i = tk.blk, s = tk.a;
+    if (bad[i]) return;
+    const int64_t q = qv[i];
+    double* W = Wall + f_off[i];
     const int tid = threadIdx.x;
-    const int nt = (int)((q + kTM - 1) / kTM);
-    for (int64_t r = tid; r < q; r += kFT) {
-        T a = A[r * q + r];
-        D[r] = (a > T(0) && isfinite(a)) ? T(1) / sqrt(a) : T(1);
+    const int64_t s0 = (int64_t)s * kTM;
+    const int kb = tile_dim(q, s);
+    for (int e = tid; e < kTM * kTM; e += kFT) {
+        const int r = e / kTM, c = e % kTM;
+        Ld[r][c] = (r < kb && c < kb) ? W[(s0 + r) * q + s0 + c] : 0.0;
+    }
+    if (tid == 0) bad_s = 0;
+    __syncthreads();
+    for (int c = 0; c < kb; ++c) {
+        const double piv = Ld[c][c];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            if (tid == 0) bad_s = 1;
+            break;  // uniform: every thread read the same pivot
+        }
+        const double lc = sqrt(piv);
+        __syncthreads();
+        if (tid == 0) Ld[c][c] = lc;
+        for (int r = c + 1 + tid; r < kb; r += kFT) Ld[r][c] /= lc;
+        __syncthreads();
+        for (int e = tid; e < kTM * kTM; e += kFT) {
+            const int r = e / kTM, t = e % kTM;
+            if (t > c && t <= r && r < kb) Ld[r][t] -= Ld[r][c] * Ld[t][c];
+        }
+        __syncthreads();
     }
     __syncthreads();
-    double eps = 0.0;
-    int tries = 0;
-    for (;;) {
-        // W <- D A D + eps I
-        for (int64_t e = tid; e < q * q; e += kFT) {
-            int64_t r = e / q, c = e % q;
-            W[e] = D[r] * A[e] * D[c] + ((r == c) ? T(eps) : T(0));
-        }
-        if (tid == 0) bad = 0;
-        __syncthreads();
-        // ---- 1. blocked Cholesky
-        for (int kt = 0; kt < nt && !bad; ++kt) {
-            const int64_t k0 = (int64_t)kt * kTM;
-            const int kb = (int)((q - k0) < kTM ? (q - k0) : kTM);
-            for (int e = tid; e < kTM * kTM; e += kFT) {
-                int r = e / kTM, c = e % kTM;
-                Ld[r][c] = (r < kb && c < kb) ? W[(k0 + r) * q + k0 + c] : T(0);
-            }
-            __syncthreads();
-            for (int c = 0; c < kb; ++c) {
-                T piv = Ld[c][c];
-                if (!(piv > T(0)) || !isfinite(piv)) {
-                    if (tid == 0) bad = 1;
-                    __syncthreads();
-                    break;
-                }
-                T lc = sqrt(piv);
-                __syncthreads();
-                if (tid == 0) Ld[c][c] = lc;
-                for (int r = c + 1 + tid; r < kb; r += kFT) Ld[r][c] /= lc;
-                __syncthreads();
-                for (int e = tid; e < kTM * kTM; e += kFT) {
-                    int r = e / kTM, s = e % kTM;
-                    if (s > c && s <= r && r < kb) Ld[r][s] -= Ld[r][c] * Ld[s][c];
-                }
-                __syncthreads();
-            }
-            if (bad) break;
-            for (int e = tid; e < kTM * kTM; e += kFT) {
-                int r = e / kTM, c = e % kTM;
-                if (r < kb && c <= r) W[(k0 + r) * q + k0 + c] = Ld[r][c];
-            }
-            tri_inverse_lds<T>(Ld, Xd, kb);
-            // panel: P_it = A_it L_kk^{-T}, for every tile row below
-            for (int it = kt + 1; it < nt; ++it) {
-                const int64_t i0 = (int64_t)it * kTM;
-                const int ib = (int)((q - i0) < kTM ? (q - i0) : kTM);
-                TileAcc<T> acc;
-                acc.zero();
-                // B[k][n] = Xd[n][k]  (LDS source: stage from LDS by hand)
-                for (int s0 = 0; s0 < kb; s0 += kTK) {
-                    stage<T, false>(As, W, q, i0, k0, s0, kb, ib);
-                    {
-                        const int n = tid >> 2, k4 = (tid & 3) * 4;
-                        for (int e2 = 0; e2 < 4; ++e2) {
-                            const int kk = k4 + e2;
-                            Bs[kk][n] = (s0 + kk < kb && n < kb) ? Xd[n][s0 + kk] : T(0);
-                        }
-                    }
-                    __syncthreads();
-                    acc.step(As, Bs);
-                    __syncthreads();
-                }
-                acc.each([&](int r, int c, T v) {
-                    if (r < ib && c < kb) W[(i0 + r) * q + k0 + c] = v;
-                });
-                __syncthreads();
-            }
-            // trailing update W_ij -= P_i P_j^T for kt < jt <= it
-            for (int it = kt + 1; it < nt; ++it) {
-                const int64_t i0 = (int64_t)it * kTM;
-                const int ib = (int)((q - i0) < kTM ? (q - i0) : kTM);
-                for (int jt = kt + 1; jt <= it; ++jt) {
-                    const int64_t j0 = (int64_t)jt * kTM;
-                    const int jb = (int)((q - j0) < kTM ? (q - j0) : kTM);
-                    TileAcc<T> acc;
-                    acc.zero();
-                    tile_gemm<T, false, false>(acc, As, Bs, W, q, i0, k0, ib, W, q, j0, k0, jb, kb);
-                    acc.each([&](int r, int c, T v) {
-                        if (r < ib && c < jb) W[(i0 + r) * q + j0 + c] -= v;
-                    });
-                    __syncthreads();
-                }
-            }
-        }
-        __syncthreads();
-        if (!bad) break;
-        ++tries;
-        if (tries > 12) {
-            if (tid == 0) atomicAdd(fail, 1);
-            return;
-        }
-        eps = (eps == 0.0) ? 10.0 * Unit<T>::u * (double)q : eps * 10.0;
+    if (bad_s) {
+        if (tid == 0) bad[i] = 1;
+        return;
     }
-    if (tid == 0 && tries > 0) atomicAdd(shifts, 1);
-    // ---- 2. X = L^{-1} into A (lower tiles)
-    for (int kt = 0; kt < nt; ++kt) {
-        const int64_t k0 = (int64_t)kt * kTM;
-        const int kb = (int)((q - k0) < kTM ? (q - k0) : kTM);
-        for (int e = tid; e < kTM * kTM; e += kFT) {
-            int r = e / kTM, c = e % kTM;
-            Ld[r][c] = (r < kb && c <= r) ? W[(k0 + r) * q + k0 + c] : T(0);
-        }
-        __syncthreads();
-        tri_inverse_lds<T>(Ld, Xd, kb);
-        for (int e = tid; e < kTM * kTM; e += kFT) {
-            int r = e / kTM, c = e % kTM;
-            if (r < kb && c < kb) A[(k0 + r) * q + k0 + c] = Xd[r][c];
-        }
-        __syncthreads();
+    for (int e = tid; e < kTM * kTM; e += kFT) {
+        const int r = e / kTM, c = e % kTM;
+        if (r < kb && c <= r) W[(s0 + r) * q + s0 + c] = Ld[r][c];
     }
-    for (int kt = 0; kt < nt; ++kt) {
-        const int64_t k0 = (int64_t)kt * kTM;
-        const int kb = (int)((q - k0) < kTM ? (q - k0) : kTM);
-        for (int it = kt + 1; it < nt; ++it) {
-            const int64_t i0 = (int64_t)it * kTM;
-            const int ib = (int)((q - i0) < kTM ? (q - i0) : kTM);
-            // S = sum_{jt=kt}^{it-1} L_{it,jt} X_{jt,kt}
-            TileAcc<T> acc;
-            acc.zero();
-            const int kspan = (int)(i0 - k0);  // columns k0 .. i0-1 of L's row block it
-            tile_gemm<T, false, true>(acc, As, Bs, W, q, i0, k0, ib, A, q, k0, k0, kb, kspan);
-            acc.each([&](int r, int c, T v) {
-                if (r < ib && c < kb) A[(i0 + r) * q + k0 + c] = v;
-            });
-            __syncthreads();
-            // X_{it,kt} = -X_{it,it} S
-            TileAcc<T> acc2;
-            acc2.zero();
-            tile_gemm<T, false, true>(acc2, As, Bs, A, q, i0, i0, ib, A, q, i0, k0, kb, ib);
-            acc2.each([&](int r, int c, T v) {
-                if (r < ib && c < kb) A[(i0 + r) * q + k0 + c] = -v;
-            });
-            __syncthreads();
-        }
+    tri_inverse_lds<double>(Ld, Xs, kb);
+    double* X = Xd + xd_off[i] + (int64_t)s * kTM * kTM;
+    for (int e = tid; e < kTM * kTM; e += kFT) X[e] = Xs[e / kTM][e % kTM];
+}
+
+// L_as = W_as X_ss^T  (a > s)
+__global__ void __launch_bounds__(kFT) k_chol_panel(const TileTask* __restrict__ tasks,
+                                                    const int64_t* __restrict__ f_off,
+                                                    const int64_t* __restrict__ qv,
+                                                    const int64_t* __restrict__ xd_off,
+                                                    double* __restrict__ Wall,
+                                                    const double* __restrict__ Xd,
+                                                    const int32_t* __restrict__ bad) {
+    __shared__ double As[kTK][kTM + kPad];
+    __shared__ double Bs[kTK][kTN + kPad];
+    const TileTask tk = tasks[blockIdx.x];
+    const int i = tk.blk, a = tk.a, s = tk.b;
+    if (bad[i]) return;
+    const int64_t q = qv[i];
+    double* W = Wall + f_off[i];
+    const int64_t a0 = (int64_t)a * kTM, s0 = (int64_t)s * kTM;
+    const int ab = tile_dim(q, a), kb = tile_dim(q, s);
+    const double* X = Xd + xd_off[i] + (int64_t)s * kTM * kTM;
+    TileAcc<double> acc;
+    acc.zero();
+    tile_gemm<double, false, false>(acc, As, Bs, W, q, a0, s0, ab, X, kTM, 0, 0, kb, kb);
+    acc.each([&](int r, int c, double v) {
+        if (r < ab && c < kb) W[(a0 + r) * q + s0 + c] = v;
+    });
+}
+
+// W_ab -= L_as L_bs^T  (s < b <= a)
+__global__ void __launch_bounds__(kFT) k_chol_trail(const TileTask* __restrict__ tasks, int s,
+                                                    const int64_t* __restrict__ f_off,
+                                                    const int64_t* __restrict__ qv,
+                                                    double* __restrict__ Wall,
+                                                    const int32_t* __restrict__ bad) {
+    __shared__ double As[kTK][kTM + kPad];
+    __shared__ double Bs[kTK][kTN + kPad];
+    const TileTask tk = tasks[blockIdx.x];
+    const int i = tk.blk, a = tk.a, b = tk.b;
+    if (bad[i]) return;
+    const int64_t q = qv[i];
+    double* W = Wall + f_off[i];
+    const int64_t a0 = (int64_t)a * kTM, b0 = (int64_t)b * kTM, s0 = (int64_t)s * kTM;
+    const int ab = tile_dim(q, a), bb = tile_dim(q, b), kb = tile_dim(q, s);
+    TileAcc<double> acc;
+    acc.zero();
+    tile_gemm<double, false, false>(acc, As, Bs, W, q, a0, s0, ab, W, q, b0, s0, bb, kb);
+    acc.each([&](int r, int c, double v) {
+        if (r < ab && c < bb) W[(a0 + r) * q + b0 + c] -= v;
+    });
+}
+
+// X_aa = Xd[a] (full tile, zeros above the diagonal) into the X storage
+__global__ void k_place_diag(const TileTask* __restrict__ tasks, const int64_t* __restrict__ f_off,
+                             const int64_t* __restrict__ qv, const int64_t* __restrict__ xd_off,
+                             const double* __restrict__ Xd, double* __restrict__ Xall) {
+    const TileTask tk = tasks[blockIdx.x];
+    const int i = tk.blk, a = tk.a;
+    const int64_t q = qv[i];
+    const int64_t a0 = (int64_t)a * kTM;
+    const int ab = tile_dim(q, a);
+    const double* src = Xd + xd_off[i] + (int64_t)a * kTM * kTM;
+    double* X = Xall + f_off[i];
+    for (int e = threadIdx.x; e < kTM * kTM; e += blockDim.x) {
+        const int r = e / kTM, c = e % kTM;
+        if (r < ab && c < ab) X[(a0 + r) * q + a0 + c] = src[e];
     }
-    // ---- 3. W = D X^T X D (lower tiles computed, mirrored)
-    for (int at = 0; at < nt; ++at) {
-        const int64_t a0 = (int64_t)at * kTM;
-        const int ab = (int)((q - a0) < kTM ? (q - a0) : kTM);
-        for (int bt = 0; bt <= at; ++bt) {
-            const int64_t b0 = (int64_t)bt * kTM;
-            const int bb = (int)((q - b0) < kTM ? (q - b0) : kTM);
-            TileAcc<T> acc;
-            acc.zero();
-            // sum over rows t >= a0 of X[t][a0+m] X[t][b0+n]
-            tile_gemm<T, true, true>(acc, As, Bs, A, q, a0, a0, ab, A, q, a0, b0, bb, (int)(q - a0));
-            acc.each([&](int r, int c, T v) {
-                if (r < ab && c < bb) {
-                    const int64_t gr = a0 + r, gc = b0 + c;
-                    if (gc <= gr) {
-                        T s = D[gr] * v * D[gc];
-                        W[gr * q + gc] = s;
-                        W[gc * q + gr] = s;
-                    }
-                }
-            });
-            __syncthreads();
-        }
+}
+
+// X_ab = -X_aa sum_{c=b}^{a-1} L_ac X_cb  (a > b; X_cb known for c < a)
+__global__ void __launch_bounds__(kFT) k_inv_off(const TileTask* __restrict__ tasks,
+                                                 const int64_t* __restrict__ f_off,
+                                                 const int64_t* __restrict__ qv,
+                                                 const double* __restrict__ Lall,
+                                                 double* __restrict__ Xall) {
+    __shared__ double As[kTK][kTM + kPad];
+    __shared__ double Bs[kTK][kTN + kPad];
+    const TileTask tk = tasks[blockIdx.x];
+    const int i = tk.blk, a = tk.a, b = tk.b;
+    const int64_t q = qv[i];
+    const double* L = Lall + f_off[i];
+    double* X = Xall + f_off[i];
+    const int64_t a0 = (int64_t)a * kTM, b0 = (int64_t)b * kTM;
+    const int ab = tile_dim(q, a), bb = tile_dim(q, b);
+    TileAcc<double> acc;
+    acc.zero();
+    tile_gemm<double, false, true>(acc, As, Bs, L, q, a0, b0, ab, X, q, b0, b0, bb, (int)(a0 - b0));
+    acc.each([&](int r, int c, double v) {
+        if (r < ab && c < bb) X[(a0 + r) * q + b0 + c] = v;
+    });
+    __syncthreads();
+    TileAcc<double> acc2;
+    acc2.zero();
+    tile_gemm<double, false, true>(acc2, As, Bs, X, q, a0, a0, ab, X, q, a0, b0, bb, ab);
+    acc2.each([&](int r, int c, double v) {
+        if (r < ab && c < bb) X[(a0 + r) * q + b0 + c] = -v;
+    });
+}
+
+// packed tile (a, b) of Y = X D, zero-padded to 64 x 64
+template <class T>
+__global__ void k_make_Y(const TileTask* __restrict__ tasks, const int64_t* __restrict__ f_off,
+                         const int64_t* __restrict__ qv, const int64_t* __restrict__ ub_off,
+                         const int64_t* __restrict__ t_off, const double* __restrict__ Xall,
+                         const double* __restrict__ Dall, T* __restrict__ Y) {
+    const TileTask tk = tasks[blockIdx.x];
+    const int i = tk.blk, a = tk.a, b = tk.b;
+    const int64_t q = qv[i];
+    const int64_t a0 = (int64_t)a * kTM, b0 = (int64_t)b * kTM;
+    const int ab = tile_dim(q, a), bb = tile_dim(q, b);
+    const double* X = Xall + f_off[i];
+    const double* D = Dall + ub_off[i];
+    T* out = Y + t_off[i] + ((int64_t)a * (a + 1) / 2 + b) * kTM * kTM;
+    for (int e = threadIdx.x; e < kTM * kTM; e += blockDim.x) {
+        const int r = e / kTM, c = e % kTM;
+        double v = 0.0;
+        if (r < ab && c < bb && (a > b || c <= r)) v = X[(a0 + r) * q + b0 + c] * D[b0 + c];
+        out[e] = (T)v;
     }
 }
 
 }  // namespace
 
-template <class T>
-int factor_inverse(Handle& h, T* A, T* M, T* D, int32_t* flags) {
-    KTimer kt_(h.stream, "k_factor_inverse");
-    hipLaunchKernelGGL((k_factor_inverse<T>), dim3(h.geo.J), dim3(kFT), 0, h.stream, h.d_f_off, h.d_q,
-                       h.d_ub_off, A, M, D, flags, flags + 1);
-    kt_.stop();
-    RDD_HIP(hipGetLastError());
+// Tile counts and packed offsets of every block (host tables and device copy).
+int plan_tiles(Handle& h) {
+    const int J = h.geo.J;
+    h.nt.assign(J, 0);
+    h.t_off.assign(J + 1, 0);
+    for (int i = 0; i < J; ++i) {
+        const int64_t nt = (h.q[i] + kTM - 1) / kTM;
+        h.nt[i] = (int32_t)nt;
+        h.t_off[i + 1] = h.t_off[i] + nt * (nt + 1) / 2 * kTM * kTM;
+    }
+    h.tile_elems = h.t_off[J];
+    RDD_TRY(dev_alloc(h, &h.d_t_off, (size_t)J + 1));
+    RDD_HIP(hipMemcpy(h.d_t_off, h.t_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
     return RANN_OK;
 }
 
-template int factor_inverse<double>(Handle&, double*, double*, double*, int32_t*);
-template int factor_inverse<float>(Handle&, float*, float*, float*, int32_t*);
+namespace {
+
+struct Launch {
+    int64_t off, cnt;
+};
+
+int upload_tasks(Handle& h, const std::vector<TileTask>& v, TileTask** d) {
+    RDD_TRY(dev_alloc(h, d, v.size()));
+    if (!v.empty())
+        RDD_HIP(hipMemcpy(*d, v.data(), sizeof(TileTask) * v.size(), hipMemcpyHostToDevice));
+    return RANN_OK;
+}
+
+}  // namespace
+
+// A (q x q per block, FP64, row-major) -> packed tiles of Y = L^{-1} D into
+// h.d_M64 or h.d_M32.  A is left unchanged until the factorisations succeed
+// and is then overwritten with X = L^{-1}.  Synchronous.
+int factor_tiles(Handle& h, double* A, double* W) {
+    const int J = h.geo.J;
+    KTimer kt_(h.stream, "k_factor");
+    int ntmax = 0;
+    for (int i = 0; i < J; ++i) ntmax = std::max(ntmax, h.nt[i]);
+    std::vector<int64_t> xd_off(J + 1, 0);
+    for (int i = 0; i < J; ++i) xd_off[i + 1] = xd_off[i] + (int64_t)h.nt[i] * kTM * kTM;
+    double *d_D = nullptr, *d_Xd = nullptr, *d_eps = nullptr;
+    int64_t* d_xd_off = nullptr;
+    int32_t *d_bad = nullptr, *d_blks = nullptr;
+    RDD_TRY(dev_alloc(h, &d_D, (size_t)h.ub_total));
+    RDD_TRY(dev_alloc(h, &d_Xd, (size_t)xd_off[J]));
+    RDD_TRY(dev_alloc(h, &d_eps, (size_t)J));
+    RDD_TRY(dev_alloc(h, &d_xd_off, (size_t)J + 1));
+    RDD_TRY(dev_alloc(h, &d_bad, (size_t)J));
+    RDD_TRY(dev_alloc(h, &d_blks, (size_t)J));
+    RDD_HIP(hipMemcpy(d_xd_off, xd_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_equil, dim3(J), dim3(256), 0, h.stream, h.d_f_off, h.d_q, h.d_ub_off, A, d_D);
+    RDD_HIP(hipGetLastError());
+
+    std::vector<double> eps(J, 0.0);
+    std::vector<int32_t> active;
+    for (int i = 0; i < J; ++i)
+        if (h.q[i] > 0) active.push_back(i);
+    std::vector<int32_t> bad(J, 0);
+    h.shifts = 0;
+    std::vector<TileTask*> task_bufs;
+    int tries = 0;
+    while (!active.empty()) {
+        // task lists of the Cholesky launches for the active blocks
+        std::vector<TileTask> tasks;
+        std::vector<Launch> diag(ntmax), panel(ntmax), trail(ntmax);
+        for (int s = 0; s < ntmax; ++s) {
+            diag[s].off = (int64_t)tasks.size();
+            for (int i : active)
+                if (h.nt[i] > s) tasks.push_back({i, s, s, 0});
+            diag[s].cnt = (int64_t)tasks.size() - diag[s].off;
+            panel[s].off = (int64_t)tasks.size();
+            for (int i : active)
+                for (int a = s + 1; a < h.nt[i]; ++a) tasks.push_back({i, a, s, 0});
+            panel[s].cnt = (int64_t)tasks.size() - panel[s].off;
+            trail[s].off = (int64_t)tasks.size();
+            for (int i : active)
+                for (int a = s + 1; a < h.nt[i]; ++a)
+                    for (int b = s + 1; b <= a; ++b) tasks.push_back({i, a, b, 0});
+            trail[s].cnt = (int64_t)tasks.size() - trail[s].off;
+        }
+        TileTask* d_tasks = nullptr;
+        RDD_TRY(upload_tasks(h, tasks, &d_tasks));
+        task_bufs.push_back(d_tasks);
+        RDD_HIP(hipMemcpy(d_eps, eps.data(), sizeof(double) * J, hipMemcpyHostToDevice));
+        RDD_HIP(hipMemcpy(d_blks, active.data(), sizeof(int32_t) * active.size(), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_scale_shift, dim3(64, (unsigned)active.size()), dim3(256), 0, h.stream,
+                           d_blks, h.d_f_off, h.d_q, h.d_ub_off, d_eps, A, d_D, W, d_bad);
+        RDD_HIP(hipGetLastError());
+        for (int s = 0; s < ntmax; ++s) {
+            if (diag[s].cnt)
+                hipLaunchKernelGGL(k_chol_diag, dim3((unsigned)diag[s].cnt), dim3(kFT), 0, h.stream,
+                                   d_tasks + diag[s].off, h.d_f_off, h.d_q, d_xd_off, W, d_Xd, d_bad);
+            if (panel[s].cnt)
+                hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)panel[s].cnt), dim3(kFT), 0, h.stream,
+                                   d_tasks + panel[s].off, h.d_f_off, h.d_q, d_xd_off, W, d_Xd, d_bad);
+            if (trail[s].cnt)
+                hipLaunchKernelGGL(k_chol_trail, dim3((unsigned)trail[s].cnt), dim3(kFT), 0, h.stream,
+                                   d_tasks + trail[s].off, s, h.d_f_off, h.d_q, W, d_bad);
+            RDD_HIP(hipGetLastError());
+        }
+        RDD_HIP(hipMemcpyAsync(bad.data(), d_bad, sizeof(int32_t) * J, hipMemcpyDeviceToHost, h.stream));
+        RDD_HIP(hipStreamSynchronize(h.stream));
+        std::vector<int32_t> again;
+        for (int i : active)
+            if (bad[i]) again.push_back(i);
+        if (again.empty()) break;
+        if (++tries > 12) {
+            set_error("a local Schwarz block is not positive definite even after diagonal shifts");
+            return RANN_EBREAKDOWN;
+        }
+        for (int i : again) {
+            if (eps[i] == 0.0) ++h.shifts;
+            eps[i] = (eps[i] == 0.0) ? 10.0 * DBL_EPSILON * (double)h.q[i] : eps[i] * 10.0;
+        }
+        active.swap(again);
+    }
+    // X = L^{-1} into A, by tile distance
+    {
+        std::vector<TileTask> tasks;
+        std::vector<Launch> dist(ntmax);
+        for (int i = 0; i < J; ++i)
+            for (int a = 0; a < h.nt[i]; ++a) tasks.push_back({i, a, a, 0});
+        const int64_t ndiag = (int64_t)tasks.size();
+        for (int t = 1; t < ntmax; ++t) {
+            dist[t].off = (int64_t)tasks.size();
+            for (int i = 0; i < J; ++i)
+                for (int b = 0; b + t < h.nt[i]; ++b) tasks.push_back({i, b + t, b, 0});
+            dist[t].cnt = (int64_t)tasks.size() - dist[t].off;
+        }
+        TileTask* d_tasks = nullptr;
+        RDD_TRY(upload_tasks(h, tasks, &d_tasks));
+        task_bufs.push_back(d_tasks);
+        if (ndiag)
+            hipLaunchKernelGGL(k_place_diag, dim3((unsigned)ndiag), dim3(256), 0, h.stream, d_tasks,
+                               h.d_f_off, h.d_q, d_xd_off, d_Xd, A);
+        for (int t = 1; t < ntmax; ++t)
+            if (dist[t].cnt)
+                hipLaunchKernelGGL(k_inv_off, dim3((unsigned)dist[t].cnt), dim3(kFT), 0, h.stream,
+                                   d_tasks + dist[t].off, h.d_f_off, h.d_q, W, A);
+        RDD_HIP(hipGetLastError());
+    }
+    // Y = X D in packed tiles
+    {
+        std::vector<TileTask> tasks;
+        for (int i = 0; i < J; ++i)
+            for (int a = 0; a < h.nt[i]; ++a)
+                for (int b = 0; b <= a; ++b) tasks.push_back({i, a, b, 0});
+        TileTask* d_tasks = nullptr;
+        RDD_TRY(upload_tasks(h, tasks, &d_tasks));
+        task_bufs.push_back(d_tasks);
+        if (!tasks.empty()) {
+            if (h.precision == RANN_MIXED)
+                hipLaunchKernelGGL(k_make_Y<float>, dim3((unsigned)tasks.size()), dim3(256), 0,
+                                   h.stream, d_tasks, h.d_f_off, h.d_q, h.d_ub_off, h.d_t_off, A,
+                                   d_D, h.d_M32);
+            else
+                hipLaunchKernelGGL(k_make_Y<double>, dim3((unsigned)tasks.size()), dim3(256), 0,
+                                   h.stream, d_tasks, h.d_f_off, h.d_q, h.d_ub_off, h.d_t_off, A,
+                                   d_D, h.d_M64);
+        }
+        RDD_HIP(hipGetLastError());
+    }
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    kt_.stop();
+    for (TileTask* p : task_bufs) dev_free(h, p);
+    dev_free(h, d_D);
+    dev_free(h, d_Xd);
+    dev_free(h, d_eps);
+    dev_free(h, d_xd_off);
+    dev_free(h, d_bad);
+    dev_free(h, d_blks);
+    return RANN_OK;
+}
 
 }  // namespace rdd

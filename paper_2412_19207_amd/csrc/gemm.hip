@@ -349,7 +349,7 @@ int feature_rows(Handle& h) {
     KTimer kt_(h.stream, "k_feat_rows");
     hipLaunchKernelGGL(k_feat_rows, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, h.geo, d_t,
                        h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, h.d_p,
-                       h.d_v_off, h.d_V, h.d_h_off, h.d_H, h.d_H32);
+                       h.d_v_off, h.d_V, h.d_h_off, h.d_H, (float*)nullptr);
     kt_.stop();
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));
@@ -493,6 +493,5 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
 }
 
 template int local_blocks<double>(Handle&, const double*, double*);
-template int local_blocks<float>(Handle&, const float*, float*);
 
 }  // namespace rdd

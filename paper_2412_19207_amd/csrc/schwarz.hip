@@ -5,9 +5,12 @@
 //   SAS: D_i = 1 / (number of blocks containing the column)
 //
 // Block i selects the columns of every subdomain in its stencil.  The local
-// inverse (factor.hip) is stored explicitly as the symmetric matrix
-// A_i^{-1} = D L^{-T} L^{-1} D, so that applying it is a streaming
-// matrix-vector product instead of two dependent triangular solves.
+// inverse is kept as the packed lower-triangular tiles of Y_i = L_i^{-1} D_i
+// (factor.hip), A_i^{-1} = Y_i^T Y_i, and applied as two streaming passes
+// instead of two dependent triangular solves:
+//   row pass   : u_a = sum_{b <= a} Y_ab x_b   (one workgroup per tile row)
+//   column pass: z_b = sum_{a >= b} Y_ab^T u_a (one workgroup per tile column)
+// Tile rows of Y are contiguous in memory; every tile is read once per pass.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,45 +23,144 @@ namespace rdd {
 
 template <class T>
 int local_blocks(Handle& h, const T* H, T* A_out);
-template <class T>
-int factor_inverse(Handle& h, T* A, T* M, T* D, int32_t* flags);
+int plan_tiles(Handle& h);
+int factor_tiles(Handle& h, double* A, double* W);
 
 namespace {
 
-// u_i = A_i^{-1} r_{N(i)} for the rows [row_lo_i, row_hi_i) of each block; one
-// wave per row, lanes stride the row (coalesced), FP64 accumulation.
+constexpr int kT = 64;              // tile edge
+constexpr int kTE = kT * kT;        // tile elements
+constexpr int kXChunk = 8;          // tiles of the input vector staged in LDS at once
+
+// 16 consecutive elements (16-byte aligned) into registers
+__device__ __forceinline__ void load16(const double* p, double* v) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const double2 w = q[e];
+        v[2 * e] = w.x;
+        v[2 * e + 1] = w.y;
+    }
+}
+__device__ __forceinline__ void load16(const float* p, float* v) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float4 w = q[e];
+        v[4 * e] = w.x;
+        v[4 * e + 1] = w.y;
+        v[4 * e + 2] = w.z;
+        v[4 * e + 3] = w.w;
+    }
+}
+
+// row pass: u_a = sum_{b <= a} Y_ab x_b with x = r gathered through the block's
+// column list.  Thread (row, seg) owns 16 consecutive columns of one tile row;
+// FP64 accumulation.
 template <class T, int KB>
-__global__ void __launch_bounds__(256) k_local_apply(const int64_t* __restrict__ row_start,
-                                                     int64_t nrows_total, int J,
-                                                     const int64_t* __restrict__ row_blk_off,
-                                                     const int32_t* __restrict__ row_blk,
-                                                     const int64_t* __restrict__ f_off,
-                                                     const int64_t* __restrict__ qv,
-                                                     const int64_t* __restrict__ ub_off,
-                                                     const int32_t* __restrict__ blk_cols,
-                                                     const T* __restrict__ Minv,
-                                                     const double* __restrict__ r, int k, int k0,
-                                                     double* __restrict__ u) {
-    const int lane = threadIdx.x & 63;
-    const int64_t gr = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (gr >= nrows_total) return;
-    const int i = row_blk[gr];
-    const int64_t row = row_start[i] + (gr - row_blk_off[i]);
+__global__ void __launch_bounds__(256) k_tri_row(const int2* __restrict__ tasks,
+                                                 const int64_t* __restrict__ t_off,
+                                                 const int64_t* __restrict__ qv,
+                                                 const int64_t* __restrict__ ub_off,
+                                                 const int32_t* __restrict__ blk_cols,
+                                                 const T* __restrict__ Y,
+                                                 const double* __restrict__ r, int k, int k0,
+                                                 double* __restrict__ u) {
+    __shared__ double xs[kXChunk * kT][KB];
+    const int2 tk = tasks[blockIdx.x];
+    const int i = tk.x, a = tk.y;
     const int64_t q = qv[i];
-    const T* Mr = Minv + f_off[i] + row * q;
+    const int tid = threadIdx.x, row = tid >> 2, seg = tid & 3;
+    const T* Ya = Y + t_off[i] + (int64_t)a * (a + 1) / 2 * kTE + row * kT + seg * 16;
     const int32_t* cols = blk_cols + ub_off[i];
     double acc[KB];
+#pragma unroll
     for (int t = 0; t < KB; ++t) acc[t] = 0.0;
-    for (int64_t c = lane; c < q; c += 64) {
-        const double mv = (double)Mr[c];
-        const double* rc = r + (int64_t)cols[c] * k + k0;
-        for (int t = 0; t < KB; ++t) acc[t] = fma(mv, rc[t], acc[t]);
+    for (int b0 = 0; b0 <= a; b0 += kXChunk) {
+        const int nb = (a + 1 - b0 < kXChunk) ? a + 1 - b0 : kXChunk;
+        __syncthreads();
+        for (int e = tid; e < nb * kT * KB; e += 256) {
+            const int c = e / KB, t = e % KB;
+            const int64_t gc = (int64_t)b0 * kT + c;
+            xs[c][t] = (gc < q) ? r[(int64_t)cols[gc] * k + k0 + t] : 0.0;
+        }
+        __syncthreads();
+        for (int bb = 0; bb < nb; ++bb) {
+            T v[16];
+            load16(Ya + (int64_t)(b0 + bb) * kTE, v);
+            const double (*xr)[KB] = xs + bb * kT + seg * 16;
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+#pragma unroll
+                for (int t = 0; t < KB; ++t) acc[t] = fma((double)v[cc], xr[cc][t], acc[t]);
+        }
     }
-    for (int t = 0; t < KB; ++t)
-        for (int off = 32; off > 0; off >>= 1) acc[t] += __shfl_xor(acc[t], off);
-    if (lane == 0) {
-        double* uo = u + (ub_off[i] + row) * k + k0;
-        for (int t = 0; t < KB; ++t) uo[t] = acc[t];
+#pragma unroll
+    for (int t = 0; t < KB; ++t) {
+        acc[t] += __shfl_xor(acc[t], 1);
+        acc[t] += __shfl_xor(acc[t], 2);
+    }
+    const int64_t gr = (int64_t)a * kT + row;
+    if (seg == 0 && gr < q) {
+        double* o = u + (ub_off[i] + gr) * k + k0;
+#pragma unroll
+        for (int t = 0; t < KB; ++t) o[t] = acc[t];
+    }
+}
+
+// column pass: z_b = sum_{a >= b} Y_ab^T x_a with x the row-pass output.
+// Thread (col, wave) owns 16 rows of one tile column; the four waves are
+// summed in LDS at the end.
+template <class T, int KB>
+__global__ void __launch_bounds__(256) k_tri_col(const int2* __restrict__ tasks,
+                                                 const int64_t* __restrict__ t_off,
+                                                 const int64_t* __restrict__ qv,
+                                                 const int64_t* __restrict__ ub_off,
+                                                 const T* __restrict__ Y,
+                                                 const double* __restrict__ x, int k, int k0,
+                                                 double* __restrict__ z) {
+    __shared__ double xs[kXChunk * kT][KB];
+    __shared__ double red[4][kT][KB];
+    const int2 tk = tasks[blockIdx.x];
+    const int i = tk.x, b = tk.y;
+    const int64_t q = qv[i];
+    const int nt = (int)((q + kT - 1) / kT);
+    const int tid = threadIdx.x, col = tid & 63, rs = tid >> 6;
+    const T* Yi = Y + t_off[i] + (int64_t)(rs * 16) * kT + col;
+    const double* xi = x + ub_off[i] * k + k0;
+    double acc[KB];
+#pragma unroll
+    for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+    for (int a0 = b; a0 < nt; a0 += kXChunk) {
+        const int na = (nt - a0 < kXChunk) ? nt - a0 : kXChunk;
+        __syncthreads();
+        for (int e = tid; e < na * kT * KB; e += 256) {
+            const int c = e / KB, t = e % KB;
+            const int64_t gr = (int64_t)a0 * kT + c;
+            xs[c][t] = (gr < q) ? xi[gr * k + t] : 0.0;
+        }
+        __syncthreads();
+        for (int aa = 0; aa < na; ++aa) {
+            const int a = a0 + aa;
+            const T* src = Yi + ((int64_t)a * (a + 1) / 2 + b) * kTE;
+            T v[16];
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) v[rr] = src[rr * kT];
+            const double (*xr)[KB] = xs + aa * kT + rs * 16;
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr)
+#pragma unroll
+                for (int t = 0; t < KB; ++t) acc[t] = fma((double)v[rr], xr[rr][t], acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < KB; ++t) red[rs][col][t] = acc[t];
+    __syncthreads();
+    const int64_t gc = (int64_t)b * kT + col;
+    if (rs == 0 && gc < q) {
+        double* o = z + (ub_off[i] + gc) * k + k0;
+#pragma unroll
+        for (int t = 0; t < KB; ++t) o[t] = red[0][col][t] + red[1][col][t] + red[2][col][t] + red[3][col][t];
     }
 }
 
@@ -210,91 +312,85 @@ int build_schwarz(Handle& h) {
         RDD_HIP(hipMemcpy(h.d_gat_w, gat_w.data(), sizeof(double) * gat_w.size(),
                           hipMemcpyHostToDevice));
     }
-    // applied rows per block (RAS: owned rows only)
-    std::vector<int64_t> row_blk_off(J + 1, 0), row_start(J);
-    std::vector<int32_t> row_blk;
-    for (int i = 0; i < J; ++i) {
-        row_start[i] = plan.row_start[i];
-        row_blk_off[i + 1] = row_blk_off[i] + plan.row_cnt[i];
-        for (int64_t t = 0; t < plan.row_cnt[i]; ++t) row_blk.push_back(i);
-    }
-    int64_t *d_rs = nullptr, *d_rbo = nullptr;
-    int32_t* d_rb = nullptr;
-    RDD_TRY(dev_alloc(h, &d_rs, J));
-    RDD_TRY(dev_alloc(h, &d_rbo, J + 1));
-    RDD_TRY(dev_alloc(h, &d_rb, row_blk.size()));
-    RDD_HIP(hipMemcpy(d_rs, row_start.data(), sizeof(int64_t) * J, hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(d_rbo, row_blk_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(d_rb, row_blk.data(), sizeof(int32_t) * row_blk.size(), hipMemcpyHostToDevice));
-    h.prec_rows = row_blk_off[J];
-    h.d_prec_row_start = d_rs;
-    h.d_prec_row_blk_off = d_rbo;
-    h.d_prec_row_blk = d_rb;
     h.ub_total = ub_off[J];
 
-    // local Gram blocks, factorisation and explicit inverses
-    int32_t* d_flags = nullptr;
-    RDD_TRY(dev_alloc(h, &d_flags, 2));
-    RDD_HIP(hipMemsetAsync(d_flags, 0, sizeof(int32_t) * 2, h.stream));
-    if (h.precision == RANN_MIXED) {
-        float *d_A = nullptr, *d_D = nullptr;
-        RDD_TRY(dev_alloc(h, &d_A, (size_t)h.factor_elems));
-        RDD_TRY(dev_alloc(h, &d_D, (size_t)ub_off[J]));
-        RDD_TRY(dev_alloc(h, &h.d_M32, (size_t)h.factor_elems));
-        RDD_TRY(local_blocks<float>(h, h.d_H32, d_A));
-        RDD_TRY(factor_inverse<float>(h, d_A, h.d_M32, d_D, d_flags));
-        RDD_HIP(hipStreamSynchronize(h.stream));
-        dev_free(h, d_A);
-        dev_free(h, d_D);
-    } else {
-        double *d_A = nullptr, *d_D = nullptr;
-        RDD_TRY(dev_alloc(h, &d_A, (size_t)h.factor_elems));
-        RDD_TRY(dev_alloc(h, &d_D, (size_t)ub_off[J]));
-        RDD_TRY(dev_alloc(h, &h.d_M64, (size_t)h.factor_elems));
-        RDD_TRY(local_blocks<double>(h, h.d_H, d_A));
-        RDD_TRY(factor_inverse<double>(h, d_A, h.d_M64, d_D, d_flags));
-        RDD_HIP(hipStreamSynchronize(h.stream));
-        dev_free(h, d_A);
-        dev_free(h, d_D);
+    // packed tiles and the task lists of the two passes (RAS: only the tile
+    // columns holding owned unknowns, and the tile rows they need)
+    RDD_TRY(plan_tiles(h));
+    std::vector<std::pair<int, int2>> rt, ct;  // (work, task)
+    for (int i = 0; i < J; ++i) {
+        const int nt = h.nt[i];
+        if (nt == 0 || plan.row_cnt[i] == 0) continue;
+        const int b_lo = (int)(plan.row_start[i] / 64);
+        const int b_hi = (int)((plan.row_start[i] + plan.row_cnt[i] - 1) / 64);
+        for (int a = b_lo; a < nt; ++a) rt.push_back({a + 1, make_int2(i, a)});
+        for (int b = b_lo; b <= b_hi; ++b) ct.push_back({nt - b, make_int2(i, b)});
     }
-    int32_t flags[2] = {0, 0};
-    RDD_HIP(hipMemcpy(flags, d_flags, sizeof(flags), hipMemcpyDeviceToHost));
-    dev_free(h, d_flags);
-    h.shifts = flags[0];
-    if (flags[1] != 0) {
-        set_error("a local Schwarz block is not positive definite even after diagonal shifts");
-        return RANN_EBREAKDOWN;
-    }
-    return RANN_OK;
+    auto by_work = [](const std::pair<int, int2>& x, const std::pair<int, int2>& y) {
+        return x.first > y.first;
+    };
+    std::stable_sort(rt.begin(), rt.end(), by_work);
+    std::stable_sort(ct.begin(), ct.end(), by_work);
+    std::vector<int2> rtv, ctv;
+    for (auto& e : rt) rtv.push_back(e.second);
+    for (auto& e : ct) ctv.push_back(e.second);
+    h.n_row_tasks = (int64_t)rtv.size();
+    h.n_col_tasks = (int64_t)ctv.size();
+    RDD_TRY(dev_alloc(h, &h.d_row_tasks, rtv.size()));
+    RDD_TRY(dev_alloc(h, &h.d_col_tasks, ctv.size()));
+    if (!rtv.empty())
+        RDD_HIP(hipMemcpy(h.d_row_tasks, rtv.data(), sizeof(int2) * rtv.size(), hipMemcpyHostToDevice));
+    if (!ctv.empty())
+        RDD_HIP(hipMemcpy(h.d_col_tasks, ctv.data(), sizeof(int2) * ctv.size(), hipMemcpyHostToDevice));
+
+    // local Gram blocks (FP64) and their factorisation
+    double *d_A = nullptr, *d_W = nullptr;
+    RDD_TRY(dev_alloc(h, &d_A, (size_t)h.factor_elems));
+    RDD_TRY(dev_alloc(h, &d_W, (size_t)h.factor_elems));
+    if (h.precision == RANN_MIXED)
+        RDD_TRY(dev_alloc(h, &h.d_M32, (size_t)h.tile_elems));
+    else
+        RDD_TRY(dev_alloc(h, &h.d_M64, (size_t)h.tile_elems));
+    RDD_TRY(local_blocks<double>(h, h.d_H, d_A));
+    const int rc = factor_tiles(h, d_A, d_W);
+    dev_free(h, d_A);
+    dev_free(h, d_W);
+    return rc;
 }
 
-// u_i = A_i^{-1} r_{N(i)} for every block (the local solves only)
+// u_i = A_i^{-1} r_{N(i)} for every block (the local solves only).  ub holds
+// 2 ub_total k doubles: the result, then the row-pass intermediate.
 int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
-    const unsigned grid = (unsigned)((h.prec_rows + 3) / 4);
+    double* u1 = ub + h.ub_total * k;
     KTimer kt_(h.stream, "k_local_apply");
     for (int k0 = 0; k0 < k;) {
-        int rem = k - k0;
-        int kb = rem >= 32 ? 32 : rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
-#define RDD_LA(T, M, KBV)                                                                         \
-    hipLaunchKernelGGL((k_local_apply<T, KBV>), dim3(grid), dim3(256), 0, h.stream,               \
-                       h.d_prec_row_start, h.prec_rows, h.geo.J, h.d_prec_row_blk_off,            \
-                       h.d_prec_row_blk, h.d_f_off, h.d_q, h.d_ub_off, h.d_blk_cols, M, r, k, k0, ub)
-#define RDD_LA_ALL(T, M)                     \
-    switch (kb) {                            \
-        case 32: RDD_LA(T, M, 32); break;    \
-        case 16: RDD_LA(T, M, 16); break;    \
-        case 8: RDD_LA(T, M, 8); break;      \
-        case 4: RDD_LA(T, M, 4); break;      \
-        case 2: RDD_LA(T, M, 2); break;      \
-        default: RDD_LA(T, M, 1); break;     \
+        const int rem = k - k0;
+        const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+#define RDD_TRI(T, M, KBV)                                                                         \
+    do {                                                                                           \
+        if (h.n_row_tasks)                                                                         \
+            hipLaunchKernelGGL((k_tri_row<T, KBV>), dim3((unsigned)h.n_row_tasks), dim3(256), 0,   \
+                               h.stream, h.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off,              \
+                               h.d_blk_cols, M, r, k, k0, u1);                                     \
+        if (h.n_col_tasks)                                                                         \
+            hipLaunchKernelGGL((k_tri_col<T, KBV>), dim3((unsigned)h.n_col_tasks), dim3(256), 0,   \
+                               h.stream, h.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, M, u1, k,    \
+                               k0, ub);                                                            \
+    } while (0)
+#define RDD_TRI_ALL(T, M)                   \
+    switch (kb) {                           \
+        case 8: RDD_TRI(T, M, 8); break;    \
+        case 4: RDD_TRI(T, M, 4); break;    \
+        case 2: RDD_TRI(T, M, 2); break;    \
+        default: RDD_TRI(T, M, 1); break;   \
     }
         if (h.precision == RANN_MIXED) {
-            RDD_LA_ALL(float, h.d_M32);
+            RDD_TRI_ALL(float, h.d_M32);
         } else {
-            RDD_LA_ALL(double, h.d_M64);
+            RDD_TRI_ALL(double, h.d_M64);
         }
-#undef RDD_LA_ALL
-#undef RDD_LA
+#undef RDD_TRI_ALL
+#undef RDD_TRI
         k0 += kb;
     }
     kt_.stop();
