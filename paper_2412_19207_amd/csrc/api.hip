@@ -284,8 +284,8 @@ static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, con
         double *G = nullptr, *Z = nullptr, *Y = nullptr;
         int32_t* flags = nullptr;
         int64_t* d_s_off = nullptr;
-        std::vector<int64_t> s_off(J + 1, 0);  // eigensolver scratch: 6 m^2 per subdomain
-        for (int j = 0; j < J; ++j) s_off[j + 1] = s_off[j] + 6 * (int64_t)h.m[j] * h.m[j];
+        std::vector<int64_t> s_off(J + 1, 0);  // eigensolver scratch per subdomain
+        for (int j = 0; j < J; ++j) s_off[j + 1] = s_off[j] + eig_scratch_elems(h.m[j]);
         RDD_TRY(dev_alloc(h, &G, (size_t)g_off[J]));
         RDD_TRY(dev_alloc(h, &Z, (size_t)s_off[J]));
         RDD_TRY(dev_alloc(h, &Y, (size_t)g_off[J]));

@@ -201,6 +201,7 @@ int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g
 int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const int64_t* d_s_off,
                 double* Y, double tol, int mode, int32_t* d_p, double* d_eig, int32_t* d_tie);
 int compact_V(Handle& h, const double* Z, const int64_t* d_g_off, double* V);
+int64_t eig_scratch_elems(int m);
 int feature_rows(Handle& h);
 int build_schwarz(Handle& h);
 template <class T>
