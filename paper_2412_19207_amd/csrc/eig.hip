@@ -9,13 +9,14 @@
 //      reflectors, so the matrix is only read), then one batched matrix-core
 //      launch applies the rank-2 kNB update A -= V W^T + W V^T to the trailing
 //      part of every matrix;
-//   2. every eigenvalue of T by Sturm-count bisection, four interleaved
-//      evaluation points per thread; the truncation count p is the Sturm
+//   2. every eigenvalue of T by Sturm-count bisection, one thread per
+//      eigenvalue across many workgroups; the truncation count p is the Sturm
 //      count at the threshold;
 //   3. eigenvectors of T for the p largest eigenvalues by inverse iteration
-//      (tridiagonal LU with partial pivoting, one thread per vector, vectors
-//      interleaved in memory), then classical Gram-Schmidt applied twice in
-//      descending eigenvalue order;
+//      (tridiagonal LU with partial pivoting, one thread per vector), then an
+//      orthonormal basis in descending eigenvalue order by Cholesky QR applied
+//      twice (classical Gram-Schmidt twice when p is large or the vectors are
+//      nearly dependent);
 //   4. y = Q z with the reflectors of each panel applied as one block
 //      reflector I - V T V^T (last panel first).
 // The reflector of step k is kept in row k of A right of the diagonal; Y
@@ -37,10 +38,9 @@ namespace {
 constexpr int kNB = 32;                  // panel width of the blocked reduction
 constexpr int kPT = 1024;                // threads of the panel and solve kernels
 constexpr int kPC = 64, kPG = kPT / kPC; // 64 columns x 16 row groups
-constexpr int kTC = 128;                 // eigenvector columns per back-transform pass
 
-// per-matrix scratch: W (kNB x m), the tridiagonal (d, e, tau: 3 m), and the
-// inverse-iteration LU factors (5 fields x m x m, vector index fastest)
+// per-matrix scratch: W (kNB x m), the tridiagonal (d, e, tau: 3 m), the
+// inverse-iteration LU factors (5 rows of m per vector) and the vectors (m x m)
 __host__ __device__ inline int64_t scr_tri(int64_t m) { return kNB * m; }
 __host__ __device__ inline int64_t scr_LU(int64_t m) { return kNB * m + 3 * m; }
 
@@ -229,31 +229,8 @@ __global__ void __launch_bounds__(256) k_tri_update(const int4* __restrict__ tas
     });
 }
 
-// ---------------------------------------------------------------- 2-4. solve
-// counts of eigenvalues of the tridiagonal (d, e2 = e^2) below x[0..3]
-__device__ inline void sturm_count4(const double* d, const double* e2, int m, const double* x,
-                                    double pivmin, int* cnt) {
-    double q[4];
-    int c[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        q[u] = d[0] - x[u];
-        if (fabs(q[u]) < pivmin) q[u] = -pivmin;
-        c[u] = (q[u] < 0.0) ? 1 : 0;
-    }
-    for (int i = 1; i < m; ++i) {
-        const double di = d[i], ei = e2[i - 1];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            q[u] = (di - x[u]) - ei / q[u];
-            if (fabs(q[u]) < pivmin) q[u] = -pivmin;
-            c[u] += (q[u] < 0.0) ? 1 : 0;
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) cnt[u] = c[u];
-}
-
+// ---------------------------------------------------------------- 2. eigenvalues
+// count of eigenvalues of the tridiagonal (d, e2 = e^2) below x, with IEEE division
 __device__ int sturm_count(const double* d, const double* e2, int m, double x, double pivmin) {
     int cnt = 0;
     double q = d[0] - x;
@@ -267,255 +244,539 @@ __device__ int sturm_count(const double* d, const double* e2, int m, double x, d
     return cnt;
 }
 
-__global__ void __launch_bounds__(kPT) k_tri_solve(const int32_t* __restrict__ mvec,
-                                                   const int64_t* __restrict__ g_off,
-                                                   const double* __restrict__ Gall,
-                                                   double* __restrict__ Sall,
-                                                   const int64_t* __restrict__ s_off,
-                                                   double* __restrict__ Yall, double tol, int mode,
-                                                   int32_t* __restrict__ p_out,
-                                                   double* __restrict__ eig_out,
-                                                   const int64_t* __restrict__ m_off,
-                                                   int32_t* __restrict__ flags) {
+// the same count with 1/q from the hardware reciprocal refined by two Newton
+// steps (full FP64 accuracy at a third of the cost of the division); |q| >=
+// pivmin keeps e2 / q finite
+__device__ int sturm_count_fast(const double* d, const double* e2, int m, double x, double pivmin) {
+    int cnt = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0) ? 1 : 0;
+    for (int i = 1; i < m; ++i) {
+        double r = __builtin_amdgcn_rcp(q);
+        r = fma(r, fma(-q, r, 1.0), r);
+        r = fma(r, fma(-q, r, 1.0), r);
+        q = (d[i] - x) - e2[i - 1] * r;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += (q < 0.0) ? 1 : 0;
+    }
+    return cnt;
+}
+
+struct TriBounds {
+    double gl, gu, tnorm, pivmin, atol;
+};
+
+// Gershgorin interval of the tridiagonal (d, |e|) by one wave
+__device__ TriBounds tri_bounds(const double* d, const double* ea, int m) {
+    double lo = 0.0, hi = 0.0;
+    bool any = false;
+    for (int i = (threadIdx.x & 63); i < m; i += 64) {
+        const double r = (i > 0 ? ea[i - 1] : 0.0) + (i + 1 < m ? ea[i] : 0.0);
+        const double l = d[i] - r, u = d[i] + r;
+        lo = any ? fmin(lo, l) : l;
+        hi = any ? fmax(hi, u) : u;
+        any = true;
+    }
+    if (!any) {
+        lo = d[0];
+        hi = d[0];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off));
+        hi = fmax(hi, __shfl_xor(hi, off));
+    }
+    TriBounds b;
+    b.gl = lo;
+    b.gu = hi;
+    b.tnorm = fmax(fabs(lo), fabs(hi));
+    b.pivmin = DBL_MIN * fmax(1.0, b.tnorm * b.tnorm);
+    b.atol = 2.0 * DBL_EPSILON * b.tnorm + b.pivmin;
+    return b;
+}
+
+// every eigenvalue by bisection, one thread per eigenvalue, 64 per workgroup
+__global__ void __launch_bounds__(64) k_bisect(const int32_t* __restrict__ mvec,
+                                               const double* __restrict__ Sall,
+                                               const int64_t* __restrict__ s_off,
+                                               double* __restrict__ lam_all,
+                                               const int64_t* __restrict__ m_off,
+                                               double* __restrict__ eig_out) {
     __shared__ double dd[kMaxWidth];
     __shared__ double e2[kMaxWidth];
-    __shared__ double ee[kMaxWidth];
-    __shared__ double lam[kMaxWidth];  // ascending eigenvalues of T
-    __shared__ double hcoef[kMaxWidth];
-    __shared__ double part[kPG][kPC + 1];
-    __shared__ double Tm[kNB][kNB + 1];
-    __shared__ double Z1[kNB][kTC + 1];
-    __shared__ double red[kPT / 64];
+    __shared__ double ea[kMaxWidth];
     const int j = blockIdx.x;
     const int m = mvec[j];
+    const int idx = blockIdx.y * 64 + threadIdx.x;
+    if ((int)blockIdx.y * 64 >= m) return;  // uniform per workgroup
+    const int64_t mm = m;
+    const double* tri = Sall + s_off[j] + scr_tri(mm);
+    for (int i = threadIdx.x; i < m; i += 64) {
+        const double e = (i + 1 < m) ? tri[mm + i] : 0.0;
+        dd[i] = tri[i];
+        ea[i] = fabs(e);
+        e2[i] = e * e;
+    }
+    __syncthreads();
+    const TriBounds tb = tri_bounds(dd, ea, m);
+    if (idx >= m) return;
+    // the idx-th smallest eigenvalue: count(lo) <= idx < count(hi)
+    double lo = tb.gl - tb.atol, hi = tb.gu + tb.atol;
+    for (int it = 0; it < 200; ++it) {
+        if (!((hi - lo) > tb.atol + 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
+        const double mid = 0.5 * (lo + hi);
+        if (sturm_count_fast(dd, e2, m, mid, tb.pivmin) > idx)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    const double l = 0.5 * (lo + hi);
+    lam_all[m_off[j] + idx] = l;
+    eig_out[m_off[j] + m - 1 - idx] = l;
+}
+
+// ---------------------------------------------------------------- 3-4. vectors
+constexpr int kLds = 18432;  // doubles of LDS shared by the phases of k_vectors
+constexpr int kQRMax = 120;  // Cholesky QR for p <= kQRMax, Gram-Schmidt beyond
+constexpr int kStg = 16;     // vector entries per staging chunk of the Gram matrix
+constexpr int kRC = 64;      // rows per staging chunk of the back-transform
+
+// Orthonormal rows Q = L^{-1} Z of the p x m matrix Z (rows = vectors, t < p)
+// with Z Z^T = L L^T: Gram matrix, Cholesky (one barrier per column; column c
+// of L is kept scaled in row c of the unused upper triangle), X = L^{-1} in
+// the lower triangle, then Q = X Z in chunks of kStg columns.  Q goes to Zout;
+// returns false (nothing written) when a pivot shows near dependence.
+__device__ bool chol_qr(const double* __restrict__ Zin, double* __restrict__ Zout, int p, int m,
+                        double* lds) {
+    const int tid = threadIdx.x;
+    const int ldg = p + 1;
+    double* Gs = lds;            // p x (p + 1)
+    double* Zs = lds + p * ldg;  // p x (kStg + 1)
+    __shared__ double gdiag[kQRMax], ldiag[kQRMax];
+    __shared__ int fail;
+    const int npair = p * (p + 1) / 2;
+    constexpr int kMaxPairs = (kQRMax * (kQRMax + 1) / 2 + kPT - 1) / kPT;
+    double acc[kMaxPairs];
+    int pa[kMaxPairs], pb[kMaxPairs];
+#pragma unroll
+    for (int u = 0; u < kMaxPairs; ++u) {
+        acc[u] = 0.0;
+        const int pr = tid + u * kPT;
+        int a = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
+        while ((a + 1) * (a + 2) / 2 <= pr) ++a;
+        while (a * (a + 1) / 2 > pr) --a;
+        pa[u] = a;
+        pb[u] = pr - a * (a + 1) / 2;
+    }
+    for (int i0 = 0; i0 < m; i0 += kStg) {
+        for (int e = tid; e < p * kStg; e += kPT) {
+            const int t = e / kStg, ii = e % kStg;
+            Zs[t * (kStg + 1) + ii] = (i0 + ii < m) ? Zin[(int64_t)t * m + i0 + ii] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kMaxPairs; ++u) {
+            if (tid + u * kPT < npair) {
+                const double* za = Zs + pa[u] * (kStg + 1);
+                const double* zb = Zs + pb[u] * (kStg + 1);
+                double sacc = acc[u];
+#pragma unroll
+                for (int ii = 0; ii < kStg; ++ii) sacc = fma(za[ii], zb[ii], sacc);
+                acc[u] = sacc;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < kMaxPairs; ++u)
+        if (tid + u * kPT < npair) Gs[pa[u] * ldg + pb[u]] = acc[u];
+    if (tid == 0) fail = 0;
+    __syncthreads();
+    for (int c = tid; c < p; c += kPT) gdiag[c] = Gs[c * ldg + c];
+    __syncthreads();
+    // lower Cholesky: step c reads column c unscaled, updates the trailing lower
+    // part and stores L[r][c] = G[r][c] / l in Gs[c][r] (r > c)
+    for (int c = 0; c < p; ++c) {
+        const double piv = Gs[c * ldg + c];
+        if (!(piv > 1e-10 * gdiag[c])) {  // uniform: every thread reads the same pivot
+            if (tid == 0) fail = 1;
+            break;
+        }
+        const double l = sqrt(piv), il = 1.0 / l, ip = 1.0 / piv;
+        const int n = p - c - 1;
+        for (int e = tid; e < n * n + n; e += kPT) {
+            if (e < n * n) {
+                const int r = c + 1 + e / n, t = c + 1 + e % n;
+                if (t <= r) Gs[r * ldg + t] -= Gs[r * ldg + c] * Gs[t * ldg + c] * ip;
+            } else {
+                const int r = c + 1 + (e - n * n);
+                Gs[c * ldg + r] = Gs[r * ldg + c] * il;
+            }
+        }
+        if (tid == 0) ldiag[c] = l;
+        __syncthreads();
+    }
+    __syncthreads();
+    if (fail) return false;
+    // X = L^{-1} (lower, diagonal included) into the lower triangle; column c per thread
+    for (int c = tid; c < p; c += kPT) {
+        Gs[c * ldg + c] = 1.0 / ldiag[c];
+        for (int r = c + 1; r < p; ++r) {
+            double sacc = 0.0;
+            for (int k = c; k < r; ++k) sacc = fma(Gs[k * ldg + r], Gs[k * ldg + c], sacc);  // L[r][k] X[k][c]
+            Gs[r * ldg + c] = -sacc / ldiag[r];
+        }
+    }
+    __syncthreads();
+    // Q = X Z, kStg columns at a time
+    for (int i0 = 0; i0 < m; i0 += kStg) {
+        for (int e = tid; e < p * kStg; e += kPT) {
+            const int t = e / kStg, ii = e % kStg;
+            Zs[t * (kStg + 1) + ii] = (i0 + ii < m) ? Zin[(int64_t)t * m + i0 + ii] : 0.0;
+        }
+        __syncthreads();
+        for (int e = tid; e < p * kStg; e += kPT) {
+            const int t = e / kStg, ii = e % kStg;
+            if (i0 + ii < m) {
+                double sacc = 0.0;
+                for (int a2 = 0; a2 <= t; ++a2) sacc = fma(Gs[t * ldg + a2], Zs[a2 * (kStg + 1) + ii], sacc);
+                Zout[(int64_t)t * m + i0 + ii] = sacc;
+            }
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// classical Gram-Schmidt twice, descending order, on the rows of Zt
+__device__ void cgs2(double* Zt, int p, int m, double* hcoef, double* red) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int t = 1; t < p; ++t) {
+        double* zt = Zt + (int64_t)t * m;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int q = wave; q < t; q += kPT / 64) {
+                const double* zq = Zt + (int64_t)q * m;
+                double s = 0.0;
+                for (int i = lane; i < m; i += 64) s = fma(zq[i], zt[i], s);
+                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+                if (lane == 0) hcoef[q] = s;
+            }
+            __syncthreads();
+            for (int i = tid; i < m; i += kPT) {
+                double acc = zt[i];
+                for (int q = 0; q < t; ++q) acc -= hcoef[q] * Zt[(int64_t)q * m + i];
+                zt[i] = acc;
+            }
+            __syncthreads();
+        }
+        double pp = 0.0;
+        for (int i = tid; i < m; i += kPT) pp += zt[i] * zt[i];
+        const double nn = block_sum(pp, red);
+        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        for (int i = tid; i < m; i += kPT) zt[i] *= inv;
+        __syncthreads();
+    }
+}
+
+// p (the Sturm count at the truncation threshold) and the tie flag; one
+// workgroup per matrix
+__global__ void __launch_bounds__(256) k_pcount(const int32_t* __restrict__ mvec,
+                                                const double* __restrict__ Sall,
+                                                const int64_t* __restrict__ s_off,
+                                                const double* __restrict__ lam_all, double tol,
+                                                int mode, int32_t* __restrict__ p_out,
+                                                const int64_t* __restrict__ m_off,
+                                                int32_t* __restrict__ flags) {
+    __shared__ double dd[kMaxWidth];
+    __shared__ double e2[kMaxWidth];
+    __shared__ double ea[kMaxWidth];
+    const int j = blockIdx.x;
+    const int m = mvec[j];
+    const int64_t mm = m;
+    const double* tri = Sall + s_off[j] + scr_tri(mm);
+    const double* lam = lam_all + m_off[j];  // ascending
+    const int tid = threadIdx.x;
+    for (int i = tid; i < m; i += blockDim.x) {
+        const double e = (i + 1 < m) ? tri[mm + i] : 0.0;
+        dd[i] = tri[i];
+        ea[i] = fabs(e);
+        e2[i] = e * e;
+    }
+    __syncthreads();
+    const TriBounds tb = tri_bounds(dd, ea, m);
+    const double thr = (mode == RANN_PCA_REL_EIG) ? tol * lam[m - 1] : tol * tol;
+    int tie = 0;
+    for (int i = tid; i < m; i += blockDim.x) tie |= (fabs(lam[i] - thr) <= 1e-6 * fabs(thr)) ? 1 : 0;
+    tie = __syncthreads_or(tie);
+    if (tid == 0) {
+        int p = m;
+        if (mode != RANN_PCA_OFF) p = m - sturm_count(dd, e2, m, thr, tb.pivmin);
+        p_out[j] = (p < 0) ? 0 : p;
+        if (tie && mode != RANN_PCA_OFF) flags[1] = 1;
+    }
+}
+
+// eigenvectors of T for the p largest eigenvalues by inverse iteration, one
+// thread per vector (vector t <-> lam[m-1-t]); vector t is row t of Zt and its
+// LU factors are 5 rows of m entries
+__global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec,
+                                                double* __restrict__ Sall,
+                                                const int64_t* __restrict__ s_off,
+                                                const double* __restrict__ lam_all,
+                                                const int32_t* __restrict__ p_out,
+                                                const int64_t* __restrict__ m_off) {
+    __shared__ double dd[kMaxWidth];
+    __shared__ double ee[kMaxWidth];
+    __shared__ double ea[kMaxWidth];
+    const int j = blockIdx.x;
+    const int m = mvec[j];
+    const int p = p_out[j];
+    if ((int)blockIdx.y * 64 >= p) return;  // uniform per workgroup
+    const int64_t mm = m;
+    const double* tri = Sall + s_off[j] + scr_tri(mm);
+    const double* lam = lam_all + m_off[j];
+    double* LU = Sall + s_off[j] + scr_LU(mm);
+    double* Zt = LU + 5 * mm * mm;
+    for (int i = threadIdx.x; i < m; i += 64) {
+        const double e = (i + 1 < m) ? tri[mm + i] : 0.0;
+        dd[i] = tri[i];
+        ee[i] = e;
+        ea[i] = fabs(e);
+    }
+    __syncthreads();
+    const TriBounds tb = tri_bounds(dd, ea, m);
+    const int t = blockIdx.y * 64 + threadIdx.x;
+    if (t >= p) return;
+    // ---- 3. inverse iteration for the p largest: vector t <-> lam[m-1-t]
+    const double eps_piv = DBL_EPSILON * tb.tnorm + tb.pivmin;
+    {
+        const double lmb = lam[m - 1 - t];
+        double* __restrict__ fr = LU + (int64_t)t * 5 * mm;  // reciprocal of the diagonal of U
+        double* __restrict__ fb = fr + mm;                    // first superdiagonal
+        double* __restrict__ fc = fr + 2 * mm;                // second superdiagonal (fill-in)
+        double* __restrict__ fm = fr + 3 * mm;                // multipliers
+        double* __restrict__ fp = fr + 4 * mm;                // 1.0 where rows i, i+1 were swapped
+        double ai = dd[0] - lmb, bi = ee[0];
+        for (int i = 0; i + 1 < m; ++i) {
+            const double sub = ee[i];
+            const double an = dd[i + 1] - lmb;                 // a[i+1] before step i
+            const double bn = (i + 2 < m) ? ee[i + 1] : 0.0;   // b[i+1] before step i
+            if (fabs(ai) >= fabs(sub)) {
+                double a = ai;
+                if (fabs(a) < eps_piv) a = (a < 0.0) ? -eps_piv : eps_piv;
+                const double mu = sub / a;
+                fr[i] = 1.0 / a;
+                fb[i] = bi;
+                fc[i] = 0.0;
+                fm[i] = mu;
+                fp[i] = 0.0;
+                ai = an - mu * bi;
+                bi = bn;
+            } else {
+                const double mu = ai / sub;
+                fr[i] = 1.0 / sub;
+                fb[i] = an;
+                fc[i] = bn;
+                fm[i] = mu;
+                fp[i] = 1.0;
+                ai = bi - mu * an;
+                bi = -mu * bn;
+            }
+        }
+        if (fabs(ai) < eps_piv) ai = (ai < 0.0) ? -eps_piv : eps_piv;
+        fr[m - 1] = 1.0 / ai;
+        double* __restrict__ z = Zt + (int64_t)t * mm;
+        for (int i = 0; i < m; ++i) z[i] = 1.0 + 0.5 * sin(0.7 * (double)(i + 1) + 1.3 * (double)(t + 1));
+        for (int iter = 0; iter < 3; ++iter) {
+            // forward: row swaps and multipliers, 8 steps per batch of loads
+            double zc = z[0];
+            for (int i0 = 0; i0 + 1 < m; i0 += 8) {
+                const int n = (m - 1 - i0 < 8) ? m - 1 - i0 : 8;
+                double zn[8], mu[8], pv[8], out[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < n) {
+                        zn[u] = z[i0 + u + 1];
+                        mu[u] = fm[i0 + u];
+                        pv[u] = fp[i0 + u];
+                    }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < n) {
+                        if (pv[u] != 0.0) {
+                            out[u] = zn[u];
+                            zc = zc - mu[u] * zn[u];
+                        } else {
+                            out[u] = zc;
+                            zc = zn[u] - mu[u] * zc;
+                        }
+                    }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < n) z[i0 + u] = out[u];
+            }
+            // backward: U z = y, 8 steps per batch of loads
+            double z1 = zc * fr[m - 1], z2 = 0.0;
+            z[m - 1] = z1;
+            double nn = z1 * z1;
+            for (int i1 = m - 2; i1 >= 0; i1 -= 8) {
+                const int n = (i1 + 1 < 8) ? i1 + 1 : 8;
+                double zv[8], bv[8], cv[8], rv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < n) {
+                        zv[u] = z[i1 - u];
+                        bv[u] = fb[i1 - u];
+                        cv[u] = fc[i1 - u];
+                        rv[u] = fr[i1 - u];
+                    }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < n) {
+                        const double zi = (zv[u] - bv[u] * z1 - cv[u] * z2) * rv[u];
+                        zv[u] = zi;
+                        nn = fma(zi, zi, nn);
+                        z2 = z1;
+                        z1 = zi;
+                    }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (u < n) z[i1 - u] = zv[u];
+            }
+            const double inv = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+            for (int i = 0; i < m; ++i) z[i] *= inv;
+        }
+    }
+}
+
+// orthonormalisation and y = Q z for the p vectors; one workgroup per matrix
+__global__ void __launch_bounds__(kPT) k_vectors(const int32_t* __restrict__ mvec,
+                                                 const int64_t* __restrict__ g_off,
+                                                 const double* __restrict__ Gall,
+                                                 double* __restrict__ Sall,
+                                                 const int64_t* __restrict__ s_off,
+                                                 double* __restrict__ Yall,
+                                                 const int32_t* __restrict__ p_out) {
+    __shared__ double lds[kLds];
+    __shared__ double red[kPT / 64];
+    __shared__ double Tm[kNB][kNB + 1];
+    const int j = blockIdx.x;
+    const int m = mvec[j];
+    const int p = p_out[j];
     const int64_t mm = m;
     const double* A = Gall + g_off[j];
     double* Y = Yall + g_off[j];
     const double* tri = Sall + s_off[j] + scr_tri(mm);
     const double* taus = tri + 2 * mm;
     double* LU = Sall + s_off[j] + scr_LU(mm);
+    double* Zt = LU + 5 * mm * mm;
     const int tid = threadIdx.x;
-    const int tc = tid % kPC, tr = tid / kPC;
-    for (int i = tid; i < m; i += kPT) {
-        dd[i] = tri[i];
-        ee[i] = (i + 1 < m) ? tri[mm + i] : 0.0;
-    }
-    __syncthreads();
-    // ---- 2. eigenvalues by bisection (Gershgorin bounds, Sturm counts)
-    double gl = 0.0, gu = 0.0;
-    for (int i = 0; i < m; ++i) {
-        const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < m ? fabs(ee[i]) : 0.0);
-        const double lo_i = dd[i] - r, hi_i = dd[i] + r;
-        gl = (i == 0 || lo_i < gl) ? lo_i : gl;
-        gu = (i == 0 || hi_i > gu) ? hi_i : gu;
-    }
-    const double tnorm = fmax(fabs(gl), fabs(gu));
-    for (int i = tid; i < m; i += kPT) e2[i] = (i + 1 < m) ? ee[i] * ee[i] : 0.0;
-    __syncthreads();
-    const double pivmin = DBL_MIN * fmax(1.0, tnorm * tnorm);
-    const double atol = 2.0 * DBL_EPSILON * tnorm + pivmin;
-    for (int idx = tid; idx < m; idx += kPT) {
-        // the idx-th smallest eigenvalue: count(lo) <= idx < count(hi); each
-        // round evaluates 4 interior points and keeps one of the 5 pieces
-        double lo = gl - atol, hi = gu + atol;
-        for (int it = 0; it < 100; ++it) {
-            if (!((hi - lo) > atol + 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
-            double xs[4];
-            int cs[4];
-            for (int u = 0; u < 4; ++u) xs[u] = lo + (hi - lo) * (0.2 * (u + 1));
-            sturm_count4(dd, e2, m, xs, pivmin, cs);
-            double nlo = xs[3], nhi = hi;
-            for (int u = 3; u >= 0; --u)
-                if (cs[u] > idx) {
-                    nhi = xs[u];
-                    nlo = (u > 0) ? xs[u - 1] : lo;
-                }
-            lo = nlo;
-            hi = nhi;
-        }
-        lam[idx] = 0.5 * (lo + hi);
-    }
-    __syncthreads();
-    const double lam1 = lam[m - 1];
-    const double thr = (mode == RANN_PCA_REL_EIG) ? tol * lam1 : tol * tol;
-    int p = m;
-    if (mode != RANN_PCA_OFF) p = m - sturm_count(dd, e2, m, thr, pivmin);  // same in every thread
-    if (p < 0) p = 0;
-    for (int i = tid; i < m; i += kPT) eig_out[m_off[j] + i] = lam[m - 1 - i];
-    if (tid == 0) {
-        p_out[j] = p;
-        int tie = 0;
-        for (int i = 0; i < m; ++i) tie |= (fabs(lam[i] - thr) <= 1e-6 * fabs(thr)) ? 1 : 0;
-        if (tie && mode != RANN_PCA_OFF) flags[1] = 1;
-    }
-    // ---- 3. inverse iteration for the p largest: vector t <-> eigenvalue
-    // lam[m-1-t], z_t stored as column t of Y; LU field f of row i at
-    // LU[(f m + i) m + t]
-    const double eps_piv = DBL_EPSILON * tnorm + pivmin;
-    for (int t = tid; t < p; t += kPT) {
-        const double lmb = lam[m - 1 - t];
-        double* fa = LU + t;                // diagonal of U
-        double* fb = LU + mm * mm + t;      // first superdiagonal
-        double* fc = LU + 2 * mm * mm + t;  // second superdiagonal (fill-in)
-        double* fm = LU + 3 * mm * mm + t;  // multipliers
-        double* fp = LU + 4 * mm * mm + t;  // 1.0 where rows i, i+1 were swapped
-        double ai = dd[0] - lmb, bi = ee[0];
-        for (int i = 0; i + 1 < m; ++i) {
-            const double sub = ee[i];
-            const double an = dd[i + 1] - lmb;                // a[i+1] before step i
-            const double bn = (i + 2 < m) ? ee[i + 1] : 0.0;  // b[i+1] before step i
-            const int64_t o = (int64_t)i * mm;
-            if (fabs(ai) >= fabs(sub)) {
-                double a = ai;
-                if (fabs(a) < eps_piv) a = (a < 0.0) ? -eps_piv : eps_piv;
-                const double mu = sub / a;
-                fa[o] = a;
-                fb[o] = bi;
-                fc[o] = 0.0;
-                fm[o] = mu;
-                fp[o] = 0.0;
-                ai = an - mu * bi;
-                bi = bn;
-            } else {
-                const double mu = ai / sub;
-                fa[o] = sub;
-                fb[o] = an;
-                fc[o] = bn;
-                fm[o] = mu;
-                fp[o] = 1.0;
-                ai = bi - mu * an;
-                bi = -mu * bn;
+    // orthonormal basis in descending order (the LU area is free again)
+    double* Z = Zt;
+    double* Zb = LU;
+    bool done = false;
+    if (p <= kQRMax && p > 1) {
+        if (chol_qr(Z, Zb, p, m, lds)) {
+            double* tsw = Z;
+            Z = Zb;
+            Zb = tsw;
+            if (chol_qr(Z, Zb, p, m, lds)) {
+                tsw = Z;
+                Z = Zb;
+                Zb = tsw;
+                done = true;
             }
         }
-        if (fabs(ai) < eps_piv) ai = (ai < 0.0) ? -eps_piv : eps_piv;
-        fa[(int64_t)(m - 1) * mm] = ai;
-        double* z = Y + t;
-        for (int i = 0; i < m; ++i)
-            z[(int64_t)i * mm] = 1.0 + 0.5 * sin(0.7 * (double)(i + 1) + 1.3 * (double)(t + 1));
-        for (int iter = 0; iter < 3; ++iter) {
-            // forward: row swaps and multipliers
-            double zc = z[0];
-            for (int i = 0; i + 1 < m; ++i) {
-                const int64_t o = (int64_t)i * mm;
-                const double zn = z[o + mm];
-                const double mu = fm[o];
-                if (fp[o] != 0.0) {
-                    z[o] = zn;
-                    zc = zc - mu * zn;
-                } else {
-                    z[o] = zc;
-                    zc = zn - mu * zc;
-                }
-            }
-            // backward: U z = y
-            double z1 = zc / fa[(int64_t)(m - 1) * mm], z2 = 0.0;
-            z[(int64_t)(m - 1) * mm] = z1;
-            double nn = z1 * z1;
-            for (int i = m - 2; i >= 0; --i) {
-                const int64_t o = (int64_t)i * mm;
-                const double zi = (z[o] - fb[o] * z1 - fc[o] * z2) / fa[o];
-                z[o] = zi;
-                nn = fma(zi, zi, nn);
-                z2 = z1;
-                z1 = zi;
-            }
-            const double inv = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
-            for (int i = 0; i < m; ++i) z[(int64_t)i * mm] *= inv;
-        }
     }
+    if (!done) cgs2(Z, p, m, lds, red);
     __syncthreads();
-    // classical Gram-Schmidt, twice, in descending eigenvalue order (columns of Y)
-    for (int t = 1; t < p; ++t) {
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int q0 = 0; q0 < t; q0 += kPC) {
-                const int q = q0 + tc;
-                double s = 0.0;
-                if (q < t)
-                    for (int i = tr; i < m; i += kPG)
-                        s = fma(Y[(int64_t)i * mm + q], Y[(int64_t)i * mm + t], s);
-                part[tr][tc] = s;
-                __syncthreads();
-                if (tr == 0 && q < t) {
-                    double h = 0.0;
-                    for (int g = 0; g < kPG; ++g) h += part[g][tc];
-                    hcoef[q] = h;
-                }
-                __syncthreads();
-            }
-            for (int i = tid; i < m; i += kPT) {
-                const double* yi = Y + (int64_t)i * mm;
-                double acc = yi[t];
-                for (int q = 0; q < t; ++q) acc -= hcoef[q] * yi[q];
-                Y[(int64_t)i * mm + t] = acc;
-            }
-            __syncthreads();
-        }
-        double pp2 = 0.0;
-        for (int i = tid; i < m; i += kPT) pp2 += Y[(int64_t)i * mm + t] * Y[(int64_t)i * mm + t];
-        const double nn = block_sum(pp2, red);
-        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-        for (int i = tid; i < m; i += kPT) Y[(int64_t)i * mm + t] *= inv;
-        __syncthreads();
-    }
     // ---- 4. y = Q z, Q = H_0 ... H_{m-3}: panels last to first, each applied
-    // as I - V T V^T with V[r][q] = A[k0 + q][r] for r > k0 + q (zero otherwise)
+    // as I - V T V^T with V[q][r] = A[k0 + q][r] for r > k0 + q (zero
+    // otherwise).  T^{-1} = diag(1 / tau) + strict_upper(V V^T), so T Z1 is one
+    // upper-triangular back substitution per column.
+    double* Vs = lds;                      // kNB x (kRC + 1)
+    double* Zs = lds + kNB * (kRC + 1);    // kQRMax x (kRC + 1)
+    double* Z1 = Zs + kQRMax * (kRC + 1);  // kNB x (kQRMax + 1)
     const int nref = (m >= 2) ? m - 2 : 0;
+    constexpr int kPer = (kNB * kQRMax + kPT - 1) / kPT;  // (q, t) pairs per thread
+    const int ga = (tid < kNB * kNB) ? tid / kNB : 0, gb = (tid < kNB * kNB) ? tid % kNB : 0;
     for (int k0 = ((nref - 1) / kNB) * kNB; nref > 0 && k0 >= 0; k0 -= kNB) {
         const int nb = (k0 + kNB < nref) ? kNB : nref - k0;
-        // V^T V above the diagonal, zero elsewhere
-        for (int e = tid; e < kNB * kNB; e += kPT) {
-            const int a = e / kNB, b = e % kNB;
-            double s = 0.0;
-            if (a < b && b < nb) {
-                const double* va = A + (int64_t)(k0 + a) * mm;
-                const double* vb = A + (int64_t)(k0 + b) * mm;
-                for (int r = k0 + b + 1; r < m; ++r) s = fma(va[r], vb[r], s);
-            }
-            Tm[a][b] = s;
-        }
-        __syncthreads();
-        // T[b][b] = tau_b, T[a][b] = -tau_b sum_{c=a}^{b-1} T[a][c] (V^T V)[c][b]
-        for (int b = 0; b < nb; ++b) {
-            double s = 0.0;
-            if (tid < b)
-                for (int c = tid; c < b; ++c) s = fma(Tm[tid][c], Tm[c][b], s);
-            __syncthreads();
-            if (tid < b) Tm[tid][b] = -taus[k0 + b] * s;
-            if (tid == b) Tm[b][b] = taus[k0 + b];
-            __syncthreads();
-        }
-        for (int t0 = 0; t0 < p; t0 += kTC) {
-            const int nc = (p - t0 < kTC) ? p - t0 : kTC;
-            // Z1 = V^T Y[:, t0 .. t0 + nc)
-            for (int e = tid; e < nb * kTC; e += kPT) {
-                const int q = e / kTC, c = e % kTC;
-                double s = 0.0;
-                if (c < nc) {
-                    const double* vq = A + (int64_t)(k0 + q) * mm;
-                    for (int r = k0 + q + 1; r < m; ++r) s = fma(vq[r], Y[(int64_t)r * mm + t0 + c], s);
+        for (int t0 = 0; t0 < p; t0 += kQRMax) {
+            const int nc = (p - t0 < kQRMax) ? p - t0 : kQRMax;
+            double acc[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) acc[u] = 0.0;
+            double gacc = 0.0;  // (V V^T)[ga][gb], first column block only
+            for (int r0 = k0 + 1; r0 < m; r0 += kRC) {
+                for (int e = tid; e < kNB * kRC; e += kPT) {
+                    const int q = e / kRC, rr = e % kRC, r = r0 + rr;
+                    Vs[q * (kRC + 1) + rr] =
+                        (q < nb && r < m && r > k0 + q) ? A[(int64_t)(k0 + q) * mm + r] : 0.0;
                 }
-                Z1[q][c] = s;
+                for (int e = tid; e < nc * kRC; e += kPT) {
+                    const int t = e / kRC, rr = e % kRC, r = r0 + rr;
+                    Zs[t * (kRC + 1) + rr] = (r < m) ? Z[(int64_t)(t0 + t) * mm + r] : 0.0;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) {
+                    const int pr = tid + u * kPT, q = pr / kQRMax, t = pr % kQRMax;
+                    if (q < nb && t < nc) {
+                        const double* vq = Vs + q * (kRC + 1);
+                        const double* zt = Zs + t * (kRC + 1);
+                        double sacc = acc[u];
+                        for (int rr = 0; rr < kRC; ++rr) sacc = fma(vq[rr], zt[rr], sacc);
+                        acc[u] = sacc;
+                    }
+                }
+                if (t0 == 0 && tid < kNB * kNB && ga < gb && gb < nb) {
+                    const double* va = Vs + ga * (kRC + 1);
+                    const double* vb = Vs + gb * (kRC + 1);
+                    for (int rr = 0; rr < kRC; ++rr) gacc = fma(va[rr], vb[rr], gacc);
+                }
+                __syncthreads();
             }
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int pr = tid + u * kPT, q = pr / kQRMax, t = pr % kQRMax;
+                if (q < kNB) Z1[q * (kQRMax + 1) + t] = acc[u];
+            }
+            if (t0 == 0 && tid < kNB * kNB) Tm[ga][gb] = (ga < gb && gb < nb) ? gacc : 0.0;
             __syncthreads();
-            // Z2 = T Z1 in place (row q reads rows >= q)
+            // Z2 = T Z1: Z2[q] = tau_q (Z1[q] - sum_{b > q} (V V^T)[q][b] Z2[b])
             for (int c = tid; c < nc; c += kPT) {
-                for (int q = 0; q < nb; ++q) {
-                    double s = 0.0;
-                    for (int b = q; b < nb; ++b) s = fma(Tm[q][b], Z1[b][c], s);
-                    Z1[q][c] = s;
+                for (int q = nb - 1; q >= 0; --q) {
+                    double sacc = Z1[q * (kQRMax + 1) + c];
+                    for (int b2 = q + 1; b2 < nb; ++b2) sacc -= Tm[q][b2] * Z1[b2 * (kQRMax + 1) + c];
+                    Z1[q * (kQRMax + 1) + c] = taus[k0 + q] * sacc;
                 }
             }
             __syncthreads();
-            // Y -= V Z2 on rows > k0
-            for (int64_t e = tid; e < (int64_t)(m - k0 - 1) * nc; e += kPT) {
-                const int r = k0 + 1 + (int)(e / nc), c = (int)(e % nc);
-                double s = 0.0;
-                const int qmax = (r - k0 < nb) ? r - k0 : nb;  // V[r][q] != 0 for q < r - k0
-                for (int q = 0; q < qmax; ++q) s = fma(A[(int64_t)(k0 + q) * mm + r], Z1[q][c], s);
-                Y[(int64_t)r * mm + t0 + c] -= s;
+            // z_t[r] -= sum_q V[q][r] Z2[q][t] on rows > k0
+            for (int r0 = k0 + 1; r0 < m; r0 += kRC) {
+                for (int e = tid; e < kNB * kRC; e += kPT) {
+                    const int q = e / kRC, rr = e % kRC, r = r0 + rr;
+                    Vs[q * (kRC + 1) + rr] =
+                        (q < nb && r < m && r > k0 + q) ? A[(int64_t)(k0 + q) * mm + r] : 0.0;
+                }
+                __syncthreads();
+                for (int e = tid; e < nc * kRC; e += kPT) {
+                    const int t = e / kRC, rr = e % kRC, r = r0 + rr;
+                    if (r < m) {
+                        double sacc = 0.0;
+                        for (int q = 0; q < nb; ++q) sacc = fma(Vs[q * (kRC + 1) + rr], Z1[q * (kQRMax + 1) + t], sacc);
+                        Z[(int64_t)(t0 + t) * mm + r] -= sacc;
+                    }
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
+    }
+    // eigenvectors as columns of Y
+    for (int64_t e = tid; e < (int64_t)m * p; e += kPT) {
+        const int i = (int)(e / p), t = (int)(e % p);
+        Y[(int64_t)i * mm + t] = Z[(int64_t)t * mm + i];
     }
 }
 
@@ -532,7 +793,7 @@ __global__ void k_compact_V(const int32_t* __restrict__ mvec, const int32_t* __r
 
 }  // namespace
 
-int64_t eig_scratch_elems(int m) { return scr_LU(m) + 5LL * m * m; }
+int64_t eig_scratch_elems(int m) { return scr_LU(m) + 6LL * m * m; }
 
 int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const int64_t* d_s_off,
                 double* Y, double tol, int mode, int32_t* d_p, double* d_eig, int32_t* d_flags) {
@@ -568,12 +829,20 @@ int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const i
                                d_tasks + off[pi], h.d_m, d_g_off, G, S, d_s_off, k0);
         RDD_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_tri_solve, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S, d_s_off,
-                       Y, tol, mode, d_p, d_eig, h.d_m_off, d_flags);
+    double* d_lam = nullptr;
+    RDD_TRY(dev_alloc(h, &d_lam, (size_t)h.sum_m));
+    hipLaunchKernelGGL(k_bisect, dim3(J, (unsigned)((mmax + 63) / 64)), dim3(64), 0, h.stream, h.d_m, S,
+                       d_s_off, d_lam, h.d_m_off, d_eig);
+    hipLaunchKernelGGL(k_pcount, dim3(J), dim3(256), 0, h.stream, h.d_m, S, d_s_off, d_lam, tol, mode,
+                       d_p, h.d_m_off, d_flags);
+    hipLaunchKernelGGL(k_inviter, dim3(J, (unsigned)((mmax + 63) / 64)), dim3(64), 0, h.stream, h.d_m, S,
+                       d_s_off, d_lam, d_p, h.d_m_off);
+    hipLaunchKernelGGL(k_vectors, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S, d_s_off, Y, d_p);
     kt_.stop();
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));
     dev_free(h, d_tasks);
+    dev_free(h, d_lam);
     return RANN_OK;
 }
 
