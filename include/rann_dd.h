@@ -20,7 +20,9 @@
  *     row-major; multi-right-hand-side arrays are (rows, k) row-major (the
  *     right-hand-side index is fastest).
  *   - The caller owns every buffer it passes; the library copies what it keeps.
- *     The handle owns all internal device memory until rann_dd_destroy.
+ *     The handle owns all internal device memory until rann_dd_destroy, which
+ *     returns it to a process-wide cache of device blocks (reused by later
+ *     handles on the same device; rann_dd_trim_cache gives it back to HIP).
  *   - Work is ordered on the stream given to rann_dd_assemble.  Calls marked
  *     "synchronous" return after the device work has finished.
  *   - Return value: 0 = success; negative = error (outputs undefined, message in
@@ -209,15 +211,21 @@ RANN_API int rann_dd_get_blocks(const rann_dd_handle* h, int64_t* q);
 /* Kernel timing for measurement (process-wide, off by default).  When enabled,
  * the main kernels are bracketed by HIP events on the stream they run on;
  * rann_dd_ktime_enable(on) also clears the accumulated times.  Query by kernel
- * name ("k_eig", "k_factor_inverse", "k_pca_gram", "k_feat_rows",
+ * name ("k_eig", "k_factor", "k_pca_gram", "k_feat_rows",
  * "k_local_gram", "k_Hx", "k_HTy_part", "k_local_apply"): total milliseconds
  * and number of launches since the last enable.  Query synchronises on the
  * recorded events. */
 RANN_API int rann_dd_ktime_enable(int32_t on);
 RANN_API int rann_dd_ktime_query(const char* name, double* total_ms, int64_t* launches);
 
-/* Release the handle and its device memory (NULL is ignored). */
+/* Release the handle and its device memory (NULL is ignored).  The memory goes
+ * to the process-wide block cache. */
 RANN_API void rann_dd_destroy(rann_dd_handle* h);
+
+/* Free every cached device block and pinned staging buffer not held by a live
+ * handle, after a device synchronisation.  Returns the number of bytes
+ * released.  Not to be called while another thread uses the library. */
+RANN_API size_t rann_dd_trim_cache(void);
 
 /* Message of the last error on the calling thread ("" if none). */
 RANN_API const char* rann_dd_last_error(void);

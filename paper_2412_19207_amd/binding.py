@@ -84,6 +84,7 @@ _SIGS = {
     "rann_dd_ktime_query": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]),
     "rann_dd_destroy": (None, [ctypes.c_void_p]),
+    "rann_dd_trim_cache": (ctypes.c_size_t, []),
     "rann_dd_last_error": (ctypes.c_char_p, []),
 }
 
@@ -224,6 +225,10 @@ def rann_dd_ktime_query(name: str):
 
 def rann_dd_destroy(h):
     load().rann_dd_destroy(h)
+
+
+def rann_dd_trim_cache():
+    return int(load().rann_dd_trim_cache())
 
 
 def rann_dd_last_error() -> str:

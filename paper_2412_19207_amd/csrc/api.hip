@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -53,13 +54,206 @@ void ktime_record(const char* name, hipEvent_t a, hipEvent_t b) {
     if (g_ktime_pending.size() > 4096) ktime_flush_locked();
 }
 
+namespace {
+
+struct CachedBlock {
+    void* p;
+    hipStream_t stream;  // stream of the last use
+};
+
+constexpr int kCacheDevices = 64;
+
+struct DeviceCache {
+    std::mutex mu;
+    std::multimap<size_t, CachedBlock> free_blocks[kCacheDevices];
+    std::unordered_map<void*, size_t> size_of;  // every block the cache owns
+    std::multimap<size_t, char*> free_pinned;
+    std::unordered_map<char*, size_t> pinned_size;
+};
+
+// leaked on purpose: it outlives every handle and needs no teardown ordering
+DeviceCache& device_cache() {
+    static DeviceCache* c = new DeviceCache();
+    return *c;
+}
+
+size_t round_block(size_t b) {
+    if (b <= (size_t(1) << 20)) return (b + 511) & ~size_t(511);
+    const size_t g = size_t(2) << 20;
+    return (b + g - 1) / g * g;
+}
+
+size_t trim_device(DeviceCache& c, int device) {
+    size_t released = 0;
+    auto& fb = c.free_blocks[device];
+    for (auto& e : fb) {
+        (void)hipFree(e.second.p);
+        c.size_of.erase(e.second.p);
+        released += e.first;
+    }
+    fb.clear();
+    return released;
+}
+
+char* pinned_get(size_t bytes) {
+    DeviceCache& c = device_cache();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.free_pinned.lower_bound(bytes);
+        if (it != c.free_pinned.end()) {
+            char* p = it->second;
+            c.free_pinned.erase(it);
+            return p;
+        }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.pinned_size[static_cast<char*>(p)] = bytes;
+    return static_cast<char*>(p);
+}
+
+void pinned_put(char* p) {
+    DeviceCache& c = device_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.free_pinned.insert({c.pinned_size[p], p});
+}
+
+}  // namespace
+
+void* cache_alloc(int device, size_t bytes, hipStream_t stream, hipError_t* err) {
+    DeviceCache& c = device_cache();
+    const size_t r = round_block(bytes);
+    if (device < 0 || device >= kCacheDevices) device = 0;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto& fb = c.free_blocks[device];
+        auto it = fb.lower_bound(r);
+        if (it != fb.end() && it->first <= r + r / 4) {
+            CachedBlock b = it->second;
+            fb.erase(it);
+            // a block last used on another stream may still be read there
+            if (b.stream != stream) (void)hipDeviceSynchronize();
+            return b.p;
+        }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, r);
+    if (e != hipSuccess) {
+        {
+            std::lock_guard<std::mutex> lk(c.mu);
+            (void)hipDeviceSynchronize();
+            trim_device(c, device);
+        }
+        (void)hipGetLastError();
+        e = hipMalloc(&p, r);
+    }
+    if (e != hipSuccess) {
+        if (err) *err = e;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.size_of[p] = r;
+    return p;
+}
+
+void release_pinned(char* p) { pinned_put(p); }
+
+size_t cache_trim_all() {
+    DeviceCache& c = device_cache();
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lk(c.mu);
+    size_t released = 0;
+    for (int d = 0; d < kCacheDevices; ++d) released += trim_device(c, d);
+    for (auto& e : c.free_pinned) {
+        (void)hipHostFree(e.second);
+        c.pinned_size.erase(e.second);
+        released += e.first;
+    }
+    c.free_pinned.clear();
+    return released;
+}
+
+void cache_free(int device, void* p, hipStream_t stream) {
+    if (!p) return;
+    DeviceCache& c = device_cache();
+    if (device < 0 || device >= kCacheDevices) device = 0;
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.size_of.find(p);
+    if (it == c.size_of.end()) return;
+    c.free_blocks[device].insert({it->second, CachedBlock{p, stream}});
+}
+
 void dev_free(Handle& h, void* p) {
     if (!p) return;
     auto it = std::find(h.allocs.begin(), h.allocs.end(), p);
     if (it != h.allocs.end()) {
         h.allocs.erase(it);
-        (void)hipFree(p);
+        cache_free(h.device, p, h.stream);
     }
+}
+
+int upload(Handle& h, void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return RANN_OK;
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (h.stage.empty() || h.stage_used + need > h.stage.back().second) {
+        const size_t cap = std::max(need, size_t(4) << 20);
+        char* p = pinned_get(cap);
+        if (!p) {
+            set_error("pinned staging allocation failed");
+            return RANN_ENOMEM;
+        }
+        DeviceCache& c = device_cache();
+        size_t got = cap;
+        {
+            std::lock_guard<std::mutex> lk(c.mu);
+            got = c.pinned_size[p];
+        }
+        h.stage.push_back({p, got});
+        h.stage_used = 0;
+    }
+    char* s = h.stage.back().first + h.stage_used;
+    std::memcpy(s, src, bytes);
+    h.stage_used += need;
+    RDD_HIP(hipMemcpyAsync(dst, s, bytes, hipMemcpyHostToDevice, h.stream));
+    return RANN_OK;
+}
+
+int download(Handle& h, void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return RANN_OK;
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (h.stage.empty() || h.stage_used + need > h.stage.back().second) {
+        const size_t cap = std::max(need, size_t(4) << 20);
+        char* p = pinned_get(cap);
+        if (!p) {
+            set_error("pinned staging allocation failed");
+            return RANN_ENOMEM;
+        }
+        DeviceCache& c = device_cache();
+        size_t got = cap;
+        {
+            std::lock_guard<std::mutex> lk(c.mu);
+            got = c.pinned_size[p];
+        }
+        h.stage.push_back({p, got});
+        h.stage_used = 0;
+    }
+    char* s = h.stage.back().first + h.stage_used;
+    RDD_HIP(hipMemcpyAsync(s, src, bytes, hipMemcpyDeviceToHost, h.stream));
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    std::memcpy(dst, s, bytes);
+    stage_reset(h);  // the stream is idle: every staged copy has completed
+    return RANN_OK;
+}
+
+void stage_reset(Handle& h) {
+    // keep the current chunk, give the older ones back
+    if (h.stage.size() > 1) {
+        for (size_t i = 0; i + 1 < h.stage.size(); ++i) pinned_put(h.stage[i].first);
+        h.stage.erase(h.stage.begin(), h.stage.end() - 1);
+    }
+    h.stage_used = 0;
 }
 
 int ensure_ws(Handle& h, size_t bytes) {
@@ -215,11 +409,11 @@ static int assemble_impl(const rann_dd_desc* ds, void* stream, Handle*& hp) {
     for (int64_t j = 0; j < J; ++j) h->m_off[j + 1] = h->m_off[j] + h->m[j];
     h->sum_m = h->m_off[J];
     RDD_TRY(dev_alloc(*h, &h->d_mu, (size_t)sum_l));
-    RDD_HIP(hipMemcpy(h->d_mu, ds->mu, sizeof(double) * sum_l, hipMemcpyHostToDevice));
+    RDD_TRY(upload(*h, h->d_mu, ds->mu, sizeof(double) * sum_l));
     RDD_TRY(dev_alloc(*h, &h->d_m, (size_t)J));
     RDD_TRY(dev_alloc(*h, &h->d_m_off, (size_t)J + 1));
-    RDD_HIP(hipMemcpy(h->d_m, h->m.data(), sizeof(int32_t) * J, hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h->d_m_off, h->m_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+    RDD_TRY(upload(*h, h->d_m, h->m.data(), sizeof(int32_t) * J));
+    RDD_TRY(upload(*h, h->d_m_off, h->m_off.data(), sizeof(int64_t) * (J + 1)));
     RDD_TRY(dev_alloc(*h, &h->d_Rf, (size_t)h->sum_m * 4));
     RDD_TRY(dev_alloc(*h, &h->d_bf, (size_t)h->sum_m));
     hipLaunchKernelGGL(k_pad_features, dim3((unsigned)((h->sum_m + 255) / 256)), dim3(256), 0,
@@ -292,15 +486,15 @@ static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, con
         RDD_TRY(dev_alloc(h, &d_g_off, (size_t)J + 1));
         RDD_TRY(dev_alloc(h, &d_s_off, (size_t)J + 1));
         RDD_TRY(dev_alloc(h, &flags, 2));
-        RDD_HIP(hipMemcpy(d_g_off, g_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
-        RDD_HIP(hipMemcpy(d_s_off, s_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+        RDD_TRY(upload(h, d_g_off, g_off.data(), sizeof(int64_t) * (J + 1)));
+        RDD_TRY(upload(h, d_s_off, s_off.data(), sizeof(int64_t) * (J + 1)));
         RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, h.stream));
         RDD_TRY(pca_gram(h, G, g_off.data(), d_g_off));
         RDD_TRY(eig_batched(h, G, d_g_off, Z, d_s_off, Y, tol, mode, h.d_p, h.d_eig, flags));
         dev_free(h, d_s_off);
         int32_t fl[2];
-        RDD_HIP(hipMemcpy(fl, flags, sizeof(fl), hipMemcpyDeviceToHost));
-        RDD_HIP(hipMemcpy(h.p.data(), h.d_p, sizeof(int32_t) * J, hipMemcpyDeviceToHost));
+        RDD_TRY(download(h, fl, flags, sizeof(fl)));
+        RDD_TRY(download(h, h.p.data(), h.d_p, sizeof(int32_t) * J));
         dev_free(h, Z);
         dev_free(h, G);
         dev_free(h, flags);
@@ -324,7 +518,7 @@ static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, con
             h.p[j] = p_force[j];
         }
     }
-    RDD_HIP(hipMemcpy(h.d_p, h.p.data(), sizeof(int32_t) * J, hipMemcpyHostToDevice));
+    RDD_TRY(upload(h, h.d_p, h.p.data(), sizeof(int32_t) * J));
     h.col_off.assign(J + 1, 0);
     h.v_off.assign(J + 1, 0);
     h.h_off.assign(J + 1, 0);
@@ -338,9 +532,9 @@ static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, con
     RDD_TRY(dev_alloc(h, &h.d_col_off, J + 1));
     RDD_TRY(dev_alloc(h, &h.d_v_off, J + 1));
     RDD_TRY(dev_alloc(h, &h.d_h_off, J + 1));
-    RDD_HIP(hipMemcpy(h.d_col_off, h.col_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h.d_v_off, h.v_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h.d_h_off, h.h_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+    RDD_TRY(upload(h, h.d_col_off, h.col_off.data(), sizeof(int64_t) * (J + 1)));
+    RDD_TRY(upload(h, h.d_v_off, h.v_off.data(), sizeof(int64_t) * (J + 1)));
+    RDD_TRY(upload(h, h.d_h_off, h.h_off.data(), sizeof(int64_t) * (J + 1)));
     RDD_TRY(dev_alloc(h, &h.d_V, (size_t)h.v_off[J]));
     if (V_force) {
         RDD_HIP(hipMemcpyAsync(h.d_V, V_force, sizeof(double) * h.v_off[J], hipMemcpyDeviceToDevice,
@@ -622,11 +816,15 @@ int rann_dd_get_blocks(const rann_dd_handle* hh, int64_t* q) {
     return RANN_OK;
 }
 
+size_t rann_dd_trim_cache(void) { return rdd::cache_trim_all(); }
+
 void rann_dd_destroy(rann_dd_handle* hh) {
     if (!hh) return;
     (void)hipStreamSynchronize(hh->h.stream);
-    for (void* p : hh->h.allocs) (void)hipFree(p);
+    for (void* p : hh->h.allocs) rdd::cache_free(hh->h.device, p, hh->h.stream);
     hh->h.allocs.clear();
+    for (auto& c : hh->h.stage) rdd::release_pinned(c.first);
+    hh->h.stage.clear();
     delete hh;
 }
 

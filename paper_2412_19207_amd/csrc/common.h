@@ -122,6 +122,8 @@ struct Handle {
     void* ws2 = nullptr;           // true-residual scratch
     size_t ws2_bytes = 0;
     double* pinned = nullptr;      // host pinned scalars
+    std::vector<std::pair<char*, size_t>> stage;  // pinned staging chunks (last one current)
+    size_t stage_used = 0;
 
     double setup_ms[4] = {0, 0, 0, 0};  // assemble, pca+factor host-clock times
 
@@ -147,14 +149,21 @@ void set_error(const std::string& msg);
         if (r_ < 0) return r_;                                                 \
     } while (0)
 
+// Device memory comes from a process-wide cache: blocks released by dev_free
+// are kept per device and size and handed out again, so the set-up and solve
+// calls do not pay for hipMalloc/hipFree each time (rann_dd_trim_cache returns
+// them to the runtime).
+void* cache_alloc(int device, size_t bytes, hipStream_t stream, hipError_t* err);
+void cache_free(int device, void* p, hipStream_t stream);
+
 template <class T>
 int dev_alloc(Handle& h, T** ptr, size_t count) {
     *ptr = nullptr;
     if (count == 0) count = 1;
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-        set_error("hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " +
+    hipError_t e = hipSuccess;
+    void* p = cache_alloc(h.device, count * sizeof(T), h.stream, &e);
+    if (!p) {
+        set_error("device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed: " +
                   hipGetErrorString(e));
         return RANN_ENOMEM;
     }
@@ -162,6 +171,14 @@ int dev_alloc(Handle& h, T** ptr, size_t count) {
     *ptr = static_cast<T*>(p);
     return RANN_OK;
 }
+
+// Host -> device copy ordered on the handle's stream through pinned staging
+// memory (the source may be released on return).
+int upload(Handle& h, void* dst, const void* src, size_t bytes);
+// Device -> host copy through pinned staging memory; synchronises the stream.
+int download(Handle& h, void* dst, const void* src, size_t bytes);
+// Release staging space; call only when the handle's stream is idle.
+void stage_reset(Handle& h);
 
 void dev_free(Handle& h, void* p);
 int ensure_ws(Handle& h, size_t bytes);

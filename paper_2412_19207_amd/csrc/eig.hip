@@ -56,6 +56,10 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------- 1. panel
+constexpr int kMG = 4;                  // row groups of the panel matrix-vector product
+constexpr int kMC = kPT / kMG;          // column lanes (256)
+constexpr int kMU = kMaxWidth / kMC;    // columns per thread (4)
+
 // Steps k = k0 .. k0 + kNB - 1 of the reduction of every matrix.  With V the
 // panel's reflectors (rows of A) and W its update vectors (rows of Wb), the
 // current matrix is A_start - V W^T - W V^T on rows/columns >= k.
@@ -67,8 +71,8 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
     __shared__ double x[kMaxWidth];
     __shared__ double v[kMaxWidth];
     __shared__ double w[kMaxWidth];
-    __shared__ double part[kPG][kPC + 1];
-    __shared__ double hv[kNB], hw[kNB];
+    __shared__ double part[kMG][kMaxWidth];
+    __shared__ double hv[kNB], hw[kNB], sv[kNB], sw[kNB];
     __shared__ double red[kPT / 64];
     const int j = blockIdx.x;
     const int m = mvec[j];
@@ -81,21 +85,29 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
     double* ee = tri + mm;
     double* taus = tri + 2 * mm;
     const int tid = threadIdx.x;
-    const int tc = tid % kPC, tr = tid / kPC;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int mg = tid / kMC, mc = tid % kMC;
     const int kend = (k0 + kNB < m) ? k0 + kNB : m;
     for (int k = k0; k < kend; ++k) {
         const int i = k - k0;
         const int n1 = m - k - 1;
+        // the panel's earlier reflectors at row k: V[k][q] and W[k][q]
+        if (tid < i) {
+            sv[tid] = A[(int64_t)(k0 + tid) * mm + k];
+            sw[tid] = Wb[(int64_t)tid * mm + k];
+        }
+        __syncthreads();
         // row k of the current matrix, entries c >= k
         for (int c = k + tid; c < m; c += kPT) {
-            double s = A[(int64_t)k * mm + c];
-            for (int q = 0; q < i; ++q) {
-                const double* Vq = A + (int64_t)(k0 + q) * mm;
-                const double* Wq = Wb + (int64_t)q * mm;
-                s -= Vq[k] * Wq[c] + Wq[k] * Vq[c];
+            double s0 = A[(int64_t)k * mm + c], s1 = 0.0;
+            int q = 0;
+            for (; q + 1 < i; q += 2) {
+                const double w0 = Wb[(int64_t)q * mm + c], v0 = A[(int64_t)(k0 + q) * mm + c];
+                const double w1 = Wb[(int64_t)(q + 1) * mm + c], v1 = A[(int64_t)(k0 + q + 1) * mm + c];
+                s0 -= sv[q] * w0 + sw[q] * v0;
+                s1 -= sv[q + 1] * w1 + sw[q + 1] * v1;
             }
-            x[c - k] = s;
+            if (q < i) s0 -= sv[q] * Wb[(int64_t)q * mm + c] + sw[q] * A[(int64_t)(k0 + q) * mm + c];
+            x[c - k] = s0 + s1;
         }
         __syncthreads();
         if (n1 < 2) {  // no reflector: the last 2 x 2 block is already tridiagonal
@@ -112,11 +124,11 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
         double pp = 0.0;
         for (int c = tid; c < n1; c += kPT) pp += x[1 + c] * x[1 + c];
         const double nrm2 = block_sum(pp, red);
-        const double v0 = x[1];
-        const double alpha = (v0 >= 0.0) ? -sqrt(nrm2) : sqrt(nrm2);
-        const double tau = (nrm2 > 0.0) ? 1.0 / (nrm2 - v0 * alpha) : 0.0;  // 2 / v^T v
+        const double x1 = x[1];
+        const double alpha = (x1 >= 0.0) ? -sqrt(nrm2) : sqrt(nrm2);
+        const double tau = (nrm2 > 0.0) ? 1.0 / (nrm2 - x1 * alpha) : 0.0;  // 2 / v^T v
         for (int c = tid; c < n1; c += kPT) {
-            const double vc = (nrm2 > 0.0) ? ((c == 0) ? v0 - alpha : x[1 + c]) : 0.0;
+            const double vc = (nrm2 > 0.0) ? ((c == 0) ? x1 - alpha : x[1 + c]) : 0.0;
             v[c] = vc;
             A[(int64_t)k * mm + k + 1 + c] = vc;
         }
@@ -126,55 +138,79 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
             taus[k] = tau;
         }
         __syncthreads();
-        // p = A_start[k+1.., k+1..] v  (column sums, 16 row groups)
+        // p = A_start[k+1.., k+1..] v: thread (mg, mc) sums rows r = mg (mod kMG)
+        // of columns mc + kMC u, four rows per batch of loads
         const double* Ap = A + (int64_t)(k + 1) * mm + (k + 1);
-        for (int c0 = 0; c0 < n1; c0 += kPC) {
-            const int c = c0 + tc;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            if (c < n1) {
-                int r = tr;
-                for (; r + 3 * kPG < n1; r += 4 * kPG) {
-                    s0 = fma(Ap[(int64_t)r * mm + c], v[r], s0);
-                    s1 = fma(Ap[(int64_t)(r + kPG) * mm + c], v[r + kPG], s1);
-                    s2 = fma(Ap[(int64_t)(r + 2 * kPG) * mm + c], v[r + 2 * kPG], s2);
-                    s3 = fma(Ap[(int64_t)(r + 3 * kPG) * mm + c], v[r + 3 * kPG], s3);
+        const int ncu = (n1 + kMC - 1) / kMC;
+        double acc[kMU];
+#pragma unroll
+        for (int u = 0; u < kMU; ++u) acc[u] = 0.0;
+        int r = mg;
+        for (; r + 3 * kMG < n1; r += 4 * kMG) {
+            const double v0 = v[r], v1 = v[r + kMG], v2 = v[r + 2 * kMG], v3 = v[r + 3 * kMG];
+            const double* a0 = Ap + (int64_t)r * mm;
+            const double* a1 = a0 + kMG * mm;
+            const double* a2 = a1 + kMG * mm;
+            const double* a3 = a2 + kMG * mm;
+#pragma unroll
+            for (int u = 0; u < kMU; ++u) {
+                const int c = mc + u * kMC;
+                if (u < ncu && c < n1) {
+                    const double t0 = a0[c], t1 = a1[c], t2 = a2[c], t3 = a3[c];
+                    acc[u] = fma(t0, v0, fma(t1, v1, fma(t2, v2, fma(t3, v3, acc[u]))));
                 }
-                for (; r < n1; r += kPG) s0 = fma(Ap[(int64_t)r * mm + c], v[r], s0);
             }
-            part[tr][tc] = (s0 + s1) + (s2 + s3);
-            __syncthreads();
-            if (tr == 0 && c < n1) {
-                double s = 0.0;
-                for (int g = 0; g < kPG; ++g) s += part[g][tc];
-                w[c] = s;
-            }
-            __syncthreads();
         }
-        // hv = W^T v, hw = V^T v over rows k+1 .. m-1 (one wave per dot product)
-        for (int dq = wave; dq < 2 * i; dq += kPT / 64) {
-            const int q = dq >> 1;
-            const double* src = (dq & 1) ? A + (int64_t)(k0 + q) * mm : Wb + (int64_t)q * mm;
-            double s = 0.0;
-            for (int c = lane; c < n1; c += 64) s = fma(src[k + 1 + c], v[c], s);
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            if (lane == 0) {
+        for (; r < n1; r += kMG) {
+            const double vr = v[r];
+            const double* a0 = Ap + (int64_t)r * mm;
+#pragma unroll
+            for (int u = 0; u < kMU; ++u) {
+                const int c = mc + u * kMC;
+                if (u < ncu && c < n1) acc[u] = fma(a0[c], vr, acc[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kMU; ++u) {
+            const int c = mc + u * kMC;
+            if (u < ncu && c < n1) part[mg][c] = acc[u];
+        }
+        // hv = W^T v, hw = V^T v over rows k+1 .. m-1: 16 lanes per dot product
+        {
+            const int dq = tid >> 4, g = tid & 15;
+            double sacc = 0.0;
+            if (dq < 2 * i) {
+                const int q = dq >> 1;
+                const double* src = ((dq & 1) ? A + (int64_t)(k0 + q) * mm : Wb + (int64_t)q * mm) + k + 1;
+                for (int c = g; c < n1; c += 16) sacc = fma(src[c], v[c], sacc);
+            }
+            for (int off = 8; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off);
+            if (dq < 2 * i && g == 0) {
                 if (dq & 1)
-                    hw[q] = s;
+                    hw[dq >> 1] = sacc;
                 else
-                    hv[q] = s;
+                    hv[dq >> 1] = sacc;
             }
         }
         __syncthreads();
         // w = tau (p - V hv - W hw), then w -= (tau/2)(w^T v) v
         double pv = 0.0;
         for (int c = tid; c < n1; c += kPT) {
-            double s = w[c];
-            for (int q = 0; q < i; ++q)
-                s -= A[(int64_t)(k0 + q) * mm + k + 1 + c] * hv[q] +
-                     Wb[(int64_t)q * mm + k + 1 + c] * hw[q];
-            s *= tau;
-            w[c] = s;
-            pv += s * v[c];
+            double s0 = 0.0;
+#pragma unroll
+            for (int g = 0; g < kMG; ++g) s0 += part[g][c];
+            double s1 = 0.0;
+            int q = 0;
+            for (; q + 1 < i; q += 2) {
+                const double a0 = A[(int64_t)(k0 + q) * mm + k + 1 + c], b0 = Wb[(int64_t)q * mm + k + 1 + c];
+                const double a1 = A[(int64_t)(k0 + q + 1) * mm + k + 1 + c], b1 = Wb[(int64_t)(q + 1) * mm + k + 1 + c];
+                s0 -= a0 * hv[q] + b0 * hw[q];
+                s1 -= a1 * hv[q + 1] + b1 * hw[q + 1];
+            }
+            if (q < i) s0 -= A[(int64_t)(k0 + q) * mm + k + 1 + c] * hv[q] + Wb[(int64_t)q * mm + k + 1 + c] * hw[q];
+            const double wc = tau * (s0 + s1);
+            w[c] = wc;
+            pv += wc * v[c];
         }
         const double K = 0.5 * tau * block_sum(pv, red);
         double* Wi = Wb + (int64_t)i * mm;
@@ -478,6 +514,14 @@ __device__ void cgs2(double* Zt, int p, int m, double* hcoef, double* red) {
     }
 }
 
+// element i of a vector stored with a fixed stride (vectors interleaved so
+// that the lanes of a wave touch adjacent addresses)
+struct StridedRef {
+    double* base;
+    int64_t stride;
+    __device__ __forceinline__ double& operator[](int64_t i) const { return base[i * stride]; }
+};
+
 // p (the Sturm count at the truncation threshold) and the tie flag; one
 // workgroup per matrix
 __global__ void __launch_bounds__(256) k_pcount(const int32_t* __restrict__ mvec,
@@ -517,8 +561,8 @@ __global__ void __launch_bounds__(256) k_pcount(const int32_t* __restrict__ mvec
 }
 
 // eigenvectors of T for the p largest eigenvalues by inverse iteration, one
-// thread per vector (vector t <-> lam[m-1-t]); vector t is row t of Zt and its
-// LU factors are 5 rows of m entries
+// thread per vector (vector t <-> lam[m-1-t]); entry i of vector t is kept at
+// Zt[i m + t] and its LU factors at LU[(f m + i) m + t]
 __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec,
                                                 double* __restrict__ Sall,
                                                 const int64_t* __restrict__ s_off,
@@ -551,11 +595,12 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
     const double eps_piv = DBL_EPSILON * tb.tnorm + tb.pivmin;
     {
         const double lmb = lam[m - 1 - t];
-        double* __restrict__ fr = LU + (int64_t)t * 5 * mm;  // reciprocal of the diagonal of U
-        double* __restrict__ fb = fr + mm;                    // first superdiagonal
-        double* __restrict__ fc = fr + 2 * mm;                // second superdiagonal (fill-in)
-        double* __restrict__ fm = fr + 3 * mm;                // multipliers
-        double* __restrict__ fp = fr + 4 * mm;                // 1.0 where rows i, i+1 were swapped
+        // field f of step i at LU[(f m + i) m + t]: consecutive vectors are adjacent
+        StridedRef fr{LU + t, mm};                  // reciprocal of the diagonal of U
+        StridedRef fb{LU + mm * mm + t, mm};        // first superdiagonal
+        StridedRef fc{LU + 2 * mm * mm + t, mm};    // second superdiagonal (fill-in)
+        StridedRef fm{LU + 3 * mm * mm + t, mm};    // multipliers
+        StridedRef fp{LU + 4 * mm * mm + t, mm};    // 1.0 where rows i, i+1 were swapped
         double ai = dd[0] - lmb, bi = ee[0];
         for (int i = 0; i + 1 < m; ++i) {
             const double sub = ee[i];
@@ -585,7 +630,7 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
         }
         if (fabs(ai) < eps_piv) ai = (ai < 0.0) ? -eps_piv : eps_piv;
         fr[m - 1] = 1.0 / ai;
-        double* __restrict__ z = Zt + (int64_t)t * mm;
+        StridedRef z{Zt + t, mm};  // z_t[i] at Zt[i m + t]
         for (int i = 0; i < m; ++i) z[i] = 1.0 + 0.5 * sin(0.7 * (double)(i + 1) + 1.3 * (double)(t + 1));
         for (int iter = 0; iter < 3; ++iter) {
             // forward: row swaps and multipliers, 8 steps per batch of loads
@@ -671,9 +716,15 @@ __global__ void __launch_bounds__(kPT) k_vectors(const int32_t* __restrict__ mve
     double* LU = Sall + s_off[j] + scr_LU(mm);
     double* Zt = LU + 5 * mm * mm;
     const int tid = threadIdx.x;
-    // orthonormal basis in descending order (the LU area is free again)
-    double* Z = Zt;
-    double* Zb = LU;
+    // vectors as rows ([t][i]) in the LU area, which is free again
+    for (int64_t e = tid; e < (int64_t)m * p; e += kPT) {
+        const int i = (int)(e / p), t = (int)(e % p);
+        LU[(int64_t)t * mm + i] = Zt[(int64_t)i * mm + t];
+    }
+    __syncthreads();
+    // orthonormal basis in descending order
+    double* Z = LU;
+    double* Zb = Zt;
     bool done = false;
     if (p <= kQRMax && p > 1) {
         if (chol_qr(Z, Zb, p, m, lds)) {
@@ -818,7 +869,7 @@ int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const i
     int4* d_tasks = nullptr;
     RDD_TRY(dev_alloc(h, &d_tasks, tasks.size()));
     if (!tasks.empty())
-        RDD_HIP(hipMemcpy(d_tasks, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice));
+        RDD_TRY(upload(h, d_tasks, tasks.data(), sizeof(int4) * tasks.size()));
     int pi = 0;
     for (int k0 = 0; k0 < mmax; k0 += kNB, ++pi) {
         hipLaunchKernelGGL(k_tri_panel, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S,

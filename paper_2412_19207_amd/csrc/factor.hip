@@ -317,7 +317,7 @@ int plan_tiles(Handle& h) {
     }
     h.tile_elems = h.t_off[J];
     RDD_TRY(dev_alloc(h, &h.d_t_off, (size_t)J + 1));
-    RDD_HIP(hipMemcpy(h.d_t_off, h.t_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+    RDD_TRY(upload(h, h.d_t_off, h.t_off.data(), sizeof(int64_t) * (J + 1)));
     return RANN_OK;
 }
 
@@ -330,7 +330,7 @@ struct Launch {
 int upload_tasks(Handle& h, const std::vector<TileTask>& v, TileTask** d) {
     RDD_TRY(dev_alloc(h, d, v.size()));
     if (!v.empty())
-        RDD_HIP(hipMemcpy(*d, v.data(), sizeof(TileTask) * v.size(), hipMemcpyHostToDevice));
+        RDD_TRY(upload(h, *d, v.data(), sizeof(TileTask) * v.size()));
     return RANN_OK;
 }
 
@@ -355,7 +355,7 @@ int factor_tiles(Handle& h, double* A, double* W) {
     RDD_TRY(dev_alloc(h, &d_xd_off, (size_t)J + 1));
     RDD_TRY(dev_alloc(h, &d_bad, (size_t)J));
     RDD_TRY(dev_alloc(h, &d_blks, (size_t)J));
-    RDD_HIP(hipMemcpy(d_xd_off, xd_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
+    RDD_TRY(upload(h, d_xd_off, xd_off.data(), sizeof(int64_t) * (J + 1)));
     hipLaunchKernelGGL(k_equil, dim3(J), dim3(256), 0, h.stream, h.d_f_off, h.d_q, h.d_ub_off, A, d_D);
     RDD_HIP(hipGetLastError());
 
@@ -389,8 +389,8 @@ int factor_tiles(Handle& h, double* A, double* W) {
         TileTask* d_tasks = nullptr;
         RDD_TRY(upload_tasks(h, tasks, &d_tasks));
         task_bufs.push_back(d_tasks);
-        RDD_HIP(hipMemcpy(d_eps, eps.data(), sizeof(double) * J, hipMemcpyHostToDevice));
-        RDD_HIP(hipMemcpy(d_blks, active.data(), sizeof(int32_t) * active.size(), hipMemcpyHostToDevice));
+        RDD_TRY(upload(h, d_eps, eps.data(), sizeof(double) * J));
+        RDD_TRY(upload(h, d_blks, active.data(), sizeof(int32_t) * active.size()));
         hipLaunchKernelGGL(k_scale_shift, dim3(64, (unsigned)active.size()), dim3(256), 0, h.stream,
                            d_blks, h.d_f_off, h.d_q, h.d_ub_off, d_eps, A, d_D, W, d_bad);
         RDD_HIP(hipGetLastError());
@@ -406,7 +406,7 @@ int factor_tiles(Handle& h, double* A, double* W) {
                                    d_tasks + trail[s].off, s, h.d_f_off, h.d_q, W, d_bad);
             RDD_HIP(hipGetLastError());
         }
-        RDD_HIP(hipMemcpyAsync(bad.data(), d_bad, sizeof(int32_t) * J, hipMemcpyDeviceToHost, h.stream));
+        RDD_TRY(download(h, bad.data(), d_bad, sizeof(int32_t) * J));
         RDD_HIP(hipStreamSynchronize(h.stream));
         std::vector<int32_t> again;
         for (int i : active)

@@ -321,8 +321,7 @@ int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g
     }
     GramTile* d_t = nullptr;
     RDD_TRY(dev_alloc(h, &d_t, tiles.size()));
-    RDD_HIP(hipMemcpyAsync(d_t, tiles.data(), sizeof(GramTile) * tiles.size(),
-                           hipMemcpyHostToDevice, h.stream));
+    RDD_TRY(upload(h, d_t, tiles.data(), sizeof(GramTile) * tiles.size()));
     KTimer kt_(h.stream, "k_pca_gram");
     hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, h.geo, d_t,
                        h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, d_g_off, G);
@@ -344,8 +343,7 @@ int feature_rows(Handle& h) {
     if (tiles.empty()) return RANN_OK;
     GramTile* d_t = nullptr;
     RDD_TRY(dev_alloc(h, &d_t, tiles.size()));
-    RDD_HIP(hipMemcpyAsync(d_t, tiles.data(), sizeof(GramTile) * tiles.size(),
-                           hipMemcpyHostToDevice, h.stream));
+    RDD_TRY(upload(h, d_t, tiles.data(), sizeof(GramTile) * tiles.size()));
     KTimer kt_(h.stream, "k_feat_rows");
     hipLaunchKernelGGL(k_feat_rows, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, h.geo, d_t,
                        h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, h.d_p,
@@ -372,8 +370,7 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
     std::vector<std::vector<double>> cen(J, std::vector<double>(h.geo.d));
     {
         std::vector<double> mu_all(h.geo.mu_off[h.geo.d - 1] + h.geo.l[h.geo.d - 1]);
-        RDD_HIP(hipMemcpy(mu_all.data(), h.d_mu, sizeof(double) * mu_all.size(),
-                          hipMemcpyDeviceToHost));
+        RDD_TRY(download(h, mu_all.data(), h.d_mu, sizeof(double) * mu_all.size()));
         for (int j = 0; j < J; ++j)
             for (int i = 0; i < h.geo.d; ++i) cen[j][i] = mu_all[h.geo.mu_off[i] + centre(j, i)];
     }
@@ -408,14 +405,14 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
     RDD_TRY(dev_alloc(h, &d_blocks, nb));
     // count shared rows
     for (auto& B : blocks) B.len = (B.isect < 0) ? (h.pts.row_off[B.j + 1] - h.pts.row_off[B.j]) : 0;
-    RDD_HIP(hipMemcpy(d_blocks, blocks.data(), sizeof(PairBlock) * nb, hipMemcpyHostToDevice));
+    RDD_TRY(upload(h, d_blocks, blocks.data(), sizeof(PairBlock) * nb));
     int64_t* d_cnt = nullptr;
     RDD_TRY(dev_alloc(h, &d_cnt, nb));
     hipLaunchKernelGGL((k_intersect<false>), dim3(nb), dim3(256), 0, h.stream, d_blocks,
                        h.pts.d_row_off, h.pts.d_rows, d_cnt, nullptr, nullptr);
     RDD_HIP(hipGetLastError());
     std::vector<int64_t> cnt(nb);
-    RDD_HIP(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, h.stream));
+    RDD_TRY(download(h, cnt.data(), d_cnt, sizeof(int64_t) * nb));
     RDD_HIP(hipStreamSynchronize(h.stream));
     int64_t tot_isect = 0, tot_g = 0;
     for (int b = 0; b < nb; ++b) {
@@ -428,7 +425,7 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
         B.g_off = tot_g;
         tot_g += (int64_t)h.p[B.j] * h.p[B.k];
     }
-    RDD_HIP(hipMemcpy(d_blocks, blocks.data(), sizeof(PairBlock) * nb, hipMemcpyHostToDevice));
+    RDD_TRY(upload(h, d_blocks, blocks.data(), sizeof(PairBlock) * nb));
     int32_t *d_lj = nullptr, *d_lk = nullptr;
     RDD_TRY(dev_alloc(h, &d_lj, (size_t)tot_isect));
     RDD_TRY(dev_alloc(h, &d_lk, (size_t)tot_isect));
@@ -446,7 +443,7 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
     }
     LocalTile* d_tiles = nullptr;
     RDD_TRY(dev_alloc(h, &d_tiles, tiles.size()));
-    RDD_HIP(hipMemcpy(d_tiles, tiles.data(), sizeof(LocalTile) * tiles.size(), hipMemcpyHostToDevice));
+    RDD_TRY(upload(h, d_tiles, tiles.data(), sizeof(LocalTile) * tiles.size()));
     if (!tiles.empty()) {
         KTimer kt_(h.stream, "k_local_gram");
         hipLaunchKernelGGL((k_local_gram<T>), dim3((unsigned)tiles.size()), dim3(256), 0, h.stream,
@@ -479,9 +476,9 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
     RDD_TRY(dev_alloc(h, &d_so, sten_off.size()));
     RDD_TRY(dev_alloc(h, &d_sf, sten_flat.size()));
     RDD_TRY(dev_alloc(h, &d_po, pair_of.size()));
-    RDD_HIP(hipMemcpy(d_so, sten_off.data(), sizeof(int32_t) * sten_off.size(), hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(d_sf, sten_flat.data(), sizeof(int32_t) * sten_flat.size(), hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(d_po, pair_of.data(), sizeof(int32_t) * pair_of.size(), hipMemcpyHostToDevice));
+    RDD_TRY(upload(h, d_so, sten_off.data(), sizeof(int32_t) * sten_off.size()));
+    RDD_TRY(upload(h, d_sf, sten_flat.data(), sizeof(int32_t) * sten_flat.size()));
+    RDD_TRY(upload(h, d_po, pair_of.data(), sizeof(int32_t) * pair_of.size()));
     hipLaunchKernelGGL((k_assemble_A<T>), dim3(J, max_ns * 32), dim3(256), 0, h.stream, J, d_so, d_sf,
                        d_po, d_blocks, h.d_p, h.d_f_off, d_G, A_out);
     RDD_HIP(hipGetLastError());

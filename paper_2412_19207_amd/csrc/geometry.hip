@@ -344,8 +344,7 @@ int bin_points(Handle& h, const double* X, int64_t n, PointSet& ps) {
                        nullptr, nullptr, nullptr);
     RDD_HIP(hipGetLastError());
     std::vector<int64_t> cnt(g.J);
-    RDD_HIP(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int64_t) * g.J, hipMemcpyDeviceToHost,
-                           h.stream));
+    RDD_TRY(download(h, cnt.data(), d_cnt, sizeof(int64_t) * g.J));
     RDD_HIP(hipStreamSynchronize(h.stream));
     dev_free(h, d_cnt);
     ps.row_off.assign(g.J + 1, 0);
@@ -358,8 +357,7 @@ int bin_points(Handle& h, const double* X, int64_t n, PointSet& ps) {
     RDD_TRY(dev_alloc(h, &ps.d_row_off, (size_t)g.J + 1));
     RDD_TRY(dev_alloc(h, &ps.d_rows, (size_t)ps.pairs));
     RDD_TRY(dev_alloc(h, &ps.d_pair_sub, (size_t)ps.pairs));
-    RDD_HIP(hipMemcpyAsync(ps.d_row_off, ps.row_off.data(), sizeof(int64_t) * (g.J + 1),
-                           hipMemcpyHostToDevice, h.stream));
+    RDD_TRY(upload(h, ps.d_row_off, ps.row_off.data(), sizeof(int64_t) * (g.J + 1)));
     hipLaunchKernelGGL((k_bin<true>), dim3(g.J), dim3(256), 0, h.stream, g, h.d_mu, X, n, nullptr,
                        ps.d_row_off, ps.d_rows, ps.d_pair_sub);
     RDD_HIP(hipGetLastError());
@@ -372,8 +370,7 @@ int bin_points(Handle& h, const double* X, int64_t n, PointSet& ps) {
     RDD_HIP(hipGetLastError());
     RDD_TRY(exclusive_scan_i64(h, d_cc, ps.d_cover_off, n));
     int64_t total = 0;
-    RDD_HIP(hipMemcpyAsync(&total, ps.d_cover_off + n, sizeof(int64_t), hipMemcpyDeviceToHost,
-                           h.stream));
+    RDD_TRY(download(h, &total, ps.d_cover_off + n, sizeof(int64_t)));
     // uncovered points: detected through the per-point count
     std::vector<int64_t> cc_host;
     RDD_HIP(hipStreamSynchronize(h.stream));
@@ -384,7 +381,7 @@ int bin_points(Handle& h, const double* X, int64_t n, PointSet& ps) {
     {
         // minimum cover must be >= 1: read the counts back (integers, cheap)
         cc_host.resize(n);
-        RDD_HIP(hipMemcpy(cc_host.data(), d_cc, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
+        RDD_TRY(download(h, cc_host.data(), d_cc, sizeof(int64_t) * n));
         int64_t mx = 0;
         for (int64_t i = 0; i < n; ++i) {
             if (cc_host[i] == 0) {

@@ -723,8 +723,8 @@ int true_residual(Handle& h, const double* Fs, const double* W, int k, double* o
     RDD_TRY(dot(h, h.P, k, r, r, dp, o1));
     RDD_TRY(dot(h, h.P, k, g, g, dp, o2));
     std::vector<double> a(k), b(k);
-    RDD_HIP(hipMemcpyAsync(a.data(), o1, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
-    RDD_HIP(hipMemcpyAsync(b.data(), o2, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_TRY(download(h, a.data(), o1, sizeof(double) * k));
+    RDD_TRY(download(h, b.data(), o2, sizeof(double) * k));
     RDD_HIP(hipStreamSynchronize(h.stream));
     for (int t = 0; t < k; ++t) {
         out_host[t] = std::sqrt(a[t]);
@@ -787,11 +787,11 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     }
     std::vector<double> bn2h(k), tmp(k);
     std::vector<int32_t> act(k, 1), ith(k, 0);
-    RDD_HIP(hipMemcpyAsync(bn2h.data(), bn2, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_TRY(download(h, bn2h.data(), bn2, sizeof(double) * k));
     RDD_HIP(hipStreamSynchronize(h.stream));
     for (int t = 0; t < k; ++t)
         if (!(bn2h[t] > 0.0)) bn2h[t] = 1.0;  // zero right-hand side: solution 0
-    RDD_HIP(hipMemcpyAsync(bn2, bn2h.data(), sizeof(double) * k, hipMemcpyHostToDevice, h.stream));
+    RDD_TRY(upload(h, bn2, bn2h.data(), sizeof(double) * k));
 
     auto restart = [&]() -> int {
         RDD_TRY(launch_precond(h, r, k, z, ub));
@@ -799,9 +799,9 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
         RDD_TRY(dot(h, P, k, r, z, dp, rhoB + (size_t)par * k));
         return RANN_OK;
     };
-    RDD_HIP(hipMemcpyAsync(active, act.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, h.stream));
+    RDD_TRY(upload(h, active, act.data(), sizeof(int32_t) * k));
     std::vector<double> tol2h(k, o.tol * o.tol);
-    RDD_HIP(hipMemcpyAsync(tol2v, tol2h.data(), sizeof(double) * k, hipMemcpyHostToDevice, h.stream));
+    RDD_TRY(upload(h, tol2v, tol2h.data(), sizeof(double) * k));
     RDD_TRY(restart());
     int it = 0;
     const int every = std::max(1, o.check_every);
@@ -834,8 +834,8 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
         }
         RDD_HIP(hipGetLastError());
         int32_t fl[4];
-        RDD_HIP(hipMemcpyAsync(act.data(), active, sizeof(int32_t) * k, hipMemcpyDeviceToHost, h.stream));
-        RDD_HIP(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, h.stream));
+        RDD_TRY(download(h, act.data(), active, sizeof(int32_t) * k));
+        RDD_TRY(download(h, fl, flags, sizeof(fl)));
         RDD_HIP(hipStreamSynchronize(h.stream));
         if (fl[1]) {
             set_error("NaN or Inf in the Krylov iteration");
@@ -855,7 +855,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
             // recurrence has drifted far from it
             RDD_TRY(true_residual(h, Fs, W, k, tres.data(), tmp.data()));
             std::vector<double> rrh(k);
-            RDD_HIP(hipMemcpy(rrh.data(), rres, sizeof(double) * k, hipMemcpyDeviceToHost));
+            RDD_TRY(download(h, rrh.data(), rres, sizeof(double) * k));
             bool again = false, drift = false;
             for (int t = 0; t < k; ++t) {
                 double relr = tmp[t] > 0 ? tres[t] / tmp[t] : 0.0;
@@ -881,9 +881,8 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
                 if (again) *status = RANN_ENOTCONV;
                 break;
             }
-            RDD_HIP(hipMemcpyAsync(tol2v, tol2h.data(), sizeof(double) * k, hipMemcpyHostToDevice, h.stream));
-            RDD_HIP(hipMemcpyAsync(active, act.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice,
-                                   h.stream));
+            RDD_TRY(upload(h, tol2v, tol2h.data(), sizeof(double) * k));
+            RDD_TRY(upload(h, active, act.data(), sizeof(int32_t) * k));
             if (drift) {
                 ++replacements;
                 RDD_TRY(launch_Hx(h, W, k, y, false));
@@ -899,9 +898,9 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
             break;
         }
     }
-    RDD_HIP(hipMemcpyAsync(ith.data(), iters, sizeof(int32_t) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_TRY(download(h, ith.data(), iters, sizeof(int32_t) * k));
     std::vector<double> rrh(k);
-    RDD_HIP(hipMemcpyAsync(rrh.data(), rres, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_TRY(download(h, rrh.data(), rres, sizeof(double) * k));
     RDD_HIP(hipStreamSynchronize(h.stream));
     iters_out.assign(ith.begin(), ith.end());
     res_out = rrh;
@@ -1007,10 +1006,10 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
     RDD_TRY(launch_precond(h, rhs, k, w, ub));
     RDD_TRY(dot(h, P, k, w, w, dp, nrm));
     std::vector<double> mb(k);
-    RDD_HIP(hipMemcpyAsync(mb.data(), nrm, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_TRY(download(h, mb.data(), nrm, sizeof(double) * k));
     RDD_HIP(hipStreamSynchronize(h.stream));
     for (int t = 0; t < k; ++t) mb[t] = mb[t] > 0 ? std::sqrt(mb[t]) : 1.0;
-    RDD_HIP(hipMemcpyAsync(mbn, mb.data(), sizeof(double) * k, hipMemcpyHostToDevice, h.stream));
+    RDD_TRY(upload(h, mbn, mb.data(), sizeof(double) * k));
     double tol_p = o.tol;
     int it = 0, cycles = 0;
     std::vector<int32_t> act(k, 1);
@@ -1026,14 +1025,14 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
                            w, V);
         hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(256), 0, h.stream, k, nrm, g, m, nused);
         // active: those whose preconditioned residual is above tol_p
-        RDD_HIP(hipMemcpyAsync(rh.data(), nrm, sizeof(double) * k, hipMemcpyDeviceToHost, h.stream));
+        RDD_TRY(download(h, rh.data(), nrm, sizeof(double) * k));
         RDD_HIP(hipStreamSynchronize(h.stream));
         bool any = false;
         for (int t = 0; t < k; ++t) {
             act[t] = (std::sqrt(rh[t]) > tol_p * mb[t]) ? 1 : 0;
             any |= act[t] != 0;
         }
-        RDD_HIP(hipMemcpyAsync(active, act.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, h.stream));
+        RDD_TRY(upload(h, active, act.data(), sizeof(int32_t) * k));
         int jn = 0;
         if (any) {
             for (int j = 0; j < m && it < o.maxiter; ++j, ++it) {
@@ -1064,8 +1063,7 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
                                    active);
                 jn = j + 1;
                 if ((j + 1) % std::max(1, o.check_every) == 0) {
-                    RDD_HIP(hipMemcpyAsync(act.data(), active, sizeof(int32_t) * k, hipMemcpyDeviceToHost,
-                                           h.stream));
+                    RDD_TRY(download(h, act.data(), active, sizeof(int32_t) * k));
                     RDD_HIP(hipStreamSynchronize(h.stream));
                     bool a2 = false;
                     for (int t = 0; t < k; ++t) a2 |= act[t] != 0;
@@ -1094,7 +1092,7 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
         }
     }
     std::vector<int32_t> ith(k);
-    RDD_HIP(hipMemcpyAsync(ith.data(), iters, sizeof(int32_t) * k, hipMemcpyDeviceToHost, h.stream));
+    RDD_TRY(download(h, ith.data(), iters, sizeof(int32_t) * k));
     RDD_HIP(hipStreamSynchronize(h.stream));
     iters_out.assign(ith.begin(), ith.end());
     return RANN_OK;

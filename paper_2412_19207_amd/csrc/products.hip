@@ -164,13 +164,10 @@ int plan_products(Handle& h) {
     RDD_TRY(dev_alloc(h, &h.d_chunk_off, h.chunk_off.size()));
     RDD_TRY(dev_alloc(h, &h.d_part_off, part_off.size()));
     if (!chunk_sub.empty()) {
-        RDD_HIP(hipMemcpy(h.d_chunk_sub, chunk_sub.data(), sizeof(int32_t) * chunk_sub.size(),
-                          hipMemcpyHostToDevice));
-        RDD_HIP(hipMemcpy(h.d_part_off, part_off.data(), sizeof(int64_t) * part_off.size(),
-                          hipMemcpyHostToDevice));
+        RDD_TRY(upload(h, h.d_chunk_sub, chunk_sub.data(), sizeof(int32_t) * chunk_sub.size()));
+        RDD_TRY(upload(h, h.d_part_off, part_off.data(), sizeof(int64_t) * part_off.size()));
     }
-    RDD_HIP(hipMemcpy(h.d_chunk_off, h.chunk_off.data(), sizeof(int64_t) * h.chunk_off.size(),
-                      hipMemcpyHostToDevice));
+    RDD_TRY(upload(h, h.d_chunk_off, h.chunk_off.data(), sizeof(int64_t) * h.chunk_off.size()));
     std::vector<int32_t> col_sub(h.P), feat_sub(h.sum_m);
     for (int j = 0; j < J; ++j) {
         for (int64_t c = h.col_off[j]; c < h.col_off[j + 1]; ++c) col_sub[c] = j;
@@ -179,10 +176,8 @@ int plan_products(Handle& h) {
     RDD_TRY(dev_alloc(h, &h.d_col_sub, col_sub.size()));
     RDD_TRY(dev_alloc(h, &h.d_feat_sub, feat_sub.size()));
     if (!col_sub.empty())
-        RDD_HIP(hipMemcpy(h.d_col_sub, col_sub.data(), sizeof(int32_t) * col_sub.size(),
-                          hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h.d_feat_sub, feat_sub.data(), sizeof(int32_t) * feat_sub.size(),
-                      hipMemcpyHostToDevice));
+        RDD_TRY(upload(h, h.d_col_sub, col_sub.data(), sizeof(int32_t) * col_sub.size()));
+    RDD_TRY(upload(h, h.d_feat_sub, feat_sub.data(), sizeof(int32_t) * feat_sub.size()));
     // per-column partial metadata for the fused reductions
     std::vector<int64_t> pbase(h.P);
     std::vector<int32_t> pstride(h.P), nch(h.P);
@@ -200,9 +195,9 @@ int plan_products(Handle& h) {
     RDD_TRY(dev_alloc(h, &h.d_col_pstride, pstride.size()));
     RDD_TRY(dev_alloc(h, &h.d_col_nch, nch.size()));
     if (h.P > 0) {
-        RDD_HIP(hipMemcpy(h.d_col_pbase, pbase.data(), sizeof(int64_t) * h.P, hipMemcpyHostToDevice));
-        RDD_HIP(hipMemcpy(h.d_col_pstride, pstride.data(), sizeof(int32_t) * h.P, hipMemcpyHostToDevice));
-        RDD_HIP(hipMemcpy(h.d_col_nch, nch.data(), sizeof(int32_t) * h.P, hipMemcpyHostToDevice));
+        RDD_TRY(upload(h, h.d_col_pbase, pbase.data(), sizeof(int64_t) * h.P));
+        RDD_TRY(upload(h, h.d_col_pstride, pstride.data(), sizeof(int32_t) * h.P));
+        RDD_TRY(upload(h, h.d_col_nch, nch.data(), sizeof(int32_t) * h.P));
     }
     return RANN_OK;
 }

@@ -219,8 +219,7 @@ int build_schwarz(Handle& h) {
     std::vector<std::vector<double>> cen(J, std::vector<double>(h.geo.d));
     {
         std::vector<double> mu_all(h.geo.mu_off[h.geo.d - 1] + h.geo.l[h.geo.d - 1]);
-        RDD_HIP(hipMemcpy(mu_all.data(), h.d_mu, sizeof(double) * mu_all.size(),
-                          hipMemcpyDeviceToHost));
+        RDD_TRY(download(h, mu_all.data(), h.d_mu, sizeof(double) * mu_all.size()));
         for (int j = 0; j < J; ++j) {
             int t = j;
             for (int i = 0; i < h.geo.d; ++i) {
@@ -300,17 +299,14 @@ int build_schwarz(Handle& h) {
     RDD_TRY(dev_alloc(h, &h.d_gat_off, gat_off.size()));
     RDD_TRY(dev_alloc(h, &h.d_gat, gat.size()));
     RDD_TRY(dev_alloc(h, &h.d_gat_w, gat_w.size()));
-    RDD_HIP(hipMemcpy(h.d_f_off, h.f_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h.d_q, h.q.data(), sizeof(int64_t) * J, hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h.d_ub_off, ub_off.data(), sizeof(int64_t) * (J + 1), hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h.d_blk_cols, blk_cols.data(), sizeof(int32_t) * blk_cols.size(),
-                      hipMemcpyHostToDevice));
-    RDD_HIP(hipMemcpy(h.d_gat_off, gat_off.data(), sizeof(int64_t) * gat_off.size(),
-                      hipMemcpyHostToDevice));
+    RDD_TRY(upload(h, h.d_f_off, h.f_off.data(), sizeof(int64_t) * (J + 1)));
+    RDD_TRY(upload(h, h.d_q, h.q.data(), sizeof(int64_t) * J));
+    RDD_TRY(upload(h, h.d_ub_off, ub_off.data(), sizeof(int64_t) * (J + 1)));
+    RDD_TRY(upload(h, h.d_blk_cols, blk_cols.data(), sizeof(int32_t) * blk_cols.size()));
+    RDD_TRY(upload(h, h.d_gat_off, gat_off.data(), sizeof(int64_t) * gat_off.size()));
     if (!gat.empty()) {
-        RDD_HIP(hipMemcpy(h.d_gat, gat.data(), sizeof(int64_t) * gat.size(), hipMemcpyHostToDevice));
-        RDD_HIP(hipMemcpy(h.d_gat_w, gat_w.data(), sizeof(double) * gat_w.size(),
-                          hipMemcpyHostToDevice));
+        RDD_TRY(upload(h, h.d_gat, gat.data(), sizeof(int64_t) * gat.size()));
+        RDD_TRY(upload(h, h.d_gat_w, gat_w.data(), sizeof(double) * gat_w.size()));
     }
     h.ub_total = ub_off[J];
 
@@ -339,9 +335,9 @@ int build_schwarz(Handle& h) {
     RDD_TRY(dev_alloc(h, &h.d_row_tasks, rtv.size()));
     RDD_TRY(dev_alloc(h, &h.d_col_tasks, ctv.size()));
     if (!rtv.empty())
-        RDD_HIP(hipMemcpy(h.d_row_tasks, rtv.data(), sizeof(int2) * rtv.size(), hipMemcpyHostToDevice));
+        RDD_TRY(upload(h, h.d_row_tasks, rtv.data(), sizeof(int2) * rtv.size()));
     if (!ctv.empty())
-        RDD_HIP(hipMemcpy(h.d_col_tasks, ctv.data(), sizeof(int2) * ctv.size(), hipMemcpyHostToDevice));
+        RDD_TRY(upload(h, h.d_col_tasks, ctv.data(), sizeof(int2) * ctv.size()));
 
     // local Gram blocks (FP64) and their factorisation
     double *d_A = nullptr, *d_W = nullptr;
