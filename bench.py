@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # dense FP64 (matrix cores and vector ALUs)
 FP32_PEAK_TFLOPS = 157.3
-KERNELS = ["k_eig", "k_factor", "k_pca_gram", "k_feat_rows", "k_local_gram", "k_Hx",
+KERNELS = ["k_eig", "k_factor", "k_pca_gram", "k_feat_rows", "k_local_gram", "k_normal", "k_Hx",
            "k_HTy_part", "k_local_apply"]
 
 
@@ -83,6 +83,8 @@ def work_model(s, prob, k):
         "k_feat_rows": ("mfma", float(np.sum(2.0 * n * m * p)), "flop", FP64_PEAK_TFLOPS),
         # Gram blocks H_j^T H_k: counted for the diagonal blocks only (a lower bound)
         "k_local_gram": ("mfma", float(np.sum(2.0 * n * p * p)), "flop", FP64_PEAK_TFLOPS),
+        # slabs of the normal matrix read once, x read, s written
+        "k_normal": ("hbm", 8.0 * (float(s.info.normal_elems) + 2.0 * P * k), "byte", HBM_PEAK_GBS),
         # H read once, x read, y written
         "k_Hx": ("hbm", 8.0 * (nnz + P * k + N * k), "byte", HBM_PEAK_GBS),
         "k_HTy_part": ("hbm", 8.0 * (nnz + N * k + P * k), "byte", HBM_PEAK_GBS),

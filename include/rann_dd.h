@@ -132,6 +132,7 @@ typedef struct rann_dd_info {
     int64_t factor_elems;     /* stored entries of the local inverse operators */
     int32_t max_q;            /* largest Schwarz block */
     int32_t pca_done;
+    int64_t normal_elems;     /* stored entries of the assembled normal matrix H^T H */
 } rann_dd_info;
 
 /* Steps 1-3 of Algorithm 1 (paper Sec. 4): bin the points into the subdomain
@@ -211,7 +212,7 @@ RANN_API int rann_dd_get_blocks(const rann_dd_handle* h, int64_t* q);
 /* Kernel timing for measurement (process-wide, off by default).  When enabled,
  * the main kernels are bracketed by HIP events on the stream they run on;
  * rann_dd_ktime_enable(on) also clears the accumulated times.  Query by kernel
- * name ("k_eig", "k_factor", "k_pca_gram", "k_feat_rows",
+ * name ("k_eig", "k_factor", "k_pca_gram", "k_feat_rows", "k_normal",
  * "k_local_gram", "k_Hx", "k_HTy_part", "k_local_apply"): total milliseconds
  * and number of launches since the last enable.  Query synchronises on the
  * recorded events. */

@@ -57,7 +57,7 @@ class Info(ctypes.Structure):
                 ("N_bnd", ctypes.c_int64), ("N", ctypes.c_int64), ("P", ctypes.c_int64),
                 ("pairs", ctypes.c_int64), ("nnz", ctypes.c_int64), ("sum_m", ctypes.c_int64),
                 ("factor_elems", ctypes.c_int64), ("max_q", ctypes.c_int32),
-                ("pca_done", ctypes.c_int32)]
+                ("pca_done", ctypes.c_int32), ("normal_elems", ctypes.c_int64)]
 
 
 _SIGS = {

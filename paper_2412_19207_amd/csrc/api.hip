@@ -552,7 +552,12 @@ static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, con
     RDD_TRY(dev_alloc(h, &h.d_H, (size_t)h.nnz));
     RDD_TRY(feature_rows(h));
     RDD_TRY(plan_products(h));
-    RDD_TRY(build_schwarz(h));
+    RDD_TRY(normal_blocks(h));
+    {
+        const int rc_s = build_schwarz(h);
+        release_gram(h);
+        RDD_TRY(rc_s);
+    }
     if (p_out) std::copy(h.p.begin(), h.p.end(), p_out);
     h.pca_done = true;
     return warn;
@@ -783,6 +788,7 @@ int rann_dd_get_info(const rann_dd_handle* hh, rann_dd_info* out) {
     out->factor_elems = h.tile_elems;
     out->max_q = h.max_q;
     out->pca_done = h.pca_done ? 1 : 0;
+    out->normal_elems = h.N_elems;
     return RANN_OK;
 }
 

@@ -102,6 +102,21 @@ struct Handle {
     int32_t shifts = 0;
     int64_t ub_total = 0;          // sum q_i
 
+    // normal matrix N = H^T H: block row j as a dense p_j x Q_j slab over the
+    // columns of the subdomains meeting j (N_cols); Gram blocks of meeting
+    // pairs kept during set-up only
+    std::vector<int64_t> N_off, N_coff;  // J+1: slab elements / column-list offsets
+    int64_t N_elems = 0;
+    double* d_N = nullptr;
+    int64_t* d_N_off = nullptr;
+    int64_t* d_N_coff = nullptr;
+    int32_t* d_N_cols = nullptr;
+    int2* d_slab_tasks = nullptr;   // (subdomain, first row) per product workgroup
+    int64_t n_slab_tasks = 0;
+    std::vector<std::vector<std::pair<int, int>>> pair_tab;  // j -> (k >= j, pair id)
+    double* d_G = nullptr;
+    void* d_pair_blocks = nullptr;
+
     // products with H: row chunks of each block, partial sums per chunk
     std::vector<int64_t> chunk_off; // J+1 (chunks per subdomain)
     int64_t n_chunks = 0, part_total = 0;
@@ -224,6 +239,12 @@ int build_schwarz(Handle& h);
 template <class T>
 int local_blocks(Handle& h, const T* H, T* A_out);
 int plan_products(Handle& h);
+int normal_blocks(Handle& h);
+void release_gram(Handle& h);
+constexpr int kSlabRows = 16;       // slab rows per product workgroup
+// s = N x (N = H^T H from the slabs); with part != null also per-workgroup
+// partials of <x, s> at part[wg * k + t] (n_slab_tasks workgroups)
+int launch_normal(Handle& h, const double* x, int k, double* s, double* part);
 
 int launch_Hx(Handle& h, const double* x, int k, double* y, bool scale_bnd);
 int launch_HTy(Handle& h, const double* y, int k, double* x, double* partial);

@@ -309,6 +309,44 @@ __global__ void __launch_bounds__(256) k_assemble_A(int J, const int32_t* __rest
     }
 }
 
+// block row j of the normal matrix N = H^T H as a dense p_j x Q_j slab whose
+// columns are those of the subdomains meeting j (ascending): block (j, k) is
+// H_j^T H_k over the shared rows, read from the Gram block store
+__global__ void __launch_bounds__(256) k_assemble_slab(const int32_t* __restrict__ nbr_off,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const int32_t* __restrict__ nbr_pid,
+                                                       const int64_t* __restrict__ nbr_col,
+                                                       const PairBlock* __restrict__ blocks,
+                                                       const int32_t* __restrict__ p,
+                                                       const int64_t* __restrict__ N_off,
+                                                       const int64_t* __restrict__ N_coff,
+                                                       const double* __restrict__ Gs,
+                                                       double* __restrict__ N) {
+    const int j = blockIdx.x;
+    const int a = nbr_off[j] + blockIdx.y;
+    if (a >= nbr_off[j + 1]) return;
+    const int k = nbr[a];
+    const int pj = p[j], pk = p[k];
+    const int64_t Q = N_coff[j + 1] - N_coff[j];
+    const int64_t c0 = nbr_col[a];
+    const PairBlock B = blocks[nbr_pid[a]];
+    const double* G = Gs + B.g_off;
+    double* Nj = N + N_off[j];
+    for (int64_t e = threadIdx.x; e < (int64_t)pj * pk; e += blockDim.x) {
+        const int r = (int)(e / pk), c = (int)(e % pk);
+        double v;
+        if (j == k) {
+            const int hi = r > c ? r : c, lo = r > c ? c : r;
+            v = G[(int64_t)hi * pk + lo];
+        } else if (j < k) {
+            v = G[(int64_t)r * pk + c];
+        } else {
+            v = G[(int64_t)c * pj + r];
+        }
+        Nj[r * Q + c0 + c] = v;
+    }
+}
+
 }  // namespace
 
 int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g_off) {
@@ -355,12 +393,11 @@ int feature_rows(Handle& h) {
     return RANN_OK;
 }
 
-// Gram blocks of every stencil and the assembled A_i (device, q_i x q_i each)
-template <class T>
-int local_blocks(Handle& h, const T* H, T* A_out) {
+// Gram blocks H_j^T H_k of every pair of subdomains whose supports meet
+// (kept in the handle until release_gram) and the block rows of the normal
+// matrix N = H^T H as dense slabs (kept for the Krylov iterations).
+int normal_blocks(Handle& h) {
     const int J = h.geo.J;
-    // supports of j and k intersect (open boxes)
-    std::vector<double> mu_host;  // recomputed centres per subdomain
     auto centre = [&](int j, int i) {
         int c = j;
         for (int q = 0; q < i; ++q) c /= h.geo.l[q];
@@ -379,31 +416,22 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
             if (!(std::fabs(cen[j][i] - cen[k][i]) < 2.0 * h.geo.sigma[i])) return false;
         return true;
     };
-    // unique (j <= k) pairs needed by some stencil
+    // every meeting pair (j <= k), and the sorted neighbour list of each j
     std::vector<PairBlock> blocks;
-    std::vector<int> index(0);
-    std::vector<std::vector<int>> pid_of(J);  // sparse map j -> list of (k, pid)
-    auto find_pair = [&](int j, int k) -> int {
-        for (size_t t = 0; t < pid_of[j].size(); t += 2)
-            if (pid_of[j][t] == k) return pid_of[j][t + 1];
-        return -1;
-    };
-    for (int i = 0; i < J; ++i) {
-        const auto& s = h.sten[i];
-        for (size_t a = 0; a < s.size(); ++a)
-            for (size_t b = a; b < s.size(); ++b) {
-                int j = std::min(s[a], s[b]), k = std::max(s[a], s[b]);
-                if (!meet(j, k) || find_pair(j, k) >= 0) continue;
-                PairBlock B{j, k, j == k ? -1 : 0, 0, 0};
-                pid_of[j].push_back(k);
-                pid_of[j].push_back((int)blocks.size());
-                blocks.push_back(B);
-            }
-    }
+    h.pair_tab.assign(J, {});
+    std::vector<std::vector<int>> nbrs(J);
+    for (int j = 0; j < J; ++j)
+        for (int k = j; k < J; ++k) {
+            if (!meet(j, k)) continue;
+            h.pair_tab[j].push_back({k, (int)blocks.size()});
+            blocks.push_back(PairBlock{j, k, j == k ? -1 : 0, 0, 0});
+            nbrs[j].push_back(k);
+            if (k != j) nbrs[k].push_back(j);
+        }
+    for (auto& v : nbrs) std::sort(v.begin(), v.end());
     const int nb = (int)blocks.size();
     PairBlock* d_blocks = nullptr;
     RDD_TRY(dev_alloc(h, &d_blocks, nb));
-    // count shared rows
     for (auto& B : blocks) B.len = (B.isect < 0) ? (h.pts.row_off[B.j + 1] - h.pts.row_off[B.j]) : 0;
     RDD_TRY(upload(h, d_blocks, blocks.data(), sizeof(PairBlock) * nb));
     int64_t* d_cnt = nullptr;
@@ -413,7 +441,6 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
     RDD_HIP(hipGetLastError());
     std::vector<int64_t> cnt(nb);
     RDD_TRY(download(h, cnt.data(), d_cnt, sizeof(int64_t) * nb));
-    RDD_HIP(hipStreamSynchronize(h.stream));
     int64_t tot_isect = 0, tot_g = 0;
     for (int b = 0; b < nb; ++b) {
         auto& B = blocks[b];
@@ -432,8 +459,7 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
     hipLaunchKernelGGL((k_intersect<true>), dim3(nb), dim3(256), 0, h.stream, d_blocks,
                        h.pts.d_row_off, h.pts.d_rows, nullptr, d_lj, d_lk);
     RDD_HIP(hipGetLastError());
-    // Gram blocks
-    T* d_G = nullptr;
+    double* d_G = nullptr;
     RDD_TRY(dev_alloc(h, &d_G, (size_t)tot_g));
     std::vector<LocalTile> tiles;
     for (int b = 0; b < nb; ++b) {
@@ -446,12 +472,93 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
     RDD_TRY(upload(h, d_tiles, tiles.data(), sizeof(LocalTile) * tiles.size()));
     if (!tiles.empty()) {
         KTimer kt_(h.stream, "k_local_gram");
-        hipLaunchKernelGGL((k_local_gram<T>), dim3((unsigned)tiles.size()), dim3(256), 0, h.stream,
-                           d_tiles, d_blocks, d_lj, d_lk, h.d_p, h.d_h_off, H, d_G);
+        hipLaunchKernelGGL((k_local_gram<double>), dim3((unsigned)tiles.size()), dim3(256), 0, h.stream,
+                           d_tiles, d_blocks, d_lj, d_lk, h.d_p, h.d_h_off, h.d_H, d_G);
         kt_.stop();
         RDD_HIP(hipGetLastError());
     }
-    // stencil tables and assembly
+    // slabs of N: block row j, columns of nbrs[j] in ascending order
+    std::vector<int32_t> nbr_off(J + 1, 0), nbr_flat, nbr_pid;
+    std::vector<int64_t> nbr_col;
+    h.N_off.assign(J + 1, 0);
+    h.N_coff.assign(J + 1, 0);
+    std::vector<int32_t> N_cols;
+    int max_nbr = 0;
+    auto find_pair = [&](int j, int k) -> int {
+        for (auto& e : h.pair_tab[j])
+            if (e.first == k) return e.second;
+        return -1;
+    };
+    for (int j = 0; j < J; ++j) {
+        int64_t q = 0;
+        for (int k : nbrs[j]) {
+            nbr_flat.push_back(k);
+            nbr_pid.push_back(find_pair(std::min(j, k), std::max(j, k)));
+            nbr_col.push_back(q);
+            for (int c = 0; c < h.p[k]; ++c) N_cols.push_back((int32_t)(h.col_off[k] + c));
+            q += h.p[k];
+        }
+        nbr_off[j + 1] = (int32_t)nbr_flat.size();
+        max_nbr = std::max(max_nbr, (int)nbrs[j].size());
+        h.N_coff[j + 1] = h.N_coff[j] + q;
+        h.N_off[j + 1] = h.N_off[j] + (int64_t)h.p[j] * q;
+    }
+    h.N_elems = h.N_off[J];
+    int32_t *d_no = nullptr, *d_nf = nullptr, *d_np = nullptr;
+    int64_t* d_nc = nullptr;
+    RDD_TRY(dev_alloc(h, &d_no, nbr_off.size()));
+    RDD_TRY(dev_alloc(h, &d_nf, nbr_flat.size()));
+    RDD_TRY(dev_alloc(h, &d_np, nbr_pid.size()));
+    RDD_TRY(dev_alloc(h, &d_nc, nbr_col.size()));
+    RDD_TRY(dev_alloc(h, &h.d_N, (size_t)h.N_elems));
+    RDD_TRY(dev_alloc(h, &h.d_N_off, (size_t)J + 1));
+    RDD_TRY(dev_alloc(h, &h.d_N_coff, (size_t)J + 1));
+    RDD_TRY(dev_alloc(h, &h.d_N_cols, N_cols.size()));
+    RDD_TRY(upload(h, d_no, nbr_off.data(), sizeof(int32_t) * nbr_off.size()));
+    RDD_TRY(upload(h, d_nf, nbr_flat.data(), sizeof(int32_t) * nbr_flat.size()));
+    RDD_TRY(upload(h, d_np, nbr_pid.data(), sizeof(int32_t) * nbr_pid.size()));
+    RDD_TRY(upload(h, d_nc, nbr_col.data(), sizeof(int64_t) * nbr_col.size()));
+    RDD_TRY(upload(h, h.d_N_off, h.N_off.data(), sizeof(int64_t) * (J + 1)));
+    RDD_TRY(upload(h, h.d_N_coff, h.N_coff.data(), sizeof(int64_t) * (J + 1)));
+    RDD_TRY(upload(h, h.d_N_cols, N_cols.data(), sizeof(int32_t) * N_cols.size()));
+    if (max_nbr > 0)
+        hipLaunchKernelGGL(k_assemble_slab, dim3(J, max_nbr), dim3(256), 0, h.stream, d_no, d_nf, d_np,
+                           d_nc, d_blocks, h.d_p, h.d_N_off, h.d_N_coff, d_G, h.d_N);
+    RDD_HIP(hipGetLastError());
+    // slab row tasks of the product kernel
+    std::vector<int2> tasks;
+    for (int j = 0; j < J; ++j)
+        for (int r = 0; r < h.p[j]; r += kSlabRows) tasks.push_back(make_int2(j, r));
+    h.n_slab_tasks = (int64_t)tasks.size();
+    RDD_TRY(dev_alloc(h, &h.d_slab_tasks, tasks.size()));
+    RDD_TRY(upload(h, h.d_slab_tasks, tasks.data(), sizeof(int2) * tasks.size()));
+    RDD_HIP(hipStreamSynchronize(h.stream));
+    for (void* ptr : {(void*)d_cnt, (void*)d_lj, (void*)d_lk, (void*)d_tiles, (void*)d_no, (void*)d_nf,
+                      (void*)d_np, (void*)d_nc})
+        dev_free(h, ptr);
+    h.d_G = d_G;
+    h.d_pair_blocks = d_blocks;
+    return RANN_OK;
+}
+
+void release_gram(Handle& h) {
+    dev_free(h, h.d_G);
+    dev_free(h, h.d_pair_blocks);
+    h.d_G = nullptr;
+    h.d_pair_blocks = nullptr;
+    h.pair_tab.clear();
+}
+
+// The Schwarz blocks A_i (device, q_i x q_i each) from the Gram block store
+template <class T>
+int local_blocks(Handle& h, const T* H, T* A_out) {
+    (void)H;
+    const int J = h.geo.J;
+    auto find_pair = [&](int j, int k) -> int {
+        for (auto& e : h.pair_tab[j])
+            if (e.first == k) return e.second;
+        return -1;
+    };
     std::vector<int32_t> sten_off(J + 1, 0), sten_flat, pair_of;
     int max_ns = 0;
     for (int i = 0; i < J; ++i) {
@@ -480,12 +587,10 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
     RDD_TRY(upload(h, d_sf, sten_flat.data(), sizeof(int32_t) * sten_flat.size()));
     RDD_TRY(upload(h, d_po, pair_of.data(), sizeof(int32_t) * pair_of.size()));
     hipLaunchKernelGGL((k_assemble_A<T>), dim3(J, max_ns * 32), dim3(256), 0, h.stream, J, d_so, d_sf,
-                       d_po, d_blocks, h.d_p, h.d_f_off, d_G, A_out);
+                       d_po, static_cast<const PairBlock*>(h.d_pair_blocks), h.d_p, h.d_f_off, h.d_G, A_out);
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));
-    for (void* ptr : {(void*)d_blocks, (void*)d_cnt, (void*)d_lj, (void*)d_lk, (void*)d_G,
-                      (void*)d_tiles, (void*)d_so, (void*)d_sf, (void*)d_po})
-        dev_free(h, ptr);
+    for (void* ptr : {(void*)d_so, (void*)d_sf, (void*)d_po}) dev_free(h, ptr);
     return RANN_OK;
 }
 

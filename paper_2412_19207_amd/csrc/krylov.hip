@@ -457,13 +457,13 @@ __device__ void block_partial_by_rhs(double val, int k, double* sh, double* out)
     __syncthreads();
 }
 
-// res[t] = sum over the kRed partials (fixed-order tree), for t < k
-__device__ void sum_partials(const double* part, int k, double* res, double* sh) {
+// res[t] = sum over the nparts partials (fixed-order tree), for t < k
+__device__ void sum_partials(const double* part, int nparts, int k, double* res, double* sh) {
     const int per = 256 / k;
     const int t = threadIdx.x % k, ro = threadIdx.x / k;
     double acc = 0.0;
     if (ro < per)
-        for (int b = ro; b < kRed; b += per) acc += part[b * k + t];
+        for (int b = ro; b < nparts; b += per) acc += part[b * k + t];
     sh[threadIdx.x] = (ro < per) ? acc : 0.0;
     __syncthreads();
     for (int st = 1; st < per; st <<= 1) {
@@ -503,8 +503,8 @@ __global__ void __launch_bounds__(256) k_nrm_reduce_dot(int64_t P, int k, const 
     block_partial_by_rhs(acc, k, sh, partA);
 }
 
-// alpha = rho / <p, s>; x += alpha p; r -= alpha s; partials of <r, r>
-__global__ void __launch_bounds__(256) k_cg_xr2(int64_t P, int k, const double* __restrict__ partA,
+// alpha = rho / <p, s> (from nA partials); x += alpha p; r -= alpha s; partials of <r, r>
+__global__ void __launch_bounds__(256) k_cg_xr2(int64_t P, int k, int nA, const double* __restrict__ partA,
                                                 const double* __restrict__ rho_in,
                                                 const int32_t* __restrict__ active_in,
                                                 const double* __restrict__ p,
@@ -513,7 +513,7 @@ __global__ void __launch_bounds__(256) k_cg_xr2(int64_t P, int k, const double* 
                                                 int32_t* __restrict__ flags) {
     __shared__ double sh[256];
     __shared__ double al[256];
-    sum_partials(partA, k, al, sh);
+    sum_partials(partA, nA, k, al, sh);
     if (threadIdx.x < k) {
         const int t = threadIdx.x;
         double a = 0.0;
@@ -590,8 +590,8 @@ __global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, const double* _
     __shared__ double sh[256];
     __shared__ double rr[256];
     __shared__ double rz[256];
-    sum_partials(partB, k, rr, sh);
-    sum_partials(partC, k, rz, sh);
+    sum_partials(partB, kRed, k, rr, sh);
+    sum_partials(partC, kRed, k, rz, sh);
     if (threadIdx.x < k) {
         const int t = threadIdx.x;
         const int act = active_in[t];
@@ -674,7 +674,17 @@ int dot(Handle& h, int64_t rows, int k, const double* a, const double* b, double
     return RANN_OK;
 }
 
+// s = H^T H x through the assembled normal matrix
 int normal_op(Handle& h, const double* x, int k, double* y, double* part, double* s) {
+    (void)y;
+    (void)part;
+    return launch_normal(h, x, k, s, nullptr);
+}
+
+// s = H^T (H x) from the rows of H (y: N k, part: part_total k scratch); the
+// residuals that decide convergence use this form, so the assembled normal
+// matrix only drives the corrections (iterative refinement)
+int exact_normal_op(Handle& h, const double* x, int k, double* y, double* part, double* s) {
     RDD_TRY(launch_Hx(h, x, k, y, false));
     RDD_TRY(launch_HTy(h, y, k, s, part));
     return RANN_OK;
@@ -740,7 +750,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
                    std::vector<double>& res_out, int* status) {
     const size_t P = (size_t)h.P, N = (size_t)h.N;
     const size_t need = P * k * 4 + N * k + (size_t)h.part_total * k + (size_t)h.ub_total * k * 2 +
-                        (size_t)kDotBlocks * k + 3 * (size_t)kRed * k + 24 * (size_t)k + 2048;
+                        (size_t)kDotBlocks * k + 3 * (size_t)kRed * k + (size_t)h.n_slab_tasks * k + 24 * (size_t)k + 2048;
     RDD_TRY(ensure_ws(h, need * sizeof(double)));
     Scratch sc{static_cast<double*>(h.ws), 0};
     double* r = sc.take(P * k);
@@ -761,7 +771,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     double* rres = sc.take(k);
     double* tol2v = sc.take(k);
     double* rhoB = sc.take(2 * (size_t)k);       // rho, double-buffered
-    double* partA = sc.take((size_t)kRed * k);
+    double* partA = sc.take((size_t)std::max<int64_t>(kRed, h.n_slab_tasks) * k);
     double* partB = sc.take((size_t)kRed * k);
     double* partC = sc.take((size_t)kRed * k);
     int32_t* activeB = reinterpret_cast<int32_t*>(sc.take(2 * (size_t)k));  // activity, double-buffered
@@ -815,13 +825,10 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
             double* rho_out = rhoB + (size_t)(par ^ 1) * k;
             int32_t* act_in = activeB + (size_t)par * k;
             int32_t* act_out = activeB + (size_t)(par ^ 1) * k;
-            // s = H^T H p and <p, s>
-            RDD_TRY(launch_Hx(h, p, k, y, false));
-            RDD_TRY(launch_HTy_part(h, y, k, part));
-            hipLaunchKernelGGL(k_nrm_reduce_dot, dim3(kRed), dim3(256), 0, h.stream, (int64_t)P, k,
-                               h.d_col_pbase, h.d_col_pstride, h.d_col_nch, part, p, s, partA);
-            hipLaunchKernelGGL(k_cg_xr2, dim3(kRed), dim3(256), 0, h.stream, (int64_t)P, k, partA, rho_in,
-                               act_in, p, s, W, r, partB, flags);
+            // s = H^T H p (assembled normal matrix) and partials of <p, s>
+            RDD_TRY(launch_normal(h, p, k, s, partA));
+            hipLaunchKernelGGL(k_cg_xr2, dim3(kRed), dim3(256), 0, h.stream, (int64_t)P, k,
+                               (int)h.n_slab_tasks, partA, rho_in, act_in, p, s, W, r, partB, flags);
             // z = M^{-1} r and <r, z>
             const int ident = (h.precond == RANN_PRECOND_NONE) ? 1 : 0;
             if (!ident) RDD_TRY(launch_precond_local(h, r, k, ub));
@@ -1016,8 +1023,8 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
     std::vector<double> tres(k), bn(k), rh(k);
     *status = RANN_OK;
     while (true) {
-        // r = M^{-1}(rhs - A W)
-        RDD_TRY(normal_op(h, W, k, y, part, s));
+        // r = M^{-1}(rhs - A W), A applied through the rows of H
+        RDD_TRY(exact_normal_op(h, W, k, y, part, s));
         hipLaunchKernelGGL(k_sub, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, s, t0);
         RDD_TRY(launch_precond(h, t0, k, w, ub));
         RDD_TRY(dot(h, P, k, w, w, dp, nrm));

@@ -139,6 +139,88 @@ __global__ void __launch_bounds__(256) k_HTy_chunk(const int32_t* __restrict__ c
     }
 }
 
+
+// s = N x from the slabs of N = H^T H: workgroup = kSlabRows rows of block row
+// j, each wave kSlabRows / 4 rows (loaded together), x gathered through the
+// slab's column list and staged in LDS; optional per-workgroup <x, s>.
+template <int KB>
+__global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks,
+                                                  const int32_t* __restrict__ p,
+                                                  const int64_t* __restrict__ col_off,
+                                                  const int64_t* __restrict__ N_off,
+                                                  const int64_t* __restrict__ N_coff,
+                                                  const int32_t* __restrict__ N_cols,
+                                                  const double* __restrict__ N,
+                                                  const double* __restrict__ x, int k, int k0,
+                                                  double* __restrict__ s, double* __restrict__ part) {
+    constexpr int kXS = 4096 / KB;      // staged columns per pass
+    constexpr int kRW = kSlabRows / 4;  // rows per wave
+    __shared__ double xs[kXS][KB];
+    __shared__ double red[4][KB];
+    const int2 tk = tasks[blockIdx.x];
+    const int j = tk.x, r0 = tk.y;
+    const int pj = p[j];
+    const int64_t Q = N_coff[j + 1] - N_coff[j];
+    const int32_t* cols = N_cols + N_coff[j];
+    const double* Nj = N + N_off[j];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double acc[kRW][KB];
+#pragma unroll
+    for (int u = 0; u < kRW; ++u)
+#pragma unroll
+        for (int t = 0; t < KB; ++t) acc[u][t] = 0.0;
+    int nrow = 0;  // rows of this wave that exist
+#pragma unroll
+    for (int u = 0; u < kRW; ++u)
+        if (r0 + wave + 4 * u < pj) nrow = u + 1;
+    for (int64_t c0 = 0; c0 < Q; c0 += kXS) {
+        const int nc = (Q - c0 < kXS) ? (int)(Q - c0) : kXS;
+        __syncthreads();
+        for (int e = threadIdx.x; e < nc * KB; e += 256) {
+            const int c = e / KB, t = e % KB;
+            xs[c][t] = x[(int64_t)cols[c0 + c] * k + k0 + t];
+        }
+        __syncthreads();
+        const double* Nr = Nj + (int64_t)(r0 + wave) * Q + c0;
+        for (int c = lane; c < nc; c += 64) {
+            double nv[kRW];
+#pragma unroll
+            for (int u = 0; u < kRW; ++u) nv[u] = (u < nrow) ? Nr[(int64_t)4 * u * Q + c] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kRW; ++u)
+#pragma unroll
+                for (int t = 0; t < KB; ++t) acc[u][t] = fma(nv[u], xs[c][t], acc[u][t]);
+        }
+    }
+    double dotv[KB];
+#pragma unroll
+    for (int t = 0; t < KB; ++t) dotv[t] = 0.0;
+#pragma unroll
+    for (int u = 0; u < kRW; ++u) {
+#pragma unroll
+        for (int t = 0; t < KB; ++t)
+            for (int off = 32; off > 0; off >>= 1) acc[u][t] += __shfl_xor(acc[u][t], off);
+        if (lane == 0 && u < nrow) {
+            const int64_t g = (col_off[j] + r0 + wave + 4 * u) * k + k0;
+#pragma unroll
+            for (int t = 0; t < KB; ++t) {
+                s[g + t] = acc[u][t];
+                dotv[t] = fma(acc[u][t], x[g + t], dotv[t]);
+            }
+        }
+    }
+    if (part) {
+        if (lane == 0)
+#pragma unroll
+            for (int t = 0; t < KB; ++t) red[wave][t] = dotv[t];
+        __syncthreads();
+        if (threadIdx.x < KB) {
+            const int t = threadIdx.x;
+            part[(int64_t)blockIdx.x * k + k0 + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+        }
+    }
+}
+
 }  // namespace
 
 // chunk tables
@@ -250,6 +332,35 @@ int launch_HTy_part(Handle& h, const double* y, int k, double* part) {
             default: RDD_HTC(1); break;
         }
 #undef RDD_HTC
+        k0 += kb;
+    }
+    kt_.stop();
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
+}  // namespace rdd
+
+namespace rdd {
+
+int launch_normal(Handle& h, const double* x, int k, double* s, double* part) {
+    KTimer kt_(h.stream, "k_normal");
+    for (int k0 = 0; k0 < k;) {
+        const int rem = k - k0;
+        const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+#define RDD_NS(KBV)                                                                                 \
+    hipLaunchKernelGGL((k_nrm_slab<KBV>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,   \
+                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff, h.d_N_cols, h.d_N, \
+                       x, k, k0, s, part)
+        if (h.n_slab_tasks) {
+            switch (kb) {
+                case 8: RDD_NS(8); break;
+                case 4: RDD_NS(4); break;
+                case 2: RDD_NS(2); break;
+                default: RDD_NS(1); break;
+            }
+        }
+#undef RDD_NS
         k0 += kb;
     }
     kt_.stop();
