@@ -73,6 +73,8 @@ def work_model(s, prob, k):
     q = s.blocks().astype(np.float64)
     nnz, N, P = float(s.info.nnz), float(s.info.N), float(s.info.P)
     f_bytes = 4.0 if s.precision == "mixed" else 8.0
+    ntile = np.ceil(q / 64.0)
+    slots = float(np.sum(ntile * (ntile + 1) / 2.0 * 64.0))
     return {
         # nominal count of a dense symmetric eigendecomposition with vectors
         "k_eig": ("alu", float(np.sum(9.0 * m ** 3)), "flop", FP64_PEAK_TFLOPS),
@@ -88,10 +90,11 @@ def work_model(s, prob, k):
         # H read once, x read, y written
         "k_Hx": ("hbm", 8.0 * (nnz + P * k + N * k), "byte", HBM_PEAK_GBS),
         "k_HTy_part": ("hbm", 8.0 * (nnz + N * k + P * k), "byte", HBM_PEAK_GBS),
-        # triangular factors Y_i (q_i (q_i + 1) / 2 entries) read by both passes;
-        # gathered r, the intermediate u (written and read) and the result
-        "k_local_apply": ("hbm", 2.0 * f_bytes * float(np.sum(q * (q + 1) / 2.0))
-                          + 32.0 * float(np.sum(q)) * k, "byte", HBM_PEAK_GBS),
+        # the stored local operators (q_i (q_i + 1) / 2 entries each: W_i in FP64,
+        # the factor Y_i in FP32) read once; gathered r, the column-sum slots
+        # (written and read) and the local results
+        "k_local_apply": ("hbm", f_bytes * float(np.sum(q * (q + 1) / 2.0))
+                          + 8.0 * (2.0 * float(np.sum(q)) + 2.0 * slots) * k, "byte", HBM_PEAK_GBS),
     }
 
 

@@ -765,7 +765,7 @@ int rann_dd_apply_precond(rann_dd_handle* hh, const double* r, int32_t k, double
     Handle& h = hh->h;
     if (!r || !z || k < 1) return (rdd::set_error("invalid apply_precond arguments"), RANN_EINVAL);
     double* ub = nullptr;
-    RDD_TRY(rdd::dev_alloc(h, &ub, (size_t)std::max<int64_t>(h.ub_total, 1) * k * 2));
+    RDD_TRY(rdd::dev_alloc(h, &ub, (size_t)std::max<int64_t>(2 * h.ub_total + 2 * h.slot_total, 1) * k));
     int rc = rdd::launch_precond(h, r, k, z, ub);
     if (rc == RANN_OK && hipStreamSynchronize(h.stream) != hipSuccess) rc = RANN_EDEVICE;
     rdd::dev_free(h, ub);

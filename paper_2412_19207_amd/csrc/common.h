@@ -88,9 +88,13 @@ struct Handle {
     int64_t* d_t_off = nullptr;
     double* d_M64 = nullptr;       // Y_i = L_i^{-1} D_i, packed tiles, FP64
     float* d_M32 = nullptr;        // the same in FP32 (mixed)
-    int2* d_row_tasks = nullptr;   // (block, tile row) of the row pass
-    int2* d_col_tasks = nullptr;   // (block, tile column) of the column pass
-    int64_t n_row_tasks = 0, n_col_tasks = 0;
+    int4* d_tile_tasks = nullptr;  // (block, tile row, tile column) of the local solves
+    int64_t n_tile_tasks = 0;
+    int2* d_row_tasks = nullptr;   // (block, tile row), longest first (triangular factor)
+    int64_t n_row_tasks = 0;
+    int64_t slot_total = 0;        // row- or column-sum slots per right-hand side (sum nt(nt+1)/2 * 64)
+    int64_t* d_s_off = nullptr;    // J+1 slot offsets
+    int32_t* d_ent_blk = nullptr;  // ub_total: block of each block entry
     int64_t* d_f_off = nullptr;
     int64_t* d_q = nullptr;
     int64_t* d_ub_off = nullptr;   // J+1 offsets of per-block local vectors (sum q_i)
@@ -249,6 +253,7 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part);
 int launch_Hx(Handle& h, const double* x, int k, double* y, bool scale_bnd);
 int launch_HTy(Handle& h, const double* y, int k, double* x, double* partial);
 int launch_precond(Handle& h, const double* r, int k, double* z, double* ub);
+// ub: (2 ub_total + 2 slot_total) k doubles of scratch
 int launch_precond_local(Handle& h, const double* r, int k, double* ub);
 
 int krylov_cg(Handle& h, const double* rhs, int k, const double* W0, const rann_dd_solve_opts& o,

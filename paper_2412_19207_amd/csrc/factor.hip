@@ -1,12 +1,12 @@
 // Local inverses of the Schwarz blocks on matrix cores (paper Sec. 3: the
 // local inverse A_i^{-1} of A_i = R_i H^T H R_i^T).
 //
-// The inverse is kept as a triangular factor: with D = diag(A)^{-1/2} and the
-// Cholesky factorisation D A D + eps I = L L^T,
-//     A^{-1} = Y^T Y,   Y = L^{-1} D,
-// stored as packed lower 64x64 tiles (FP64, or FP32 in the mixed path).  Y^T Y
-// is positive semi-definite by construction whatever the storage precision,
-// so the rounded factor still gives a valid CG preconditioner.
+// With D = diag(A)^{-1/2} and the Cholesky factorisation D A D + eps I = L L^T,
+//     A^{-1} = Y^T Y,   Y = L^{-1} D.
+// The FP64 path stores W = Y^T Y itself as packed lower 64x64 tiles (read once
+// per application); the mixed path stores Y in FP32 (Y^T Y stays positive
+// semi-definite whatever the rounding of Y, so the FP32 operator is still a
+// valid CG preconditioner, which a rounded W would not be).
 //
 // All blocks are factorised together, one tile per workgroup, in launches
 // that follow the data dependences of the blocked algorithms:
@@ -14,7 +14,7 @@
 //                                     panel(s) : L_as = W_as L_ss^{-T}
 //                                     trail(s) : W_ab -= L_as L_bs^T (s < b <= a)
 //   X = L^{-1}, by tile distance t:    X_ab = -L_aa^{-1} sum_{c=b}^{a-1} L_ac X_cb
-//   Y = X D, rounded to the storage type.
+//   Y = X D rounded to FP32 (mixed) or W = D X^T X D on matrix cores (FP64).
 // A pivot that is not positive restarts that block with a diagonal shift
 // eps = 10 u q, growing tenfold (the count is reported as `shifts`).
 #include <hip/hip_runtime.h>
@@ -303,6 +303,42 @@ __global__ void k_make_Y(const TileTask* __restrict__ tasks, const int64_t* __re
     }
 }
 
+
+// packed tile (a, b), b <= a, of W = A^{-1} = D X^T X D: sum over the rows t >= a0
+// of X[t][a0 + r] X[t][b0 + c] (X is lower triangular), scaled by D on both
+// sides; a diagonal tile is written whole and exactly symmetric
+__global__ void __launch_bounds__(kFT) k_make_W(const TileTask* __restrict__ tasks,
+                                                const int64_t* __restrict__ f_off,
+                                                const int64_t* __restrict__ qv,
+                                                const int64_t* __restrict__ ub_off,
+                                                const int64_t* __restrict__ t_off,
+                                                const double* __restrict__ Xall,
+                                                const double* __restrict__ Dall,
+                                                double* __restrict__ Wt) {
+    __shared__ double As[kTK][kTM + kPad];
+    __shared__ double Bs[kTK][kTN + kPad];
+    __shared__ double Cs[kTM][kTM + kPad];
+    const TileTask tk = tasks[blockIdx.x];
+    const int i = tk.blk, a = tk.a, b = tk.b;
+    const int64_t q = qv[i];
+    const int64_t a0 = (int64_t)a * kTM, b0 = (int64_t)b * kTM;
+    const int ab = tile_dim(q, a), bb = tile_dim(q, b);
+    const double* X = Xall + f_off[i];
+    const double* D = Dall + ub_off[i];
+    double* out = Wt + t_off[i] + ((int64_t)a * (a + 1) / 2 + b) * kTM * kTM;
+    TileAcc<double> acc;
+    acc.zero();
+    tile_gemm<double, true, true>(acc, As, Bs, X, q, a0, a0, ab, X, q, a0, b0, bb, (int)(q - a0));
+    acc.each([&](int r, int c, double v) {
+        Cs[r][c] = (r < ab && c < bb) ? D[a0 + r] * v * D[b0 + c] : 0.0;
+    });
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTM * kTM; e += kFT) {
+        const int r = e / kTM, c = e % kTM;
+        out[e] = (a == b && c > r) ? Cs[c][r] : Cs[r][c];
+    }
+}
+
 }  // namespace
 
 // Tile counts and packed offsets of every block (host tables and device copy).
@@ -447,7 +483,7 @@ int factor_tiles(Handle& h, double* A, double* W) {
                                    d_tasks + dist[t].off, h.d_f_off, h.d_q, W, A);
         RDD_HIP(hipGetLastError());
     }
-    // Y = X D in packed tiles
+    // Y = X D (mixed, FP32) or W = Y^T Y (FP64) in packed lower tiles
     {
         std::vector<TileTask> tasks;
         for (int i = 0; i < J; ++i)
@@ -462,9 +498,8 @@ int factor_tiles(Handle& h, double* A, double* W) {
                                    h.stream, d_tasks, h.d_f_off, h.d_q, h.d_ub_off, h.d_t_off, A,
                                    d_D, h.d_M32);
             else
-                hipLaunchKernelGGL(k_make_Y<double>, dim3((unsigned)tasks.size()), dim3(256), 0,
-                                   h.stream, d_tasks, h.d_f_off, h.d_q, h.d_ub_off, h.d_t_off, A,
-                                   d_D, h.d_M64);
+                hipLaunchKernelGGL(k_make_W, dim3((unsigned)tasks.size()), dim3(kFT), 0, h.stream,
+                                   d_tasks, h.d_f_off, h.d_q, h.d_ub_off, h.d_t_off, A, d_D, h.d_M64);
         }
         RDD_HIP(hipGetLastError());
     }

@@ -749,7 +749,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
                    const rann_dd_solve_opts& o, double* W, std::vector<int>& iters_out,
                    std::vector<double>& res_out, int* status) {
     const size_t P = (size_t)h.P, N = (size_t)h.N;
-    const size_t need = P * k * 4 + N * k + (size_t)h.part_total * k + (size_t)h.ub_total * k * 2 +
+    const size_t need = P * k * 4 + N * k + (size_t)h.part_total * k + (size_t)(2 * h.ub_total + 2 * h.slot_total) * k +
                         (size_t)kDotBlocks * k + 3 * (size_t)kRed * k + (size_t)h.n_slab_tasks * k + 24 * (size_t)k + 2048;
     RDD_TRY(ensure_ws(h, need * sizeof(double)));
     Scratch sc{static_cast<double*>(h.ws), 0};
@@ -759,7 +759,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     double* s = sc.take(P * k);
     double* y = sc.take(N * k);
     double* part = sc.take((size_t)h.part_total * k);
-    double* ub = sc.take((size_t)h.ub_total * k * 2);
+    double* ub = sc.take((size_t)(2 * h.ub_total + 2 * h.slot_total) * k);
     double* dp = sc.take((size_t)kDotBlocks * k);
     double* rho = sc.take(k);
     double* pS = sc.take(k);
@@ -977,7 +977,7 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
     const int m = std::max(1, std::min(o.restart, 128));
     const size_t P = (size_t)h.P, N = (size_t)h.N;
     const size_t need = P * k * (m + 1) + P * k * 3 + N * k + (size_t)h.part_total * k +
-                        (size_t)h.ub_total * k * 2 + (size_t)kDotBlocks * k * (m + 1) +
+                        (size_t)(2 * h.ub_total + 2 * h.slot_total) * k + (size_t)kDotBlocks * k * (m + 1) +
                         (size_t)k * ((m + 1) * m + 6 * (m + 1) + 16) + 1024;
     RDD_TRY(ensure_ws(h, need * sizeof(double)));
     Scratch sc{static_cast<double*>(h.ws), 0};
@@ -987,7 +987,7 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
     double* t0 = sc.take(P * k);
     double* y = sc.take(N * k);
     double* part = sc.take((size_t)h.part_total * k);
-    double* ub = sc.take((size_t)h.ub_total * k * 2);
+    double* ub = sc.take((size_t)(2 * h.ub_total + 2 * h.slot_total) * k);
     double* dp = sc.take((size_t)kDotBlocks * k * (m + 1));
     double* Hs = sc.take((size_t)k * (m + 1) * m);
     double* h1 = sc.take((size_t)k * (m + 1));

@@ -5,12 +5,15 @@
 //   SAS: D_i = 1 / (number of blocks containing the column)
 //
 // Block i selects the columns of every subdomain in its stencil.  The local
-// inverse is kept as the packed lower-triangular tiles of Y_i = L_i^{-1} D_i
-// (factor.hip), A_i^{-1} = Y_i^T Y_i, and applied as two streaming passes
-// instead of two dependent triangular solves:
-//   row pass   : u_a = sum_{b <= a} Y_ab x_b   (one workgroup per tile row)
-//   column pass: z_b = sum_{a >= b} Y_ab^T u_a (one workgroup per tile column)
-// Tile rows of Y are contiguous in memory; every tile is read once per pass.
+// inverse A_i^{-1} is kept as packed lower 64x64 tiles (factor.hip): the
+// symmetric W_i itself in FP64, or the triangular factor Y_i (A_i^{-1} =
+// Y_i^T Y_i) in FP32 for the mixed path.  One workgroup per tile (a, b), b <=
+// a, writes the row sums R_ab = M_ab x_b and/or the column sums C_ab =
+// M_ab^T x_a into slots of its own, and a reduction adds them in a fixed order
+// (no atomics):
+//   FP64: z_c = sum_{b <= c} R_cb + sum_{a > c} C_ac      (one pass over W)
+//   FP32: u_c = sum_{b <= c} R_cb, then z_c = sum_{a >= c} C_ac with x = u
+//         (two passes over Y, the second usually from cache).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,7 +33,6 @@ namespace {
 
 constexpr int kT = 64;              // tile edge
 constexpr int kTE = kT * kT;        // tile elements
-constexpr int kXChunk = 8;          // tiles of the input vector staged in LDS at once
 
 // 16 consecutive elements (16-byte aligned) into registers
 __device__ __forceinline__ void load16(const double* p, double* v) {
@@ -54,115 +56,203 @@ __device__ __forceinline__ void load16(const float* p, float* v) {
     }
 }
 
-// row pass: u_a = sum_{b <= a} Y_ab x_b with x = r gathered through the block's
-// column list.  Thread (row, seg) owns 16 consecutive columns of one tile row;
-// FP64 accumulation.
+// Column sums of one tile held in the row mapping (thread = (row, 16-column
+// segment)): out[c] = sum_r tile[r][c] xv[r], through a transposed copy in
+// LDS; thread (c, quarter) sums 16 rows, the 4 quarters meet by shuffles.
+// With one tile per workgroup, or two buffers used alternately, one barrier
+// per tile suffices.
 template <class T, int KB>
-__global__ void __launch_bounds__(256) k_tri_row(const int2* __restrict__ tasks,
-                                                 const int64_t* __restrict__ t_off,
-                                                 const int64_t* __restrict__ qv,
-                                                 const int64_t* __restrict__ ub_off,
-                                                 const int32_t* __restrict__ blk_cols,
-                                                 const T* __restrict__ Y,
-                                                 const double* __restrict__ r, int k, int k0,
-                                                 double* __restrict__ u) {
-    __shared__ double xs[kXChunk * kT][KB];
+__device__ __forceinline__ void tile_colsum(const T* v, const double (*xv)[KB], T (*ts)[kT + 1],
+                                            double* out, int k, int cmax) {
+    const int tid = threadIdx.x, row = tid >> 2, seg = tid & 3;
+    const int col = tid >> 2, rq = tid & 3;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) ts[row][seg * 16 + cc] = v[cc];
+    __syncthreads();
+    double c[KB];
+#pragma unroll
+    for (int t = 0; t < KB; ++t) c[t] = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+        const int r = rq * 16 + rr;
+        const double tv = (double)ts[r][col];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) c[t] = fma(tv, xv[r][t], c[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < KB; ++t) {
+        c[t] += __shfl_xor(c[t], 1);
+        c[t] += __shfl_xor(c[t], 2);
+    }
+    if (rq == 0 && col < cmax)
+#pragma unroll
+        for (int t = 0; t < KB; ++t) out[(int64_t)col * k + t] = c[t];
+}
+
+// One tile (a, b) of the local solves: R = M_ab x_b into the R slot (a, b)
+// when WR, C = M_ab^T xa into the C slot (a, b) when WC (skipped for the
+// diagonal tile of the symmetric W).  xb comes from r through the block's
+// column list; xa from r (symmetric W) or from the block vector u (second
+// pass of the triangular factor).
+template <class T, int KB, bool WR, bool WC, bool XA_FROM_U, bool SYM>
+__global__ void __launch_bounds__(256) k_tile_apply(const int4* __restrict__ tasks,
+                                                    const int64_t* __restrict__ t_off,
+                                                    const int64_t* __restrict__ qv,
+                                                    const int64_t* __restrict__ ub_off,
+                                                    const int64_t* __restrict__ s_off,
+                                                    const int32_t* __restrict__ blk_cols,
+                                                    const T* __restrict__ M,
+                                                    const double* __restrict__ r,
+                                                    const double* __restrict__ u, int k, int k0,
+                                                    double* __restrict__ Rs, double* __restrict__ Cs) {
+    __shared__ double xb[kT][KB];
+    __shared__ double xa[kT][KB];
+    __shared__ T ts[kT][kT + 1];
+    const int4 tk = tasks[blockIdx.x];
+    const int i = tk.x, a = tk.y, b = tk.z;
+    const int64_t q = qv[i];
+    const int tid = threadIdx.x, row = tid >> 2, seg = tid & 3;
+    const int64_t tile = (int64_t)a * (a + 1) / 2 + b;
+    T v[16];
+    load16(M + t_off[i] + tile * kTE + row * kT + seg * 16, v);
+    const int32_t* cols = blk_cols + ub_off[i];
+    const bool do_c = WC && !(SYM && a == b);
+    for (int e = tid; e < kT * KB; e += 256) {
+        const int c = e / KB, t = e % KB;
+        if (WR) {
+            const int64_t gc = (int64_t)b * kT + c;
+            xb[c][t] = (gc < q) ? r[(int64_t)cols[gc] * k + k0 + t] : 0.0;
+        }
+        if (do_c) {
+            const int64_t gc = (int64_t)a * kT + c;
+            double xv = 0.0;
+            if (gc < q) xv = XA_FROM_U ? u[(ub_off[i] + gc) * k + k0 + t] : r[(int64_t)cols[gc] * k + k0 + t];
+            xa[c][t] = xv;
+        }
+    }
+    __syncthreads();
+    const int64_t so = (s_off[i] + tile * kT) * k + k0;  // slot (a, b), entry 0
+    if (WR) {
+        double acc[KB];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc)
+#pragma unroll
+            for (int t = 0; t < KB; ++t) acc[t] = fma((double)v[cc], xb[seg * 16 + cc][t], acc[t]);
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+            acc[t] += __shfl_xor(acc[t], 1);
+            acc[t] += __shfl_xor(acc[t], 2);
+        }
+        if (seg == 0)
+#pragma unroll
+            for (int t = 0; t < KB; ++t) Rs[so + (int64_t)row * k + t] = acc[t];
+    }
+    if (do_c) {
+        const int cmax = (int)((q - (int64_t)b * kT) < kT ? q - (int64_t)b * kT : kT);
+        tile_colsum<T, KB>(v, xa, ts, Cs + so, k, cmax);
+    }
+}
+
+// One (block, tile row a) of the triangular factor (mixed path): u_a = sum_b
+// Y_ab x_b over the contiguous tiles (a, 0..a), then C(a, b) = Y_ab^T u_a for
+// every b <= a, the tile row read a second time (from cache); the next tile
+// is loaded while the current one is used.
+template <int KB>
+__global__ void __launch_bounds__(256) k_trirow_apply(const int2* __restrict__ tasks,
+                                                      const int64_t* __restrict__ t_off,
+                                                      const int64_t* __restrict__ qv,
+                                                      const int64_t* __restrict__ ub_off,
+                                                      const int64_t* __restrict__ s_off,
+                                                      const int32_t* __restrict__ blk_cols,
+                                                      const float* __restrict__ Y,
+                                                      const double* __restrict__ r, int k, int k0,
+                                                      double* __restrict__ Cs) {
+    constexpr int kXC = 8;                // tiles of x staged per chunk
+    __shared__ double xs[kXC * kT][KB];
+    __shared__ double ua[kT][KB];
+    __shared__ float ts[2][kT][kT + 1];
     const int2 tk = tasks[blockIdx.x];
     const int i = tk.x, a = tk.y;
     const int64_t q = qv[i];
     const int tid = threadIdx.x, row = tid >> 2, seg = tid & 3;
-    const T* Ya = Y + t_off[i] + (int64_t)a * (a + 1) / 2 * kTE + row * kT + seg * 16;
+    const float* Ya = Y + t_off[i] + (int64_t)a * (a + 1) / 2 * kTE + row * kT + seg * 16;
     const int32_t* cols = blk_cols + ub_off[i];
+    double* cla = Cs + s_off[i] * k + k0 + (int64_t)a * (a + 1) / 2 * kT * k;  // slot (a, b) at cla + b kT k
     double acc[KB];
 #pragma unroll
     for (int t = 0; t < KB; ++t) acc[t] = 0.0;
-    for (int b0 = 0; b0 <= a; b0 += kXChunk) {
-        const int nb = (a + 1 - b0 < kXChunk) ? a + 1 - b0 : kXChunk;
-        __syncthreads();
-        for (int e = tid; e < nb * kT * KB; e += 256) {
-            const int c = e / KB, t = e % KB;
-            const int64_t gc = (int64_t)b0 * kT + c;
-            xs[c][t] = (gc < q) ? r[(int64_t)cols[gc] * k + k0 + t] : 0.0;
+    float v[16], vn[16];
+    load16(Ya, v);
+    for (int b = 0; b <= a; ++b) {
+        const int bb = b % kXC;
+        if (bb == 0) {
+            const int nb = (a + 1 - b < kXC) ? a + 1 - b : kXC;
+            __syncthreads();
+            for (int e = tid; e < nb * kT * KB; e += 256) {
+                const int c = e / KB, t = e % KB;
+                const int64_t gc = (int64_t)b * kT + c;
+                xs[c][t] = (gc < q) ? r[(int64_t)cols[gc] * k + k0 + t] : 0.0;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        for (int bb = 0; bb < nb; ++bb) {
-            T v[16];
-            load16(Ya + (int64_t)(b0 + bb) * kTE, v);
-            const double (*xr)[KB] = xs + bb * kT + seg * 16;
+        if (b < a) load16(Ya + (int64_t)(b + 1) * kTE, vn);
+        const double (*xr)[KB] = xs + bb * kT + seg * 16;
 #pragma unroll
-            for (int cc = 0; cc < 16; ++cc)
+        for (int cc = 0; cc < 16; ++cc)
 #pragma unroll
-                for (int t = 0; t < KB; ++t) acc[t] = fma((double)v[cc], xr[cc][t], acc[t]);
-        }
+            for (int t = 0; t < KB; ++t) acc[t] = fma((double)v[cc], xr[cc][t], acc[t]);
+        if (b < a)
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) v[cc] = vn[cc];
     }
 #pragma unroll
     for (int t = 0; t < KB; ++t) {
         acc[t] += __shfl_xor(acc[t], 1);
         acc[t] += __shfl_xor(acc[t], 2);
     }
-    const int64_t gr = (int64_t)a * kT + row;
-    if (seg == 0 && gr < q) {
-        double* o = u + (ub_off[i] + gr) * k + k0;
+    if (seg == 0)
 #pragma unroll
-        for (int t = 0; t < KB; ++t) o[t] = acc[t];
+        for (int t = 0; t < KB; ++t) ua[row][t] = acc[t];
+    load16(Ya, v);
+    __syncthreads();
+    for (int b = 0; b <= a; ++b) {
+        if (b < a) load16(Ya + (int64_t)(b + 1) * kTE, vn);
+        const int cmax = (int)((q - (int64_t)b * kT) < kT ? q - (int64_t)b * kT : kT);
+        tile_colsum<float, KB>(v, ua, ts[b & 1], cla + (int64_t)b * kT * k, k, cmax);
+        if (b < a)
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) v[cc] = vn[cc];
     }
 }
 
-// column pass: z_b = sum_{a >= b} Y_ab^T x_a with x the row-pass output.
-// Thread (col, wave) owns 16 rows of one tile column; the four waves are
-// summed in LDS at the end.
-template <class T, int KB>
-__global__ void __launch_bounds__(256) k_tri_col(const int2* __restrict__ tasks,
-                                                 const int64_t* __restrict__ t_off,
-                                                 const int64_t* __restrict__ qv,
-                                                 const int64_t* __restrict__ ub_off,
-                                                 const T* __restrict__ Y,
-                                                 const double* __restrict__ x, int k, int k0,
-                                                 double* __restrict__ z) {
-    __shared__ double xs[kXChunk * kT][KB];
-    __shared__ double red[4][kT][KB];
-    const int2 tk = tasks[blockIdx.x];
-    const int i = tk.x, b = tk.y;
-    const int64_t q = qv[i];
-    const int nt = (int)((q + kT - 1) / kT);
-    const int tid = threadIdx.x, col = tid & 63, rs = tid >> 6;
-    const T* Yi = Y + t_off[i] + (int64_t)(rs * 16) * kT + col;
-    const double* xi = x + ub_off[i] * k + k0;
-    double acc[KB];
-#pragma unroll
-    for (int t = 0; t < KB; ++t) acc[t] = 0.0;
-    for (int a0 = b; a0 < nt; a0 += kXChunk) {
-        const int na = (nt - a0 < kXChunk) ? nt - a0 : kXChunk;
-        __syncthreads();
-        for (int e = tid; e < na * kT * KB; e += 256) {
-            const int c = e / KB, t = e % KB;
-            const int64_t gr = (int64_t)a0 * kT + c;
-            xs[c][t] = (gr < q) ? xi[gr * k + t] : 0.0;
-        }
-        __syncthreads();
-        for (int aa = 0; aa < na; ++aa) {
-            const int a = a0 + aa;
-            const T* src = Yi + ((int64_t)a * (a + 1) / 2 + b) * kTE;
-            T v[16];
-#pragma unroll
-            for (int rr = 0; rr < 16; ++rr) v[rr] = src[rr * kT];
-            const double (*xr)[KB] = xs + aa * kT + rs * 16;
-#pragma unroll
-            for (int rr = 0; rr < 16; ++rr)
-#pragma unroll
-                for (int t = 0; t < KB; ++t) acc[t] = fma((double)v[rr], xr[rr][t], acc[t]);
-        }
+// z[e] for block entry e in tile column c (offset o):
+//   (with R) sum_{b <= c} R(c, b)[o]  +  (with C) sum_{a >= c + c_skip} C(a, c)[o]
+__global__ void k_slot_reduce(int64_t nent, int k, int use_r, int use_c, int c_skip,
+                              const int32_t* __restrict__ ent_blk, const int64_t* __restrict__ ub_off,
+                              const int64_t* __restrict__ s_off, const int64_t* __restrict__ qv,
+                              const double* __restrict__ Rs, const double* __restrict__ Cs,
+                              double* __restrict__ z) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= nent * k) return;
+    const int64_t e = idx / k;
+    const int t = (int)(idx % k);
+    const int i = ent_blk[e];
+    const int64_t c = e - ub_off[i];
+    const int tc = (int)(c / kT), o = (int)(c % kT);
+    const int nt = (int)((qv[i] + kT - 1) / kT);
+    const int64_t base = s_off[i] * k + t + (int64_t)o * k;
+    double s = 0.0;
+    if (use_r) {
+        const int64_t row0 = (int64_t)tc * (tc + 1) / 2;
+        for (int b = 0; b <= tc; ++b) s += Rs[base + (row0 + b) * kT * k];
     }
-#pragma unroll
-    for (int t = 0; t < KB; ++t) red[rs][col][t] = acc[t];
-    __syncthreads();
-    const int64_t gc = (int64_t)b * kT + col;
-    if (rs == 0 && gc < q) {
-        double* o = z + (ub_off[i] + gc) * k + k0;
-#pragma unroll
-        for (int t = 0; t < KB; ++t) o[t] = red[0][col][t] + red[1][col][t] + red[2][col][t] + red[3][col][t];
-    }
+    if (use_c)
+        for (int a = tc + c_skip; a < nt; ++a) s += Cs[base + ((int64_t)a * (a + 1) / 2 + tc) * kT * k];
+    z[idx] = s;
 }
+
 
 // z[g] = sum over (block entry e containing column g) of w_e u[e]
 __global__ void k_gather_sum(int64_t P, int k, const int64_t* __restrict__ gat_off,
@@ -310,34 +400,41 @@ int build_schwarz(Handle& h) {
     }
     h.ub_total = ub_off[J];
 
-    // packed tiles and the task lists of the two passes (RAS: only the tile
-    // columns holding owned unknowns, and the tile rows they need)
+    // packed tiles, one task per stored tile (RAS: tile rows from the first
+    // owned tile column on) and the slot layout of the row and column sums
     RDD_TRY(plan_tiles(h));
-    std::vector<std::pair<int, int2>> rt, ct;  // (work, task)
+    std::vector<int4> tv;
+    std::vector<int64_t> s_off(J + 1, 0);
+    std::vector<int32_t> ent_blk((size_t)h.ub_total);
     for (int i = 0; i < J; ++i) {
         const int nt = h.nt[i];
+        s_off[i + 1] = s_off[i] + (int64_t)nt * (nt + 1) / 2 * 64;
+        for (int64_t e = ub_off[i]; e < ub_off[i + 1]; ++e) ent_blk[e] = i;
         if (nt == 0 || plan.row_cnt[i] == 0) continue;
         const int b_lo = (int)(plan.row_start[i] / 64);
-        const int b_hi = (int)((plan.row_start[i] + plan.row_cnt[i] - 1) / 64);
-        for (int a = b_lo; a < nt; ++a) rt.push_back({a + 1, make_int2(i, a)});
-        for (int b = b_lo; b <= b_hi; ++b) ct.push_back({nt - b, make_int2(i, b)});
+        for (int a = b_lo; a < nt; ++a)
+            for (int b = 0; b <= a; ++b) tv.push_back(make_int4(i, a, b, 0));
     }
-    auto by_work = [](const std::pair<int, int2>& x, const std::pair<int, int2>& y) {
+    h.n_tile_tasks = (int64_t)tv.size();
+    // tile rows, longest first (triangular factor of the mixed path)
+    std::vector<std::pair<int, int2>> rt;
+    for (const int4& t4 : tv)
+        if (t4.z == 0) rt.push_back({t4.y + 1, make_int2(t4.x, t4.y)});
+    std::stable_sort(rt.begin(), rt.end(), [](const std::pair<int, int2>& x, const std::pair<int, int2>& y) {
         return x.first > y.first;
-    };
-    std::stable_sort(rt.begin(), rt.end(), by_work);
-    std::stable_sort(ct.begin(), ct.end(), by_work);
-    std::vector<int2> rtv, ctv;
+    });
+    std::vector<int2> rtv;
     for (auto& e : rt) rtv.push_back(e.second);
-    for (auto& e : ct) ctv.push_back(e.second);
     h.n_row_tasks = (int64_t)rtv.size();
-    h.n_col_tasks = (int64_t)ctv.size();
     RDD_TRY(dev_alloc(h, &h.d_row_tasks, rtv.size()));
-    RDD_TRY(dev_alloc(h, &h.d_col_tasks, ctv.size()));
-    if (!rtv.empty())
-        RDD_TRY(upload(h, h.d_row_tasks, rtv.data(), sizeof(int2) * rtv.size()));
-    if (!ctv.empty())
-        RDD_TRY(upload(h, h.d_col_tasks, ctv.data(), sizeof(int2) * ctv.size()));
+    if (!rtv.empty()) RDD_TRY(upload(h, h.d_row_tasks, rtv.data(), sizeof(int2) * rtv.size()));
+    h.slot_total = s_off[J];
+    RDD_TRY(dev_alloc(h, &h.d_tile_tasks, tv.size()));
+    RDD_TRY(dev_alloc(h, &h.d_s_off, s_off.size()));
+    RDD_TRY(dev_alloc(h, &h.d_ent_blk, ent_blk.size()));
+    if (!tv.empty()) RDD_TRY(upload(h, h.d_tile_tasks, tv.data(), sizeof(int4) * tv.size()));
+    RDD_TRY(upload(h, h.d_s_off, s_off.data(), sizeof(int64_t) * s_off.size()));
+    if (!ent_blk.empty()) RDD_TRY(upload(h, h.d_ent_blk, ent_blk.data(), sizeof(int32_t) * ent_blk.size()));
 
     // local Gram blocks (FP64) and their factorisation
     double *d_A = nullptr, *d_W = nullptr;
@@ -355,40 +452,60 @@ int build_schwarz(Handle& h) {
 }
 
 // u_i = A_i^{-1} r_{N(i)} for every block (the local solves only).  ub holds
-// 2 ub_total k doubles: the result, then the row-pass intermediate.
+// (2 ub_total + 2 slot_total) k doubles: the result, the intermediate block
+// vector of the triangular factor, and the row and column sum slots.
 int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
     double* u1 = ub + h.ub_total * k;
+    double* Rs = u1 + h.ub_total * k;
+    double* Cs = Rs + h.slot_total * k;
+    const int64_t tot = h.ub_total * k;
+    const unsigned rgrid = (unsigned)((tot + 255) / 256);
+    const unsigned tgrid = (unsigned)h.n_tile_tasks;
     KTimer kt_(h.stream, "k_local_apply");
+    if (tgrid == 0 || tot == 0) {
+        kt_.stop();
+        return RANN_OK;
+    }
     for (int k0 = 0; k0 < k;) {
         const int rem = k - k0;
         const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
-#define RDD_TRI(T, M, KBV)                                                                         \
-    do {                                                                                           \
-        if (h.n_row_tasks)                                                                         \
-            hipLaunchKernelGGL((k_tri_row<T, KBV>), dim3((unsigned)h.n_row_tasks), dim3(256), 0,   \
-                               h.stream, h.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off,              \
-                               h.d_blk_cols, M, r, k, k0, u1);                                     \
-        if (h.n_col_tasks)                                                                         \
-            hipLaunchKernelGGL((k_tri_col<T, KBV>), dim3((unsigned)h.n_col_tasks), dim3(256), 0,   \
-                               h.stream, h.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, M, u1, k,    \
-                               k0, ub);                                                            \
-    } while (0)
-#define RDD_TRI_ALL(T, M)                   \
-    switch (kb) {                           \
-        case 8: RDD_TRI(T, M, 8); break;    \
-        case 4: RDD_TRI(T, M, 4); break;    \
-        case 2: RDD_TRI(T, M, 2); break;    \
-        default: RDD_TRI(T, M, 1); break;   \
+#define RDD_TA(T, M, KBV, WR, WC, XU, SY)                                                          \
+    hipLaunchKernelGGL((k_tile_apply<T, KBV, WR, WC, XU, SY>), dim3(tgrid), dim3(256), 0, h.stream, \
+                       h.d_tile_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols, M, r, \
+                       u1, k, k0, Rs, Cs)
+#define RDD_TR(KBV)                                                                                 \
+    hipLaunchKernelGGL((k_trirow_apply<KBV>), dim3((unsigned)h.n_row_tasks), dim3(256), 0, h.stream, \
+                       h.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols, h.d_M32, r, \
+                       k, k0, Cs)
+#define RDD_TA_KB(T, M, WR, WC, XU, SY)                  \
+    switch (kb) {                                        \
+        case 8: RDD_TA(T, M, 8, WR, WC, XU, SY); break;  \
+        case 4: RDD_TA(T, M, 4, WR, WC, XU, SY); break;  \
+        case 2: RDD_TA(T, M, 2, WR, WC, XU, SY); break;  \
+        default: RDD_TA(T, M, 1, WR, WC, XU, SY); break; \
     }
         if (h.precision == RANN_MIXED) {
-            RDD_TRI_ALL(float, h.d_M32);
+            switch (kb) {
+                case 8: RDD_TR(8); break;
+                case 4: RDD_TR(4); break;
+                case 2: RDD_TR(2); break;
+                default: RDD_TR(1); break;
+            }
         } else {
-            RDD_TRI_ALL(double, h.d_M64);
+            RDD_TA_KB(double, h.d_M64, true, true, false, true);
         }
-#undef RDD_TRI_ALL
-#undef RDD_TRI
         k0 += kb;
     }
+    if (h.precision == RANN_MIXED) {
+        hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, 0, 1, 0,
+                           h.d_ent_blk, h.d_ub_off, h.d_s_off, h.d_q, Rs, Cs, ub);
+    } else {
+        hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, 1, 1, 1,
+                           h.d_ent_blk, h.d_ub_off, h.d_s_off, h.d_q, Rs, Cs, ub);
+    }
+#undef RDD_TA_KB
+#undef RDD_TR
+#undef RDD_TA
     kt_.stop();
     RDD_HIP(hipGetLastError());
     return RANN_OK;
