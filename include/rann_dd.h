@@ -70,7 +70,8 @@ extern "C" {
 #define RANN_PCA_OFF       2    /* no truncation, V = I */
 
 #define RANN_METHOD_CG     0
-#define RANN_METHOD_GMRES  1
+#define RANN_METHOD_GMRES  1        /* left-preconditioned (paper Sec. 5) */
+#define RANN_METHOD_GMRES_RIGHT 2   /* right-preconditioned: minimises the true residual */
 
 typedef struct rann_dd_handle rann_dd_handle;
 
@@ -106,7 +107,7 @@ typedef struct rann_dd_desc {
 typedef struct rann_dd_solve_opts {
     double tol;               /* relative true normal residual ||H^T(F - H W)|| / ||H^T F|| */
     int32_t maxiter;          /* iteration limit (>= 1) */
-    int32_t method;           /* RANN_METHOD_CG (AS, SAS-free) or RANN_METHOD_GMRES */
+    int32_t method;           /* RANN_METHOD_CG (AS), RANN_METHOD_GMRES or RANN_METHOD_GMRES_RIGHT */
     int32_t restart;          /* GMRES restart length (1..128) */
     int32_t check_every;      /* host convergence check cadence (>= 1) */
 } rann_dd_solve_opts;

@@ -58,21 +58,27 @@ def pcg(A, M, B, X0=None, tol=1e-10, maxiter=1000, true_res=None):
     return X, iters, np.array(hist)
 
 
-def gmres(A, M, b, x0=None, restart=50, tol=1e-5, maxiter=1000):
-    """Left-preconditioned GMRES(restart) for one right-hand side b (P,)."""
+def gmres(A, M, b, x0=None, restart=50, tol=1e-5, maxiter=1000, side="left"):
+    """GMRES(restart) for one right-hand side b (P,).
+
+    side="left"  : Arnoldi on M A, residuals M (b - A x) (the paper's form);
+    side="right" : Arnoldi on A M, x = x0 + M V y, residuals b - A x.
+    """
     b = b.ravel()
     P = b.size
     A0, M0 = A, M
     A = lambda v: np.asarray(A0(v.reshape(P, 1))).ravel()
     M = lambda v: np.asarray(M0(v.reshape(P, 1))).ravel()
     x = np.zeros(P) if x0 is None else np.array(x0, dtype=float).ravel()
-    mb = np.linalg.norm(M(b))
+    right = (side == "right")
+    pre = (lambda v: v) if right else M   # applied to residuals
+    mb = np.linalg.norm(pre(b))
     if mb == 0:
         return x, 0, []
     it = 0
     hist = []
     while it < maxiter:
-        r = M(b - A(x))
+        r = pre(b - A(x))
         beta = np.linalg.norm(r)
         if beta / mb <= tol:
             break
@@ -86,7 +92,7 @@ def gmres(A, M, b, x0=None, restart=50, tol=1e-5, maxiter=1000):
         V[0] = r / beta
         j_used = 0
         for j in range(m):
-            w = M(A(V[j]))
+            w = A(M(V[j])) if right else M(A(V[j]))
             for i in range(j + 1):
                 Hh[i, j] = V[i] @ w
                 w = w - Hh[i, j] * V[i]
@@ -112,9 +118,9 @@ def gmres(A, M, b, x0=None, restart=50, tol=1e-5, maxiter=1000):
         y = np.zeros(j_used)
         for i in range(j_used - 1, -1, -1):
             y[i] = (g[i] - Hh[i, i + 1:j_used] @ y[i + 1:]) / Hh[i, i]
-        x = x + V[:j_used].T @ y
+        x = x + (M(V[:j_used].T @ y) if right else V[:j_used].T @ y)
         if hist and hist[-1] <= tol:
-            r = M(b - A(x))
+            r = pre(b - A(x))
             if np.linalg.norm(r) / mb <= tol:
                 break
     return x, it, hist

@@ -50,7 +50,7 @@ def iterative(prob, sysm, stencil="full", precond="as", method="cg", tol=1e-10,
         cols, iters, hist = [], [], []
         for q in range(rhs.shape[1]):
             x, it, h = kr.gmres(bh.normal, M.apply, rhs[:, q], restart=restart, tol=tol,
-                                maxiter=maxiter)
+                                maxiter=maxiter, side="right" if method == "gmres_right" else "left")
             cols.append(x)
             iters.append(it)
             hist.append(h)

@@ -22,7 +22,7 @@ FP64, MIXED = 0, 1
 STENCIL = {"self": 0, "face": 1, "full": 2}
 PRECOND = {"none": 0, "as": 1, "ras": 2, "sas": 3}
 PCA_MODE = {"rel_eig": 0, "abs_sigma": 1, "off": 2}
-METHOD = {"cg": 0, "gmres": 1}
+METHOD = {"cg": 0, "gmres": 1, "gmres_right": 2}
 
 c_dp = ctypes.POINTER(ctypes.c_double)
 c_ip = ctypes.POINTER(ctypes.c_int32)

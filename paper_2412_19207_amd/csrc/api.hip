@@ -308,8 +308,9 @@ int validate_opts(const rann_dd_solve_opts* o) {
         return RANN_EINVAL;
     }
     if (!(o->tol > 0.0) || o->maxiter < 1 || o->check_every < 1 ||
-        (o->method != RANN_METHOD_CG && o->method != RANN_METHOD_GMRES) ||
-        (o->method == RANN_METHOD_GMRES && (o->restart < 1 || o->restart > 128))) {
+        (o->method != RANN_METHOD_CG && o->method != RANN_METHOD_GMRES &&
+         o->method != RANN_METHOD_GMRES_RIGHT) ||
+        (o->method != RANN_METHOD_CG && (o->restart < 1 || o->restart > 128))) {
         set_error("invalid solve options");
         return RANN_EINVAL;
     }

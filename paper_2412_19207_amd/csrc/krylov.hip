@@ -151,6 +151,11 @@ __global__ void k_scale_rows(int64_t row0, int64_t rows, int k, double f, const 
     out[row0 * k + idx] = f * in[row0 * k + idx];
 }
 
+__global__ void k_add(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] += a[i];
+}
+
 __global__ void k_copy(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
     int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx < n) b[idx] = a[idx];
@@ -1009,8 +1014,14 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
     } else {
         RDD_HIP(hipMemsetAsync(W, 0, sizeof(double) * Pk, h.stream));
     }
-    // ||M^{-1} rhs||
-    RDD_TRY(launch_precond(h, rhs, k, w, ub));
+    // right preconditioning: GMRES on A M^{-1}, W = W0 + M^{-1} (V y), residuals
+    // unpreconditioned; left: GMRES on M^{-1} A with preconditioned residuals
+    const bool right = (o.method == RANN_METHOD_GMRES_RIGHT);
+    // ||M^{-1} rhs|| (left) or ||rhs|| (right)
+    if (right)
+        hipLaunchKernelGGL(k_copy, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, w);
+    else
+        RDD_TRY(launch_precond(h, rhs, k, w, ub));
     RDD_TRY(dot(h, P, k, w, w, dp, nrm));
     std::vector<double> mb(k);
     RDD_TRY(download(h, mb.data(), nrm, sizeof(double) * k));
@@ -1023,10 +1034,14 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
     std::vector<double> tres(k), bn(k), rh(k);
     *status = RANN_OK;
     while (true) {
-        // r = M^{-1}(rhs - A W), A applied through the rows of H
+        // r = M^{-1}(rhs - A W) (left) or rhs - A W (right), A applied through the rows of H
         RDD_TRY(exact_normal_op(h, W, k, y, part, s));
-        hipLaunchKernelGGL(k_sub, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, s, t0);
-        RDD_TRY(launch_precond(h, t0, k, w, ub));
+        if (right) {
+            hipLaunchKernelGGL(k_sub, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, s, w);
+        } else {
+            hipLaunchKernelGGL(k_sub, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, s, t0);
+            RDD_TRY(launch_precond(h, t0, k, w, ub));
+        }
         RDD_TRY(dot(h, P, k, w, w, dp, nrm));
         hipLaunchKernelGGL(k_normalize, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P, k, nrm,
                            w, V);
@@ -1044,8 +1059,13 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
         if (any) {
             for (int j = 0; j < m && it < o.maxiter; ++j, ++it) {
                 double* vj = V + (size_t)j * P * k;
-                RDD_TRY(normal_op(h, vj, k, y, part, s));
-                RDD_TRY(launch_precond(h, s, k, w, ub));
+                if (right) {
+                    RDD_TRY(launch_precond(h, vj, k, t0, ub));
+                    RDD_TRY(normal_op(h, t0, k, y, part, w));
+                } else {
+                    RDD_TRY(normal_op(h, vj, k, y, part, s));
+                    RDD_TRY(launch_precond(h, s, k, w, ub));
+                }
                 // classical Gram-Schmidt, twice
                 hipLaunchKernelGGL(k_mdot_part, dim3(kDotBlocks, j + 1), dim3(256), 0, h.stream,
                                    (int64_t)P, k, j + 1, V, w, dp);
@@ -1078,8 +1098,17 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
                 }
             }
             hipLaunchKernelGGL(k_gmres_solve, dim3(1), dim3(256), 0, h.stream, k, jn, m, Hs, g, yv, nused);
-            hipLaunchKernelGGL(k_gmres_update, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P, k,
-                               jn, V, yv, W);
+            if (right) {
+                // W += M^{-1} (V y)
+                RDD_HIP(hipMemsetAsync(t0, 0, sizeof(double) * Pk, h.stream));
+                hipLaunchKernelGGL(k_gmres_update, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P,
+                                   k, jn, V, yv, t0);
+                RDD_TRY(launch_precond(h, t0, k, w, ub));
+                hipLaunchKernelGGL(k_add, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, w, W);
+            } else {
+                hipLaunchKernelGGL(k_gmres_update, dim3(grid_for(Pk)), dim3(256), 0, h.stream, (int64_t)P,
+                                   k, jn, V, yv, W);
+            }
             RDD_HIP(hipGetLastError());
         }
         ++cycles;

@@ -364,8 +364,8 @@ def cfg4(**kw) -> Problem:
                 rhs_fn=lambda X: np.zeros(X.shape[0]),
                 bnd_fn=lambda X, k: gaussian_st(X, nu)[:, None].repeat(k, 1),
                 exact_fn=lambda X: gaussian_st(X, nu), probes_per_dim=[48, 48, 48],
-                meta=dict(pca_tol=1e-8, tol=1e-6, stencil="face", method="gmres",
-                          restart=50, precond="ras", precision="mixed"))
+                meta=dict(pca_tol=1e-8, tol=1e-6, stencil="full", method="gmres",
+                          restart=50, precond="sas", precision="mixed"))
     args.update(kw)
     return build_problem(**args)
 
@@ -395,7 +395,7 @@ def cfg5(k=16, **kw) -> Problem:
                 bnd_counts=[pts[i] * l[i] for i in range(3)], coeff_fn=_laplace_coeffs,
                 rhs_fn=rhs, bnd_fn=_zero_bnd, exact_fn=exact,
                 probes_per_dim=[32, 32, 32], obs_noise=0.01,
-                meta=dict(pca_tol=1e-8, tol=1e-6, stencil="self", method="cg",
+                meta=dict(pca_tol=1e-8, tol=1e-6, stencil="full", method="cg",
                           precond="as"))
     args.update(kw)
     return build_problem(**args)

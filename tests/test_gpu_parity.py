@@ -216,12 +216,13 @@ def test_fp64_end_to_end_independent_pca(case_small2d):
 
 
 @pytest.mark.parametrize("kind", ["ras", "sas", "as"])
-def test_gmres_matches_qr(case_small2d, kind):
+@pytest.mark.parametrize("method", ["gmres", "gmres_right"])
+def test_gmres_matches_qr(case_small2d, kind, method):
     prob, ref = case_small2d
     sysm = ref["sys"]
     s = binding.Solver(prob, device=DEV, precond=kind)
     s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
-    W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-12, method="gmres", restart=50,
+    W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-12, method=method, restart=50,
                       maxiter=5000)
     assert info["max_rel_residual"] <= 1e-12
     assert rel(W.cpu().numpy(), ref["W"]) <= 1e-7

@@ -270,6 +270,32 @@ def test_gmres_reaches_qr_solution(small2d, kind):
     assert np.all(it["res"] < 1e-8)
 
 
+@pytest.mark.parametrize("kind", ["ras", "sas", "as"])
+def test_right_preconditioned_gmres_reaches_qr_solution(small2d, kind):
+    prob, ref = small2d
+    it = solve.iterative(prob, ref["sys"], "full", kind, "gmres_right", tol=1e-12, maxiter=2000)
+    err = np.linalg.norm(it["W"] - ref["W"]) / np.linalg.norm(ref["W"])
+    assert err < 1e-5
+    assert np.all(it["res"] < 1e-8)
+
+
+def test_right_preconditioned_gmres_residual_is_the_true_one_and_monotone(small2d):
+    """Right preconditioning minimises ||b - A x|| over the Krylov space of A M:
+    within one cycle the recorded residuals never increase, and the last one
+    equals the recomputed true residual of the returned x."""
+    prob, ref = small2d
+    from oracle import blocksparse as bs, krylov as kr, schwarz as sw
+    bh = bs.BlockH(ref["sys"])
+    M = sw.schwarz_blocks(bh, sw.stencil(prob, "face"), kind="ras", local="chol")
+    b = bh.rmatvec(ref["sys"].Fs)[:, 0]
+    x, its, hist = kr.gmres(bh.normal, M.apply, b, restart=400, tol=1e-6, maxiter=400, side="right")
+    assert 1 < its < 400                    # one cycle, stopped by the tolerance
+    assert np.all(np.diff(hist) <= 0.0)
+    true = np.linalg.norm(b - bh.normal(x.reshape(-1, 1)).ravel()) / np.linalg.norm(b)
+    assert true <= 1e-6
+    assert abs(true - hist[-1]) <= 1e-3 * hist[-1]
+
+
 def test_ex1_replica_statistics_match_paper_order_of_magnitude():
     """Paper Table 1a/1b (4x4 subdomains, m=16, delta=2, 40x40 points, no PCA):
     AS-CG 8 iterations, AS-GMRES 13 iterations, e_L2 6.44e-3, averaged over 10 draws.
