@@ -1,0 +1,212 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration the benchmark uses (GPU).
+
+Outputs the oracle computes one by one are sampled (rows of H at chosen
+points); the rest is checked through properties that hold at any size: equal
+PCA truncation counts, the spectrum and subspace bounds of the eigen-PCA, and
+the normal residual ||H^T (F - H W)|| / ||H^T F|| of the GPU solution
+evaluated by the oracle's own operator in the GPU's PCA basis (which pins the
+rows, the products and the solve together).  The adjoint is checked by central
+differences of the probe misfit on random directions.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import assemble as oasm  # noqa: E402
+from oracle import blocksparse as obs  # noqa: E402
+from oracle import solve as osolve  # noqa: E402
+from paper_2412_19207_amd import binding  # noqa: E402
+from paper_2412_19207_amd import workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+EPS = np.finfo(float).eps
+_cache = {}
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _prob(name):
+    if name not in _cache:
+        _cache[name] = wl.make(name)
+    return _cache[name]
+
+
+def _oracle_pca(name):
+    key = name + ":oracle"
+    if key not in _cache:
+        prob = _prob(name)
+        _cache[key] = oasm.assemble(prob, "rel_eig", prob.meta["pca_tol"])
+    return _cache[key]
+
+
+def _gpu_basis(s, prob, p):
+    """The GPU's PCA basis as a list of (m_j, p_j) arrays."""
+    _, V, eig = s.arrays()
+    V = V.cpu().numpy()
+    out, off = [], 0
+    for m, pj in zip(prob.m, p):
+        out.append(V[off:off + int(m) * int(pj)].reshape(int(m), int(pj)))
+        off += int(m) * int(pj)
+    return out, eig.cpu().numpy()
+
+
+def _solver(prob, precision):
+    meta = prob.meta
+    return binding.Solver(prob, device=DEV, precision=precision, stencil=meta["stencil"],
+                          precond=meta["precond"])
+
+
+def _check_pca(prob, sysm, p, Vg, eig):
+    assert np.array_equal(p, sysm.p)
+    off = 0
+    for j in range(prob.J):
+        m = int(prob.m[j])
+        lam = sysm.lam[j]
+        n = min(lam.size, m)
+        # eigenvalues of the FP64 Gram matrix agree within its rounding level
+        assert np.max(np.abs(eig[off:off + n] - lam[:n])) <= 10 * m * EPS * lam[0], j
+        Vj = Vg[j]
+        assert np.allclose(Vj.T @ Vj, np.eye(p[j]), atol=1e-10), j
+        gap = lam[p[j] - 1] - (lam[p[j]] if p[j] < lam.size else 0.0)
+        bound = 100 * m * EPS * lam[0] / max(gap, 1e-300)
+        sin_t = np.linalg.norm(sysm.V[j] - Vj @ (Vj.T @ sysm.V[j]), 2)
+        assert sin_t <= max(bound, 1e-10), (j, sin_t, bound)
+        off += m
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cfg2_full_size_bench_configuration(precision):
+    """2D Poisson, 8x8 subdomains, width 300 (the benchmark workload)."""
+    _need_gpu()
+    prob = _prob("cfg2")
+    meta = prob.meta
+    sysm = _oracle_pca("cfg2")
+    s = _solver(prob, precision)
+    p = s.pca(meta["pca_tol"], "rel_eig")
+    Vg, eig = _gpu_basis(s, prob, p)
+    _check_pca(prob, sysm, p, Vg, eig)
+    F = torch.as_tensor(prob.F, device=DEV)
+    W, info = s.solve(F, tol=meta["tol"], method=meta["method"])
+    assert info["max_rel_residual"] <= meta["tol"]
+    Wn = W.cpu().numpy()
+    # the oracle's operator in the GPU's basis: W solves its normal equations
+    key = "cfg2:gpu-basis"
+    if key not in _cache:
+        _cache[key] = oasm.assemble(prob, "rel_eig", meta["pca_tol"], V_force=Vg)
+    sysg = _cache[key]
+    res = osolve.normal_residual(obs.BlockH(sysg), Wn, sysg.Fs)
+    assert np.all(res <= meta["tol"] * 1.01 + 1e-9), res
+    # probe evaluation and raw-neuron coefficients
+    Xq = prob.probes
+    U = s.eval(torch.as_tensor(Xq, device=DEV), W).cpu().numpy()
+    Pm = oasm.probe_matrix(prob, sysg, Xq)
+    assert np.linalg.norm(U - Pm @ Wn) <= 1e-12 * np.linalg.norm(Pm @ Wn)
+    c = s.coeffs(W).cpu().numpy()
+    c_ref = sysg.coeffs(Wn)
+    assert np.linalg.norm(c - c_ref) <= 1e-12 * np.linalg.norm(c_ref)
+    s.close()
+
+
+def test_cfg3_full_size_batched_right_hand_sides():
+    """Multiscale 2D problem, 16x16 subdomains of uneven width, 32 right-hand
+    sides in one batched solve, mixed and FP64."""
+    _need_gpu()
+    prob = _prob("cfg3")
+    meta = prob.meta
+    sysm = _oracle_pca("cfg3")
+    F = torch.as_tensor(prob.F, device=DEV)
+    assert F.shape[1] == 32
+    sysg = None
+    for precision in ["mixed", "fp64"]:
+        s = _solver(prob, precision)
+        p = s.pca(meta["pca_tol"], "rel_eig")
+        if sysg is None:
+            Vg, eig = _gpu_basis(s, prob, p)
+            _check_pca(prob, sysm, p, Vg, eig)
+            sysg = oasm.assemble(prob, "rel_eig", meta["pca_tol"], V_force=Vg)
+        W, info = s.solve(F, tol=meta["tol"], method=meta["method"])
+        assert info["max_rel_residual"] <= meta["tol"]
+        res = osolve.normal_residual(obs.BlockH(sysg), W.cpu().numpy(), sysg.Fs)
+        assert res.shape == (32,)
+        assert np.all(res <= meta["tol"] * 1.01 + 1e-9), (precision, res)
+        s.close()
+
+
+def _sampled_subproblem(prob, n_int, n_bnd, seed):
+    rng = np.random.default_rng(seed)
+    si = np.sort(rng.choice(prob.N_I, n_int, replace=False))
+    nb = prob.N - prob.N_I
+    sb = np.sort(rng.choice(nb, min(n_bnd, nb), replace=False)) if nb else np.zeros(0, int)
+    rows = np.concatenate([si, prob.N_I + sb])
+    sub = dataclasses.replace(
+        prob, X_int=prob.X_int[si], a=prob.a[si], beta=prob.beta[si], c=prob.c[si],
+        X_bnd=prob.X_bnd[sb] if nb else prob.X_bnd, F=prob.F[rows],
+        Lfun=None if prob.Lfun is None else prob.Lfun[rows])
+    return sub, rows
+
+
+def test_cfg4_full_size_sampled_rows_and_convergence():
+    """Space-time advection-diffusion, 8x8x8 subdomains, width 400: rows of H at
+    sampled points against the oracle's (in the GPU's basis), then the solve."""
+    _need_gpu()
+    prob = _prob("cfg4")
+    meta = prob.meta
+    s = _solver(prob, meta["precision"])
+    p = s.pca(meta["pca_tol"], "rel_eig")
+    Vg, _ = _gpu_basis(s, prob, p)
+    sub, rows = _sampled_subproblem(prob, 500, 100, seed=11)
+    sysg = oasm.assemble(sub, "rel_eig", meta["pca_tol"], V_force=Vg)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((int(s.info.P), 2))
+    y = s.matvec(torch.as_tensor(x, device=DEV)).cpu().numpy()[rows]
+    y_ref = obs.BlockH(sysg).matvec(x)
+    assert np.linalg.norm(y - y_ref) <= 1e-13 * np.linalg.norm(y_ref) * 10
+    F = torch.as_tensor(prob.F, device=DEV)
+    W, info = s.solve(F, tol=meta["tol"], method=meta["method"], restart=meta["restart"], maxiter=1000)
+    assert info.get("status", 0) == 0
+    assert info["max_rel_residual"] <= meta["tol"]
+    s.close()
+
+
+def test_cfg5_full_size_adjoint_central_differences():
+    """3D Poisson, 6x6x6 subdomains, width 500, 32^3 probes: the gradient of
+    L = ||u_h - u_obs||^2 (right-hand side column 0) with respect to f and g
+    from the library's adjoint, against central differences (h = 1e-6) on 20
+    random directions, all perturbed right-hand sides in one batched solve."""
+    _need_gpu()
+    prob = _prob("cfg5")
+    meta = prob.meta
+    s = _solver(prob, "fp64")
+    s.pca(meta["pca_tol"], "rel_eig")
+    Xq = torch.as_tensor(prob.probes, device=DEV)
+    u_obs = torch.as_tensor(prob.u_obs[:, None], device=DEV)
+    tol = 1e-12
+    fn = binding.RannDDSolve.make(s, Xq, tol=tol, maxiter=4000)
+    NI = prob.N_I
+    f = torch.as_tensor(prob.F[:NI, :1], device=DEV).clone().requires_grad_(True)
+    g = torch.as_tensor(prob.F[NI:, :1], device=DEV).clone().requires_grad_(True)
+    loss = ((fn(f, g) - u_obs) ** 2).sum()
+    loss.backward()
+    grad = torch.cat([f.grad, g.grad], 0).cpu().numpy()[:, 0]
+    rng = np.random.default_rng(4)
+    nd, h = 20, 1e-6
+    D = rng.standard_normal((prob.N, nd))
+    F0 = prob.F[:, :1]
+    Fb = np.concatenate([F0 + h * D, F0 - h * D], axis=1)
+    W, info = s.solve(torch.as_tensor(Fb, device=DEV), tol=tol, maxiter=4000)
+    assert info["max_rel_residual"] <= tol
+    U = s.eval(Xq, W)
+    L = ((U - u_obs) ** 2).sum(0).cpu().numpy()
+    fd = (L[:nd] - L[nd:]) / (2 * h)
+    ad = grad @ D
+    scale = np.maximum(np.abs(ad), 1e-12 * np.linalg.norm(grad) * np.linalg.norm(D, axis=0))
+    assert np.all(np.abs(fd - ad) <= 1e-6 * scale), np.max(np.abs(fd - ad) / scale)
+    s.close()
