@@ -34,7 +34,29 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # dense FP64 (matrix cores and vector ALUs)
 FP32_PEAK_TFLOPS = 157.3
 KERNELS = ["k_eig", "k_factor", "k_pca_gram", "k_feat_rows", "k_local_gram", "k_normal", "k_Hx",
-           "k_HTy_part", "k_local_apply"]
+           "k_HTy_part", "k_tile_apply", "k_slot_reduce"]
+# timers that cover several different kernels (not candidates for the roofline line)
+GROUPS = {"k_eig", "k_factor", "k_Hx"}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter measurement
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when there is none or the kernel's source changed since it was taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh).get(kernel)
+        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError, KeyError, TypeError, AttributeError):
+        return None
+    if sha != rec.get("sha256"):
+        return None
+    return rec["fetch_bytes_per_launch"] * rec["fetch_scale"] + rec["write_bytes_per_launch"] * rec["write_scale"]
 
 
 def parse():
@@ -47,7 +69,10 @@ def parse():
     ap.add_argument("--stencil", default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 32-RHS mixed/FP64 comparison")
     ap.add_argument("--quick", action="store_true", help="skip the side measurements")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 512 MiB (counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -91,10 +116,14 @@ def work_model(s, prob, k):
         "k_Hx": ("hbm", 8.0 * (nnz + P * k + N * k), "byte", HBM_PEAK_GBS),
         "k_HTy_part": ("hbm", 8.0 * (nnz + N * k + P * k), "byte", HBM_PEAK_GBS),
         # the stored local operators (q_i (q_i + 1) / 2 entries each: W_i in FP64,
-        # the factor Y_i in FP32) read once; gathered r, the column-sum slots
-        # (written and read) and the local results
-        "k_local_apply": ("hbm", f_bytes * float(np.sum(q * (q + 1) / 2.0))
-                          + 8.0 * (2.0 * float(np.sum(q)) + 2.0 * slots) * k, "byte", HBM_PEAK_GBS),
+        # the factor Y_i in FP32) read once, the gathered r, and the row/column
+        # sum slots written (both kinds for W, the column sums for Y)
+        "k_tile_apply": ("hbm", f_bytes * float(np.sum(q * (q + 1) / 2.0))
+                         + 8.0 * (float(np.sum(q)) + (1.0 if s.precision == "mixed" else 2.0) * slots) * k,
+                         "byte", HBM_PEAK_GBS),
+        # the slots read, the local results written
+        "k_slot_reduce": ("hbm", 8.0 * ((1.0 if s.precision == "mixed" else 2.0) * slots + float(np.sum(q))) * k,
+                          "byte", HBM_PEAK_GBS),
     }
 
 
@@ -150,17 +179,72 @@ def solve_only(inp, precision, stencil, tol, torch, reps=3):
     return stats
 
 
-def cpu_baseline(prob, tol, stencil):
+def cpu_baseline(prob, tol, stencil, min_seconds=10.0, max_reps=3):
     """The FP64 oracle on the same workload, on the host cores: assembly with PCA,
-    then block-sparse AS-PCG to the same tolerance."""
+    then block-sparse AS-PCG to the same tolerance, repeated until about
+    min_seconds of host work (at most max_reps solves)."""
     from oracle import assemble as oasm
     from oracle import solve as osolve
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([int(t.get("num_threads", 1)) for t in threadpool_info()] or [1])
+    except Exception:  # threadpoolctl missing: report the interpreter's view
+        threads = os.cpu_count()
+    reps, t_all, iters = 0, 0.0, 0
+    while reps < max_reps and (reps == 0 or t_all < min_seconds):
+        t0 = time.perf_counter()
+        sysm = oasm.assemble(prob, "rel_eig", prob.meta["pca_tol"])
+        it = osolve.iterative(prob, sysm, stencil, "as", "cg", tol=tol, maxiter=5000)
+        t_all += time.perf_counter() - t0
+        iters = int(it["iters"].max())
+        reps += 1
+    return dict(total_s=t_all / reps, reps=reps, iters=iters, threads=threads)
+
+
+def batched_comparison(torch, binding, wl, dev):
+    """Many right-hand sides in one solve, mixed against FP64, on the
+    multiscale workload with 32 batched right-hand sides (end-to-end time to
+    the tolerance and the solve alone), and the same right-hand sides solved
+    one at a time in FP64 for reference."""
+    prob = wl.make("cfg3")
+    meta = prob.meta
+    F = torch.as_tensor(prob.F, device=dev)
+    k = F.shape[1]
+    out = {"workload": prob.name, "rhs": int(k), "subdomains": [int(x) for x in prob.l],
+           "hidden_width": [int(prob.m.min()), int(prob.m.max())], "rows": int(prob.N),
+           "tol": meta["tol"], "stencil": meta["stencil"], "precond": meta["precond"]}
+    for precision in ["fp64", "mixed", "fp64", "mixed"]:  # first pair warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = binding.Solver(prob, precision=precision, stencil=meta["stencil"], precond=meta["precond"])
+        s.pca(meta["pca_tol"], "rel_eig")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        W, info = s.solve(F, tol=meta["tol"], maxiter=5000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        W, info = s.solve(F, tol=meta["tol"], maxiter=5000)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        e2e = (t2 - t0) * 1e3
+        out[precision] = {"time_to_tol_ms": {"end_to_end": e2e, "solve_only": (t3 - t2) * 1e3},
+                          "solves_per_s": k / (e2e / 1e3), "iterations": int(info["iterations"]),
+                          "max_rel_residual": float(info["max_rel_residual"])}
+        s.close()
+    # the same right-hand sides one at a time (FP64, preconditioner built once)
+    s = binding.Solver(prob, precision="fp64", stencil=meta["stencil"], precond=meta["precond"])
+    s.pca(meta["pca_tol"], "rel_eig")
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sysm = oasm.assemble(prob, "rel_eig", prob.meta["pca_tol"])
-    t1 = time.perf_counter()
-    it = osolve.iterative(prob, sysm, stencil, "as", "cg", tol=tol, maxiter=5000)
-    t2 = time.perf_counter()
-    return dict(total_s=t2 - t0, assemble_s=t1 - t0, solve_s=t2 - t1, iters=int(it["iters"].max()))
+    for q in range(k):
+        s.solve(F[:, q:q + 1], tol=meta["tol"], maxiter=5000)
+    torch.cuda.synchronize()
+    out["fp64_one_at_a_time_solve_ms"] = (time.perf_counter() - t0) * 1e3
+    s.close()
+    out["mixed_over_fp64_speedup"] = {
+        "end_to_end": out["fp64"]["time_to_tol_ms"]["end_to_end"] / out["mixed"]["time_to_tol_ms"]["end_to_end"],
+        "solve_only": out["fp64"]["time_to_tol_ms"]["solve_only"] / out["mixed"]["time_to_tol_ms"]["solve_only"]}
+    return out
 
 
 def main():
@@ -179,6 +263,15 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        n = (512 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 5}))
+        return
     prob = wl.make(args.workload)
     inp = Inputs(prob, torch, dev)
     k = prob.F.shape[1]
@@ -200,14 +293,14 @@ def main():
     tm = {}
     _, _, model = run_step(inp, "fp64", args.stencil, args.tol, torch, timings=tm, want_model=True)
     # dominant kernel over the timed region and its roofline position
-    dom = max(ktimes, key=lambda n: ktimes[n][0])
+    dom = max((n for n in ktimes if n not in GROUPS), key=lambda n: ktimes[n][0])
     tot_ms, launches = ktimes[dom]
     avg_s = tot_ms / max(launches, 1) / 1e3
     bound, work, wunit, peak = model[dom]
     achieved = work / avg_s / (1e9 if wunit == "byte" else 1e12)
     roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
                 "unit": "GB/s" if wunit == "byte" else "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "avg_launch_us": avg_s * 1e6, "launches": launches,
+                "traffic": measured_traffic(dom), "avg_launch_us": avg_s * 1e6, "launches": launches,
                 "algorithmic_work_per_launch": work}
     kernel_table = {}
     for name, (ms, cnt) in ktimes.items():
@@ -217,7 +310,9 @@ def main():
         av = ms / cnt / 1e3
         ach = w_ / av / (1e9 if u_ == "byte" else 1e12)
         kernel_table[name] = {"ms_per_step": ms / args.steps, "avg_us": av * 1e6, "bound": b_,
-                              "achieved": ach, "frac": ach / pk_}
+                              "achieved": ach, "frac": ach / pk_, "launches_per_step": cnt / args.steps}
+        if name in GROUPS:
+            kernel_table[name]["group_of_kernels"] = True
 
     out = {
         "metric": "time-to-1e-6 residual & solves/s, mixed-batched vs FP64 AS-CG; fwd+bwd ms",
@@ -256,12 +351,15 @@ def main():
             out["mixed"] = {"time_to_1e-6_ms": {"end_to_end": tmm["assemble_ms"] + tmm["pca_factor_ms"] + tmm["solve_ms"],
                                                 "solve_only": som["ms"]},
                             "iterations": int(mi["iterations"]), "phases_ms": tmm}
+        if not args.no_batched:
+            out["batched"] = batched_comparison(torch, binding, wl, dev)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(prob, args.tol, args.stencil)
         out["cpu_baseline"] = {"value": k / cb["total_s"], "unit": "solves/s",
-                               "cores": os.cpu_count(), "kind": "oracle",
-                               "sample": f"one full solve of the same workload (assembly with PCA + "
-                                         f"block-sparse AS-PCG to {args.tol:g}, {cb['iters']} iterations)",
+                               "cores": cb["threads"], "kind": "oracle",
+                               "sample": f"{cb['reps']} full solve(s) of the same workload (assembly "
+                                         f"with PCA + block-sparse AS-PCG to {args.tol:g}, "
+                                         f"{cb['iters']} iterations), averaged",
                                "seconds": cb["total_s"]}
     print(json.dumps(out))
 

@@ -214,7 +214,7 @@ RANN_API int rann_dd_get_blocks(const rann_dd_handle* h, int64_t* q);
  * the main kernels are bracketed by HIP events on the stream they run on;
  * rann_dd_ktime_enable(on) also clears the accumulated times.  Query by kernel
  * name ("k_eig", "k_factor", "k_pca_gram", "k_feat_rows", "k_normal",
- * "k_local_gram", "k_Hx", "k_HTy_part", "k_local_apply"): total milliseconds
+ * "k_local_gram", "k_Hx", "k_HTy_part", "k_tile_apply", "k_slot_reduce"): total milliseconds
  * and number of launches since the last enable.  Query synchronises on the
  * recorded events. */
 RANN_API int rann_dd_ktime_enable(int32_t on);

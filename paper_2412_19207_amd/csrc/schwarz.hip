@@ -461,11 +461,8 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
     const int64_t tot = h.ub_total * k;
     const unsigned rgrid = (unsigned)((tot + 255) / 256);
     const unsigned tgrid = (unsigned)h.n_tile_tasks;
-    KTimer kt_(h.stream, "k_local_apply");
-    if (tgrid == 0 || tot == 0) {
-        kt_.stop();
-        return RANN_OK;
-    }
+    if (tgrid == 0 || tot == 0) return RANN_OK;
+    KTimer kt_(h.stream, "k_tile_apply");
     for (int k0 = 0; k0 < k;) {
         const int rem = k - k0;
         const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
@@ -496,6 +493,8 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
         }
         k0 += kb;
     }
+    kt_.stop();
+    KTimer kr_(h.stream, "k_slot_reduce");
     if (h.precision == RANN_MIXED) {
         hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, 0, 1, 0,
                            h.d_ent_blk, h.d_ub_off, h.d_s_off, h.d_q, Rs, Cs, ub);
@@ -506,7 +505,7 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
 #undef RDD_TA_KB
 #undef RDD_TR
 #undef RDD_TA
-    kt_.stop();
+    kr_.stop();
     RDD_HIP(hipGetLastError());
     return RANN_OK;
 }
