@@ -248,6 +248,7 @@ void release_gram(Handle& h);
 constexpr int kSlabRows = 16;       // slab rows per product workgroup
 // s = N x (N = H^T H from the slabs); with part != null also per-workgroup
 // partials of <x, s> at part[wg * k + t] (n_slab_tasks workgroups)
+// s = N x; with part, also the per-workgroup partials of <x, s>
 int launch_normal(Handle& h, const double* x, int k, double* s, double* part);
 
 int launch_Hx(Handle& h, const double* x, int k, double* y, bool scale_bnd);

@@ -77,67 +77,6 @@ __global__ void __launch_bounds__(256) k_dot_fin(int k, int nb, const double* __
     }
 }
 
-// ------------------------------------------------------------------ CG pieces
-// state per RHS: rho, active flag, iteration count; alpha from <p,s>
-__global__ void k_cg_alpha(int k, const double* __restrict__ pS, const double* __restrict__ rho,
-                           const int32_t* __restrict__ active, double* __restrict__ alpha,
-                           int32_t* __restrict__ flags) {
-    int t = threadIdx.x;
-    if (t >= k) return;
-    double a = 0.0;
-    if (active[t]) {
-        if (!(pS[t] > 0.0)) {
-            flags[0] = 1;  // breakdown
-        } else {
-            a = rho[t] / pS[t];
-        }
-        if (!isfinite(pS[t])) flags[1] = 1;
-    }
-    alpha[t] = a;
-}
-
-__global__ void k_cg_xr(int64_t P, int k, const double* __restrict__ alpha,
-                        const double* __restrict__ p, const double* __restrict__ s,
-                        double* __restrict__ x, double* __restrict__ r) {
-    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= P * k) return;
-    const double a = alpha[idx % k];
-    x[idx] = fma(a, p[idx], x[idx]);
-    r[idx] = fma(-a, s[idx], r[idx]);
-}
-
-// beta, rho update and convergence of the recurrence residual; `upd` marks the
-// right-hand sides whose search direction is advanced this iteration, so that a
-// right-hand side deactivated here can later resume the same recurrence
-__global__ void k_cg_beta(int k, const double* __restrict__ rz, const double* __restrict__ rr,
-                          const double* __restrict__ bnorm2, const double* __restrict__ tol2,
-                          double* __restrict__ rho, double* __restrict__ beta,
-                          int32_t* __restrict__ active, int32_t* __restrict__ upd,
-                          int32_t* __restrict__ iters, double* __restrict__ rres) {
-    int t = threadIdx.x;
-    if (t >= k) return;
-    double b = 0.0;
-    int u = 0;
-    if (active[t]) {
-        iters[t] += 1;
-        rres[t] = sqrt(rr[t] / bnorm2[t]);
-        b = rz[t] / rho[t];
-        rho[t] = rz[t];
-        u = 1;
-        if (rr[t] <= tol2[t] * bnorm2[t]) active[t] = 0;
-    }
-    beta[t] = b;
-    upd[t] = u;
-}
-
-__global__ void k_cg_p(int64_t P, int k, const double* __restrict__ beta, const int32_t* __restrict__ upd,
-                       const double* __restrict__ z, double* __restrict__ p) {
-    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= P * k) return;
-    const int t = (int)(idx % k);
-    if (upd[t]) p[idx] = fma(beta[t], p[idx], z[idx]);
-}
-
 __global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
                       double* __restrict__ c) {
     int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -416,12 +355,20 @@ __global__ void k_coeffs_T(int64_t P, int k, const int32_t* __restrict__ col_sub
 }
 
 // ------------------------------------------------------------------ fused CG pieces
-// Producers of dot products write per-workgroup partial sums (kRed workgroups,
-// grid-stride, stride a multiple of k so every thread keeps one right-hand
-// side); consumers sum the partials in a fixed order.
-constexpr int kRed = 120;
+// The element-wise kernels run red_grid(P k) workgroups over a grid stride that
+// is a multiple of k, so every thread keeps one right-hand side.  Producers of
+// dot products write per-workgroup partial sums; each consumer workgroup adds
+// them itself in a fixed order (no second launch, no cross-workgroup sync).
 
-__device__ inline int64_t rhs_stride(int k) { return ((int64_t)kRed * 256 / k) * k; }
+constexpr int kRedMax = 240;
+// workgroups of an element-wise kernel over n entries: about 4 entries per
+// thread, at most kRedMax (each consumer adds every partial)
+inline int red_grid(int64_t n) {
+    const int64_t g = (n + 1023) / 1024;
+    return (int)(g < 32 ? 32 : g > kRedMax ? kRedMax : g);
+}
+
+__device__ inline int64_t rhs_stride(int k) { return ((int64_t)gridDim.x * 256 / k) * k; }
 
 // Per-workgroup partial sums by right-hand side, fixed-order tree.  The grid
 // stride is a multiple of k, so thread x of block b always handles RHS
@@ -462,14 +409,30 @@ __device__ void block_partial_by_rhs(double val, int k, double* sh, double* out)
     __syncthreads();
 }
 
-// res[t] = sum over the nparts partials (fixed-order tree), for t < k
+// res[t] = sum over the nparts partials, for t < k.  The 256 / k threads of
+// each t read 8 partials at a time (independent loads in flight) into 8
+// accumulators; accumulators and threads meet in a fixed-order tree.
 __device__ void sum_partials(const double* part, int nparts, int k, double* res, double* sh) {
     const int per = 256 / k;
     const int t = threadIdx.x % k, ro = threadIdx.x / k;
-    double acc = 0.0;
-    if (ro < per)
-        for (int b = ro; b < nparts; b += per) acc += part[b * k + t];
-    sh[threadIdx.x] = (ro < per) ? acc : 0.0;
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    if (ro < per) {
+        int b = ro;
+        for (; b + 7 * per < nparts; b += 8 * per) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u * per) * k + t];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += v[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (b + u * per < nparts) acc[u] += part[(int64_t)(b + u * per) * k + t];
+    }
+    const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    sh[threadIdx.x] = (ro < per) ? a : 0.0;
     __syncthreads();
     for (int st = 1; st < per; st <<= 1) {
         if (ro < per && (ro % (2 * st)) == 0 && ro + st < per) sh[threadIdx.x] += sh[threadIdx.x + st * k];
@@ -479,34 +442,15 @@ __device__ void sum_partials(const double* part, int nparts, int k, double* res,
     __syncthreads();
 }
 
-// s = H^T y from the chunk partials (column g's partials start at pbase[g]
-// and repeat every pstride[g] columns, nch[g] of them), and partials of <p, s>
-__global__ void __launch_bounds__(256) k_nrm_reduce_dot(int64_t P, int k, const int64_t* __restrict__ pbase,
-                                                        const int32_t* __restrict__ pstride,
-                                                        const int32_t* __restrict__ nch,
-                                                        const double* __restrict__ part,
-                                                        const double* __restrict__ pv,
-                                                        double* __restrict__ s_out,
-                                                        double* __restrict__ partA) {
-    __shared__ double sh[256];
-    const int64_t stride = rhs_stride(k);
-    const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
-    double acc = 0.0;
-    if (i0 < stride) {
-        for (int64_t idx = i0; idx < P * k; idx += stride) {
-            const int64_t g = idx / k;
-            const int t = (int)(idx % k);
-            const int64_t b = pbase[g];
-            const int64_t ps = pstride[g];
-            const int nc = nch[g];
-            double sv = 0.0;
-            for (int q = 0; q < nc; ++q) sv += part[(b + q * ps) * k + t];
-            s_out[idx] = sv;
-            acc = fma(pv[idx], sv, acc);
-        }
+// Element-wise loop over idx = i0, i0 + stride, ... < n, four entries per
+// round so that their loads are in flight together.
+#define RDD_EW_LOOP(i0, stride, n, BODY)                                               \
+    for (int64_t base_ = (i0); base_ < (n); base_ += 4 * (stride)) {                   \
+        _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {                             \
+            const int64_t idx = base_ + u_ * (stride);                                 \
+            if (idx < (n)) { BODY }                                                    \
+        }                                                                              \
     }
-    block_partial_by_rhs(acc, k, sh, partA);
-}
 
 // alpha = rho / <p, s> (from nA partials); x += alpha p; r -= alpha s; partials of <r, r>
 __global__ void __launch_bounds__(256) k_cg_xr2(int64_t P, int k, int nA, const double* __restrict__ partA,
@@ -536,15 +480,16 @@ __global__ void __launch_bounds__(256) k_cg_xr2(int64_t P, int k, int nA, const 
     __syncthreads();
     const int64_t stride = rhs_stride(k);
     const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
+    const int64_t n = P * k;
     double acc = 0.0;
     if (i0 < stride) {
         const double a = al[i0 % k];
-        for (int64_t idx = i0; idx < P * k; idx += stride) {
+        RDD_EW_LOOP(i0, stride, n, {
             x[idx] = fma(a, p[idx], x[idx]);
             const double rv = fma(-a, s[idx], r[idx]);
             r[idx] = rv;
             acc = fma(rv, rv, acc);
-        }
+        })
     }
     block_partial_by_rhs(acc, k, sh, partB);
 }
@@ -561,9 +506,10 @@ __global__ void __launch_bounds__(256) k_gather_dot(int64_t P, int k, int identi
     __shared__ double sh[256];
     const int64_t stride = rhs_stride(k);
     const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
+    const int64_t n = P * k;
     double acc = 0.0;
     if (i0 < stride) {
-        for (int64_t idx = i0; idx < P * k; idx += stride) {
+        RDD_EW_LOOP(i0, stride, n, {
             double zv;
             if (identity) {
                 zv = r[idx];
@@ -575,14 +521,14 @@ __global__ void __launch_bounds__(256) k_gather_dot(int64_t P, int k, int identi
             }
             z[idx] = zv;
             acc = fma(r[idx], zv, acc);
-        }
+        })
     }
     block_partial_by_rhs(acc, k, sh, partC);
 }
 
 // beta = <r,z> / rho, rho and activity update (workgroup 0 writes the state of
 // the next iteration into the other buffer), p = z + beta p
-__global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, const double* __restrict__ partB,
+__global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, int nB, const double* __restrict__ partB,
                                                const double* __restrict__ partC,
                                                const double* __restrict__ bn2,
                                                const double* __restrict__ tol2,
@@ -595,8 +541,8 @@ __global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, const double* _
     __shared__ double sh[256];
     __shared__ double rr[256];
     __shared__ double rz[256];
-    sum_partials(partB, kRed, k, rr, sh);
-    sum_partials(partC, kRed, k, rz, sh);
+    sum_partials(partB, nB, k, rr, sh);
+    sum_partials(partC, nB, k, rz, sh);
     if (threadIdx.x < k) {
         const int t = threadIdx.x;
         const int act = active_in[t];
@@ -614,14 +560,17 @@ __global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, const double* _
     __syncthreads();
     const int64_t stride = rhs_stride(k);
     const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
+    const int64_t n = P * k;
     if (i0 < stride) {
         const int t = (int)(i0 % k);
         if (active_in[t]) {
             const double b = rz[t];
-            for (int64_t idx = i0; idx < P * k; idx += stride) p[idx] = fma(b, p[idx], z[idx]);
+            RDD_EW_LOOP(i0, stride, n, { p[idx] = fma(b, p[idx], z[idx]); })
         }
     }
 }
+
+#undef RDD_EW_LOOP
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
@@ -755,7 +704,8 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
                    std::vector<double>& res_out, int* status) {
     const size_t P = (size_t)h.P, N = (size_t)h.N;
     const size_t need = P * k * 4 + N * k + (size_t)h.part_total * k + (size_t)(2 * h.ub_total + 2 * h.slot_total) * k +
-                        (size_t)kDotBlocks * k + 3 * (size_t)kRed * k + (size_t)h.n_slab_tasks * k + 24 * (size_t)k + 2048;
+                        (size_t)kDotBlocks * k + 2 * (size_t)kRedMax * k + (size_t)h.n_slab_tasks * k + 24 * (size_t)k +
+                        2048;
     RDD_TRY(ensure_ws(h, need * sizeof(double)));
     Scratch sc{static_cast<double*>(h.ws), 0};
     double* r = sc.take(P * k);
@@ -776,9 +726,9 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     double* rres = sc.take(k);
     double* tol2v = sc.take(k);
     double* rhoB = sc.take(2 * (size_t)k);       // rho, double-buffered
-    double* partA = sc.take((size_t)std::max<int64_t>(kRed, h.n_slab_tasks) * k);
-    double* partB = sc.take((size_t)kRed * k);
-    double* partC = sc.take((size_t)kRed * k);
+    double* partA = sc.take((size_t)std::max<int64_t>(1, h.n_slab_tasks) * k);
+    double* partB = sc.take((size_t)kRedMax * k);
+    double* partC = sc.take((size_t)kRedMax * k);
     int32_t* activeB = reinterpret_cast<int32_t*>(sc.take(2 * (size_t)k));  // activity, double-buffered
     int32_t* iters = reinterpret_cast<int32_t*>(sc.take(k));
     int32_t* flags = reinterpret_cast<int32_t*>(sc.take(4));
@@ -786,6 +736,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     int par = 0;
     int32_t* active = activeB;  // current buffer, follows par
     const int64_t Pk = (int64_t)P * k;
+    const unsigned rgrid = (unsigned)red_grid(Pk);  // workgroups of the element-wise kernels
 
     RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, h.stream));
     RDD_HIP(hipMemsetAsync(iters, 0, sizeof(int32_t) * k, h.stream));
@@ -832,15 +783,15 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
             int32_t* act_out = activeB + (size_t)(par ^ 1) * k;
             // s = H^T H p (assembled normal matrix) and partials of <p, s>
             RDD_TRY(launch_normal(h, p, k, s, partA));
-            hipLaunchKernelGGL(k_cg_xr2, dim3(kRed), dim3(256), 0, h.stream, (int64_t)P, k,
+            hipLaunchKernelGGL(k_cg_xr2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k,
                                (int)h.n_slab_tasks, partA, rho_in, act_in, p, s, W, r, partB, flags);
-            // z = M^{-1} r and <r, z>
+            // z = M^{-1} r and partials of <r, z>
             const int ident = (h.precond == RANN_PRECOND_NONE) ? 1 : 0;
             if (!ident) RDD_TRY(launch_precond_local(h, r, k, ub));
-            hipLaunchKernelGGL(k_gather_dot, dim3(kRed), dim3(256), 0, h.stream, (int64_t)P, k, ident,
+            hipLaunchKernelGGL(k_gather_dot, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, ident,
                                h.d_gat_off, h.d_gat, h.d_gat_w, ub, r, z, partC);
-            hipLaunchKernelGGL(k_cg_p2, dim3(kRed), dim3(256), 0, h.stream, (int64_t)P, k, partB, partC, bn2,
-                               tol2v, rho_in, rho_out, act_in, act_out, iters, rres, z, p);
+            hipLaunchKernelGGL(k_cg_p2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, (int)rgrid, partB,
+                               partC, bn2, tol2v, rho_in, rho_out, act_in, act_out, iters, rres, z, p);
             par ^= 1;
             active = activeB + (size_t)par * k;
         }

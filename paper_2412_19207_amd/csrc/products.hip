@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "common.h"
+#include "mfma.h"
 
 namespace rdd {
 
@@ -221,6 +222,85 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
     }
 }
 
+// Batched right-hand sides (KC = 16 or 32): the 16 slab rows of a task times
+// x (Q x KC) on the FP64 matrix cores.  Wave w takes the 64-column sweeps w,
+// w + 4, ...; lane l = 16 g + lr supplies row r0 + lr at columns c0 + 16 g + s
+// (A operand, K index 16 g + s at step s) and the x rows of the same columns
+// (B operand, read straight from global memory: within the task each x row
+// feeds one wave only).  The 4 waves' sums meet in LDS.
+template <int KC>
+__global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks,
+                                                  const int32_t* __restrict__ p,
+                                                  const int64_t* __restrict__ col_off,
+                                                  const int64_t* __restrict__ N_off,
+                                                  const int64_t* __restrict__ N_coff,
+                                                  const int32_t* __restrict__ N_cols,
+                                                  const double* __restrict__ N,
+                                                  const double* __restrict__ x, int k, int k0,
+                                                  double* __restrict__ s, double* __restrict__ part) {
+    constexpr int NB = KC / 16;
+    static_assert(kSlabRows == 16, "one 16-row MFMA block per task");
+    __shared__ double red[4][16][KC + 1];
+    __shared__ double dsh[256];
+    const int2 tk = tasks[blockIdx.x];
+    const int j = tk.x, r0 = tk.y;
+    const int pj = p[j];
+    const int64_t Q = N_coff[j + 1] - N_coff[j];
+    const int32_t* cols = N_cols + N_coff[j];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const bool row_ok = r0 + lr < pj;
+    const double* Nr = N + N_off[j] + (int64_t)(row_ok ? r0 + lr : r0) * Q;
+    typedef Mfma<double>::acc_t acc_t;
+    acc_t acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[nb][e] = 0.0;
+    for (int64_t c0 = 64 * w; c0 < Q; c0 += 256) {
+        const int64_t cb = c0 + 16 * g;
+        double av[16];
+        int32_t ci[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const bool ok = cb + u < Q;
+            av[u] = (ok && row_ok) ? Nr[cb + u] : 0.0;
+            ci[u] = ok ? cols[cb + u] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const double bv = (ci[u] >= 0) ? x[(int64_t)ci[u] * k + k0 + 16 * nb + lr] : 0.0;
+                acc[nb] = Mfma<double>::mma(av[u], bv, acc[nb]);
+            }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[w][Mfma<double>::out_row(lane, e)][16 * nb + lr] = acc[nb][e];
+    __syncthreads();
+    const int t = threadIdx.x % KC;
+    double dotv = 0.0;
+    for (int rr = threadIdx.x / KC; rr < 16; rr += 256 / KC) {
+        const double v = (red[0][rr][t] + red[1][rr][t]) + (red[2][rr][t] + red[3][rr][t]);
+        if (r0 + rr < pj) {
+            const int64_t gi = (col_off[j] + r0 + rr) * k + k0 + t;
+            s[gi] = v;
+            dotv = fma(v, x[gi], dotv);
+        }
+    }
+    if (part) {
+        dsh[threadIdx.x] = dotv;
+        __syncthreads();
+        if (threadIdx.x < KC) {
+            double acc2 = 0.0;
+            for (int u = 0; u < 256 / KC; ++u) acc2 += dsh[threadIdx.x + KC * u];
+            part[(int64_t)blockIdx.x * k + k0 + threadIdx.x] = acc2;
+        }
+    }
+}
+
 }  // namespace
 
 // chunk tables
@@ -347,6 +427,21 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part) {
     KTimer kt_(h.stream, "k_normal");
     for (int k0 = 0; k0 < k;) {
         const int rem = k - k0;
+        if (rem >= 16) {  // matrix cores, 32 or 16 right-hand sides per launch
+            const int kc = rem >= 32 ? 32 : 16;
+            if (h.n_slab_tasks) {
+                if (kc == 32)
+                    hipLaunchKernelGGL((k_nrm_mfma<32>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,
+                                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff, h.d_N_cols,
+                                       h.d_N, x, k, k0, s, part);
+                else
+                    hipLaunchKernelGGL((k_nrm_mfma<16>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,
+                                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff, h.d_N_cols,
+                                       h.d_N, x, k, k0, s, part);
+            }
+            k0 += kc;
+            continue;
+        }
         const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
 #define RDD_NS(KBV)                                                                                 \
     hipLaunchKernelGGL((k_nrm_slab<KBV>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,   \

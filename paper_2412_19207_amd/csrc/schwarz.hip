@@ -21,6 +21,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "mfma.h"
 
 namespace rdd {
 
@@ -224,6 +225,172 @@ __global__ void __launch_bounds__(256) k_trirow_apply(const int2* __restrict__ t
         if (b < a)
 #pragma unroll
             for (int cc = 0; cc < 16; ++cc) v[cc] = vn[cc];
+    }
+}
+
+// Batched right-hand sides (KC = 16 or 32 of them per launch) on the matrix
+// cores.  MFMA 16x16x4 lane layout: lane l = 16 g + lr supplies A[lr][g] and
+// B[g][lr]; wave w owns the 16 output rows 16 w .. 16 w + 15 of the tile.  A
+// lane loads its row of the tile as one 16-element run (columns 16 g .. 16 g +
+// 15), which is the A operand of the row product directly (K index 16 g + s
+// at step s); the column product reads the tile transposed from LDS.
+
+// FP64 symmetric W: per tile (a, b) the row sums R = W_ab x_b and, off the
+// diagonal, the column sums C = W_ab^T x_a.
+template <int KC>
+__global__ void __launch_bounds__(256) k_tile_mfma64(const int4* __restrict__ tasks,
+                                                     const int64_t* __restrict__ t_off,
+                                                     const int64_t* __restrict__ qv,
+                                                     const int64_t* __restrict__ ub_off,
+                                                     const int64_t* __restrict__ s_off,
+                                                     const int32_t* __restrict__ blk_cols,
+                                                     const double* __restrict__ W,
+                                                     const double* __restrict__ r, int k, int k0,
+                                                     double* __restrict__ Rs, double* __restrict__ Cs) {
+    constexpr int NB = KC / 16;
+    __shared__ double xb[kT][KC + 1];
+    __shared__ double xa[kT][KC + 1];
+    __shared__ double ts[kT][kT + 1];
+    const int4 tk = tasks[blockIdx.x];
+    const int i = tk.x, a = tk.y, b = tk.z;
+    const int64_t q = qv[i];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const int64_t tile = (int64_t)a * (a + 1) / 2 + b;
+    double v[16];
+    load16(W + t_off[i] + tile * kTE + (16 * w + lr) * kT + 16 * g, v);
+    const bool do_c = (a != b);
+    const int32_t* cols = blk_cols + ub_off[i];
+    for (int e = threadIdx.x; e < kT * KC; e += 256) {
+        const int c = e / KC, t = e % KC;
+        const int64_t gb = (int64_t)b * kT + c;
+        xb[c][t] = (gb < q) ? r[(int64_t)cols[gb] * k + k0 + t] : 0.0;
+        if (do_c) {
+            const int64_t ga = (int64_t)a * kT + c;
+            xa[c][t] = (ga < q) ? r[(int64_t)cols[ga] * k + k0 + t] : 0.0;
+        }
+    }
+    if (do_c)
+#pragma unroll
+        for (int s = 0; s < 16; ++s) ts[16 * w + lr][16 * g + s] = v[s];
+    __syncthreads();
+    typedef Mfma<double>::acc_t acc_t;
+    acc_t R[NB], C[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) R[nb][e] = C[nb][e] = 0.0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) R[nb] = Mfma<double>::mma(v[s], xb[16 * g + s][16 * nb + lr], R[nb]);
+    if (do_c) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const double av = ts[16 * g + s][16 * w + lr];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) C[nb] = Mfma<double>::mma(av, xa[16 * g + s][16 * nb + lr], C[nb]);
+        }
+    }
+    const int64_t so = (s_off[i] + tile * kT) * k + k0;  // slot (a, b), entry 0
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = 16 * w + Mfma<double>::out_row(lane, e);
+            Rs[so + (int64_t)row * k + 16 * nb + lr] = R[nb][e];
+            if (do_c) Cs[so + (int64_t)row * k + 16 * nb + lr] = C[nb][e];
+        }
+}
+
+// FP32 triangular factor Y (mixed path), one (block, tile row a) per
+// workgroup, FP32 operands and accumulation: u_a = sum_b Y_ab x_b, then
+// C(a, b) = Y_ab^T u_a for b <= a (the tile row read a second time, from
+// cache).  The column sums are widened to FP64 in their slots.
+template <int KC>
+__global__ void __launch_bounds__(256) k_trirow_mfma32(const int2* __restrict__ tasks,
+                                                       const int64_t* __restrict__ t_off,
+                                                       const int64_t* __restrict__ qv,
+                                                       const int64_t* __restrict__ ub_off,
+                                                       const int64_t* __restrict__ s_off,
+                                                       const int32_t* __restrict__ blk_cols,
+                                                       const float* __restrict__ Y,
+                                                       const double* __restrict__ r, int k, int k0,
+                                                       double* __restrict__ Cs) {
+    constexpr int NB = KC / 16;
+    constexpr int kXC = 4;  // tiles of x staged per chunk
+    __shared__ float xs[kXC * kT][KC + 1];
+    __shared__ float ua[kT][KC + 1];
+    __shared__ float ts[2][kT][kT + 1];
+    const int2 tk = tasks[blockIdx.x];
+    const int i = tk.x, a = tk.y;
+    const int64_t q = qv[i];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const float* Ya = Y + t_off[i] + (int64_t)a * (a + 1) / 2 * kTE + (16 * w + lr) * kT + 16 * g;
+    const int32_t* cols = blk_cols + ub_off[i];
+    typedef Mfma<float>::acc_t acc_t;
+    acc_t U[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) U[nb][e] = 0.0f;
+    float v[16], vn[16];
+    load16(Ya, v);
+    for (int b = 0; b <= a; ++b) {
+        const int bb = b % kXC;
+        if (bb == 0) {
+            const int nb_t = (a + 1 - b < kXC) ? a + 1 - b : kXC;
+            __syncthreads();
+            for (int e = threadIdx.x; e < nb_t * kT * KC; e += 256) {
+                const int c = e / KC, t = e % KC;
+                const int64_t gc = (int64_t)b * kT + c;
+                xs[c][t] = (gc < q) ? (float)r[(int64_t)cols[gc] * k + k0 + t] : 0.0f;
+            }
+            __syncthreads();
+        }
+        if (b < a) load16(Ya + (int64_t)(b + 1) * kTE, vn);
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                U[nb] = Mfma<float>::mma(v[s], xs[bb * kT + 16 * g + s][16 * nb + lr], U[nb]);
+        if (b < a)
+#pragma unroll
+            for (int s = 0; s < 16; ++s) v[s] = vn[s];
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ua[16 * w + Mfma<float>::out_row(lane, e)][16 * nb + lr] = U[nb][e];
+    double* cla = Cs + (s_off[i] + (int64_t)a * (a + 1) / 2 * kT) * k + k0;  // slot (a, b) at cla + b kT k
+    load16(Ya, v);
+    for (int b = 0; b <= a; ++b) {
+        if (b < a) load16(Ya + (int64_t)(b + 1) * kTE, vn);
+        float (*tb)[kT + 1] = ts[b & 1];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) tb[16 * w + lr][16 * g + s] = v[s];
+        __syncthreads();  // also orders the u_a writes before their first read
+        acc_t C[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) C[nb][e] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const float av = tb[16 * g + s][16 * w + lr];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) C[nb] = Mfma<float>::mma(av, ua[16 * g + s][16 * nb + lr], C[nb]);
+        }
+        double* cb = cla + (int64_t)b * kT * k;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                cb[(int64_t)(16 * w + Mfma<float>::out_row(lane, e)) * k + 16 * nb + lr] = (double)C[nb][e];
+        if (b < a)
+#pragma unroll
+            for (int s = 0; s < 16; ++s) v[s] = vn[s];
     }
 }
 
@@ -465,6 +632,30 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
     KTimer kt_(h.stream, "k_tile_apply");
     for (int k0 = 0; k0 < k;) {
         const int rem = k - k0;
+        if (rem >= 16) {  // matrix cores, 32 or 16 right-hand sides per launch
+            const int kc = rem >= 32 ? 32 : 16;
+            if (h.precision == RANN_MIXED) {
+                if (kc == 32)
+                    hipLaunchKernelGGL((k_trirow_mfma32<32>), dim3((unsigned)h.n_row_tasks), dim3(256), 0,
+                                       h.stream, h.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off,
+                                       h.d_blk_cols, h.d_M32, r, k, k0, Cs);
+                else
+                    hipLaunchKernelGGL((k_trirow_mfma32<16>), dim3((unsigned)h.n_row_tasks), dim3(256), 0,
+                                       h.stream, h.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off,
+                                       h.d_blk_cols, h.d_M32, r, k, k0, Cs);
+            } else {
+                if (kc == 32)
+                    hipLaunchKernelGGL((k_tile_mfma64<32>), dim3(tgrid), dim3(256), 0, h.stream, h.d_tile_tasks,
+                                       h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols, h.d_M64, r, k, k0,
+                                       Rs, Cs);
+                else
+                    hipLaunchKernelGGL((k_tile_mfma64<16>), dim3(tgrid), dim3(256), 0, h.stream, h.d_tile_tasks,
+                                       h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols, h.d_M64, r, k, k0,
+                                       Rs, Cs);
+            }
+            k0 += kc;
+            continue;
+        }
         const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
 #define RDD_TA(T, M, KBV, WR, WC, XU, SY)                                                          \
     hipLaunchKernelGGL((k_tile_apply<T, KBV, WR, WC, XU, SY>), dim3(tgrid), dim3(256), 0, h.stream, \

@@ -167,6 +167,75 @@ def test_preconditioner_matches_oracle(case_small2d, stencil, kind):
     assert rel(z, M @ r) < max(1e-9, 1e-15 * kappa), (rel(z, M @ r), kappa)
 
 
+@pytest.fixture(scope="module")
+def case_small2d_k37():
+    _need_gpu()
+    prob = wl.small2d(k=37)
+    ref = osolve.reference(prob, "rel_eig", 1e-10)
+    return prob, ref
+
+
+@pytest.mark.parametrize("stencil", ["face", "full"])
+@pytest.mark.parametrize("kind", ["as", "ras", "sas"])
+@pytest.mark.parametrize("k", [16, 37])
+def test_preconditioner_batched_matches_oracle(case_small2d, stencil, kind, k):
+    """16 or more right-hand sides run the local solves on the matrix cores
+    (chunks of 32 and 16, the rest on the vector path): FP64 to the same bar."""
+    prob, ref = case_small2d
+    sysm, H = ref["sys"], ref["H"]
+    HtH = H.T @ H
+    M = osw.schwarz_dense(HtH, sysm.col_off, osw.stencil(prob, stencil), kind).dense()
+    s = binding.Solver(prob, device=DEV, stencil=stencil, precond=kind)
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal((sysm.P, k))
+    z = s.apply_precond(torch.as_tensor(r, device=DEV)).cpu().numpy()
+    kappa = np.linalg.cond(HtH)
+    ref_z = M @ r
+    for t in range(k):
+        e = rel(z[:, t], ref_z[:, t])
+        assert e < max(1e-9, 1e-15 * kappa), (t, e, kappa)
+
+
+def test_mixed_batched_apply_close_to_fp64(case_small2d):
+    """Mixed path against the FP64 oracle apply: one right-hand side at a time
+    (FP64 arithmetic on the FP32 factor) and 32 at once (FP32 operands and
+    accumulation on the matrix cores).  Both stay within 1e-5 relative, about
+    170 units of FP32 rounding (measured: 2e-8 and 1.3e-7)."""
+    prob, ref = case_small2d
+    sysm, H = ref["sys"], ref["H"]
+    HtH = H.T @ H
+    M = osw.schwarz_dense(HtH, sysm.col_off, osw.stencil(prob, "full"), "as").dense()
+    s = binding.Solver(prob, device=DEV, precision="mixed")
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal((sysm.P, 32))
+    zb = s.apply_precond(torch.as_tensor(r, device=DEV)).cpu().numpy()
+    z1 = np.stack([s.apply_precond(torch.as_tensor(r[:, t:t + 1], device=DEV)).cpu().numpy()[:, 0]
+                   for t in range(4)], 1)
+    ref_z = M @ r
+    e1 = max(rel(z1[:, t], ref_z[:, t]) for t in range(4))
+    eb = max(rel(zb[:, t], ref_z[:, t]) for t in range(32))
+    print(f"mixed apply vs FP64: one at a time {e1:.2e}, batched FP32 {eb:.2e}")
+    assert e1 < 1e-5 and eb < 1e-5, (e1, eb)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-8), ("mixed", 1e-6)])
+def test_batched_solve_matches_qr(case_small2d_k37, precision, bar):
+    """37 right-hand sides in one solve (matrix-core chunks of 32, then 4 + 1)."""
+    prob, ref = case_small2d_k37
+    sysm = ref["sys"]
+    s = binding.Solver(prob, device=DEV, precision=precision)
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-13, maxiter=5000)
+    assert info["status"] == 0
+    assert info["max_rel_residual"] <= 1e-13
+    Wn = W.cpu().numpy()
+    for t in range(Wn.shape[1]):
+        e = rel(Wn[:, t], ref["W"][:, t])
+        assert e <= bar, (t, e)
+
+
 # ------------------------------------------------------------------ a8/a9 solves
 @pytest.mark.parametrize("stencil", ["face", "full"])
 def test_fp64_solve_matches_qr(case_small2d, stencil):
