@@ -92,6 +92,8 @@ struct Handle {
     int64_t n_tile_tasks = 0;
     int2* d_row_tasks = nullptr;   // (block, tile row), longest first (triangular factor)
     int64_t n_row_tasks = 0;
+    int2* d_col_tasks = nullptr;   // (block, tile of the result that is used), longest first
+    int64_t n_col_tasks = 0;
     int64_t slot_total = 0;        // row- or column-sum slots per right-hand side (sum nt(nt+1)/2 * 64)
     int64_t* d_s_off = nullptr;    // J+1 slot offsets
     int32_t* d_ent_blk = nullptr;  // ub_total: block of each block entry

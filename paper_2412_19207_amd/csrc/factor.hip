@@ -33,59 +33,77 @@ namespace {
 
 constexpr int kFT = 256;  // threads
 
-// Stage one BK slice of a 64-wide operand into LDS (k-major).
+constexpr int kBK = 32;  // k-steps per LDS stage of the tile products
+
+// One kBK slice of a 64-wide operand, 8 elements per thread, held in
+// registers between its global load and its LDS store (so the next slice is
+// in flight while the current one is multiplied):
 //  kAlongRows: element (kk, m) = src[(r0 + k0 + kk) * ld + c0 + m]
 //  otherwise : element (kk, m) = src[(r0 + m) * ld + c0 + k0 + kk]
 template <class T, bool kAlongRows>
-__device__ __forceinline__ void stage(T (*S)[kTM + kPad], const T* src, int64_t ld, int64_t r0,
-                                      int64_t c0, int k0, int kvalid, int mvalid) {
+__device__ __forceinline__ void fetch(T* reg, const T* src, int64_t ld, int64_t r0, int64_t c0, int k0,
+                                      int kvalid, int mvalid) {
     const int t = threadIdx.x;
     if (kAlongRows) {
-        const int kk = t >> 4, m4 = (t & 15) * 4;
-        for (int e = 0; e < 4; ++e) {
-            const int m = m4 + e;
-            S[kk][m] = (k0 + kk < kvalid && m < mvalid) ? src[(r0 + k0 + kk) * ld + c0 + m] : T(0);
+        const int m4 = (t & 15) * 4;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int kk = (t >> 4) + 16 * j;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m4 + e;
+                reg[4 * j + e] = (k0 + kk < kvalid && m < mvalid) ? src[(r0 + k0 + kk) * ld + c0 + m] : T(0);
+            }
         }
     } else {
-        const int m = t >> 2, k4 = (t & 3) * 4;
-        for (int e = 0; e < 4; ++e) {
-            const int kk = k4 + e;
-            S[kk][m] = (k0 + kk < kvalid && m < mvalid) ? src[(r0 + m) * ld + c0 + k0 + kk] : T(0);
+        const int m = t >> 2, k8 = (t & 3) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int kk = k8 + e;
+            reg[e] = (k0 + kk < kvalid && m < mvalid) ? src[(r0 + m) * ld + c0 + k0 + kk] : T(0);
         }
     }
 }
 
-// acc = op(A) op(B) over K = kvalid (<= 64 per call chunk handled by the caller loop)
+template <class T, bool kAlongRows>
+__device__ __forceinline__ void put(T (*S)[kTM + kPad], const T* reg) {
+    const int t = threadIdx.x;
+    if (kAlongRows) {
+        const int m4 = (t & 15) * 4;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) S[(t >> 4) + 16 * j][m4 + e] = reg[4 * j + e];
+    } else {
+        const int m = t >> 2, k8 = (t & 3) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) S[k8 + e][m] = reg[e];
+    }
+}
+
+// acc += op(A) op(B) over K = kvalid, kBK k-steps per LDS stage (As, Bs hold
+// kBK rows); the next stage is loaded while the current one is multiplied
 template <class T, bool kAAlongRows, bool kBAlongRows>
 __device__ void tile_gemm(TileAcc<T>& acc, T (*As)[kTM + kPad], T (*Bs)[kTN + kPad], const T* A,
                           int64_t lda, int64_t ar0, int64_t ac0, int amv, const T* B, int64_t ldb,
                           int64_t br0, int64_t bc0, int bmv, int kvalid) {
-    for (int k0 = 0; k0 < kvalid; k0 += kTK) {
-        stage<T, kAAlongRows>(As, A, lda, ar0, ac0, k0, kvalid, amv);
-        stage<T, kBAlongRows>(Bs, B, ldb, br0, bc0, k0, kvalid, bmv);
-        __syncthreads();
-        acc.step(As, Bs);
-        __syncthreads();
+    T ra[8], rb[8];
+    if (kvalid > 0) {
+        fetch<T, kAAlongRows>(ra, A, lda, ar0, ac0, 0, kvalid, amv);
+        fetch<T, kBAlongRows>(rb, B, ldb, br0, bc0, 0, kvalid, bmv);
     }
-}
-
-// in-LDS inverse of a lower-triangular tile (n <= 64): one thread per column
-template <class T>
-__device__ void tri_inverse_lds(T (*L)[kTM + kPad], T (*X)[kTM + kPad], int n) {
-    const int c = threadIdx.x;
-    if (c < 64) {
-        for (int r = 0; r < 64; ++r) X[r][c] = T(0);
-        if (c < n) {
-            for (int r = c; r < n; ++r) {
-                T acc = (r == c) ? T(1) : T(0);
-                for (int k = c; k < r; ++k) acc -= L[r][k] * X[k][c];
-                X[r][c] = acc / L[r][r];
-            }
+    for (int k0 = 0; k0 < kvalid; k0 += kBK) {
+        put<T, kAAlongRows>(As, ra);
+        put<T, kBAlongRows>(Bs, rb);
+        __syncthreads();
+        if (k0 + kBK < kvalid) {
+            fetch<T, kAAlongRows>(ra, A, lda, ar0, ac0, k0 + kBK, kvalid, amv);
+            fetch<T, kBAlongRows>(rb, B, ldb, br0, bc0, k0 + kBK, kvalid, bmv);
         }
+        acc.template step_k<kBK>(As, Bs);
+        __syncthreads();
     }
-    __syncthreads();
 }
-
 
 struct TileTask {
     int32_t blk, a, b, pad;
@@ -129,60 +147,76 @@ __global__ void k_scale_shift(const int32_t* __restrict__ blks, const int64_t* _
     }
 }
 
-// L_ss = chol(W_ss) in LDS (written to W), X_ss = L_ss^{-1} (written to Xd)
-__global__ void __launch_bounds__(kFT) k_chol_diag(const TileTask* __restrict__ tasks,
-                                                   const int64_t* __restrict__ f_off,
-                                                   const int64_t* __restrict__ qv,
-                                                   const int64_t* __restrict__ xd_off,
-                                                   double* __restrict__ Wall,
-                                                   double* __restrict__ Xd,
-                                                   int32_t* __restrict__ bad) {
-    __shared__ double Ld[kTM][kTM + kPad];
-    __shared__ double Xs[kTM][kTM + kPad];
-    __shared__ int bad_s;
+// value of v in lane l (l uniform), through the scalar unit
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// L_ss = chol(W_ss) (written to W) and X_ss = L_ss^{-1} (written to Xd) for
+// one diagonal tile, in one wave, in registers: lane r keeps row r of the
+// tile.  Cholesky (right-looking): at column c the pivot and the scaled
+// column entries are read from their lanes and every lane updates its row.
+// Inverse (forward substitution on the identity, row-wise): at step c lane c
+// scales its row of X by 1 / L_cc and every lane r > c subtracts L_rc times
+// that row.  Beyond the block edge the tile is the identity during the
+// factorisation and zero in the outputs.
+__global__ void __launch_bounds__(64) k_chol_diag(const TileTask* __restrict__ tasks,
+                                                  const int64_t* __restrict__ f_off,
+                                                  const int64_t* __restrict__ qv,
+                                                  const int64_t* __restrict__ xd_off,
+                                                  double* __restrict__ Wall,
+                                                  double* __restrict__ Xd,
+                                                  int32_t* __restrict__ bad) {
     const TileTask tk = tasks[blockIdx.x];
     const int i = tk.blk, s = tk.a;
     if (bad[i]) return;
     const int64_t q = qv[i];
     double* W = Wall + f_off[i];
-    const int tid = threadIdx.x;
     const int64_t s0 = (int64_t)s * kTM;
     const int kb = tile_dim(q, s);
-    for (int e = tid; e < kTM * kTM; e += kFT) {
-        const int r = e / kTM, c = e % kTM;
-        Ld[r][c] = (r < kb && c < kb) ? W[(s0 + r) * q + s0 + c] : 0.0;
-    }
-    if (tid == 0) bad_s = 0;
-    __syncthreads();
-    for (int c = 0; c < kb; ++c) {
-        const double piv = Ld[c][c];
+    const int r = threadIdx.x;
+    double a[kTM];
+#pragma unroll
+    for (int c = 0; c < kTM; ++c)
+        a[c] = (r < kb && c < kb) ? W[(s0 + r) * q + s0 + c] : (r == c ? 1.0 : 0.0);
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < kTM; ++c) {
+        const double piv = read_lane(a[c], c);
         if (!(piv > 0.0) || !isfinite(piv)) {
-            if (tid == 0) bad_s = 1;
-            break;  // uniform: every thread read the same pivot
+            ok = false;  // uniform: every lane read the same pivot
+            break;
         }
         const double lc = sqrt(piv);
-        __syncthreads();
-        if (tid == 0) Ld[c][c] = lc;
-        for (int r = c + 1 + tid; r < kb; r += kFT) Ld[r][c] /= lc;
-        __syncthreads();
-        for (int e = tid; e < kTM * kTM; e += kFT) {
-            const int r = e / kTM, t = e % kTM;
-            if (t > c && t <= r && r < kb) Ld[r][t] -= Ld[r][c] * Ld[t][c];
-        }
-        __syncthreads();
+        const double l = (r == c) ? lc : (r > c ? a[c] / lc : 0.0);
+        a[c] = l;
+#pragma unroll
+        for (int t = c + 1; t < kTM; ++t) a[t] = fma(-l, read_lane(l, t), a[t]);
     }
-    __syncthreads();
-    if (bad_s) {
-        if (tid == 0) bad[i] = 1;
+    if (!ok) {
+        if (r == 0) bad[i] = 1;
         return;
     }
-    for (int e = tid; e < kTM * kTM; e += kFT) {
-        const int r = e / kTM, c = e % kTM;
-        if (r < kb && c <= r) W[(s0 + r) * q + s0 + c] = Ld[r][c];
+#pragma unroll
+    for (int c = 0; c < kTM; ++c)
+        if (r < kb && c <= r) W[(s0 + r) * q + s0 + c] = a[c];
+    double x[kTM];
+#pragma unroll
+    for (int t = 0; t < kTM; ++t) x[t] = (t == r) ? 1.0 : 0.0;
+#pragma unroll
+    for (int c = 0; c < kTM; ++c) {
+        const double inv = 1.0 / read_lane(a[c], c);
+#pragma unroll
+        for (int t = 0; t <= c; ++t) x[t] = (r == c) ? x[t] * inv : x[t];
+        const double lrc = (r > c) ? a[c] : 0.0;
+#pragma unroll
+        for (int t = 0; t <= c; ++t) x[t] = fma(-lrc, read_lane(x[t], c), x[t]);
     }
-    tri_inverse_lds<double>(Ld, Xs, kb);
     double* X = Xd + xd_off[i] + (int64_t)s * kTM * kTM;
-    for (int e = tid; e < kTM * kTM; e += kFT) X[e] = Xs[e / kTM][e % kTM];
+#pragma unroll
+    for (int t = 0; t < kTM; ++t) X[r * kTM + t] = (r < kb && t < kb) ? x[t] : 0.0;
 }
 
 // L_as = W_as X_ss^T  (a > s)
@@ -193,8 +227,8 @@ __global__ void __launch_bounds__(kFT) k_chol_panel(const TileTask* __restrict__
                                                     double* __restrict__ Wall,
                                                     const double* __restrict__ Xd,
                                                     const int32_t* __restrict__ bad) {
-    __shared__ double As[kTK][kTM + kPad];
-    __shared__ double Bs[kTK][kTN + kPad];
+    __shared__ double As[kBK][kTM + kPad];
+    __shared__ double Bs[kBK][kTN + kPad];
     const TileTask tk = tasks[blockIdx.x];
     const int i = tk.blk, a = tk.a, s = tk.b;
     if (bad[i]) return;
@@ -217,8 +251,8 @@ __global__ void __launch_bounds__(kFT) k_chol_trail(const TileTask* __restrict__
                                                     const int64_t* __restrict__ qv,
                                                     double* __restrict__ Wall,
                                                     const int32_t* __restrict__ bad) {
-    __shared__ double As[kTK][kTM + kPad];
-    __shared__ double Bs[kTK][kTN + kPad];
+    __shared__ double As[kBK][kTM + kPad];
+    __shared__ double Bs[kBK][kTN + kPad];
     const TileTask tk = tasks[blockIdx.x];
     const int i = tk.blk, a = tk.a, b = tk.b;
     if (bad[i]) return;
@@ -257,8 +291,8 @@ __global__ void __launch_bounds__(kFT) k_inv_off(const TileTask* __restrict__ ta
                                                  const int64_t* __restrict__ qv,
                                                  const double* __restrict__ Lall,
                                                  double* __restrict__ Xall) {
-    __shared__ double As[kTK][kTM + kPad];
-    __shared__ double Bs[kTK][kTN + kPad];
+    __shared__ double As[kBK][kTM + kPad];
+    __shared__ double Bs[kBK][kTN + kPad];
     const TileTask tk = tasks[blockIdx.x];
     const int i = tk.blk, a = tk.a, b = tk.b;
     const int64_t q = qv[i];
@@ -315,8 +349,8 @@ __global__ void __launch_bounds__(kFT) k_make_W(const TileTask* __restrict__ tas
                                                 const double* __restrict__ Xall,
                                                 const double* __restrict__ Dall,
                                                 double* __restrict__ Wt) {
-    __shared__ double As[kTK][kTM + kPad];
-    __shared__ double Bs[kTK][kTN + kPad];
+    __shared__ double As[kBK][kTM + kPad];
+    __shared__ double Bs[kBK][kTN + kPad];
     __shared__ double Cs[kTM][kTM + kPad];
     const TileTask tk = tasks[blockIdx.x];
     const int i = tk.blk, a = tk.a, b = tk.b;
@@ -432,7 +466,7 @@ int factor_tiles(Handle& h, double* A, double* W) {
         RDD_HIP(hipGetLastError());
         for (int s = 0; s < ntmax; ++s) {
             if (diag[s].cnt)
-                hipLaunchKernelGGL(k_chol_diag, dim3((unsigned)diag[s].cnt), dim3(kFT), 0, h.stream,
+                hipLaunchKernelGGL(k_chol_diag, dim3((unsigned)diag[s].cnt), dim3(64), 0, h.stream,
                                    d_tasks + diag[s].off, h.d_f_off, h.d_q, d_xd_off, W, d_Xd, d_bad);
             if (panel[s].cnt)
                 hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)panel[s].cnt), dim3(kFT), 0, h.stream,

@@ -284,7 +284,10 @@ __global__ void k_point_sum(int64_t n, int k, const int64_t* __restrict__ cover_
     U[idx] = s;
 }
 
-// transpose: dc_j[f] = sum over probe pairs of j of P0 tanh(z_f) dU[row]
+// transpose: dc_j[f] = sum over probe pairs of j of P0 tanh(z_f) dU[row].
+// Workgroup (j, 64-feature group, pair slice z): thread (f, lane pl) sums the
+// pairs pl, pl + 4, ... of the slice; the 4 lanes meet in LDS.  With several
+// slices the partial sums go to part[z] and k_eval_T_sum adds them in order.
 template <int KB>
 __global__ void __launch_bounds__(256) k_eval_T(Geo g, const int64_t* __restrict__ row_off,
                                                 const int32_t* __restrict__ rows,
@@ -294,25 +297,51 @@ __global__ void __launch_bounds__(256) k_eval_T(Geo g, const int64_t* __restrict
                                                 const double* __restrict__ Rf,
                                                 const double* __restrict__ bf,
                                                 const double* __restrict__ dU, int k, int k0,
-                                                double* __restrict__ dc) {
+                                                int64_t sum_m, double* __restrict__ dc) {
+    __shared__ double red[4][64];
     const int j = blockIdx.x;
-    for (int f = threadIdx.x; f < m[j]; f += blockDim.x) {
-        const int64_t gf = m_off[j] + f;
-        double R[kMaxDim];
-        for (int i = 0; i < kMaxDim; ++i) R[i] = Rf[gf * 4 + i];
-        const double b = bf[gf];
-        double acc[KB];
-        for (int t = 0; t < KB; ++t) acc[t] = 0.0;
-        for (int64_t pid = row_off[j]; pid < row_off[j + 1]; ++pid) {
+    const int f = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int pl = threadIdx.x >> 6;
+    const bool live = f < m[j];
+    const int64_t gf = m_off[j] + (live ? f : 0);
+    const int64_t p0 = row_off[j], np = row_off[j + 1] - p0;
+    const int64_t s_lo = p0 + np * blockIdx.z / gridDim.z, s_hi = p0 + np * (blockIdx.z + 1) / gridDim.z;
+    double R[kMaxDim];
+    for (int i = 0; i < kMaxDim; ++i) R[i] = Rf[gf * 4 + i];
+    const double b = bf[gf];
+    double acc[KB];
+#pragma unroll
+    for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+    if (live) {
+        for (int64_t pid = s_lo + pl; pid < s_hi; pid += 4) {
             const double* rr = rec + pid * kPairRec;
             double z = b;
             for (int i = 0; i < g.d; ++i) z = fma(R[i], rr[kRecX + i], z);
             const double w = rr[kRecP0] * tanh(z);
             const double* du = dU + (int64_t)rows[pid] * k + k0;
+#pragma unroll
             for (int t = 0; t < KB; ++t) acc[t] = fma(w, du[t], acc[t]);
         }
-        for (int t = 0; t < KB; ++t) dc[gf * k + k0 + t] = acc[t];
     }
+    double* out = dc + (int64_t)blockIdx.z * sum_m * k;
+#pragma unroll
+    for (int t = 0; t < KB; ++t) {
+        red[pl][threadIdx.x & 63] = acc[t];
+        __syncthreads();
+        if (pl == 0 && live)
+            out[gf * k + k0 + t] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                   (red[2][threadIdx.x] + red[3][threadIdx.x]);
+        __syncthreads();
+    }
+}
+
+// dc = sum over the nz pair slices of part[z], in slice order
+__global__ void k_eval_T_sum(int64_t n, int nz, const double* __restrict__ part, double* __restrict__ dc) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    double s = 0.0;
+    for (int z = 0; z < nz; ++z) s += part[(int64_t)z * n + idx];
+    dc[idx] = s;
 }
 
 // c_j = V_j W_j (raw-neuron coefficients) and its transpose
@@ -1184,12 +1213,20 @@ int eval_points(Handle& h, const double* Xq, int64_t M, const double* Lq, const 
         hipLaunchKernelGGL(k_point_sum, dim3(grid_for(M * k)), dim3(256), 0, h.stream, M, k,
                            ps.d_cover_off, ps.d_cover, val, U);
     } else if (rc == RANN_OK) {
-        // U holds dW (output), W holds dU (input) in the transposed call
-        for (int k0 = 0; k0 < k;) {
+        // U holds dW (output), W holds dU (input) in the transposed call.
+        // Pair slices per subdomain so that about 1024 workgroups run.
+        int max_m = 0;
+        for (int j = 0; j < h.geo.J; ++j) max_m = std::max(max_m, h.m[j]);
+        const int fgroups = (max_m + 63) / 64;
+        const int nz = std::max(1, std::min(16, 1024 / std::max(1, h.geo.J * fgroups)));
+        double* cpart = cf;
+        if (nz > 1) rc = dev_alloc(h, &cpart, (size_t)nz * h.sum_m * k);
+        for (int k0 = 0; rc == RANN_OK && k0 < k;) {
             int kb = kb_for(k - k0);
-#define RDD_ET(KBV)                                                                                 \
-    hipLaunchKernelGGL((k_eval_T<KBV>), dim3(h.geo.J), dim3(256), 0, h.stream, h.geo, ps.d_row_off, \
-                       ps.d_rows, ps.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, W, k, k0, cf)
+#define RDD_ET(KBV)                                                                                    \
+    hipLaunchKernelGGL((k_eval_T<KBV>), dim3(h.geo.J, fgroups, nz), dim3(256), 0, h.stream, h.geo,      \
+                       ps.d_row_off, ps.d_rows, ps.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, W, k, k0, \
+                       (int64_t)h.sum_m, cpart)
             switch (kb) {
                 case 32: RDD_ET(32); break;
                 case 16: RDD_ET(16); break;
@@ -1201,7 +1238,10 @@ int eval_points(Handle& h, const double* Xq, int64_t M, const double* Lq, const 
 #undef RDD_ET
             k0 += kb;
         }
-        rc = coeffs_raw(h, cf, k, U, true);
+        if (rc == RANN_OK && nz > 1)
+            hipLaunchKernelGGL(k_eval_T_sum, dim3(grid_for(h.sum_m * k)), dim3(256), 0, h.stream,
+                               (int64_t)h.sum_m * k, nz, cpart, cf);
+        if (rc == RANN_OK) rc = coeffs_raw(h, cf, k, U, true);
     }
     if (rc == RANN_OK) {
         hipError_t e = hipStreamSynchronize(h.stream);

@@ -62,6 +62,24 @@ struct TileAcc {
             c[1][1] = Mfma<T>::mma(a1, b1, c[1][1]);
         }
     }
+    // KS k-steps from LDS (As, Bs hold KS rows)
+    template <int KS>
+    __device__ __forceinline__ void step_k(const T (*As)[kTM + kPad], const T (*Bs)[kTN + kPad]) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int wm = wave >> 1, wn = wave & 1;
+        const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+        for (int kk = 0; kk < KS; kk += 4) {
+            T a0 = As[kk + lk][wm * 32 + lr];
+            T a1 = As[kk + lk][wm * 32 + 16 + lr];
+            T b0 = Bs[kk + lk][wn * 32 + lr];
+            T b1 = Bs[kk + lk][wn * 32 + 16 + lr];
+            c[0][0] = Mfma<T>::mma(a0, b0, c[0][0]);
+            c[0][1] = Mfma<T>::mma(a0, b1, c[0][1]);
+            c[1][0] = Mfma<T>::mma(a1, b0, c[1][0]);
+            c[1][1] = Mfma<T>::mma(a1, b1, c[1][1]);
+        }
+    }
     // visit every accumulator element with its tile-local (row, col)
     template <class F>
     __device__ __forceinline__ void each(F f) const {

@@ -230,98 +230,117 @@ __global__ void __launch_bounds__(256) k_trirow_apply(const int2* __restrict__ t
 
 // Batched right-hand sides (KC = 16 or 32 of them per launch) on the matrix
 // cores.  MFMA 16x16x4 lane layout: lane l = 16 g + lr supplies A[lr][g] and
-// B[g][lr]; wave w owns the 16 output rows 16 w .. 16 w + 15 of the tile.  A
-// lane loads its row of the tile as one 16-element run (columns 16 g .. 16 g +
+// B[g][lr]; wave w owns the 16 output rows 16 w .. 16 w + 15 of a tile.  A
+// lane loads its row of a tile as one 16-element run (columns 16 g .. 16 g +
 // 15), which is the A operand of the row product directly (K index 16 g + s
-// at step s); the column product reads the tile transposed from LDS.
+// at step s); products with a transposed tile read it from LDS.
+// Every workgroup owns a 64-entry piece of a block result and accumulates it
+// in its MFMA registers, so the results go straight to the block vector (no
+// slots, no reduction pass).
 
-// FP64 symmetric W: per tile (a, b) the row sums R = W_ab x_b and, off the
-// diagonal, the column sums C = W_ab^T x_a.
+// FP64 symmetric W, one (block, tile a) per workgroup: z_a = sum_b W_ab x_b
+// over the stored tiles (a, b), b <= a, and the transposes of the tiles
+// (b, a), b > a.  Every tile off the diagonal is read by two workgroups.  The
+// next tile and x segment are loaded while the current ones are used.
 template <int KC>
-__global__ void __launch_bounds__(256) k_tile_mfma64(const int4* __restrict__ tasks,
-                                                     const int64_t* __restrict__ t_off,
-                                                     const int64_t* __restrict__ qv,
-                                                     const int64_t* __restrict__ ub_off,
-                                                     const int64_t* __restrict__ s_off,
-                                                     const int32_t* __restrict__ blk_cols,
-                                                     const double* __restrict__ W,
-                                                     const double* __restrict__ r, int k, int k0,
-                                                     double* __restrict__ Rs, double* __restrict__ Cs) {
+__global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ tasks,
+                                                       const int64_t* __restrict__ t_off,
+                                                       const int64_t* __restrict__ qv,
+                                                       const int64_t* __restrict__ ub_off,
+                                                       const int32_t* __restrict__ blk_cols,
+                                                       const double* __restrict__ W,
+                                                       const double* __restrict__ r, int k, int k0,
+                                                       double* __restrict__ z) {
     constexpr int NB = KC / 16;
-    __shared__ double xb[kT][KC + 1];
-    __shared__ double xa[kT][KC + 1];
+    constexpr int XPT = kT * KC / 256;  // x values staged per thread
+    __shared__ double xs[kT][KC + 1];
     __shared__ double ts[kT][kT + 1];
-    const int4 tk = tasks[blockIdx.x];
-    const int i = tk.x, a = tk.y, b = tk.z;
+    const int2 tk = tasks[blockIdx.x];
+    const int i = tk.x, a = tk.y;
     const int64_t q = qv[i];
+    const int nt = (int)((q + kT - 1) / kT);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lr = lane & 15, g = lane >> 4;
-    const int64_t tile = (int64_t)a * (a + 1) / 2 + b;
-    double v[16];
-    load16(W + t_off[i] + tile * kTE + (16 * w + lr) * kT + 16 * g, v);
-    const bool do_c = (a != b);
+    const double* Wi = W + t_off[i] + (16 * w + lr) * kT + 16 * g;
     const int32_t* cols = blk_cols + ub_off[i];
-    for (int e = threadIdx.x; e < kT * KC; e += 256) {
-        const int c = e / KC, t = e % KC;
-        const int64_t gb = (int64_t)b * kT + c;
-        xb[c][t] = (gb < q) ? r[(int64_t)cols[gb] * k + k0 + t] : 0.0;
-        if (do_c) {
-            const int64_t ga = (int64_t)a * kT + c;
-            xa[c][t] = (ga < q) ? r[(int64_t)cols[ga] * k + k0 + t] : 0.0;
-        }
-    }
-    if (do_c)
+    auto tile_of = [&](int b) -> int64_t {
+        return (b <= a) ? (int64_t)a * (a + 1) / 2 + b : (int64_t)b * (b + 1) / 2 + a;
+    };
+    auto load_x = [&](int b, double* xr) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) ts[16 * w + lr][16 * g + s] = v[s];
-    __syncthreads();
+        for (int m = 0; m < XPT; ++m) {
+            const int e = threadIdx.x + 256 * m;
+            const int64_t gc = (int64_t)b * kT + e / KC;
+            xr[m] = (gc < q) ? r[(int64_t)cols[gc] * k + k0 + e % KC] : 0.0;
+        }
+    };
     typedef Mfma<double>::acc_t acc_t;
-    acc_t R[NB], C[NB];
+    acc_t Z[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) R[nb][e] = C[nb][e] = 0.0;
+        for (int e = 0; e < 4; ++e) Z[nb][e] = 0.0;
+    double v[16], xr[XPT];
+    load16(Wi + tile_of(0) * kTE, v);
+    load_x(0, xr);
+    for (int b = 0; b < nt; ++b) {
+        const bool tr = b > a;
+        __syncthreads();  // the previous step's reads of xs and ts are done
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) R[nb] = Mfma<double>::mma(v[s], xb[16 * g + s][16 * nb + lr], R[nb]);
-    if (do_c) {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const double av = ts[16 * g + s][16 * w + lr];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) C[nb] = Mfma<double>::mma(av, xa[16 * g + s][16 * nb + lr], C[nb]);
+        for (int m = 0; m < XPT; ++m) {
+            const int e = threadIdx.x + 256 * m;
+            xs[e / KC][e % KC] = xr[m];
         }
+        if (tr)
+#pragma unroll
+            for (int s = 0; s < 16; ++s) ts[16 * w + lr][16 * g + s] = v[s];
+        __syncthreads();
+        double vn[16];
+        if (b + 1 < nt) {
+            load16(Wi + tile_of(b + 1) * kTE, vn);
+            load_x(b + 1, xr);
+        }
+        if (!tr) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<double>::mma(v[s], xs[16 * g + s][16 * nb + lr], Z[nb]);
+        } else {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const double av = ts[16 * g + s][16 * w + lr];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<double>::mma(av, xs[16 * g + s][16 * nb + lr], Z[nb]);
+            }
+        }
+        if (b + 1 < nt)
+#pragma unroll
+            for (int s = 0; s < 16; ++s) v[s] = vn[s];
     }
-    const int64_t so = (s_off[i] + tile * kT) * k + k0;  // slot (a, b), entry 0
+    double* zi = z + ub_off[i] * k + k0;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int row = 16 * w + Mfma<double>::out_row(lane, e);
-            Rs[so + (int64_t)row * k + 16 * nb + lr] = R[nb][e];
-            if (do_c) Cs[so + (int64_t)row * k + 16 * nb + lr] = C[nb][e];
+            const int64_t ga = (int64_t)a * kT + 16 * w + Mfma<double>::out_row(lane, e);
+            if (ga < q) zi[ga * k + 16 * nb + lr] = Z[nb][e];
         }
 }
 
-// FP32 triangular factor Y (mixed path), one (block, tile row a) per
-// workgroup, FP32 operands and accumulation: u_a = sum_b Y_ab x_b, then
-// C(a, b) = Y_ab^T u_a for b <= a (the tile row read a second time, from
-// cache).  The column sums are widened to FP64 in their slots.
+// FP32 triangular factor Y (mixed path), first pass, one (block, tile row a)
+// per workgroup: u_a = sum_{b <= a} Y_ab x_b in FP32, stored as FP32.
 template <int KC>
-__global__ void __launch_bounds__(256) k_trirow_mfma32(const int2* __restrict__ tasks,
-                                                       const int64_t* __restrict__ t_off,
-                                                       const int64_t* __restrict__ qv,
-                                                       const int64_t* __restrict__ ub_off,
-                                                       const int64_t* __restrict__ s_off,
-                                                       const int32_t* __restrict__ blk_cols,
-                                                       const float* __restrict__ Y,
-                                                       const double* __restrict__ r, int k, int k0,
-                                                       double* __restrict__ Cs) {
+__global__ void __launch_bounds__(256) k_urow_mfma32(const int2* __restrict__ tasks,
+                                                     const int64_t* __restrict__ t_off,
+                                                     const int64_t* __restrict__ qv,
+                                                     const int64_t* __restrict__ ub_off,
+                                                     const int32_t* __restrict__ blk_cols,
+                                                     const float* __restrict__ Y,
+                                                     const double* __restrict__ r, int k, int k0,
+                                                     float* __restrict__ u) {
     constexpr int NB = KC / 16;
-    constexpr int kXC = 4;  // tiles of x staged per chunk
-    __shared__ float xs[kXC * kT][KC + 1];
-    __shared__ float ua[kT][KC + 1];
-    __shared__ float ts[2][kT][kT + 1];
+    constexpr int XPT = kT * KC / 256;
+    __shared__ float xs[2][kT][KC + 1];
     const int2 tk = tasks[blockIdx.x];
     const int i = tk.x, a = tk.y;
     const int64_t q = qv[i];
@@ -329,82 +348,140 @@ __global__ void __launch_bounds__(256) k_trirow_mfma32(const int2* __restrict__ 
     const int lr = lane & 15, g = lane >> 4;
     const float* Ya = Y + t_off[i] + (int64_t)a * (a + 1) / 2 * kTE + (16 * w + lr) * kT + 16 * g;
     const int32_t* cols = blk_cols + ub_off[i];
+    auto load_x = [&](int b, float* xr) {
+#pragma unroll
+        for (int m = 0; m < XPT; ++m) {
+            const int e = threadIdx.x + 256 * m;
+            const int64_t gc = (int64_t)b * kT + e / KC;
+            xr[m] = (gc < q) ? (float)r[(int64_t)cols[gc] * k + k0 + e % KC] : 0.0f;
+        }
+    };
     typedef Mfma<float>::acc_t acc_t;
     acc_t U[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) U[nb][e] = 0.0f;
-    float v[16], vn[16];
+    float v[16], xr[XPT];
     load16(Ya, v);
+    load_x(0, xr);
     for (int b = 0; b <= a; ++b) {
-        const int bb = b % kXC;
-        if (bb == 0) {
-            const int nb_t = (a + 1 - b < kXC) ? a + 1 - b : kXC;
-            __syncthreads();
-            for (int e = threadIdx.x; e < nb_t * kT * KC; e += 256) {
-                const int c = e / KC, t = e % KC;
-                const int64_t gc = (int64_t)b * kT + c;
-                xs[c][t] = (gc < q) ? (float)r[(int64_t)cols[gc] * k + k0 + t] : 0.0f;
-            }
-            __syncthreads();
+        float (*xb)[KC + 1] = xs[b & 1];
+#pragma unroll
+        for (int m = 0; m < XPT; ++m) {
+            const int e = threadIdx.x + 256 * m;
+            xb[e / KC][e % KC] = xr[m];
         }
-        if (b < a) load16(Ya + (int64_t)(b + 1) * kTE, vn);
+        __syncthreads();  // xs[b & 1] written; its previous reads (step b - 2) ended before step b - 1's barrier
+        float vn[16];
+        if (b < a) {
+            load16(Ya + (int64_t)(b + 1) * kTE, vn);
+            load_x(b + 1, xr);
+        }
 #pragma unroll
         for (int s = 0; s < 16; ++s)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                U[nb] = Mfma<float>::mma(v[s], xs[bb * kT + 16 * g + s][16 * nb + lr], U[nb]);
+            for (int nb = 0; nb < NB; ++nb) U[nb] = Mfma<float>::mma(v[s], xb[16 * g + s][16 * nb + lr], U[nb]);
         if (b < a)
 #pragma unroll
             for (int s = 0; s < 16; ++s) v[s] = vn[s];
     }
+    float* ui = u + ub_off[i] * k + k0;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ua[16 * w + Mfma<float>::out_row(lane, e)][16 * nb + lr] = U[nb][e];
-    double* cla = Cs + (s_off[i] + (int64_t)a * (a + 1) / 2 * kT) * k + k0;  // slot (a, b) at cla + b kT k
-    load16(Ya, v);
-    for (int b = 0; b <= a; ++b) {
-        if (b < a) load16(Ya + (int64_t)(b + 1) * kTE, vn);
-        float (*tb)[kT + 1] = ts[b & 1];
+        for (int e = 0; e < 4; ++e) {
+            const int64_t ga = (int64_t)a * kT + 16 * w + Mfma<float>::out_row(lane, e);
+            if (ga < q) ui[ga * k + 16 * nb + lr] = U[nb][e];
+        }
+}
+
+// Second pass, one (block, tile column c) per workgroup: z_c = sum_{a >= c}
+// Y_ac^T u_a (FP32 operands and accumulation), written as FP64.
+template <int KC>
+__global__ void __launch_bounds__(256) k_zcol_mfma32(const int2* __restrict__ tasks,
+                                                     const int64_t* __restrict__ t_off,
+                                                     const int64_t* __restrict__ qv,
+                                                     const int64_t* __restrict__ ub_off,
+                                                     const float* __restrict__ Y,
+                                                     const float* __restrict__ u, int k, int k0,
+                                                     double* __restrict__ z) {
+    constexpr int NB = KC / 16;
+    constexpr int XPT = kT * KC / 256;
+    __shared__ float us[kT][KC + 1];
+    __shared__ float ts[kT][kT + 1];
+    const int2 tk = tasks[blockIdx.x];
+    const int i = tk.x, c = tk.y;
+    const int64_t q = qv[i];
+    const int nt = (int)((q + kT - 1) / kT);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const float* Yi = Y + t_off[i] + (16 * w + lr) * kT + 16 * g;
+    const float* ui = u + ub_off[i] * k + k0;
+    auto load_u = [&](int a, float* ur) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) tb[16 * w + lr][16 * g + s] = v[s];
-        __syncthreads();  // also orders the u_a writes before their first read
-        acc_t C[NB];
+        for (int m = 0; m < XPT; ++m) {
+            const int e = threadIdx.x + 256 * m;
+            const int64_t ga = (int64_t)a * kT + e / KC;
+            ur[m] = (ga < q) ? ui[ga * k + e % KC] : 0.0f;
+        }
+    };
+    typedef Mfma<float>::acc_t acc_t;
+    acc_t Z[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) C[nb][e] = 0.0f;
+        for (int e = 0; e < 4; ++e) Z[nb][e] = 0.0f;
+    float v[16], ur[XPT];
+    load16(Yi + ((int64_t)c * (c + 1) / 2 + c) * kTE, v);
+    load_u(c, ur);
+    for (int a = c; a < nt; ++a) {
+        __syncthreads();  // the previous step's reads of us and ts are done
+#pragma unroll
+        for (int m = 0; m < XPT; ++m) {
+            const int e = threadIdx.x + 256 * m;
+            us[e / KC][e % KC] = ur[m];
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) ts[16 * w + lr][16 * g + s] = v[s];
+        __syncthreads();
+        float vn[16];
+        if (a + 1 < nt) {
+            load16(Yi + ((int64_t)(a + 1) * (a + 2) / 2 + c) * kTE, vn);
+            load_u(a + 1, ur);
+        }
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
-            const float av = tb[16 * g + s][16 * w + lr];
+            const float av = ts[16 * g + s][16 * w + lr];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) C[nb] = Mfma<float>::mma(av, ua[16 * g + s][16 * nb + lr], C[nb]);
+            for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<float>::mma(av, us[16 * g + s][16 * nb + lr], Z[nb]);
         }
-        double* cb = cla + (int64_t)b * kT * k;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                cb[(int64_t)(16 * w + Mfma<float>::out_row(lane, e)) * k + 16 * nb + lr] = (double)C[nb][e];
-        if (b < a)
+        if (a + 1 < nt)
 #pragma unroll
             for (int s = 0; s < 16; ++s) v[s] = vn[s];
     }
+    double* zi = z + ub_off[i] * k + k0;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t gcol = (int64_t)c * kT + 16 * w + Mfma<float>::out_row(lane, e);
+            if (gcol < q) zi[gcol * k + 16 * nb + lr] = (double)Z[nb][e];
+        }
 }
 
 // z[e] for block entry e in tile column c (offset o):
 //   (with R) sum_{b <= c} R(c, b)[o]  +  (with C) sum_{a >= c + c_skip} C(a, c)[o]
-__global__ void k_slot_reduce(int64_t nent, int k, int use_r, int use_c, int c_skip,
+// (right-hand sides t0 .. t0 + kt - 1 of the k)
+__global__ void k_slot_reduce(int64_t nent, int k, int t0, int kt, int use_r, int use_c, int c_skip,
                               const int32_t* __restrict__ ent_blk, const int64_t* __restrict__ ub_off,
                               const int64_t* __restrict__ s_off, const int64_t* __restrict__ qv,
                               const double* __restrict__ Rs, const double* __restrict__ Cs,
                               double* __restrict__ z) {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= nent * k) return;
-    const int64_t e = idx / k;
-    const int t = (int)(idx % k);
+    if (idx >= nent * kt) return;
+    const int64_t e = idx / kt;
+    const int t = t0 + (int)(idx % kt);
     const int i = ent_blk[e];
     const int64_t c = e - ub_off[i];
     const int tc = (int)(c / kT), o = (int)(c % kT);
@@ -417,7 +494,7 @@ __global__ void k_slot_reduce(int64_t nent, int k, int use_r, int use_c, int c_s
     }
     if (use_c)
         for (int a = tc + c_skip; a < nt; ++a) s += Cs[base + ((int64_t)a * (a + 1) / 2 + tc) * kT * k];
-    z[idx] = s;
+    z[e * k + t] = s;
 }
 
 
@@ -595,6 +672,24 @@ int build_schwarz(Handle& h) {
     h.n_row_tasks = (int64_t)rtv.size();
     RDD_TRY(dev_alloc(h, &h.d_row_tasks, rtv.size()));
     if (!rtv.empty()) RDD_TRY(upload(h, h.d_row_tasks, rtv.data(), sizeof(int2) * rtv.size()));
+    // tiles of the block results that are used (RAS: those holding owned
+    // entries), ordered by the tiles a column pass reads, longest first
+    std::vector<std::pair<int, int2>> ct;
+    for (int i = 0; i < J; ++i) {
+        const int nt = h.nt[i];
+        if (nt == 0 || plan.row_cnt[i] == 0) continue;
+        const int c_lo = (int)(plan.row_start[i] / 64);
+        const int c_hi = (int)((plan.row_start[i] + plan.row_cnt[i] - 1) / 64);
+        for (int c = c_lo; c <= c_hi; ++c) ct.push_back({nt - c, make_int2(i, c)});
+    }
+    std::stable_sort(ct.begin(), ct.end(), [](const std::pair<int, int2>& x, const std::pair<int, int2>& y) {
+        return x.first > y.first;
+    });
+    std::vector<int2> ctv;
+    for (auto& e : ct) ctv.push_back(e.second);
+    h.n_col_tasks = (int64_t)ctv.size();
+    RDD_TRY(dev_alloc(h, &h.d_col_tasks, ctv.size()));
+    if (!ctv.empty()) RDD_TRY(upload(h, h.d_col_tasks, ctv.data(), sizeof(int2) * ctv.size()));
     h.slot_total = s_off[J];
     RDD_TRY(dev_alloc(h, &h.d_tile_tasks, tv.size()));
     RDD_TRY(dev_alloc(h, &h.d_s_off, s_off.size()));
@@ -626,34 +721,39 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
     double* Rs = u1 + h.ub_total * k;
     double* Cs = Rs + h.slot_total * k;
     const int64_t tot = h.ub_total * k;
-    const unsigned rgrid = (unsigned)((tot + 255) / 256);
     const unsigned tgrid = (unsigned)h.n_tile_tasks;
     if (tgrid == 0 || tot == 0) return RANN_OK;
     KTimer kt_(h.stream, "k_tile_apply");
+    int kv0 = 0;  // right-hand sides from kv0 on take the slot path
     for (int k0 = 0; k0 < k;) {
         const int rem = k - k0;
-        if (rem >= 16) {  // matrix cores, 32 or 16 right-hand sides per launch
+        if (rem >= 16) {  // matrix cores, 32 or 16 right-hand sides per launch, no slots
             const int kc = rem >= 32 ? 32 : 16;
+            float* u32 = reinterpret_cast<float*>(u1);
             if (h.precision == RANN_MIXED) {
-                if (kc == 32)
-                    hipLaunchKernelGGL((k_trirow_mfma32<32>), dim3((unsigned)h.n_row_tasks), dim3(256), 0,
-                                       h.stream, h.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off,
-                                       h.d_blk_cols, h.d_M32, r, k, k0, Cs);
-                else
-                    hipLaunchKernelGGL((k_trirow_mfma32<16>), dim3((unsigned)h.n_row_tasks), dim3(256), 0,
-                                       h.stream, h.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off,
-                                       h.d_blk_cols, h.d_M32, r, k, k0, Cs);
+#define RDD_MX(KCV)                                                                                        \
+    hipLaunchKernelGGL((k_urow_mfma32<KCV>), dim3((unsigned)h.n_row_tasks), dim3(256), 0, h.stream,          \
+                       h.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_blk_cols, h.d_M32, r, k, k0, u32);  \
+    hipLaunchKernelGGL((k_zcol_mfma32<KCV>), dim3((unsigned)h.n_col_tasks), dim3(256), 0, h.stream,          \
+                       h.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_M32, u32, k, k0, ub)
+                if (kc == 32) {
+                    RDD_MX(32);
+                } else {
+                    RDD_MX(16);
+                }
+#undef RDD_MX
             } else {
                 if (kc == 32)
-                    hipLaunchKernelGGL((k_tile_mfma64<32>), dim3(tgrid), dim3(256), 0, h.stream, h.d_tile_tasks,
-                                       h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols, h.d_M64, r, k, k0,
-                                       Rs, Cs);
+                    hipLaunchKernelGGL((k_rowcol_mfma64<32>), dim3((unsigned)h.n_col_tasks), dim3(256), 0, h.stream,
+                                       h.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_blk_cols, h.d_M64, r, k,
+                                       k0, ub);
                 else
-                    hipLaunchKernelGGL((k_tile_mfma64<16>), dim3(tgrid), dim3(256), 0, h.stream, h.d_tile_tasks,
-                                       h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols, h.d_M64, r, k, k0,
-                                       Rs, Cs);
+                    hipLaunchKernelGGL((k_rowcol_mfma64<16>), dim3((unsigned)h.n_col_tasks), dim3(256), 0, h.stream,
+                                       h.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_blk_cols, h.d_M64, r, k,
+                                       k0, ub);
             }
             k0 += kc;
+            kv0 = k0;
             continue;
         }
         const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
@@ -686,11 +786,14 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
     }
     kt_.stop();
     KTimer kr_(h.stream, "k_slot_reduce");
-    if (h.precision == RANN_MIXED) {
-        hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, 0, 1, 0,
+    const int kt = k - kv0;
+    const unsigned rgrid = (unsigned)((h.ub_total * kt + 255) / 256);
+    if (kt == 0) {
+    } else if (h.precision == RANN_MIXED) {
+        hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, kv0, kt, 0, 1, 0,
                            h.d_ent_blk, h.d_ub_off, h.d_s_off, h.d_q, Rs, Cs, ub);
     } else {
-        hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, 1, 1, 1,
+        hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, kv0, kt, 1, 1, 1,
                            h.d_ent_blk, h.d_ub_off, h.d_s_off, h.d_q, Rs, Cs, ub);
     }
 #undef RDD_TA_KB
