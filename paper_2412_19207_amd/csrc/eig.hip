@@ -56,9 +56,10 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------- 1. panel
-constexpr int kMG = 4;                  // row groups of the panel matrix-vector product
-constexpr int kMC = kPT / kMG;          // column lanes (256)
-constexpr int kMU = kMaxWidth / kMC;    // columns per thread (4)
+// The panel product p = A v runs on G row groups of C column lanes, C = the
+// trailing size rounded up to 64 (G C <= kPT), so that small trailing
+// matrices still keep every thread busy; loops over the panel's reflectors
+// and over rows take 8 entries per round to keep many loads in flight.
 
 // Steps k = k0 .. k0 + kNB - 1 of the reduction of every matrix.  With V the
 // panel's reflectors (rows of A) and W its update vectors (rows of Wb), the
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
     __shared__ double x[kMaxWidth];
     __shared__ double v[kMaxWidth];
     __shared__ double w[kMaxWidth];
-    __shared__ double part[kMG][kMaxWidth];
+    __shared__ double part[kPT];
     __shared__ double hv[kNB], hw[kNB], sv[kNB], sw[kNB];
     __shared__ double red[kPT / 64];
     const int j = blockIdx.x;
@@ -85,7 +86,6 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
     double* ee = tri + mm;
     double* taus = tri + 2 * mm;
     const int tid = threadIdx.x;
-    const int mg = tid / kMC, mc = tid % kMC;
     const int kend = (k0 + kNB < m) ? k0 + kNB : m;
     for (int k = k0; k < kend; ++k) {
         const int i = k - k0;
@@ -98,16 +98,25 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
         __syncthreads();
         // row k of the current matrix, entries c >= k
         for (int c = k + tid; c < m; c += kPT) {
-            double s0 = A[(int64_t)k * mm + c], s1 = 0.0;
+            double s8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s8[u] = 0.0;
             int q = 0;
-            for (; q + 1 < i; q += 2) {
-                const double w0 = Wb[(int64_t)q * mm + c], v0 = A[(int64_t)(k0 + q) * mm + c];
-                const double w1 = Wb[(int64_t)(q + 1) * mm + c], v1 = A[(int64_t)(k0 + q + 1) * mm + c];
-                s0 -= sv[q] * w0 + sw[q] * v0;
-                s1 -= sv[q + 1] * w1 + sw[q + 1] * v1;
+            for (; q + 7 < i; q += 8) {
+                double wv[8], vv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    wv[u] = Wb[(int64_t)(q + u) * mm + c];
+                    vv[u] = A[(int64_t)(k0 + q + u) * mm + c];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s8[u] -= sv[q + u] * wv[u] + sw[q + u] * vv[u];
             }
-            if (q < i) s0 -= sv[q] * Wb[(int64_t)q * mm + c] + sw[q] * A[(int64_t)(k0 + q) * mm + c];
-            x[c - k] = s0 + s1;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q + u < i)
+                    s8[u] -= sv[q + u] * Wb[(int64_t)(q + u) * mm + c] + sw[q + u] * A[(int64_t)(k0 + q + u) * mm + c];
+            x[c - k] = A[(int64_t)k * mm + c] + (((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7])));
         }
         __syncthreads();
         if (n1 < 2) {  // no reflector: the last 2 x 2 block is already tridiagonal
@@ -138,42 +147,31 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
             taus[k] = tau;
         }
         __syncthreads();
-        // p = A_start[k+1.., k+1..] v: thread (mg, mc) sums rows r = mg (mod kMG)
-        // of columns mc + kMC u, four rows per batch of loads
+        // p = A_start[k+1.., k+1..] v: thread (g, c) sums rows r = g (mod G)
+        // of column c, 8 rows per batch of loads; partial sums part[g C + c]
         const double* Ap = A + (int64_t)(k + 1) * mm + (k + 1);
-        const int ncu = (n1 + kMC - 1) / kMC;
-        double acc[kMU];
+        const int C = (n1 + 63) / 64 * 64;
+        const int G = kPT / C;
+        {
+            const int g = tid / C, c = tid % C;
+            double acc8[8];
 #pragma unroll
-        for (int u = 0; u < kMU; ++u) acc[u] = 0.0;
-        int r = mg;
-        for (; r + 3 * kMG < n1; r += 4 * kMG) {
-            const double v0 = v[r], v1 = v[r + kMG], v2 = v[r + 2 * kMG], v3 = v[r + 3 * kMG];
-            const double* a0 = Ap + (int64_t)r * mm;
-            const double* a1 = a0 + kMG * mm;
-            const double* a2 = a1 + kMG * mm;
-            const double* a3 = a2 + kMG * mm;
+            for (int u = 0; u < 8; ++u) acc8[u] = 0.0;
+            if (g < G && c < n1) {
+                int r = g;
+                for (; r + 7 * G < n1; r += 8 * G) {
+                    double av[8];
 #pragma unroll
-            for (int u = 0; u < kMU; ++u) {
-                const int c = mc + u * kMC;
-                if (u < ncu && c < n1) {
-                    const double t0 = a0[c], t1 = a1[c], t2 = a2[c], t3 = a3[c];
-                    acc[u] = fma(t0, v0, fma(t1, v1, fma(t2, v2, fma(t3, v3, acc[u]))));
+                    for (int u = 0; u < 8; ++u) av[u] = Ap[(int64_t)(r + u * G) * mm + c];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc8[u] = fma(av[u], v[r + u * G], acc8[u]);
                 }
-            }
-        }
-        for (; r < n1; r += kMG) {
-            const double vr = v[r];
-            const double* a0 = Ap + (int64_t)r * mm;
 #pragma unroll
-            for (int u = 0; u < kMU; ++u) {
-                const int c = mc + u * kMC;
-                if (u < ncu && c < n1) acc[u] = fma(a0[c], vr, acc[u]);
+                for (int u = 0; u < 8; ++u)
+                    if (r + u * G < n1) acc8[u] = fma(Ap[(int64_t)(r + u * G) * mm + c], v[r + u * G], acc8[u]);
             }
-        }
-#pragma unroll
-        for (int u = 0; u < kMU; ++u) {
-            const int c = mc + u * kMC;
-            if (u < ncu && c < n1) part[mg][c] = acc[u];
+            if (g < G)
+                part[g * C + c] = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
         }
         // hv = W^T v, hw = V^T v over rows k+1 .. m-1: 16 lanes per dot product
         {
@@ -182,7 +180,19 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
             if (dq < 2 * i) {
                 const int q = dq >> 1;
                 const double* src = ((dq & 1) ? A + (int64_t)(k0 + q) * mm : Wb + (int64_t)q * mm) + k + 1;
-                for (int c = g; c < n1; c += 16) sacc = fma(src[c], v[c], sacc);
+                double s4[4] = {0.0, 0.0, 0.0, 0.0};
+                int c = g;
+                for (; c + 48 < n1; c += 64) {
+                    double tv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) tv[u] = src[c + 16 * u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) s4[u] = fma(tv[u], v[c + 16 * u], s4[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (c + 16 * u < n1) s4[u] = fma(src[c + 16 * u], v[c + 16 * u], s4[u]);
+                sacc = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             }
             for (int off = 8; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off);
             if (dq < 2 * i && g == 0) {
@@ -197,18 +207,26 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
         double pv = 0.0;
         for (int c = tid; c < n1; c += kPT) {
             double s0 = 0.0;
+            for (int g = 0; g < G; ++g) s0 += part[g * C + c];
+            double s8[8];
 #pragma unroll
-            for (int g = 0; g < kMG; ++g) s0 += part[g][c];
-            double s1 = 0.0;
+            for (int u = 0; u < 8; ++u) s8[u] = 0.0;
             int q = 0;
-            for (; q + 1 < i; q += 2) {
-                const double a0 = A[(int64_t)(k0 + q) * mm + k + 1 + c], b0 = Wb[(int64_t)q * mm + k + 1 + c];
-                const double a1 = A[(int64_t)(k0 + q + 1) * mm + k + 1 + c], b1 = Wb[(int64_t)(q + 1) * mm + k + 1 + c];
-                s0 -= a0 * hv[q] + b0 * hw[q];
-                s1 -= a1 * hv[q + 1] + b1 * hw[q + 1];
+            for (; q + 7 < i; q += 8) {
+                double av[8], bv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    av[u] = A[(int64_t)(k0 + q + u) * mm + k + 1 + c];
+                    bv[u] = Wb[(int64_t)(q + u) * mm + k + 1 + c];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s8[u] -= av[u] * hv[q + u] + bv[u] * hw[q + u];
             }
-            if (q < i) s0 -= A[(int64_t)(k0 + q) * mm + k + 1 + c] * hv[q] + Wb[(int64_t)q * mm + k + 1 + c] * hw[q];
-            const double wc = tau * (s0 + s1);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q + u < i)
+                    s8[u] -= A[(int64_t)(k0 + q + u) * mm + k + 1 + c] * hv[q + u] + Wb[(int64_t)(q + u) * mm + k + 1 + c] * hw[q + u];
+            const double wc = tau * (s0 + (((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]))));
             w[c] = wc;
             pv += wc * v[c];
         }
@@ -331,7 +349,11 @@ __device__ TriBounds tri_bounds(const double* d, const double* ea, int m) {
     return b;
 }
 
-// every eigenvalue by bisection, one thread per eigenvalue, 64 per workgroup
+// every eigenvalue by multisection: 4 lanes per eigenvalue, 16 eigenvalues
+// per workgroup.  In each round the 4 lanes count the eigenvalues below the 4
+// inner points of 5 equal parts of the interval, and the part that holds the
+// idx-th smallest eigenvalue (count(lo) <= idx < count(hi)) becomes the new
+// interval; the same stopping width as plain bisection.
 __global__ void __launch_bounds__(64) k_bisect(const int32_t* __restrict__ mvec,
                                                const double* __restrict__ Sall,
                                                const int64_t* __restrict__ s_off,
@@ -343,11 +365,12 @@ __global__ void __launch_bounds__(64) k_bisect(const int32_t* __restrict__ mvec,
     __shared__ double ea[kMaxWidth];
     const int j = blockIdx.x;
     const int m = mvec[j];
-    const int idx = blockIdx.y * 64 + threadIdx.x;
-    if ((int)blockIdx.y * 64 >= m) return;  // uniform per workgroup
+    const int lane = threadIdx.x, sub = lane & 3;
+    const int idx = blockIdx.y * 16 + (lane >> 2);
+    if ((int)blockIdx.y * 16 >= m) return;  // uniform per workgroup
     const int64_t mm = m;
     const double* tri = Sall + s_off[j] + scr_tri(mm);
-    for (int i = threadIdx.x; i < m; i += 64) {
+    for (int i = lane; i < m; i += 64) {
         const double e = (i + 1 < m) ? tri[mm + i] : 0.0;
         dd[i] = tri[i];
         ea[i] = fabs(e);
@@ -355,20 +378,41 @@ __global__ void __launch_bounds__(64) k_bisect(const int32_t* __restrict__ mvec,
     }
     __syncthreads();
     const TriBounds tb = tri_bounds(dd, ea, m);
-    if (idx >= m) return;
-    // the idx-th smallest eigenvalue: count(lo) <= idx < count(hi)
+    const bool live = idx < m;
     double lo = tb.gl - tb.atol, hi = tb.gu + tb.atol;
     for (int it = 0; it < 200; ++it) {
-        if (!((hi - lo) > tb.atol + 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
-        const double mid = 0.5 * (lo + hi);
-        if (sturm_count_fast(dd, e2, m, mid, tb.pivmin) > idx)
-            hi = mid;
-        else
-            lo = mid;
+        const bool go = live && (hi - lo) > tb.atol + 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi));
+        if (!__any(go)) break;  // wave-uniform: the shuffles below need every lane
+        const double h = (hi - lo) * 0.2;
+        double pt[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pt[u] = (u == 3) ? hi - h : lo + h * (u + 1);
+        const int cnt = go ? sturm_count_fast(dd, e2, m, pt[sub], tb.pivmin) : 0;
+        const int base = lane & ~3;
+        const int c0 = __shfl(cnt, base), c1 = __shfl(cnt, base + 1);
+        const int c2 = __shfl(cnt, base + 2), c3 = __shfl(cnt, base + 3);
+        if (go) {
+            if (c0 > idx) {
+                hi = pt[0];
+            } else if (c1 > idx) {
+                lo = pt[0];
+                hi = pt[1];
+            } else if (c2 > idx) {
+                lo = pt[1];
+                hi = pt[2];
+            } else if (c3 > idx) {
+                lo = pt[2];
+                hi = pt[3];
+            } else {
+                lo = pt[3];
+            }
+        }
     }
-    const double l = 0.5 * (lo + hi);
-    lam_all[m_off[j] + idx] = l;
-    eig_out[m_off[j] + m - 1 - idx] = l;
+    if (live && sub == 0) {
+        const double l = 0.5 * (lo + hi);
+        lam_all[m_off[j] + idx] = l;
+        eig_out[m_off[j] + m - 1 - idx] = l;
+    }
 }
 
 // ---------------------------------------------------------------- 3-4. vectors
@@ -741,93 +785,111 @@ __global__ void __launch_bounds__(kPT) k_vectors(const int32_t* __restrict__ mve
     }
     if (!done) cgs2(Z, p, m, lds, red);
     __syncthreads();
-    // ---- 4. y = Q z, Q = H_0 ... H_{m-3}: panels last to first, each applied
-    // as I - V T V^T with V[q][r] = A[k0 + q][r] for r > k0 + q (zero
-    // otherwise).  T^{-1} = diag(1 / tau) + strict_upper(V V^T), so T Z1 is one
-    // upper-triangular back substitution per column.
-    double* Vs = lds;                      // kNB x (kRC + 1)
-    double* Zs = lds + kNB * (kRC + 1);    // kQRMax x (kRC + 1)
-    double* Z1 = Zs + kQRMax * (kRC + 1);  // kNB x (kQRMax + 1)
+    // leave the orthonormal rows in the LU area for the back-transform
+    if (Z != LU)
+        for (int64_t e = tid; e < (int64_t)m * p; e += kPT) {
+            const int t = (int)(e / m), i = (int)(e % m);
+            LU[(int64_t)t * mm + i] = Z[(int64_t)t * mm + i];
+        }
+}
+
+// ---- 4. y = Q z for the vectors t0 .. t0 + nc - 1 of matrix j (workgroup
+// (j, slice)), Q = H_0 ... H_{m-3}: panels last to first, each applied as
+// I - V T V^T with V[q][r] = A[k0 + q][r] for r > k0 + q (zero otherwise).
+// T^{-1} = diag(1 / tau) + strict_upper(V V^T), so T Z1 is one
+// upper-triangular back substitution per column.  The slices are independent.
+constexpr int kSlice = 24;  // vectors per back-transform workgroup
+__global__ void __launch_bounds__(kPT) k_backxf(const int32_t* __restrict__ mvec,
+                                                const int64_t* __restrict__ g_off,
+                                                const double* __restrict__ Gall,
+                                                double* __restrict__ Sall,
+                                                const int64_t* __restrict__ s_off,
+                                                double* __restrict__ Yall,
+                                                const int32_t* __restrict__ p_out) {
+    __shared__ double Vs[kNB * (kRC + 1)];
+    __shared__ double Zs[kSlice * (kRC + 1)];
+    __shared__ double Z1[kNB * (kSlice + 1)];
+    __shared__ double Tm[kNB][kNB + 1];
+    const int j = blockIdx.x;
+    const int m = mvec[j];
+    const int p = p_out[j];
+    const int t0 = blockIdx.y * kSlice;
+    if (t0 >= p) return;
+    const int nc = (p - t0 < kSlice) ? p - t0 : kSlice;
+    const int64_t mm = m;
+    const double* A = Gall + g_off[j];
+    double* Y = Yall + g_off[j];
+    const double* tri = Sall + s_off[j] + scr_tri(mm);
+    const double* taus = tri + 2 * mm;
+    double* Z = Sall + s_off[j] + scr_LU(mm) + (int64_t)t0 * mm;  // rows of this slice
+    const int tid = threadIdx.x;
     const int nref = (m >= 2) ? m - 2 : 0;
-    constexpr int kPer = (kNB * kQRMax + kPT - 1) / kPT;  // (q, t) pairs per thread
     const int ga = (tid < kNB * kNB) ? tid / kNB : 0, gb = (tid < kNB * kNB) ? tid % kNB : 0;
+    // thread (q, t) of the V Z^T product
+    static_assert(kNB * kSlice <= kPT, "one thread per (q, t)");
+    const bool pact = tid < kNB * kSlice;
+    const int pq = pact ? tid / kSlice : 0, pt = pact ? tid % kSlice : 0;
     for (int k0 = ((nref - 1) / kNB) * kNB; nref > 0 && k0 >= 0; k0 -= kNB) {
         const int nb = (k0 + kNB < nref) ? kNB : nref - k0;
-        for (int t0 = 0; t0 < p; t0 += kQRMax) {
-            const int nc = (p - t0 < kQRMax) ? p - t0 : kQRMax;
-            double acc[kPer];
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) acc[u] = 0.0;
-            double gacc = 0.0;  // (V V^T)[ga][gb], first column block only
-            for (int r0 = k0 + 1; r0 < m; r0 += kRC) {
-                for (int e = tid; e < kNB * kRC; e += kPT) {
-                    const int q = e / kRC, rr = e % kRC, r = r0 + rr;
-                    Vs[q * (kRC + 1) + rr] =
-                        (q < nb && r < m && r > k0 + q) ? A[(int64_t)(k0 + q) * mm + r] : 0.0;
-                }
-                for (int e = tid; e < nc * kRC; e += kPT) {
-                    const int t = e / kRC, rr = e % kRC, r = r0 + rr;
-                    Zs[t * (kRC + 1) + rr] = (r < m) ? Z[(int64_t)(t0 + t) * mm + r] : 0.0;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int u = 0; u < kPer; ++u) {
-                    const int pr = tid + u * kPT, q = pr / kQRMax, t = pr % kQRMax;
-                    if (q < nb && t < nc) {
-                        const double* vq = Vs + q * (kRC + 1);
-                        const double* zt = Zs + t * (kRC + 1);
-                        double sacc = acc[u];
-                        for (int rr = 0; rr < kRC; ++rr) sacc = fma(vq[rr], zt[rr], sacc);
-                        acc[u] = sacc;
-                    }
-                }
-                if (t0 == 0 && tid < kNB * kNB && ga < gb && gb < nb) {
-                    const double* va = Vs + ga * (kRC + 1);
-                    const double* vb = Vs + gb * (kRC + 1);
-                    for (int rr = 0; rr < kRC; ++rr) gacc = fma(va[rr], vb[rr], gacc);
-                }
-                __syncthreads();
+        double acc = 0.0;
+        double gacc = 0.0;  // (V V^T)[ga][gb]
+        for (int r0 = k0 + 1; r0 < m; r0 += kRC) {
+            for (int e = tid; e < kNB * kRC; e += kPT) {
+                const int q = e / kRC, rr = e % kRC, r = r0 + rr;
+                Vs[q * (kRC + 1) + rr] = (q < nb && r < m && r > k0 + q) ? A[(int64_t)(k0 + q) * mm + r] : 0.0;
             }
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int pr = tid + u * kPT, q = pr / kQRMax, t = pr % kQRMax;
-                if (q < kNB) Z1[q * (kQRMax + 1) + t] = acc[u];
-            }
-            if (t0 == 0 && tid < kNB * kNB) Tm[ga][gb] = (ga < gb && gb < nb) ? gacc : 0.0;
-            __syncthreads();
-            // Z2 = T Z1: Z2[q] = tau_q (Z1[q] - sum_{b > q} (V V^T)[q][b] Z2[b])
-            for (int c = tid; c < nc; c += kPT) {
-                for (int q = nb - 1; q >= 0; --q) {
-                    double sacc = Z1[q * (kQRMax + 1) + c];
-                    for (int b2 = q + 1; b2 < nb; ++b2) sacc -= Tm[q][b2] * Z1[b2 * (kQRMax + 1) + c];
-                    Z1[q * (kQRMax + 1) + c] = taus[k0 + q] * sacc;
-                }
+            for (int e = tid; e < nc * kRC; e += kPT) {
+                const int t = e / kRC, rr = e % kRC, r = r0 + rr;
+                Zs[t * (kRC + 1) + rr] = (r < m) ? Z[(int64_t)t * mm + r] : 0.0;
             }
             __syncthreads();
-            // z_t[r] -= sum_q V[q][r] Z2[q][t] on rows > k0
-            for (int r0 = k0 + 1; r0 < m; r0 += kRC) {
-                for (int e = tid; e < kNB * kRC; e += kPT) {
-                    const int q = e / kRC, rr = e % kRC, r = r0 + rr;
-                    Vs[q * (kRC + 1) + rr] =
-                        (q < nb && r < m && r > k0 + q) ? A[(int64_t)(k0 + q) * mm + r] : 0.0;
-                }
-                __syncthreads();
-                for (int e = tid; e < nc * kRC; e += kPT) {
-                    const int t = e / kRC, rr = e % kRC, r = r0 + rr;
-                    if (r < m) {
-                        double sacc = 0.0;
-                        for (int q = 0; q < nb; ++q) sacc = fma(Vs[q * (kRC + 1) + rr], Z1[q * (kQRMax + 1) + t], sacc);
-                        Z[(int64_t)(t0 + t) * mm + r] -= sacc;
-                    }
-                }
-                __syncthreads();
+            if (pact && pq < nb && pt < nc) {
+                const double* vq = Vs + pq * (kRC + 1);
+                const double* zt = Zs + pt * (kRC + 1);
+#pragma unroll 16
+                for (int rr = 0; rr < kRC; ++rr) acc = fma(vq[rr], zt[rr], acc);
             }
+            if (tid < kNB * kNB && ga < gb && gb < nb) {
+                const double* va = Vs + ga * (kRC + 1);
+                const double* vb = Vs + gb * (kRC + 1);
+                for (int rr = 0; rr < kRC; ++rr) gacc = fma(va[rr], vb[rr], gacc);
+            }
+            __syncthreads();
+        }
+        if (pact) Z1[pq * (kSlice + 1) + pt] = (pq < nb && pt < nc) ? acc : 0.0;
+        if (tid < kNB * kNB) Tm[ga][gb] = (ga < gb && gb < nb) ? gacc : 0.0;
+        __syncthreads();
+        // Z2 = T Z1: Z2[q] = tau_q (Z1[q] - sum_{b > q} (V V^T)[q][b] Z2[b])
+        for (int c = tid; c < nc; c += kPT) {
+            for (int q = nb - 1; q >= 0; --q) {
+                double sacc = Z1[q * (kSlice + 1) + c];
+                for (int b2 = q + 1; b2 < nb; ++b2) sacc -= Tm[q][b2] * Z1[b2 * (kSlice + 1) + c];
+                Z1[q * (kSlice + 1) + c] = taus[k0 + q] * sacc;
+            }
+        }
+        __syncthreads();
+        // z_t[r] -= sum_q V[q][r] Z2[q][t] on rows > k0
+        for (int r0 = k0 + 1; r0 < m; r0 += kRC) {
+            for (int e = tid; e < kNB * kRC; e += kPT) {
+                const int q = e / kRC, rr = e % kRC, r = r0 + rr;
+                Vs[q * (kRC + 1) + rr] = (q < nb && r < m && r > k0 + q) ? A[(int64_t)(k0 + q) * mm + r] : 0.0;
+            }
+            __syncthreads();
+            for (int e = tid; e < nc * kRC; e += kPT) {
+                const int t = e / kRC, rr = e % kRC, r = r0 + rr;
+                if (r < m) {
+                    double sacc = 0.0;
+                    for (int q = 0; q < nb; ++q) sacc = fma(Vs[q * (kRC + 1) + rr], Z1[q * (kSlice + 1) + t], sacc);
+                    Z[(int64_t)t * mm + r] -= sacc;
+                }
+            }
+            __syncthreads();
         }
     }
     // eigenvectors as columns of Y
-    for (int64_t e = tid; e < (int64_t)m * p; e += kPT) {
-        const int i = (int)(e / p), t = (int)(e % p);
-        Y[(int64_t)i * mm + t] = Z[(int64_t)t * mm + i];
+    for (int64_t e = tid; e < (int64_t)m * nc; e += kPT) {
+        const int i = (int)(e / nc), t = (int)(e % nc);
+        Y[(int64_t)i * mm + t0 + t] = Z[(int64_t)t * mm + i];
     }
 }
 
@@ -882,13 +944,15 @@ int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const i
     }
     double* d_lam = nullptr;
     RDD_TRY(dev_alloc(h, &d_lam, (size_t)h.sum_m));
-    hipLaunchKernelGGL(k_bisect, dim3(J, (unsigned)((mmax + 63) / 64)), dim3(64), 0, h.stream, h.d_m, S,
+    hipLaunchKernelGGL(k_bisect, dim3(J, (unsigned)((mmax + 15) / 16)), dim3(64), 0, h.stream, h.d_m, S,
                        d_s_off, d_lam, h.d_m_off, d_eig);
     hipLaunchKernelGGL(k_pcount, dim3(J), dim3(256), 0, h.stream, h.d_m, S, d_s_off, d_lam, tol, mode,
                        d_p, h.d_m_off, d_flags);
     hipLaunchKernelGGL(k_inviter, dim3(J, (unsigned)((mmax + 63) / 64)), dim3(64), 0, h.stream, h.d_m, S,
                        d_s_off, d_lam, d_p, h.d_m_off);
     hipLaunchKernelGGL(k_vectors, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S, d_s_off, Y, d_p);
+    hipLaunchKernelGGL(k_backxf, dim3(J, (unsigned)((mmax + kSlice - 1) / kSlice)), dim3(kPT), 0, h.stream, h.d_m,
+                       d_g_off, G, S, d_s_off, Y, d_p);
     kt_.stop();
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));
