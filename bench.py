@@ -36,7 +36,7 @@ FP32_PEAK_TFLOPS = 157.3
 KERNELS = ["k_eig", "k_factor", "k_pca_gram", "k_feat_rows", "k_local_gram", "k_normal", "k_Hx",
            "k_HTy_part", "k_tile_apply", "k_slot_reduce"]
 # timers that cover several different kernels (not candidates for the roofline line)
-GROUPS = {"k_eig", "k_factor", "k_Hx"}
+GROUPS = {"k_eig", "k_factor", "k_Hx", "k_pca_gram"}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")

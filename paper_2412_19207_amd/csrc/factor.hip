@@ -33,78 +33,6 @@ namespace {
 
 constexpr int kFT = 256;  // threads
 
-constexpr int kBK = 32;  // k-steps per LDS stage of the tile products
-
-// One kBK slice of a 64-wide operand, 8 elements per thread, held in
-// registers between its global load and its LDS store (so the next slice is
-// in flight while the current one is multiplied):
-//  kAlongRows: element (kk, m) = src[(r0 + k0 + kk) * ld + c0 + m]
-//  otherwise : element (kk, m) = src[(r0 + m) * ld + c0 + k0 + kk]
-template <class T, bool kAlongRows>
-__device__ __forceinline__ void fetch(T* reg, const T* src, int64_t ld, int64_t r0, int64_t c0, int k0,
-                                      int kvalid, int mvalid) {
-    const int t = threadIdx.x;
-    if (kAlongRows) {
-        const int m4 = (t & 15) * 4;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int kk = (t >> 4) + 16 * j;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int m = m4 + e;
-                reg[4 * j + e] = (k0 + kk < kvalid && m < mvalid) ? src[(r0 + k0 + kk) * ld + c0 + m] : T(0);
-            }
-        }
-    } else {
-        const int m = t >> 2, k8 = (t & 3) * 8;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int kk = k8 + e;
-            reg[e] = (k0 + kk < kvalid && m < mvalid) ? src[(r0 + m) * ld + c0 + k0 + kk] : T(0);
-        }
-    }
-}
-
-template <class T, bool kAlongRows>
-__device__ __forceinline__ void put(T (*S)[kTM + kPad], const T* reg) {
-    const int t = threadIdx.x;
-    if (kAlongRows) {
-        const int m4 = (t & 15) * 4;
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) S[(t >> 4) + 16 * j][m4 + e] = reg[4 * j + e];
-    } else {
-        const int m = t >> 2, k8 = (t & 3) * 8;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) S[k8 + e][m] = reg[e];
-    }
-}
-
-// acc += op(A) op(B) over K = kvalid, kBK k-steps per LDS stage (As, Bs hold
-// kBK rows); the next stage is loaded while the current one is multiplied
-template <class T, bool kAAlongRows, bool kBAlongRows>
-__device__ void tile_gemm(TileAcc<T>& acc, T (*As)[kTM + kPad], T (*Bs)[kTN + kPad], const T* A,
-                          int64_t lda, int64_t ar0, int64_t ac0, int amv, const T* B, int64_t ldb,
-                          int64_t br0, int64_t bc0, int bmv, int kvalid) {
-    T ra[8], rb[8];
-    if (kvalid > 0) {
-        fetch<T, kAAlongRows>(ra, A, lda, ar0, ac0, 0, kvalid, amv);
-        fetch<T, kBAlongRows>(rb, B, ldb, br0, bc0, 0, kvalid, bmv);
-    }
-    for (int k0 = 0; k0 < kvalid; k0 += kBK) {
-        put<T, kAAlongRows>(As, ra);
-        put<T, kBAlongRows>(Bs, rb);
-        __syncthreads();
-        if (k0 + kBK < kvalid) {
-            fetch<T, kAAlongRows>(ra, A, lda, ar0, ac0, k0 + kBK, kvalid, amv);
-            fetch<T, kBAlongRows>(rb, B, ldb, br0, bc0, k0 + kBK, kvalid, bmv);
-        }
-        acc.template step_k<kBK>(As, Bs);
-        __syncthreads();
-    }
-}
-
 struct TileTask {
     int32_t blk, a, b, pad;
 };

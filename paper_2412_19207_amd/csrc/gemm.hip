@@ -1,8 +1,8 @@
 // Matrix-core GEMMs of the set-up phase.
 //
-//  * k_pca_gram  : G_j = Psi_j^T Psi_j, Psi_j[i,k] = w_j(x_i) tanh(z_k(x_i)),
+//  * k_psi, k_pca_gram: G_j = Psi_j^T Psi_j, Psi_j[i,k] = w_j(x_i) tanh(z_k(x_i)),
 //                  the value matrix of the PCA step (paper Sec. 4); Psi is
-//                  generated tile by tile in LDS and never stored.
+//                  evaluated once into scratch memory, then multiplied by tiles.
 //  * k_feat_rows : H_j = A_j V_j with A_j[i,k] = A[L w_j phi_k](x_i) generated
 //                  in the GEMM prologue from the pair coefficients (eqs. (sum),
 //                  (system_new)); FP64 output plus an FP32 copy in the mixed path.
@@ -10,6 +10,9 @@
 //                  share, the pieces of the Schwarz blocks A_i = R_i H^T H R_i^T
 //                  (Sec. 3); FP64, or FP32 with FP32 accumulation.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "common.h"
 #include "mfma.h"
@@ -26,61 +29,59 @@ __device__ __forceinline__ double feature_z(const double* Rk, double bk, const d
     return z;
 }
 
-__global__ void __launch_bounds__(256) k_pca_gram(Geo g, const GramTile* __restrict__ tiles,
+// Psi_j[i][f] = w_j(x_i) tanh(z_f(x_i)), row-major n_j x m_j, for the 16 pair
+// rows of workgroup (j, chunk); each value is computed once
+__global__ void __launch_bounds__(256) k_psi(Geo g, const int64_t* __restrict__ row_off,
+                                             const double* __restrict__ rec, const int32_t* __restrict__ m,
+                                             const int64_t* __restrict__ m_off, const double* __restrict__ Rf,
+                                             const double* __restrict__ bf, const int64_t* __restrict__ psi_off,
+                                             double* __restrict__ Psi) {
+    const int j = blockIdx.x, mj = m[j];
+    const int64_t n = row_off[j + 1] - row_off[j];
+    const int64_t r0 = (int64_t)blockIdx.y * 16;
+    if (r0 >= n) return;
+    const double* rj = rec + row_off[j] * kPairRec;
+    double* out = Psi + psi_off[j];
+    for (int e = threadIdx.x; e < 16 * mj; e += 256) {
+        const int64_t i = r0 + e / mj;
+        const int f = e % mj;
+        if (i < n) {
+            double xt[kMaxDim] = {0, 0, 0, 0};
+            for (int q = 0; q < g.d; ++q) xt[q] = rj[i * kPairRec + kRecX + q];
+            const double w = rj[i * kPairRec + kRecW];
+            const int64_t gf = m_off[j] + f;
+            out[i * mj + f] = w * tanh(feature_z(Rf + gf * 4, bf[gf], xt, g.d));
+        }
+    }
+}
+
+// tile (a, b), b <= a, of G_j = Psi_j^T Psi_j (both triangles written)
+__global__ void __launch_bounds__(256) k_pca_gram(const GramTile* __restrict__ tiles,
                                                   const int64_t* __restrict__ row_off,
-                                                  const double* __restrict__ rec,
                                                   const int32_t* __restrict__ m,
-                                                  const int64_t* __restrict__ m_off,
-                                                  const double* __restrict__ Rf,
-                                                  const double* __restrict__ bf,
+                                                  const int64_t* __restrict__ psi_off,
+                                                  const double* __restrict__ Psi,
                                                   const int64_t* __restrict__ g_off,
                                                   double* __restrict__ G) {
-    __shared__ double As[kTK][kTM + kPad];
-    __shared__ double Bs[kTK][kTN + kPad];
+    __shared__ double As[kBK][kTM + kPad];
+    __shared__ double Bs[kBK][kTN + kPad];
     const GramTile t = tiles[blockIdx.x];
     const int j = t.j, mj = m[j];
-    const int64_t n = row_off[j + 1] - row_off[j];
-    const double* rj = rec + row_off[j] * kPairRec;
-    const int kk = threadIdx.x >> 4, c4 = (threadIdx.x & 15) * 4;
-    const bool diag = (t.tm == t.tn);
+    const int n = (int)(row_off[j + 1] - row_off[j]);
+    const double* Pj = Psi + psi_off[j];
+    const int64_t a0 = (int64_t)t.tm * kTM, b0 = (int64_t)t.tn * kTN;
+    const int av = (int)((mj - a0) < kTM ? (mj - a0) : kTM), bv = (int)((mj - b0) < kTN ? (mj - b0) : kTN);
     TileAcc<double> acc;
     acc.zero();
-    for (int64_t i0 = 0; i0 < n; i0 += kTK) {
-        const int64_t i = i0 + kk;
-        double xt[kMaxDim] = {0, 0, 0, 0}, w = 0.0;
-        if (i < n) {
-            for (int q = 0; q < g.d; ++q) xt[q] = rj[i * kPairRec + kRecX + q];
-            w = rj[i * kPairRec + kRecW];
-        }
-        for (int e = 0; e < 4; ++e) {
-            int f = t.tm * kTM + c4 + e;
-            double v = 0.0;
-            if (i < n && f < mj) {
-                int64_t gf = m_off[j] + f;
-                v = w * tanh(feature_z(Rf + gf * 4, bf[gf], xt, g.d));
-            }
-            As[kk][c4 + e] = v;
-            if (!diag) {
-                int f2 = t.tn * kTN + c4 + e;
-                double v2 = 0.0;
-                if (i < n && f2 < mj) {
-                    int64_t gf = m_off[j] + f2;
-                    v2 = w * tanh(feature_z(Rf + gf * 4, bf[gf], xt, g.d));
-                }
-                Bs[kk][c4 + e] = v2;
-            }
-        }
-        __syncthreads();
-        acc.step(As, diag ? As : Bs);
-        __syncthreads();
-    }
+    tile_gemm<double, true, true>(acc, As, Bs, Pj, mj, 0, a0, av, Pj, mj, 0, b0, bv, n);
+    const bool diag = (t.tm == t.tn);
     double* Gj = G + g_off[j];
     acc.each([&](int r, int c, double v) {
-        int gr = t.tm * kTM + r, gc = t.tn * kTN + c;
+        const int64_t gr = a0 + r, gc = b0 + c;
         if (gr < mj && gc < mj) {
             if (!diag || gr >= gc) {
-                Gj[(int64_t)gr * mj + gc] = v;
-                Gj[(int64_t)gc * mj + gr] = v;
+                Gj[gr * mj + gc] = v;
+                Gj[gc * mj + gr] = v;
             }
         }
     });
@@ -360,10 +361,29 @@ int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g
     GramTile* d_t = nullptr;
     RDD_TRY(dev_alloc(h, &d_t, tiles.size()));
     RDD_TRY(upload(h, d_t, tiles.data(), sizeof(GramTile) * tiles.size()));
+    // the value matrices Psi_j, computed once and kept for the Gram tiles
+    const int J = h.geo.J;
+    std::vector<int64_t> psi_off(J + 1, 0);
+    int64_t max_n = 0;
+    for (int j = 0; j < J; ++j) {
+        const int64_t n = h.pts.row_off[j + 1] - h.pts.row_off[j];
+        psi_off[j + 1] = psi_off[j] + n * h.m[j];
+        max_n = std::max(max_n, n);
+    }
+    int64_t* d_psi_off = nullptr;
+    double* d_psi = nullptr;
+    RDD_TRY(dev_alloc(h, &d_psi_off, (size_t)J + 1));
+    RDD_TRY(dev_alloc(h, &d_psi, (size_t)std::max<int64_t>(1, psi_off[J])));
+    RDD_TRY(upload(h, d_psi_off, psi_off.data(), sizeof(int64_t) * (J + 1)));
     KTimer kt_(h.stream, "k_pca_gram");
-    hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, h.geo, d_t,
-                       h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, d_g_off, G);
+    if (max_n > 0)
+        hipLaunchKernelGGL(k_psi, dim3(J, (unsigned)((max_n + 15) / 16)), dim3(256), 0, h.stream, h.geo,
+                           h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, d_psi_off, d_psi);
+    hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, d_t, h.pts.d_row_off,
+                       h.d_m, d_psi_off, d_psi, d_g_off, G);
     kt_.stop();
+    dev_free(h, d_psi);
+    dev_free(h, d_psi_off);
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));
     dev_free(h, d_t);

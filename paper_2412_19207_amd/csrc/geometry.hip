@@ -10,6 +10,7 @@
 // sorted and identical from run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -34,25 +35,29 @@ __device__ inline bool inside(const Geo& g, const double* mu, const int* c, cons
     return in;
 }
 
-// one workgroup per subdomain scans every point; pass 0 counts, pass 1 writes
-// the sorted row list by ballot compaction
+// workgroup (j, chunk) scans the points of one contiguous chunk of the point
+// range for subdomain j; pass 0 counts (count[j * nchunk + chunk]), pass 1
+// writes the sorted row list by ballot compaction from the chunk's offset
+// off[j * nchunk + chunk] (chunks in order, so S_j stays ascending)
 template <bool kFill>
 __global__ void __launch_bounds__(256) k_bin(Geo g, const double* __restrict__ mu,
                                              const double* __restrict__ X, int64_t n,
                                              int64_t* __restrict__ count,
-                                             const int64_t* __restrict__ row_off,
+                                             const int64_t* __restrict__ off,
                                              int32_t* __restrict__ rows,
                                              int32_t* __restrict__ pair_sub) {
     const int j = blockIdx.x;
+    const int nchunk = gridDim.y;
+    const int64_t lo = n * blockIdx.y / nchunk, hi = n * (blockIdx.y + 1) / nchunk;
     int c[kMaxDim];
     sub_coords(g, j, c);
     __shared__ int wave_cnt[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t base = 0;
-    for (int64_t p0 = 0; p0 < n; p0 += 256) {
+    int64_t base = kFill ? off[(int64_t)j * nchunk + blockIdx.y] : 0;
+    for (int64_t p0 = lo; p0 < hi; p0 += 256) {
         int64_t p = p0 + threadIdx.x;
         bool in = false;
-        if (p < n) {
+        if (p < hi) {
             double x[kMaxDim];
             for (int i = 0; i < g.d; ++i) x[i] = X[p * g.d + i];
             in = inside(g, mu, c, x);
@@ -67,14 +72,14 @@ __global__ void __launch_bounds__(256) k_bin(Geo g, const double* __restrict__ m
         }
         if (kFill && in) {
             uint64_t lower = (lane == 0) ? 0ull : (mask & ((~0ull) >> (64 - lane)));
-            int64_t pos = row_off[j] + base + before + __popcll(lower);
+            int64_t pos = base + before + __popcll(lower);
             rows[pos] = (int32_t)p;
             pair_sub[pos] = j;
         }
         base += total;
         __syncthreads();
     }
-    if (!kFill && threadIdx.x == 0) count[j] = base;
+    if (!kFill && threadIdx.x == 0) count[(int64_t)j * nchunk + blockIdx.y] = base;
 }
 
 // number of subdomains whose support contains each point (a tensor product of
@@ -338,17 +343,26 @@ int exclusive_scan_i64(Handle& h, const int64_t* in, int64_t* out, int64_t n) {
 int bin_points(Handle& h, const double* X, int64_t n, PointSet& ps) {
     const Geo& g = h.geo;
     ps.n = n;
+    // chunks of the point range per subdomain, about 4096 points each
+    const int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, (n + 4095) / 4096));
+    const size_t ncell = (size_t)g.J * nchunk;
     int64_t* d_cnt = nullptr;
-    RDD_TRY(dev_alloc(h, &d_cnt, (size_t)g.J));
-    hipLaunchKernelGGL((k_bin<false>), dim3(g.J), dim3(256), 0, h.stream, g, h.d_mu, X, n, d_cnt,
+    RDD_TRY(dev_alloc(h, &d_cnt, ncell));
+    hipLaunchKernelGGL((k_bin<false>), dim3(g.J, nchunk), dim3(256), 0, h.stream, g, h.d_mu, X, n, d_cnt,
                        nullptr, nullptr, nullptr);
     RDD_HIP(hipGetLastError());
-    std::vector<int64_t> cnt(g.J);
-    RDD_TRY(download(h, cnt.data(), d_cnt, sizeof(int64_t) * g.J));
+    std::vector<int64_t> cnt(ncell), coff(ncell);
+    RDD_TRY(download(h, cnt.data(), d_cnt, sizeof(int64_t) * ncell));
     RDD_HIP(hipStreamSynchronize(h.stream));
-    dev_free(h, d_cnt);
     ps.row_off.assign(g.J + 1, 0);
-    for (int j = 0; j < g.J; ++j) ps.row_off[j + 1] = ps.row_off[j] + cnt[j];
+    for (int j = 0; j < g.J; ++j) {
+        int64_t o = ps.row_off[j];
+        for (int c = 0; c < nchunk; ++c) {
+            coff[(size_t)j * nchunk + c] = o;
+            o += cnt[(size_t)j * nchunk + c];
+        }
+        ps.row_off[j + 1] = o;
+    }
     ps.pairs = ps.row_off[g.J];
     if (ps.pairs >= (int64_t)INT32_MAX) {
         set_error("too many (point, subdomain) pairs");
@@ -358,9 +372,11 @@ int bin_points(Handle& h, const double* X, int64_t n, PointSet& ps) {
     RDD_TRY(dev_alloc(h, &ps.d_rows, (size_t)ps.pairs));
     RDD_TRY(dev_alloc(h, &ps.d_pair_sub, (size_t)ps.pairs));
     RDD_TRY(upload(h, ps.d_row_off, ps.row_off.data(), sizeof(int64_t) * (g.J + 1)));
-    hipLaunchKernelGGL((k_bin<true>), dim3(g.J), dim3(256), 0, h.stream, g, h.d_mu, X, n, nullptr,
-                       ps.d_row_off, ps.d_rows, ps.d_pair_sub);
+    RDD_TRY(upload(h, d_cnt, coff.data(), sizeof(int64_t) * ncell));  // chunk offsets
+    hipLaunchKernelGGL((k_bin<true>), dim3(g.J, nchunk), dim3(256), 0, h.stream, g, h.d_mu, X, n, nullptr,
+                       d_cnt, ps.d_rows, ps.d_pair_sub);
     RDD_HIP(hipGetLastError());
+    dev_free(h, d_cnt);
     // point -> pairs
     int64_t* d_cc = nullptr;
     RDD_TRY(dev_alloc(h, &d_cc, (size_t)n));
