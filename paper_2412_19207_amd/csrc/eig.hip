@@ -733,7 +733,15 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
                     if (u < n) z[i1 - u] = zv[u];
             }
             const double inv = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
-            for (int i = 0; i < m; ++i) z[i] *= inv;
+            for (int i0 = 0; i0 < m; i0 += 8) {
+                double zv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (i0 + u < m) zv[u] = z[i0 + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (i0 + u < m) z[i0 + u] = zv[u] * inv;
+            }
         }
     }
 }

@@ -75,13 +75,6 @@ __global__ void k_scale_shift(const int32_t* __restrict__ blks, const int64_t* _
     }
 }
 
-// value of v in lane l (l uniform), through the scalar unit
-__device__ __forceinline__ double read_lane(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
 // L_ss = chol(W_ss) (written to W) and X_ss = L_ss^{-1} (written to Xd) for
 // one diagonal tile, in one wave, in registers: lane r keeps row r of the
 // tile.  Cholesky (right-looking): at column c the pivot and the scaled

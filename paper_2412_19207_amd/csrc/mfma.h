@@ -167,4 +167,11 @@ __device__ void tile_gemm(TileAcc<T>& acc, T (*As)[kTM + kPad], T (*Bs)[kTN + kP
     }
 }
 
+// value of v in lane l (l uniform), through the scalar unit
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 }  // namespace rdd
