@@ -1,0 +1,99 @@
+// Pieces shared by the CG kernels and the normal-matrix product, which can
+// finish the previous CG iteration on the fly: with the direction update
+// p_new = z + beta p (beta = <r, z> / rho, per right-hand side, only where the
+// right-hand side is still active) folded into the product s = N p_new, the
+// separate direction-update launch disappears inside a check window.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rdd {
+
+// res[t] = sum over the nparts partials part[b * k + k0 + t], for t < kb:
+// the 256 / kb threads of each t read 8 partials at a time into 8
+// accumulators; accumulators and threads meet in a fixed-order tree
+__device__ inline void sum_partials_kb(const double* part, int nparts, int k, int k0, int kb, double* res,
+                                       double* sh) {
+    const int per = 256 / kb;
+    const int t = threadIdx.x % kb, ro = threadIdx.x / kb;
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    if (ro < per) {
+        int b = ro;
+        for (; b + 7 * per < nparts; b += 8 * per) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u * per) * k + k0 + t];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += v[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (b + u * per < nparts) acc[u] += part[(int64_t)(b + u * per) * k + k0 + t];
+    }
+    const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    sh[threadIdx.x] = (ro < per) ? a : 0.0;
+    __syncthreads();
+    for (int st = 1; st < per; st <<= 1) {
+        if (ro < per && (ro % (2 * st)) == 0 && ro + st < per) sh[threadIdx.x] += sh[threadIdx.x + st * kb];
+        __syncthreads();
+    }
+    if (threadIdx.x < kb) res[threadIdx.x] = sh[threadIdx.x];
+    __syncthreads();
+}
+
+// the previous iteration's direction update and bookkeeping, carried by a
+// normal-matrix product (pprev == nullptr: plain product of x)
+struct PUpd {
+    const double* pprev;     // p of the previous iteration
+    const double* z;         // preconditioned residual
+    double* pcur;            // p of this iteration (rows of the product's own slab rows)
+    const double* partB;     // partials of <r, r>  (nB workgroups)
+    const double* partC;     // partials of <r, z>
+    int nB;
+    const double* bn2;       // ||rhs||^2
+    const double* tol2;      // tolerance^2
+    const double* rho_in;    // rho of the previous iteration
+    double* rho_out;
+    const int32_t* act_in;   // activity of the previous iteration
+    int32_t* act_out;
+    int32_t* iters;
+    double* rres;            // recurrence residual
+};
+
+// beta and activity for the right-hand sides k0 .. k0 + kb - 1 into
+// beta_s / act_s (shared); workgroup 0 also writes the bookkeeping
+__device__ inline void pupd_begin(const PUpd& u, int k, int k0, int kb, double* beta_s, int* act_s, double* rz_s,
+                                  double* rr_s, double* sh) {
+    sum_partials_kb(u.partC, u.nB, k, k0, kb, rz_s, sh);
+    if (blockIdx.x == 0) sum_partials_kb(u.partB, u.nB, k, k0, kb, rr_s, sh);
+    if (threadIdx.x < kb) {
+        const int t = k0 + threadIdx.x;
+        const int act = u.act_in[t];
+        const double rz = rz_s[threadIdx.x];
+        beta_s[threadIdx.x] = act ? rz / u.rho_in[t] : 0.0;
+        act_s[threadIdx.x] = act;
+        if (blockIdx.x == 0) {
+            const double rr = rr_s[threadIdx.x];
+            u.rho_out[t] = act ? rz : u.rho_in[t];
+            u.act_out[t] = (act && !(rr <= u.tol2[t] * u.bn2[t])) ? 1 : 0;
+            if (act) {
+                u.iters[t] += 1;
+                u.rres[t] = sqrt(rr / u.bn2[t]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// p_new at flat index gi (right-hand side slot tl of the chunk)
+__device__ __forceinline__ double pupd_value(const PUpd& u, int64_t gi, int tl, const double* beta_s,
+                                             const int* act_s) {
+    const double pp = u.pprev[gi];
+    return act_s[tl] ? fma(beta_s[tl], pp, u.z[gi]) : pp;
+}
+
+}  // namespace rdd

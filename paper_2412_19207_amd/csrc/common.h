@@ -250,8 +250,12 @@ void release_gram(Handle& h);
 constexpr int kSlabRows = 16;       // slab rows per product workgroup
 // s = N x (N = H^T H from the slabs); with part != null also per-workgroup
 // partials of <x, s> at part[wg * k + t] (n_slab_tasks workgroups)
-// s = N x; with part, also the per-workgroup partials of <x, s>
-int launch_normal(Handle& h, const double* x, int k, double* s, double* part);
+// s = N x; with part, also the per-workgroup partials of <x, s>.  With pu,
+// x is the previous CG direction and the product first forms the new one
+// (p = z + beta p, written to pu->pcur) and the previous iteration's
+// bookkeeping (see cg_step.h); the partials are then those of <p, s>.
+struct PUpd;
+int launch_normal(Handle& h, const double* x, int k, double* s, double* part, const PUpd* pu = nullptr);
 
 int launch_Hx(Handle& h, const double* x, int k, double* y, bool scale_bnd);
 int launch_HTy(Handle& h, const double* y, int k, double* x, double* partial);

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <vector>
 
+#include "cg_step.h"
 #include "common.h"
 
 namespace rdd {
@@ -732,14 +733,17 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
                    const rann_dd_solve_opts& o, double* W, std::vector<int>& iters_out,
                    std::vector<double>& res_out, int* status) {
     const size_t P = (size_t)h.P, N = (size_t)h.N;
-    const size_t need = P * k * 4 + N * k + (size_t)h.part_total * k + (size_t)(2 * h.ub_total + 2 * h.slot_total) * k +
+    const size_t need = P * k * 5 + N * k + (size_t)h.part_total * k + (size_t)(2 * h.ub_total + 2 * h.slot_total) * k +
                         (size_t)kDotBlocks * k + 2 * (size_t)kRedMax * k + (size_t)h.n_slab_tasks * k + 24 * (size_t)k +
                         2048;
     RDD_TRY(ensure_ws(h, need * sizeof(double)));
     Scratch sc{static_cast<double*>(h.ws), 0};
     double* r = sc.take(P * k);
     double* z = sc.take(P * k);
-    double* p = sc.take(P * k);
+    double* pbuf[2];  // the direction, double-buffered (see the loop)
+    pbuf[0] = sc.take(P * k);
+    pbuf[1] = sc.take(P * k);
+    int pc = 0;
     double* s = sc.take(P * k);
     double* y = sc.take(N * k);
     double* part = sc.take((size_t)h.part_total * k);
@@ -790,7 +794,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
 
     auto restart = [&]() -> int {
         RDD_TRY(launch_precond(h, r, k, z, ub));
-        hipLaunchKernelGGL(k_copy, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, z, p);
+        hipLaunchKernelGGL(k_copy, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, z, pbuf[pc]);
         RDD_TRY(dot(h, P, k, r, z, dp, rhoB + (size_t)par * k));
         return RANN_OK;
     };
@@ -810,8 +814,21 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
             double* rho_out = rhoB + (size_t)(par ^ 1) * k;
             int32_t* act_in = activeB + (size_t)par * k;
             int32_t* act_out = activeB + (size_t)(par ^ 1) * k;
-            // s = H^T H p (assembled normal matrix) and partials of <p, s>
-            RDD_TRY(launch_normal(h, p, k, s, partA));
+            // s = H^T H p (assembled normal matrix) and partials of <p, s>.
+            // Inside a check window the previous iteration's direction update
+            // p = z + beta p and its bookkeeping ride on this product (into
+            // the other direction buffer); the window's last iteration does
+            // them itself, so the host always sees a finished iteration.
+            if (q > 0) {
+                const size_t pq = (size_t)(par ^ 1) * k;  // the previous iteration's state
+                const PUpd pu{pbuf[pc], z, pbuf[pc ^ 1], partB, partC, (int)rgrid, bn2, tol2v,
+                              rhoB + pq, rho_in, activeB + pq, act_in, iters, rres};
+                RDD_TRY(launch_normal(h, pbuf[pc], k, s, partA, &pu));
+                pc ^= 1;
+            } else {
+                RDD_TRY(launch_normal(h, pbuf[pc], k, s, partA));
+            }
+            double* p = pbuf[pc];
             hipLaunchKernelGGL(k_cg_xr2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k,
                                (int)h.n_slab_tasks, partA, rho_in, act_in, p, s, W, r, partB, flags);
             // z = M^{-1} r and partials of <r, z>
@@ -819,8 +836,9 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
             if (!ident) RDD_TRY(launch_precond_local(h, r, k, ub));
             hipLaunchKernelGGL(k_gather_dot, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, ident,
                                h.d_gat_off, h.d_gat, h.d_gat_w, ub, r, z, partC);
-            hipLaunchKernelGGL(k_cg_p2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, (int)rgrid, partB,
-                               partC, bn2, tol2v, rho_in, rho_out, act_in, act_out, iters, rres, z, p);
+            if (q + 1 == every || it + 1 >= o.maxiter)
+                hipLaunchKernelGGL(k_cg_p2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, (int)rgrid, partB,
+                                   partC, bn2, tol2v, rho_in, rho_out, act_in, act_out, iters, rres, z, p);
             par ^= 1;
             active = activeB + (size_t)par * k;
         }

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "common.h"
+#include "cg_step.h"
 #include "mfma.h"
 
 namespace rdd {
@@ -153,11 +154,15 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
                                                   const int32_t* __restrict__ N_cols,
                                                   const double* __restrict__ N,
                                                   const double* __restrict__ x, int k, int k0,
-                                                  double* __restrict__ s, double* __restrict__ part) {
+                                                  double* __restrict__ s, double* __restrict__ part,
+                                                  PUpd pu) {
     constexpr int kXS = 4096 / KB;      // staged columns per pass
     constexpr int kRW = kSlabRows / 4;  // rows per wave
     __shared__ double xs[kXS][KB];
     __shared__ double red[4][KB];
+    __shared__ double beta_s[KB], rz_s[KB], rr_s[KB], psh[256];
+    __shared__ int act_s[KB];
+    if (pu.pprev) pupd_begin(pu, k, k0, KB, beta_s, act_s, rz_s, rr_s, psh);
     const int2 tk = tasks[blockIdx.x];
     const int j = tk.x, r0 = tk.y;
     const int pj = p[j];
@@ -179,7 +184,8 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
         __syncthreads();
         for (int e = threadIdx.x; e < nc * KB; e += 256) {
             const int c = e / KB, t = e % KB;
-            xs[c][t] = x[(int64_t)cols[c0 + c] * k + k0 + t];
+            const int64_t gi = (int64_t)cols[c0 + c] * k + k0 + t;
+            xs[c][t] = pu.pprev ? pupd_value(pu, gi, t, beta_s, act_s) : x[gi];
         }
         __syncthreads();
         const double* Nr = Nj + (int64_t)(r0 + wave) * Q + c0;
@@ -206,7 +212,14 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
 #pragma unroll
             for (int t = 0; t < KB; ++t) {
                 s[g + t] = acc[u][t];
-                dotv[t] = fma(acc[u][t], x[g + t], dotv[t]);
+                double xv;
+                if (pu.pprev) {
+                    xv = pupd_value(pu, g + t, t, beta_s, act_s);
+                    pu.pcur[g + t] = xv;
+                } else {
+                    xv = x[g + t];
+                }
+                dotv[t] = fma(acc[u][t], xv, dotv[t]);
             }
         }
     }
@@ -237,11 +250,15 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
                                                   const int32_t* __restrict__ N_cols,
                                                   const double* __restrict__ N,
                                                   const double* __restrict__ x, int k, int k0,
-                                                  double* __restrict__ s, double* __restrict__ part) {
+                                                  double* __restrict__ s, double* __restrict__ part,
+                                                  PUpd pu) {
     constexpr int NB = KC / 16;
     static_assert(kSlabRows == 16, "one 16-row MFMA block per task");
     __shared__ double red[4][16][KC + 1];
     __shared__ double dsh[256];
+    __shared__ double beta_s[KC], rz_s[KC], rr_s[KC];
+    __shared__ int act_s[KC];
+    if (pu.pprev) pupd_begin(pu, k, k0, KC, beta_s, act_s, rz_s, rr_s, dsh);
     const int2 tk = tasks[blockIdx.x];
     const int j = tk.x, r0 = tk.y;
     const int pj = p[j];
@@ -271,7 +288,11 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
         for (int u = 0; u < 16; ++u)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const double bv = (ci[u] >= 0) ? x[(int64_t)ci[u] * k + k0 + 16 * nb + lr] : 0.0;
+                double bv = 0.0;
+                if (ci[u] >= 0) {
+                    const int64_t gi = (int64_t)ci[u] * k + k0 + 16 * nb + lr;
+                    bv = pu.pprev ? pupd_value(pu, gi, 16 * nb + lr, beta_s, act_s) : x[gi];
+                }
                 acc[nb] = Mfma<double>::mma(av[u], bv, acc[nb]);
             }
     }
@@ -287,7 +308,14 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
         if (r0 + rr < pj) {
             const int64_t gi = (col_off[j] + r0 + rr) * k + k0 + t;
             s[gi] = v;
-            dotv = fma(v, x[gi], dotv);
+            double xv;
+            if (pu.pprev) {
+                xv = pupd_value(pu, gi, t, beta_s, act_s);
+                pu.pcur[gi] = xv;
+            } else {
+                xv = x[gi];
+            }
+            dotv = fma(v, xv, dotv);
         }
     }
     if (part) {
@@ -423,7 +451,9 @@ int launch_HTy_part(Handle& h, const double* y, int k, double* part) {
 
 namespace rdd {
 
-int launch_normal(Handle& h, const double* x, int k, double* s, double* part) {
+int launch_normal(Handle& h, const double* x, int k, double* s, double* part, const PUpd* pup) {
+    PUpd pu{};
+    if (pup) pu = *pup;
     KTimer kt_(h.stream, "k_normal");
     for (int k0 = 0; k0 < k;) {
         const int rem = k - k0;
@@ -433,11 +463,11 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part) {
                 if (kc == 32)
                     hipLaunchKernelGGL((k_nrm_mfma<32>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,
                                        h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff, h.d_N_cols,
-                                       h.d_N, x, k, k0, s, part);
+                                       h.d_N, x, k, k0, s, part, pu);
                 else
                     hipLaunchKernelGGL((k_nrm_mfma<16>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,
                                        h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff, h.d_N_cols,
-                                       h.d_N, x, k, k0, s, part);
+                                       h.d_N, x, k, k0, s, part, pu);
             }
             k0 += kc;
             continue;
@@ -446,7 +476,7 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part) {
 #define RDD_NS(KBV)                                                                                 \
     hipLaunchKernelGGL((k_nrm_slab<KBV>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,   \
                        h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff, h.d_N_cols, h.d_N, \
-                       x, k, k0, s, part)
+                       x, k, k0, s, part, pu)
         if (h.n_slab_tasks) {
             switch (kb) {
                 case 8: RDD_NS(8); break;
