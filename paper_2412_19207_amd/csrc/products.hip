@@ -182,21 +182,40 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
     for (int64_t c0 = 0; c0 < Q; c0 += kXS) {
         const int nc = (Q - c0 < kXS) ? (int)(Q - c0) : kXS;
         __syncthreads();
-        for (int e = threadIdx.x; e < nc * KB; e += 256) {
-            const int c = e / KB, t = e % KB;
-            const int64_t gi = (int64_t)cols[c0 + c] * k + k0 + t;
-            xs[c][t] = pu.pprev ? pupd_value(pu, gi, t, beta_s, act_s) : x[gi];
+        // 4 entries per thread and round, so that their loads are in flight together
+        for (int e0 = threadIdx.x; e0 < nc * KB; e0 += 4 * 256) {
+            int64_t gi[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int e = e0 + v * 256;
+                gi[v] = (e < nc * KB) ? (int64_t)cols[c0 + e / KB] * k + k0 + e % KB : -1;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int e = e0 + v * 256;
+                if (gi[v] >= 0) xs[e / KB][e % KB] = pu.pprev ? pupd_value(pu, gi[v], e % KB, beta_s, act_s) : x[gi[v]];
+            }
         }
         __syncthreads();
         const double* Nr = Nj + (int64_t)(r0 + wave) * Q + c0;
-        for (int c = lane; c < nc; c += 64) {
-            double nv[kRW];
+        for (int cb = lane; cb < nc; cb += 4 * 64) {
+            double nv[4][kRW];
 #pragma unroll
-            for (int u = 0; u < kRW; ++u) nv[u] = (u < nrow) ? Nr[(int64_t)4 * u * Q + c] : 0.0;
+            for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int u = 0; u < kRW; ++u)
+                for (int u = 0; u < kRW; ++u) {
+                    const int c = cb + v * 64;
+                    nv[v][u] = (u < nrow && c < nc) ? Nr[(int64_t)4 * u * Q + c] : 0.0;
+                }
 #pragma unroll
-                for (int t = 0; t < KB; ++t) acc[u][t] = fma(nv[u], xs[c][t], acc[u][t]);
+            for (int v = 0; v < 4; ++v) {
+                const int c = cb + v * 64;
+                if (c < nc)
+#pragma unroll
+                    for (int u = 0; u < kRW; ++u)
+#pragma unroll
+                        for (int t = 0; t < KB; ++t) acc[u][t] = fma(nv[v][u], xs[c][t], acc[u][t]);
+            }
         }
     }
     double dotv[KB];
