@@ -245,6 +245,8 @@ __global__ void k_gmres_deactivate(int k, double tol, const double* __restrict__
 
 // ------------------------------------------------------------------ probes
 // value of each (probe, subdomain) pair: P0 * sum_f c_f tanh(z_f)
+// val[pair] = P0 sum_f c_f tanh(z_f): 16 pairs per workgroup, 16 lanes per
+// pair each summing every 16th feature, lanes meeting by shuffles
 template <int KB>
 __global__ void __launch_bounds__(256) k_eval_pairs(Geo g, int64_t pairs, const int32_t* __restrict__ pair_sub,
                                                     const double* __restrict__ rec,
@@ -254,23 +256,33 @@ __global__ void __launch_bounds__(256) k_eval_pairs(Geo g, int64_t pairs, const 
                                                     const double* __restrict__ bf,
                                                     const double* __restrict__ cf, int k, int k0,
                                                     double* __restrict__ val) {
-    int64_t pid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (pid >= pairs) return;
-    const int j = pair_sub[pid];
-    const double* rr = rec + pid * kPairRec;
+    const int64_t pid = blockIdx.x * 16LL + (threadIdx.x >> 4);
+    const int fl = threadIdx.x & 15;
+    const bool live = pid < pairs;
+    const int j = live ? pair_sub[pid] : 0;
+    const double* rr = rec + (live ? pid : 0) * kPairRec;
     double xt[kMaxDim];
     for (int i = 0; i < kMaxDim; ++i) xt[i] = rr[kRecX + i];
     double acc[KB];
+#pragma unroll
     for (int t = 0; t < KB; ++t) acc[t] = 0.0;
-    for (int f = 0; f < m[j]; ++f) {
+    const int mj = live ? m[j] : 0;
+    for (int f = fl; f < mj; f += 16) {
         const int64_t gf = m_off[j] + f;
         double z = bf[gf];
         for (int i = 0; i < g.d; ++i) z = fma(Rf[gf * 4 + i], xt[i], z);
         const double th = tanh(z);
+#pragma unroll
         for (int t = 0; t < KB; ++t) acc[t] = fma(th, cf[gf * k + k0 + t], acc[t]);
     }
-    const double P0 = rr[kRecP0];
-    for (int t = 0; t < KB; ++t) val[pid * k + k0 + t] = P0 * acc[t];
+#pragma unroll
+    for (int t = 0; t < KB; ++t)
+        for (int off = 1; off < 16; off <<= 1) acc[t] += __shfl_xor(acc[t], off);
+    if (live && fl == 0) {
+        const double P0 = rr[kRecP0];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) val[pid * k + k0 + t] = P0 * acc[t];
+    }
 }
 
 __global__ void k_point_sum(int64_t n, int k, const int64_t* __restrict__ cover_off,
@@ -345,43 +357,55 @@ __global__ void k_eval_T_sum(int64_t n, int nz, const double* __restrict__ part,
     dc[idx] = s;
 }
 
-// c_j = V_j W_j (raw-neuron coefficients) and its transpose
-__global__ void k_coeffs(int64_t sum_m, int k, const int32_t* __restrict__ feat_sub,
-                         const int64_t* __restrict__ m_off, const int32_t* __restrict__ p,
-                         const int64_t* __restrict__ v_off, const int64_t* __restrict__ col_off,
-                         const double* __restrict__ V, const double* __restrict__ W,
-                         double* __restrict__ c) {
-    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= sum_m * k) return;
-    const int64_t gf = idx / k;
-    const int t = (int)(idx % k);
-    const int j = feat_sub[gf];
-    const int64_t f = gf - m_off[j];
-    const int pj = p[j];
-    const double* Vr = V + v_off[j] + f * pj;
-    const double* Wj = W + col_off[j] * k + t;
+// c_j = V_j W_j (raw-neuron coefficients) and its transpose: 16 outputs per
+// workgroup, 16 lanes per output each summing every 16th term, lanes meeting
+// by shuffles
+__global__ void __launch_bounds__(256) k_coeffs(int64_t sum_m, int k, const int32_t* __restrict__ feat_sub,
+                                                const int64_t* __restrict__ m_off, const int32_t* __restrict__ p,
+                                                const int64_t* __restrict__ v_off,
+                                                const int64_t* __restrict__ col_off,
+                                                const double* __restrict__ V, const double* __restrict__ W,
+                                                double* __restrict__ c) {
+    const int64_t idx = blockIdx.x * 16LL + (threadIdx.x >> 4);
+    const int ql = threadIdx.x & 15;
+    const bool live = idx < sum_m * k;
     double s = 0.0;
-    for (int q = 0; q < pj; ++q) s = fma(Vr[q], Wj[(int64_t)q * k], s);
-    c[idx] = s;
+    if (live) {
+        const int64_t gf = idx / k;
+        const int t = (int)(idx % k);
+        const int j = feat_sub[gf];
+        const int64_t f = gf - m_off[j];
+        const int pj = p[j];
+        const double* Vr = V + v_off[j] + f * pj;
+        const double* Wj = W + col_off[j] * k + t;
+        for (int q = ql; q < pj; q += 16) s = fma(Vr[q], Wj[(int64_t)q * k], s);
+    }
+    for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off);
+    if (live && ql == 0) c[idx] = s;
 }
 
-__global__ void k_coeffs_T(int64_t P, int k, const int32_t* __restrict__ col_sub,
-                           const int64_t* __restrict__ m_off, const int32_t* __restrict__ m,
-                           const int32_t* __restrict__ p, const int64_t* __restrict__ v_off,
-                           const int64_t* __restrict__ col_off, const double* __restrict__ V,
-                           const double* __restrict__ dc, double* __restrict__ dW) {
-    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= P * k) return;
-    const int64_t gcol = idx / k;
-    const int t = (int)(idx % k);
-    const int j = col_sub[gcol];
-    const int64_t q = gcol - col_off[j];
-    const int pj = p[j];
-    const double* Vj = V + v_off[j];
-    const double* dcj = dc + m_off[j] * k + t;
+__global__ void __launch_bounds__(256) k_coeffs_T(int64_t P, int k, const int32_t* __restrict__ col_sub,
+                                                  const int64_t* __restrict__ m_off, const int32_t* __restrict__ m,
+                                                  const int32_t* __restrict__ p, const int64_t* __restrict__ v_off,
+                                                  const int64_t* __restrict__ col_off,
+                                                  const double* __restrict__ V, const double* __restrict__ dc,
+                                                  double* __restrict__ dW) {
+    const int64_t idx = blockIdx.x * 16LL + (threadIdx.x >> 4);
+    const int fl = threadIdx.x & 15;
+    const bool live = idx < P * k;
     double s = 0.0;
-    for (int f = 0; f < m[j]; ++f) s = fma(Vj[(int64_t)f * pj + q], dcj[(int64_t)f * k], s);
-    dW[idx] = s;
+    if (live) {
+        const int64_t gcol = idx / k;
+        const int t = (int)(idx % k);
+        const int j = col_sub[gcol];
+        const int64_t q = gcol - col_off[j];
+        const int pj = p[j];
+        const double* Vj = V + v_off[j];
+        const double* dcj = dc + m_off[j] * k + t;
+        for (int f = fl; f < m[j]; f += 16) s = fma(Vj[(int64_t)f * pj + q], dcj[(int64_t)f * k], s);
+    }
+    for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off);
+    if (live && fl == 0) dW[idx] = s;
 }
 
 // ------------------------------------------------------------------ fused CG pieces
@@ -1192,10 +1216,10 @@ int adjoint_gmres(Handle& h, const double* dW, int k, const rann_dd_solve_opts& 
 // ------------------------------------------------------------------ probes
 int coeffs_raw(Handle& h, const double* W, int k, double* c, bool transpose) {
     if (!transpose) {
-        hipLaunchKernelGGL(k_coeffs, dim3(grid_for(h.sum_m * k)), dim3(256), 0, h.stream, h.sum_m, k,
+        hipLaunchKernelGGL(k_coeffs, dim3((unsigned)((h.sum_m * k + 15) / 16)), dim3(256), 0, h.stream, h.sum_m, k,
                            h.d_feat_sub, h.d_m_off, h.d_p, h.d_v_off, h.d_col_off, h.d_V, W, c);
     } else {
-        hipLaunchKernelGGL(k_coeffs_T, dim3(grid_for(h.P * k)), dim3(256), 0, h.stream, h.P, k,
+        hipLaunchKernelGGL(k_coeffs_T, dim3((unsigned)((h.P * k + 15) / 16)), dim3(256), 0, h.stream, h.P, k,
                            h.d_col_sub, h.d_m_off, h.d_m, h.d_p, h.d_v_off, h.d_col_off, h.d_V, W, c);
     }
     RDD_HIP(hipGetLastError());
@@ -1223,7 +1247,7 @@ int eval_points(Handle& h, const double* Xq, int64_t M, const double* Lq, const 
         for (int k0 = 0; rc == RANN_OK && k0 < k;) {
             int kb = kb_for(k - k0);
 #define RDD_EV(KBV)                                                                                    \
-    hipLaunchKernelGGL((k_eval_pairs<KBV>), dim3(grid_for(ps.pairs)), dim3(256), 0, h.stream, h.geo, \
+    hipLaunchKernelGGL((k_eval_pairs<KBV>), dim3((unsigned)((ps.pairs + 15) / 16)), dim3(256), 0, h.stream, h.geo, \
                        ps.pairs, ps.d_pair_sub, ps.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, cf, k, k0, \
                        val)
             switch (kb) {
