@@ -156,6 +156,127 @@ __global__ void __launch_bounds__(256) k_tile_apply(const int4* __restrict__ tas
     }
 }
 
+// The same tile products for the symmetric FP64 W with 1 or 2 right-hand
+// sides, persistent: workgroup w takes the tiles w, w + G, ... (G = grid
+// size) and loads the next tile, its task record and its x values while the
+// current tile is multiplied.  A tile is read with whole-line loads (thread t
+// takes the 16-byte pieces t, t + 256, ...) into LDS, from where the row sums
+// read rows and the column sums read columns.
+template <int KB>
+__global__ void __launch_bounds__(256) k_tile_apply_ps(const int4* __restrict__ tasks, int ntasks,
+                                                       const int64_t* __restrict__ t_off,
+                                                       const int64_t* __restrict__ qv,
+                                                       const int64_t* __restrict__ ub_off,
+                                                       const int64_t* __restrict__ s_off,
+                                                       const int32_t* __restrict__ blk_cols,
+                                                       const double* __restrict__ M,
+                                                       const double* __restrict__ r, int k, int k0,
+                                                       double* __restrict__ Rs, double* __restrict__ Cs) {
+    static_assert(KB <= 2, "one staged x value per thread");
+    constexpr int kTS = kT + 2;  // LDS row stride (16-byte aligned rows)
+    __shared__ double xb[kT][KB];
+    __shared__ double xa[kT][KB];
+    __shared__ __attribute__((aligned(16))) double ts[kT * kTS];
+    const int tid = threadIdx.x, row = tid >> 2, seg = tid & 3;
+    const int col = tid >> 2, rq = tid & 3;
+    // thread tid < 64 KB stages x_b entry tid, 64 KB <= tid < 128 KB stages x_a
+    const bool sb = tid < kT * KB, sa = !sb && tid < 2 * kT * KB;
+    const int se = sb ? tid : tid - kT * KB;
+    const int sc = se / KB, st = se % KB;
+    int task = blockIdx.x;
+    if (task >= ntasks) return;
+#define RDD_PS_FETCH(TK_I, TK, V, XR, SO)                                                      \
+    {                                                                                         \
+        TK = tasks[TK_I];                                                                     \
+        const int i_ = TK.x, a_ = TK.y, b_ = TK.z;                                            \
+        const int64_t q_ = qv[i_];                                                            \
+        const int64_t tile_ = (int64_t)a_ * (a_ + 1) / 2 + b_;                                \
+        const double2* src_ = reinterpret_cast<const double2*>(M + t_off[i_] + tile_ * kTE);  \
+        _Pragma("unroll") for (int e = 0; e < 8; ++e) {                                      \
+            const double2 w_ = src_[e * 256 + tid];                                           \
+            V[2 * e] = w_.x;                                                                  \
+            V[2 * e + 1] = w_.y;                                                              \
+        }                                                                                     \
+        SO = (s_off[i_] + tile_ * kT) * k + k0;                                               \
+        XR = 0.0;                                                                             \
+        if (sb || (sa && a_ != b_)) {                                                         \
+            const int64_t gc_ = (int64_t)(sb ? b_ : a_) * kT + sc;                            \
+            if (gc_ < q_) XR = r[(int64_t)blk_cols[ub_off[i_] + gc_] * k + k0 + st];          \
+        }                                                                                     \
+    }
+    int4 tk;
+    double v[16];
+    double xr;
+    int64_t so;
+    RDD_PS_FETCH(task, tk, v, xr, so)
+    while (true) {
+        const bool do_c = tk.y != tk.z;
+        const int64_t q = qv[tk.x];
+        const int cmax = (int)((q - (int64_t)tk.z * kT) < kT ? q - (int64_t)tk.z * kT : kT);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int ch = e * 256 + tid;  // 16-byte piece: row ch / 32, columns 2 (ch % 32) ..
+            *reinterpret_cast<double2*>(ts + (ch >> 5) * kTS + 2 * (ch & 31)) = make_double2(v[2 * e], v[2 * e + 1]);
+        }
+        if (sb) xb[sc][st] = xr;
+        if (sa) xa[sc][st] = xr;
+        __syncthreads();
+        const int next = task + gridDim.x;
+        int4 tkn;
+        double vn[16];
+        double xrn;
+        int64_t son;
+        RDD_PS_FETCH(next < ntasks ? next : task, tkn, vn, xrn, son)  // the last round reloads its own tile
+        // row sums: thread (row, seg) over 16 columns
+        double acc[KB];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) acc[t] = 0.0;
+        const double* tr = ts + row * kTS + seg * 16;
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc)
+#pragma unroll
+            for (int t = 0; t < KB; ++t) acc[t] = fma(tr[cc], xb[seg * 16 + cc][t], acc[t]);
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+            acc[t] += __shfl_xor(acc[t], 1);
+            acc[t] += __shfl_xor(acc[t], 2);
+        }
+        if (seg == 0)
+#pragma unroll
+            for (int t = 0; t < KB; ++t) Rs[so + (int64_t)row * k + t] = acc[t];
+        // column sums: thread (col, rq) over the rows rq, rq + 4, ...
+        if (do_c) {
+            double c[KB];
+#pragma unroll
+            for (int t = 0; t < KB; ++t) c[t] = 0.0;
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                const int rw = rq + 4 * rr;
+                const double tv = ts[rw * kTS + col];
+#pragma unroll
+                for (int t = 0; t < KB; ++t) c[t] = fma(tv, xa[rw][t], c[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < KB; ++t) {
+                c[t] += __shfl_xor(c[t], 1);
+                c[t] += __shfl_xor(c[t], 2);
+            }
+            if (rq == 0 && col < cmax)
+#pragma unroll
+                for (int t = 0; t < KB; ++t) Cs[so + (int64_t)col * k + t] = c[t];
+        }
+        __syncthreads();  // xb, xa and ts are free for the next tile
+        if (next >= ntasks) break;
+        task = next;
+        tk = tkn;
+        so = son;
+        xr = xrn;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = vn[e];
+    }
+#undef RDD_PS_FETCH
+}
+
 // One (block, tile row a) of the triangular factor (mixed path): u_a = sum_b
 // Y_ab x_b over the contiguous tiles (a, 0..a), then C(a, b) = Y_ab^T u_a for
 // every b <= a, the tile row read a second time (from cache); the next tile
@@ -793,6 +914,17 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
                 case 2: RDD_TR(2); break;
                 default: RDD_TR(1); break;
             }
+        } else if (kb <= 2) {
+            // persistent over about two workgroups per compute unit
+            const unsigned pg = std::min<unsigned>(tgrid, 512u);
+            if (kb == 2)
+                hipLaunchKernelGGL((k_tile_apply_ps<2>), dim3(pg), dim3(256), 0, h.stream, h.d_tile_tasks,
+                                   (int)h.n_tile_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols,
+                                   h.d_M64, r, k, k0, Rs, Cs);
+            else
+                hipLaunchKernelGGL((k_tile_apply_ps<1>), dim3(pg), dim3(256), 0, h.stream, h.d_tile_tasks,
+                                   (int)h.n_tile_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols,
+                                   h.d_M64, r, k, k0, Rs, Cs);
         } else {
             RDD_TA_KB(double, h.d_M64, true, true, false, true);
         }
