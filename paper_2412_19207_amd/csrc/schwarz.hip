@@ -279,8 +279,10 @@ __global__ void __launch_bounds__(256) k_tile_apply_ps(const int4* __restrict__ 
 
 // One (block, tile row a) of the triangular factor (mixed path): u_a = sum_b
 // Y_ab x_b over the contiguous tiles (a, 0..a), then C(a, b) = Y_ab^T u_a for
-// every b <= a, the tile row read a second time (from cache); the next tile
-// is loaded while the current one is used.
+// every b <= a, the tile row read a second time (from cache).  Tiles are read
+// with whole-line loads (thread t takes the 16-byte pieces t, t + 256, ...)
+// into one of two LDS buffers, the next tile in flight meanwhile; row sums
+// read LDS rows, column sums LDS columns.
 template <int KB>
 __global__ void __launch_bounds__(256) k_trirow_apply(const int2* __restrict__ tasks,
                                                       const int64_t* __restrict__ t_off,
@@ -291,22 +293,39 @@ __global__ void __launch_bounds__(256) k_trirow_apply(const int2* __restrict__ t
                                                       const float* __restrict__ Y,
                                                       const double* __restrict__ r, int k, int k0,
                                                       double* __restrict__ Cs) {
-    constexpr int kXC = 8;                // tiles of x staged per chunk
+    constexpr int kXC = 8;       // tiles of x staged per chunk
+    constexpr int kTS = kT + 4;  // LDS row stride in floats (16-byte aligned rows)
     __shared__ double xs[kXC * kT][KB];
     __shared__ double ua[kT][KB];
-    __shared__ float ts[2][kT][kT + 1];
+    __shared__ __attribute__((aligned(16))) float ts[2][kT * kTS];
     const int2 tk = tasks[blockIdx.x];
     const int i = tk.x, a = tk.y;
     const int64_t q = qv[i];
     const int tid = threadIdx.x, row = tid >> 2, seg = tid & 3;
-    const float* Ya = Y + t_off[i] + (int64_t)a * (a + 1) / 2 * kTE + row * kT + seg * 16;
+    const int col = tid >> 2, rq = tid & 3;
+    const float4* Ya = reinterpret_cast<const float4*>(Y + t_off[i] + (int64_t)a * (a + 1) / 2 * kTE);
     const int32_t* cols = blk_cols + ub_off[i];
     double* cla = Cs + s_off[i] * k + k0 + (int64_t)a * (a + 1) / 2 * kT * k;  // slot (a, b) at cla + b kT k
+    // 16-byte piece ch = e 256 + tid of a tile: row ch / 16, columns 4 (ch % 16) ..
+#define RDD_TR_PUT(DST, V)                                                                              \
+    _Pragma("unroll") for (int e = 0; e < 4; ++e) {                                                      \
+        const int ch = e * 256 + tid;                                                                    \
+        *reinterpret_cast<float4*>(DST + (ch >> 4) * kTS + 4 * (ch & 15)) =                             \
+            make_float4(V[4 * e], V[4 * e + 1], V[4 * e + 2], V[4 * e + 3]);                             \
+    }
+#define RDD_TR_GET(V, TILE)                                                                              \
+    _Pragma("unroll") for (int e = 0; e < 4; ++e) {                                                      \
+        const float4 w_ = Ya[(int64_t)(TILE) * (kTE / 4) + e * 256 + tid];                              \
+        V[4 * e] = w_.x;                                                                                 \
+        V[4 * e + 1] = w_.y;                                                                             \
+        V[4 * e + 2] = w_.z;                                                                             \
+        V[4 * e + 3] = w_.w;                                                                             \
+    }
     double acc[KB];
 #pragma unroll
     for (int t = 0; t < KB; ++t) acc[t] = 0.0;
     float v[16], vn[16];
-    load16(Ya, v);
+    RDD_TR_GET(v, 0)
     for (int b = 0; b <= a; ++b) {
         const int bb = b % kXC;
         if (bb == 0) {
@@ -317,17 +336,19 @@ __global__ void __launch_bounds__(256) k_trirow_apply(const int2* __restrict__ t
                 const int64_t gc = (int64_t)b * kT + c;
                 xs[c][t] = (gc < q) ? r[(int64_t)cols[gc] * k + k0 + t] : 0.0;
             }
-            __syncthreads();
         }
-        if (b < a) load16(Ya + (int64_t)(b + 1) * kTE, vn);
+        float* tb = ts[b & 1];
+        RDD_TR_PUT(tb, v)
+        __syncthreads();
+        RDD_TR_GET(vn, (b < a) ? b + 1 : b)
+        const float* trow = tb + row * kTS + seg * 16;
         const double (*xr)[KB] = xs + bb * kT + seg * 16;
 #pragma unroll
         for (int cc = 0; cc < 16; ++cc)
 #pragma unroll
-            for (int t = 0; t < KB; ++t) acc[t] = fma((double)v[cc], xr[cc][t], acc[t]);
-        if (b < a)
+            for (int t = 0; t < KB; ++t) acc[t] = fma((double)trow[cc], xr[cc][t], acc[t]);
 #pragma unroll
-            for (int cc = 0; cc < 16; ++cc) v[cc] = vn[cc];
+        for (int e = 0; e < 16; ++e) v[e] = vn[e];
     }
 #pragma unroll
     for (int t = 0; t < KB; ++t) {
@@ -337,16 +358,37 @@ __global__ void __launch_bounds__(256) k_trirow_apply(const int2* __restrict__ t
     if (seg == 0)
 #pragma unroll
         for (int t = 0; t < KB; ++t) ua[row][t] = acc[t];
-    load16(Ya, v);
-    __syncthreads();
+    RDD_TR_GET(v, 0)
+    __syncthreads();  // u_a complete; both LDS buffers free
     for (int b = 0; b <= a; ++b) {
-        if (b < a) load16(Ya + (int64_t)(b + 1) * kTE, vn);
+        float* tb = ts[b & 1];
+        RDD_TR_PUT(tb, v)
+        __syncthreads();
+        RDD_TR_GET(vn, (b < a) ? b + 1 : b)
         const int cmax = (int)((q - (int64_t)b * kT) < kT ? q - (int64_t)b * kT : kT);
-        tile_colsum<float, KB>(v, ua, ts[b & 1], cla + (int64_t)b * kT * k, k, cmax);
-        if (b < a)
+        double c[KB];
 #pragma unroll
-            for (int cc = 0; cc < 16; ++cc) v[cc] = vn[cc];
+        for (int t = 0; t < KB; ++t) c[t] = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int rw = rq + 4 * rr;
+            const double tv = (double)tb[rw * kTS + col];
+#pragma unroll
+            for (int t = 0; t < KB; ++t) c[t] = fma(tv, ua[rw][t], c[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+            c[t] += __shfl_xor(c[t], 1);
+            c[t] += __shfl_xor(c[t], 2);
+        }
+        if (rq == 0 && col < cmax)
+#pragma unroll
+            for (int t = 0; t < KB; ++t) cla[(int64_t)b * kT * k + (int64_t)col * k + t] = c[t];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = vn[e];
     }
+#undef RDD_TR_GET
+#undef RDD_TR_PUT
 }
 
 // Batched right-hand sides (KC = 16 or 32 of them per launch) on the matrix
