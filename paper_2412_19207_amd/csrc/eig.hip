@@ -35,7 +35,7 @@ namespace rdd {
 
 namespace {
 
-constexpr int kNB = 32;                  // panel width of the blocked reduction
+constexpr int kNB = 16;                  // panel width of the blocked reduction (a multiple of kTK)
 constexpr int kPT = 1024;                // threads of the panel and solve kernels
 constexpr int kPC = 64, kPG = kPT / kPC; // 64 columns x 16 row groups
 
@@ -263,6 +263,7 @@ __global__ void __launch_bounds__(256) k_tri_update(const int4* __restrict__ tas
     TileAcc<double> acc;
     acc.zero();
     const int t = threadIdx.x;
+    static_assert(kNB % kTK == 0, "whole staging slices of reflector rows");
     for (int half = 0; half < 2; ++half) {
         const double* L = half ? Wr : Vr;  // left operand rows, k = reflector index
         const double* R = half ? Vr : Wr;
