@@ -756,7 +756,6 @@ int build_schwarz(Handle& h) {
     h.factor_elems = h.f_off[J];
     // block entry -> global column, and the gather lists
     std::vector<int32_t> blk_cols(ub_off[J]);
-    std::vector<std::vector<std::pair<int64_t, double>>> per_col(h.P);
     std::vector<int> mult(h.P, 0);
     for (int i = 0; i < J; ++i) {
         int64_t e = ub_off[i];
@@ -767,40 +766,56 @@ int build_schwarz(Handle& h) {
                 mult[gcol]++;
             }
     }
+    std::vector<int64_t> gat;
+    std::vector<double> gat_w;
+    int64_t* gat_ = nullptr;
+    double* gatw_ = nullptr;
     PrecondPlan plan;
     plan.row_start.assign(J, 0);
     plan.row_cnt.assign(J, 0);
-    for (int i = 0; i < J; ++i) {
-        int64_t e = ub_off[i], pos = 0;
-        for (int j : h.sten[i]) {
-            for (int c = 0; c < h.p[j]; ++c) {
-                int64_t gcol = h.col_off[j] + c;
-                double w = 1.0;
-                bool use = true;
-                if (h.precond == RANN_PRECOND_SAS) w = 1.0 / (double)mult[gcol];
-                if (h.precond == RANN_PRECOND_RAS) use = (j == i);
-                if (use) per_col[gcol].push_back({e, w});
-                ++e;
+    // gather lists (CSR over global columns, entries in block order): count,
+    // then fill
+    std::vector<int64_t> gat_off(h.P + 1, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<int64_t> fill;
+        if (pass == 1) {
+            for (int64_t g = 0; g < h.P; ++g) gat_off[g + 1] += gat_off[g];
+            fill.assign(gat_off.begin(), gat_off.end() - 1);
+        }
+        for (int i = 0; i < J; ++i) {
+            int64_t e = ub_off[i], pos = 0;
+            for (int j : h.sten[i]) {
+                const bool use = (h.precond != RANN_PRECOND_RAS) || (j == i);
+                for (int c = 0; c < h.p[j]; ++c, ++e) {
+                    if (!use) continue;
+                    const int64_t gcol = h.col_off[j] + c;
+                    if (pass == 0) {
+                        gat_off[gcol + 1]++;
+                    } else {
+                        const int64_t slot = fill[gcol]++;
+                        gat_[slot] = e;
+                        gatw_[slot] = (h.precond == RANN_PRECOND_SAS) ? 1.0 / (double)mult[gcol] : 1.0;
+                    }
+                }
+                if (pass == 0 && j == i) {
+                    plan.row_start[i] = pos;
+                    plan.row_cnt[i] = h.p[j];
+                }
+                pos += h.p[j];
             }
-            if (j == i) {
-                plan.row_start[i] = pos;
-                plan.row_cnt[i] = h.p[j];
+            if (pass == 0 && h.precond != RANN_PRECOND_RAS) {
+                plan.row_start[i] = 0;
+                plan.row_cnt[i] = h.q[i];
             }
-            pos += h.p[j];
         }
-        if (h.precond != RANN_PRECOND_RAS) {
-            plan.row_start[i] = 0;
-            plan.row_cnt[i] = h.q[i];
+        if (pass == 0) {
+            int64_t tot = 0;
+            for (int64_t g = 0; g < h.P; ++g) tot += gat_off[g + 1];
+            gat.resize((size_t)tot);
+            gat_w.resize((size_t)tot);
+            gat_ = gat.data();
+            gatw_ = gat_w.data();
         }
-    }
-    std::vector<int64_t> gat_off(h.P + 1, 0), gat;
-    std::vector<double> gat_w;
-    for (int64_t g = 0; g < h.P; ++g) {
-        for (auto& pr : per_col[g]) {
-            gat.push_back(pr.first);
-            gat_w.push_back(pr.second);
-        }
-        gat_off[g + 1] = (int64_t)gat.size();
     }
     // device copies
     RDD_TRY(dev_alloc(h, &h.d_f_off, J + 1));
