@@ -4,6 +4,14 @@
          independent recurrence per right-hand side.
 * gmres: left-preconditioned restarted GMRES (any M, e.g. RAS/SAS), modified
          Gram-Schmidt Arnoldi and Givens rotations.
+* cgs  : conjugate gradients squared (Sonneveld), transpose-free, with the
+         preconditioner applied to the search directions (any M).
+* bicg : biconjugate gradients (Fletcher) with the shadow system driven by
+         A^T and M^{-T} (any M).
+The paper compares CG, CGS, BiCG and GMRES with the AS, SAS and RAS
+preconditioners (Sec. 5, Example 1, Table 1b).  CGS and BiCG stop on the
+recurrence residual b - A x (the normal residual in exact arithmetic),
+confirmed by the recomputed one.
 
 Stopping rules (reading): the paper stops on the left-preconditioned residual
 ||M^{-1}(H^T H W - H^T F)|| / ||M^{-1} H^T F|| (Sec. 5, Example 1).  Here PCG
@@ -123,4 +131,132 @@ def gmres(A, M, b, x0=None, restart=50, tol=1e-5, maxiter=1000, side="left"):
             r = pre(b - A(x))
             if np.linalg.norm(r) / mb <= tol:
                 break
+    return x, it, hist
+
+
+def cgs(A, M, b, x0=None, tol=1e-10, maxiter=1000, true_res=None, shadow="r"):
+    """Conjugate gradients squared for one right-hand side b (P,).  In exact
+    arithmetic the residual after i steps is phi_i(A M^{-1})^2 r_0, phi_i being
+    the residual polynomial of BiCG on A M^{-1} with the shadow residual r~
+    (shadow "r": r~ = r_0, the usual choice; "Mr": r~ = M^{-1} r_0, for which
+    phi_i is the polynomial of preconditioned CG when A and M are symmetric)."""
+    b = b.ravel()
+    P = b.size
+    A0, M0 = A, M
+    A = lambda v: np.asarray(A0(v.reshape(P, 1))).ravel()
+    M = lambda v: np.asarray(M0(v.reshape(P, 1))).ravel()
+    x = np.zeros(P) if x0 is None else np.array(x0, dtype=float).ravel()
+    bn = np.linalg.norm(b)
+    if bn == 0:
+        return x, 0, []
+    hist = []
+    it = 0
+    while it < maxiter:
+        r = b - A(x)
+        if true_res is None and np.linalg.norm(r) / bn <= tol:
+            break
+        rt = r.copy() if shadow == "r" else M(r)  # shadow residual
+        rho_old = None
+        q = np.zeros(P)
+        pd = np.zeros(P)
+        restart = False
+        while it < maxiter:
+            rho = rt @ r
+            if rho == 0.0:
+                restart = True
+                break
+            if rho_old is None:
+                u = r.copy()
+                pd = u.copy()
+            else:
+                beta = rho / rho_old
+                u = r + beta * q
+                pd = u + beta * (q + beta * pd)
+            ph = M(pd)
+            vh = A(ph)
+            sigma = rt @ vh
+            if sigma == 0.0:
+                restart = True
+                break
+            alpha = rho / sigma
+            q = u - alpha * vh
+            uh = M(u + q)
+            x = x + alpha * uh
+            r = r - alpha * A(uh)
+            rho_old = rho
+            it += 1
+            hist.append(np.linalg.norm(r) / bn)
+            if hist[-1] <= tol:
+                break
+        tr = np.linalg.norm(b - A(x)) / bn if true_res is None else true_res(x)
+        if tr <= tol or it >= maxiter:
+            break
+        if not restart and hist and hist[-1] > tol:
+            break
+        # the recurrence drifted from the true residual: restart from it
+    return x, it, hist
+
+
+def bicg(A, M, MT, b, x0=None, tol=1e-10, maxiter=1000, true_res=None, AT=None):
+    """Biconjugate gradients for one right-hand side b (P,): the primal system
+    preconditioned by M, the shadow system by M^T (MT) with A^T (AT, default A:
+    the normal matrix is symmetric).  With symmetric A and M its iterates are
+    those of preconditioned CG."""
+    b = b.ravel()
+    P = b.size
+    A0, M0, MT0 = A, M, MT
+    AT0 = AT if AT is not None else A
+    A = lambda v: np.asarray(A0(v.reshape(P, 1))).ravel()
+    M = lambda v: np.asarray(M0(v.reshape(P, 1))).ravel()
+    MT = lambda v: np.asarray(MT0(v.reshape(P, 1))).ravel()
+    AT = lambda v: np.asarray(AT0(v.reshape(P, 1))).ravel()
+    x = np.zeros(P) if x0 is None else np.array(x0, dtype=float).ravel()
+    bn = np.linalg.norm(b)
+    if bn == 0:
+        return x, 0, []
+    hist = []
+    it = 0
+    while it < maxiter:
+        r = b - A(x)
+        if true_res is None and np.linalg.norm(r) / bn <= tol:
+            break
+        rt = r.copy()
+        rho_old = None
+        pd = np.zeros(P)
+        pt = np.zeros(P)
+        restart = False
+        while it < maxiter:
+            z = M(r)
+            zt = MT(rt)
+            rho = z @ rt
+            if rho == 0.0:
+                restart = True
+                break
+            if rho_old is None:
+                pd = z.copy()
+                pt = zt.copy()
+            else:
+                beta = rho / rho_old
+                pd = z + beta * pd
+                pt = zt + beta * pt
+            q = A(pd)
+            qt = AT(pt)
+            sigma = pt @ q
+            if sigma == 0.0:
+                restart = True
+                break
+            alpha = rho / sigma
+            x = x + alpha * pd
+            r = r - alpha * q
+            rt = rt - alpha * qt
+            rho_old = rho
+            it += 1
+            hist.append(np.linalg.norm(r) / bn)
+            if hist[-1] <= tol:
+                break
+        tr = np.linalg.norm(b - A(x)) / bn if true_res is None else true_res(x)
+        if tr <= tol or it >= maxiter:
+            break
+        if not restart and hist and hist[-1] > tol:
+            break
     return x, it, hist

@@ -143,6 +143,16 @@ class Schwarz:
             Z[ix] += w[:, None] * solve(R2[ix])
         return Z.reshape(R.shape)
 
+    def apply_T(self, R):
+        """The transpose M^{-T} = sum_i R_i^T A_i^{-1} D_i R_i (A_i^{-1} is
+        symmetric): the weights act on the restricted input instead of the
+        local result; equal to apply for AS."""
+        R2 = R.reshape(self.P, -1)
+        Z = np.zeros_like(R2)
+        for ix, solve, w in zip(self.idx, self.solvers, self.weights):
+            Z[ix] += solve(w[:, None] * R2[ix])
+        return Z.reshape(R.shape)
+
     def dense(self):
         return self.apply(np.eye(self.P))
 

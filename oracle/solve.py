@@ -49,8 +49,13 @@ def iterative(prob, sysm, stencil="full", precond="as", method="cg", tol=1e-10,
     else:
         cols, iters, hist = [], [], []
         for q in range(rhs.shape[1]):
-            x, it, h = kr.gmres(bh.normal, M.apply, rhs[:, q], restart=restart, tol=tol,
-                                maxiter=maxiter, side="right" if method == "gmres_right" else "left")
+            if method == "cgs":
+                x, it, h = kr.cgs(bh.normal, M.apply, rhs[:, q], tol=tol, maxiter=maxiter)
+            elif method == "bicg":
+                x, it, h = kr.bicg(bh.normal, M.apply, M.apply_T, rhs[:, q], tol=tol, maxiter=maxiter)
+            else:
+                x, it, h = kr.gmres(bh.normal, M.apply, rhs[:, q], restart=restart, tol=tol,
+                                    maxiter=maxiter, side="right" if method == "gmres_right" else "left")
             cols.append(x)
             iters.append(it)
             hist.append(h)

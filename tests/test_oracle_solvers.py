@@ -328,3 +328,142 @@ def test_manufactured_accuracy_1d(tol, bound):
     u = asm.probe_matrix(prob, ref["sys"], prob.probes) @ ref["W"]
     err = np.linalg.norm(u[:, 0] - prob.u_probe) / np.linalg.norm(prob.u_probe)
     assert err < bound
+
+
+# ---------------------------------------------------------------- CGS and BiCG
+def _small_normal_system(kind):
+    prob = wl.small2d(k=1)
+    sysm = asm.assemble(prob, "rel_eig", 1e-10)
+    bh = bs.BlockH(sysm)
+    M = sw.schwarz_blocks(bh, sw.stencil(prob, "full"), kind=kind)
+    b = bh.rmatvec(sysm.Fs)[:, 0]
+    return prob, sysm, bh, M, b
+
+
+@pytest.mark.parametrize("kind", ["as", "sas", "ras"])
+@pytest.mark.parametrize("method", ["cgs", "bicg"])
+def test_cgs_and_bicg_reach_the_qr_solution(kind, method):
+    """Table 1b's CG variants with the AS, SAS and RAS preconditioners reach the
+    exact least-squares solution (the QR solution of the oracle)."""
+    prob, sysm, bh, M, b = _small_normal_system(kind)
+    ref = solve.reference(prob, "rel_eig", 1e-10, sysm=sysm)
+    if method == "cgs":
+        x, it, _ = kr.cgs(bh.normal, M.apply, b, tol=1e-13, maxiter=3000)
+    else:
+        x, it, _ = kr.bicg(bh.normal, M.apply, M.apply_T, b, tol=1e-13, maxiter=3000)
+    err = np.linalg.norm(x - ref["W"][:, 0]) / np.linalg.norm(ref["W"][:, 0])
+    assert err <= 1e-7, (method, kind, it, err)
+
+
+def test_transposed_schwarz_apply_is_the_transpose():
+    """<M^{-1} u, v> = <u, M^{-T} v> for SAS and RAS (and M^{-T} = M^{-1} for AS)."""
+    rng = np.random.default_rng(3)
+    for kind in ["as", "sas", "ras"]:
+        _, _, _, M, b = _small_normal_system(kind)
+        u, v = rng.standard_normal(b.size), rng.standard_normal(b.size)
+        lhs = M.apply(u[:, None])[:, 0] @ v
+        rhs = u @ M.apply_T(v[:, None])[:, 0]
+        assert abs(lhs - rhs) <= 1e-10 * (abs(lhs) + 1.0), kind
+    _, _, _, M, b = _small_normal_system("as")
+    u = rng.standard_normal((b.size, 2))
+    assert np.allclose(M.apply(u), M.apply_T(u), rtol=0, atol=1e-12 * np.abs(M.apply(u)).max())
+
+
+def test_bicg_with_symmetric_operator_and_preconditioner_is_pcg():
+    """With A = H^T H and the symmetric AS preconditioner, BiCG's shadow sequence
+    equals its primal one and its iterates are those of preconditioned CG."""
+    _, _, bh, M, b = _small_normal_system("as")
+    for k in range(1, 6):
+        xb, itb, _ = kr.bicg(bh.normal, M.apply, M.apply_T, b, tol=1e-300, maxiter=k)
+        xc, itc, _ = kr.pcg(bh.normal, M.apply, b, tol=1e-300, maxiter=k)
+        assert itb == k and int(itc[0]) == k
+        assert np.linalg.norm(xb - xc[:, 0]) <= 1e-9 * np.linalg.norm(xc[:, 0]), k
+
+
+def test_cgs_residual_is_the_squared_cg_polynomial():
+    """Sonneveld's identity: with the shadow M^{-1} r_0 and symmetric A, M, the
+    CGS residual after k steps is phi_k(A M^{-1})^2 r_0, where phi_k is the
+    residual polynomial of preconditioned CG (its coefficients from a plain CG
+    run, the polynomial built with numpy.polynomial)."""
+    from numpy.polynomial import polynomial as npoly
+    _, _, bh, M, b = _small_normal_system("as")
+    A = lambda v: bh.normal(v[:, None])[:, 0]
+    Mi = lambda v: M.apply(v[:, None])[:, 0]
+    B = lambda v: A(Mi(v))
+    # plain PCG from x0 = 0: r_{j+1} = r_j - a_j A p_j, p_{j+1} = z_{j+1} + c_j p_j
+    r = b.copy()
+    z = Mi(r)
+    pdir = z.copy()
+    phi = np.array([1.0])      # r_j = phi_j(B) r_0
+    psi = np.array([0.0, 1.0])  # A p_j = psi_j(B) r_0
+    for k in range(1, 5):
+        Ap = A(pdir)
+        a = (r @ z) / (pdir @ Ap)
+        r_new = r - a * Ap
+        z_new = Mi(r_new)
+        c = (r_new @ z_new) / (r @ z)
+        phi = npoly.polysub(phi, a * psi)
+        psi = npoly.polyadd(npoly.polymulx(phi), c * psi)
+        pdir = z_new + c * pdir
+        r, z = r_new, z_new
+        # phi_k(B)^2 r_0 by Horner's rule in B
+        coef = npoly.polymul(phi, phi)
+        v = coef[-1] * b
+        for cf in coef[-2::-1]:
+            v = B(v) + cf * b
+        x, it, _ = kr.cgs(bh.normal, M.apply, b, tol=1e-300, maxiter=k, shadow="Mr")
+        r_cgs = b - A(x)
+        assert it == k
+        assert np.linalg.norm(r_cgs - v) <= 1e-6 * np.linalg.norm(b), (k, np.linalg.norm(r_cgs - v))
+
+
+def _moment_polynomial(B, r0, s0, k):
+    """Residual polynomial of BiCG on the operator B after k steps, from its
+    Petrov-Galerkin definition alone: r_k = phi_k(B) r_0 with phi_k(0) = 1 and
+    r_k orthogonal to span{s0, B^T s0, ..., (B^T)^{k-1} s0}.  In the monomial
+    basis this is the k x k moment system sum_j c_j s0.B^{i+j+1} r0 = s0.B^i r0."""
+    K = [r0]
+    for _ in range(2 * k):
+        K.append(B(K[-1]))
+    mom = np.array([s0 @ v for v in K])
+    G = np.array([[mom[i + j + 1] for j in range(k)] for i in range(k)])
+    c = np.linalg.solve(G, mom[:k])
+    return np.concatenate([[1.0], -c])
+
+
+def _poly_apply(B, coef, v):
+    out = coef[-1] * v
+    for cf in coef[-2::-1]:
+        out = B(out) + cf * v
+    return out
+
+
+@pytest.mark.parametrize("kind", ["sas", "ras"])
+def test_bicg_and_cgs_residuals_match_the_petrov_galerkin_polynomial(kind):
+    """With a non-symmetric preconditioner (SAS, RAS): BiCG's residual after k
+    steps is phi_k(A M^{-1}) r_0, where phi_k is fixed by the Petrov-Galerkin
+    condition against the shadow Krylov space K_k((A M^{-1})^T, M^{-T} r_0)
+    (the shadow search directions are M^{-T} applied to the shadow residuals);
+    CGS with the shadow r_0 has the residual phi_k(A M^{-1})^2 r_0 with the
+    polynomial of BiCG on A M^{-1} tested against K_k((A M^{-1})^T, r_0)."""
+    prob, sysm, bh, M, b = _small_normal_system(kind)
+    A = lambda v: bh.normal(v[:, None])[:, 0]
+    Mi = lambda v: M.apply(v[:, None])[:, 0]
+    MiT = lambda v: M.apply_T(v[:, None])[:, 0]
+    B = lambda v: A(Mi(v))
+    nb = np.linalg.norm(b)
+    # k <= 3: the monomial moment system loses about three digits per degree
+    for k in range(1, 4):
+        phi = _moment_polynomial(B, b, MiT(b), k)
+        out = solve.iterative(prob, sysm, "full", kind, "bicg", tol=1e-300, maxiter=k)
+        assert out["iters"][0] == k
+        rb = b - A(out["W"][:, 0])
+        assert np.linalg.norm(rb - _poly_apply(B, phi, b)) <= 1e-6 * nb, (kind, k)
+        chi = _moment_polynomial(B, b, b, k)
+        out = solve.iterative(prob, sysm, "full", kind, "cgs", tol=1e-300, maxiter=k)
+        assert out["iters"][0] == k
+        rc = b - A(out["W"][:, 0])
+        want = _poly_apply(B, np.polynomial.polynomial.polymul(chi, chi), b)
+        # CGS may amplify the residual (squared polynomial): relative to it
+        scale = max(nb, np.linalg.norm(want))
+        assert np.linalg.norm(rc - want) <= 1e-6 * scale, (kind, k, np.linalg.norm(rc - want) / scale)
