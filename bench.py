@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-RHS mixed/FP64 comparison")
+    ap.add_argument("--no-variants", action="store_true", help="skip the Krylov method x preconditioner grid")
     ap.add_argument("--quick", action="store_true", help="skip the side measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB (counter calibration) and exit")
@@ -177,6 +178,30 @@ def solve_only(inp, precision, stencil, tol, torch, reps=3):
                  factor_elems=int(s.info.factor_elems), N=int(s.info.N))
     s.close()
     return stats
+
+
+def krylov_variants(inp, stencil, tol, torch):
+    """The Krylov method x preconditioner grid of Table 1b on the benchmark
+    workload (FP64, preconditioner built once per kind): iterations and the
+    solve time to the tolerance (second of two solves), at most 1000
+    iterations (status 1: not converged)."""
+    b = inp.binding
+    grid = {"as": ["cg", "cgs", "bicg", "gmres"], "sas": ["cgs", "bicg", "gmres"], "ras": ["cgs", "gmres"]}
+    out = {}
+    for kind, methods in grid.items():
+        s = b.Solver(inp.prob, precision="fp64", stencil=stencil, precond=kind)
+        s.pca(inp.prob.meta["pca_tol"], "rel_eig")
+        for m in methods:
+            s.solve(inp.F, tol=tol, maxiter=1000, method=m, restart=50, check_every=10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            W, info = s.solve(inp.F, tol=tol, maxiter=1000, method=m, restart=50, check_every=10)
+            torch.cuda.synchronize()
+            out[f"{m}/{kind}"] = {"iterations": int(info["iterations"]), "solve_ms": (time.perf_counter() - t0) * 1e3,
+                                  "status": int(info["status"]),
+                                  "max_rel_residual": float(info["max_rel_residual"])}
+        s.close()
+    return out
 
 
 def cpu_baseline(prob, tol, stencil, min_seconds=10.0, max_reps=3):
@@ -353,6 +378,8 @@ def main():
                             "iterations": int(mi["iterations"]), "phases_ms": tmm}
         if not args.no_batched:
             out["batched"] = batched_comparison(torch, binding, wl, dev)
+        if not args.no_variants:
+            out["krylov_variants"] = krylov_variants(inp, args.stencil, args.tol, torch)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(prob, args.tol, args.stencil)
         out["cpu_baseline"] = {"value": k / cb["total_s"], "unit": "solves/s",

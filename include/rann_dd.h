@@ -72,6 +72,10 @@ extern "C" {
 #define RANN_METHOD_CG     0
 #define RANN_METHOD_GMRES  1        /* left-preconditioned (paper Sec. 5) */
 #define RANN_METHOD_GMRES_RIGHT 2   /* right-preconditioned: minimises the true residual */
+#define RANN_METHOD_CGS    3        /* conjugate gradients squared (Sec. 5, Table 1b) */
+#define RANN_METHOD_BICG   4        /* biconjugate gradients (Sec. 5, Table 1b); needs the
+                                       transposed preconditioner: NONE, AS or SAS
+                                       (RANN_EINVAL with RAS) */
 
 typedef struct rann_dd_handle rann_dd_handle;
 
@@ -107,8 +111,12 @@ typedef struct rann_dd_desc {
 typedef struct rann_dd_solve_opts {
     double tol;               /* relative true normal residual ||H^T(F - H W)|| / ||H^T F|| */
     int32_t maxiter;          /* iteration limit (>= 1) */
-    int32_t method;           /* RANN_METHOD_CG (AS), RANN_METHOD_GMRES or RANN_METHOD_GMRES_RIGHT */
-    int32_t restart;          /* GMRES restart length (1..128) */
+    int32_t method;           /* RANN_METHOD_CG (AS), RANN_METHOD_GMRES, RANN_METHOD_GMRES_RIGHT,
+                                 RANN_METHOD_CGS or RANN_METHOD_BICG */
+    int32_t restart;          /* GMRES restart length (1..128); CGS and BiCG with
+                                 RANN_MIXED: longest refinement cycle, after which
+                                 the right-hand side restarts from its FP64
+                                 residual (<= 0: no limit) */
     int32_t check_every;      /* host convergence check cadence (>= 1) */
 } rann_dd_solve_opts;
 
@@ -171,7 +179,10 @@ RANN_API int rann_dd_solve(rann_dd_handle* h, const double* F, int32_t k, const 
 /* Adjoint of rann_dd_solve: dF = H (H^T H)^{-1} dW with the boundary rows
  * multiplied by lambda_B, i.e. the gradient with respect to the unscaled
  * (f, g) rows of F of any loss whose gradient with respect to W is dW.
- *   dW device (P, k); dF device (N, k). */
+ *   dW device (P, k); dF device (N, k).
+ * CG stops on its recurrence residual; CGS and BiCG confirm on the recomputed
+ * FP64 residual ||dW - H^T H z|| / ||dW||, whose floor for a dW with weight on
+ * the smallest singular directions is near 1e-16 kappa(H^T H). */
 RANN_API int rann_dd_solve_backward(rann_dd_handle* h, const double* dW, int32_t k,
                            const rann_dd_solve_opts* opts, double* dF, rann_dd_stats* st);
 
@@ -194,6 +205,12 @@ RANN_API int rann_dd_matvec(rann_dd_handle* h, const double* x, int32_t k, doubl
 RANN_API int rann_dd_rmatvec(rann_dd_handle* h, const double* y, int32_t k, double* x);
 RANN_API int rann_dd_apply_normal(rann_dd_handle* h, const double* x, int32_t k, double* s);
 RANN_API int rann_dd_apply_precond(rann_dd_handle* h, const double* r, int32_t k, double* z);
+/* z = M^{-T} r, the transposed Schwarz preconditioner that BiCG's shadow
+ * recurrence applies (Sec. 5, Table 1b): the weights D_i move from the local
+ * results onto the restricted input, sum_i R_i^T A_i^{-1} D_i R_i r.  r, z
+ * device (P, k), k >= 1, not aliased.  Equal to rann_dd_apply_precond for AS and
+ * no preconditioner.  Synchronous.  RANN_EINVAL for RAS (not provided). */
+RANN_API int rann_dd_apply_precond_T(rann_dd_handle* h, const double* r, int32_t k, double* z);
 
 /* Sizes; valid after rann_dd_assemble (P, nnz after rann_dd_pca). */
 RANN_API int rann_dd_get_info(const rann_dd_handle* h, rann_dd_info* out);

@@ -22,7 +22,7 @@ FP64, MIXED = 0, 1
 STENCIL = {"self": 0, "face": 1, "full": 2}
 PRECOND = {"none": 0, "as": 1, "ras": 2, "sas": 3}
 PCA_MODE = {"rel_eig": 0, "abs_sigma": 1, "off": 2}
-METHOD = {"cg": 0, "gmres": 1, "gmres_right": 2}
+METHOD = {"cg": 0, "gmres": 1, "gmres_right": 2, "cgs": 3, "bicg": 4}
 
 c_dp = ctypes.POINTER(ctypes.c_double)
 c_ip = ctypes.POINTER(ctypes.c_int32)
@@ -76,6 +76,7 @@ _SIGS = {
     "rann_dd_rmatvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rann_dd_apply_normal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rann_dd_apply_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "rann_dd_apply_precond_T": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rann_dd_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     "rann_dd_get_layout": (ctypes.c_int, [ctypes.c_void_p, c_lp, c_ip, c_ip]),
     "rann_dd_get_arrays": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -183,6 +184,10 @@ def rann_dd_apply_normal(h, x_ptr, k, s_ptr):
 
 def rann_dd_apply_precond(h, r_ptr, k, z_ptr):
     return _check(load().rann_dd_apply_precond(h, ctypes.c_void_p(r_ptr), int(k), ctypes.c_void_p(z_ptr)))
+
+
+def rann_dd_apply_precond_T(h, r_ptr, k, z_ptr):
+    return _check(load().rann_dd_apply_precond_T(h, ctypes.c_void_p(r_ptr), int(k), ctypes.c_void_p(z_ptr)))
 
 
 def rann_dd_get_info(h) -> Info:
@@ -361,6 +366,11 @@ class Solver:
     def apply_precond(self, r):
         z = self.torch.empty((self.info.P, r.shape[1]), dtype=self.torch.float64, device=self.dev)
         rann_dd_apply_precond(self.handle, r.contiguous().data_ptr(), r.shape[1], z.data_ptr())
+        return z
+
+    def apply_precond_T(self, r):
+        z = self.torch.empty((self.info.P, r.shape[1]), dtype=self.torch.float64, device=self.dev)
+        rann_dd_apply_precond_T(self.handle, r.contiguous().data_ptr(), r.shape[1], z.data_ptr())
         return z
 
     def eval(self, Xq, W, Lq=None):

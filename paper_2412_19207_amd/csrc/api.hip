@@ -308,9 +308,9 @@ int validate_opts(const rann_dd_solve_opts* o) {
         return RANN_EINVAL;
     }
     if (!(o->tol > 0.0) || o->maxiter < 1 || o->check_every < 1 ||
-        (o->method != RANN_METHOD_CG && o->method != RANN_METHOD_GMRES &&
-         o->method != RANN_METHOD_GMRES_RIGHT) ||
-        (o->method != RANN_METHOD_CG && (o->restart < 1 || o->restart > 128))) {
+        o->method < RANN_METHOD_CG || o->method > RANN_METHOD_BICG ||
+        ((o->method == RANN_METHOD_GMRES || o->method == RANN_METHOD_GMRES_RIGHT) &&
+         (o->restart < 1 || o->restart > 128))) {
         set_error("invalid solve options");
         return RANN_EINVAL;
     }
@@ -657,10 +657,20 @@ int rann_dd_solve(rann_dd_handle* hh, const double* F, int32_t k, const double* 
     int rc = rdd::scale_boundary(h, F, k, Fs, h.lambda_B);
     int status = RANN_OK;
     if (rc == RANN_OK) {
-        if (opts->method == RANN_METHOD_CG)
+        if (opts->method == RANN_METHOD_CG) {
             rc = rdd::krylov_cg(h, Fs, k, W0, *opts, W, st, &status);
-        else
+        } else if (opts->method == RANN_METHOD_CGS || opts->method == RANN_METHOD_BICG) {
+            double* rhs = nullptr;
+            double* part = nullptr;
+            rc = rdd::dev_alloc(h, &rhs, (size_t)h.P * k);
+            if (rc == RANN_OK) rc = rdd::dev_alloc(h, &part, (size_t)h.part_total * k);
+            if (rc == RANN_OK) rc = rdd::launch_HTy(h, Fs, k, rhs, part);
+            if (rc == RANN_OK) rc = rdd::krylov_lanczos(h, rhs, Fs, k, W0, *opts, W, st, &status);
+            if (part) rdd::dev_free(h, part);
+            if (rhs) rdd::dev_free(h, rhs);
+        } else {
             rc = rdd::krylov_gmres(h, Fs, k, W0, *opts, W, st, &status);
+        }
     }
     rdd::dev_free(h, Fs);
     if (rc < 0) return rc;
@@ -679,8 +689,13 @@ int rann_dd_solve_backward(rann_dd_handle* hh, const double* dW, int32_t k,
     double* z = nullptr;
     RDD_TRY(rdd::dev_alloc(h, &z, (size_t)h.P * k));
     int status = RANN_OK;
-    int rc = (opts->method == RANN_METHOD_CG) ? rdd::adjoint_cg(h, dW, k, *opts, z, st, &status)
-                                              : rdd::adjoint_gmres(h, dW, k, *opts, z, st, &status);
+    int rc;
+    if (opts->method == RANN_METHOD_CG)
+        rc = rdd::adjoint_cg(h, dW, k, *opts, z, st, &status);
+    else if (opts->method == RANN_METHOD_CGS || opts->method == RANN_METHOD_BICG)
+        rc = rdd::krylov_lanczos(h, dW, nullptr, k, nullptr, *opts, z, st, &status);
+    else
+        rc = rdd::adjoint_gmres(h, dW, k, *opts, z, st, &status);
     if (rc == RANN_OK) rc = rdd::launch_Hx(h, z, k, dF, false);
     if (rc == RANN_OK && h.n_bnd > 0) {
         hipLaunchKernelGGL(rdd::k_scale_tail, dim3((unsigned)((h.n_bnd * k + 255) / 256)), dim3(256), 0,
@@ -769,6 +784,21 @@ int rann_dd_apply_precond(rann_dd_handle* hh, const double* r, int32_t k, double
     RDD_TRY(rdd::dev_alloc(h, &ub, (size_t)std::max<int64_t>(2 * h.ub_total + 2 * h.slot_total, 1) * k));
     int rc = rdd::launch_precond(h, r, k, z, ub);
     if (rc == RANN_OK && hipStreamSynchronize(h.stream) != hipSuccess) rc = RANN_EDEVICE;
+    rdd::dev_free(h, ub);
+    return rc;
+}
+
+int rann_dd_apply_precond_T(rann_dd_handle* hh, const double* r, int32_t k, double* z) {
+    RDD_TRY(guard_handle(hh, true));
+    Handle& h = hh->h;
+    if (!r || !z || k < 1) return (rdd::set_error("invalid apply_precond_T arguments"), RANN_EINVAL);
+    double* ub = nullptr;
+    double* tmp = nullptr;
+    RDD_TRY(rdd::dev_alloc(h, &ub, (size_t)std::max<int64_t>(2 * h.ub_total + 2 * h.slot_total, 1) * k));
+    int rc = rdd::dev_alloc(h, &tmp, (size_t)h.P * k);
+    if (rc == RANN_OK) rc = rdd::launch_precond_T(h, r, k, z, ub, tmp);
+    if (rc == RANN_OK && hipStreamSynchronize(h.stream) != hipSuccess) rc = RANN_EDEVICE;
+    if (tmp) rdd::dev_free(h, tmp);
     rdd::dev_free(h, ub);
     return rc;
 }

@@ -260,6 +260,8 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part, co
 int launch_Hx(Handle& h, const double* x, int k, double* y, bool scale_bnd);
 int launch_HTy(Handle& h, const double* y, int k, double* x, double* partial);
 int launch_precond(Handle& h, const double* r, int k, double* z, double* ub);
+// z = M^{-T} r (AS, SAS; RANN_EINVAL for RAS); tmp: P k scratch
+int launch_precond_T(Handle& h, const double* r, int k, double* z, double* ub, double* tmp);
 // ub: (2 ub_total + 2 slot_total) k doubles of scratch
 int launch_precond_local(Handle& h, const double* r, int k, double* ub);
 
@@ -271,6 +273,9 @@ int adjoint_gmres(Handle& h, const double* dW, int k, const rann_dd_solve_opts& 
                   rann_dd_stats* st, int* status);
 int krylov_gmres(Handle& h, const double* rhs, int k, const double* W0,
                  const rann_dd_solve_opts& o, double* W, rann_dd_stats* st, int* status);
+// CGS and BiCG (method RANN_METHOD_CGS / RANN_METHOD_BICG); Fs = null: adjoint
+int krylov_lanczos(Handle& h, const double* rhs, const double* Fs, int k, const double* W0,
+                   const rann_dd_solve_opts& o, double* W, rann_dd_stats* st, int* status);
 int true_residual(Handle& h, const double* Fs, const double* W, int k, double* out_host,
                   double* rhs_norm_host);
 int scale_boundary(Handle& h, const double* F, int k, double* Fs, double factor);

@@ -675,7 +675,8 @@ __global__ void k_slot_reduce(int64_t nent, int k, int t0, int kt, int use_r, in
 }
 
 
-// z[g] = sum over (block entry e containing column g) of w_e u[e]
+// z[g] = sum over (block entry e containing column g) of w_e u[e]; unit
+// weights when gat_w is null
 __global__ void k_gather_sum(int64_t P, int k, const int64_t* __restrict__ gat_off,
                              const int64_t* __restrict__ gat, const double* __restrict__ gat_w,
                              const double* __restrict__ u, double* __restrict__ z) {
@@ -684,8 +685,22 @@ __global__ void k_gather_sum(int64_t P, int k, const int64_t* __restrict__ gat_o
     int64_t g = idx / k;
     int t = (int)(idx % k);
     double s = 0.0;
-    for (int64_t e = gat_off[g]; e < gat_off[g + 1]; ++e) s += gat_w[e] * u[gat[e] * k + t];
+    if (gat_w) {
+        for (int64_t e = gat_off[g]; e < gat_off[g + 1]; ++e) s += gat_w[e] * u[gat[e] * k + t];
+    } else {
+        for (int64_t e = gat_off[g]; e < gat_off[g + 1]; ++e) s += u[gat[e] * k + t];
+    }
     z[idx] = s;
+}
+
+// out[g] = r[g] / (number of blocks containing column g), the count being the
+// length of g's gather list (every entry is listed unless the blocks are RAS)
+__global__ void k_div_count(int64_t P, int k, const int64_t* __restrict__ gat_off,
+                            const double* __restrict__ r, double* __restrict__ out) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= P * k) return;
+    const int64_t g = idx / k;
+    out[idx] = r[idx] / (double)(gat_off[g + 1] - gat_off[g]);
 }
 
 }  // namespace
@@ -1016,6 +1031,27 @@ int launch_precond(Handle& h, const double* r, int k, double* z, double* ub) {
     const int64_t tot = h.P * k;
     hipLaunchKernelGGL(k_gather_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h.stream,
                        h.P, k, h.d_gat_off, h.d_gat, h.d_gat_w, ub, z);
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
+// z = M^{-T} r.  The local inverses are symmetric, so the transpose moves the
+// weights D_i from the local results onto the restricted input.  AS: M^{-T} =
+// M^{-1}.  SAS: D_i R_i = R_i D with D = 1/multiplicity, so M^{-T} r is the AS
+// apply of D r (tmp: P k scratch).  RAS: its blocks only compute their owned
+// rows, which the transpose does not use; not provided.
+int launch_precond_T(Handle& h, const double* r, int k, double* z, double* ub, double* tmp) {
+    if (h.precond == RANN_PRECOND_NONE || h.precond == RANN_PRECOND_AS) return launch_precond(h, r, k, z, ub);
+    if (h.precond != RANN_PRECOND_SAS) {
+        set_error("the transposed RAS preconditioner is not provided");
+        return RANN_EINVAL;
+    }
+    const int64_t tot = h.P * k;
+    const unsigned g = (unsigned)((tot + 255) / 256);
+    hipLaunchKernelGGL(k_div_count, dim3(g), dim3(256), 0, h.stream, h.P, k, h.d_gat_off, r, tmp);
+    RDD_TRY(launch_precond_local(h, tmp, k, ub));
+    hipLaunchKernelGGL(k_gather_sum, dim3(g), dim3(256), 0, h.stream, h.P, k, h.d_gat_off, h.d_gat,
+                       (const double*)nullptr, ub, z);
     RDD_HIP(hipGetLastError());
     return RANN_OK;
 }

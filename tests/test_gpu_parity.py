@@ -297,6 +297,96 @@ def test_gmres_matches_qr(case_small2d, kind, method):
     assert rel(W.cpu().numpy(), ref["W"]) <= 1e-7
 
 
+# ------------------------------------------------------------------ CGS and BiCG (Table 1b)
+@pytest.mark.parametrize("stencil", ["face", "full"])
+@pytest.mark.parametrize("kind", ["as", "sas", "ras"])
+@pytest.mark.parametrize("k", [1, 16, 37])
+def test_transposed_preconditioner_matches_oracle(case_small2d, stencil, kind, k):
+    """M^{-T} r against the transpose of the oracle's dense M^{-1} (the vector,
+    the matrix-core and the mixed chunking of the local solves); RAS declines."""
+    prob, ref = case_small2d
+    sysm, H = ref["sys"], ref["H"]
+    HtH = H.T @ H
+    s = binding.Solver(prob, device=DEV, stencil=stencil, precond=kind)
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal((sysm.P, k))
+    if kind == "ras":
+        with pytest.raises(binding.RannError) as e:
+            s.apply_precond_T(torch.as_tensor(r, device=DEV))
+        assert e.value.code == binding.RANN_EINVAL
+        return
+    M = osw.schwarz_dense(HtH, sysm.col_off, osw.stencil(prob, stencil), kind).dense()
+    z = s.apply_precond_T(torch.as_tensor(r, device=DEV)).cpu().numpy()
+    kappa = np.linalg.cond(HtH)
+    ref_z = M.T @ r
+    for t in range(k):
+        e = rel(z[:, t], ref_z[:, t])
+        assert e < max(1e-9, 1e-15 * kappa), (t, e, kappa)
+
+
+@pytest.mark.parametrize("method,kind", [("cgs", "as"), ("cgs", "sas"), ("cgs", "ras"),
+                                         ("bicg", "as"), ("bicg", "sas")])
+def test_cgs_bicg_match_qr_and_oracle_iterations(case_small2d, method, kind):
+    """FP64 CGS and BiCG reach the QR solution to the FP64 bar, with per-RHS
+    iteration counts close to the oracle's (same recurrences, summation order
+    and the assembled normal matrix aside)."""
+    prob, ref = case_small2d
+    sysm = ref["sys"]
+    s = binding.Solver(prob, device=DEV, precond=kind)
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-12, method=method, maxiter=5000)
+    assert info["status"] == 0
+    assert info["max_rel_residual"] <= 1e-12
+    err = rel(W.cpu().numpy(), ref["W"])
+    it = osolve.iterative(prob, sysm, "full", kind, method, tol=1e-12, maxiter=5000)
+    print(f"{method}/{kind}: GPU iterations {info['rhs_iterations']}, oracle {it['iters']}, err {err:.2e}")
+    assert err <= 1e-8, err
+    for t in range(prob.F.shape[1]):
+        g, o = int(info["rhs_iterations"][t]), int(it["iters"][t])
+        assert abs(g - o) <= max(3, 0.25 * o), (t, g, o)
+
+
+def test_bicg_declines_ras(case_small2d):
+    prob, ref = case_small2d
+    sysm = ref["sys"]
+    s = binding.Solver(prob, device=DEV, precond="ras")
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    with pytest.raises(binding.RannError) as e:
+        s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-10, method="bicg")
+    assert e.value.code == binding.RANN_EINVAL
+
+
+@pytest.mark.parametrize("method", ["cgs", "bicg"])
+def test_cgs_bicg_batched_mixed_and_adjoint(case_small2d_k37, method):
+    """37 right-hand sides (matrix-core chunks of the preconditioner) with the
+    SAS preconditioner: mixed precision to 1e-6; then the adjoint through the
+    same method against the QR adjoint.  The tolerance is 1e-12: without CG's
+    symmetric recurrence these methods stall near 1e-13 in FP64 (the oracle
+    leaves 5 (CGS) and 12 (BiCG) of these 37 right-hand sides above 1e-13)."""
+    prob, ref = case_small2d_k37
+    sysm, qr = ref["sys"], ref["qr"]
+    s = binding.Solver(prob, device=DEV, precision="mixed", precond="sas")
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-12, method=method, maxiter=5000)
+    assert info["status"] == 0
+    assert info["max_rel_residual"] <= 1e-12
+    Wn = W.cpu().numpy()
+    for t in range(Wn.shape[1]):
+        assert rel(Wn[:, t], ref["W"][:, t]) <= 1e-6, t
+    s64 = binding.Solver(prob, device=DEV, precond="sas")
+    s64.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    rng = np.random.default_rng(5)
+    dW = rng.standard_normal((sysm.P, 3))
+    # the adjoint confirms on ||dW - H^T H z|| / ||dW||, whose FP64 floor for a
+    # random dW is near u kappa(H^T H) (about 6e-10 here, even for a direct solve)
+    dF, st = s64.solve_backward(torch.as_tensor(dW, device=DEV), tol=1e-9, maxiter=5000, method=method)
+    assert st["status"] == 0
+    expect = qr.adjoint(dW)
+    expect[prob.N_I:] *= prob.lambda_B
+    assert rel(dF.cpu().numpy(), expect) <= 1e-8
+
+
 def test_mixed_precision_solution(case_small2d):
     prob, ref = case_small2d
     sysm = ref["sys"]
