@@ -518,9 +518,46 @@ def small3d(l=(2, 2, 2), m=(30, 41, 25, 36, 44, 29, 33, 38), pts=(5, 6, 4), k=1,
     return build_problem(**args)
 
 
+def semilinear2d(size="full", **kw) -> Problem:
+    """Semilinear 2D problem -lap u + g(u) = f with the reaction g(u) = u^3
+    (meta["gamma"]: coefficients of g in powers of u), u = sin(pi x) sin(pi y)
+    exp(x+y) on the boundary; f from that manufactured solution.  The problem's
+    own coefficients are those of the linear part (c = 0); a Picard or Newton
+    step replaces c and the interior rows of F.  "full": the 8x8, width-300
+    layout of the 2D Poisson workload; "small": 3x2 subdomains of uneven width."""
+    def exact(X):
+        x, y = X[:, 0], X[:, 1]
+        return np.sin(PI * x) * np.sin(PI * y) * np.exp(x + y)
+
+    def rhs(X):
+        x, y = X[:, 0], X[:, 1]
+        e = np.exp(x + y)
+        mlap = e * (2 * (PI ** 2 - 1) * np.sin(PI * x) * np.sin(PI * y)
+                    - 2 * PI * (np.cos(PI * x) * np.sin(PI * y) + np.sin(PI * x) * np.cos(PI * y)))
+        return mlap + exact(X) ** 3
+
+    meta = dict(pca_tol=1e-8, tol=1e-10, stencil="full", method="cg", precond="as",
+                gamma=[0.0, 0.0, 0.0, 1.0])
+    if size == "small":
+        l, m = [3, 2], np.resize(np.asarray((40, 57, 33, 64, 48, 71), dtype=np.int32), 6)
+        args = dict(name="semilinear2d_small", d=2, l=l, m=m, weight_scale=2.0,
+                    pts_per_sub=[11, 9], overlap_frac=0.2, faces=_all_faces(2),
+                    bnd_counts=[21, 10], probes_per_dim=[23, 19])
+        meta.update(pca_tol=1e-10, tol=1e-12)
+    else:
+        args = dict(name="semilinear2d_8x8_m300", d=2, l=[8, 8], m=300, weight_scale=3.0,
+                    pts_per_sub=[30, 30], overlap_frac=0.1, faces=_all_faces(2),
+                    bnd_counts=[64, 64], probes_per_dim=[160, 160])
+    args.update(coeff_fn=_laplace_coeffs, rhs_fn=rhs,
+                bnd_fn=lambda X, k: exact(X)[:, None].repeat(k, 1), exact_fn=exact, meta=meta)
+    args.update(kw)
+    return build_problem(**args)
+
+
 WORKLOADS = {
     "cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4, "cfg5": cfg5,
     "ex1": ex1_replica, "small2d": small2d, "small3d": small3d,
+    "semilinear2d": semilinear2d,
 }
 
 
