@@ -77,6 +77,10 @@ extern "C" {
                                        transposed preconditioner: NONE, AS or SAS
                                        (RANN_EINVAL with RAS) */
 
+#define RANN_LIN_NEWTON    0        /* Newton (Gauss-Newton) linearisation of g */
+#define RANN_LIN_PICARD    1        /* Picard: g(u) = gamma_0 + u q(u), q frozen */
+#define RANN_MAX_GAMMA     16       /* coefficients of the polynomial reaction */
+
 typedef struct rann_dd_handle rann_dd_handle;
 
 /* Problem description (paper eq. (1), Sec. 2 local networks, Sec. 5 layout). */
@@ -195,6 +199,24 @@ RANN_API int rann_dd_eval(rann_dd_handle* h, const double* Xq, int64_t M, const 
 /* Transpose of rann_dd_eval: dW = Pmat^T dU.  dU device (M, k); dW device (P, k). */
 RANN_API int rann_dd_eval_T(rann_dd_handle* h, const double* Xq, int64_t M, const double* Lq,
                    const double* dU, int32_t k, double* dW);
+
+/* One Picard or Newton linearisation of a semilinear problem A[u] + g(u) = f
+ * with g(u) = sum_{p < n_gamma} gamma[p] u^p (Sec. 2, the remark after eq.
+ * (sum): each step of the nonlinear iteration is one linear least-squares
+ * problem).  From the values u (device, n: the current iterate at the n
+ * interior collocation points, e.g. from rann_dd_eval at X_int), the reaction
+ * c0 (device, n) and source f (device, n) of the linear part, it writes the
+ * reaction c_out and interior right-hand side f_out (device, n) of the next
+ * step's linear problem:
+ *   RANN_LIN_NEWTON: c_out = c0 + g'(u),  f_out = f - g(u) + g'(u) u
+ *   RANN_LIN_PICARD: c_out = c0 + q(u),   f_out = f - gamma[0],  g = gamma[0] + u q(u)
+ * gamma: host, 1 <= n_gamma <= RANN_MAX_GAMMA.  u_prev (device, n) or NULL;
+ * when given with inc (host), *inc = ||u - u_prev|| / ||u|| (synchronous).
+ * Runs on the handle's stream (h needs no PCA), or on the default stream when
+ * h is NULL (then without the increment).  RANN_EINVAL for bad sizes. */
+RANN_API int rann_dd_linearize(rann_dd_handle* h, const double* u, const double* c0, const double* f,
+                  int64_t n, const double* gamma, int32_t n_gamma, int32_t mode, double* c_out,
+                  double* f_out, const double* u_prev, double* inc);
 
 /* Raw-neuron coefficients c_j = V_j W_j (device, sum_j m_j x k). */
 RANN_API int rann_dd_coeffs(rann_dd_handle* h, const double* W, int32_t k, double* c);

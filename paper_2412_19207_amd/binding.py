@@ -23,6 +23,7 @@ STENCIL = {"self": 0, "face": 1, "full": 2}
 PRECOND = {"none": 0, "as": 1, "ras": 2, "sas": 3}
 PCA_MODE = {"rel_eig": 0, "abs_sigma": 1, "off": 2}
 METHOD = {"cg": 0, "gmres": 1, "gmres_right": 2, "cgs": 3, "bicg": 4}
+LINEARIZE = {"newton": 0, "picard": 1}
 
 c_dp = ctypes.POINTER(ctypes.c_double)
 c_ip = ctypes.POINTER(ctypes.c_int32)
@@ -77,6 +78,9 @@ _SIGS = {
     "rann_dd_apply_normal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rann_dd_apply_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rann_dd_apply_precond_T": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "rann_dd_linearize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int64, c_dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, c_dp]),
     "rann_dd_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     "rann_dd_get_layout": (ctypes.c_int, [ctypes.c_void_p, c_lp, c_ip, c_ip]),
     "rann_dd_get_arrays": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -190,6 +194,17 @@ def rann_dd_apply_precond_T(h, r_ptr, k, z_ptr):
     return _check(load().rann_dd_apply_precond_T(h, ctypes.c_void_p(r_ptr), int(k), ctypes.c_void_p(z_ptr)))
 
 
+def rann_dd_linearize(h, u_ptr, c0_ptr, f_ptr, n, gamma, mode, c_out_ptr, f_out_ptr, u_prev_ptr=0):
+    """Returns the relative increment ||u - u_prev|| / ||u|| (0.0 without u_prev)."""
+    g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
+    inc = ctypes.c_double(0.0)
+    _check(load().rann_dd_linearize(h, ctypes.c_void_p(u_ptr), ctypes.c_void_p(c0_ptr), ctypes.c_void_p(f_ptr),
+                                    int(n), g.ctypes.data_as(c_dp), int(g.size), int(mode),
+                                    ctypes.c_void_p(c_out_ptr), ctypes.c_void_p(f_out_ptr),
+                                    ctypes.c_void_p(u_prev_ptr or None), ctypes.byref(inc)))
+    return float(inc.value)
+
+
 def rann_dd_get_info(h) -> Info:
     info = Info()
     _check(load().rann_dd_get_info(h, ctypes.byref(info)))
@@ -247,10 +262,11 @@ class Solver:
 
     `prob` is a workloads.Problem (or any object with the same fields).  Every
     array is uploaded once as an FP64 device tensor; the library copies what it
-    keeps, so the uploads are released after assembly."""
+    keeps, so the uploads are released after assembly.  `c` (an FP64 device
+    tensor of n_int entries) replaces the problem's reaction coefficient."""
 
     def __init__(self, prob, precision="fp64", stencil="full", precond="as", device="cuda:0",
-                 stream=None):
+                 stream=None, c=None):
         import torch
         self.torch = torch
         self.dev = torch.device(device)
@@ -262,7 +278,8 @@ class Solver:
         t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=self.dev)
         R = t(np.concatenate([np.asarray(r).reshape(-1, d) for r in prob.R], axis=0))
         b = t(np.concatenate([np.asarray(x).ravel() for x in prob.b]))
-        Xi, a, be, c = t(prob.X_int), t(prob.a), t(prob.beta), t(prob.c)
+        Xi, a, be = t(prob.X_int), t(prob.a), t(prob.beta)
+        c = t(prob.c) if c is None else c.to(self.dev, torch.float64).contiguous()
         Xb = t(prob.X_bnd) if prob.X_bnd.shape[0] else None
         Lf = t(prob.Lfun) if prob.Lfun is not None else None
         self._mu = np.ascontiguousarray(np.concatenate([np.asarray(m, float) for m in prob.mu]))

@@ -788,6 +788,22 @@ int rann_dd_apply_precond(rann_dd_handle* hh, const double* r, int32_t k, double
     return rc;
 }
 
+int rann_dd_linearize(rann_dd_handle* hh, const double* u, const double* c0, const double* f, int64_t n,
+                      const double* gamma, int32_t n_gamma, int32_t mode, double* c_out, double* f_out,
+                      const double* u_prev, double* inc) {
+    if (n < 0 || (n > 0 && (!u || !c0 || !f || !c_out || !f_out)) || !gamma || n_gamma < 1 ||
+        n_gamma > RANN_MAX_GAMMA || (mode != RANN_LIN_NEWTON && mode != RANN_LIN_PICARD))
+        return (rdd::set_error("invalid linearize arguments"), RANN_EINVAL);
+    for (int p = 0; p < n_gamma; ++p)
+        if (!std::isfinite(gamma[p])) return (rdd::set_error("gamma must be finite"), RANN_EINVAL);
+    if (!hh) {
+        if (inc && u_prev) return (rdd::set_error("the increment needs a handle"), RANN_EINVAL);
+        Handle tmp;  // default stream, no allocation
+        return rdd::linearize(tmp, u, c0, f, n, gamma, n_gamma, mode, c_out, f_out, nullptr, inc);
+    }
+    return rdd::linearize(hh->h, u, c0, f, n, gamma, n_gamma, mode, c_out, f_out, u_prev, inc);
+}
+
 int rann_dd_apply_precond_T(rann_dd_handle* hh, const double* r, int32_t k, double* z) {
     RDD_TRY(guard_handle(hh, true));
     Handle& h = hh->h;

@@ -273,6 +273,9 @@ int adjoint_gmres(Handle& h, const double* dW, int k, const rann_dd_solve_opts& 
                   rann_dd_stats* st, int* status);
 int krylov_gmres(Handle& h, const double* rhs, int k, const double* W0,
                  const rann_dd_solve_opts& o, double* W, rann_dd_stats* st, int* status);
+// Picard / Newton linearisation of a polynomial reaction (nonlinear.hip)
+int linearize(Handle& h, const double* u, const double* c0, const double* f, int64_t n, const double* gamma,
+              int n_gamma, int mode, double* c_out, double* f_out, const double* u_prev, double* inc);
 // CGS and BiCG (method RANN_METHOD_CGS / RANN_METHOD_BICG); Fs = null: adjoint
 int krylov_lanczos(Handle& h, const double* rhs, const double* Fs, int k, const double* W0,
                    const rann_dd_solve_opts& o, double* W, rann_dd_stats* st, int* status);
