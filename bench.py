@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-RHS mixed/FP64 comparison")
     ap.add_argument("--no-variants", action="store_true", help="skip the Krylov method x preconditioner grid")
+    ap.add_argument("--no-nonlinear", action="store_true", help="skip the Newton iteration on the semilinear problem")
     ap.add_argument("--quick", action="store_true", help="skip the side measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB (counter calibration) and exit")
@@ -202,6 +203,31 @@ def krylov_variants(inp, stencil, tol, torch):
                                   "max_rel_residual": float(info["max_rel_residual"])}
         s.close()
     return out
+
+
+def nonlinear_newton(torch, wl, dev, steps=10):
+    """Newton on the semilinear problem -lap u + u^3 = f with the benchmark's
+    8x8, width-300 layout (FP64 AS-CG per step to 1e-10; the first step builds
+    the PCA basis, later steps reuse it): time per step, increments, linear
+    iterations, and the relative L2 error at the probes."""
+    from paper_2412_19207_amd import nonlinear as gnl
+    prob = wl.make("semilinear2d")
+    gamma = prob.meta["gamma"]
+    s, W, rec = gnl.solve_semilinear(prob, gamma, mode="newton", steps=steps, stop=1e-10,
+                                     tol=prob.meta["tol"], device=str(dev))
+    s.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s, W, rec = gnl.solve_semilinear(prob, gamma, mode="newton", steps=steps, stop=1e-10,
+                                     tol=prob.meta["tol"], device=str(dev))
+    torch.cuda.synchronize()
+    total = (time.perf_counter() - t0) * 1e3
+    U = s.eval(torch.as_tensor(prob.probes, device=dev), W)[:, 0].cpu().numpy()
+    s.close()
+    e = float(np.linalg.norm(U - prob.u_probe) / np.linalg.norm(prob.u_probe))
+    return {"workload": prob.name, "g": "u^3", "steps": len(rec["inc"]), "total_ms": total,
+            "step_ms": rec["step_ms"], "increments": rec["inc"], "linear_iterations": rec["iterations"],
+            "e_L2_probes": e}
 
 
 def cpu_baseline(prob, tol, stencil, min_seconds=10.0, max_reps=3):
@@ -380,6 +406,8 @@ def main():
             out["batched"] = batched_comparison(torch, binding, wl, dev)
         if not args.no_variants:
             out["krylov_variants"] = krylov_variants(inp, args.stencil, args.tol, torch)
+        if not args.no_nonlinear:
+            out["nonlinear_newton"] = nonlinear_newton(torch, wl, dev)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(prob, args.tol, args.stencil)
         out["cpu_baseline"] = {"value": k / cb["total_s"], "unit": "solves/s",

@@ -8,7 +8,8 @@ linear problem come from `rann_dd_linearize` (Newton or Picard) at the current
 values u_k on the interior collocation points, a handle is assembled with that
 reaction, its PCA basis is the first step's (the basis depends only on the
 value matrix, not on the operator), the linear problem is solved by the chosen
-Krylov method, and u_{k+1} at the interior points comes from `rann_dd_eval`.
+Krylov method from the previous step's coefficients, and u_{k+1} at the
+interior points comes from `rann_dd_eval`.
 This module only sequences those calls and holds the device buffers.
 """
 from __future__ import annotations
@@ -22,7 +23,7 @@ from . import binding
 
 def solve_semilinear(prob, gamma, mode="newton", steps=8, stop=0.0, tol=1e-10, maxiter=5000,
                      precision="fp64", stencil="full", precond="as", method="cg", pca_tol=None,
-                     p_force=None, V_force=None, device="cuda:0", keep_iterates=False):
+                     pca_mode=None, p_force=None, V_force=None, device="cuda:0", keep_iterates=False):
     """Run up to `steps` steps from u_0 = 0 on the first right-hand side column;
     stop early when the relative increment of u at the interior points drops to
     `stop`.  Returns the last handle (open; the caller closes it), its W, and a
@@ -38,6 +39,7 @@ def solve_semilinear(prob, gamma, mode="newton", steps=8, stop=0.0, tol=1e-10, m
     c = torch.empty_like(u)
     fl = torch.empty_like(u)
     pca_tol = prob.meta["pca_tol"] if pca_tol is None else pca_tol
+    pca_mode = prob.meta.get("pca_mode", "rel_eig") if pca_mode is None else pca_mode
     rec = dict(inc=[], iterations=[], step_ms=[], W=[])
     s_prev = None
     s = W = None
@@ -49,12 +51,13 @@ def solve_semilinear(prob, gamma, mode="newton", steps=8, stop=0.0, tol=1e-10, m
                                       binding.LINEARIZE[mode], c.data_ptr(), fl.data_ptr())
         s = binding.Solver(prob, precision=precision, stencil=stencil, precond=precond, device=device, c=c)
         if V_force is None:
-            p_force = s.pca(pca_tol, "rel_eig")
+            p_force = s.pca(pca_tol, pca_mode)
             V_force = s.arrays()[1].clone()
         else:
-            s.pca(pca_tol, "rel_eig", p_force=p_force, V_force=V_force)
+            s.pca(pca_tol, pca_mode, p_force=p_force, V_force=V_force)
         F = torch.cat([fl[:, None], g_bnd], 0)
-        W, info = s.solve(F, tol=tol, maxiter=maxiter, method=method)
+        # warm start from the previous step's coefficients (same basis)
+        W, info = s.solve(F, tol=tol, maxiter=maxiter, method=method, W0=W)
         u_new = s.eval(Xi, W)[:, 0].contiguous()
         # the next step's data, and the increment of this one
         inc = binding.rann_dd_linearize(s.handle, u_new.data_ptr(), c0.data_ptr(), f.data_ptr(), nI, gamma,

@@ -536,14 +536,15 @@ def semilinear2d(size="full", **kw) -> Problem:
                     - 2 * PI * (np.cos(PI * x) * np.sin(PI * y) + np.sin(PI * x) * np.cos(PI * y)))
         return mlap + exact(X) ** 3
 
-    meta = dict(pca_tol=1e-8, tol=1e-10, stencil="full", method="cg", precond="as",
-                gamma=[0.0, 0.0, 0.0, 1.0])
+    # the paper's absolute singular-value threshold tau = 1e-3 on the value matrices
+    meta = dict(pca_mode="abs_sigma", pca_tol=1e-3, tol=1e-10, stencil="full", method="cg",
+                precond="as", gamma=[0.0, 0.0, 0.0, 1.0])
     if size == "small":
         l, m = [3, 2], np.resize(np.asarray((40, 57, 33, 64, 48, 71), dtype=np.int32), 6)
         args = dict(name="semilinear2d_small", d=2, l=l, m=m, weight_scale=2.0,
                     pts_per_sub=[11, 9], overlap_frac=0.2, faces=_all_faces(2),
                     bnd_counts=[21, 10], probes_per_dim=[23, 19])
-        meta.update(pca_tol=1e-10, tol=1e-12)
+        meta.update(pca_mode="rel_eig", pca_tol=1e-10, tol=1e-12)
     else:
         args = dict(name="semilinear2d_8x8_m300", d=2, l=[8, 8], m=300, weight_scale=3.0,
                     pts_per_sub=[30, 30], overlap_frac=0.1, faces=_all_faces(2),
