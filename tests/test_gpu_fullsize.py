@@ -210,3 +210,68 @@ def test_cfg5_full_size_adjoint_central_differences():
     scale = np.maximum(np.abs(ad), 1e-12 * np.linalg.norm(grad) * np.linalg.norm(D, axis=0))
     assert np.all(np.abs(fd - ad) <= 1e-6 * scale), np.max(np.abs(fd - ad) / scale)
     s.close()
+
+
+@pytest.mark.parametrize("method", ["cgs", "bicg"])
+def test_cfg2_full_size_cgs_bicg_with_sas(method):
+    """The benchmark workload with the non-symmetric SAS preconditioner (Table
+    1b's pairing): CGS and BiCG reach the tolerance, and the normal residual of
+    the GPU solution, evaluated by the oracle's own operator in the GPU's
+    basis, meets it too."""
+    _need_gpu()
+    prob = _prob("cfg2")
+    meta = prob.meta
+    s = binding.Solver(prob, device=DEV, precision="fp64", stencil=meta["stencil"], precond="sas")
+    p = s.pca(meta["pca_tol"], "rel_eig")
+    F = torch.as_tensor(prob.F, device=DEV)
+    W, info = s.solve(F, tol=meta["tol"], method=method, maxiter=2000)
+    assert info["status"] == 0
+    assert info["max_rel_residual"] <= meta["tol"]
+    key = "cfg2:gpu-basis"
+    if key not in _cache:
+        Vg, _ = _gpu_basis(s, prob, p)
+        _cache[key] = oasm.assemble(prob, "rel_eig", meta["pca_tol"], V_force=Vg)
+    sysg = _cache[key]
+    res = osolve.normal_residual(obs.BlockH(sysg), W.cpu().numpy(), sysg.Fs)
+    assert np.all(res <= meta["tol"] * 1.01 + 1e-9), res
+    s.close()
+
+
+def test_semilinear_full_size_newton():
+    """Newton on -lap u + u^3 = f with the 8x8, width-300 layout: fast
+    convergence of the increments, the manufactured solution to the
+    discretisation error, and the Gauss-Newton stationarity J^T r = 0 of the
+    limit checked with the library's own products: r from the operator rows of
+    the linear part and the values at the collocation points, J^T from the last
+    step's operator (reaction c0 + g'(u))."""
+    _need_gpu()
+    from paper_2412_19207_amd import nonlinear as gnl
+    prob = _prob("semilinear2d")
+    meta = prob.meta
+    gamma = meta["gamma"]
+    s, W, rec = gnl.solve_semilinear(prob, gamma, mode="newton", steps=10, stop=1e-11, tol=meta["tol"],
+                                     device=DEV)
+    inc = rec["inc"]
+    assert inc[-1] <= 1e-11, inc
+    # Gauss-Newton: quadratic once in the basin, until the linear rate that the
+    # least-squares residual sets (here below 1e-3) takes over
+    for k in range(2, len(inc) - 1):
+        if inc[k] < 1e-2:
+            assert inc[k + 1] <= max(10.0 * inc[k] ** 2, 1e-3 * inc[k]), (k, inc)
+    U = s.eval(torch.as_tensor(prob.probes, device=DEV), W)[:, 0].cpu().numpy()
+    e = np.linalg.norm(U - prob.u_probe) / np.linalg.norm(prob.u_probe)
+    assert e < 3e-2, e
+    # the nonlinear residual with the linear part's rows (reaction c0, same basis)
+    s0 = binding.Solver(prob, device=DEV)
+    s0.pca(meta["pca_tol"], meta["pca_mode"], p_force=rec["p"], V_force=rec["V"])
+    nI = prob.N_I
+    Fs = torch.as_tensor(prob.F[:, :1], device=DEV).clone()
+    Fs[nI:] *= prob.lambda_B
+    r = s0.matvec(W) - Fs
+    u = s.eval(torch.as_tensor(prob.X_int, device=DEV), W)
+    r[:nI] += sum(c * u ** q for q, c in enumerate(gamma))
+    g = s.rmatvec(r)
+    scale = s.rmatvec(Fs)
+    assert float(torch.linalg.norm(g) / torch.linalg.norm(scale)) <= 1e-7
+    s0.close()
+    s.close()
