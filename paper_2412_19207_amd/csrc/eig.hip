@@ -608,6 +608,8 @@ __global__ void __launch_bounds__(256) k_pcount(const int32_t* __restrict__ mvec
 // eigenvectors of T for the p largest eigenvalues by inverse iteration, one
 // thread per vector (vector t <-> lam[m-1-t]); entry i of vector t is kept at
 // Zt[i m + t] and its LU factors at LU[(f m + i) m + t]
+constexpr int kIB = 16;  // steps of a sweep whose loads are issued together
+
 __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec,
                                                 double* __restrict__ Sall,
                                                 const int64_t* __restrict__ s_off,
@@ -677,21 +679,24 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
         fr[m - 1] = 1.0 / ai;
         StridedRef z{Zt + t, mm};  // z_t[i] at Zt[i m + t]
         for (int i = 0; i < m; ++i) z[i] = 1.0 + 0.5 * sin(0.7 * (double)(i + 1) + 1.3 * (double)(t + 1));
+        // three sweeps; the normalisation of each iterate is folded into the
+        // next forward sweep (scale sc), and done once at the end
+        double sc = 1.0;
         for (int iter = 0; iter < 3; ++iter) {
-            // forward: row swaps and multipliers, 8 steps per batch of loads
-            double zc = z[0];
-            for (int i0 = 0; i0 + 1 < m; i0 += 8) {
-                const int n = (m - 1 - i0 < 8) ? m - 1 - i0 : 8;
-                double zn[8], mu[8], pv[8], out[8];
+            // forward: row swaps and multipliers, kIB steps per batch of loads
+            double zc = z[0] * sc;
+            for (int i0 = 0; i0 + 1 < m; i0 += kIB) {
+                const int n = (m - 1 - i0 < kIB) ? m - 1 - i0 : kIB;
+                double zn[kIB], mu[kIB], pv[kIB], out[kIB];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < kIB; ++u)
                     if (u < n) {
-                        zn[u] = z[i0 + u + 1];
+                        zn[u] = z[i0 + u + 1] * sc;
                         mu[u] = fm[i0 + u];
                         pv[u] = fp[i0 + u];
                     }
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < kIB; ++u)
                     if (u < n) {
                         if (pv[u] != 0.0) {
                             out[u] = zn[u];
@@ -702,18 +707,18 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
                         }
                     }
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < kIB; ++u)
                     if (u < n) z[i0 + u] = out[u];
             }
-            // backward: U z = y, 8 steps per batch of loads
+            // backward: U z = y, kIB steps per batch of loads
             double z1 = zc * fr[m - 1], z2 = 0.0;
             z[m - 1] = z1;
             double nn = z1 * z1;
-            for (int i1 = m - 2; i1 >= 0; i1 -= 8) {
-                const int n = (i1 + 1 < 8) ? i1 + 1 : 8;
-                double zv[8], bv[8], cv[8], rv[8];
+            for (int i1 = m - 2; i1 >= 0; i1 -= kIB) {
+                const int n = (i1 + 1 < kIB) ? i1 + 1 : kIB;
+                double zv[kIB], bv[kIB], cv[kIB], rv[kIB];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < kIB; ++u)
                     if (u < n) {
                         zv[u] = z[i1 - u];
                         bv[u] = fb[i1 - u];
@@ -721,7 +726,7 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
                         rv[u] = fr[i1 - u];
                     }
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < kIB; ++u)
                     if (u < n) {
                         const double zi = (zv[u] - bv[u] * z1 - cv[u] * z2) * rv[u];
                         zv[u] = zi;
@@ -730,19 +735,19 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
                         z1 = zi;
                     }
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < kIB; ++u)
                     if (u < n) z[i1 - u] = zv[u];
             }
-            const double inv = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
-            for (int i0 = 0; i0 < m; i0 += 8) {
-                double zv[8];
+            sc = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+        }
+        for (int i0 = 0; i0 < m; i0 += kIB) {
+            double zv[kIB];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (i0 + u < m) zv[u] = z[i0 + u];
+            for (int u = 0; u < kIB; ++u)
+                if (i0 + u < m) zv[u] = z[i0 + u];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (i0 + u < m) z[i0 + u] = zv[u] * inv;
-            }
+            for (int u = 0; u < kIB; ++u)
+                if (i0 + u < m) z[i0 + u] = zv[u] * sc;
         }
     }
 }
