@@ -608,8 +608,22 @@ __global__ void __launch_bounds__(256) k_pcount(const int32_t* __restrict__ mvec
 // eigenvectors of T for the p largest eigenvalues by inverse iteration, one
 // thread per vector (vector t <-> lam[m-1-t]); entry i of vector t is kept at
 // Zt[i m + t] and its LU factors at LU[(f m + i) m + t]
-constexpr int kIB = 16;  // steps of a sweep whose loads are issued together
+constexpr int kIvLds = 16384;  // doubles of LDS for the factors and iterates of inverse iteration
 
+// vectors of one inverse-iteration workgroup for width m: six LDS arrays of m
+// entries per vector (the factors of T - lam I, the swap flags, the iterate)
+__host__ __device__ inline int inviter_vectors(int m) {
+    const int v = kIvLds / (6 * (m > 0 ? m : 1));
+    return v < 1 ? 1 : (v > 64 ? 64 : v);
+}
+
+// Inverse iteration on the tridiagonal T for the p largest eigenvalues: lane v
+// of the workgroup takes vector t = y V + v (V = inviter_vectors(m)) <-> lam[m-1-t].
+// T - lam I is factored once with partial pivoting (rows i, i+1 swapped when
+// |sub| > |a_i|, tiny pivots replaced by +-eps_piv), the factors kept in LDS;
+// then three sweeps (swaps and multipliers, then U z = y) from a fixed start
+// vector, the normalisation of each iterate folded into the next sweep.  The
+// result goes to Zt[i m + t].
 __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec,
                                                 double* __restrict__ Sall,
                                                 const int64_t* __restrict__ s_off,
@@ -619,15 +633,16 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
     __shared__ double dd[kMaxWidth];
     __shared__ double ee[kMaxWidth];
     __shared__ double ea[kMaxWidth];
+    __shared__ double fs[kIvLds];
     const int j = blockIdx.x;
     const int m = mvec[j];
     const int p = p_out[j];
-    if ((int)blockIdx.y * 64 >= p) return;  // uniform per workgroup
+    const int V = inviter_vectors(m);
+    if ((int)blockIdx.y * V >= p) return;  // uniform per workgroup
     const int64_t mm = m;
     const double* tri = Sall + s_off[j] + scr_tri(mm);
     const double* lam = lam_all + m_off[j];
-    double* LU = Sall + s_off[j] + scr_LU(mm);
-    double* Zt = LU + 5 * mm * mm;
+    double* Zt = Sall + s_off[j] + scr_LU(mm) + 5 * mm * mm;
     for (int i = threadIdx.x; i < m; i += 64) {
         const double e = (i + 1 < m) ? tri[mm + i] : 0.0;
         dd[i] = tri[i];
@@ -636,120 +651,76 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
     }
     __syncthreads();
     const TriBounds tb = tri_bounds(dd, ea, m);
-    const int t = blockIdx.y * 64 + threadIdx.x;
-    if (t >= p) return;
-    // ---- 3. inverse iteration for the p largest: vector t <-> lam[m-1-t]
+    const int v = threadIdx.x;
+    const int t = blockIdx.y * V + v;
+    if (v >= V || t >= p) return;
     const double eps_piv = DBL_EPSILON * tb.tnorm + tb.pivmin;
+    const double lmb = lam[m - 1 - t];
+    // entry i of this lane's arrays at [i V + v]
+    const int64_t mv = (int64_t)m * V;
+    double* fr = fs + v;           // reciprocal of the diagonal of U
+    double* fb = fs + mv + v;      // first superdiagonal
+    double* fc = fs + 2 * mv + v;  // second superdiagonal (fill-in)
+    double* fm = fs + 3 * mv + v;  // multipliers
+    double* fp = fs + 4 * mv + v;  // 1.0 where rows i, i+1 were swapped
+    double* z = fs + 5 * mv + v;   // the iterate
+    double ai = dd[0] - lmb, bi = ee[0];
+    for (int i = 0; i + 1 < m; ++i) {
+        const double sub = ee[i];
+        const double an = dd[i + 1] - lmb;                 // a[i+1] before step i
+        const double bn = (i + 2 < m) ? ee[i + 1] : 0.0;   // b[i+1] before step i
+        const bool swap = fabs(ai) < fabs(sub);
+        double a = swap ? sub : ai;
+        if (!swap && fabs(a) < eps_piv) a = (a < 0.0) ? -eps_piv : eps_piv;
+        const double ra = 1.0 / a;
+        const double mu = (swap ? ai : sub) * ra;
+        fr[i * V] = ra;
+        fb[i * V] = swap ? an : bi;
+        fc[i * V] = swap ? bn : 0.0;
+        fm[i * V] = mu;
+        fp[i * V] = swap ? 1.0 : 0.0;
+        const double ai_n = swap ? bi - mu * an : an - mu * bi;
+        bi = swap ? -mu * bn : bn;
+        ai = ai_n;
+    }
+    if (fabs(ai) < eps_piv) ai = (ai < 0.0) ? -eps_piv : eps_piv;
+    const double rlast = 1.0 / ai;
+    // start vector 1 + sin(0.7 (i + 1) + 1.3 (t + 1)) / 2 by the angle-addition recurrence
     {
-        const double lmb = lam[m - 1 - t];
-        // field f of step i at LU[(f m + i) m + t]: consecutive vectors are adjacent
-        StridedRef fr{LU + t, mm};                  // reciprocal of the diagonal of U
-        StridedRef fb{LU + mm * mm + t, mm};        // first superdiagonal
-        StridedRef fc{LU + 2 * mm * mm + t, mm};    // second superdiagonal (fill-in)
-        StridedRef fm{LU + 3 * mm * mm + t, mm};    // multipliers
-        StridedRef fp{LU + 4 * mm * mm + t, mm};    // 1.0 where rows i, i+1 were swapped
-        double ai = dd[0] - lmb, bi = ee[0];
-        for (int i = 0; i + 1 < m; ++i) {
-            const double sub = ee[i];
-            const double an = dd[i + 1] - lmb;                 // a[i+1] before step i
-            const double bn = (i + 2 < m) ? ee[i + 1] : 0.0;   // b[i+1] before step i
-            if (fabs(ai) >= fabs(sub)) {
-                double a = ai;
-                if (fabs(a) < eps_piv) a = (a < 0.0) ? -eps_piv : eps_piv;
-                const double mu = sub / a;
-                fr[i] = 1.0 / a;
-                fb[i] = bi;
-                fc[i] = 0.0;
-                fm[i] = mu;
-                fp[i] = 0.0;
-                ai = an - mu * bi;
-                bi = bn;
-            } else {
-                const double mu = ai / sub;
-                fr[i] = 1.0 / sub;
-                fb[i] = an;
-                fc[i] = bn;
-                fm[i] = mu;
-                fp[i] = 1.0;
-                ai = bi - mu * an;
-                bi = -mu * bn;
-            }
-        }
-        if (fabs(ai) < eps_piv) ai = (ai < 0.0) ? -eps_piv : eps_piv;
-        fr[m - 1] = 1.0 / ai;
-        StridedRef z{Zt + t, mm};  // z_t[i] at Zt[i m + t]
-        for (int i = 0; i < m; ++i) z[i] = 1.0 + 0.5 * sin(0.7 * (double)(i + 1) + 1.3 * (double)(t + 1));
-        // three sweeps; the normalisation of each iterate is folded into the
-        // next forward sweep (scale sc), and done once at the end
-        double sc = 1.0;
-        for (int iter = 0; iter < 3; ++iter) {
-            // forward: row swaps and multipliers, kIB steps per batch of loads
-            double zc = z[0] * sc;
-            for (int i0 = 0; i0 + 1 < m; i0 += kIB) {
-                const int n = (m - 1 - i0 < kIB) ? m - 1 - i0 : kIB;
-                double zn[kIB], mu[kIB], pv[kIB], out[kIB];
-#pragma unroll
-                for (int u = 0; u < kIB; ++u)
-                    if (u < n) {
-                        zn[u] = z[i0 + u + 1] * sc;
-                        mu[u] = fm[i0 + u];
-                        pv[u] = fp[i0 + u];
-                    }
-#pragma unroll
-                for (int u = 0; u < kIB; ++u)
-                    if (u < n) {
-                        if (pv[u] != 0.0) {
-                            out[u] = zn[u];
-                            zc = zc - mu[u] * zn[u];
-                        } else {
-                            out[u] = zc;
-                            zc = zn[u] - mu[u] * zc;
-                        }
-                    }
-#pragma unroll
-                for (int u = 0; u < kIB; ++u)
-                    if (u < n) z[i0 + u] = out[u];
-            }
-            // backward: U z = y, kIB steps per batch of loads
-            double z1 = zc * fr[m - 1], z2 = 0.0;
-            z[m - 1] = z1;
-            double nn = z1 * z1;
-            for (int i1 = m - 2; i1 >= 0; i1 -= kIB) {
-                const int n = (i1 + 1 < kIB) ? i1 + 1 : kIB;
-                double zv[kIB], bv[kIB], cv[kIB], rv[kIB];
-#pragma unroll
-                for (int u = 0; u < kIB; ++u)
-                    if (u < n) {
-                        zv[u] = z[i1 - u];
-                        bv[u] = fb[i1 - u];
-                        cv[u] = fc[i1 - u];
-                        rv[u] = fr[i1 - u];
-                    }
-#pragma unroll
-                for (int u = 0; u < kIB; ++u)
-                    if (u < n) {
-                        const double zi = (zv[u] - bv[u] * z1 - cv[u] * z2) * rv[u];
-                        zv[u] = zi;
-                        nn = fma(zi, zi, nn);
-                        z2 = z1;
-                        z1 = zi;
-                    }
-#pragma unroll
-                for (int u = 0; u < kIB; ++u)
-                    if (u < n) z[i1 - u] = zv[u];
-            }
-            sc = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
-        }
-        for (int i0 = 0; i0 < m; i0 += kIB) {
-            double zv[kIB];
-#pragma unroll
-            for (int u = 0; u < kIB; ++u)
-                if (i0 + u < m) zv[u] = z[i0 + u];
-#pragma unroll
-            for (int u = 0; u < kIB; ++u)
-                if (i0 + u < m) z[i0 + u] = zv[u] * sc;
+        double sn = sin(0.7 + 1.3 * (double)(t + 1)), cs = cos(0.7 + 1.3 * (double)(t + 1));
+        const double s7 = sin(0.7), c7 = cos(0.7);
+        for (int i = 0; i < m; ++i) {
+            z[i * V] = 1.0 + 0.5 * sn;
+            const double sn2 = sn * c7 + cs * s7;
+            cs = cs * c7 - sn * s7;
+            sn = sn2;
         }
     }
+    double sc = 1.0;
+    for (int iter = 0; iter < 3; ++iter) {
+        // forward: the swaps and multipliers on the scaled iterate
+        double zc = z[0] * sc;
+        for (int i = 0; i + 1 < m; ++i) {
+            const double zn = z[(i + 1) * V] * sc;
+            const double mu = fm[i * V];
+            const bool swap = fp[i * V] != 0.0;
+            z[i * V] = swap ? zn : zc;
+            zc = swap ? zc - mu * zn : zn - mu * zc;
+        }
+        // backward: U z = y
+        double z1 = zc * rlast, z2 = 0.0;
+        z[(m - 1) * V] = z1;
+        double nn = z1 * z1;
+        for (int i = m - 2; i >= 0; --i) {
+            const double zi = (z[i * V] - fb[i * V] * z1 - fc[i * V] * z2) * fr[i * V];
+            z[i * V] = zi;
+            nn = fma(zi, zi, nn);
+            z2 = z1;
+            z1 = zi;
+        }
+        sc = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+    }
+    for (int i = 0; i < m; ++i) Zt[(int64_t)i * mm + t] = z[i * V] * sc;
 }
 
 // orthonormalisation and y = Q z for the p vectors; one workgroup per matrix
@@ -962,7 +933,12 @@ int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const i
                        d_s_off, d_lam, h.d_m_off, d_eig);
     hipLaunchKernelGGL(k_pcount, dim3(J), dim3(256), 0, h.stream, h.d_m, S, d_s_off, d_lam, tol, mode,
                        d_p, h.d_m_off, d_flags);
-    hipLaunchKernelGGL(k_inviter, dim3(J, (unsigned)((mmax + 63) / 64)), dim3(64), 0, h.stream, h.d_m, S,
+    int iv_y = 1;  // workgroups per matrix: enough for all m vectors
+    for (int jj = 0; jj < J; ++jj) {
+        const int V = inviter_vectors(h.m[jj]);
+        iv_y = std::max(iv_y, (h.m[jj] + V - 1) / V);
+    }
+    hipLaunchKernelGGL(k_inviter, dim3(J, (unsigned)iv_y), dim3(64), 0, h.stream, h.d_m, S,
                        d_s_off, d_lam, d_p, h.d_m_off);
     hipLaunchKernelGGL(k_vectors, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S, d_s_off, Y, d_p);
     hipLaunchKernelGGL(k_backxf, dim3(J, (unsigned)((mmax + kSlice - 1) / kSlice)), dim3(kPT), 0, h.stream, h.d_m,
