@@ -192,8 +192,13 @@ __global__ void __launch_bounds__(256) k_tile_apply_ps(const int4* __restrict__ 
         const int64_t q_ = qv[i_];                                                            \
         const int64_t tile_ = (int64_t)a_ * (a_ + 1) / 2 + b_;                                \
         const double2* src_ = reinterpret_cast<const double2*>(M + t_off[i_] + tile_ * kTE);  \
+        /* rows and columns of the tile inside the block: the zero padding of */            \
+        /* the last tile row and column is not read */                                      \
+        const int64_t rv_ = q_ - (int64_t)a_ * kT, cv_ = q_ - (int64_t)b_ * kT;               \
         _Pragma("unroll") for (int e = 0; e < 8; ++e) {                                      \
-            const double2 w_ = src_[e * 256 + tid];                                           \
+            const int ch_ = e * 256 + tid;                                                    \
+            const bool in_ = (ch_ >> 5) < rv_ && 2 * (ch_ & 31) < cv_;                        \
+            const double2 w_ = in_ ? src_[ch_] : make_double2(0.0, 0.0);                      \
             V[2 * e] = w_.x;                                                                  \
             V[2 * e + 1] = w_.y;                                                              \
         }                                                                                     \
