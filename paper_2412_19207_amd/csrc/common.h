@@ -208,19 +208,25 @@ int ensure_ws(Handle& h, size_t bytes);
 // off by default): KTimer t(stream, "k_name"); <launch>; t.stop();
 bool ktime_enabled();
 void ktime_record(const char* name, hipEvent_t a, hipEvent_t b);
+// Times the launches between construction and stop() with two events on the
+// stream.  With on_launch, the region is one launch that records the events
+// itself (hipExtLaunchKernelGGL with a and b: its start and end), so the
+// figure is that kernel's own duration.
 struct KTimer {
     hipStream_t s;
     const char* name;
     hipEvent_t a = nullptr, b = nullptr;
-    KTimer(hipStream_t stream, const char* n) : s(stream), name(n) {
-        if (ktime_enabled() && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
-            (void)hipEventRecord(a, s);
-        else
+    bool on_launch = false;
+    KTimer(hipStream_t stream, const char* n, bool by_launch = false) : s(stream), name(n), on_launch(by_launch) {
+        if (ktime_enabled() && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+            if (!on_launch) (void)hipEventRecord(a, s);
+        } else {
             a = b = nullptr;
+        }
     }
     void stop() {
         if (a) {
-            (void)hipEventRecord(b, s);
+            if (!on_launch) (void)hipEventRecord(b, s);
             ktime_record(name, a, b);
             a = b = nullptr;
         }

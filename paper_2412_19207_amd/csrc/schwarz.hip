@@ -16,6 +16,8 @@
 //         (two passes over Y, the second usually from cache).
 #include <hip/hip_runtime.h>
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -935,7 +937,10 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
     const int64_t tot = h.ub_total * k;
     const unsigned tgrid = (unsigned)h.n_tile_tasks;
     if (tgrid == 0 || tot == 0) return RANN_OK;
-    KTimer kt_(h.stream, "k_tile_apply");
+    // FP64 with one or two right-hand sides is a single persistent launch,
+    // timed by the events it records itself
+    const bool one_launch = h.precision != RANN_MIXED && k <= 2;
+    KTimer kt_(h.stream, "k_tile_apply", one_launch);
     int kv0 = 0;  // right-hand sides from kv0 on take the slot path
     for (int k0 = 0; k0 < k;) {
         const int rem = k - k0;
@@ -994,14 +999,17 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
         } else if (kb <= 2) {
             // persistent over about two workgroups per compute unit
             const unsigned pg = std::min<unsigned>(tgrid, 512u);
+            hipEvent_t ea = one_launch ? kt_.a : nullptr, eb = one_launch ? kt_.b : nullptr;
             if (kb == 2)
-                hipLaunchKernelGGL((k_tile_apply_ps<2>), dim3(pg), dim3(256), 0, h.stream, h.d_tile_tasks,
-                                   (int)h.n_tile_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols,
-                                   h.d_M64, r, k, k0, Rs, Cs);
+                hipExtLaunchKernelGGL((k_tile_apply_ps<2>), dim3(pg), dim3(256), 0, h.stream, ea, eb, 0,
+                                      (const int4*)h.d_tile_tasks, (int)h.n_tile_tasks, (const int64_t*)h.d_t_off,
+                                      (const int64_t*)h.d_q, (const int64_t*)h.d_ub_off, (const int64_t*)h.d_s_off,
+                                      (const int32_t*)h.d_blk_cols, (const double*)h.d_M64, r, k, k0, Rs, Cs);
             else
-                hipLaunchKernelGGL((k_tile_apply_ps<1>), dim3(pg), dim3(256), 0, h.stream, h.d_tile_tasks,
-                                   (int)h.n_tile_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols,
-                                   h.d_M64, r, k, k0, Rs, Cs);
+                hipExtLaunchKernelGGL((k_tile_apply_ps<1>), dim3(pg), dim3(256), 0, h.stream, ea, eb, 0,
+                                      (const int4*)h.d_tile_tasks, (int)h.n_tile_tasks, (const int64_t*)h.d_t_off,
+                                      (const int64_t*)h.d_q, (const int64_t*)h.d_ub_off, (const int64_t*)h.d_s_off,
+                                      (const int32_t*)h.d_blk_cols, (const double*)h.d_M64, r, k, k0, Rs, Cs);
         } else {
             RDD_TA_KB(double, h.d_M64, true, true, false, true);
         }
