@@ -102,7 +102,7 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+        raise RuntimeError(f"{path} is missing: build the library first (paper_2412_19207_amd.build.build())")
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

@@ -5,7 +5,7 @@ counts that are not multiples of the tile).  Tolerances:
   * integer work (binning, truncation counts): bit-exact
   * entries of H, products, local inverses: 1e-11 relative to the largest entry
     (same FP64 formulas, different summation order)
-  * FP64 solve: coefficient error <= 1e-8 relative (the benchmark spec), mixed <= 1e-6
+  * FP64 solve: coefficient error <= 1e-8 relative, mixed <= 1e-6
 """
 import numpy as np
 import pytest
