@@ -161,9 +161,12 @@ __global__ void __launch_bounds__(256) k_tile_apply(const int4* __restrict__ tas
 // The same tile products for the symmetric FP64 W with 1 or 2 right-hand
 // sides, persistent: workgroup w takes the tiles w, w + G, ... (G = grid
 // size) and loads the next tile, its task record and its x values while the
-// current tile is multiplied.  A tile is read with whole-line loads (thread t
-// takes the 16-byte pieces t, t + 256, ...) into LDS, from where the row sums
-// read rows and the column sums read columns.
+// current tile is multiplied.  A tile is read with whole-line loads: thread t
+// takes the 16-byte pieces t, t + 256, ..., i.e. columns 2 (t % 32), + 1 of
+// the rows 8 e + t / 32 (e = 0..7), and multiplies them in registers.  Row
+// sums reduce over the 32 lanes that share the rows (a reduce-scatter over
+// shuffles, one row per lane group at the end); column sums reduce over the
+// eight row groups (the two of a wave by a shuffle, the four waves in LDS).
 template <int KB>
 __global__ void __launch_bounds__(256) k_tile_apply_ps(const int4* __restrict__ tasks, int ntasks,
                                                        const int64_t* __restrict__ t_off,
@@ -175,12 +178,11 @@ __global__ void __launch_bounds__(256) k_tile_apply_ps(const int4* __restrict__ 
                                                        const double* __restrict__ r, int k, int k0,
                                                        double* __restrict__ Rs, double* __restrict__ Cs) {
     static_assert(KB <= 2, "one staged x value per thread");
-    constexpr int kTS = kT + 2;  // LDS row stride (16-byte aligned rows)
     __shared__ double xb[kT][KB];
     __shared__ double xa[kT][KB];
-    __shared__ __attribute__((aligned(16))) double ts[kT * kTS];
-    const int tid = threadIdx.x, row = tid >> 2, seg = tid & 3;
-    const int col = tid >> 2, rq = tid & 3;
+    __shared__ double red[4][kT][KB];  // column partials of the four waves
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lrow = tid >> 5, cp = tid & 31;  // rows 8 e + lrow, columns 2 cp, 2 cp + 1
     // thread tid < 64 KB stages x_b entry tid, 64 KB <= tid < 128 KB stages x_a
     const bool sb = tid < kT * KB, sa = !sb && tid < 2 * kT * KB;
     const int se = sb ? tid : tid - kT * KB;
@@ -220,65 +222,76 @@ __global__ void __launch_bounds__(256) k_tile_apply_ps(const int4* __restrict__ 
         const bool do_c = tk.y != tk.z;
         const int64_t q = qv[tk.x];
         const int cmax = (int)((q - (int64_t)tk.z * kT) < kT ? q - (int64_t)tk.z * kT : kT);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int ch = e * 256 + tid;  // 16-byte piece: row ch / 32, columns 2 (ch % 32) ..
-            *reinterpret_cast<double2*>(ts + (ch >> 5) * kTS + 2 * (ch & 31)) = make_double2(v[2 * e], v[2 * e + 1]);
-        }
         if (sb) xb[sc][st] = xr;
         if (sa) xa[sc][st] = xr;
-        __syncthreads();
+        __syncthreads();  // x staged; the previous tile's column partials are read
         const int next = task + gridDim.x;
         int4 tkn;
         double vn[16];
         double xrn;
         int64_t son;
         RDD_PS_FETCH(next < ntasks ? next : task, tkn, vn, xrn, son)  // the last round reloads its own tile
-        // row sums: thread (row, seg) over 16 columns
-        double acc[KB];
-#pragma unroll
-        for (int t = 0; t < KB; ++t) acc[t] = 0.0;
-        const double* tr = ts + row * kTS + seg * 16;
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc)
-#pragma unroll
-            for (int t = 0; t < KB; ++t) acc[t] = fma(tr[cc], xb[seg * 16 + cc][t], acc[t]);
 #pragma unroll
         for (int t = 0; t < KB; ++t) {
-            acc[t] += __shfl_xor(acc[t], 1);
-            acc[t] += __shfl_xor(acc[t], 2);
-        }
-        if (seg == 0)
+            const double x0 = xb[2 * cp][t], x1 = xb[2 * cp + 1][t];
+            // row partials of rows 8 e + lrow, e = 0..7
+            double p[8];
 #pragma unroll
-            for (int t = 0; t < KB; ++t) Rs[so + (int64_t)row * k + t] = acc[t];
-        // column sums: thread (col, rq) over the rows rq, rq + 4, ...
-        if (do_c) {
-            double c[KB];
+            for (int e = 0; e < 8; ++e) p[e] = fma(v[2 * e], x0, v[2 * e + 1] * x1);
+            // reduce-scatter over lanes xor 16, 8, 4: lane keeps one row
+            // (e = 4 b4 + 2 b3 + b2 from its lane bits 4, 3, 2)
+            const int b4 = (cp >> 4) & 1, b3 = (cp >> 3) & 1, b2 = (cp >> 2) & 1;
+            double p4[4];
 #pragma unroll
-            for (int t = 0; t < KB; ++t) c[t] = 0.0;
-#pragma unroll
-            for (int rr = 0; rr < 16; ++rr) {
-                const int rw = rq + 4 * rr;
-                const double tv = ts[rw * kTS + col];
-#pragma unroll
-                for (int t = 0; t < KB; ++t) c[t] = fma(tv, xa[rw][t], c[t]);
+            for (int u = 0; u < 4; ++u) {
+                const double mine = b4 ? p[4 + u] : p[u], other = b4 ? p[u] : p[4 + u];
+                p4[u] = mine + __shfl_xor(other, 16);
             }
+            double p2[2];
 #pragma unroll
-            for (int t = 0; t < KB; ++t) {
-                c[t] += __shfl_xor(c[t], 1);
-                c[t] += __shfl_xor(c[t], 2);
+            for (int u = 0; u < 2; ++u) {
+                const double mine = b3 ? p4[2 + u] : p4[u], other = b3 ? p4[u] : p4[2 + u];
+                p2[u] = mine + __shfl_xor(other, 8);
             }
-            if (rq == 0 && col < cmax)
+            double p1;
+            {
+                const double mine = b2 ? p2[1] : p2[0], other = b2 ? p2[0] : p2[1];
+                p1 = mine + __shfl_xor(other, 4);
+            }
+            p1 += __shfl_xor(p1, 2);
+            p1 += __shfl_xor(p1, 1);
+            if ((cp & 3) == 0) {
+                const int e = 4 * b4 + 2 * b3 + b2;
+                Rs[so + (int64_t)(8 * e + lrow) * k + t] = p1;
+            }
+            // column partials of columns 2 cp, 2 cp + 1 over this thread's rows
+            if (do_c) {
+                double c0 = 0.0, c1 = 0.0;
 #pragma unroll
-                for (int t = 0; t < KB; ++t) Cs[so + (int64_t)col * k + t] = c[t];
+                for (int e = 0; e < 8; ++e) {
+                    const double xv = xa[8 * e + lrow][t];
+                    c0 = fma(v[2 * e], xv, c0);
+                    c1 = fma(v[2 * e + 1], xv, c1);
+                }
+                c0 += __shfl_xor(c0, 32);  // the wave's other row group
+                c1 += __shfl_xor(c1, 32);
+                if (lane < 32) {
+                    red[wave][2 * cp][t] = c0;
+                    red[wave][2 * cp + 1][t] = c1;
+                }
+            }
         }
-        __syncthreads();  // xb, xa and ts are free for the next tile
+        __syncthreads();  // column partials written; x may be restaged
+        if (do_c && tid < kT * KB) {
+            const int col = tid / KB, t = tid % KB;
+            const double c = (red[0][col][t] + red[1][col][t]) + (red[2][col][t] + red[3][col][t]);
+            if (col < cmax) Cs[so + (int64_t)col * k + t] = c;
+        }
         if (next >= ntasks) break;
         task = next;
         tk = tkn;
         so = son;
         xr = xrn;
-#pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = vn[e];
     }
 #undef RDD_PS_FETCH
@@ -997,8 +1010,9 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
                 default: RDD_TR(1); break;
             }
         } else if (kb <= 2) {
-            // persistent over about two workgroups per compute unit
-            const unsigned pg = std::min<unsigned>(tgrid, 512u);
+            // persistent over three workgroups per compute unit (its register
+            // budget admits three waves per SIMD)
+            const unsigned pg = std::min<unsigned>(tgrid, 768u);
             hipEvent_t ea = one_launch ? kt_.a : nullptr, eb = one_launch ? kt_.b : nullptr;
             if (kb == 2)
                 hipExtLaunchKernelGGL((k_tile_apply_ps<2>), dim3(pg), dim3(256), 0, h.stream, ea, eb, 0,
