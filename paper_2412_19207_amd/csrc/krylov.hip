@@ -572,14 +572,16 @@ __global__ void __launch_bounds__(256) k_gather_dot(int64_t P, int k, int identi
                 const int t = (int)(idx % k);
                 zv = 0.0;
                 const int64_t e1 = gat_off[g + 1];
-                for (int64_t e0 = gat_off[g]; e0 < e1; e0 += 4) {  // 4 entries per round
-                    int64_t gi[4];
-                    double wv[4];
-                    _Pragma("unroll") for (int v = 0; v < 4; ++v) {
+                // 12 entries per round (a column of a 2D full stencil has up to 9),
+                // so that their loads are in flight together
+                for (int64_t e0 = gat_off[g]; e0 < e1; e0 += 12) {
+                    int64_t gi[12];
+                    double wv[12];
+                    _Pragma("unroll") for (int v = 0; v < 12; ++v) {
                         gi[v] = (e0 + v < e1) ? gat[e0 + v] : -1;
                         wv[v] = (e0 + v < e1) ? gat_w[e0 + v] : 0.0;
                     }
-                    _Pragma("unroll") for (int v = 0; v < 4; ++v) if (gi[v] >= 0) zv += wv[v] * u[gi[v] * k + t];
+                    _Pragma("unroll") for (int v = 0; v < 12; ++v) if (gi[v] >= 0) zv += wv[v] * u[gi[v] * k + t];
                 }
             }
             z[idx] = zv;
