@@ -35,6 +35,20 @@ __device__ inline void sum_partials_kb(const double* part, int nparts, int k, in
             if (b + u * per < nparts) acc[u] += part[(int64_t)(b + u * per) * k + k0 + t];
     }
     const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    if (kb <= 64 && (kb & (kb - 1)) == 0) {
+        // the lanes of a wave that share t differ in the bits from kb up: a
+        // butterfly over those, then the four waves through LDS
+        double w = a;
+        for (int off = 32; off >= kb; off >>= 1) w += __shfl_xor(w, off);
+        const int lane = threadIdx.x & 63;
+        if (lane < kb) sh[(threadIdx.x >> 6) * kb + lane] = w;
+        __syncthreads();
+        if (threadIdx.x < kb)
+            res[threadIdx.x] = (sh[threadIdx.x] + sh[kb + threadIdx.x]) +
+                               (sh[2 * kb + threadIdx.x] + sh[3 * kb + threadIdx.x]);
+        __syncthreads();
+        return;
+    }
     sh[threadIdx.x] = (ro < per) ? a : 0.0;
     __syncthreads();
     for (int st = 1; st < per; st <<= 1) {

@@ -486,6 +486,20 @@ __device__ void sum_partials(const double* part, int nparts, int k, double* res,
             if (b + u * per < nparts) acc[u] += part[(int64_t)(b + u * per) * k + t];
     }
     const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    if (k <= 64 && (k & (k - 1)) == 0) {
+        // the lanes of a wave that share t differ in the bits from k up: a
+        // butterfly over those, then the four waves through LDS
+        double w = a;
+        for (int off = 32; off >= k; off >>= 1) w += __shfl_xor(w, off);
+        const int lane = threadIdx.x & 63;
+        if (lane < k) sh[(threadIdx.x >> 6) * k + lane] = w;
+        __syncthreads();
+        if (threadIdx.x < k)
+            res[threadIdx.x] = (sh[threadIdx.x] + sh[k + threadIdx.x]) +
+                               (sh[2 * k + threadIdx.x] + sh[3 * k + threadIdx.x]);
+        __syncthreads();
+        return;
+    }
     sh[threadIdx.x] = (ro < per) ? a : 0.0;
     __syncthreads();
     for (int st = 1; st < per; st <<= 1) {
