@@ -428,17 +428,17 @@ __device__ inline int64_t rhs_stride(int k) { return ((int64_t)gridDim.x * 256 /
 // stride is a multiple of k, so thread x of block b always handles RHS
 // t = (b * 256 + x) % k; threads are grouped by that t.
 __device__ void block_partial_by_rhs(double val, int k, double* sh, double* out) {
-    sh[threadIdx.x] = val;
-    __syncthreads();
-    if (k == 1) {
-        for (int st = 128; st > 0; st >>= 1) {
-            if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+    if (k == 1) {  // a butterfly over each wave, then the four waves
+        double w = val;
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
+        __syncthreads();
+        if (threadIdx.x == 0) out[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
         __syncthreads();
         return;
     }
+    sh[threadIdx.x] = val;
+    __syncthreads();
     // general k: thread x with e = x belongs to t(e) = (base + e) % k; sum the
     // entries of each t along e = e0, e0 + k, ... with a pairwise tree
     const int base = (int)(((int64_t)blockIdx.x * 256) % k);
