@@ -39,6 +39,20 @@ __global__ void k_HTy_reduce(int64_t P, int k, const int32_t* __restrict__ col_s
 }
 
 // ------------------------------------------------------------------ reductions
+// Sum over the 256 / k threads x = ro k + t that share t (k a power of two up to
+// 64): a butterfly over the lanes of each wave, then the four waves through
+// LDS (sh: 4 k doubles).  The result is returned to threads t < k.
+__device__ inline double wave_block_sum(double v, int k, double* sh) {
+    for (int off = 32; off >= k; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63;
+    if (lane < k) sh[(threadIdx.x >> 6) * k + lane] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x < k) r = (sh[threadIdx.x] + sh[k + threadIdx.x]) + (sh[2 * k + threadIdx.x] + sh[3 * k + threadIdx.x]);
+    return r;
+}
+__device__ inline bool pow2_upto64(int k) { return k <= 64 && (k & (k - 1)) == 0; }
+
 // partial[b * k + t] = sum over this block's rows of a[row, t] * b[row, t]
 __global__ void __launch_bounds__(256) k_dot_part(int64_t rows, int k, const double* __restrict__ a,
                                                   const double* __restrict__ b,
@@ -50,6 +64,11 @@ __global__ void __launch_bounds__(256) k_dot_part(int64_t rows, int k, const dou
     if (ro < per) {
         for (int64_t r = (int64_t)blockIdx.x * per + ro; r < rows; r += (int64_t)gridDim.x * per)
             acc = fma(a[r * k + t], b[r * k + t], acc);
+    }
+    if (pow2_upto64(k)) {
+        const double tot = wave_block_sum(acc, k, s);
+        if (threadIdx.x < k) partial[blockIdx.x * k + threadIdx.x] = tot;
+        return;
     }
     s[threadIdx.x] = (ro < per) ? acc : 0.0;
     __syncthreads();
@@ -69,6 +88,11 @@ __global__ void __launch_bounds__(256) k_dot_fin(int k, int nb, const double* __
     double acc = 0.0;
     if (ro < per)
         for (int b = ro; b < nb; b += per) acc += partial[b * k + t];
+    if (pow2_upto64(k)) {
+        const double tot = wave_block_sum(acc, k, s);
+        if (threadIdx.x < k) out[threadIdx.x] = tot;
+        return;
+    }
     s[threadIdx.x] = (ro < per) ? acc : 0.0;
     __syncthreads();
     if (threadIdx.x < k) {
@@ -1250,6 +1274,15 @@ __global__ void __launch_bounds__(256) k_dot2_part(int64_t rows, int k, const do
             acc1 = fma(a[r * k + t], b[r * k + t], acc1);
             acc2 = fma(c[r * k + t], d[r * k + t], acc2);
         }
+    }
+    if (pow2_upto64(k)) {
+        const double t1 = wave_block_sum(acc1, k, s1);
+        const double t2 = wave_block_sum(acc2, k, s2);
+        if (threadIdx.x < k) {
+            partial[blockIdx.x * k + threadIdx.x] = t1;
+            partial[((int64_t)gridDim.x + blockIdx.x) * k + threadIdx.x] = t2;
+        }
+        return;
     }
     s1[threadIdx.x] = (ro < per) ? acc1 : 0.0;
     s2[threadIdx.x] = (ro < per) ? acc2 : 0.0;
