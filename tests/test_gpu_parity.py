@@ -489,3 +489,24 @@ def test_bitwise_repeatable(case_small2d):
     W1, _ = s.solve(F, tol=1e-12)
     W2, _ = s.solve(F, tol=1e-12)
     assert torch.equal(W1, W2)
+
+
+@pytest.mark.parametrize("method", ["cg", "bicg", "gmres"])
+@pytest.mark.parametrize("k", [4, 8, 64])
+def test_power_of_two_rhs_reductions(method, k):
+    """Right-hand-side counts whose dot products and partial sums take the
+    wave-butterfly reductions (k a power of two up to 64): solutions against
+    the QR solution column by column, FP64."""
+    _need_gpu()
+    prob = wl.small2d(k=k)
+    ref = osolve.reference(prob, "rel_eig", 1e-10)
+    sysm = ref["sys"]
+    s = binding.Solver(prob, device=DEV, precond="as")
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-12, method=method, maxiter=5000)
+    assert info["status"] == 0
+    assert info["max_rel_residual"] <= 1e-12
+    Wn = W.cpu().numpy()
+    for t in range(k):
+        e = rel(Wn[:, t], ref["W"][:, t])
+        assert e <= 1e-8, (t, e)
