@@ -670,26 +670,26 @@ __global__ void k_slot_reduce(int64_t nent, int k, int t0, int kt, int use_r, in
     const int tc = (int)(c / kT), o = (int)(c % kT);
     const int nt = (int)((qv[i] + kT - 1) / kT);
     const int64_t base = s_off[i] * k + t + (int64_t)o * k;
-    // 4 slots per round (their loads in flight together), fixed order
+    // 8 slots per round (their loads in flight together), fixed order
     double s = 0.0;
     if (use_r) {
         const int64_t row0 = (int64_t)tc * (tc + 1) / 2;
-        for (int b0 = 0; b0 <= tc; b0 += 4) {
-            double v[4];
+        for (int b0 = 0; b0 <= tc; b0 += 8) {
+            double v[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = (b0 + u <= tc) ? Rs[base + (row0 + b0 + u) * kT * k] : 0.0;
-            s += (v[0] + v[1]) + (v[2] + v[3]);
+            for (int u = 0; u < 8; ++u) v[u] = (b0 + u <= tc) ? Rs[base + (row0 + b0 + u) * kT * k] : 0.0;
+            s += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
         }
     }
     if (use_c)
-        for (int a0 = tc + c_skip; a0 < nt; a0 += 4) {
-            double v[4];
+        for (int a0 = tc + c_skip; a0 < nt; a0 += 8) {
+            double v[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const int a = a0 + u;
                 v[u] = (a < nt) ? Cs[base + ((int64_t)a * (a + 1) / 2 + tc) * kT * k] : 0.0;
             }
-            s += (v[0] + v[1]) + (v[2] + v[3]);
+            s += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
         }
     z[e * k + t] = s;
 }
