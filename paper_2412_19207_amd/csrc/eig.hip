@@ -63,7 +63,13 @@ __device__ double block_sum(double v, double* red) {
 
 // Steps k = k0 .. k0 + kNB - 1 of the reduction of every matrix.  With V the
 // panel's reflectors (rows of A) and W its update vectors (rows of Wb), the
-// current matrix is A_start - V W^T - W V^T on rows/columns >= k.
+// current matrix is A_start - V W^T - W V^T on rows/columns >= k.  With kInLds
+// (every m <= kPanelCols) the panel's V and W rows are also kept in LDS from
+// column k0 on, and the steps read them there; the trailing block of A_start
+// is read from global memory either way.
+constexpr int kPanelCols = 480;  // widest matrix whose panel rows fit in LDS
+
+template <bool kInLds>
 __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ mvec,
                                                    const int64_t* __restrict__ g_off,
                                                    double* __restrict__ Gall,
@@ -75,6 +81,8 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
     __shared__ double part[kPT];
     __shared__ double hv[kNB], hw[kNB], sv[kNB], sw[kNB];
     __shared__ double red[kPT / 64];
+    __shared__ double Vl[kInLds ? kNB * kPanelCols : 1];  // Vl[q][c - k0] = A[k0 + q][c]
+    __shared__ double Wl[kInLds ? kNB * kPanelCols : 1];  // Wl[q][c - k0] = Wb[q][c]
     const int j = blockIdx.x;
     const int m = mvec[j];
     if (k0 >= m) return;
@@ -86,14 +94,28 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
     double* ee = tri + mm;
     double* taus = tri + 2 * mm;
     const int tid = threadIdx.x;
+    // row q of the panel's V and W at column c >= k0
+    auto Vr = [&](int q, int c) -> double {
+        if constexpr (kInLds) return Vl[q * kPanelCols + (c - k0)];
+        else return A[(int64_t)(k0 + q) * mm + c];
+    };
+    auto Wr = [&](int q, int c) -> double {
+        if constexpr (kInLds) return Wl[q * kPanelCols + (c - k0)];
+        else return Wb[(int64_t)q * mm + c];
+    };
     const int kend = (k0 + kNB < m) ? k0 + kNB : m;
+    // LDS mode (m - k <= kPT: one column per thread): x[tid] holds A_start[k][k + tid]
+    // on entry to step k; later rows are fetched one step ahead, beside the
+    // loads of the panel product
+    if constexpr (kInLds)
+        if (k0 + tid < m) x[tid] = A[(int64_t)k0 * mm + k0 + tid];
     for (int k = k0; k < kend; ++k) {
         const int i = k - k0;
         const int n1 = m - k - 1;
         // the panel's earlier reflectors at row k: V[k][q] and W[k][q]
         if (tid < i) {
-            sv[tid] = A[(int64_t)(k0 + tid) * mm + k];
-            sw[tid] = Wb[(int64_t)tid * mm + k];
+            sv[tid] = Vr(tid, k);
+            sw[tid] = Wr(tid, k);
         }
         __syncthreads();
         // row k of the current matrix, entries c >= k
@@ -106,17 +128,19 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
                 double wv[8], vv[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    wv[u] = Wb[(int64_t)(q + u) * mm + c];
-                    vv[u] = A[(int64_t)(k0 + q + u) * mm + c];
+                    wv[u] = Wr(q + u, c);
+                    vv[u] = Vr(q + u, c);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) s8[u] -= sv[q + u] * wv[u] + sw[q + u] * vv[u];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u < i)
-                    s8[u] -= sv[q + u] * Wb[(int64_t)(q + u) * mm + c] + sw[q + u] * A[(int64_t)(k0 + q + u) * mm + c];
-            x[c - k] = A[(int64_t)k * mm + c] + (((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7])));
+                if (q + u < i) s8[u] -= sv[q + u] * Wr(q + u, c) + sw[q + u] * Vr(q + u, c);
+            double a_kc;
+            if constexpr (kInLds) a_kc = x[c - k];  // fetched by this thread
+            else a_kc = A[(int64_t)k * mm + c];
+            x[c - k] = a_kc + (((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7])));
         }
         __syncthreads();
         if (n1 < 2) {  // no reflector: the last 2 x 2 block is already tridiagonal
@@ -125,9 +149,18 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
                 ee[k] = (n1 == 1) ? x[1] : 0.0;
                 taus[k] = 0.0;
             }
-            for (int c = tid; c < n1; c += kPT) A[(int64_t)k * mm + k + 1 + c] = 0.0;
-            for (int c = tid; c < m; c += kPT) Wb[(int64_t)i * mm + c] = 0.0;
+            for (int c = tid; c < n1; c += kPT) {
+                A[(int64_t)k * mm + k + 1 + c] = 0.0;
+                if constexpr (kInLds) Vl[i * kPanelCols + (k + 1 + c - k0)] = 0.0;
+            }
+            for (int c = tid; c < m; c += kPT) {
+                Wb[(int64_t)i * mm + c] = 0.0;
+                if constexpr (kInLds)
+                    if (c >= k0) Wl[i * kPanelCols + (c - k0)] = 0.0;
+            }
             __syncthreads();
+            if constexpr (kInLds)
+                if (k + 1 < kend && k + 1 + tid < m) x[tid] = A[(int64_t)(k + 1) * mm + k + 1 + tid];
             continue;
         }
         double pp = 0.0;
@@ -140,6 +173,7 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
             const double vc = (nrm2 > 0.0) ? ((c == 0) ? x1 - alpha : x[1 + c]) : 0.0;
             v[c] = vc;
             A[(int64_t)k * mm + k + 1 + c] = vc;
+            if constexpr (kInLds) Vl[i * kPanelCols + (k + 1 + c - k0)] = vc;
         }
         if (tid == 0) {
             dd[k] = x[0];
@@ -154,6 +188,9 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
         const int G = kPT / C;
         {
             const int g = tid / C, c = tid % C;
+            double a_next = 0.0;
+            if constexpr (kInLds)
+                if (k + 1 < kend && k + 1 + tid < m) a_next = A[(int64_t)(k + 1) * mm + k + 1 + tid];
             double acc8[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc8[u] = 0.0;
@@ -172,6 +209,9 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
             }
             if (g < G)
                 part[g * C + c] = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+            // x is free until step k + 1 reads its own entry
+            if constexpr (kInLds)
+                if (k + 1 < kend && k + 1 + tid < m) x[tid] = a_next;
         }
         // hv = W^T v, hw = V^T v over rows k+1 .. m-1: 16 lanes per dot product
         {
@@ -179,7 +219,11 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
             double sacc = 0.0;
             if (dq < 2 * i) {
                 const int q = dq >> 1;
-                const double* src = ((dq & 1) ? A + (int64_t)(k0 + q) * mm : Wb + (int64_t)q * mm) + k + 1;
+                const double* src;
+                if constexpr (kInLds)
+                    src = ((dq & 1) ? Vl : Wl) + q * kPanelCols + (k + 1 - k0);
+                else
+                    src = ((dq & 1) ? A + (int64_t)(k0 + q) * mm : Wb + (int64_t)q * mm) + k + 1;
                 double s4[4] = {0.0, 0.0, 0.0, 0.0};
                 int c = g;
                 for (; c + 48 < n1; c += 64) {
@@ -216,16 +260,15 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
                 double av[8], bv[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    av[u] = A[(int64_t)(k0 + q + u) * mm + k + 1 + c];
-                    bv[u] = Wb[(int64_t)(q + u) * mm + k + 1 + c];
+                    av[u] = Vr(q + u, k + 1 + c);
+                    bv[u] = Wr(q + u, k + 1 + c);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) s8[u] -= av[u] * hv[q + u] + bv[u] * hw[q + u];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u < i)
-                    s8[u] -= A[(int64_t)(k0 + q + u) * mm + k + 1 + c] * hv[q + u] + Wb[(int64_t)(q + u) * mm + k + 1 + c] * hw[q + u];
+                if (q + u < i) s8[u] -= Vr(q + u, k + 1 + c) * hv[q + u] + Wr(q + u, k + 1 + c) * hw[q + u];
             const double wc = tau * (s0 + (((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]))));
             w[c] = wc;
             pv += wc * v[c];
@@ -234,7 +277,10 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
         double* Wi = Wb + (int64_t)i * mm;
         for (int c = tid; c < m; c += kPT) {
             const int cc = c - (k + 1);
-            Wi[c] = (cc >= 0) ? w[cc] - K * v[cc] : 0.0;
+            const double wc = (cc >= 0) ? w[cc] - K * v[cc] : 0.0;
+            Wi[c] = wc;
+            if constexpr (kInLds)
+                if (c >= k0) Wl[i * kPanelCols + (c - k0)] = wc;
         }
         __syncthreads();
     }
@@ -919,8 +965,12 @@ int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const i
         RDD_TRY(upload(h, d_tasks, tasks.data(), sizeof(int4) * tasks.size()));
     int pi = 0;
     for (int k0 = 0; k0 < mmax; k0 += kNB, ++pi) {
-        hipLaunchKernelGGL(k_tri_panel, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S,
-                           d_s_off, k0);
+        if (mmax <= kPanelCols)
+            hipLaunchKernelGGL(k_tri_panel<true>, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S,
+                               d_s_off, k0);
+        else
+            hipLaunchKernelGGL(k_tri_panel<false>, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S,
+                               d_s_off, k0);
         const int64_t cnt = off[pi + 1] - off[pi];
         if (cnt > 0)
             hipLaunchKernelGGL(k_tri_update, dim3((unsigned)cnt), dim3(256), 0, h.stream,
