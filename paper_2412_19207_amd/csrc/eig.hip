@@ -55,6 +55,18 @@ __device__ double block_sum(double v, double* red) {
     return s;
 }
 
+// block_sum without its leading barrier, for a caller whose buffer red has
+// not been read since its last barrier
+__device__ double block_sum_fresh(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kPT / 64; ++w) s += red[w];
+    return s;
+}
+
 // ---------------------------------------------------------------- 1. panel
 // The panel product p = A v runs on G row groups of C column lanes, C = the
 // trailing size rounded up to 64 (G C <= kPT), so that small trailing
@@ -80,7 +92,7 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
     __shared__ double w[kMaxWidth];
     __shared__ double part[kPT];
     __shared__ double hv[kNB], hw[kNB], sv[kNB], sw[kNB];
-    __shared__ double red[kPT / 64];
+    __shared__ double red_n[kPT / 64], red_k[kPT / 64];  // one buffer per block sum of a step
     __shared__ double Vl[kInLds ? kNB * kPanelCols : 1];  // Vl[q][c - k0] = A[k0 + q][c]
     __shared__ double Wl[kInLds ? kNB * kPanelCols : 1];  // Wl[q][c - k0] = Wb[q][c]
     const int j = blockIdx.x;
@@ -112,12 +124,23 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
     for (int k = k0; k < kend; ++k) {
         const int i = k - k0;
         const int n1 = m - k - 1;
-        // the panel's earlier reflectors at row k: V[k][q] and W[k][q]
-        if (tid < i) {
-            sv[tid] = Vr(tid, k);
-            sw[tid] = Wr(tid, k);
+        // the panel's earlier reflectors at row k: V[k][q] and W[k][q] (staged
+        // from global memory; read in place from LDS)
+        if constexpr (!kInLds) {
+            if (tid < i) {
+                sv[tid] = Vr(tid, k);
+                sw[tid] = Wr(tid, k);
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        auto Vk = [&](int q) -> double {
+            if constexpr (kInLds) return Vl[q * kPanelCols + (k - k0)];
+            else return sv[q];
+        };
+        auto Wk = [&](int q) -> double {
+            if constexpr (kInLds) return Wl[q * kPanelCols + (k - k0)];
+            else return sw[q];
+        };
         // row k of the current matrix, entries c >= k
         for (int c = k + tid; c < m; c += kPT) {
             double s8[8];
@@ -132,11 +155,11 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
                     vv[u] = Vr(q + u, c);
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) s8[u] -= sv[q + u] * wv[u] + sw[q + u] * vv[u];
+                for (int u = 0; u < 8; ++u) s8[u] -= Vk(q + u) * wv[u] + Wk(q + u) * vv[u];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q + u < i) s8[u] -= sv[q + u] * Wr(q + u, c) + sw[q + u] * Vr(q + u, c);
+                if (q + u < i) s8[u] -= Vk(q + u) * Wr(q + u, c) + Wk(q + u) * Vr(q + u, c);
             double a_kc;
             if constexpr (kInLds) a_kc = x[c - k];  // fetched by this thread
             else a_kc = A[(int64_t)k * mm + c];
@@ -165,7 +188,7 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
         }
         double pp = 0.0;
         for (int c = tid; c < n1; c += kPT) pp += x[1 + c] * x[1 + c];
-        const double nrm2 = block_sum(pp, red);
+        const double nrm2 = block_sum_fresh(pp, red_n);
         const double x1 = x[1];
         const double alpha = (x1 >= 0.0) ? -sqrt(nrm2) : sqrt(nrm2);
         const double tau = (nrm2 > 0.0) ? 1.0 / (nrm2 - x1 * alpha) : 0.0;  // 2 / v^T v
@@ -273,7 +296,7 @@ __global__ void __launch_bounds__(kPT) k_tri_panel(const int32_t* __restrict__ m
             w[c] = wc;
             pv += wc * v[c];
         }
-        const double K = 0.5 * tau * block_sum(pv, red);
+        const double K = 0.5 * tau * block_sum_fresh(pv, red_k);
         double* Wi = Wb + (int64_t)i * mm;
         for (int c = tid; c < m; c += kPT) {
             const int cc = c - (k + 1);
