@@ -677,12 +677,14 @@ __global__ void __launch_bounds__(256) k_pcount(const int32_t* __restrict__ mvec
 // eigenvectors of T for the p largest eigenvalues by inverse iteration, one
 // thread per vector (vector t <-> lam[m-1-t]); entry i of vector t is kept at
 // Zt[i m + t] and its LU factors at LU[(f m + i) m + t]
-constexpr int kIvLds = 16384;  // doubles of LDS for the factors and iterates of inverse iteration
+constexpr int kIvLds = 17152;  // doubles of LDS for the factors and iterates of inverse iteration
 
-// vectors of one inverse-iteration workgroup for width m: six LDS arrays of m
-// entries per vector (the factors of T - lam I, the swap flags, the iterate)
+// vectors of one inverse-iteration workgroup for width m: per vector five LDS
+// arrays of m doubles (the factors of T - lam I and the iterate) and m bytes of
+// swap flags, 41 m bytes.  The LDS sets how many workgroups run at once, so the
+// workgroup takes as many vectors as fit.
 __host__ __device__ inline int inviter_vectors(int m) {
-    const int v = kIvLds / (6 * (m > 0 ? m : 1));
+    const int v = (int)((8LL * kIvLds) / (41LL * (m > 0 ? m : 1)));
     return v < 1 ? 1 : (v > 64 ? 64 : v);
 }
 
@@ -731,8 +733,8 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
     double* fb = fs + mv + v;      // first superdiagonal
     double* fc = fs + 2 * mv + v;  // second superdiagonal (fill-in)
     double* fm = fs + 3 * mv + v;  // multipliers
-    double* fp = fs + 4 * mv + v;  // 1.0 where rows i, i+1 were swapped
-    double* z = fs + 5 * mv + v;   // the iterate
+    double* z = fs + 4 * mv + v;   // the iterate
+    unsigned char* fp = reinterpret_cast<unsigned char*>(fs + 5 * mv) + v;  // 1 where rows i, i+1 were swapped
     double ai = dd[0] - lmb, bi = ee[0];
     for (int i = 0; i + 1 < m; ++i) {
         const double sub = ee[i];
@@ -747,7 +749,7 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
         fb[i * V] = swap ? an : bi;
         fc[i * V] = swap ? bn : 0.0;
         fm[i * V] = mu;
-        fp[i * V] = swap ? 1.0 : 0.0;
+        fp[i * V] = swap ? 1 : 0;
         const double ai_n = swap ? bi - mu * an : an - mu * bi;
         bi = swap ? -mu * bn : bn;
         ai = ai_n;
@@ -772,7 +774,7 @@ __global__ void __launch_bounds__(64) k_inviter(const int32_t* __restrict__ mvec
         for (int i = 0; i + 1 < m; ++i) {
             const double zn = z[(i + 1) * V] * sc;
             const double mu = fm[i * V];
-            const bool swap = fp[i * V] != 0.0;
+            const bool swap = fp[i * V] != 0;
             z[i * V] = swap ? zn : zc;
             zc = swap ? zc - mu * zn : zn - mu * zc;
         }
