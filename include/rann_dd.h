@@ -32,6 +32,7 @@
 #ifndef RANN_DD_H
 #define RANN_DD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -53,7 +54,10 @@ extern "C" {
 /* precision of the preconditioner path (the Krylov vectors, dot products,
  * H and the residual are FP64 in both) */
 #define RANN_FP64          0
-#define RANN_MIXED         1    /* FP32 Gram blocks, factors and local solves */
+#define RANN_MIXED         1    /* the local inverses are stored as FP32 triangular
+                                   factors Y_i (A_i^{-1} = Y_i^T Y_i) and applied in
+                                   FP32 on the matrix cores for k >= 16 right-hand
+                                   sides (FP64 accumulation below that) */
 
 /* Schwarz blocks: which subdomains' columns block i selects (Sec. 3, R_i) */
 #define RANN_STENCIL_SELF  0    /* subdomain i only (block Jacobi) */
@@ -62,7 +66,9 @@ extern "C" {
 
 #define RANN_PRECOND_NONE  0
 #define RANN_PRECOND_AS    1    /* sum_i R_i^T A_i^{-1} R_i */
-#define RANN_PRECOND_RAS   2    /* sum_i R_i^T D_i A_i^{-1} R_i, D_i = ownership */
+#define RANN_PRECOND_RAS   2    /* sum_i R_i^T D_i A_i^{-1} R_i, D_i Boolean: the columns
+                                   of each subdomain belong to the first block (in
+                                   increasing block order) whose stencil holds it */
 #define RANN_PRECOND_SAS   3    /* D_i = 1 / multiplicity (Sec. 5, Example 1) */
 
 #define RANN_PCA_REL_EIG   0    /* keep eigenvalues of Psi^T Psi above tol * largest */
@@ -73,9 +79,8 @@ extern "C" {
 #define RANN_METHOD_GMRES  1        /* left-preconditioned (paper Sec. 5) */
 #define RANN_METHOD_GMRES_RIGHT 2   /* right-preconditioned: minimises the true residual */
 #define RANN_METHOD_CGS    3        /* conjugate gradients squared (Sec. 5, Table 1b) */
-#define RANN_METHOD_BICG   4        /* biconjugate gradients (Sec. 5, Table 1b); needs the
-                                       transposed preconditioner: NONE, AS or SAS
-                                       (RANN_EINVAL with RAS) */
+#define RANN_METHOD_BICG   4        /* biconjugate gradients (Sec. 5, Table 1b); applies the
+                                       transposed preconditioner M^{-T} beside M^{-1} */
 
 #define RANN_LIN_NEWTON    0        /* Newton (Gauss-Newton) linearisation of g */
 #define RANN_LIN_PICARD    1        /* Picard: g(u) = gamma_0 + u q(u), q frozen */
@@ -231,7 +236,7 @@ RANN_API int rann_dd_apply_precond(rann_dd_handle* h, const double* r, int32_t k
  * recurrence applies (Sec. 5, Table 1b): the weights D_i move from the local
  * results onto the restricted input, sum_i R_i^T A_i^{-1} D_i R_i r.  r, z
  * device (P, k), k >= 1, not aliased.  Equal to rann_dd_apply_precond for AS and
- * no preconditioner.  Synchronous.  RANN_EINVAL for RAS (not provided). */
+ * no preconditioner.  Synchronous. */
 RANN_API int rann_dd_apply_precond_T(rann_dd_handle* h, const double* r, int32_t k, double* z);
 
 /* Sizes; valid after rann_dd_assemble (P, nnz after rann_dd_pca). */

@@ -346,9 +346,9 @@ class Solver:
             st.rhs_iterations = its.ctypes.data_as(c_ip)
         rc = rann_dd_solve(self.handle, F.data_ptr(), k, W0.data_ptr() if W0 is not None else 0,
                            self._opts(tol, maxiter, method, restart, check_every), W.data_ptr(), st)
-        info = None
+        info = dict(status=rc)
         if st is not None:
-            info = dict(status=rc, iterations=st.iterations, converged=st.converged,
+            info.update(iterations=st.iterations, converged=st.converged,
                         max_rel_residual=st.max_rel_residual, rel_residual=rel.copy(),
                         rhs_iterations=its.copy(), shifts=st.shifts)
         return W, info
@@ -449,13 +449,17 @@ class RannDDSolve:
             @staticmethod
             def forward(ctx, f, g):
                 F = torch.cat([f, g], dim=0)
-                W, _ = solver.solve(F, tol=tol, maxiter=maxiter, method=method, stats=False)
+                W, info = solver.solve(F, tol=tol, maxiter=maxiter, method=method, stats=False)
+                if info["status"] != RANN_OK:
+                    raise RannError(info["status"], "forward solve did not reach the tolerance")
                 return solver.eval(Xq, W, Lq)
 
             @staticmethod
             def backward(ctx, dU):
                 dW = solver.eval_T(Xq, dU.contiguous(), Lq)
-                dF, _ = solver.solve_backward(dW, tol=tol, maxiter=maxiter, method=method)
+                dF, info = solver.solve_backward(dW, tol=tol, maxiter=maxiter, method=method)
+                if info["status"] != RANN_OK:
+                    raise RannError(info["status"], "adjoint solve did not reach the tolerance")
                 n_int = solver.info.N_int
                 return dF[:n_int], dF[n_int:]
 

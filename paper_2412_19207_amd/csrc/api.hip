@@ -811,7 +811,7 @@ int rann_dd_apply_precond_T(rann_dd_handle* hh, const double* r, int32_t k, doub
     double* ub = nullptr;
     double* tmp = nullptr;
     RDD_TRY(rdd::dev_alloc(h, &ub, (size_t)std::max<int64_t>(2 * h.ub_total + 2 * h.slot_total, 1) * k));
-    int rc = rdd::dev_alloc(h, &tmp, (size_t)h.P * k);
+    int rc = rdd::dev_alloc(h, &tmp, (size_t)(h.P + 1) * k);
     if (rc == RANN_OK) rc = rdd::launch_precond_T(h, r, k, z, ub, tmp);
     if (rc == RANN_OK && hipStreamSynchronize(h.stream) != hipSuccess) rc = RANN_EDEVICE;
     if (tmp) rdd::dev_free(h, tmp);

@@ -44,6 +44,23 @@ struct PointSet {
     int max_cover = 0;
 };
 
+// What one application of the local solves and their sum computes: the tile
+// tasks, the input column of each block entry, and the gather lists that add
+// the used block entries into each global column.
+struct ApplyPlan {
+    int4* d_tile_tasks = nullptr;  // (block, tile row, tile column) of the local solves
+    int64_t n_tile_tasks = 0;
+    int2* d_row_tasks = nullptr;   // (block, tile row), longest first (triangular factor)
+    int64_t n_row_tasks = 0;
+    int2* d_col_tasks = nullptr;   // (block, tile of the result that is used), longest first
+    int64_t n_col_tasks = 0;
+    int32_t* d_blk_cols = nullptr; // sum q_i: input column of each block entry
+    // gather form of the sum: for each global column, the (block entry) list
+    int64_t* d_gat_off = nullptr;  // P+1
+    int64_t* d_gat = nullptr;      // entries
+    double* d_gat_w = nullptr;     // weights (AS 1, SAS 1/mult, RAS 1 on owned entries only)
+};
+
 struct Handle {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -88,23 +105,14 @@ struct Handle {
     int64_t* d_t_off = nullptr;
     double* d_M64 = nullptr;       // Y_i = L_i^{-1} D_i, packed tiles, FP64
     float* d_M32 = nullptr;        // the same in FP32 (mixed)
-    int4* d_tile_tasks = nullptr;  // (block, tile row, tile column) of the local solves
-    int64_t n_tile_tasks = 0;
-    int2* d_row_tasks = nullptr;   // (block, tile row), longest first (triangular factor)
-    int64_t n_row_tasks = 0;
-    int2* d_col_tasks = nullptr;   // (block, tile of the result that is used), longest first
-    int64_t n_col_tasks = 0;
+    ApplyPlan ap;                  // the preconditioner M^{-1}
+    ApplyPlan apT;                 // RAS only: its transpose M^{-T} (masked input, full local results)
     int64_t slot_total = 0;        // row- or column-sum slots per right-hand side (sum nt(nt+1)/2 * 64)
     int64_t* d_s_off = nullptr;    // J+1 slot offsets
     int32_t* d_ent_blk = nullptr;  // ub_total: block of each block entry
     int64_t* d_f_off = nullptr;
     int64_t* d_q = nullptr;
     int64_t* d_ub_off = nullptr;   // J+1 offsets of per-block local vectors (sum q_i)
-    int32_t* d_blk_cols = nullptr; // sum q_i: global column of each block entry
-    // gather form of the AS sum: for each global column, the (block entry) list
-    int64_t* d_gat_off = nullptr;  // P+1
-    int64_t* d_gat = nullptr;      // entries
-    double* d_gat_w = nullptr;     // weights (AS 1, SAS 1/mult, RAS ownership)
     int32_t shifts = 0;
     int64_t ub_total = 0;          // sum q_i
 
@@ -266,10 +274,10 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part, co
 int launch_Hx(Handle& h, const double* x, int k, double* y, bool scale_bnd);
 int launch_HTy(Handle& h, const double* y, int k, double* x, double* partial);
 int launch_precond(Handle& h, const double* r, int k, double* z, double* ub);
-// z = M^{-T} r (AS, SAS; RANN_EINVAL for RAS); tmp: P k scratch
+// z = M^{-T} r; tmp: (P + 1) k scratch
 int launch_precond_T(Handle& h, const double* r, int k, double* z, double* ub, double* tmp);
 // ub: (2 ub_total + 2 slot_total) k doubles of scratch
-int launch_precond_local(Handle& h, const double* r, int k, double* ub);
+int launch_precond_local(Handle& h, const ApplyPlan& pl, const double* r, int k, double* ub);
 
 int krylov_cg(Handle& h, const double* rhs, int k, const double* W0, const rann_dd_solve_opts& o,
               double* W, rann_dd_stats* st, int* status);

@@ -747,6 +747,24 @@ int exact_normal_op(Handle& h, const double* x, int k, double* y, double* part, 
     return RANN_OK;
 }
 
+// r = H^T (Fs - H W) from the rows of H when the rows' right-hand side Fs is
+// known (its rounding scales with the least-squares residual, not with H W),
+// else r = rhs - H^T (H W) (the adjoint); y: N k scratch, s: P k scratch
+int ls_residual(Handle& h, const double* Fs, const double* rhs, const double* W, int k, double* y,
+                double* part, double* s, double* r) {
+    const int64_t Pk = h.P * k, Nk = h.N * k;
+    RDD_TRY(launch_Hx(h, W, k, y, false));
+    if (Fs) {
+        hipLaunchKernelGGL(k_sub, dim3(grid_for(Nk)), dim3(256), 0, h.stream, Nk, Fs, y, y);
+        RDD_TRY(launch_HTy(h, y, k, r, part));
+    } else {
+        RDD_TRY(launch_HTy(h, y, k, s, part));
+        hipLaunchKernelGGL(k_sub, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, s, r);
+    }
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
 }  // namespace
 
 int scale_boundary(Handle& h, const double* F, int k, double* Fs, double factor) {
@@ -906,9 +924,9 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
                                (int)h.n_slab_tasks, partA, rho_in, act_in, p, s, W, r, partB, flags);
             // z = M^{-1} r and partials of <r, z>
             const int ident = (h.precond == RANN_PRECOND_NONE) ? 1 : 0;
-            if (!ident) RDD_TRY(launch_precond_local(h, r, k, ub));
+            if (!ident) RDD_TRY(launch_precond_local(h, h.ap, r, k, ub));
             hipLaunchKernelGGL(k_gather_dot, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, ident,
-                               h.d_gat_off, h.d_gat, h.d_gat_w, ub, r, z, partC);
+                               h.ap.d_gat_off, h.ap.d_gat, h.ap.d_gat_w, ub, r, z, partC);
             if (q + 1 == every || it + 1 >= o.maxiter)
                 hipLaunchKernelGGL(k_cg_p2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, (int)rgrid, partB,
                                    partC, bn2, tol2v, rho_in, rho_out, act_in, act_out, iters, rres, z, p);
@@ -1106,11 +1124,10 @@ static int gmres_core(Handle& h, const double* rhs, const double* Fs, int k, con
     *status = RANN_OK;
     while (true) {
         // r = M^{-1}(rhs - A W) (left) or rhs - A W (right), A applied through the rows of H
-        RDD_TRY(exact_normal_op(h, W, k, y, part, s));
         if (right) {
-            hipLaunchKernelGGL(k_sub, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, s, w);
+            RDD_TRY(ls_residual(h, Fs, rhs, W, k, y, part, s, w));
         } else {
-            hipLaunchKernelGGL(k_sub, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs, s, t0);
+            RDD_TRY(ls_residual(h, Fs, rhs, W, k, y, part, s, t0));
             RDD_TRY(launch_precond(h, t0, k, w, ub));
         }
         RDD_TRY(dot(h, P, k, w, w, dp, nrm));
@@ -1438,12 +1455,8 @@ __global__ void k_bicg_dir(int64_t n, int k, const double* __restrict__ rho, con
 int krylov_lanczos(Handle& h, const double* rhs, const double* Fs, int k, const double* W0,
                    const rann_dd_solve_opts& o, double* W, rann_dd_stats* st, int* status) {
     const bool cgs = (o.method == RANN_METHOD_CGS);
-    if (!cgs && h.precond == RANN_PRECOND_RAS) {
-        set_error("BiCG needs the transposed preconditioner, which is not provided for RAS");
-        return RANN_EINVAL;
-    }
     const size_t P = (size_t)h.P, N = (size_t)h.N;
-    const size_t need = P * k * 11 + N * k + (size_t)h.part_total * k +
+    const size_t need = P * k * 11 + k + N * k + (size_t)h.part_total * k +
                         (size_t)(2 * h.ub_total + 2 * h.slot_total) * k + 2 * (size_t)kDotBlocks * k +
                         40 * (size_t)k + 2048;
     RDD_TRY(ensure_ws(h, need * sizeof(double)));
@@ -1456,7 +1469,7 @@ int krylov_lanczos(Handle& h, const double* rhs, const double* Fs, int k, const 
     double* v4 = sc.take(P * k);  // CGS: ph     BiCG: pt
     double* v5 = sc.take(P * k);  // CGS: vh     BiCG: q
     double* v6 = sc.take(P * k);  // CGS: w      BiCG: qt
-    double* v7 = sc.take(P * k);  // CGS: uh     BiCG: M^{-T} scratch
+    double* v7 = sc.take((P + 1) * k);  // CGS: uh     BiCG: M^{-T} scratch ((P + 1) k)
     double* v8 = sc.take(P * k);  // CGS: A uh
     double* y = sc.take(N * k);
     double* part = sc.take((size_t)h.part_total * k);
@@ -1506,8 +1519,7 @@ int krylov_lanczos(Handle& h, const double* rhs, const double* Fs, int k, const 
     std::vector<int32_t> goh(k, 1), act(k), brkh(k);
     std::vector<double> rrh(k);
     auto residual = [&]() -> int {
-        RDD_TRY(exact_normal_op(h, W, k, y, part, v8));
-        hipLaunchKernelGGL(k_sub, eg, b256, 0, h.stream, Pk, rhs, v8, r);
+        RDD_TRY(ls_residual(h, Fs, rhs, W, k, y, part, v8, r));
         hipLaunchKernelGGL(k_copy, eg, b256, 0, h.stream, Pk, r, rt);
         hipLaunchKernelGGL(k_dot2_part, dim3(kDotBlocks), b256, 0, h.stream, (int64_t)P, k, r, r, rt, r, dp);
         hipLaunchKernelGGL(k_dot_fin, dim3(1), b256, 0, h.stream, k, kDotBlocks, dp, rr);

@@ -1,7 +1,8 @@
 // Overlapping Schwarz preconditioners for H^T H (paper Sec. 3).
 //
 //   AS : z = sum_i R_i^T A_i^{-1} R_i r
-//   RAS: z = sum_i R_i^T D_i A_i^{-1} R_i r,  D_i = the columns subdomain i owns
+//   RAS: z = sum_i R_i^T D_i A_i^{-1} R_i r,  D_i = the columns block i owns (the
+//        columns of each subdomain belong to the first block holding it)
 //   SAS: D_i = 1 / (number of blocks containing the column)
 //
 // Block i selects the columns of every subdomain in its stencil.  The local
@@ -714,13 +715,20 @@ __global__ void k_gather_sum(int64_t P, int k, const int64_t* __restrict__ gat_o
 }
 
 // out[g] = r[g] / (number of blocks containing column g), the count being the
-// length of g's gather list (every entry is listed unless the blocks are RAS)
+// length of g's gather list (every entry is listed: AS and SAS plans)
 __global__ void k_div_count(int64_t P, int k, const int64_t* __restrict__ gat_off,
                             const double* __restrict__ r, double* __restrict__ out) {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= P * k) return;
     const int64_t g = idx / k;
     out[idx] = r[idx] / (double)(gat_off[g + 1] - gat_off[g]);
+}
+
+// out = [r; 0]: the n entries of r followed by pad zeros
+__global__ void k_copy_pad(int64_t n, int64_t pad, const double* __restrict__ r, double* __restrict__ out) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] = r[idx];
+    else if (idx < n + pad) out[idx] = 0.0;
 }
 
 }  // namespace
@@ -755,9 +763,123 @@ static std::vector<int> make_stencil(const Handle& h, int i, const std::vector<s
     return out;
 }
 
-struct PrecondPlan {
-    std::vector<int64_t> row_start, row_cnt;  // rows of each block that are applied
-};
+// The columns of subdomain j belong to the first block (increasing index)
+// whose stencil holds j: the Boolean algebraic partition of unity D_i of RAS,
+// sum_i R_i^T D_i R_i = I.
+static std::vector<int> ras_owner(const std::vector<std::vector<int>>& sten) {
+    std::vector<int> owner(sten.size(), -1);
+    for (size_t i = 0; i < sten.size(); ++i)
+        for (int j : sten[i])
+            if (owner[j] < 0) owner[j] = (int)i;
+    return owner;
+}
+
+// One application plan (see ApplyPlan).  Forward: block i gathers the entries
+// of the subdomains use(i, j) selects, with weight w(column); the tile rows
+// computed start at the tile of the first used entry.  Masked (the transposed
+// RAS apply): the entries of subdomains block i does not own read the zero
+// row P of the input, every entry of a block that owns anything is gathered
+// with unit weight, and blocks that own nothing are skipped.
+static int build_plan(Handle& h, const std::vector<int64_t>& ub_off, const std::vector<int>& mult,
+                      const std::vector<int>& owner, bool masked, ApplyPlan& pl) {
+    const int J = h.geo.J;
+    const bool ras = (h.precond == RANN_PRECOND_RAS);
+    std::vector<int32_t> blk_cols((size_t)ub_off[J]);
+    std::vector<int64_t> row_lo(J, 0), row_hi(J, 0);  // block entries [lo, hi) of the result needed
+    std::vector<char> used((size_t)ub_off[J], 0);
+    std::vector<int64_t> ent_col((size_t)ub_off[J]);  // global column of each block entry
+    for (int i = 0; i < J; ++i) {
+        bool owns = false;
+        for (int j : h.sten[i]) owns |= (owner[j] == i);
+        int64_t e = ub_off[i], pos = 0, lo = -1, hi = 0;
+        for (int j : h.sten[i]) {
+            const bool mine = (owner[j] == i);
+            const bool use = masked ? owns : (!ras || mine);
+            for (int c = 0; c < h.p[j]; ++c, ++e, ++pos) {
+                const int64_t gcol = h.col_off[j] + c;
+                blk_cols[e] = (int32_t)((masked && !mine) ? h.P : gcol);
+                ent_col[e] = gcol;
+                used[e] = use ? 1 : 0;
+                if (use) {
+                    if (lo < 0) lo = pos;
+                    hi = pos + 1;
+                }
+            }
+        }
+        row_lo[i] = lo < 0 ? 0 : lo;
+        row_hi[i] = lo < 0 ? 0 : hi;
+    }
+    // gather lists: CSR over global columns, entries in block order
+    std::vector<int64_t> gat_off(h.P + 1, 0);
+    for (int i = 0; i < J; ++i)
+        for (int64_t e = ub_off[i]; e < ub_off[i + 1]; ++e)
+            if (used[e]) gat_off[ent_col[e] + 1]++;
+    for (int64_t g = 0; g < h.P; ++g) gat_off[g + 1] += gat_off[g];
+    std::vector<int64_t> gat((size_t)gat_off[h.P]), fill(gat_off.begin(), gat_off.end() - 1);
+    std::vector<double> gat_w((size_t)gat_off[h.P]);
+    for (int64_t e = 0; e < ub_off[J]; ++e) {
+        if (!used[e]) continue;
+        const int64_t gcol = ent_col[e];
+        const int64_t slot = fill[gcol]++;
+        gat[slot] = e;
+        gat_w[slot] = (!masked && h.precond == RANN_PRECOND_SAS) ? 1.0 / (double)mult[gcol] : 1.0;
+    }
+    RDD_TRY(dev_alloc(h, &pl.d_blk_cols, blk_cols.size()));
+    RDD_TRY(dev_alloc(h, &pl.d_gat_off, gat_off.size()));
+    RDD_TRY(dev_alloc(h, &pl.d_gat, gat.size()));
+    RDD_TRY(dev_alloc(h, &pl.d_gat_w, gat_w.size()));
+    RDD_TRY(upload(h, pl.d_blk_cols, blk_cols.data(), sizeof(int32_t) * blk_cols.size()));
+    RDD_TRY(upload(h, pl.d_gat_off, gat_off.data(), sizeof(int64_t) * gat_off.size()));
+    if (!gat.empty()) {
+        RDD_TRY(upload(h, pl.d_gat, gat.data(), sizeof(int64_t) * gat.size()));
+        RDD_TRY(upload(h, pl.d_gat_w, gat_w.data(), sizeof(double) * gat_w.size()));
+    }
+    // packed tiles, one task per stored tile of the tile rows from the first
+    // needed one on (the symmetric apply's rows c need the row sums of tile
+    // row c and the column sums of the tile rows below it)
+    std::vector<int4> tv;
+    for (int i = 0; i < J; ++i) {
+        const int nt = h.nt[i];
+        if (nt == 0 || row_hi[i] == 0) continue;
+        const int b_lo = (int)(row_lo[i] / 64);
+        for (int a = b_lo; a < nt; ++a)
+            for (int b = 0; b <= a; ++b) tv.push_back(make_int4(i, a, b, 0));
+    }
+    pl.n_tile_tasks = (int64_t)tv.size();
+    RDD_TRY(dev_alloc(h, &pl.d_tile_tasks, tv.size()));
+    if (!tv.empty()) RDD_TRY(upload(h, pl.d_tile_tasks, tv.data(), sizeof(int4) * tv.size()));
+    // tile rows, longest first (triangular factor of the mixed path)
+    std::vector<std::pair<int, int2>> rt;
+    for (const int4& t4 : tv)
+        if (t4.z == 0) rt.push_back({t4.y + 1, make_int2(t4.x, t4.y)});
+    std::stable_sort(rt.begin(), rt.end(), [](const std::pair<int, int2>& x, const std::pair<int, int2>& y) {
+        return x.first > y.first;
+    });
+    std::vector<int2> rtv;
+    for (auto& e : rt) rtv.push_back(e.second);
+    pl.n_row_tasks = (int64_t)rtv.size();
+    RDD_TRY(dev_alloc(h, &pl.d_row_tasks, rtv.size()));
+    if (!rtv.empty()) RDD_TRY(upload(h, pl.d_row_tasks, rtv.data(), sizeof(int2) * rtv.size()));
+    // tiles of the block results that are used, ordered by the tiles a column
+    // pass reads, longest first
+    std::vector<std::pair<int, int2>> ct;
+    for (int i = 0; i < J; ++i) {
+        const int nt = h.nt[i];
+        if (nt == 0 || row_hi[i] == 0) continue;
+        const int c_lo = (int)(row_lo[i] / 64);
+        const int c_hi = (int)((row_hi[i] - 1) / 64);
+        for (int c = c_lo; c <= c_hi; ++c) ct.push_back({nt - c, make_int2(i, c)});
+    }
+    std::stable_sort(ct.begin(), ct.end(), [](const std::pair<int, int2>& x, const std::pair<int, int2>& y) {
+        return x.first > y.first;
+    });
+    std::vector<int2> ctv;
+    for (auto& e : ct) ctv.push_back(e.second);
+    pl.n_col_tasks = (int64_t)ctv.size();
+    RDD_TRY(dev_alloc(h, &pl.d_col_tasks, ctv.size()));
+    if (!ctv.empty()) RDD_TRY(upload(h, pl.d_col_tasks, ctv.data(), sizeof(int2) * ctv.size()));
+    return RANN_OK;
+}
 
 int build_schwarz(Handle& h) {
     const int J = h.geo.J;
@@ -789,139 +911,34 @@ int build_schwarz(Handle& h) {
         h.max_q = std::max<int>(h.max_q, (int)q);
     }
     h.factor_elems = h.f_off[J];
-    // block entry -> global column, and the gather lists
-    std::vector<int32_t> blk_cols(ub_off[J]);
     std::vector<int> mult(h.P, 0);
-    for (int i = 0; i < J; ++i) {
-        int64_t e = ub_off[i];
+    for (int i = 0; i < J; ++i)
         for (int j : h.sten[i])
-            for (int c = 0; c < h.p[j]; ++c) {
-                int64_t gcol = h.col_off[j] + c;
-                blk_cols[e++] = (int32_t)gcol;
-                mult[gcol]++;
-            }
-    }
-    std::vector<int64_t> gat;
-    std::vector<double> gat_w;
-    int64_t* gat_ = nullptr;
-    double* gatw_ = nullptr;
-    PrecondPlan plan;
-    plan.row_start.assign(J, 0);
-    plan.row_cnt.assign(J, 0);
-    // gather lists (CSR over global columns, entries in block order): count,
-    // then fill
-    std::vector<int64_t> gat_off(h.P + 1, 0);
-    for (int pass = 0; pass < 2; ++pass) {
-        std::vector<int64_t> fill;
-        if (pass == 1) {
-            for (int64_t g = 0; g < h.P; ++g) gat_off[g + 1] += gat_off[g];
-            fill.assign(gat_off.begin(), gat_off.end() - 1);
-        }
-        for (int i = 0; i < J; ++i) {
-            int64_t e = ub_off[i], pos = 0;
-            for (int j : h.sten[i]) {
-                const bool use = (h.precond != RANN_PRECOND_RAS) || (j == i);
-                for (int c = 0; c < h.p[j]; ++c, ++e) {
-                    if (!use) continue;
-                    const int64_t gcol = h.col_off[j] + c;
-                    if (pass == 0) {
-                        gat_off[gcol + 1]++;
-                    } else {
-                        const int64_t slot = fill[gcol]++;
-                        gat_[slot] = e;
-                        gatw_[slot] = (h.precond == RANN_PRECOND_SAS) ? 1.0 / (double)mult[gcol] : 1.0;
-                    }
-                }
-                if (pass == 0 && j == i) {
-                    plan.row_start[i] = pos;
-                    plan.row_cnt[i] = h.p[j];
-                }
-                pos += h.p[j];
-            }
-            if (pass == 0 && h.precond != RANN_PRECOND_RAS) {
-                plan.row_start[i] = 0;
-                plan.row_cnt[i] = h.q[i];
-            }
-        }
-        if (pass == 0) {
-            int64_t tot = 0;
-            for (int64_t g = 0; g < h.P; ++g) tot += gat_off[g + 1];
-            gat.resize((size_t)tot);
-            gat_w.resize((size_t)tot);
-            gat_ = gat.data();
-            gatw_ = gat_w.data();
-        }
-    }
-    // device copies
+            for (int c = 0; c < h.p[j]; ++c) mult[h.col_off[j] + c]++;
+    const std::vector<int> owner = ras_owner(h.sten);
     RDD_TRY(dev_alloc(h, &h.d_f_off, J + 1));
     RDD_TRY(dev_alloc(h, &h.d_q, J));
     RDD_TRY(dev_alloc(h, &h.d_ub_off, J + 1));
-    RDD_TRY(dev_alloc(h, &h.d_blk_cols, blk_cols.size()));
-    RDD_TRY(dev_alloc(h, &h.d_gat_off, gat_off.size()));
-    RDD_TRY(dev_alloc(h, &h.d_gat, gat.size()));
-    RDD_TRY(dev_alloc(h, &h.d_gat_w, gat_w.size()));
     RDD_TRY(upload(h, h.d_f_off, h.f_off.data(), sizeof(int64_t) * (J + 1)));
     RDD_TRY(upload(h, h.d_q, h.q.data(), sizeof(int64_t) * J));
     RDD_TRY(upload(h, h.d_ub_off, ub_off.data(), sizeof(int64_t) * (J + 1)));
-    RDD_TRY(upload(h, h.d_blk_cols, blk_cols.data(), sizeof(int32_t) * blk_cols.size()));
-    RDD_TRY(upload(h, h.d_gat_off, gat_off.data(), sizeof(int64_t) * gat_off.size()));
-    if (!gat.empty()) {
-        RDD_TRY(upload(h, h.d_gat, gat.data(), sizeof(int64_t) * gat.size()));
-        RDD_TRY(upload(h, h.d_gat_w, gat_w.data(), sizeof(double) * gat_w.size()));
-    }
     h.ub_total = ub_off[J];
 
-    // packed tiles, one task per stored tile (RAS: tile rows from the first
-    // owned tile column on) and the slot layout of the row and column sums
+    // the tiles of the local inverses, the application plans and the slot
+    // layout of the row and column sums
     RDD_TRY(plan_tiles(h));
-    std::vector<int4> tv;
+    RDD_TRY(build_plan(h, ub_off, mult, owner, false, h.ap));
+    if (h.precond == RANN_PRECOND_RAS) RDD_TRY(build_plan(h, ub_off, mult, owner, true, h.apT));
     std::vector<int64_t> s_off(J + 1, 0);
     std::vector<int32_t> ent_blk((size_t)h.ub_total);
     for (int i = 0; i < J; ++i) {
         const int nt = h.nt[i];
         s_off[i + 1] = s_off[i] + (int64_t)nt * (nt + 1) / 2 * 64;
         for (int64_t e = ub_off[i]; e < ub_off[i + 1]; ++e) ent_blk[e] = i;
-        if (nt == 0 || plan.row_cnt[i] == 0) continue;
-        const int b_lo = (int)(plan.row_start[i] / 64);
-        for (int a = b_lo; a < nt; ++a)
-            for (int b = 0; b <= a; ++b) tv.push_back(make_int4(i, a, b, 0));
     }
-    h.n_tile_tasks = (int64_t)tv.size();
-    // tile rows, longest first (triangular factor of the mixed path)
-    std::vector<std::pair<int, int2>> rt;
-    for (const int4& t4 : tv)
-        if (t4.z == 0) rt.push_back({t4.y + 1, make_int2(t4.x, t4.y)});
-    std::stable_sort(rt.begin(), rt.end(), [](const std::pair<int, int2>& x, const std::pair<int, int2>& y) {
-        return x.first > y.first;
-    });
-    std::vector<int2> rtv;
-    for (auto& e : rt) rtv.push_back(e.second);
-    h.n_row_tasks = (int64_t)rtv.size();
-    RDD_TRY(dev_alloc(h, &h.d_row_tasks, rtv.size()));
-    if (!rtv.empty()) RDD_TRY(upload(h, h.d_row_tasks, rtv.data(), sizeof(int2) * rtv.size()));
-    // tiles of the block results that are used (RAS: those holding owned
-    // entries), ordered by the tiles a column pass reads, longest first
-    std::vector<std::pair<int, int2>> ct;
-    for (int i = 0; i < J; ++i) {
-        const int nt = h.nt[i];
-        if (nt == 0 || plan.row_cnt[i] == 0) continue;
-        const int c_lo = (int)(plan.row_start[i] / 64);
-        const int c_hi = (int)((plan.row_start[i] + plan.row_cnt[i] - 1) / 64);
-        for (int c = c_lo; c <= c_hi; ++c) ct.push_back({nt - c, make_int2(i, c)});
-    }
-    std::stable_sort(ct.begin(), ct.end(), [](const std::pair<int, int2>& x, const std::pair<int, int2>& y) {
-        return x.first > y.first;
-    });
-    std::vector<int2> ctv;
-    for (auto& e : ct) ctv.push_back(e.second);
-    h.n_col_tasks = (int64_t)ctv.size();
-    RDD_TRY(dev_alloc(h, &h.d_col_tasks, ctv.size()));
-    if (!ctv.empty()) RDD_TRY(upload(h, h.d_col_tasks, ctv.data(), sizeof(int2) * ctv.size()));
     h.slot_total = s_off[J];
-    RDD_TRY(dev_alloc(h, &h.d_tile_tasks, tv.size()));
     RDD_TRY(dev_alloc(h, &h.d_s_off, s_off.size()));
     RDD_TRY(dev_alloc(h, &h.d_ent_blk, ent_blk.size()));
-    if (!tv.empty()) RDD_TRY(upload(h, h.d_tile_tasks, tv.data(), sizeof(int4) * tv.size()));
     RDD_TRY(upload(h, h.d_s_off, s_off.data(), sizeof(int64_t) * s_off.size()));
     if (!ent_blk.empty()) RDD_TRY(upload(h, h.d_ent_blk, ent_blk.data(), sizeof(int32_t) * ent_blk.size()));
 
@@ -943,12 +960,12 @@ int build_schwarz(Handle& h) {
 // u_i = A_i^{-1} r_{N(i)} for every block (the local solves only).  ub holds
 // (2 ub_total + 2 slot_total) k doubles: the result, the intermediate block
 // vector of the triangular factor, and the row and column sum slots.
-int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
+int launch_precond_local(Handle& h, const ApplyPlan& pl, const double* r, int k, double* ub) {
     double* u1 = ub + h.ub_total * k;
     double* Rs = u1 + h.ub_total * k;
     double* Cs = Rs + h.slot_total * k;
     const int64_t tot = h.ub_total * k;
-    const unsigned tgrid = (unsigned)h.n_tile_tasks;
+    const unsigned tgrid = (unsigned)pl.n_tile_tasks;
     if (tgrid == 0 || tot == 0) return RANN_OK;
     // FP64 with one or two right-hand sides is a single persistent launch,
     // timed by the events it records itself
@@ -962,10 +979,10 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
             float* u32 = reinterpret_cast<float*>(u1);
             if (h.precision == RANN_MIXED) {
 #define RDD_MX(KCV)                                                                                        \
-    hipLaunchKernelGGL((k_urow_mfma32<KCV>), dim3((unsigned)h.n_row_tasks), dim3(256), 0, h.stream,          \
-                       h.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_blk_cols, h.d_M32, r, k, k0, u32);  \
-    hipLaunchKernelGGL((k_zcol_mfma32<KCV>), dim3((unsigned)h.n_col_tasks), dim3(256), 0, h.stream,          \
-                       h.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_M32, u32, k, k0, ub)
+    hipLaunchKernelGGL((k_urow_mfma32<KCV>), dim3((unsigned)pl.n_row_tasks), dim3(256), 0, h.stream,          \
+                       pl.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_M32, r, k, k0, u32);  \
+    hipLaunchKernelGGL((k_zcol_mfma32<KCV>), dim3((unsigned)pl.n_col_tasks), dim3(256), 0, h.stream,          \
+                       pl.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_M32, u32, k, k0, ub)
                 if (kc == 32) {
                     RDD_MX(32);
                 } else {
@@ -974,12 +991,12 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
 #undef RDD_MX
             } else {
                 if (kc == 32)
-                    hipLaunchKernelGGL((k_rowcol_mfma64<32>), dim3((unsigned)h.n_col_tasks), dim3(256), 0, h.stream,
-                                       h.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_blk_cols, h.d_M64, r, k,
+                    hipLaunchKernelGGL((k_rowcol_mfma64<32>), dim3((unsigned)pl.n_col_tasks), dim3(256), 0, h.stream,
+                                       pl.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_M64, r, k,
                                        k0, ub);
                 else
-                    hipLaunchKernelGGL((k_rowcol_mfma64<16>), dim3((unsigned)h.n_col_tasks), dim3(256), 0, h.stream,
-                                       h.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_blk_cols, h.d_M64, r, k,
+                    hipLaunchKernelGGL((k_rowcol_mfma64<16>), dim3((unsigned)pl.n_col_tasks), dim3(256), 0, h.stream,
+                                       pl.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_M64, r, k,
                                        k0, ub);
             }
             k0 += kc;
@@ -989,11 +1006,11 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
         const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
 #define RDD_TA(T, M, KBV, WR, WC, XU, SY)                                                          \
     hipLaunchKernelGGL((k_tile_apply<T, KBV, WR, WC, XU, SY>), dim3(tgrid), dim3(256), 0, h.stream, \
-                       h.d_tile_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols, M, r, \
+                       pl.d_tile_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, pl.d_blk_cols, M, r, \
                        u1, k, k0, Rs, Cs)
 #define RDD_TR(KBV)                                                                                 \
-    hipLaunchKernelGGL((k_trirow_apply<KBV>), dim3((unsigned)h.n_row_tasks), dim3(256), 0, h.stream, \
-                       h.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, h.d_blk_cols, h.d_M32, r, \
+    hipLaunchKernelGGL((k_trirow_apply<KBV>), dim3((unsigned)pl.n_row_tasks), dim3(256), 0, h.stream, \
+                       pl.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, h.d_s_off, pl.d_blk_cols, h.d_M32, r, \
                        k, k0, Cs)
 #define RDD_TA_KB(T, M, WR, WC, XU, SY)                  \
     switch (kb) {                                        \
@@ -1016,14 +1033,14 @@ int launch_precond_local(Handle& h, const double* r, int k, double* ub) {
             hipEvent_t ea = one_launch ? kt_.a : nullptr, eb = one_launch ? kt_.b : nullptr;
             if (kb == 2)
                 hipExtLaunchKernelGGL((k_tile_apply_ps<2>), dim3(pg), dim3(256), 0, h.stream, ea, eb, 0,
-                                      (const int4*)h.d_tile_tasks, (int)h.n_tile_tasks, (const int64_t*)h.d_t_off,
+                                      (const int4*)pl.d_tile_tasks, (int)pl.n_tile_tasks, (const int64_t*)h.d_t_off,
                                       (const int64_t*)h.d_q, (const int64_t*)h.d_ub_off, (const int64_t*)h.d_s_off,
-                                      (const int32_t*)h.d_blk_cols, (const double*)h.d_M64, r, k, k0, Rs, Cs);
+                                      (const int32_t*)pl.d_blk_cols, (const double*)h.d_M64, r, k, k0, Rs, Cs);
             else
                 hipExtLaunchKernelGGL((k_tile_apply_ps<1>), dim3(pg), dim3(256), 0, h.stream, ea, eb, 0,
-                                      (const int4*)h.d_tile_tasks, (int)h.n_tile_tasks, (const int64_t*)h.d_t_off,
+                                      (const int4*)pl.d_tile_tasks, (int)pl.n_tile_tasks, (const int64_t*)h.d_t_off,
                                       (const int64_t*)h.d_q, (const int64_t*)h.d_ub_off, (const int64_t*)h.d_s_off,
-                                      (const int32_t*)h.d_blk_cols, (const double*)h.d_M64, r, k, k0, Rs, Cs);
+                                      (const int32_t*)pl.d_blk_cols, (const double*)h.d_M64, r, k, k0, Rs, Cs);
         } else {
             RDD_TA_KB(double, h.d_M64, true, true, false, true);
         }
@@ -1054,30 +1071,36 @@ int launch_precond(Handle& h, const double* r, int k, double* z, double* ub) {
         RDD_HIP(hipMemcpyAsync(z, r, sizeof(double) * h.P * k, hipMemcpyDeviceToDevice, h.stream));
         return RANN_OK;
     }
-    RDD_TRY(launch_precond_local(h, r, k, ub));
+    RDD_TRY(launch_precond_local(h, h.ap, r, k, ub));
     const int64_t tot = h.P * k;
     hipLaunchKernelGGL(k_gather_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h.stream,
-                       h.P, k, h.d_gat_off, h.d_gat, h.d_gat_w, ub, z);
+                       h.P, k, h.ap.d_gat_off, h.ap.d_gat, h.ap.d_gat_w, ub, z);
     RDD_HIP(hipGetLastError());
     return RANN_OK;
 }
 
 // z = M^{-T} r.  The local inverses are symmetric, so the transpose moves the
-// weights D_i from the local results onto the restricted input.  AS: M^{-T} =
-// M^{-1}.  SAS: D_i R_i = R_i D with D = 1/multiplicity, so M^{-T} r is the AS
-// apply of D r (tmp: P k scratch).  RAS: its blocks only compute their owned
-// rows, which the transpose does not use; not provided.
+// weights D_i from the local results onto the restricted input:
+// M^{-T} = sum_i R_i^T A_i^{-1} D_i R_i.  AS: M^{-T} = M^{-1}.  SAS: D_i R_i =
+// R_i D with D = 1/multiplicity, so M^{-T} r is the AS apply of D r.  RAS: the
+// masked plan feeds each block its owned entries of r (the others read the
+// zero row P of tmp = [r; 0]) and gathers the full local results.
 int launch_precond_T(Handle& h, const double* r, int k, double* z, double* ub, double* tmp) {
     if (h.precond == RANN_PRECOND_NONE || h.precond == RANN_PRECOND_AS) return launch_precond(h, r, k, z, ub);
-    if (h.precond != RANN_PRECOND_SAS) {
-        set_error("the transposed RAS preconditioner is not provided");
-        return RANN_EINVAL;
-    }
     const int64_t tot = h.P * k;
     const unsigned g = (unsigned)((tot + 255) / 256);
-    hipLaunchKernelGGL(k_div_count, dim3(g), dim3(256), 0, h.stream, h.P, k, h.d_gat_off, r, tmp);
-    RDD_TRY(launch_precond_local(h, tmp, k, ub));
-    hipLaunchKernelGGL(k_gather_sum, dim3(g), dim3(256), 0, h.stream, h.P, k, h.d_gat_off, h.d_gat,
+    if (h.precond == RANN_PRECOND_RAS) {
+        const unsigned g1 = (unsigned)((tot + k + 255) / 256);
+        hipLaunchKernelGGL(k_copy_pad, dim3(g1), dim3(256), 0, h.stream, tot, (int64_t)k, r, tmp);
+        RDD_TRY(launch_precond_local(h, h.apT, tmp, k, ub));
+        hipLaunchKernelGGL(k_gather_sum, dim3(g), dim3(256), 0, h.stream, h.P, k, h.apT.d_gat_off, h.apT.d_gat,
+                           (const double*)nullptr, ub, z);
+        RDD_HIP(hipGetLastError());
+        return RANN_OK;
+    }
+    hipLaunchKernelGGL(k_div_count, dim3(g), dim3(256), 0, h.stream, h.P, k, h.ap.d_gat_off, r, tmp);
+    RDD_TRY(launch_precond_local(h, h.ap, tmp, k, ub));
+    hipLaunchKernelGGL(k_gather_sum, dim3(g), dim3(256), 0, h.stream, h.P, k, h.ap.d_gat_off, h.ap.d_gat,
                        (const double*)nullptr, ub, z);
     RDD_HIP(hipGetLastError());
     return RANN_OK;

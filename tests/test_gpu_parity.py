@@ -291,10 +291,16 @@ def test_gmres_matches_qr(case_small2d, kind, method):
     sysm = ref["sys"]
     s = binding.Solver(prob, device=DEV, precond=kind)
     s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    # 1e-12: the FP64 floor of the true normal residual here is 3e-14 to 1e-13
+    # (left-preconditioned SAS stalls at 1e-13); the coefficient error at 1e-12 is
+    # about 1e-12 to 4e-10, so the FP64 bar holds with room
     W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-12, method=method, restart=50,
                       maxiter=5000)
+    assert info["status"] == 0
     assert info["max_rel_residual"] <= 1e-12
-    assert rel(W.cpu().numpy(), ref["W"]) <= 1e-7
+    err = rel(W.cpu().numpy(), ref["W"])
+    print(f"gmres {method}/{kind}: iterations {info['iterations']}, coefficient error {err:.2e}")
+    assert err <= 1e-8, err
 
 
 # ------------------------------------------------------------------ CGS and BiCG (Table 1b)
@@ -303,7 +309,7 @@ def test_gmres_matches_qr(case_small2d, kind, method):
 @pytest.mark.parametrize("k", [1, 16, 37])
 def test_transposed_preconditioner_matches_oracle(case_small2d, stencil, kind, k):
     """M^{-T} r against the transpose of the oracle's dense M^{-1} (the vector,
-    the matrix-core and the mixed chunking of the local solves); RAS declines."""
+    the matrix-core and the mixed chunking of the local solves)."""
     prob, ref = case_small2d
     sysm, H = ref["sys"], ref["H"]
     HtH = H.T @ H
@@ -311,11 +317,6 @@ def test_transposed_preconditioner_matches_oracle(case_small2d, stencil, kind, k
     s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
     rng = np.random.default_rng(9)
     r = rng.standard_normal((sysm.P, k))
-    if kind == "ras":
-        with pytest.raises(binding.RannError) as e:
-            s.apply_precond_T(torch.as_tensor(r, device=DEV))
-        assert e.value.code == binding.RANN_EINVAL
-        return
     M = osw.schwarz_dense(HtH, sysm.col_off, osw.stencil(prob, stencil), kind).dense()
     z = s.apply_precond_T(torch.as_tensor(r, device=DEV)).cpu().numpy()
     kappa = np.linalg.cond(HtH)
@@ -326,7 +327,7 @@ def test_transposed_preconditioner_matches_oracle(case_small2d, stencil, kind, k
 
 
 @pytest.mark.parametrize("method,kind", [("cgs", "as"), ("cgs", "sas"), ("cgs", "ras"),
-                                         ("bicg", "as"), ("bicg", "sas")])
+                                         ("bicg", "as"), ("bicg", "sas"), ("bicg", "ras")])
 def test_cgs_bicg_match_qr_and_oracle_iterations(case_small2d, method, kind):
     """FP64 CGS and BiCG reach the QR solution to the FP64 bar, with per-RHS
     iteration counts close to the oracle's (same recurrences, summation order
@@ -345,16 +346,6 @@ def test_cgs_bicg_match_qr_and_oracle_iterations(case_small2d, method, kind):
     for t in range(prob.F.shape[1]):
         g, o = int(info["rhs_iterations"][t]), int(it["iters"][t])
         assert abs(g - o) <= max(3, 0.25 * o), (t, g, o)
-
-
-def test_bicg_declines_ras(case_small2d):
-    prob, ref = case_small2d
-    sysm = ref["sys"]
-    s = binding.Solver(prob, device=DEV, precond="ras")
-    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
-    with pytest.raises(binding.RannError) as e:
-        s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-10, method="bicg")
-    assert e.value.code == binding.RANN_EINVAL
 
 
 @pytest.mark.parametrize("method", ["cgs", "bicg"])
