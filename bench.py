@@ -1,27 +1,35 @@
 """Benchmark of the RaNN overlapping-Schwarz hot path on one MI355X.
 
-One step = one pass of the whole path on the 2D Poisson workload (8x8
-subdomains, width-300 tanh RaNN per subdomain, 30x30 collocation points per
-subdomain plus 64 per boundary edge, relative PCA threshold 1e-8, AS-CG with
-the full stencil) with inputs resident in HBM:
+Headline: the 2D multiscale workload -div(a grad u) = f (a = 2 + sin(32 pi x)
+sin(32 pi y)), 16x16 subdomains with hidden widths drawn from U{200..600},
+24x24 collocation points per subdomain, relative PCA threshold 1e-8, 32
+right-hand sides (f = 1 and random smooth sine series) solved in one batched
+FP64 AS-CG with the full stencil.  One step is one pass of the whole path
+with the inputs resident in HBM:
 
   assemble (binning, window partition of unity, operator coefficients)
   -> PCA (value Gram, FP64 eigendecomposition, truncation)
   -> operator rows H, local Gram blocks, local inverses
-  -> preconditioned CG to a relative normal residual of 1e-6
-  -> probe evaluation u_h and misfit gradient (transpose evaluation)
+  -> batched preconditioned CG to a relative normal residual of 1e-6
+  -> probe evaluation u_h and the gradient of L = ||u_h||^2 at the probes
+     (transpose evaluation; the workload has no observations)
   -> adjoint solve and dF = H z
 
-The JSON line reports solves/s of that step (value), time-to-1e-6 end-to-end
-and solve-only, the mixed-precision path on the same problem, fwd+bwd ms, the
-roofline position of the dominant kernel, and the FP64 oracle timed on the
-host cores on the same workload.
+`value` is right-hand sides per second of that step.  Beside it, under the
+protocol of 3 warm-up and 10 timed runs (min / median / max): time to 1e-6
+end-to-end (assembly to solution) and solve-only for the batched FP64 path,
+the batched mixed path and the FP64 path solving the 32 right-hand sides one
+after another; fwd+bwd ms on the 3D Poisson workload (16 right-hand sides);
+RAS-GMRES(50) on the space-time workload; the Krylov x preconditioner grid and
+Newton on the 2D Poisson layout; the roofline position of the dominant kernel;
+and the FP64 oracle timed on the host cores.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -37,19 +45,20 @@ KERNELS = ["k_eig", "k_factor", "k_pca_gram", "k_feat_rows", "k_local_gram", "k_
            "k_HTy_part", "k_tile_apply", "k_slot_reduce"]
 # timers that cover several different kernels (not candidates for the roofline line)
 GROUPS = {"k_eig", "k_factor", "k_Hx", "k_pca_gram"}
-
+METRIC = "time-to-1e-6 residual & solves/s, mixed-batched vs FP64 AS-CG; fwd+bwd ms"
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter measurement
-    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when there is none or the kernel's source changed since it was taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    measurement (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when there is none or the kernel's source changed
+    since it was taken."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh).get(kernel)
+            rec = json.load(fh)[f"{kernel}@{workload}"]
         with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError, KeyError, TypeError, AttributeError):
@@ -62,20 +71,23 @@ def measured_traffic(kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--stencil", default="full")
+    ap.add_argument("--runs", type=int, default=10, help="timed runs of each side measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 32-RHS mixed/FP64 comparison")
-    ap.add_argument("--no-variants", action="store_true", help="skip the Krylov method x preconditioner grid")
-    ap.add_argument("--no-nonlinear", action="store_true", help="skip the Newton iteration on the semilinear problem")
-    ap.add_argument("--quick", action="store_true", help="skip the side measurements")
+    ap.add_argument("--quick", action="store_true", help="headline only: no side measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB (counter calibration) and exit")
     return ap.parse_args()
+
+
+def stats3(xs):
+    xs = [float(x) for x in xs]
+    return {"min": min(xs), "median": float(np.median(xs)), "max": max(xs)}
 
 
 class Inputs:
@@ -86,23 +98,30 @@ class Inputs:
         self.prob = prob
         self.F = torch.as_tensor(prob.F, device=dev)
         self.Xq = torch.as_tensor(prob.probes, device=dev)
-        self.u_obs = torch.as_tensor(prob.u_probe[:, None], device=dev).repeat(1, prob.F.shape[1])
+        k = prob.F.shape[1]
+        if prob.u_obs is not None:
+            self.u_obs = torch.as_tensor(prob.u_obs[:, None], device=dev).repeat(1, k)
+        else:
+            self.u_obs = torch.zeros((prob.probes.shape[0], k), dtype=torch.float64, device=dev)
         self.binding = binding
+        self.meta = prob.meta
 
 
-def work_model(s, prob, k):
+def work_model(s, prob, k, precision):
     """Algorithmic work per launch of each timed kernel (bytes the method must
-    move, or flops it must do), from the handle's sizes."""
+    move, or flops it must do), from the handle's sizes: (bound, work, unit,
+    peak).  Bytes count what the method reads and writes, not intermediate data
+    of this implementation (the slots of the row and column sums)."""
     row_off, _, p = s.layout()
     n = np.diff(row_off).astype(np.float64)
     m = np.asarray(prob.m, dtype=np.float64)
     p = np.asarray(p, dtype=np.float64)
     q = s.blocks().astype(np.float64)
     nnz, N, P = float(s.info.nnz), float(s.info.N), float(s.info.P)
-    f_bytes = 4.0 if s.precision == "mixed" else 8.0
-    ntile = np.ceil(q / 64.0)
-    slots = float(np.sum(ntile * (ntile + 1) / 2.0 * 64.0))
-    return {
+    f_bytes = 4.0 if precision == "mixed" else 8.0
+    sq = float(np.sum(q))
+    tri = float(np.sum(q * (q + 1) / 2.0))
+    model = {
         # nominal count of a dense symmetric eigendecomposition with vectors
         "k_eig": ("alu", float(np.sum(9.0 * m ** 3)), "flop", FP64_PEAK_TFLOPS),
         # Cholesky q^3/3 + triangular inverse q^3/3, FP64 on matrix cores
@@ -112,35 +131,44 @@ def work_model(s, prob, k):
         "k_feat_rows": ("mfma", float(np.sum(2.0 * n * m * p)), "flop", FP64_PEAK_TFLOPS),
         # Gram blocks H_j^T H_k: counted for the diagonal blocks only (a lower bound)
         "k_local_gram": ("mfma", float(np.sum(2.0 * n * p * p)), "flop", FP64_PEAK_TFLOPS),
-        # slabs of the normal matrix read once, x read, s written
-        "k_normal": ("hbm", 8.0 * (float(s.info.normal_elems) + 2.0 * P * k), "byte", HBM_PEAK_GBS),
         # H read once, x read, y written
         "k_Hx": ("hbm", 8.0 * (nnz + P * k + N * k), "byte", HBM_PEAK_GBS),
         "k_HTy_part": ("hbm", 8.0 * (nnz + N * k + P * k), "byte", HBM_PEAK_GBS),
-        # the stored local operators (q_i (q_i + 1) / 2 entries each: W_i in FP64,
-        # the factor Y_i in FP32) read once, the gathered r, and the row/column
-        # sum slots written (both kinds for W, the column sums for Y)
-        "k_tile_apply": ("hbm", f_bytes * float(np.sum(q * (q + 1) / 2.0))
-                         + 8.0 * (float(np.sum(q)) + (1.0 if s.precision == "mixed" else 2.0) * slots) * k,
-                         "byte", HBM_PEAK_GBS),
-        # the slots read, the local results written
-        "k_slot_reduce": ("hbm", 8.0 * ((1.0 if s.precision == "mixed" else 2.0) * slots + float(np.sum(q))) * k,
-                          "byte", HBM_PEAK_GBS),
+        # the local results: the gathered r read, the results written
+        "k_slot_reduce": ("hbm", 8.0 * 2.0 * sq * k, "byte", HBM_PEAK_GBS),
     }
+    # slabs of the normal matrix read once, x read, s written; with k >= 16 the
+    # flops 2 k entries decide whether the bytes or the matrix cores bound it
+    nb = 8.0 * (float(s.info.normal_elems) + 2.0 * P * k)
+    nf = 2.0 * k * float(s.info.normal_elems)
+    model["k_normal"] = (("mfma", nf, "flop", FP64_PEAK_TFLOPS) if nf / nb > FP64_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS
+                         else ("hbm", nb, "byte", HBM_PEAK_GBS))
+    # local solves z_i = A_i^{-1} r_i: the stored triangle of every local
+    # operator read once (W_i in FP64, or Y_i in FP32), the gathered r read and
+    # the local results written; 2 k q_i^2 flops (a symmetric product per
+    # right-hand side, or Y_i then Y_i^T)
+    tb = f_bytes * tri + 8.0 * 2.0 * sq * k
+    tf = 2.0 * k * float(np.sum(q * q))
+    peak_f = FP32_PEAK_TFLOPS if (precision == "mixed" and k >= 16) else FP64_PEAK_TFLOPS
+    model["k_tile_apply"] = (("mfma", tf, "flop", peak_f) if tf / tb > peak_f * 1e3 / HBM_PEAK_GBS
+                             else ("hbm", tb, "byte", HBM_PEAK_GBS))
+    return model
+
+
+def new_solver(inp, precision, stencil, precond="as"):
+    return inp.binding.Solver(inp.prob, precision=precision, stencil=stencil, precond=precond)
 
 
 def run_step(inp, precision, stencil, tol, torch, timings=None, want_model=False):
     """One pass of the path; returns (solve info, adjoint info, work model or None)."""
-    b = inp.binding
     sync = torch.cuda.synchronize
     t0 = time.perf_counter()
-    s = b.Solver(inp.prob, precision=precision, stencil=stencil, precond="as")
-    s.precision = precision
+    s = new_solver(inp, precision, stencil)
     if timings is not None:
         sync()
         timings["assemble_ms"] = (time.perf_counter() - t0) * 1e3
         t0 = time.perf_counter()
-    s.pca(inp.prob.meta["pca_tol"], "rel_eig")
+    s.pca(inp.meta["pca_tol"], "rel_eig")
     if timings is not None:
         sync()
         timings["pca_factor_ms"] = (time.perf_counter() - t0) * 1e3
@@ -157,46 +185,157 @@ def run_step(inp, precision, stencil, tol, torch, timings=None, want_model=False
     if timings is not None:
         sync()
         timings["eval_adjoint_ms"] = (time.perf_counter() - t0) * 1e3
-    model = work_model(s, inp.prob, inp.prob.F.shape[1]) if want_model else None
+    model = work_model(s, inp.prob, inp.prob.F.shape[1], precision) if want_model else None
     s.close()
+    if info["status"] != 0 or ainfo["status"] != 0:
+        raise RuntimeError(f"solve status {info['status']}, adjoint status {ainfo['status']}")
     return info, ainfo, model
 
 
-def solve_only(inp, precision, stencil, tol, torch, reps=3):
-    """Time-to-tol of the solve with the preconditioner already built."""
-    b = inp.binding
-    s = b.Solver(inp.prob, precision=precision, stencil=stencil, precond="as")
-    s.pca(inp.prob.meta["pca_tol"], "rel_eig")
-    W, info = s.solve(inp.F, tol=tol, maxiter=5000, check_every=10)
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(reps):
+def time_to_tol(inp, precision, stencil, tol, torch, runs, warm=3, looped=False):
+    """Time to tol under the protocol (warm-up runs, then `runs` timed ones):
+    end-to-end (assembly, PCA, factors and the solve; one handle per run) and
+    solve-only (the preconditioner built once).  looped: the right-hand sides
+    are solved one after another."""
+    sync = torch.cuda.synchronize
+    k = inp.F.shape[1]
+
+    def solve(s):
+        if not looped:
+            W, info = s.solve(inp.F, tol=tol, maxiter=5000, check_every=10)
+            return W, info
+        cols, its, res, st = [], [], [], 0
+        for q in range(k):
+            Wq, iq = s.solve(inp.F[:, q:q + 1], tol=tol, maxiter=5000, check_every=10)
+            cols.append(Wq)
+            its.append(int(iq["iterations"]))
+            res.append(float(iq["max_rel_residual"]))
+            st = max(st, int(iq["status"]))
+        return torch.cat(cols, 1), {"status": st, "iterations": max(its), "max_rel_residual": max(res),
+                                    "rhs_iterations": np.array(its)}
+
+    e2e = []
+    for r in range(warm + runs):
+        sync()
         t0 = time.perf_counter()
-        W, info = s.solve(inp.F, tol=tol, maxiter=5000, check_every=10)
-        torch.cuda.synchronize()
-        times.append((time.perf_counter() - t0) * 1e3)
-    stats = dict(info=info, ms=float(np.median(times)), P=int(s.info.P), nnz=int(s.info.nnz),
-                 factor_elems=int(s.info.factor_elems), N=int(s.info.N))
+        s = new_solver(inp, precision, stencil)
+        s.pca(inp.meta["pca_tol"], "rel_eig")
+        W, info = solve(s)
+        sync()
+        if r >= warm:
+            e2e.append((time.perf_counter() - t0) * 1e3)
+        if r + 1 < warm + runs:
+            s.close()
+    so = []
+    for r in range(warm + runs):
+        sync()
+        t0 = time.perf_counter()
+        W, info = solve(s)
+        sync()
+        if r >= warm:
+            so.append((time.perf_counter() - t0) * 1e3)
+    if info["status"] != 0:
+        raise RuntimeError(f"{precision} solve did not reach {tol}: status {info['status']}")
+    U = s.eval(inp.Xq, W)
+    out = {"end_to_end_ms": stats3(e2e), "solve_only_ms": stats3(so),
+           "solves_per_s": {"end_to_end": k / (float(np.median(e2e)) / 1e3),
+                            "solve_only": k / (float(np.median(so)) / 1e3)},
+           "iterations": int(info["iterations"]), "max_rel_residual": float(info["max_rel_residual"]),
+           "shifts": int(info.get("shifts", 0)) if not looped else None, "P": int(s.info.P)}
     s.close()
-    return stats
+    return out, U
 
 
-def krylov_variants(inp, stencil, tol, torch):
-    """The Krylov method x preconditioner grid of Table 1b on the benchmark
-    workload (FP64, preconditioner built once per kind): iterations and the
-    solve time to the tolerance (second of two solves), at most 1000
-    iterations (status 1: not converged)."""
-    b = inp.binding
-    grid = {"as": ["cg", "cgs", "bicg", "gmres"], "sas": ["cgs", "bicg", "gmres"], "ras": ["cgs", "gmres"]}
-    out = {}
+def fwd_bwd(torch, wl, dev, runs, warm=3):
+    """fwd+bwd on the 3D Poisson workload (16 right-hand sides): the forward
+    batched FP64 AS-CG to 1e-6, probe evaluation, and the backward pass (the
+    misfit gradient at the 32^3 probes, transpose evaluation, adjoint solve and
+    dF = H z); set-up timed separately."""
+    from paper_2412_19207_amd import binding
+    prob = wl.make("cfg5")
+    inp = Inputs(prob, torch, dev)
+    meta = prob.meta
+    sync = torch.cuda.synchronize
+    sync()
+    t0 = time.perf_counter()
+    s = binding.Solver(prob, precision="fp64", stencil=meta["stencil"], precond=meta["precond"])
+    s.pca(meta["pca_tol"], "rel_eig")
+    sync()
+    setup = (time.perf_counter() - t0) * 1e3
+    fw, bw, tot = [], [], []
+    for r in range(warm + runs):
+        sync()
+        t0 = time.perf_counter()
+        W, info = s.solve(inp.F, tol=meta["tol"], maxiter=5000)
+        U = s.eval(inp.Xq, W)
+        sync()
+        t1 = time.perf_counter()
+        dW = s.eval_T(inp.Xq, 2.0 * (U - inp.u_obs))
+        dF, ainfo = s.solve_backward(dW, tol=meta["tol"], maxiter=5000)
+        sync()
+        t2 = time.perf_counter()
+        if r >= warm:
+            fw.append((t1 - t0) * 1e3)
+            bw.append((t2 - t1) * 1e3)
+            tot.append((t2 - t0) * 1e3)
+    if info["status"] != 0 or ainfo["status"] != 0:
+        raise RuntimeError("fwd+bwd solve did not converge")
+    e = float(np.linalg.norm(U[:, 0].cpu().numpy() - prob.u_probe) / np.linalg.norm(prob.u_probe))
+    out = {"workload": prob.name, "rhs": int(prob.k), "P": int(s.info.P), "stencil": meta["stencil"],
+           "fwd_bwd_ms": stats3(tot), "fwd_ms": stats3(fw), "bwd_ms": stats3(bw), "setup_ms": setup,
+           "iterations": int(info["iterations"]), "adjoint_iterations": int(ainfo["iterations"]),
+           "e_L2_probes_rhs0": e}
+    s.close()
+    return out
+
+
+def gmres_spacetime(torch, wl, dev, stencil="face"):
+    """RAS-GMRES(50) on the space-time advection-diffusion workload (8x8x8
+    subdomains, width 400), mixed precision, one right-hand side; SAS beside it."""
+    from paper_2412_19207_amd import binding
+    prob = wl.make("cfg4")
+    meta = prob.meta
+    F = torch.as_tensor(prob.F, device=dev)
+    Xq = torch.as_tensor(prob.probes, device=dev)
+    out = {"workload": prob.name, "stencil": stencil, "restart": 50, "precision": "mixed"}
+    for kind in ["ras", "sas"]:
+        sync = torch.cuda.synchronize
+        sync()
+        t0 = time.perf_counter()
+        s = binding.Solver(prob, precision="mixed", stencil=stencil, precond=kind)
+        s.pca(meta["pca_tol"], "rel_eig")
+        sync()
+        t1 = time.perf_counter()
+        W, info = s.solve(F, tol=meta["tol"], maxiter=1500, method="gmres", restart=50, check_every=10)
+        sync()
+        t2 = time.perf_counter()
+        U = s.eval(Xq, W)[:, 0].cpu().numpy()
+        out[kind] = {"setup_ms": (t1 - t0) * 1e3, "solve_ms": (t2 - t1) * 1e3, "status": int(info["status"]),
+                     "iterations": int(info["iterations"]), "max_rel_residual": float(info["max_rel_residual"]),
+                     "P": int(s.info.P),
+                     "e_L2_probes": float(np.linalg.norm(U - prob.u_probe) / np.linalg.norm(prob.u_probe))}
+        s.close()
+    return out
+
+
+def krylov_variants(torch, wl, dev, tol):
+    """The Krylov method x preconditioner grid of Table 1b on the 2D Poisson
+    workload (8x8 subdomains, width 300, FP64, full stencil, preconditioner
+    built once per kind): iterations and the solve time to the tolerance
+    (second of two solves), at most 1000 iterations (status 1: not converged)."""
+    from paper_2412_19207_amd import binding
+    prob = wl.make("cfg2")
+    F = torch.as_tensor(prob.F, device=dev)
+    grid = {"as": ["cg", "cgs", "bicg", "gmres"], "sas": ["cgs", "bicg", "gmres"], "ras": ["cgs", "bicg", "gmres"]}
+    out = {"workload": prob.name}
     for kind, methods in grid.items():
-        s = b.Solver(inp.prob, precision="fp64", stencil=stencil, precond=kind)
-        s.pca(inp.prob.meta["pca_tol"], "rel_eig")
+        s = binding.Solver(prob, precision="fp64", stencil="full", precond=kind)
+        s.pca(prob.meta["pca_tol"], "rel_eig")
         for m in methods:
-            s.solve(inp.F, tol=tol, maxiter=1000, method=m, restart=50, check_every=10)
+            s.solve(F, tol=tol, maxiter=1000, method=m, restart=50, check_every=10)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            W, info = s.solve(inp.F, tol=tol, maxiter=1000, method=m, restart=50, check_every=10)
+            W, info = s.solve(F, tol=tol, maxiter=1000, method=m, restart=50, check_every=10)
             torch.cuda.synchronize()
             out[f"{m}/{kind}"] = {"iterations": int(info["iterations"]), "solve_ms": (time.perf_counter() - t0) * 1e3,
                                   "status": int(info["status"]),
@@ -206,10 +345,10 @@ def krylov_variants(inp, stencil, tol, torch):
 
 
 def nonlinear_newton(torch, wl, dev, steps=10):
-    """Newton on the semilinear problem -lap u + u^3 = f with the benchmark's
-    8x8, width-300 layout (FP64 AS-CG per step to 1e-10; the first step builds
-    the PCA basis, later steps reuse it): time per step, increments, linear
-    iterations, and the relative L2 error at the probes."""
+    """Newton on the semilinear problem -lap u + u^3 = f with the 8x8, width-300
+    layout (FP64 AS-CG per step to 1e-10; the first step builds the PCA basis,
+    later steps reuse it): time per step, increments, linear iterations, and
+    the relative L2 error at the probes."""
     from paper_2412_19207_amd import nonlinear as gnl
     prob = wl.make("semilinear2d")
     gamma = prob.meta["gamma"]
@@ -230,80 +369,51 @@ def nonlinear_newton(torch, wl, dev, steps=10):
             "e_L2_probes": e}
 
 
-def cpu_baseline(prob, tol, stencil, min_seconds=10.0, max_reps=3):
-    """The FP64 oracle on the same workload, on the host cores: assembly with PCA,
-    then block-sparse AS-PCG to the same tolerance, repeated until about
-    min_seconds of host work (at most max_reps solves)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(prob, tol, stencil, gpu_iters, sample_iters=10):
+    """The FP64 oracle on the same workload, on the host cores: the full
+    assembly with PCA (SVD per subdomain, operator rows) and its AS
+    preconditioner (local Cholesky factors), then `sample_iters` iterations of
+    its block-sparse PCG on all right-hand sides; the PCG part is scaled to
+    `gpu_iters` iterations (the count the GPU needed to reach tol)."""
     from oracle import assemble as oasm
-    from oracle import solve as osolve
+    from oracle import blocksparse as obs
+    from oracle import krylov as okr
+    from oracle import schwarz as osw
     try:
         from threadpoolctl import threadpool_info
         threads = max([int(t.get("num_threads", 1)) for t in threadpool_info()] or [1])
     except Exception:  # threadpoolctl missing: report the interpreter's view
         threads = os.cpu_count()
-    reps, t_all, iters = 0, 0.0, 0
-    while reps < max_reps and (reps == 0 or t_all < min_seconds):
-        t0 = time.perf_counter()
-        sysm = oasm.assemble(prob, "rel_eig", prob.meta["pca_tol"])
-        it = osolve.iterative(prob, sysm, stencil, "as", "cg", tol=tol, maxiter=5000)
-        t_all += time.perf_counter() - t0
-        iters = int(it["iters"].max())
-        reps += 1
-    return dict(total_s=t_all / reps, reps=reps, iters=iters, threads=threads)
-
-
-def batched_comparison(torch, binding, wl, dev):
-    """Many right-hand sides in one solve, mixed against FP64, on the
-    multiscale workload with 32 batched right-hand sides (end-to-end time to
-    the tolerance and the solve alone), and the same right-hand sides solved
-    one at a time in FP64 for reference."""
-    prob = wl.make("cfg3")
-    meta = prob.meta
-    F = torch.as_tensor(prob.F, device=dev)
-    k = F.shape[1]
-    out = {"workload": prob.name, "rhs": int(k), "subdomains": [int(x) for x in prob.l],
-           "hidden_width": [int(prob.m.min()), int(prob.m.max())], "rows": int(prob.N),
-           "tol": meta["tol"], "stencil": meta["stencil"], "precond": meta["precond"]}
-    for precision in ["fp64", "mixed", "fp64", "mixed"]:  # first pair warms up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s = binding.Solver(prob, precision=precision, stencil=meta["stencil"], precond=meta["precond"])
-        s.pca(meta["pca_tol"], "rel_eig")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        W, info = s.solve(F, tol=meta["tol"], maxiter=5000)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        W, info = s.solve(F, tol=meta["tol"], maxiter=5000)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        e2e = (t2 - t0) * 1e3
-        out[precision] = {"time_to_tol_ms": {"end_to_end": e2e, "solve_only": (t3 - t2) * 1e3},
-                          "solves_per_s": k / (e2e / 1e3), "iterations": int(info["iterations"]),
-                          "max_rel_residual": float(info["max_rel_residual"])}
-        s.close()
-    # the same right-hand sides one at a time (FP64, preconditioner built once)
-    s = binding.Solver(prob, precision="fp64", stencil=meta["stencil"], precond=meta["precond"])
-    s.pca(meta["pca_tol"], "rel_eig")
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for q in range(k):
-        s.solve(F[:, q:q + 1], tol=meta["tol"], maxiter=5000)
-    torch.cuda.synchronize()
-    out["fp64_one_at_a_time_solve_ms"] = (time.perf_counter() - t0) * 1e3
-    s.close()
-    out["mixed_over_fp64_speedup"] = {
-        "end_to_end": out["fp64"]["time_to_tol_ms"]["end_to_end"] / out["mixed"]["time_to_tol_ms"]["end_to_end"],
-        "solve_only": out["fp64"]["time_to_tol_ms"]["solve_only"] / out["mixed"]["time_to_tol_ms"]["solve_only"]}
-    return out
+    sysm = oasm.assemble(prob, "rel_eig", prob.meta["pca_tol"])
+    bh = obs.BlockH(sysm)
+    M = osw.schwarz_blocks(bh, osw.stencil(prob, stencil), kind="as", local="chol")
+    rhs = bh.rmatvec(sysm.Fs)
+    t1 = time.perf_counter()
+    okr.pcg(bh.normal, M.apply, rhs, tol=0.0, maxiter=sample_iters)
+    t2 = time.perf_counter()
+    est = (t1 - t0) + (t2 - t1) * gpu_iters / sample_iters
+    return dict(total_s=est, setup_s=t1 - t0, pcg_sample_s=t2 - t1, sample_iters=sample_iters,
+                threads=threads, measured_s=t2 - t0)
 
 
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: every GPU box here has one GPU, "
+                                   "so --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2412_19207_amd import binding
@@ -326,15 +436,20 @@ def main():
     prob = wl.make(args.workload)
     inp = Inputs(prob, torch, dev)
     k = prob.F.shape[1]
+    stencil = args.stencil
 
     for _ in range(args.warmup):
-        run_step(inp, "fp64", args.stencil, args.tol, torch)
+        run_step(inp, args.precision, stencil, args.tol, torch)
     torch.cuda.synchronize()
     binding.rann_dd_ktime_enable(True)
+    per_step = []
     t0 = time.perf_counter()
     last = None
     for _ in range(args.steps):
-        last = run_step(inp, "fp64", args.stencil, args.tol, torch)
+        ts = time.perf_counter()
+        last = run_step(inp, args.precision, stencil, args.tol, torch)
+        torch.cuda.synchronize()
+        per_step.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ktimes = {name: binding.rann_dd_ktime_query(name) for name in KERNELS}
@@ -342,7 +457,7 @@ def main():
     ms_step = elapsed / args.steps * 1e3
     info, ainfo, _ = last
     tm = {}
-    _, _, model = run_step(inp, "fp64", args.stencil, args.tol, torch, timings=tm, want_model=True)
+    _, _, model = run_step(inp, args.precision, stencil, args.tol, torch, timings=tm, want_model=True)
     # dominant kernel over the timed region and its roofline position
     dom = max((n for n in ktimes if n not in GROUPS), key=lambda n: ktimes[n][0])
     tot_ms, launches = ktimes[dom]
@@ -351,8 +466,9 @@ def main():
     achieved = work / avg_s / (1e9 if wunit == "byte" else 1e12)
     roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
                 "unit": "GB/s" if wunit == "byte" else "TFLOP/s", "frac": achieved / peak,
-                "traffic": measured_traffic(dom), "avg_launch_us": avg_s * 1e6, "launches": launches,
-                "algorithmic_work_per_launch": work}
+                "traffic": measured_traffic(dom, prob.name), "avg_launch_us": avg_s * 1e6,
+                "launches": launches, "algorithmic_work_per_launch": work,
+                "work_unit": wunit}
     kernel_table = {}
     for name, (ms, cnt) in ktimes.items():
         if cnt == 0:
@@ -361,61 +477,71 @@ def main():
         av = ms / cnt / 1e3
         ach = w_ / av / (1e9 if u_ == "byte" else 1e12)
         kernel_table[name] = {"ms_per_step": ms / args.steps, "avg_us": av * 1e6, "bound": b_,
-                              "achieved": ach, "frac": ach / pk_, "launches_per_step": cnt / args.steps}
+                              "achieved": ach, "unit": "GB/s" if u_ == "byte" else "TFLOP/s",
+                              "frac": ach / pk_, "launches_per_step": cnt / args.steps}
         if name in GROUPS:
             kernel_table[name]["group_of_kernels"] = True
 
     out = {
-        "metric": "time-to-1e-6 residual & solves/s, mixed-batched vs FP64 AS-CG; fwd+bwd ms",
+        "metric": METRIC,
         "value": k / (ms_step / 1e3),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_stats": stats3(per_step),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": prob.name, "subdomains": [int(x) for x in prob.l],
-                   "hidden_width": int(prob.m[0]), "rows": int(prob.N), "rhs": int(k),
-                   "pca_tol": prob.meta["pca_tol"], "tol": args.tol, "stencil": args.stencil,
-                   "precond": "as", "method": "cg"},
+                   "hidden_width": [int(np.min(prob.m)), int(np.max(prob.m))], "rows": int(prob.N),
+                   "rhs": int(k), "pca_tol": prob.meta["pca_tol"], "tol": args.tol, "stencil": stencil,
+                   "precond": "as", "method": "cg", "precision": args.precision,
+                   "step": "assemble + PCA + factors + batched CG to tol + probe eval + adjoint"},
         "iterations": int(info["iterations"]),
         "adjoint_iterations": int(ainfo["iterations"]),
         "rel_residual": float(info["max_rel_residual"]),
         "roofline": roofline,
         "kernels": kernel_table,
+        "phases_ms": tm,
     }
     if not args.quick:
-        out["phases_ms"] = tm
-        so = solve_only(inp, "fp64", args.stencil, args.tol, torch)
-        out["time_to_1e-6_ms"] = {"end_to_end": tm["assemble_ms"] + tm["pca_factor_ms"] + tm["solve_ms"],
-                                  "solve_only": so["ms"]}
-        out["fwd_bwd_ms"] = tm["solve_ms"] + tm["eval_adjoint_ms"]
-        out["sizes"] = {"P": so["P"], "N": so["N"], "nnz_H": so["nnz"], "factor_elems": so["factor_elems"]}
-        if not args.no_mixed:
-            tmm = {}
-            mi, _, _ = run_step(inp, "mixed", args.stencil, args.tol, torch, timings=tmm)
-            som = solve_only(inp, "mixed", args.stencil, args.tol, torch)
-            out["mixed"] = {"time_to_1e-6_ms": {"end_to_end": tmm["assemble_ms"] + tmm["pca_factor_ms"] + tmm["solve_ms"],
-                                                "solve_only": som["ms"]},
-                            "iterations": int(mi["iterations"]), "phases_ms": tmm}
-        if not args.no_batched:
-            out["batched"] = batched_comparison(torch, binding, wl, dev)
-        if not args.no_variants:
-            out["krylov_variants"] = krylov_variants(inp, args.stencil, args.tol, torch)
-        if not args.no_nonlinear:
-            out["nonlinear_newton"] = nonlinear_newton(torch, wl, dev)
+        side = {}
+        t64, U64 = time_to_tol(inp, "fp64", stencil, args.tol, torch, args.runs)
+        side["fp64_batched"] = t64
+        tmx, Umx = time_to_tol(inp, "mixed", stencil, args.tol, torch, args.runs)
+        side["mixed_batched"] = tmx
+        d = (Umx - U64).cpu().numpy()
+        nrm = np.linalg.norm(U64.cpu().numpy(), axis=0)
+        e = np.linalg.norm(d, axis=0) / np.where(nrm > 0, nrm, 1.0)
+        side["mixed_vs_fp64_u_probes"] = {"max": float(e.max()), "median": float(np.median(e))}
+        tlp, _ = time_to_tol(inp, "fp64", stencil, args.tol, torch, max(2, args.runs // 5), warm=1, looped=True)
+        side["fp64_looped"] = tlp
+        side["mixed_over_fp64_batched"] = {
+            "end_to_end": t64["end_to_end_ms"]["median"] / tmx["end_to_end_ms"]["median"],
+            "solve_only": t64["solve_only_ms"]["median"] / tmx["solve_only_ms"]["median"]}
+        side["batched_over_looped_fp64_solve_only"] = (tlp["solve_only_ms"]["median"]
+                                                       / t64["solve_only_ms"]["median"])
+        out["time_to_1e-6"] = side
+        out["fwd_bwd"] = fwd_bwd(torch, wl, dev, args.runs)
+        out["fwd_bwd_ms"] = out["fwd_bwd"]["fwd_bwd_ms"]["median"]
+        out["gmres_spacetime"] = gmres_spacetime(torch, wl, dev)
+        out["krylov_variants"] = krylov_variants(torch, wl, dev, args.tol)
+        out["nonlinear_newton"] = nonlinear_newton(torch, wl, dev)
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(prob, args.tol, args.stencil)
+        cb = cpu_baseline(prob, args.tol, stencil, int(info["iterations"]))
         out["cpu_baseline"] = {"value": k / cb["total_s"], "unit": "solves/s",
                                "cores": cb["threads"], "kind": "oracle",
-                               "sample": f"{cb['reps']} full solve(s) of the same workload (assembly "
-                                         f"with PCA + block-sparse AS-PCG to {args.tol:g}, "
-                                         f"{cb['iters']} iterations), averaged",
-                               "seconds": cb["total_s"]}
+                               "sample": f"the oracle's full assembly with PCA and AS set-up of the same "
+                                         f"workload ({cb['setup_s']:.1f} s), then {cb['sample_iters']} iterations "
+                                         f"of its block-sparse AS-PCG on all {k} right-hand sides "
+                                         f"({cb['pcg_sample_s']:.1f} s), scaled to the "
+                                         f"{int(info['iterations'])} iterations the GPU needed for {args.tol:g}",
+                               "seconds_per_step": cb["total_s"], "seconds_measured": cb["measured_s"],
+                               "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
     print(json.dumps(out))
 
 

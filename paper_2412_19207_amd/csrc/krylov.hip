@@ -977,6 +977,10 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
                 stalls = 0;
             } else {
                 ++stalls;
+                // no progress since the last check: restart from the true
+                // residual (a step of iterative refinement on H^T H through the
+                // rows of H) before counting it as the floor
+                drift = again;
             }
             if (!again || it >= o.maxiter || replacements > 20 || floor_hit || stalls >= 4) {
                 if (again) *status = RANN_ENOTCONV;

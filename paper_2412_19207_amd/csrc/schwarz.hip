@@ -969,7 +969,7 @@ int launch_precond_local(Handle& h, const ApplyPlan& pl, const double* r, int k,
     if (tgrid == 0 || tot == 0) return RANN_OK;
     // FP64 with one or two right-hand sides is a single persistent launch,
     // timed by the events it records itself
-    const bool one_launch = h.precision != RANN_MIXED && k <= 2;
+    const bool one_launch = h.precision != RANN_MIXED && (k <= 2 || k == 16 || k == 32);
     KTimer kt_(h.stream, "k_tile_apply", one_launch);
     int kv0 = 0;  // right-hand sides from kv0 on take the slot path
     for (int k0 = 0; k0 < k;) {
@@ -990,14 +990,17 @@ int launch_precond_local(Handle& h, const ApplyPlan& pl, const double* r, int k,
                 }
 #undef RDD_MX
             } else {
+                hipEvent_t ea = one_launch ? kt_.a : nullptr, eb = one_launch ? kt_.b : nullptr;
                 if (kc == 32)
-                    hipLaunchKernelGGL((k_rowcol_mfma64<32>), dim3((unsigned)pl.n_col_tasks), dim3(256), 0, h.stream,
-                                       pl.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_M64, r, k,
-                                       k0, ub);
+                    hipExtLaunchKernelGGL((k_rowcol_mfma64<32>), dim3((unsigned)pl.n_col_tasks), dim3(256), 0,
+                                          h.stream, ea, eb, 0, (const int2*)pl.d_col_tasks, (const int64_t*)h.d_t_off,
+                                          (const int64_t*)h.d_q, (const int64_t*)h.d_ub_off,
+                                          (const int32_t*)pl.d_blk_cols, (const double*)h.d_M64, r, k, k0, ub);
                 else
-                    hipLaunchKernelGGL((k_rowcol_mfma64<16>), dim3((unsigned)pl.n_col_tasks), dim3(256), 0, h.stream,
-                                       pl.d_col_tasks, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_M64, r, k,
-                                       k0, ub);
+                    hipExtLaunchKernelGGL((k_rowcol_mfma64<16>), dim3((unsigned)pl.n_col_tasks), dim3(256), 0,
+                                          h.stream, ea, eb, 0, (const int2*)pl.d_col_tasks, (const int64_t*)h.d_t_off,
+                                          (const int64_t*)h.d_q, (const int64_t*)h.d_ub_off,
+                                          (const int32_t*)pl.d_blk_cols, (const double*)h.d_M64, r, k, k0, ub);
             }
             k0 += kc;
             kv0 = k0;

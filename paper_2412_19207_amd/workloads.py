@@ -364,8 +364,8 @@ def cfg4(**kw) -> Problem:
                 rhs_fn=lambda X: np.zeros(X.shape[0]),
                 bnd_fn=lambda X, k: gaussian_st(X, nu)[:, None].repeat(k, 1),
                 exact_fn=lambda X: gaussian_st(X, nu), probes_per_dim=[48, 48, 48],
-                meta=dict(pca_tol=1e-8, tol=1e-6, stencil="full", method="gmres",
-                          restart=50, precond="sas", precision="mixed"))
+                meta=dict(pca_tol=1e-8, tol=1e-6, stencil="face", method="gmres",
+                          restart=50, precond="ras", precision="mixed"))
     args.update(kw)
     return build_problem(**args)
 

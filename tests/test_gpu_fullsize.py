@@ -42,6 +42,7 @@ def _prob(name):
 def _oracle_pca(name):
     key = name + ":oracle"
     if key not in _cache:
+        print(f"{name}: oracle PCA ...", flush=True)
         prob = _prob(name)
         _cache[key] = oasm.assemble(prob, "rel_eig", prob.meta["pca_tol"])
     return _cache[key]
@@ -82,62 +83,91 @@ def _check_pca(prob, sysm, p, Vg, eig):
         off += m
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_cfg2_full_size_bench_configuration(precision):
-    """2D Poisson, 8x8 subdomains, width 300 (the benchmark workload)."""
-    _need_gpu()
-    prob = _prob("cfg2")
-    meta = prob.meta
-    sysm = _oracle_pca("cfg2")
-    s = _solver(prob, precision)
-    p = s.pca(meta["pca_tol"], "rel_eig")
-    Vg, eig = _gpu_basis(s, prob, p)
-    _check_pca(prob, sysm, p, Vg, eig)
-    F = torch.as_tensor(prob.F, device=DEV)
-    W, info = s.solve(F, tol=meta["tol"], method=meta["method"])
-    assert info["max_rel_residual"] <= meta["tol"]
-    Wn = W.cpu().numpy()
-    # the oracle's operator in the GPU's basis: W solves its normal equations
-    key = "cfg2:gpu-basis"
+def _per_rhs(a, b):
+    """Relative error of each column of a against b."""
+    nb = np.linalg.norm(b, axis=0)
+    return np.linalg.norm(a - b, axis=0) / np.where(nb > 0, nb, 1.0)
+
+
+def _oracle_in_gpu_basis(name, Vg, tol):
+    """The oracle's operator in the GPU's PCA basis and its block-sparse AS-PCG
+    solution (FP64, full stencil, restarted from the recomputed residual) to
+    the relative normal residual tol."""
+    key = f"{name}:gpu-basis-refined"
     if key not in _cache:
-        _cache[key] = oasm.assemble(prob, "rel_eig", meta["pca_tol"], V_force=Vg)
-    sysg = _cache[key]
-    res = osolve.normal_residual(obs.BlockH(sysg), Wn, sysg.Fs)
-    assert np.all(res <= meta["tol"] * 1.01 + 1e-9), res
-    # probe evaluation and raw-neuron coefficients
-    Xq = prob.probes
-    U = s.eval(torch.as_tensor(Xq, device=DEV), W).cpu().numpy()
-    Pm = oasm.probe_matrix(prob, sysg, Xq)
-    assert np.linalg.norm(U - Pm @ Wn) <= 1e-12 * np.linalg.norm(Pm @ Wn)
-    c = s.coeffs(W).cpu().numpy()
-    c_ref = sysg.coeffs(Wn)
-    assert np.linalg.norm(c - c_ref) <= 1e-12 * np.linalg.norm(c_ref)
-    s.close()
+        prob = _prob(name)
+        sysg = oasm.assemble(prob, "rel_eig", prob.meta["pca_tol"], V_force=Vg)
+        it = osolve.refined(prob, sysg, "full", "as", tol=tol)
+        _cache[key] = (sysg, it)
+    return _cache[key]
 
 
-def test_cfg3_full_size_batched_right_hand_sides():
-    """Multiscale 2D problem, 16x16 subdomains of uneven width, 32 right-hand
-    sides in one batched solve, mixed and FP64."""
-    _need_gpu()
-    prob = _prob("cfg3")
+def _full_size_parity(name, precisions, bars, gpu_tol=1e-10, floor=None):
+    """GPU solves to gpu_tol, or to stagnation at most `floor` when gpu_tol is
+    below the FP64 floor of the normal residual of these truncated systems,
+    against the oracle's PCG in the GPU's PCA basis (to 1e-10):
+    raw-neuron coefficients and u_h at the probes, per right-hand side; then
+    the configured tolerance, whose normal residual the oracle's operator
+    recomputes."""
+    prob = _prob(name)
     meta = prob.meta
-    sysm = _oracle_pca("cfg3")
+    sysm = _oracle_pca(name)
     F = torch.as_tensor(prob.F, device=DEV)
-    assert F.shape[1] == 32
-    sysg = None
-    for precision in ["mixed", "fp64"]:
+    Xq = torch.as_tensor(prob.probes, device=DEV)
+    ref = None
+    for precision in precisions:
         s = _solver(prob, precision)
         p = s.pca(meta["pca_tol"], "rel_eig")
-        if sysg is None:
+        if ref is None:
             Vg, eig = _gpu_basis(s, prob, p)
             _check_pca(prob, sysm, p, Vg, eig)
-            sysg = oasm.assemble(prob, "rel_eig", meta["pca_tol"], V_force=Vg)
+            print(f"{name}: PCA parity checked; oracle PCG in the GPU basis ...", flush=True)
+            sysg, it = _oracle_in_gpu_basis(name, Vg, 1e-10)
+            print(f"{name}: oracle PCG {it['iters'].max()} iterations, residual {it['res'].max():.2e}", flush=True)
+            assert np.all(it["res"] <= 1e-10 * 1.01), it["res"]
+            Pm = oasm.probe_matrix(prob, sysg, prob.probes)
+            ref = (sysg, Pm, sysg.coeffs(it["W"]), Pm @ it["W"])
+        sysg, Pm, c_ref, u_ref = ref
+        W, info = s.solve(F, tol=gpu_tol, method="cg", maxiter=5000)
+        if floor is None:
+            assert info["status"] == 0 and info["max_rel_residual"] <= gpu_tol, (info["status"], info["rel_residual"])
+        else:  # stagnation: ENOTCONV with every right-hand side at its floor
+            assert info["status"] in (0, binding.RANN_ENOTCONV) and info["max_rel_residual"] <= floor, \
+                (info["status"], info["rel_residual"])
+        c_gpu, U_gpu, Wn = s.coeffs(W).cpu().numpy(), s.eval(Xq, W).cpu().numpy(), W.cpu().numpy()
+        # the coefficient map and the probe evaluation of this same W (1e-12)
+        assert np.linalg.norm(c_gpu - sysg.coeffs(Wn)) <= 1e-12 * np.linalg.norm(c_gpu)
+        assert np.linalg.norm(U_gpu - Pm @ Wn) <= 1e-12 * np.linalg.norm(U_gpu)
+        ec = _per_rhs(c_gpu, c_ref)
+        eu = _per_rhs(U_gpu, u_ref)
+        print(f"{name} {precision}: k={F.shape[1]} P={int(s.info.P)} iterations {info['iterations']} "
+              f"residual max {info['max_rel_residual']:.1e} | "
+              f"coefficient error max {ec.max():.2e} median {np.median(ec):.2e} | "
+              f"u_h error max {eu.max():.2e} median {np.median(eu):.2e}")
+        assert ec.max() <= bars[precision] and eu.max() <= bars[precision], (ec, eu)
+        # the configured tolerance: the oracle's operator recomputes the residual
         W, info = s.solve(F, tol=meta["tol"], method=meta["method"])
-        assert info["max_rel_residual"] <= meta["tol"]
+        assert info["status"] == 0 and info["max_rel_residual"] <= meta["tol"]
         res = osolve.normal_residual(obs.BlockH(sysg), W.cpu().numpy(), sysg.Fs)
-        assert res.shape == (32,)
         assert np.all(res <= meta["tol"] * 1.01 + 1e-9), (precision, res)
         s.close()
+
+
+def test_cfg2_full_size_parity():
+    """2D Poisson, 8x8 subdomains, width 300, FP64 and mixed."""
+    _need_gpu()
+    _full_size_parity("cfg2", ["fp64", "mixed"], {"fp64": 1e-8, "mixed": 1e-6})
+
+
+def test_cfg3_full_size_parity_batched():
+    """Multiscale 2D problem, 16x16 subdomains of uneven width, the 32
+    right-hand sides in one batched solve, FP64 and mixed."""
+    _need_gpu()
+    assert _prob("cfg3").F.shape[1] == 32
+    # to stagnation: the GPU's floor of the normal residual is about 2e-10 for
+    # the f = 1 column and 3e-11 to 1e-10 for the sine series (the oracle's
+    # refined PCG: 3e-11)
+    _full_size_parity("cfg3", ["fp64", "mixed"], {"fp64": 1e-8, "mixed": 1e-6}, gpu_tol=1e-11, floor=3e-10)
 
 
 def _sampled_subproblem(prob, n_int, n_bnd, seed):
@@ -257,7 +287,8 @@ def test_semilinear_full_size_newton():
     # least-squares residual sets (here below 1e-3) takes over
     for k in range(2, len(inc) - 1):
         if inc[k] < 1e-2:
-            assert inc[k + 1] <= max(10.0 * inc[k] ** 2, 1e-3 * inc[k]), (k, inc)
+            # (below 1e-11 the increments are the linear solves' own noise, tol 1e-10)
+            assert inc[k + 1] <= max(10.0 * inc[k] ** 2, 1e-3 * inc[k], 1e-11), (k, inc)
     U = s.eval(torch.as_tensor(prob.probes, device=DEV), W)[:, 0].cpu().numpy()
     e = np.linalg.norm(U - prob.u_probe) / np.linalg.norm(prob.u_probe)
     assert e < 3e-2, e

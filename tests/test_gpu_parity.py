@@ -501,3 +501,106 @@ def test_power_of_two_rhs_reductions(method, k):
     for t in range(k):
         e = rel(Wn[:, t], ref["W"][:, t])
         assert e <= 1e-8, (t, e)
+
+
+# ------------------------------------------------------------------ 3D: 27-block stencils
+@pytest.fixture(scope="module")
+def case_small3d():
+    """3x3x3 subdomains of uneven width: the full stencil of the centre block
+    holds all 27 subdomains, the face stencil 7."""
+    _need_gpu()
+    prob = wl.small3d(l=(3, 3, 3), k=2)
+    ref = osolve.reference(prob, "rel_eig", 1e-10)
+    return prob, ref
+
+
+@pytest.mark.parametrize("stencil", ["face", "full"])
+@pytest.mark.parametrize("kind", ["as", "ras", "sas"])
+@pytest.mark.parametrize("k", [1, 16])
+def test_preconditioner_3d_matches_oracle(case_small3d, stencil, kind, k):
+    prob, ref = case_small3d
+    sysm, H = ref["sys"], ref["H"]
+    HtH = H.T @ H
+    sten = osw.stencil(prob, stencil)
+    if stencil == "full":
+        assert max(len(s) for s in sten) == 27
+    M = osw.schwarz_dense(HtH, sysm.col_off, sten, kind).dense()
+    s = binding.Solver(prob, device=DEV, stencil=stencil, precond=kind)
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    rng = np.random.default_rng(21)
+    r = rng.standard_normal((sysm.P, k))
+    kappa = np.linalg.cond(HtH)
+    z = s.apply_precond(torch.as_tensor(r, device=DEV)).cpu().numpy()
+    zt = s.apply_precond_T(torch.as_tensor(r, device=DEV)).cpu().numpy()
+    for t in range(k):
+        e = rel(z[:, t], (M @ r)[:, t])
+        et = rel(zt[:, t], (M.T @ r)[:, t])
+        assert e < max(1e-9, 1e-15 * kappa), (t, e, kappa)
+        assert et < max(1e-9, 1e-15 * kappa), (t, et, kappa)
+
+
+@pytest.mark.parametrize("method,kind,stencil", [("cg", "as", "full"), ("cg", "as", "face"),
+                                                 ("gmres", "ras", "full"), ("gmres_right", "sas", "full"),
+                                                 ("bicg", "ras", "face"), ("cgs", "sas", "full")])
+def test_solve_3d_matches_qr(case_small3d, method, kind, stencil):
+    prob, ref = case_small3d
+    sysm = ref["sys"]
+    s = binding.Solver(prob, device=DEV, stencil=stencil, precond=kind)
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-12, method=method, restart=50,
+                      maxiter=5000)
+    assert info["status"] == 0
+    assert info["max_rel_residual"] <= 1e-12
+    Wn = W.cpu().numpy()
+    errs = [rel(Wn[:, t], ref["W"][:, t]) for t in range(Wn.shape[1])]
+    print(f"3D {method}/{kind}/{stencil}: iterations {info['rhs_iterations']}, errors {errs}")
+    assert max(errs) <= 1e-8, errs
+
+
+# ------------------------------------------------------------------ local shift, rank tie
+def test_local_shift_counted_and_fit_unchanged():
+    """A dead neuron (zero weights and bias) with the PCA off makes H and every
+    local block holding it singular: the equilibrated Cholesky takes a
+    diagonal shift (counted in the stats), and CG still reaches the
+    least-squares fit H W of the live columns (Sec. 3, local inverse)."""
+    _need_gpu()
+    prob = wl.small2d(k=1)
+    prob.R[2][5] = 0.0
+    prob.b[2][5] = 0.0
+    sysm = oasm.assemble(prob, "off", 0.0)
+    H = sysm.dense()
+    live = np.abs(H).sum(axis=0) > 0
+    assert np.count_nonzero(~live) == 1
+    Wl, *_ = np.linalg.lstsq(H[:, live], sysm.Fs, rcond=None)
+    s = binding.Solver(prob, device=DEV)
+    s.pca(0.0, "off")
+    W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-10, maxiter=5000)
+    print(f"dead neuron: status {info['status']} shifts {info['shifts']} residual {info['max_rel_residual']:.2e}")
+    assert info["status"] == 0
+    assert info["shifts"] >= 1
+    fit = s.matvec(W).cpu().numpy()
+    # the fit is unique; at a normal residual of 1e-10 it is pinned to about
+    # kappa(H) 1e-10 (the raw features without PCA are ill-conditioned)
+    kappa = np.linalg.cond(H[:, live])
+    assert rel(fit, H[:, live] @ Wl) <= 10 * kappa * 1e-10, (rel(fit, H[:, live] @ Wl), kappa)
+
+
+def test_pca_rank_tie_status():
+    """A relative threshold placed on an eigenvalue of one subdomain's value
+    Gram returns RANN_WRANKTIE (outputs valid); moved by 0.1 % either way the
+    count changes by one and the status is 0 (Sec. 4 threshold)."""
+    _need_gpu()
+    prob = wl.small2d(k=1)
+    sysm = oasm.assemble(prob, "rel_eig", 1e-10)
+    j, kk = 3, 6
+    lam = sysm.lam[j]
+    tol = lam[kk] / lam[0]
+    s = binding.Solver(prob, device=DEV)
+    s.pca(tol, "rel_eig")
+    assert s.pca_status == binding.RANN_WRANKTIE
+    s2 = binding.Solver(prob, device=DEV)
+    p_hi = s2.pca(tol * (1 + 1e-3), "rel_eig")
+    assert s2.pca_status == 0 and p_hi[j] == kk
+    s3 = binding.Solver(prob, device=DEV)
+    p_lo = s3.pca(tol * (1 - 1e-3), "rel_eig")
+    assert s3.pca_status == 0 and p_lo[j] == kk + 1

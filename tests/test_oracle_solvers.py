@@ -495,3 +495,16 @@ def test_bicg_and_cgs_residuals_match_the_petrov_galerkin_polynomial(kind):
         # CGS may amplify the residual (squared polynomial): relative to it
         scale = max(nb, np.linalg.norm(want))
         assert np.linalg.norm(rc - want) <= 1e-6 * scale, (kind, k, np.linalg.norm(rc - want) / scale)
+
+
+def test_refined_pcg_reaches_the_qr_solution():
+    """AS-PCG restarted from the recomputed normal residual (the full-size
+    reference) lands on the QR least-squares solution, and with tol 0 stops at
+    the FP64 floor instead of iterating on."""
+    prob = wl.small2d(k=2)
+    ref = solve.reference(prob, "rel_eig", 1e-10)
+    r = solve.refined(prob, ref["sys"], tol=1e-13)
+    assert np.all(r["res"] <= 1e-13)
+    assert np.linalg.norm(r["W"] - ref["W"]) <= 1e-9 * np.linalg.norm(ref["W"])
+    r0 = solve.refined(prob, ref["sys"], tol=0.0, cycles=50)
+    assert len(r0["hist"]) < 50 and np.all(r0["res"] <= 1e-12)
