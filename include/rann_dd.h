@@ -232,6 +232,18 @@ RANN_API int rann_dd_matvec(rann_dd_handle* h, const double* x, int32_t k, doubl
 RANN_API int rann_dd_rmatvec(rann_dd_handle* h, const double* y, int32_t k, double* x);
 RANN_API int rann_dd_apply_normal(rann_dd_handle* h, const double* x, int32_t k, double* s);
 RANN_API int rann_dd_apply_precond(rann_dd_handle* h, const double* r, int32_t k, double* z);
+/* z = M^{-1} r as rann_dd_apply_precond computes it, without allocating device
+ * memory: for callers that cannot allocate (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  The local solves use a
+ * static device array of the library (32 MiB on every device the library runs
+ * on, held until the process ends) instead of allocated scratch; a problem that
+ * needs more ((2 sum_i q_i + 2 S) k doubles, S the slots of the row and column
+ * sums) returns RANN_EINVAL.  r, z device (P, k), k >= 1, not aliased.
+ * Asynchronous on the handle's stream (no synchronisation, no event).  Every call
+ * on one GPU shares that array and leaves its contents behind: calls that may
+ * overlap on one GPU (other streams, threads or handles) race and must be
+ * serialised by the caller. */
+RANN_API int rann_dd_apply_precond_noalloc(rann_dd_handle* h, const double* r, int32_t k, double* z);
 /* z = M^{-T} r, the transposed Schwarz preconditioner that BiCG's shadow
  * recurrence applies (Sec. 5, Table 1b): the weights D_i move from the local
  * results onto the restricted input, sum_i R_i^T A_i^{-1} D_i R_i r.  r, z

@@ -77,6 +77,8 @@ _SIGS = {
     "rann_dd_rmatvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rann_dd_apply_normal": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rann_dd_apply_precond": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "rann_dd_apply_precond_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                                     ctypes.c_void_p]),
     "rann_dd_apply_precond_T": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rann_dd_linearize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_int64, c_dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
@@ -188,6 +190,10 @@ def rann_dd_apply_normal(h, x_ptr, k, s_ptr):
 
 def rann_dd_apply_precond(h, r_ptr, k, z_ptr):
     return _check(load().rann_dd_apply_precond(h, ctypes.c_void_p(r_ptr), int(k), ctypes.c_void_p(z_ptr)))
+
+
+def rann_dd_apply_precond_noalloc(h, r_ptr, k, z_ptr):
+    return _check(load().rann_dd_apply_precond_noalloc(h, ctypes.c_void_p(r_ptr), int(k), ctypes.c_void_p(z_ptr)))
 
 
 def rann_dd_apply_precond_T(h, r_ptr, k, z_ptr):

@@ -46,7 +46,45 @@ void ktime_flush_locked() {
 }
 }  // namespace
 
-bool ktime_enabled() { return g_ktime_on.load(std::memory_order_relaxed) != 0; }
+// entry points that must not create events (the allocation-free apply) turn
+// the timers off for their own thread
+static thread_local int g_ktime_off = 0;
+
+bool ktime_enabled() { return g_ktime_off == 0 && g_ktime_on.load(std::memory_order_relaxed) != 0; }
+
+// ------------------------------------------------------------ static scratch
+// Device memory of the allocation-free apply: a file-scope array that every GPU
+// the library runs on holds until the process ends.  Host code never uses the
+// array's name as an address: its device address is looked up once per device
+// (with that device current) and kept in g_scratch_dev.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;  // per device; null until looked up
+}  // namespace
+
+// Looks up the current device's address of the scratch array (once per
+// device); called with `device` current.
+static int scratch_resolve(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0) return RANN_EDEVICE;
+    if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+    if (g_scratch_dev[device]) return RANN_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        return RANN_EDEVICE;
+    }
+    g_scratch_dev[device] = static_cast<double*>(ptr);
+    return RANN_OK;
+}
+
+static double* scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return (device >= 0 && device < (int)g_scratch_dev.size()) ? g_scratch_dev[device] : nullptr;
+}
 
 void ktime_record(const char* name, hipEvent_t a, hipEvent_t b) {
     std::lock_guard<std::mutex> lk(g_ktime_mu);
@@ -626,6 +664,13 @@ int rann_dd_assemble(const rann_dd_desc* desc, void* hip_stream, rann_dd_handle*
         }
         return rc;
     }
+    // the handle's device is current here: look up its scratch address once
+    rc = rdd::scratch_resolve(raw->device);
+    if (rc < 0) {
+        for (void* p : raw->allocs) (void)hipFree(p);
+        delete raw;
+        return rc;
+    }
     auto* hh = new rann_dd_handle();
     hh->h = std::move(*raw);
     delete raw;
@@ -785,6 +830,25 @@ int rann_dd_apply_precond(rann_dd_handle* hh, const double* r, int32_t k, double
     int rc = rdd::launch_precond(h, r, k, z, ub);
     if (rc == RANN_OK && hipStreamSynchronize(h.stream) != hipSuccess) rc = RANN_EDEVICE;
     rdd::dev_free(h, ub);
+    return rc;
+}
+
+int rann_dd_apply_precond_noalloc(rann_dd_handle* hh, const double* r, int32_t k, double* z) {
+    RDD_TRY(guard_handle(hh, true));
+    Handle& h = hh->h;
+    if (!r || !z || k < 1) return (rdd::set_error("invalid apply_precond_noalloc arguments"), RANN_EINVAL);
+    const size_t need = (size_t)std::max<int64_t>(2 * h.ub_total + 2 * h.slot_total, 1) * (size_t)k;
+    if (need * sizeof(double) > rdd::kScratchBytes) {
+        rdd::set_error("apply_precond_noalloc needs " + std::to_string(need * sizeof(double)) +
+                       " bytes of scratch, more than its static " + std::to_string(rdd::kScratchBytes) +
+                       "; use rann_dd_apply_precond or fewer right-hand sides");
+        return RANN_EINVAL;
+    }
+    double* ub = rdd::scratch_of(h.device);
+    if (!ub) return (rdd::set_error("the scratch address of this device was not looked up"), RANN_EDEVICE);
+    ++rdd::g_ktime_off;
+    const int rc = rdd::launch_precond(h, r, k, z, ub);
+    --rdd::g_ktime_off;
     return rc;
 }
 
