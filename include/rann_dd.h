@@ -139,6 +139,21 @@ typedef struct rann_dd_stats {
     double setup_ms[4];       /* assemble, pca, factor, (unused) phase times */
 } rann_dd_stats;
 
+/* Launch parameters of the Krylov step (rann_dd_autotune picks them by timing).
+ * tile_grid and use_graph change the speed only (bitwise the same results);
+ * red_cap also sets the summation order of the dot products (results agree to
+ * rounding). */
+typedef struct rann_dd_tuning {
+    int32_t tile_grid;        /* persistent workgroups of the FP64 local solves with one or two
+                                 right-hand sides (64..4096; default 768) */
+    int32_t red_cap;          /* most workgroups of the CG vector kernels (32..240; default 240)
+                                 (their per-workgroup dot-product partials are summed by every
+                                 consumer workgroup) */
+    int32_t use_graph;        /* 1: the launches of each CG check window are captured once into
+                                 a HIP graph and replayed (default); 0: launched one by one */
+    int32_t reserved;         /* 0 */
+} rann_dd_tuning;
+
 /* Layout sizes, for callers that allocate W, F and the diagnostic arrays. */
 typedef struct rann_dd_info {
     int32_t d, J;
@@ -151,6 +166,8 @@ typedef struct rann_dd_info {
     int32_t max_q;            /* largest Schwarz block */
     int32_t pca_done;
     int64_t normal_elems;     /* stored entries of the assembled normal matrix H^T H */
+    int32_t cg_graphs;        /* captured CG check-window graphs held by the handle */
+    int32_t graph_failed;     /* 1 when a capture failed (windows run eagerly since) */
 } rann_dd_info;
 
 /* Steps 1-3 of Algorithm 1 (paper Sec. 4): bin the points into the subdomain
@@ -250,6 +267,19 @@ RANN_API int rann_dd_apply_precond_noalloc(rann_dd_handle* h, const double* r, i
  * device (P, k), k >= 1, not aliased.  Equal to rann_dd_apply_precond for AS and
  * no preconditioner.  Synchronous. */
 RANN_API int rann_dd_apply_precond_T(rann_dd_handle* h, const double* r, int32_t k, double* z);
+
+/* Current launch parameters of a handle / replace them (RANN_EINVAL outside the
+ * stated ranges).  Host-only; no device work. */
+RANN_API int rann_dd_get_tuning(const rann_dd_handle* h, rann_dd_tuning* out);
+RANN_API int rann_dd_set_tuning(rann_dd_handle* h, const rann_dd_tuning* t);
+/* Autotuner of the Krylov step: times `iters` CG iterations with k right-hand
+ * sides (a fixed pseudo-random right-hand side, tolerance 0) for every candidate
+ * of tile_grid (FP64 with k <= 2 only), red_cap and use_graph, keeps the fastest
+ * on the handle and returns it in *best (host) with its time per iteration in
+ * *best_us (host, may be NULL).  Synchronous; needs rann_dd_pca; 1 <= k <= 256,
+ * 2 <= iters <= 1000. */
+RANN_API int rann_dd_autotune(rann_dd_handle* h, int32_t k, int32_t iters, rann_dd_tuning* best,
+                              double* best_us);
 
 /* Sizes; valid after rann_dd_assemble (P, nnz after rann_dd_pca). */
 RANN_API int rann_dd_get_info(const rann_dd_handle* h, rann_dd_info* out);

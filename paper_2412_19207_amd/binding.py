@@ -53,15 +53,28 @@ class Stats(ctypes.Structure):
                 ("setup_ms", ctypes.c_double * 4)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_grid", ctypes.c_int32), ("red_cap", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"tile_grid": self.tile_grid, "red_cap": self.red_cap, "use_graph": self.use_graph}
+
+
 class Info(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("J", ctypes.c_int32), ("N_int", ctypes.c_int64),
                 ("N_bnd", ctypes.c_int64), ("N", ctypes.c_int64), ("P", ctypes.c_int64),
                 ("pairs", ctypes.c_int64), ("nnz", ctypes.c_int64), ("sum_m", ctypes.c_int64),
                 ("factor_elems", ctypes.c_int64), ("max_q", ctypes.c_int32),
-                ("pca_done", ctypes.c_int32), ("normal_elems", ctypes.c_int64)]
+                ("pca_done", ctypes.c_int32), ("normal_elems", ctypes.c_int64),
+                ("cg_graphs", ctypes.c_int32), ("graph_failed", ctypes.c_int32)]
 
 
 _SIGS = {
+    "rann_dd_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "rann_dd_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "rann_dd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Tuning),
+                                        ctypes.POINTER(ctypes.c_double)]),
     "rann_dd_assemble": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "rann_dd_pca": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, c_ip, ctypes.c_void_p, c_ip]),
     "rann_dd_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
@@ -192,6 +205,23 @@ def rann_dd_apply_precond(h, r_ptr, k, z_ptr):
     return _check(load().rann_dd_apply_precond(h, ctypes.c_void_p(r_ptr), int(k), ctypes.c_void_p(z_ptr)))
 
 
+def rann_dd_get_tuning(h) -> Tuning:
+    t = Tuning()
+    _check(load().rann_dd_get_tuning(h, ctypes.byref(t)))
+    return t
+
+
+def rann_dd_set_tuning(h, t: Tuning):
+    return _check(load().rann_dd_set_tuning(h, ctypes.byref(t)))
+
+
+def rann_dd_autotune(h, k, iters):
+    t = Tuning()
+    us = ctypes.c_double(0.0)
+    _check(load().rann_dd_autotune(h, int(k), int(iters), ctypes.byref(t), ctypes.byref(us)))
+    return t, us.value
+
+
 def rann_dd_apply_precond_noalloc(h, r_ptr, k, z_ptr):
     return _check(load().rann_dd_apply_precond_noalloc(h, ctypes.c_void_p(r_ptr), int(k), ctypes.c_void_p(z_ptr)))
 
@@ -275,6 +305,7 @@ class Solver:
                  stream=None, c=None):
         import torch
         self.torch = torch
+        self.precision, self.stencil, self.precond = precision, stencil, precond
         self.dev = torch.device(device)
         self.prob = prob
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
@@ -369,6 +400,32 @@ class Solver:
                                     self._opts(tol, maxiter, method, restart, check_every),
                                     dF.data_ptr(), st)
         return dF, dict(status=rc, iterations=st.iterations)
+
+    # -- launch parameters
+    def graph_state(self):
+        """(captured CG window graphs held, 1 if a capture failed)."""
+        i = rann_dd_get_info(self.handle)
+        return int(i.cg_graphs), int(i.graph_failed)
+
+    def tuning(self):
+        return rann_dd_get_tuning(self.handle).as_dict()
+
+    def set_tuning(self, tile_grid=None, red_cap=None, use_graph=None):
+        t = rann_dd_get_tuning(self.handle)
+        if tile_grid is not None:
+            t.tile_grid = int(tile_grid)
+        if red_cap is not None:
+            t.red_cap = int(red_cap)
+        if use_graph is not None:
+            t.use_graph = int(bool(use_graph))
+        rann_dd_set_tuning(self.handle, t)
+
+    def autotune(self, k, iters=20, cache=True):
+        """Launch parameters of the Krylov step for k right-hand sides: from the
+        tuning cache when it holds this case, else timed by rann_dd_autotune and
+        stored there (paper_2412_19207_amd.autotune)."""
+        from . import autotune as at
+        return at.tune(self, k, iters=iters, use_cache=cache)
 
     # -- products and probes
     def matvec(self, x):

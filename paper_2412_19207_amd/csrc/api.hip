@@ -46,9 +46,9 @@ void ktime_flush_locked() {
 }
 }  // namespace
 
-// entry points that must not create events (the allocation-free apply) turn
-// the timers off for their own thread
-static thread_local int g_ktime_off = 0;
+// entry points and captures that must not create events turn the timers off
+// for their own thread (KTimeOff)
+thread_local int g_ktime_off = 0;
 
 bool ktime_enabled() { return g_ktime_off == 0 && g_ktime_on.load(std::memory_order_relaxed) != 0; }
 
@@ -833,6 +833,59 @@ int rann_dd_apply_precond(rann_dd_handle* hh, const double* r, int32_t k, double
     return rc;
 }
 
+int rann_dd_get_tuning(const rann_dd_handle* hh, rann_dd_tuning* out) {
+    RDD_TRY(guard_handle(hh, false));
+    if (!out) return (rdd::set_error("out is NULL"), RANN_EINVAL);
+    *out = hh->h.tune;
+    return RANN_OK;
+}
+
+int rann_dd_set_tuning(rann_dd_handle* hh, const rann_dd_tuning* t) {
+    RDD_TRY(guard_handle(hh, false));
+    if (!t || t->tile_grid < 64 || t->tile_grid > 4096 || t->red_cap < 32 || t->red_cap > 240 ||
+        (t->use_graph != 0 && t->use_graph != 1) || t->reserved != 0)
+        return (rdd::set_error("tuning outside its ranges (tile_grid 64..4096, red_cap 32..240, use_graph 0/1)"),
+                RANN_EINVAL);
+    hh->h.tune = *t;
+    return RANN_OK;
+}
+
+int rann_dd_autotune(rann_dd_handle* hh, int32_t k, int32_t iters, rann_dd_tuning* best, double* best_us) {
+    RDD_TRY(guard_handle(hh, true));
+    Handle& h = hh->h;
+    if (k < 1 || k > 256 || iters < 2 || iters > 1000 || !best)
+        return (rdd::set_error("invalid autotune arguments"), RANN_EINVAL);
+    double *rhs = nullptr, *W = nullptr;
+    RDD_TRY(rdd::dev_alloc(h, &rhs, (size_t)h.P * k));
+    int rc = rdd::dev_alloc(h, &W, (size_t)h.P * k);
+    const rann_dd_tuning start = h.tune;
+    // the persistent grid matters only for the FP64 local solves with 1 or 2
+    // right-hand sides
+    std::vector<int> grids{start.tile_grid};
+    if (h.precision == RANN_FP64 && k <= 2 && h.precond != RANN_PRECOND_NONE) grids = {256, 512, 768, 1024};
+    rann_dd_tuning win = start;
+    double win_us = 1e300;
+    for (int g : grids)
+        for (int cap : {64, 128, 240})
+            for (int gr : {0, 1}) {
+                if (rc != RANN_OK) break;
+                h.tune = rann_dd_tuning{g, cap, gr, 0};
+                double us = 0.0;
+                rc = rdd::time_cg_iterations(h, k, iters, rhs, W, &us);
+                if (rc == RANN_OK && us < win_us) {
+                    win_us = us;
+                    win = h.tune;
+                }
+            }
+    rdd::dev_free(h, rhs);
+    rdd::dev_free(h, W);
+    h.tune = (rc == RANN_OK) ? win : start;
+    RDD_TRY(rc);
+    *best = win;
+    if (best_us) *best_us = win_us;
+    return RANN_OK;
+}
+
 int rann_dd_apply_precond_noalloc(rann_dd_handle* hh, const double* r, int32_t k, double* z) {
     RDD_TRY(guard_handle(hh, true));
     Handle& h = hh->h;
@@ -846,10 +899,8 @@ int rann_dd_apply_precond_noalloc(rann_dd_handle* hh, const double* r, int32_t k
     }
     double* ub = rdd::scratch_of(h.device);
     if (!ub) return (rdd::set_error("the scratch address of this device was not looked up"), RANN_EDEVICE);
-    ++rdd::g_ktime_off;
-    const int rc = rdd::launch_precond(h, r, k, z, ub);
-    --rdd::g_ktime_off;
-    return rc;
+    rdd::KTimeOff no_timers;
+    return rdd::launch_precond(h, r, k, z, ub);
 }
 
 int rann_dd_linearize(rann_dd_handle* hh, const double* u, const double* c0, const double* f, int64_t n,
@@ -900,6 +951,9 @@ int rann_dd_get_info(const rann_dd_handle* hh, rann_dd_info* out) {
     out->max_q = h.max_q;
     out->pca_done = h.pca_done ? 1 : 0;
     out->normal_elems = h.N_elems;
+    out->cg_graphs = 0;
+    for (const auto& g : h.cg_graph) out->cg_graphs += g.exec ? 1 : 0;
+    out->graph_failed = h.graph_broken;
     return RANN_OK;
 }
 
@@ -938,6 +992,9 @@ size_t rann_dd_trim_cache(void) { return rdd::cache_trim_all(); }
 void rann_dd_destroy(rann_dd_handle* hh) {
     if (!hh) return;
     (void)hipStreamSynchronize(hh->h.stream);
+    for (auto& g : hh->h.cg_graph)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (hh->h.cap_stream) (void)hipStreamDestroy(hh->h.cap_stream);
     for (void* p : hh->h.allocs) rdd::cache_free(hh->h.device, p, hh->h.stream);
     hh->h.allocs.clear();
     for (auto& c : hh->h.stage) rdd::release_pinned(c.first);

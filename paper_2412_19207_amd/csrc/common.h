@@ -156,6 +156,18 @@ struct Handle {
 
     double setup_ms[4] = {0, 0, 0, 0};  // assemble, pca+factor host-clock times
 
+    // launch parameters chosen by the autotuner (rann_dd_autotune) or the caller
+    rann_dd_tuning tune{768, 240, 1, 0};
+    // executable graphs of CG check windows, keyed by what their launches bake in
+    struct CgGraph {
+        hipGraphExec_t exec = nullptr;
+        uint64_t key = 0;
+    };
+    CgGraph cg_graph[4];
+    int cg_graph_next = 0;
+    int graph_broken = 0;          // a capture failed once: eager launches from then on
+    hipStream_t cap_stream = nullptr;  // private stream the windows are captured on
+
     std::vector<void*> allocs;     // everything to free
 };
 
@@ -215,6 +227,20 @@ int ensure_ws(Handle& h, size_t bytes);
 // Optional per-kernel timing with HIP events on the launch stream (process-wide,
 // off by default): KTimer t(stream, "k_name"); <launch>; t.stop();
 bool ktime_enabled();
+// The timers are off on this thread while a KTimeOff lives (graph capture, the
+// allocation-free entry point: no events may be created or recorded there).
+extern thread_local int g_ktime_off;
+struct KTimeOff {
+    bool on;
+    explicit KTimeOff(bool b = true) : on(b) {
+        if (on) ++g_ktime_off;
+    }
+    ~KTimeOff() {
+        if (on) --g_ktime_off;
+    }
+    KTimeOff(const KTimeOff&) = delete;
+    KTimeOff& operator=(const KTimeOff&) = delete;
+};
 void ktime_record(const char* name, hipEvent_t a, hipEvent_t b);
 // Times the launches between construction and stop() with two events on the
 // stream.  With on_launch, the region is one launch that records the events
@@ -295,6 +321,7 @@ int krylov_lanczos(Handle& h, const double* rhs, const double* Fs, int k, const 
                    const rann_dd_solve_opts& o, double* W, rann_dd_stats* st, int* status);
 int true_residual(Handle& h, const double* Fs, const double* W, int k, double* out_host,
                   double* rhs_norm_host);
+int time_cg_iterations(Handle& h, int k, int iters, double* rhs, double* W, double* us_per_iter);
 int scale_boundary(Handle& h, const double* F, int k, double* Fs, double factor);
 int eval_points(Handle& h, const double* Xq, int64_t M, const double* Lq, const double* W,
                 int k, double* U, bool transpose);

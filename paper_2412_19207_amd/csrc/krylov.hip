@@ -821,14 +821,17 @@ int true_residual(Handle& h, const double* Fs, const double* W, int k, double* o
 // Preconditioned CG on H^T H W = rhs (rhs = H^T Fs, or dW for the adjoint).
 // Fs may be null (adjoint): then only the recurrence residual is checked.
 static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const double* W0,
-                   const rann_dd_solve_opts& o, double* W, std::vector<int>& iters_out,
+                   const rann_dd_solve_opts& o, double* Wout, std::vector<int>& iters_out,
                    std::vector<double>& res_out, int* status) {
     const size_t P = (size_t)h.P, N = (size_t)h.N;
-    const size_t need = P * k * 5 + N * k + (size_t)h.part_total * k + (size_t)(2 * h.ub_total + 2 * h.slot_total) * k +
+    const size_t need = P * k * 6 + N * k + (size_t)h.part_total * k + (size_t)(2 * h.ub_total + 2 * h.slot_total) * k +
                         (size_t)kDotBlocks * k + 2 * (size_t)kRedMax * k + (size_t)h.n_slab_tasks * k + 24 * (size_t)k +
                         2048;
     RDD_TRY(ensure_ws(h, need * sizeof(double)));
     Scratch sc{static_cast<double*>(h.ws), 0};
+    // the iterate lives in the workspace (so that a captured check window does
+    // not depend on the caller's buffer) and is copied out at the end
+    double* W = sc.take(P * k);
     double* r = sc.take(P * k);
     double* z = sc.take(P * k);
     double* pbuf[2];  // the direction, double-buffered (see the loop)
@@ -860,7 +863,8 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     int par = 0;
     int32_t* active = activeB;  // current buffer, follows par
     const int64_t Pk = (int64_t)P * k;
-    const unsigned rgrid = (unsigned)red_grid(Pk);  // workgroups of the element-wise kernels
+    // workgroups of the element-wise kernels
+    const unsigned rgrid = (unsigned)std::min(red_grid(Pk), std::max(32, (int)h.tune.red_cap));
 
     RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, h.stream));
     RDD_HIP(hipMemsetAsync(iters, 0, sizeof(int32_t) * k, h.stream));
@@ -899,40 +903,106 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     int replacements = 0, stalls = 0;
     double best_true = 1e300;
     *status = RANN_OK;
-    while (true) {
-        for (int q = 0; q < every && it < o.maxiter; ++q, ++it) {
-            double* rho_in = rhoB + (size_t)par * k;
-            double* rho_out = rhoB + (size_t)(par ^ 1) * k;
-            int32_t* act_in = activeB + (size_t)par * k;
-            int32_t* act_out = activeB + (size_t)(par ^ 1) * k;
-            // s = H^T H p (assembled normal matrix) and partials of <p, s>.
-            // Inside a check window the previous iteration's direction update
-            // p = z + beta p and its bookkeeping ride on this product (into
-            // the other direction buffer); the window's last iteration does
-            // them itself, so the host always sees a finished iteration.
-            if (q > 0) {
-                const size_t pq = (size_t)(par ^ 1) * k;  // the previous iteration's state
-                const PUpd pu{pbuf[pc], z, pbuf[pc ^ 1], partB, partC, (int)rgrid, bn2, tol2v,
-                              rhoB + pq, rho_in, activeB + pq, act_in, iters, rres};
-                RDD_TRY(launch_normal(h, pbuf[pc], k, s, partA, &pu));
-                pc ^= 1;
-            } else {
-                RDD_TRY(launch_normal(h, pbuf[pc], k, s, partA));
-            }
-            double* p = pbuf[pc];
-            hipLaunchKernelGGL(k_cg_xr2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k,
-                               (int)h.n_slab_tasks, partA, rho_in, act_in, p, s, W, r, partB, flags);
-            // z = M^{-1} r and partials of <r, z>
-            const int ident = (h.precond == RANN_PRECOND_NONE) ? 1 : 0;
-            if (!ident) RDD_TRY(launch_precond_local(h, h.ap, r, k, ub));
-            hipLaunchKernelGGL(k_gather_dot, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, ident,
-                               h.ap.d_gat_off, h.ap.d_gat, h.ap.d_gat_w, ub, r, z, partC);
-            if (q + 1 == every || it + 1 >= o.maxiter)
-                hipLaunchKernelGGL(k_cg_p2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, (int)rgrid, partB,
-                                   partC, bn2, tol2v, rho_in, rho_out, act_in, act_out, iters, rres, z, p);
-            par ^= 1;
-            active = activeB + (size_t)par * k;
+    const int ident = (h.precond == RANN_PRECOND_NONE) ? 1 : 0;
+    // the launches of iteration q of a check window of nq iterations (device
+    // work only, so that a window can be captured into a graph)
+    auto launch_iter = [&](int q, int nq) -> int {
+        double* rho_in = rhoB + (size_t)par * k;
+        double* rho_out = rhoB + (size_t)(par ^ 1) * k;
+        int32_t* act_in = activeB + (size_t)par * k;
+        int32_t* act_out = activeB + (size_t)(par ^ 1) * k;
+        // s = H^T H p (assembled normal matrix) and partials of <p, s>.
+        // Inside a check window the previous iteration's direction update
+        // p = z + beta p and its bookkeeping ride on this product (into
+        // the other direction buffer); the window's last iteration does
+        // them itself, so the host always sees a finished iteration.
+        if (q > 0) {
+            const size_t pq = (size_t)(par ^ 1) * k;  // the previous iteration's state
+            const PUpd pu{pbuf[pc], z, pbuf[pc ^ 1], partB, partC, (int)rgrid, bn2, tol2v,
+                          rhoB + pq, rho_in, activeB + pq, act_in, iters, rres};
+            RDD_TRY(launch_normal(h, pbuf[pc], k, s, partA, &pu));
+            pc ^= 1;
+        } else {
+            RDD_TRY(launch_normal(h, pbuf[pc], k, s, partA));
         }
+        double* p = pbuf[pc];
+        hipLaunchKernelGGL(k_cg_xr2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k,
+                           (int)h.n_slab_tasks, partA, rho_in, act_in, p, s, W, r, partB, flags);
+        // z = M^{-1} r and partials of <r, z>
+        if (!ident) RDD_TRY(launch_precond_local(h, h.ap, r, k, ub));
+        hipLaunchKernelGGL(k_gather_dot, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, ident,
+                           h.ap.d_gat_off, h.ap.d_gat, h.ap.d_gat_w, ub, r, z, partC);
+        if (q + 1 == nq)
+            hipLaunchKernelGGL(k_cg_p2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, (int)rgrid, partB,
+                               partC, bn2, tol2v, rho_in, rho_out, act_in, act_out, iters, rres, z, p);
+        par ^= 1;
+        return RANN_OK;
+    };
+    int window = 0;
+    while (true) {
+        const int nq = std::min(every, o.maxiter - it);
+        // with the kernel timers on, one window in four runs eagerly with its
+        // timers; the others run without timers (from the graph when allowed),
+        // so that the timers' events do not slow the timed solve down
+        const bool sampled = ktime_enabled() && (window++ % 4 == 0);
+        KTimeOff quiet_window(!sampled);
+        // a full window replays a captured graph of its launches when the
+        // handle allows it: the launches depend only on the workspace, the
+        // sizes, the launch parameters and the parities of the two double
+        // buffers at the window's start
+        hipGraphExec_t ex = nullptr;
+        if (!sampled && h.tune.use_graph && !h.graph_broken && nq == every && nq > 0) {
+            uint64_t key = 1469598103934665603ULL;
+            const uint64_t parts[] = {(uint64_t)(uintptr_t)h.ws, (uint64_t)k, (uint64_t)nq, (uint64_t)par,
+                                      (uint64_t)pc, (uint64_t)h.tune.tile_grid, (uint64_t)rgrid, (uint64_t)P};
+            for (uint64_t v : parts) key = (key ^ v) * 1099511628211ULL;
+            for (auto& g : h.cg_graph)
+                if (g.exec && g.key == key) ex = g.exec;
+            if (!ex) {
+                const int par0 = par, pc0 = pc;
+                KTimeOff no_timers;
+                int rc = RANN_OK;
+                hipGraph_t graph = nullptr;
+                // captured on a private stream (the handle's may be the null
+                // stream, which cannot be captured); replayed on the handle's
+                if (!h.cap_stream && hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking) != hipSuccess)
+                    h.cap_stream = nullptr;
+                const hipStream_t own = h.stream;
+                if (h.cap_stream && hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                    h.stream = h.cap_stream;
+                    for (int q = 0; q < nq && rc == RANN_OK; ++q) rc = launch_iter(q, nq);
+                    h.stream = own;
+                    const hipError_t e = hipStreamEndCapture(h.cap_stream, &graph);
+                    if (rc == RANN_OK && e == hipSuccess && graph &&
+                        hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess)
+                        ex = nullptr;
+                    if (graph) (void)hipGraphDestroy(graph);
+                }
+                h.stream = own;
+                par = par0;  // the captured launches have not run
+                pc = pc0;
+                if (ex) {
+                    auto& slot = h.cg_graph[h.cg_graph_next];
+                    h.cg_graph_next = (h.cg_graph_next + 1) % 4;
+                    if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+                    slot.exec = ex;
+                    slot.key = key;
+                } else {
+                    h.graph_broken = 1;  // eager launches from now on
+                    (void)hipGetLastError();
+                }
+            }
+        }
+        if (ex) {
+            RDD_HIP(hipGraphLaunch(ex, h.stream));
+            // the state of the double buffers after the window's iterations
+            par ^= (nq & 1);
+            pc ^= ((nq - 1) & 1);
+        } else {
+            for (int q = 0; q < nq; ++q) RDD_TRY(launch_iter(q, nq));
+        }
+        it += nq;
+        active = activeB + (size_t)par * k;
         RDD_HIP(hipGetLastError());
         int32_t fl[4];
         RDD_TRY(download(h, act.data(), active, sizeof(int32_t) * k));
@@ -1003,12 +1073,56 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
             break;
         }
     }
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, W, Wout);
     RDD_TRY(download(h, ith.data(), iters, sizeof(int32_t) * k));
     std::vector<double> rrh(k);
     RDD_TRY(download(h, rrh.data(), rres, sizeof(double) * k));
     RDD_HIP(hipStreamSynchronize(h.stream));
     iters_out.assign(ith.begin(), ith.end());
     res_out = rrh;
+    return RANN_OK;
+}
+
+namespace {
+// x[i] = a pseudo-random value in [-1, 1) from a 64-bit mix of i (SplitMix64)
+__global__ void k_fill_mix(int64_t n, double* __restrict__ x) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ULL + 0x632BE59BD9B4E019ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+}  // namespace
+
+// Time of `iters` CG iterations with k right-hand sides under the handle's
+// current launch parameters (tolerance 0, a fixed pseudo-random right-hand
+// side; rhs and W: P k device scratch); the first run (graph capture, caches)
+// is not timed.
+int time_cg_iterations(Handle& h, int k, int iters, double* rhs, double* W, double* us_per_iter) {
+    const int64_t Pk = h.P * (int64_t)k;
+    hipLaunchKernelGGL(k_fill_mix, dim3(grid_for(Pk)), dim3(256), 0, h.stream, Pk, rhs);
+    RDD_HIP(hipGetLastError());
+    rann_dd_solve_opts o{0.0, iters, RANN_METHOD_CG, 0, std::min(10, iters)};
+    std::vector<int> its;
+    std::vector<double> res;
+    int status = 0;
+    RDD_TRY(cg_core(h, rhs, nullptr, k, nullptr, o, W, its, res, &status));
+    hipEvent_t a, b;
+    RDD_HIP(hipEventCreate(&a));
+    RDD_HIP(hipEventCreate(&b));
+    (void)hipEventRecord(a, h.stream);
+    const int rc = cg_core(h, rhs, nullptr, k, nullptr, o, W, its, res, &status);
+    (void)hipEventRecord(b, h.stream);
+    float ms = 0.0f;
+    const hipError_t e = hipEventSynchronize(b);
+    if (e == hipSuccess) (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    RDD_TRY(rc);
+    RDD_HIP(e);
+    *us_per_iter = 1e3 * (double)ms / iters;
     return RANN_OK;
 }
 

@@ -1030,9 +1030,9 @@ int launch_precond_local(Handle& h, const ApplyPlan& pl, const double* r, int k,
                 default: RDD_TR(1); break;
             }
         } else if (kb <= 2) {
-            // persistent over three workgroups per compute unit (its register
-            // budget admits three waves per SIMD)
-            const unsigned pg = std::min<unsigned>(tgrid, 768u);
+            // persistent over tune.tile_grid workgroups (default 768: three per
+            // compute unit, which its register budget admits)
+            const unsigned pg = std::min<unsigned>(tgrid, (unsigned)h.tune.tile_grid);
             hipEvent_t ea = one_launch ? kt_.a : nullptr, eb = one_launch ? kt_.b : nullptr;
             if (kb == 2)
                 hipExtLaunchKernelGGL((k_tile_apply_ps<2>), dim3(pg), dim3(256), 0, h.stream, ea, eb, 0,
