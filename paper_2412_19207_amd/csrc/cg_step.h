@@ -66,8 +66,9 @@ struct PUpd {
     const double* z;         // preconditioned residual
     double* pcur;            // p of this iteration (rows of the product's own slab rows)
     const double* partB;     // partials of <r, r>  (nB workgroups)
-    const double* partC;     // partials of <r, z>
+    const double* partC;     // partials of <r, z>  (nC workgroups)
     int nB;
+    int nC;
     const double* bn2;       // ||rhs||^2
     const double* tol2;      // tolerance^2
     const double* rho_in;    // rho of the previous iteration
@@ -82,7 +83,7 @@ struct PUpd {
 // beta_s / act_s (shared); workgroup 0 also writes the bookkeeping
 __device__ inline void pupd_begin(const PUpd& u, int k, int k0, int kb, double* beta_s, int* act_s, double* rz_s,
                                   double* rr_s, double* sh) {
-    sum_partials_kb(u.partC, u.nB, k, k0, kb, rz_s, sh);
+    sum_partials_kb(u.partC, u.nC, k, k0, kb, rz_s, sh);
     if (blockIdx.x == 0) sum_partials_kb(u.partB, u.nB, k, k0, kb, rr_s, sh);
     if (threadIdx.x < kb) {
         const int t = k0 + threadIdx.x;

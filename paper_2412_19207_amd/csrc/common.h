@@ -59,6 +59,11 @@ struct ApplyPlan {
     int64_t* d_gat_off = nullptr;  // P+1
     int64_t* d_gat = nullptr;      // entries
     double* d_gat_w = nullptr;     // weights (AS 1, SAS 1/mult, RAS 1 on owned entries only)
+    // the same sum by subdomain: the columns of subdomain j are the weighted sum
+    // of contiguous segments of the block results (one per block that uses j)
+    int64_t* d_seg_off = nullptr;  // J+1
+    int64_t* d_seg_src = nullptr;  // first block entry of each segment
+    double* d_seg_w = nullptr;     // its weight
 };
 
 struct Handle {
@@ -300,6 +305,11 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part, co
 int launch_Hx(Handle& h, const double* x, int k, double* y, bool scale_bnd);
 int launch_HTy(Handle& h, const double* y, int k, double* x, double* partial);
 int launch_precond(Handle& h, const double* r, int k, double* z, double* ub);
+// z = sum of the weighted local results of plan pl by subdomain segments and,
+// with part, the partials of <r, z> (gather_parts(h, k) workgroups)
+int launch_gather(Handle& h, const ApplyPlan& pl, const double* ub, const double* r, int k, double* z,
+                  double* part);
+int gather_parts(const Handle& h, int k);
 // z = M^{-T} r; tmp: (P + 1) k scratch
 int launch_precond_T(Handle& h, const double* r, int k, double* z, double* ub, double* tmp);
 // ub: (2 ub_total + 2 slot_total) k doubles of scratch

@@ -451,7 +451,7 @@ __device__ inline int64_t rhs_stride(int k) { return ((int64_t)gridDim.x * 256 /
 // Per-workgroup partial sums by right-hand side, fixed-order tree.  The grid
 // stride is a multiple of k, so thread x of block b always handles RHS
 // t = (b * 256 + x) % k; threads are grouped by that t.
-__device__ void block_partial_by_rhs(double val, int k, double* sh, double* out) {
+__device__ void block_partial_by_rhs(double val, int k, double* sh, double* out, int base_override = -1) {
     if (k == 1) {  // a butterfly over each wave, then the four waves
         double w = val;
         for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
@@ -465,7 +465,7 @@ __device__ void block_partial_by_rhs(double val, int k, double* sh, double* out)
     __syncthreads();
     // general k: thread x with e = x belongs to t(e) = (base + e) % k; sum the
     // entries of each t along e = e0, e0 + k, ... with a pairwise tree
-    const int base = (int)(((int64_t)blockIdx.x * 256) % k);
+    const int base = base_override >= 0 ? base_override : (int)(((int64_t)blockIdx.x * 256) % k);
     const int groups = (256 + k - 1) / k;  // entries per t (at most)
     for (int st = 1; st < groups; st <<= 1) {
         const int e = threadIdx.x;
@@ -629,9 +629,54 @@ __global__ void __launch_bounds__(256) k_gather_dot(int64_t P, int k, int identi
     block_partial_by_rhs(acc, k, sh, partC);
 }
 
+// The Schwarz sum by subdomain: the p_j k entries of z that belong to subdomain
+// j are the weighted sum of contiguous segments of the block results, one per
+// block that uses j (in block order, as the gather lists add them).
+// Workgroup (j, y) of a grid of J Y takes the entries [y E, (y + 1) E) of
+// subdomain j with E = 4 L, L = (256 / k) k: thread x < L the entries
+// y E + x + L v, v < 4, all of right-hand side x % k.  With part, the
+// workgroup's partials of <r, z> go to part[(j Y + y) k + t].
+__global__ void __launch_bounds__(256) k_gather_seg(int k, int Y, const int32_t* __restrict__ pv,
+                                                    const int64_t* __restrict__ col_off,
+                                                    const int64_t* __restrict__ seg_off,
+                                                    const int64_t* __restrict__ seg_src,
+                                                    const double* __restrict__ seg_w,
+                                                    const double* __restrict__ u, const double* __restrict__ r,
+                                                    double* __restrict__ z, double* __restrict__ part) {
+    __shared__ double sh[256];
+    const int j = blockIdx.x / Y, y = blockIdx.x % Y;
+    const int L = (256 / k) * k;
+    const int64_t n = (int64_t)pv[j] * k;
+    const int64_t s0 = seg_off[j], s1 = seg_off[j + 1];
+    const int64_t zb = col_off[j] * k;
+    double acc = 0.0;
+    if (threadIdx.x < L) {
+        const int64_t e0 = (int64_t)y * 4 * L + threadIdx.x;
+        double zv[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t q = s0; q < s1; ++q) {
+            const double w = seg_w[q];
+            const double* us = u + seg_src[q] * k;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t e = e0 + (int64_t)L * v;
+                if (e < n) zv[v] += w * us[e];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t e = e0 + (int64_t)L * v;
+            if (e < n) {
+                z[zb + e] = zv[v];
+                if (part) acc = fma(r[zb + e], zv[v], acc);
+            }
+        }
+    }
+    if (part) block_partial_by_rhs(acc, k, sh, part, 0);
+}
+
 // beta = <r,z> / rho, rho and activity update (workgroup 0 writes the state of
 // the next iteration into the other buffer), p = z + beta p
-__global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, int nB, const double* __restrict__ partB,
+__global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, int nB, int nC, const double* __restrict__ partB,
                                                const double* __restrict__ partC,
                                                const double* __restrict__ bn2,
                                                const double* __restrict__ tol2,
@@ -645,7 +690,7 @@ __global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, int nB, const d
     __shared__ double rr[256];
     __shared__ double rz[256];
     sum_partials(partB, nB, k, rr, sh);
-    sum_partials(partC, nB, k, rz, sh);
+    sum_partials(partC, nC, k, rz, sh);
     if (threadIdx.x < k) {
         const int t = threadIdx.x;
         const int act = active_in[t];
@@ -684,6 +729,25 @@ inline int kb_for(int rem) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+static int gather_rows(const Handle& h, int k) {
+    int pmax = 1;
+    for (int pj : h.p) pmax = std::max(pmax, pj);
+    const int64_t E = 4LL * ((256 / k) * k);
+    return (int)std::max<int64_t>(1, ((int64_t)pmax * k + E - 1) / E);
+}
+
+int gather_parts(const Handle& h, int k) { return h.geo.J * gather_rows(h, k); }
+
+int launch_gather(Handle& h, const ApplyPlan& pl, const double* ub, const double* r, int k, double* z,
+                  double* part) {
+    if (k < 1 || k > 256) return RANN_EINVAL;
+    const int Y = gather_rows(h, k);
+    hipLaunchKernelGGL(k_gather_seg, dim3((unsigned)(h.geo.J * Y)), dim3(256), 0, h.stream, k, Y, h.d_p,
+                       h.d_col_off, pl.d_seg_off, pl.d_seg_src, pl.d_seg_w, ub, r, z, part);
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
 int launch_Hx_pairs(Handle& h, const double* x, int k, double* y, double* tpair);
 int launch_HTy_part(Handle& h, const double* y, int k, double* part);
 
@@ -825,8 +889,8 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
                    std::vector<double>& res_out, int* status) {
     const size_t P = (size_t)h.P, N = (size_t)h.N;
     const size_t need = P * k * 6 + N * k + (size_t)h.part_total * k + (size_t)(2 * h.ub_total + 2 * h.slot_total) * k +
-                        (size_t)kDotBlocks * k + 2 * (size_t)kRedMax * k + (size_t)h.n_slab_tasks * k + 24 * (size_t)k +
-                        2048;
+                        (size_t)kDotBlocks * k + (size_t)(kRedMax + std::max(kRedMax, gather_parts(h, k))) * k +
+                        (size_t)h.n_slab_tasks * k + 24 * (size_t)k + 2048;
     RDD_TRY(ensure_ws(h, need * sizeof(double)));
     Scratch sc{static_cast<double*>(h.ws), 0};
     // the iterate lives in the workspace (so that a captured check window does
@@ -855,7 +919,8 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     double* rhoB = sc.take(2 * (size_t)k);       // rho, double-buffered
     double* partA = sc.take((size_t)std::max<int64_t>(1, h.n_slab_tasks) * k);
     double* partB = sc.take((size_t)kRedMax * k);
-    double* partC = sc.take((size_t)kRedMax * k);
+    const int nC = (h.precond == RANN_PRECOND_NONE) ? 0 : gather_parts(h, k);  // 0: rgrid partials
+    double* partC = sc.take((size_t)std::max(kRedMax, nC) * k);
     int32_t* activeB = reinterpret_cast<int32_t*>(sc.take(2 * (size_t)k));  // activity, double-buffered
     int32_t* iters = reinterpret_cast<int32_t*>(sc.take(k));
     int32_t* flags = reinterpret_cast<int32_t*>(sc.take(4));
@@ -865,6 +930,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     const int64_t Pk = (int64_t)P * k;
     // workgroups of the element-wise kernels
     const unsigned rgrid = (unsigned)std::min(red_grid(Pk), std::max(32, (int)h.tune.red_cap));
+    const int nCp = nC > 0 ? nC : (int)rgrid;  // partials of <r, z>
 
     RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, h.stream));
     RDD_HIP(hipMemsetAsync(iters, 0, sizeof(int32_t) * k, h.stream));
@@ -918,7 +984,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
         // them itself, so the host always sees a finished iteration.
         if (q > 0) {
             const size_t pq = (size_t)(par ^ 1) * k;  // the previous iteration's state
-            const PUpd pu{pbuf[pc], z, pbuf[pc ^ 1], partB, partC, (int)rgrid, bn2, tol2v,
+            const PUpd pu{pbuf[pc], z, pbuf[pc ^ 1], partB, partC, (int)rgrid, nCp, bn2, tol2v,
                           rhoB + pq, rho_in, activeB + pq, act_in, iters, rres};
             RDD_TRY(launch_normal(h, pbuf[pc], k, s, partA, &pu));
             pc ^= 1;
@@ -929,11 +995,15 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
         hipLaunchKernelGGL(k_cg_xr2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k,
                            (int)h.n_slab_tasks, partA, rho_in, act_in, p, s, W, r, partB, flags);
         // z = M^{-1} r and partials of <r, z>
-        if (!ident) RDD_TRY(launch_precond_local(h, h.ap, r, k, ub));
-        hipLaunchKernelGGL(k_gather_dot, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, ident,
-                           h.ap.d_gat_off, h.ap.d_gat, h.ap.d_gat_w, ub, r, z, partC);
+        if (!ident) {
+            RDD_TRY(launch_precond_local(h, h.ap, r, k, ub));
+            RDD_TRY(launch_gather(h, h.ap, ub, r, k, z, partC));
+        } else {
+            hipLaunchKernelGGL(k_gather_dot, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, ident,
+                               h.ap.d_gat_off, h.ap.d_gat, h.ap.d_gat_w, ub, r, z, partC);
+        }
         if (q + 1 == nq)
-            hipLaunchKernelGGL(k_cg_p2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, (int)rgrid, partB,
+            hipLaunchKernelGGL(k_cg_p2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, (int)rgrid, nCp, partB,
                                partC, bn2, tol2v, rho_in, rho_out, act_in, act_out, iters, rres, z, p);
         par ^= 1;
         return RANN_OK;

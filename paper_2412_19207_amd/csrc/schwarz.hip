@@ -824,6 +824,40 @@ static int build_plan(Handle& h, const std::vector<int64_t>& ub_off, const std::
         gat[slot] = e;
         gat_w[slot] = (!masked && h.precond == RANN_PRECOND_SAS) ? 1.0 / (double)mult[gcol] : 1.0;
     }
+    // segments: block i's entries of subdomain j, when used, in block order per j
+    {
+        std::vector<std::vector<std::pair<int64_t, double>>> segs(J);
+        for (int i = 0; i < J; ++i) {
+            int64_t e = ub_off[i];
+            for (int j : h.sten[i]) {
+                if (h.p[j] > 0 && used[e])
+                    segs[j].push_back({e, (!masked && h.precond == RANN_PRECOND_SAS)
+                                              ? 1.0 / (double)mult[h.col_off[j]] : 1.0});
+                e += h.p[j];
+            }
+        }
+        std::vector<int64_t> seg_off(J + 1, 0), seg_src;
+        std::vector<double> seg_w;
+        for (int j = 0; j < J; ++j) {
+            std::sort(segs[j].begin(), segs[j].end(),
+                      [](const std::pair<int64_t, double>& x, const std::pair<int64_t, double>& y) {
+                          return x.first < y.first;
+                      });
+            for (auto& sg : segs[j]) {
+                seg_src.push_back(sg.first);
+                seg_w.push_back(sg.second);
+            }
+            seg_off[j + 1] = (int64_t)seg_src.size();
+        }
+        RDD_TRY(dev_alloc(h, &pl.d_seg_off, seg_off.size()));
+        RDD_TRY(dev_alloc(h, &pl.d_seg_src, std::max<size_t>(seg_src.size(), 1)));
+        RDD_TRY(dev_alloc(h, &pl.d_seg_w, std::max<size_t>(seg_w.size(), 1)));
+        RDD_TRY(upload(h, pl.d_seg_off, seg_off.data(), sizeof(int64_t) * seg_off.size()));
+        if (!seg_src.empty()) {
+            RDD_TRY(upload(h, pl.d_seg_src, seg_src.data(), sizeof(int64_t) * seg_src.size()));
+            RDD_TRY(upload(h, pl.d_seg_w, seg_w.data(), sizeof(double) * seg_w.size()));
+        }
+    }
     RDD_TRY(dev_alloc(h, &pl.d_blk_cols, blk_cols.size()));
     RDD_TRY(dev_alloc(h, &pl.d_gat_off, gat_off.size()));
     RDD_TRY(dev_alloc(h, &pl.d_gat, gat.size()));
@@ -1075,11 +1109,7 @@ int launch_precond(Handle& h, const double* r, int k, double* z, double* ub) {
         return RANN_OK;
     }
     RDD_TRY(launch_precond_local(h, h.ap, r, k, ub));
-    const int64_t tot = h.P * k;
-    hipLaunchKernelGGL(k_gather_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, h.stream,
-                       h.P, k, h.ap.d_gat_off, h.ap.d_gat, h.ap.d_gat_w, ub, z);
-    RDD_HIP(hipGetLastError());
-    return RANN_OK;
+    return launch_gather(h, h.ap, ub, nullptr, k, z, nullptr);
 }
 
 // z = M^{-T} r.  The local inverses are symmetric, so the transpose moves the
@@ -1096,10 +1126,7 @@ int launch_precond_T(Handle& h, const double* r, int k, double* z, double* ub, d
         const unsigned g1 = (unsigned)((tot + k + 255) / 256);
         hipLaunchKernelGGL(k_copy_pad, dim3(g1), dim3(256), 0, h.stream, tot, (int64_t)k, r, tmp);
         RDD_TRY(launch_precond_local(h, h.apT, tmp, k, ub));
-        hipLaunchKernelGGL(k_gather_sum, dim3(g), dim3(256), 0, h.stream, h.P, k, h.apT.d_gat_off, h.apT.d_gat,
-                           (const double*)nullptr, ub, z);
-        RDD_HIP(hipGetLastError());
-        return RANN_OK;
+        return launch_gather(h, h.apT, ub, nullptr, k, z, nullptr);
     }
     hipLaunchKernelGGL(k_div_count, dim3(g), dim3(256), 0, h.stream, h.P, k, h.ap.d_gat_off, r, tmp);
     RDD_TRY(launch_precond_local(h, h.ap, tmp, k, ub));
