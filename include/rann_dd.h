@@ -151,7 +151,12 @@ typedef struct rann_dd_tuning {
                                  consumer workgroup) */
     int32_t use_graph;        /* 1: the launches of each CG check window are captured once into
                                  a HIP graph and replayed (default); 0: launched one by one */
-    int32_t reserved;         /* 0 */
+    int32_t pca_subspace;     /* 1 (default): rann_dd_pca finds the leading eigenvectors by
+                                 subspace iteration (blocks of 64) when every hidden width is at
+                                 least 128 and some width exceeds 480, and returns to the direct
+                                 solver when a subdomain keeps more than 48 eigenvectors; 0: the
+                                 direct tridiagonal eigensolver.  Set before rann_dd_pca.  With
+                                 the subspace path the eigenvalues past each block are NaN. */
 } rann_dd_tuning;
 
 /* Layout sizes, for callers that allocate W, F and the diagnostic arrays. */

@@ -529,7 +529,19 @@ static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, con
         RDD_TRY(upload(h, d_s_off, s_off.data(), sizeof(int64_t) * (J + 1)));
         RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, h.stream));
         RDD_TRY(pca_gram(h, G, g_off.data(), d_g_off));
-        RDD_TRY(eig_batched(h, G, d_g_off, Z, d_s_off, Y, tol, mode, h.d_p, h.d_eig, flags));
+        // the subspace path pays where the direct path is slowest: widths past
+        // 480, whose panel reduction no longer fits in LDS
+        const int mmin = h.m.empty() ? 0 : *std::min_element(h.m.begin(), h.m.end());
+        const int mmax = h.m.empty() ? 0 : *std::max_element(h.m.begin(), h.m.end());
+        int rc_e = kSubspaceDecline;
+        if (h.tune.pca_subspace && mmin >= 128 && mmax > 480)
+            rc_e = eig_subspace(h, G, g_off, d_g_off, tol, mode, h.d_p, h.d_eig, flags, Y);
+        if (rc_e == kSubspaceDecline) {  // the direct eigensolver (overwrites G)
+            RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 2, h.stream));
+            RDD_TRY(eig_batched(h, G, d_g_off, Z, d_s_off, Y, tol, mode, h.d_p, h.d_eig, flags));
+        } else {
+            RDD_TRY(rc_e);
+        }
         dev_free(h, d_s_off);
         int32_t fl[2];
         RDD_TRY(download(h, fl, flags, sizeof(fl)));
@@ -843,8 +855,9 @@ int rann_dd_get_tuning(const rann_dd_handle* hh, rann_dd_tuning* out) {
 int rann_dd_set_tuning(rann_dd_handle* hh, const rann_dd_tuning* t) {
     RDD_TRY(guard_handle(hh, false));
     if (!t || t->tile_grid < 64 || t->tile_grid > 4096 || t->red_cap < 32 || t->red_cap > 240 ||
-        (t->use_graph != 0 && t->use_graph != 1) || t->reserved != 0)
-        return (rdd::set_error("tuning outside its ranges (tile_grid 64..4096, red_cap 32..240, use_graph 0/1)"),
+        (t->use_graph != 0 && t->use_graph != 1) || (t->pca_subspace != 0 && t->pca_subspace != 1))
+        return (rdd::set_error("tuning outside its ranges (tile_grid 64..4096, red_cap 32..240, use_graph 0/1, "
+                               "pca_subspace 0/1)"),
                 RANN_EINVAL);
     hh->h.tune = *t;
     return RANN_OK;
@@ -869,7 +882,7 @@ int rann_dd_autotune(rann_dd_handle* hh, int32_t k, int32_t iters, rann_dd_tunin
         for (int cap : {64, 128, 240})
             for (int gr : {0, 1}) {
                 if (rc != RANN_OK) break;
-                h.tune = rann_dd_tuning{g, cap, gr, 0};
+                h.tune = rann_dd_tuning{g, cap, gr, start.pca_subspace};
                 double us = 0.0;
                 rc = rdd::time_cg_iterations(h, k, iters, rhs, W, &us);
                 if (rc == RANN_OK && us < win_us) {

@@ -162,7 +162,7 @@ struct Handle {
     double setup_ms[4] = {0, 0, 0, 0};  // assemble, pca+factor host-clock times
 
     // launch parameters chosen by the autotuner (rann_dd_autotune) or the caller
-    rann_dd_tuning tune{768, 240, 1, 0};
+    rann_dd_tuning tune{768, 240, 1, 1};
     // executable graphs of CG check windows, keyed by what their launches bake in
     struct CgGraph {
         hipGraphExec_t exec = nullptr;
@@ -283,7 +283,27 @@ int exclusive_scan_i64(Handle& h, const int64_t* in, int64_t* out, int64_t n);
 int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g_off);
 int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const int64_t* d_s_off,
                 double* Y, double tol, int mode, int32_t* d_p, double* d_eig, int32_t* d_tie);
+// sizes of a batch of symmetric matrices for the eigensolver
+struct EigDims {
+    int J;
+    const int32_t* m;      // host, J sizes
+    const int32_t* d_m;    // device, J sizes
+    const int64_t* d_m_off;  // device, J+1 offsets of the eigenvalues
+    int64_t sum_m;
+};
+// eigenvalues (descending, at d_eig + m_off) of every matrix of the batch, the
+// count p above the threshold (d_p, and the tie flag), and the eigenvectors of
+// the d_nvec[j] largest (all of them when d_nvec is null: d_p) as the columns
+// of Y (row-major m x m per matrix, at d_g_off like G, which is overwritten)
+int eig_batched_dims(Handle& h, const EigDims& dm, double* G, const int64_t* d_g_off, double* S,
+                     const int64_t* d_s_off, double* Y, double tol, int mode, int32_t* d_p, double* d_eig,
+                     int32_t* d_flags, const int32_t* d_nvec);
 int compact_V(Handle& h, const double* Z, const int64_t* d_g_off, double* V);
+// the eigen-PCA by subspace iteration with Rayleigh-Ritz (subspace.hip); returns
+// kSubspaceDecline when a subdomain would need a block wider than its limit
+constexpr int kSubspaceDecline = 100;
+int eig_subspace(Handle& h, const double* G, const std::vector<int64_t>& g_off, const int64_t* d_g_off,
+                 double tol, int mode, int32_t* d_p, double* d_eig, int32_t* d_flags, double* Yfull);
 int64_t eig_scratch_elems(int m);
 int feature_rows(Handle& h);
 int build_schwarz(Handle& h);

@@ -966,17 +966,25 @@ int64_t eig_scratch_elems(int m) { return scr_LU(m) + 6LL * m * m; }
 
 int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const int64_t* d_s_off,
                 double* Y, double tol, int mode, int32_t* d_p, double* d_eig, int32_t* d_flags) {
-    const int J = h.geo.J;
+    const EigDims dims{h.geo.J, h.m.data(), h.d_m, h.d_m_off, h.sum_m};
+    return eig_batched_dims(h, dims, G, d_g_off, S, d_s_off, Y, tol, mode, d_p, d_eig, d_flags, nullptr);
+}
+
+int eig_batched_dims(Handle& h, const EigDims& dm, double* G, const int64_t* d_g_off, double* S,
+                     const int64_t* d_s_off, double* Y, double tol, int mode, int32_t* d_p, double* d_eig,
+                     int32_t* d_flags, const int32_t* d_nvec) {
+    const int J = dm.J;
+    const int32_t* d_vec = d_nvec ? d_nvec : d_p;  // vectors computed per matrix
     KTimer kt_(h.stream, "k_eig");
     int mmax = 0;
-    for (int j = 0; j < J; ++j) mmax = std::max(mmax, h.m[j]);
+    for (int j = 0; j < J; ++j) mmax = std::max(mmax, dm.m[j]);
     // tile lists of the trailing updates, one group per panel
     std::vector<int4> tasks;
     std::vector<int64_t> off;
     for (int k0 = 0; k0 < mmax; k0 += kNB) {
         off.push_back((int64_t)tasks.size());
         for (int j = 0; j < J; ++j) {
-            const int n2 = h.m[j] - (k0 + kNB);
+            const int n2 = dm.m[j] - (k0 + kNB);
             if (n2 <= 0) continue;
             const int nt = (n2 + kTM - 1) / kTM;
             for (int a = 0; a < nt; ++a)
@@ -991,33 +999,33 @@ int eig_batched(Handle& h, double* G, const int64_t* d_g_off, double* S, const i
     int pi = 0;
     for (int k0 = 0; k0 < mmax; k0 += kNB, ++pi) {
         if (mmax <= kPanelCols)
-            hipLaunchKernelGGL(k_tri_panel<true>, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S,
+            hipLaunchKernelGGL(k_tri_panel<true>, dim3(J), dim3(kPT), 0, h.stream, dm.d_m, d_g_off, G, S,
                                d_s_off, k0);
         else
-            hipLaunchKernelGGL(k_tri_panel<false>, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S,
+            hipLaunchKernelGGL(k_tri_panel<false>, dim3(J), dim3(kPT), 0, h.stream, dm.d_m, d_g_off, G, S,
                                d_s_off, k0);
         const int64_t cnt = off[pi + 1] - off[pi];
         if (cnt > 0)
             hipLaunchKernelGGL(k_tri_update, dim3((unsigned)cnt), dim3(256), 0, h.stream,
-                               d_tasks + off[pi], h.d_m, d_g_off, G, S, d_s_off, k0);
+                               d_tasks + off[pi], dm.d_m, d_g_off, G, S, d_s_off, k0);
         RDD_HIP(hipGetLastError());
     }
     double* d_lam = nullptr;
-    RDD_TRY(dev_alloc(h, &d_lam, (size_t)h.sum_m));
-    hipLaunchKernelGGL(k_bisect, dim3(J, (unsigned)((mmax + 15) / 16)), dim3(64), 0, h.stream, h.d_m, S,
-                       d_s_off, d_lam, h.d_m_off, d_eig);
-    hipLaunchKernelGGL(k_pcount, dim3(J), dim3(256), 0, h.stream, h.d_m, S, d_s_off, d_lam, tol, mode,
-                       d_p, h.d_m_off, d_flags);
+    RDD_TRY(dev_alloc(h, &d_lam, (size_t)dm.sum_m));
+    hipLaunchKernelGGL(k_bisect, dim3(J, (unsigned)((mmax + 15) / 16)), dim3(64), 0, h.stream, dm.d_m, S,
+                       d_s_off, d_lam, dm.d_m_off, d_eig);
+    hipLaunchKernelGGL(k_pcount, dim3(J), dim3(256), 0, h.stream, dm.d_m, S, d_s_off, d_lam, tol, mode,
+                       d_p, dm.d_m_off, d_flags);
     int iv_y = 1;  // workgroups per matrix: enough for all m vectors
     for (int jj = 0; jj < J; ++jj) {
-        const int V = inviter_vectors(h.m[jj]);
-        iv_y = std::max(iv_y, (h.m[jj] + V - 1) / V);
+        const int V = inviter_vectors(dm.m[jj]);
+        iv_y = std::max(iv_y, (dm.m[jj] + V - 1) / V);
     }
-    hipLaunchKernelGGL(k_inviter, dim3(J, (unsigned)iv_y), dim3(64), 0, h.stream, h.d_m, S,
-                       d_s_off, d_lam, d_p, h.d_m_off);
-    hipLaunchKernelGGL(k_vectors, dim3(J), dim3(kPT), 0, h.stream, h.d_m, d_g_off, G, S, d_s_off, Y, d_p);
-    hipLaunchKernelGGL(k_backxf, dim3(J, (unsigned)((mmax + kSlice - 1) / kSlice)), dim3(kPT), 0, h.stream, h.d_m,
-                       d_g_off, G, S, d_s_off, Y, d_p);
+    hipLaunchKernelGGL(k_inviter, dim3(J, (unsigned)iv_y), dim3(64), 0, h.stream, dm.d_m, S,
+                       d_s_off, d_lam, d_vec, dm.d_m_off);
+    hipLaunchKernelGGL(k_vectors, dim3(J), dim3(kPT), 0, h.stream, dm.d_m, d_g_off, G, S, d_s_off, Y, d_vec);
+    hipLaunchKernelGGL(k_backxf, dim3(J, (unsigned)((mmax + kSlice - 1) / kSlice)), dim3(kPT), 0, h.stream, dm.d_m,
+                       d_g_off, G, S, d_s_off, Y, d_vec);
     kt_.stop();
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));

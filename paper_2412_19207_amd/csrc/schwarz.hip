@@ -424,8 +424,14 @@ __global__ void __launch_bounds__(256) k_trirow_apply(const int2* __restrict__ t
 
 // FP64 symmetric W, one (block, tile a) per workgroup: z_a = sum_b W_ab x_b
 // over the stored tiles (a, b), b <= a, and the transposes of the tiles
-// (b, a), b > a.  Every tile off the diagonal is read by two workgroups.  The
-// next tile and x segment are loaded while the current ones are used.
+// (b, a), b > a.  Every tile off the diagonal is read by two workgroups.  Both
+// kinds of tile go straight from global memory into the A operand: lane
+// (lr, g) of wave w takes row 16 w + lr at the columns 16 g + s (K index
+// 16 g + s at step s) of a stored tile (a 16-element run), or the same K
+// entries of column 16 w + lr of a transposed one (16 rows 64 apart, each
+// load reading 16 consecutive entries across the lanes).  The x segment of
+// tile b is staged in one of two LDS buffers while tile b - 1 is multiplied
+// (one barrier per tile); the next tile is loaded meanwhile.
 template <int KC>
 __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ tasks,
                                                        const int64_t* __restrict__ t_off,
@@ -437,18 +443,23 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
                                                        double* __restrict__ z) {
     constexpr int NB = KC / 16;
     constexpr int XPT = kT * KC / 256;  // x values staged per thread
-    __shared__ double xs[kT][KC + 1];
-    __shared__ double ts[kT][kT + 1];
+    __shared__ double xs[2][kT][KC + 1];
     const int2 tk = tasks[blockIdx.x];
     const int i = tk.x, a = tk.y;
     const int64_t q = qv[i];
     const int nt = (int)((q + kT - 1) / kT);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lr = lane & 15, g = lane >> 4;
-    const double* Wi = W + t_off[i] + (16 * w + lr) * kT + 16 * g;
+    const double* Wi = W + t_off[i];
     const int32_t* cols = blk_cols + ub_off[i];
-    auto tile_of = [&](int b) -> int64_t {
-        return (b <= a) ? (int64_t)a * (a + 1) / 2 + b : (int64_t)b * (b + 1) / 2 + a;
+    auto load_w = [&](int b, double* v) {
+        if (b <= a) {
+            load16(Wi + ((int64_t)a * (a + 1) / 2 + b) * kTE + (16 * w + lr) * kT + 16 * g, v);
+        } else {
+            const double* T = Wi + ((int64_t)b * (b + 1) / 2 + a) * kTE + (16 * g) * kT + 16 * w + lr;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) v[s] = T[s * kT];
+        }
     };
     auto load_x = [&](int b, double* xr) {
 #pragma unroll
@@ -458,6 +469,13 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
             xr[m] = (gc < q) ? r[(int64_t)cols[gc] * k + k0 + e % KC] : 0.0;
         }
     };
+    auto put_x = [&](int buf, const double* xr) {
+#pragma unroll
+        for (int m = 0; m < XPT; ++m) {
+            const int e = threadIdx.x + 256 * m;
+            xs[buf][e / KC][e % KC] = xr[m];
+        }
+    };
     typedef Mfma<double>::acc_t acc_t;
     acc_t Z[NB];
 #pragma unroll
@@ -465,41 +483,28 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
 #pragma unroll
         for (int e = 0; e < 4; ++e) Z[nb][e] = 0.0;
     double v[16], xr[XPT];
-    load16(Wi + tile_of(0) * kTE, v);
+    load_w(0, v);
     load_x(0, xr);
+    put_x(0, xr);
+    __syncthreads();
     for (int b = 0; b < nt; ++b) {
-        const bool tr = b > a;
-        __syncthreads();  // the previous step's reads of xs and ts are done
-#pragma unroll
-        for (int m = 0; m < XPT; ++m) {
-            const int e = threadIdx.x + 256 * m;
-            xs[e / KC][e % KC] = xr[m];
-        }
-        if (tr)
-#pragma unroll
-            for (int s = 0; s < 16; ++s) ts[16 * w + lr][16 * g + s] = v[s];
-        __syncthreads();
         double vn[16];
-        if (b + 1 < nt) {
-            load16(Wi + tile_of(b + 1) * kTE, vn);
+        const bool more = b + 1 < nt;
+        if (more) {
+            load_w(b + 1, vn);
             load_x(b + 1, xr);
         }
-        if (!tr) {
+        const int buf = b & 1;
 #pragma unroll
-            for (int s = 0; s < 16; ++s)
+        for (int s = 0; s < 16; ++s)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<double>::mma(v[s], xs[16 * g + s][16 * nb + lr], Z[nb]);
-        } else {
-#pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const double av = ts[16 * g + s][16 * w + lr];
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<double>::mma(av, xs[16 * g + s][16 * nb + lr], Z[nb]);
-            }
-        }
-        if (b + 1 < nt)
+            for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<double>::mma(v[s], xs[buf][16 * g + s][16 * nb + lr], Z[nb]);
+        if (more) {
+            put_x(buf ^ 1, xr);
 #pragma unroll
             for (int s = 0; s < 16; ++s) v[s] = vn[s];
+        }
+        __syncthreads();
     }
     double* zi = z + ub_off[i] * k + k0;
 #pragma unroll

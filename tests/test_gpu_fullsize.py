@@ -66,12 +66,17 @@ def _solver(prob, precision):
 
 
 def _check_pca(prob, sysm, p, Vg, eig):
+    """Equal truncation counts; the eigenvalues that decide them (the kept ones
+    and the next; the subspace path computes a leading block only, NaN past
+    it) within the Gram's rounding; the kept subspace within its gap bound."""
     assert np.array_equal(p, sysm.p)
     off = 0
     for j in range(prob.J):
         m = int(prob.m[j])
         lam = sysm.lam[j]
-        n = min(lam.size, m)
+        n_fin = int(np.isfinite(eig[off:off + m]).sum())
+        assert n_fin >= min(p[j] + 1, m), (j, n_fin, p[j])
+        n = min(lam.size, m, p[j] + 1)
         # eigenvalues of the FP64 Gram matrix agree within its rounding level
         assert np.max(np.abs(eig[off:off + n] - lam[:n])) <= 10 * m * EPS * lam[0], j
         Vj = Vg[j]
