@@ -64,6 +64,10 @@ struct ApplyPlan {
     int64_t* d_seg_off = nullptr;  // J+1
     int64_t* d_seg_src = nullptr;  // first block entry of each segment
     double* d_seg_w = nullptr;     // its weight
+    // blocks with a used result, widest first, and the most 64-wide tiles per edge
+    int32_t* d_blk_list = nullptr;
+    int64_t n_blk_list = 0;
+    int max_nt = 0;
 };
 
 struct Handle {

@@ -516,6 +516,85 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
         }
 }
 
+// FP64 symmetric W, one block per workgroup of eight waves (blocks of at most
+// kBlkNT tiles per edge): z = W x over the whole block, every stored tile read
+// from memory once per use inside the workgroup.  x (q x KC) is gathered into
+// LDS once.  Output tile a of the block takes the products with all nt input
+// tiles b: the stored tile (a, b) for b <= a, the transpose of (b, a) for
+// b > a (column runs straight into the A operand, as in k_rowcol_mfma64).
+// Wave w computes rows 16 (w % 4) .. + 15 of the output tiles a = w / 4,
+// w / 4 + 2, ..., accumulating each in registers over b and storing it; the
+// next product's tile rows are loaded while the current one is multiplied.
+constexpr int kBlkNT = 6;
+template <int KC>
+__global__ void __launch_bounds__(512) k_blk_mfma64(const int32_t* __restrict__ blocks,
+                                                    const int64_t* __restrict__ t_off,
+                                                    const int64_t* __restrict__ qv,
+                                                    const int64_t* __restrict__ ub_off,
+                                                    const int32_t* __restrict__ blk_cols,
+                                                    const double* __restrict__ W,
+                                                    const double* __restrict__ r, int k, int k0,
+                                                    double* __restrict__ z) {
+    constexpr int NB = KC / 16;
+    __shared__ double xs[kBlkNT * kT][KC + 1];
+    const int i = blocks[blockIdx.x];
+    const int64_t q = qv[i];
+    const int nt = (int)((q + kT - 1) / kT);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const int rg = w & 3, half = w >> 2;
+    const double* Wi = W + t_off[i];
+    const int32_t* cols = blk_cols + ub_off[i];
+    for (int e = tid; e < nt * kT * KC; e += 512) {
+        const int row = e / KC, t = e % KC;
+        xs[row][t] = (row < q) ? r[(int64_t)cols[row] * k + k0 + t] : 0.0;
+    }
+    // this wave's products: (a, b) for a = half, half + 2, ..., b = 0 .. nt - 1
+    const int na = (nt - half + 1) / 2;
+    const int njobs = na * nt;
+    auto load_job = [&](int jb, double* v) {
+        const int a = half + 2 * (jb / nt), b = jb % nt;
+        if (b <= a) {
+            load16(Wi + ((int64_t)a * (a + 1) / 2 + b) * kTE + (16 * rg + lr) * kT + 16 * g, v);
+        } else {
+            const double* T = Wi + ((int64_t)b * (b + 1) / 2 + a) * kTE + (16 * g) * kT + 16 * rg + lr;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) v[s] = T[s * kT];
+        }
+    };
+    typedef Mfma<double>::acc_t acc_t;
+    acc_t Z[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Z[nb][e] = 0.0;
+    double v[16], vn[16];
+    if (njobs > 0) load_job(0, v);
+    __syncthreads();  // x staged
+    double* zi = z + ub_off[i] * k + k0;
+    for (int jb = 0; jb < njobs; ++jb) {
+        const int a = half + 2 * (jb / nt), b = jb % nt;
+        if (jb + 1 < njobs) load_job(jb + 1, vn);
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                Z[nb] = Mfma<double>::mma(v[s], xs[b * kT + 16 * g + s][16 * nb + lr], Z[nb]);
+        if (b == nt - 1) {  // output tile a complete
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t ga = (int64_t)a * kT + 16 * rg + Mfma<double>::out_row(lane, e);
+                    if (ga < q) zi[ga * k + 16 * nb + lr] = Z[nb][e];
+                    Z[nb][e] = 0.0;
+                }
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) v[s] = vn[s];
+    }
+}
+
 // FP32 triangular factor Y (mixed path), first pass, one (block, tile row a)
 // per workgroup: u_a = sum_{b <= a} Y_ab x_b in FP32, stored as FP32.
 template <int KC>
@@ -917,6 +996,22 @@ static int build_plan(Handle& h, const std::vector<int64_t>& ub_off, const std::
     pl.n_col_tasks = (int64_t)ctv.size();
     RDD_TRY(dev_alloc(h, &pl.d_col_tasks, ctv.size()));
     if (!ctv.empty()) RDD_TRY(upload(h, pl.d_col_tasks, ctv.data(), sizeof(int2) * ctv.size()));
+    // whole blocks, widest first (the batched FP64 local solves of narrow blocks)
+    std::vector<std::pair<int, int>> bl;
+    pl.max_nt = 0;
+    for (int i = 0; i < J; ++i)
+        if (h.nt[i] > 0 && row_hi[i] > 0) {
+            bl.push_back({h.nt[i], i});
+            pl.max_nt = std::max(pl.max_nt, (int)h.nt[i]);
+        }
+    std::stable_sort(bl.begin(), bl.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+        return x.first > y.first;
+    });
+    std::vector<int32_t> blv;
+    for (auto& e : bl) blv.push_back(e.second);
+    pl.n_blk_list = (int64_t)blv.size();
+    RDD_TRY(dev_alloc(h, &pl.d_blk_list, std::max<size_t>(blv.size(), 1)));
+    if (!blv.empty()) RDD_TRY(upload(h, pl.d_blk_list, blv.data(), sizeof(int32_t) * blv.size()));
     return RANN_OK;
 }
 
@@ -1030,7 +1125,20 @@ int launch_precond_local(Handle& h, const ApplyPlan& pl, const double* r, int k,
 #undef RDD_MX
             } else {
                 hipEvent_t ea = one_launch ? kt_.a : nullptr, eb = one_launch ? kt_.b : nullptr;
-                if (kc == 32)
+                if (pl.max_nt <= kBlkNT && pl.n_blk_list > 0) {
+                    if (kc == 32)
+                        hipExtLaunchKernelGGL((k_blk_mfma64<32>), dim3((unsigned)pl.n_blk_list), dim3(512), 0,
+                                              h.stream, ea, eb, 0, (const int32_t*)pl.d_blk_list,
+                                              (const int64_t*)h.d_t_off, (const int64_t*)h.d_q,
+                                              (const int64_t*)h.d_ub_off, (const int32_t*)pl.d_blk_cols,
+                                              (const double*)h.d_M64, r, k, k0, ub);
+                    else
+                        hipExtLaunchKernelGGL((k_blk_mfma64<16>), dim3((unsigned)pl.n_blk_list), dim3(512), 0,
+                                              h.stream, ea, eb, 0, (const int32_t*)pl.d_blk_list,
+                                              (const int64_t*)h.d_t_off, (const int64_t*)h.d_q,
+                                              (const int64_t*)h.d_ub_off, (const int32_t*)pl.d_blk_cols,
+                                              (const double*)h.d_M64, r, k, k0, ub);
+                } else if (kc == 32)
                     hipExtLaunchKernelGGL((k_rowcol_mfma64<32>), dim3((unsigned)pl.n_col_tasks), dim3(256), 0,
                                           h.stream, ea, eb, 0, (const int2*)pl.d_col_tasks, (const int64_t*)h.d_t_off,
                                           (const int64_t*)h.d_q, (const int64_t*)h.d_ub_off,
