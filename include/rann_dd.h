@@ -157,6 +157,13 @@ typedef struct rann_dd_tuning {
                                  solver when a subdomain keeps more than 48 eigenvectors; 0: the
                                  direct tridiagonal eigensolver.  Set before rann_dd_pca.  With
                                  the subspace path the eigenvalues past each block are NaN. */
+    int32_t gram32;           /* RANN_MIXED only, set before rann_dd_pca: 1 = the operator rows
+                                 are also rounded to FP32 and the local Gram blocks of the
+                                 Schwarz blocks A_i formed from them on the FP32 matrix cores
+                                 with FP32 accumulation (the equilibrated Cholesky with its
+                                 shift stays FP64); 0 (default) = A_i from the FP64 Gram blocks.
+                                 The normal matrix and every residual use FP64 rows either way. */
+    int32_t reserved;         /* 0 */
 } rann_dd_tuning;
 
 /* Layout sizes, for callers that allocate W, F and the diagnostic arrays. */

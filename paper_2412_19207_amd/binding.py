@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_grid", ctypes.c_int32), ("red_cap", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("pca_subspace", ctypes.c_int32)]
+                ("pca_subspace", ctypes.c_int32), ("gram32", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {"tile_grid": self.tile_grid, "red_cap": self.red_cap, "use_graph": self.use_graph}
@@ -410,8 +410,10 @@ class Solver:
     def tuning(self):
         return rann_dd_get_tuning(self.handle).as_dict()
 
-    def set_tuning(self, tile_grid=None, red_cap=None, use_graph=None, pca_subspace=None):
+    def set_tuning(self, tile_grid=None, red_cap=None, use_graph=None, pca_subspace=None, gram32=None):
         t = rann_dd_get_tuning(self.handle)
+        if gram32 is not None:
+            t.gram32 = int(bool(gram32))
         if pca_subspace is not None:
             t.pca_subspace = int(bool(pca_subspace))
         if tile_grid is not None:

@@ -601,6 +601,7 @@ static int pca_impl(Handle& h, double tol, int mode, const int32_t* p_force, con
     if (d_g_off) dev_free(h, d_g_off);
     // operator rows in the PCA basis
     RDD_TRY(dev_alloc(h, &h.d_H, (size_t)h.nnz));
+    if (h.precision == RANN_MIXED && h.tune.gram32) RDD_TRY(dev_alloc(h, &h.d_H32, (size_t)h.nnz));
     RDD_TRY(feature_rows(h));
     RDD_TRY(plan_products(h));
     RDD_TRY(normal_blocks(h));
@@ -855,9 +856,10 @@ int rann_dd_get_tuning(const rann_dd_handle* hh, rann_dd_tuning* out) {
 int rann_dd_set_tuning(rann_dd_handle* hh, const rann_dd_tuning* t) {
     RDD_TRY(guard_handle(hh, false));
     if (!t || t->tile_grid < 64 || t->tile_grid > 4096 || t->red_cap < 32 || t->red_cap > 240 ||
-        (t->use_graph != 0 && t->use_graph != 1) || (t->pca_subspace != 0 && t->pca_subspace != 1))
+        (t->use_graph != 0 && t->use_graph != 1) || (t->pca_subspace != 0 && t->pca_subspace != 1) ||
+        (t->gram32 != 0 && t->gram32 != 1) || t->reserved != 0)
         return (rdd::set_error("tuning outside its ranges (tile_grid 64..4096, red_cap 32..240, use_graph 0/1, "
-                               "pca_subspace 0/1)"),
+                               "pca_subspace 0/1, gram32 0/1, reserved 0)"),
                 RANN_EINVAL);
     hh->h.tune = *t;
     return RANN_OK;
@@ -882,7 +884,7 @@ int rann_dd_autotune(rann_dd_handle* hh, int32_t k, int32_t iters, rann_dd_tunin
         for (int cap : {64, 128, 240})
             for (int gr : {0, 1}) {
                 if (rc != RANN_OK) break;
-                h.tune = rann_dd_tuning{g, cap, gr, start.pca_subspace};
+                h.tune = rann_dd_tuning{g, cap, gr, start.pca_subspace, start.gram32, 0};
                 double us = 0.0;
                 rc = rdd::time_cg_iterations(h, k, iters, rhs, W, &us);
                 if (rc == RANN_OK && us < win_us) {

@@ -101,6 +101,8 @@ struct Handle {
     double* d_eig = nullptr;       // sum m_j, descending
     double* d_V = nullptr;         // sum m_j p_j
     double* d_H = nullptr;         // nnz FP64
+    float* d_H32 = nullptr;        // nnz FP32 (mixed precision with FP32 local Gram blocks only)
+    float* d_G32 = nullptr;        // their Gram blocks (set-up only)
 
     // Schwarz blocks
     std::vector<std::vector<int>> sten;  // stencil of each block (ascending)
@@ -166,7 +168,7 @@ struct Handle {
     double setup_ms[4] = {0, 0, 0, 0};  // assemble, pca+factor host-clock times
 
     // launch parameters chosen by the autotuner (rann_dd_autotune) or the caller
-    rann_dd_tuning tune{768, 240, 1, 1};
+    rann_dd_tuning tune{768, 240, 1, 1, 0, 0};
     // executable graphs of CG check windows, keyed by what their launches bake in
     struct CgGraph {
         hipGraphExec_t exec = nullptr;

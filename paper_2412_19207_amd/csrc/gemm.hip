@@ -405,7 +405,7 @@ int feature_rows(Handle& h) {
     KTimer kt_(h.stream, "k_feat_rows");
     hipLaunchKernelGGL(k_feat_rows, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, h.geo, d_t,
                        h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, h.d_p,
-                       h.d_v_off, h.d_V, h.d_h_off, h.d_H, (float*)nullptr);
+                       h.d_v_off, h.d_V, h.d_h_off, h.d_H, h.d_H32);
     kt_.stop();
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));
@@ -496,6 +496,14 @@ int normal_blocks(Handle& h) {
                            d_tiles, d_blocks, d_lj, d_lk, h.d_p, h.d_h_off, h.d_H, d_G);
         kt_.stop();
         RDD_HIP(hipGetLastError());
+        if (h.d_H32) {  // the same Gram blocks from the FP32 rows on the FP32 matrix cores
+            RDD_TRY(dev_alloc(h, &h.d_G32, (size_t)tot_g));
+            KTimer kt32_(h.stream, "k_local_gram32");
+            hipLaunchKernelGGL((k_local_gram<float>), dim3((unsigned)tiles.size()), dim3(256), 0, h.stream,
+                               d_tiles, d_blocks, d_lj, d_lk, h.d_p, h.d_h_off, h.d_H32, h.d_G32);
+            kt32_.stop();
+            RDD_HIP(hipGetLastError());
+        }
     }
     // slabs of N: block row j, columns of nbrs[j] in ascending order
     std::vector<int32_t> nbr_off(J + 1, 0), nbr_flat, nbr_pid;
@@ -564,7 +572,11 @@ int normal_blocks(Handle& h) {
 void release_gram(Handle& h) {
     dev_free(h, h.d_G);
     dev_free(h, h.d_pair_blocks);
+    if (h.d_G32) dev_free(h, h.d_G32);
+    if (h.d_H32) dev_free(h, h.d_H32);
     h.d_G = nullptr;
+    h.d_G32 = nullptr;
+    h.d_H32 = nullptr;
     h.d_pair_blocks = nullptr;
     h.pair_tab.clear();
 }
@@ -606,8 +618,11 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
     RDD_TRY(upload(h, d_so, sten_off.data(), sizeof(int32_t) * sten_off.size()));
     RDD_TRY(upload(h, d_sf, sten_flat.data(), sizeof(int32_t) * sten_flat.size()));
     RDD_TRY(upload(h, d_po, pair_of.data(), sizeof(int32_t) * pair_of.size()));
+    const T* Gs = nullptr;
+    if constexpr (sizeof(T) == sizeof(float)) Gs = reinterpret_cast<const T*>(h.d_G32);
+    else Gs = reinterpret_cast<const T*>(h.d_G);
     hipLaunchKernelGGL((k_assemble_A<T>), dim3(J, max_ns * 32), dim3(256), 0, h.stream, J, d_so, d_sf,
-                       d_po, static_cast<const PairBlock*>(h.d_pair_blocks), h.d_p, h.d_f_off, h.d_G, A_out);
+                       d_po, static_cast<const PairBlock*>(h.d_pair_blocks), h.d_p, h.d_f_off, Gs, A_out);
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));
     for (void* ptr : {(void*)d_so, (void*)d_sf, (void*)d_po}) dev_free(h, ptr);
@@ -615,5 +630,6 @@ int local_blocks(Handle& h, const T* H, T* A_out) {
 }
 
 template int local_blocks<double>(Handle&, const double*, double*);
+template int local_blocks<float>(Handle&, const float*, float*);
 
 }  // namespace rdd

@@ -595,6 +595,112 @@ __global__ void __launch_bounds__(512) k_blk_mfma64(const int32_t* __restrict__ 
     }
 }
 
+// FP32 triangular factor Y (mixed path), one block per workgroup of eight
+// waves (blocks of at most kBlkNT tiles per edge): u = Y x, then z = Y^T u,
+// FP32 operands and accumulation on the matrix cores, z widened to FP64.  x
+// (rounded to FP32) and u stay in LDS; wave w computes rows 16 (w % 4) .. + 15
+// of the output tiles w / 4, w / 4 + 2, ... of each pass.  Pass 1 reads the
+// stored tiles (a, b), b <= a, as row runs; pass 2 their transposes as column
+// runs, both straight into the A operand; the next tile's rows are loaded
+// while the current one is multiplied.
+template <int KC>
+__global__ void __launch_bounds__(512) k_blk_mfma32(const int32_t* __restrict__ blocks,
+                                                    const int64_t* __restrict__ t_off,
+                                                    const int64_t* __restrict__ qv,
+                                                    const int64_t* __restrict__ ub_off,
+                                                    const int32_t* __restrict__ blk_cols,
+                                                    const float* __restrict__ Y,
+                                                    const double* __restrict__ r, int k, int k0,
+                                                    double* __restrict__ z) {
+    constexpr int NB = KC / 16;
+    __shared__ float xs[kBlkNT * kT][KC + 1];
+    __shared__ float us[kBlkNT * kT][KC + 1];
+    const int i = blocks[blockIdx.x];
+    const int64_t q = qv[i];
+    const int nt = (int)((q + kT - 1) / kT);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const int rg = w & 3, half = w >> 2;
+    const float* Yi = Y + t_off[i];
+    const int32_t* cols = blk_cols + ub_off[i];
+    for (int e = tid; e < nt * kT * KC; e += 512) {
+        const int row = e / KC, t = e % KC;
+        xs[row][t] = (row < q) ? (float)r[(int64_t)cols[row] * k + k0 + t] : 0.0f;
+    }
+    typedef Mfma<float>::acc_t acc_t;
+    // pass 1 jobs (a, b), b <= a, for a = half, half + 2, ...; pass 2 jobs
+    // (c, a), a >= c, for c = half, half + 2, ...  Job lists are walked by
+    // (output tile, input tile) in order.
+    auto next_job = [&](int pass, int& o, int& in) -> bool {  // advance; false at the end
+        if (pass == 1) {
+            if (++in > o) {
+                o += 2;
+                in = 0;
+            }
+        } else {
+            if (++in >= nt) {
+                o += 2;
+                in = o;
+            }
+        }
+        return o < nt;
+    };
+    auto load = [&](int pass, int o, int in, float* v) {
+        if (pass == 1) {  // Y_oin, row run
+            load16(Yi + ((int64_t)o * (o + 1) / 2 + in) * kTE + (16 * rg + lr) * kT + 16 * g, v);
+        } else {          // Y_{in, o}^T, column run
+            const float* T = Yi + ((int64_t)in * (in + 1) / 2 + o) * kTE + (16 * g) * kT + 16 * rg + lr;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) v[s] = T[s * kT];
+        }
+    };
+    double* zi = z + ub_off[i] * k + k0;
+    for (int pass = 1; pass <= 2; ++pass) {
+        float (*src)[KC + 1] = (pass == 1) ? xs : us;
+        int o = half, in = (pass == 1) ? 0 : half;
+        float v[16], vn[16];
+        bool any = o < nt;
+        if (any) load(pass, o, in, v);
+        __syncthreads();  // pass 1: x staged; pass 2: u complete
+        acc_t Acc[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Acc[nb][e] = 0.0f;
+        while (any) {
+            int o2 = o, in2 = in;
+            const bool more = next_job(pass, o2, in2);
+            if (more) load(pass, o2, in2, vn);
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    Acc[nb] = Mfma<float>::mma(v[s], src[in * kT + 16 * g + s][16 * nb + lr], Acc[nb]);
+            const bool last = (pass == 1) ? (in == o) : (in == nt - 1);
+            if (last) {  // output tile o complete
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int rr = 16 * rg + Mfma<float>::out_row(lane, e);
+                        const int64_t ga = (int64_t)o * kT + rr;
+                        if (pass == 1) {
+                            us[o * kT + rr][16 * nb + lr] = Acc[nb][e];
+                        } else if (ga < q) {
+                            zi[ga * k + 16 * nb + lr] = (double)Acc[nb][e];
+                        }
+                        Acc[nb][e] = 0.0f;
+                    }
+            }
+            o = o2;
+            in = in2;
+            any = more;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) v[s] = vn[s];
+        }
+    }
+}
+
 // FP32 triangular factor Y (mixed path), first pass, one (block, tile row a)
 // per workgroup: u_a = sum_{b <= a} Y_ab x_b in FP32, stored as FP32.
 template <int KC>
@@ -806,6 +912,12 @@ __global__ void k_div_count(int64_t P, int k, const int64_t* __restrict__ gat_of
     if (idx >= P * k) return;
     const int64_t g = idx / k;
     out[idx] = r[idx] / (double)(gat_off[g + 1] - gat_off[g]);
+}
+
+// out = (double) in
+__global__ void k_widen_f32(int64_t n, const float* __restrict__ in, double* __restrict__ out) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] = (double)in[idx];
 }
 
 // out = [r; 0]: the n entries of r followed by pad zeros
@@ -1084,7 +1196,16 @@ int build_schwarz(Handle& h) {
         RDD_TRY(dev_alloc(h, &h.d_M32, (size_t)h.tile_elems));
     else
         RDD_TRY(dev_alloc(h, &h.d_M64, (size_t)h.tile_elems));
-    RDD_TRY(local_blocks<double>(h, h.d_H, d_A));
+    if (h.d_G32) {
+        // A_i from the FP32 Gram blocks, widened for the FP64 factorisation
+        float* d_A32 = reinterpret_cast<float*>(d_W);  // d_W is free until the factorisation
+        RDD_TRY(local_blocks<float>(h, h.d_H32, d_A32));
+        hipLaunchKernelGGL(k_widen_f32, dim3((unsigned)((h.factor_elems + 255) / 256)), dim3(256), 0, h.stream,
+                           h.factor_elems, d_A32, d_A);
+        RDD_HIP(hipGetLastError());
+    } else {
+        RDD_TRY(local_blocks<double>(h, h.d_H, d_A));
+    }
     const int rc = factor_tiles(h, d_A, d_W);
     dev_free(h, d_A);
     dev_free(h, d_W);
@@ -1111,7 +1232,16 @@ int launch_precond_local(Handle& h, const ApplyPlan& pl, const double* r, int k,
         if (rem >= 16) {  // matrix cores, 32 or 16 right-hand sides per launch, no slots
             const int kc = rem >= 32 ? 32 : 16;
             float* u32 = reinterpret_cast<float*>(u1);
-            if (h.precision == RANN_MIXED) {
+            if (h.precision == RANN_MIXED && pl.max_nt <= kBlkNT && pl.n_blk_list > 0) {
+                if (kc == 32)
+                    hipLaunchKernelGGL((k_blk_mfma32<32>), dim3((unsigned)pl.n_blk_list), dim3(512), 0, h.stream,
+                                       pl.d_blk_list, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_M32, r, k,
+                                       k0, ub);
+                else
+                    hipLaunchKernelGGL((k_blk_mfma32<16>), dim3((unsigned)pl.n_blk_list), dim3(512), 0, h.stream,
+                                       pl.d_blk_list, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_M32, r, k,
+                                       k0, ub);
+            } else if (h.precision == RANN_MIXED) {
 #define RDD_MX(KCV)                                                                                        \
     hipLaunchKernelGGL((k_urow_mfma32<KCV>), dim3((unsigned)pl.n_row_tasks), dim3(256), 0, h.stream,          \
                        pl.d_row_tasks, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_M32, r, k, k0, u32);  \

@@ -604,3 +604,20 @@ def test_pca_rank_tie_status():
     s3 = binding.Solver(prob, device=DEV)
     p_lo = s3.pca(tol * (1 - 1e-3), "rel_eig")
     assert s3.pca_status == 0 and p_lo[j] == kk + 1
+
+
+def test_mixed_fp32_gram_blocks(case_small2d_k37):
+    """Mixed precision with the Schwarz blocks formed from FP32 operator rows on
+    the FP32 matrix cores (FP32 accumulation): the solve still reaches the QR
+    solution to the mixed bar, column by column (the preconditioner only shapes
+    the iteration; residuals use the FP64 rows)."""
+    prob, ref = case_small2d_k37
+    sysm = ref["sys"]
+    s = binding.Solver(prob, device=DEV, precision="mixed")
+    s.set_tuning(gram32=1)
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-13, maxiter=5000)
+    assert info["status"] == 0
+    Wn = W.cpu().numpy()
+    for t in range(Wn.shape[1]):
+        assert rel(Wn[:, t], ref["W"][:, t]) <= 1e-6, t
