@@ -327,6 +327,8 @@ constexpr int kSlabRows = 16;       // slab rows per product workgroup
 // bookkeeping (see cg_step.h); the partials are then those of <p, s>.
 struct PUpd;
 int launch_normal(Handle& h, const double* x, int k, double* s, double* part, const PUpd* pu = nullptr);
+// workgroups whose partials of <x, s> launch_normal writes (rows of part)
+int normal_parts(const Handle& h, int k);
 
 int launch_Hx(Handle& h, const double* x, int k, double* y, bool scale_bnd);
 int launch_HTy(Handle& h, const double* y, int k, double* x, double* partial);

@@ -931,6 +931,7 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     // workgroups of the element-wise kernels
     const unsigned rgrid = (unsigned)std::min(red_grid(Pk), std::max(32, (int)h.tune.red_cap));
     const int nCp = nC > 0 ? nC : (int)rgrid;  // partials of <r, z>
+    const int nA = normal_parts(h, k);          // partials of <p, s>
 
     RDD_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, h.stream));
     RDD_HIP(hipMemsetAsync(iters, 0, sizeof(int32_t) * k, h.stream));
@@ -992,8 +993,8 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
             RDD_TRY(launch_normal(h, pbuf[pc], k, s, partA));
         }
         double* p = pbuf[pc];
-        hipLaunchKernelGGL(k_cg_xr2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k,
-                           (int)h.n_slab_tasks, partA, rho_in, act_in, p, s, W, r, partB, flags);
+        hipLaunchKernelGGL(k_cg_xr2, dim3(rgrid), dim3(256), 0, h.stream, (int64_t)P, k, nA, partA, rho_in,
+                           act_in, p, s, W, r, partB, flags);
         // z = M^{-1} r and partials of <r, z>
         if (!ident) {
             RDD_TRY(launch_precond_local(h, h.ap, r, k, ub));

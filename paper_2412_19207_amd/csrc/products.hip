@@ -470,6 +470,11 @@ int launch_HTy_part(Handle& h, const double* y, int k, double* part) {
 
 namespace rdd {
 
+int normal_parts(const Handle& h, int k) {
+    (void)k;
+    return (int)h.n_slab_tasks;
+}
+
 int launch_normal(Handle& h, const double* x, int k, double* s, double* part, const PUpd* pup) {
     PUpd pu{};
     if (pup) pu = *pup;

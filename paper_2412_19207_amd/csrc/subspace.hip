@@ -158,6 +158,7 @@ __global__ void __launch_bounds__(kCT) k_chol_inv(const int32_t* __restrict__ mv
     __shared__ double L[kSMax][kSMax + 1];
     __shared__ double red[kCT / 64];
     __shared__ double sdiag[kSMax];
+    __shared__ double sinv[kSMax];
     const int j = blockIdx.x;
     const int s = sv[j], m = mv[j];
     const double* Sj = S + to[j];
@@ -194,16 +195,29 @@ __global__ void __launch_bounds__(kCT) k_chol_inv(const int32_t* __restrict__ mv
     // the factor is L_true[r][k] = L[r][k] / sqrt(d_k), d_k = L[k][k]
     for (int k = tid; k < s; k += kCT) sdiag[k] = sqrt(L[k][k] > 0.0 ? L[k][k] : 1e-300);
     __syncthreads();
-    // Rinv = L_true^{-T}: row c of Rinv is column c of L_true^{-1}, solved by
-    // thread c by forward substitution (entries below c are zero)
-    for (int c = tid; c < s; c += kCT) {
-        double* row = Rj + (int64_t)c * s;
-        for (int i = 0; i < c; ++i) row[i] = 0.0;
-        for (int i = c; i < s; ++i) {
+    // the factor's entries L_true[r][c] = L[r][c] / sqrt(d_c), below the diagonal
+    for (int e = tid; e < s * s; e += kCT) {
+        const int r = e / s, c = e % s;
+        if (c < r) L[r][c] /= sdiag[c];
+    }
+    __syncthreads();
+    // Rinv = L_true^{-T}: row c of Rinv is column c of L_true^{-1}.  Forward
+    // substitution row by row: step i finishes entry i of every column c <= i
+    // (one thread per column), the rows kept in the upper half of LDS rows
+    // (Linv[c][i] at Lt[c][i], i >= c, which the factor does not use)
+    for (int i = 0; i < s; ++i) {
+        for (int c = tid; c <= i; c += kCT) {
             double acc = (i == c) ? 1.0 : 0.0;
-            for (int l = c; l < i; ++l) acc = fma(-(L[i][l] / sdiag[l]), row[l], acc);
-            row[i] = acc / sdiag[i];
+            for (int l = c; l < i; ++l) acc = fma(-L[i][l], (l == c ? sinv[c] : L[c][l]), acc);
+            const double v = acc / sdiag[i];
+            if (i == c) sinv[c] = v;
+            else L[c][i] = v;
         }
+        __syncthreads();
+    }
+    for (int e = tid; e < s * s; e += kCT) {
+        const int r = e / s, c = e % s;
+        Rj[e] = (c < r) ? 0.0 : (c == r ? sinv[r] : L[r][c]);
     }
 }
 
