@@ -68,8 +68,7 @@ def local_terms(prob, X, rows, j, sums, Lrows):
     om, om_g, om_h = geo.partition_of_unity(prob, Xr, j, sums=tuple(s[rows] for s in sums))
     Lr = None if Lrows is None else Lrows[rows]
     M, Mg, Mh = ft.multiplier(Lr, om, om_g, om_h)
-    mu_j = geo.centre(prob, j)
-    phi, dphi, d2phi = ft.features(Xr, mu_j, prob.sigma, prob.R[j], prob.b[j])
+    phi, dphi, d2phi = ft.subdomain_features(prob, Xr, j)
     return om, M, Mg, Mh, phi, dphi, d2phi
 
 
@@ -131,6 +130,6 @@ def probe_matrix(prob, sysm, Xq, Lq=None):
             continue
         om, _, _ = geo.partition_of_unity(prob, Xq[rows], j, sums=tuple(s[rows] for s in sums))
         M = om if Lq is None else Lq[rows] * om
-        phi, _, _ = ft.features(Xq[rows], geo.centre(prob, j), prob.sigma, prob.R[j], prob.b[j])
+        phi, _, _ = ft.subdomain_features(prob, Xq[rows], j)
         Pm[np.ix_(rows, np.arange(sysm.col_off[j], sysm.col_off[j + 1]))] = (M[:, None] * phi) @ sysm.V[j]
     return Pm

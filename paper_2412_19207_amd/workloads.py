@@ -20,7 +20,17 @@ Layouts (paper Sec. 5, Example 1, subdomain formula):
               subdomain width to centre spacing.
 
 Random draws (numpy PCG64): widths (seed_m) -> for each subdomain j in linear
-order (dimension 0 fastest): R_j (m_j x d) then b_j (m_j), both scale*U[-1,1].
+order (dimension 0 fastest): R_j (m_j x d_in) then b_j (m_j), both scale*U[-1,1],
+with d_in = d for one hidden layer.
+
+Several hidden layers (paper eq. (net), inner_widths = (w_1, ..., w_{L})): the
+inner layers come from a second stream seeded with seed_w + 7919, for each
+subdomain j in turn and layer by layer: R (w_i x w_{i-1}, w_0 = d) then b
+(w_i).  The first layer acts on the normalised input with weights and biases
+U[-1,1] (Example 1's distribution); a layer fed by w tanh outputs (the deeper
+inner layers and the last layer) has weights (2/sqrt(w))*U[-1,1] and biases
+U[-1,1], which keeps its pre-activations of order one.  The last layer's R_j
+is then m_j x w_L.
 """
 from __future__ import annotations
 
@@ -58,6 +68,10 @@ class Problem:
     u_obs: Optional[np.ndarray]    # (M,) observations for the misfit loss
     meta: dict
     L_probe: Optional[np.ndarray] = None  # (M,) constraining multiplier at probes (None: L == 1)
+    # inner hidden layers of each subdomain's network (paper eq. (net)), or None
+    # for one hidden layer: inner[j] = [(R_1, b_1), ..., (R_L, b_L)], R_i (w_i x
+    # w_{i-1}) with w_0 = d; R[j] then acts on the last inner layer's output
+    inner: Optional[list] = None
 
     @property
     def J(self) -> int:
@@ -151,13 +165,35 @@ def paper_layout(lo, hi, l, delta):
     return mu, np.array(sigma)
 
 
-def draw_weights(J, m, d, scale, seed):
+def draw_weights(J, m, d, scale, seed, inner_widths=None):
+    """Last-layer weights R_j, b_j and, for several hidden layers, the inner
+    layers of every subdomain (None for one hidden layer)."""
+    inner = None
+    d_in = d
+    if inner_widths:
+        widths = [int(w) for w in inner_widths]
+        rng_in = np.random.default_rng(seed + 7919)
+        inner = []
+        for j in range(J):
+            layers, w_prev = [], d
+            for i, w in enumerate(widths):
+                s_w = 1.0 if i == 0 else 2.0 / math.sqrt(w_prev)
+                Ri = s_w * rng_in.uniform(-1.0, 1.0, size=(w, w_prev))
+                bi = rng_in.uniform(-1.0, 1.0, size=w)
+                layers.append((Ri, bi))
+                w_prev = w
+            inner.append(layers)
+        d_in = widths[-1]
     rng = np.random.default_rng(seed)
     R, b = [], []
     for j in range(J):
-        R.append(scale * rng.uniform(-1.0, 1.0, size=(int(m[j]), d)))
-        b.append(scale * rng.uniform(-1.0, 1.0, size=int(m[j])))
-    return R, b
+        if inner is None:
+            R.append(scale * rng.uniform(-1.0, 1.0, size=(int(m[j]), d)))
+            b.append(scale * rng.uniform(-1.0, 1.0, size=int(m[j])))
+        else:
+            R.append(2.0 / math.sqrt(d_in) * rng.uniform(-1.0, 1.0, size=(int(m[j]), d_in)))
+            b.append(rng.uniform(-1.0, 1.0, size=int(m[j])))
+    return R, b, inner
 
 
 def smooth_modes(d, kmax=6):
@@ -190,7 +226,7 @@ def build_problem(name, d, l, m, weight_scale, pts_per_sub, *, overlap_frac=None
                   faces=None, bnd_counts=None, coeff_fn=None, rhs_fn=None,
                   bnd_fn=None, exact_fn=None, Lfun_fn=None, lambda_B=100.0,
                   seed_w=0, probes_per_dim=None, obs_noise=0.0, seed_obs=3,
-                  meta=None) -> Problem:
+                  meta=None, inner_widths=None) -> Problem:
     lo = np.zeros(d) if lo is None else np.asarray(lo, float)
     hi = np.ones(d) if hi is None else np.asarray(hi, float)
     l = np.asarray(l, dtype=np.int64)
@@ -202,7 +238,7 @@ def build_problem(name, d, l, m, weight_scale, pts_per_sub, *, overlap_frac=None
     else:
         mu, sigma = paper_layout(lo, hi, l, delta)
     m = np.broadcast_to(np.asarray(m, dtype=np.int32), (J,)).copy()
-    R, b = draw_weights(J, m, d, weight_scale, seed_w)
+    R, b, inner = draw_weights(J, m, d, weight_scale, seed_w, inner_widths)
     counts = [int(pts_per_sub[i]) * int(l[i]) for i in range(d)]
     X_int = cell_centred_grid(lo, hi, counts)
     if faces is None:
@@ -229,7 +265,8 @@ def build_problem(name, d, l, m, weight_scale, pts_per_sub, *, overlap_frac=None
     return Problem(name=name, d=d, lo=lo, hi=hi, l=l, mu=mu, sigma=sigma, m=m,
                    R=R, b=b, X_int=X_int, a=a, beta=beta, c=c, X_bnd=X_bnd,
                    lambda_B=float(lambda_B), Lfun=Lf, F=F, probes=probes,
-                   u_probe=u_probe, u_obs=u_obs, meta=dict(meta or {}), L_probe=L_probe)
+                   u_probe=u_probe, u_obs=u_obs, meta=dict(meta or {}), L_probe=L_probe,
+                   inner=inner)
 
 
 def _laplace_coeffs(X):
