@@ -98,7 +98,8 @@ typedef struct rann_dd_desc {
     double sigma[4];          /* support half-width per dimension (> 0) */
     const int32_t* m;         /* host, J hidden widths (1..1024) */
     const double* R;          /* device, sum(m) x d: rows of R_j (weights acting on
-                                 the normalised input), subdomain after subdomain */
+                                 the normalised input), subdomain after subdomain;
+                                 sum(m) x inner_w[n_inner-1] with inner layers */
     const double* b;          /* device, sum(m) biases */
     int64_t n_int;            /* interior collocation points (>= 1) */
     const double* X_int;      /* device, n_int x d */
@@ -115,6 +116,18 @@ typedef struct rann_dd_desc {
     int32_t precision;        /* RANN_FP64 or RANN_MIXED */
     int32_t stencil;          /* RANN_STENCIL_* */
     int32_t precond;          /* RANN_PRECOND_* */
+    /* Several fixed hidden layers (paper Sec. 2, eq. (net)): each subdomain
+       network applies n_inner tanh layers f(y) = tanh(R_i y + b_i) of widths
+       inner_w[0..n_inner-1] to the normalised input before the last hidden
+       layer, whose weights R then act on the last inner output (R is
+       sum(m) x inner_w[n_inner-1]).  n_inner = 0 (one hidden layer): the
+       fields below are ignored.  Limits: n_inner 0..3, widths 1..64. */
+    int32_t n_inner;
+    int32_t inner_w[3];
+    const double* R_inner;    /* device: subdomain after subdomain, layer after layer, the
+                                 w_i x w_{i-1} weights row-major (w_0 = d) */
+    const double* b_inner;    /* device: subdomain after subdomain, layer after layer, the w_i
+                                 biases */
 } rann_dd_desc;
 
 typedef struct rann_dd_solve_opts {

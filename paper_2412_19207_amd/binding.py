@@ -38,6 +38,8 @@ class Desc(ctypes.Structure):
         ("c", ctypes.c_void_p), ("n_bnd", ctypes.c_int64), ("X_bnd", ctypes.c_void_p),
         ("lambda_B", ctypes.c_double), ("Lfun", ctypes.c_void_p), ("precision", ctypes.c_int32),
         ("stencil", ctypes.c_int32), ("precond", ctypes.c_int32),
+        ("n_inner", ctypes.c_int32), ("inner_w", ctypes.c_int32 * 3), ("R_inner", ctypes.c_void_p),
+        ("b_inner", ctypes.c_void_p),
     ]
 
 
@@ -313,7 +315,9 @@ class Solver:
         self.d = d
         self.J = int(np.prod(prob.l))
         t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=self.dev)
-        R = t(np.concatenate([np.asarray(r).reshape(-1, d) for r in prob.R], axis=0))
+        inner = getattr(prob, "inner", None)
+        w_in = d if not inner else int(np.asarray(inner[0][-1][0]).shape[0])
+        R = t(np.concatenate([np.asarray(r).reshape(-1, w_in) for r in prob.R], axis=0))
         b = t(np.concatenate([np.asarray(x).ravel() for x in prob.b]))
         Xi, a, be = t(prob.X_int), t(prob.a), t(prob.beta)
         c = t(prob.c) if c is None else c.to(self.dev, torch.float64).contiguous()
@@ -338,6 +342,15 @@ class Solver:
         desc.precision = FP64 if precision == "fp64" else MIXED
         desc.stencil = STENCIL[stencil]
         desc.precond = PRECOND[precond]
+        if inner:
+            # several hidden layers: every subdomain's inner layers, in order
+            widths = [int(np.asarray(Ri).shape[0]) for Ri, _ in inner[0]]
+            desc.n_inner = len(widths)
+            for i, w in enumerate(widths):
+                desc.inner_w[i] = w
+            Rin = t(np.concatenate([np.asarray(Ri, float).ravel() for layers in inner for Ri, _ in layers]))
+            bin_ = t(np.concatenate([np.asarray(bi, float).ravel() for layers in inner for _, bi in layers]))
+            desc.R_inner, desc.b_inner = Rin.data_ptr(), bin_.data_ptr()
         self.handle = rann_dd_assemble(desc, self.stream.cuda_stream)
         self.info = rann_dd_get_info(self.handle)
         self.p = None

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librann_dd.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "geometry.hip", "gemm.hip", "eig.hip", "factor.hip", "schwarz.hip", "products.hip", "krylov.hip",
-           "nonlinear.hip", "subspace.hip"]
+           "nonlinear.hip", "subspace.hip", "deep.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-fvisibility=hidden",

@@ -402,6 +402,19 @@ static int assemble_impl(const rann_dd_desc* ds, void* stream, Handle*& hp) {
         set_error("invalid stencil or preconditioner");
         return RANN_EINVAL;
     }
+    if (ds->n_inner < 0 || ds->n_inner > kMaxInner) {
+        set_error("n_inner must be 0..3");
+        return RANN_EINVAL;
+    }
+    for (int i = 0; i < ds->n_inner; ++i)
+        if (ds->inner_w[i] < 1 || ds->inner_w[i] > kMaxInnerWidth) {
+            set_error("inner layer widths must be 1..64");
+            return RANN_EINVAL;
+        }
+    if (ds->n_inner > 0 && (!ds->R_inner || !ds->b_inner)) {
+        set_error("R_inner and b_inner are required when n_inner > 0");
+        return RANN_EINVAL;
+    }
     {
         int64_t off = 0;
         for (int i = 0; i < d; ++i) {
@@ -455,9 +468,13 @@ static int assemble_impl(const rann_dd_desc* ds, void* stream, Handle*& hp) {
     RDD_TRY(upload(*h, h->d_m_off, h->m_off.data(), sizeof(int64_t) * (J + 1)));
     RDD_TRY(dev_alloc(*h, &h->d_Rf, (size_t)h->sum_m * 4));
     RDD_TRY(dev_alloc(*h, &h->d_bf, (size_t)h->sum_m));
-    hipLaunchKernelGGL(k_pad_features, dim3((unsigned)((h->sum_m + 255) / 256)), dim3(256), 0,
-                       h->stream, h->sum_m, d, ds->R, h->d_Rf);
-    RDD_HIP(hipGetLastError());
+    if (ds->n_inner == 0) {
+        hipLaunchKernelGGL(k_pad_features, dim3((unsigned)((h->sum_m + 255) / 256)), dim3(256), 0,
+                           h->stream, h->sum_m, d, ds->R, h->d_Rf);
+        RDD_HIP(hipGetLastError());
+    } else {
+        RDD_TRY(deep_setup(*h, ds));
+    }
     RDD_HIP(hipMemcpyAsync(h->d_bf, ds->b, sizeof(double) * h->sum_m, hipMemcpyDeviceToDevice,
                            h->stream));
     // points (interior then boundary) and operator coefficients

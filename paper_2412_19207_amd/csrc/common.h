@@ -20,6 +20,16 @@ constexpr int kPairRec = 16;        // doubles per (point, subdomain) record
 constexpr int kRecX = 0, kRecW = 4, kRecP0 = 5, kRecP1 = 6, kRecP2 = 10;
 constexpr double kEdge = 1.0 - 1e-12;  // strict support test factor
 
+// inner hidden layers of every subdomain network (paper eq. (net)); n = 0: one
+// hidden layer acting on the normalised input
+constexpr int kMaxInner = 3, kMaxInnerWidth = 64;
+struct DeepNet {             // passed by value to kernels
+    int n = 0;               // inner layers
+    int w[kMaxInner + 1] = {0, 0, 0, 0};  // w[0] = d, then the inner widths
+    int lo[kMaxInner] = {0, 0, 0};        // offset of layer i in a subdomain's packed weights
+    int stride = 0;          // packed weights per subdomain
+};
+
 struct Geo {                 // passed by value to kernels
     int d;
     int l[kMaxDim];
@@ -83,6 +93,9 @@ struct Handle {
     double* d_mu = nullptr;        // device sum(l)
     double* d_Rf = nullptr;        // device sum_m x 4 (padded)
     double* d_bf = nullptr;        // device sum_m
+    DeepNet deep;                  // inner layers (deep.n == 0: none)
+    double* d_inner = nullptr;     // device J x deep.stride packed inner weights
+    double* d_Rl = nullptr;        // device sum_m x w_last: last-layer weights (deep.n > 0)
     int64_t* d_m_off = nullptr;    // device J+1
     int32_t* d_m = nullptr;        // device J
     PointSet pts;                  // collocation points
@@ -312,6 +325,15 @@ int eig_subspace(Handle& h, const double* G, const std::vector<int64_t>& g_off, 
                  double tol, int mode, int32_t* d_p, double* d_eig, int32_t* d_flags, double* Yfull);
 int64_t eig_scratch_elems(int m);
 int feature_rows(Handle& h);
+// several hidden layers (deep.hip): set-up from the descriptor, the value
+// matrices (slot kRecW) or probe values (slot kRecP0) of a point set into out
+// (n_j x m_j at d_out_off[j]), the operator rows H (and H32), and the probe
+// evaluation: y = per-pair values (x: raw coefficients, sum_m x k) or, with
+// transpose, y = raw-coefficient gradient (x: per point, M x k)
+int deep_setup(Handle& h, const rann_dd_desc* ds);
+int deep_values(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_off, double* out);
+int deep_feature_rows(Handle& h);
+int deep_eval(Handle& h, const PointSet& ps, const double* x, int k, double* y, bool transpose);
 int build_schwarz(Handle& h);
 template <class T>
 int local_blocks(Handle& h, const T* H, T* A_out);

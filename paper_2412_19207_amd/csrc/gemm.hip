@@ -6,6 +6,8 @@
 //  * k_feat_rows : H_j = A_j V_j with A_j[i,k] = A[L w_j phi_k](x_i) generated
 //                  in the GEMM prologue from the pair coefficients (eqs. (sum),
 //                  (system_new)); FP64 output plus an FP32 copy in the mixed path.
+//                  (Networks with several hidden layers take deep.hip instead,
+//                  for both products.)
 //  * k_local_gram: Gram blocks G_jk = H_j^T H_k over the rows the two supports
 //                  share, the pieces of the Schwarz blocks A_i = R_i H^T H R_i^T
 //                  (Sec. 3); FP64, or FP32 with FP32 accumulation.
@@ -375,8 +377,9 @@ int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g
     RDD_TRY(dev_alloc(h, &d_psi_off, (size_t)J + 1));
     RDD_TRY(dev_alloc(h, &d_psi, (size_t)std::max<int64_t>(1, psi_off[J])));
     RDD_TRY(upload(h, d_psi_off, psi_off.data(), sizeof(int64_t) * (J + 1)));
+    if (h.deep.n > 0) RDD_TRY(deep_values(h, h.pts, kRecW, d_psi_off, d_psi));
     KTimer kt_(h.stream, "k_pca_gram");
-    if (max_n > 0)
+    if (max_n > 0 && h.deep.n == 0)
         hipLaunchKernelGGL(k_psi, dim3(J, (unsigned)((max_n + 15) / 16)), dim3(256), 0, h.stream, h.geo,
                            h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, d_psi_off, d_psi);
     hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, d_t, h.pts.d_row_off,
@@ -391,6 +394,7 @@ int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g
 }
 
 int feature_rows(Handle& h) {
+    if (h.deep.n > 0) return deep_feature_rows(h);
     std::vector<GramTile> tiles;
     for (int j = 0; j < h.geo.J; ++j) {
         int64_t n = h.pts.row_off[j + 1] - h.pts.row_off[j];

@@ -56,11 +56,33 @@ def test_library_exports_every_declared_symbol(lib):
         assert name in binding._SIGS, f"binding lacks {name}"
 
 
-def test_struct_layouts_match_header():
-    # offsets computed by ctypes must match the C layout (natural alignment)
-    assert ctypes.sizeof(binding.SolveOpts) == 24
-    assert binding.Desc.lambda_B.offset % 8 == 0
-    assert ctypes.sizeof(binding.Info) % 8 == 0
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals the C
+    compiler's for the header (a program built here prints them)."""
+    structs = {"rann_dd_desc": binding.Desc, "rann_dd_solve_opts": binding.SolveOpts,
+               "rann_dd_stats": binding.Stats, "rann_dd_tuning": binding.Tuning, "rann_dd_info": binding.Info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rann_dd.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            a, b, c = ln.split()
+            got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def _valid_desc(keep):
@@ -90,7 +112,7 @@ def _valid_desc(keep):
 
 @pytest.mark.parametrize("field,value", [
     ("d", 0), ("d", 5), ("lambda_B", -1.0), ("lambda_B", float("nan")), ("precision", 7),
-    ("stencil", 9), ("precond", -2), ("n_int", 0),
+    ("stencil", 9), ("precond", -2), ("n_int", 0), ("n_inner", 4), ("n_inner", -1),
 ])
 def test_invalid_descriptor_is_rejected(lib, field, value):
     keep = []
@@ -101,6 +123,22 @@ def test_invalid_descriptor_is_rejected(lib, field, value):
     assert rc == binding.RANN_EINVAL
     assert not h.value
     assert len(binding.rann_dd_last_error()) > 0
+
+
+@pytest.mark.parametrize("case", ["width0", "width65", "no_weights"])
+def test_invalid_inner_layers_are_rejected(lib, case):
+    keep = []
+    d = _valid_desc(keep)
+    d.n_inner = 2
+    d.inner_w[0], d.inner_w[1] = 8, {"width0": 0, "width65": 65, "no_weights": 8}[case]
+    fake = np.zeros(8)
+    keep.append(fake)
+    if case != "no_weights":
+        d.R_inner = d.b_inner = fake.ctypes.data
+    h = ctypes.c_void_p()
+    rc = lib.rann_dd_assemble(ctypes.byref(d), None, ctypes.byref(h))
+    assert rc == binding.RANN_EINVAL
+    assert not h.value
 
 
 def test_non_increasing_centres_rejected(lib):
