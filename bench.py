@@ -415,6 +415,57 @@ def nonlinear_newton(torch, wl, dev, steps=10):
             "e_L2_probes": e}
 
 
+def deep_features(torch, wl, dev, runs=3):
+    """The 2D Poisson layout (8x8 subdomains, last hidden width 300) with one
+    hidden layer and with two fixed inner layers of width 64 before it (paper
+    eq. (net)): set-up (assembly, PCA, operator rows, local factors) and the
+    FP64 AS-CG solve to the workload's tolerance (median of `runs` after one
+    warm-up), P, iterations, the probe error, and the set-up kernels of one
+    timed set-up."""
+    from paper_2412_19207_amd import binding
+    sync = torch.cuda.synchronize
+    out = {}
+    for name in ["cfg2", "deep2d"]:
+        prob = wl.make(name)
+        meta = prob.meta
+        F = torch.as_tensor(prob.F, device=dev)
+        Xq = torch.as_tensor(prob.probes, device=dev)
+        su, so = [], []
+        for r in range(runs + 1):
+            if r == runs:
+                binding.rann_dd_ktime_enable(True)
+            sync()
+            t0 = time.perf_counter()
+            s = binding.Solver(prob, precision="fp64", stencil="full", precond="as")
+            s.pca(meta["pca_tol"], "rel_eig")
+            sync()
+            t1 = time.perf_counter()
+            if r == runs:
+                kt = {n: binding.rann_dd_ktime_query(n) for n in
+                      ["k_deep_values", "k_pca_gram", "k_eig", "k_feat_rows", "k_deep_rows", "k_seg_gemm", "k_factor"]}
+                binding.rann_dd_ktime_enable(False)
+                s.close()
+                break
+            W, info = s.solve(F, tol=meta["tol"], maxiter=5000)
+            sync()
+            t2 = time.perf_counter()
+            if r > 0:
+                su.append((t1 - t0) * 1e3)
+                so.append((t2 - t1) * 1e3)
+            if info["status"] != 0:
+                raise RuntimeError(f"{name}: solve did not converge")
+            if r == runs - 1:
+                U = s.eval(Xq, W)[:, 0].cpu().numpy()
+                P, iters = int(s.info.P), int(info["iterations"])
+            s.close()
+        inner = [int(np.asarray(Ri).shape[0]) for Ri, _ in prob.inner[0]] if prob.inner else []
+        out[name] = {"workload": prob.name, "inner_widths": inner, "P": P, "iterations": iters,
+                     "setup_ms": stats3(su), "solve_ms": stats3(so),
+                     "setup_kernels_ms": {n: v[0] for n, v in kt.items() if v[1] > 0},
+                     "e_L2_probes": float(np.linalg.norm(U - prob.u_probe) / np.linalg.norm(prob.u_probe))}
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -588,6 +639,7 @@ def main():
         out["gmres_spacetime"] = gmres_spacetime(torch, wl, dev)
         out["krylov_variants"] = krylov_variants(torch, wl, dev, args.tol)
         out["nonlinear_newton"] = nonlinear_newton(torch, wl, dev)
+        out["deep_features"] = deep_features(torch, wl, dev)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(prob, args.tol, stencil, int(info["iterations"]))
         out["cpu_baseline"] = {"value": k / cb["total_s"], "unit": "solves/s",

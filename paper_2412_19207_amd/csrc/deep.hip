@@ -383,6 +383,7 @@ int deep_values(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_of
     if (mx == 0) return RANN_OK;
     double* C0 = nullptr;
     RDD_TRY(dev_alloc(h, &C0, (size_t)ps.pairs * wl));
+    KTimer kt_(h.stream, "k_deep_values");
     hipLaunchKernelGGL(k_deep_chain<false>, dim3(h.geo.J, (unsigned)((mx + 3) / 4)), dim3(256), 0, h.stream, h.geo,
                        D, ps.d_row_off, ps.d_rec, h.d_inner, C0);
     RDD_HIP(hipGetLastError());
@@ -393,6 +394,7 @@ int deep_values(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_of
     hipLaunchKernelGGL(k_deep_values, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, d_t, wl,
                        ps.d_row_off, ps.d_rec, slot, h.d_m, h.d_m_off, h.d_Rl, h.d_bf, C0, d_out_off, out);
     RDD_HIP(hipGetLastError());
+    kt_.stop();
     RDD_HIP(hipStreamSynchronize(h.stream));
     dev_free(h, d_t);
     dev_free(h, C0);

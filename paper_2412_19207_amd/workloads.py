@@ -592,10 +592,19 @@ def semilinear2d(size="full", **kw) -> Problem:
     return build_problem(**args)
 
 
+def deep2d(**kw) -> Problem:
+    """The 2D Poisson workload (8x8 subdomains, last hidden width 300, 30x30
+    points per subdomain) with two fixed inner hidden layers of width 64
+    before the last hidden layer (paper eq. (net))."""
+    args = dict(inner_widths=(64, 64), name="poisson2d_8x8_m300_inner64x64")
+    args.update(kw)
+    return cfg2(**args)
+
+
 WORKLOADS = {
     "cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4, "cfg5": cfg5,
     "ex1": ex1_replica, "small2d": small2d, "small3d": small3d,
-    "semilinear2d": semilinear2d,
+    "semilinear2d": semilinear2d, "deep2d": deep2d,
 }
 
 

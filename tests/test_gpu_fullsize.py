@@ -175,6 +175,15 @@ def test_cfg3_full_size_parity_batched():
     _full_size_parity("cfg3", ["fp64", "mixed"], {"fp64": 1e-8, "mixed": 1e-6}, gpu_tol=1e-11, floor=3e-10)
 
 
+def test_deep2d_full_size_parity():
+    """The 2D Poisson layout with two fixed inner hidden layers of width 64
+    before the last hidden layer (width 300), FP64 and mixed."""
+    _need_gpu()
+    # to stagnation: the GPU's floor of the normal residual is about 1.5e-10
+    # here (the oracle's refined PCG: 2.8e-11)
+    _full_size_parity("deep2d", ["fp64", "mixed"], {"fp64": 1e-8, "mixed": 1e-6}, gpu_tol=1e-10, floor=3e-10)
+
+
 def _sampled_subproblem(prob, n_int, n_bnd, seed):
     rng = np.random.default_rng(seed)
     si = np.sort(rng.choice(prob.N_I, n_int, replace=False))
