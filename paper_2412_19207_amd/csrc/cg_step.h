@@ -12,7 +12,7 @@
 namespace rdd {
 
 // res[t] = sum over the nparts partials part[b * k + k0 + t], for t < kb:
-// the 256 / kb threads of each t read 8 partials at a time into 8
+// the 256 / kb threads of each t read 16 partials at a time into 8
 // accumulators; accumulators and threads meet in a fixed-order tree
 __device__ inline void sum_partials_kb(const double* part, int nparts, int k, int k0, int kb, double* res,
                                        double* sh) {
@@ -22,17 +22,18 @@ __device__ inline void sum_partials_kb(const double* part, int nparts, int k, in
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = 0.0;
     if (ro < per) {
+        // 16 loads in flight per round, two per accumulator
         int b = ro;
-        for (; b + 7 * per < nparts; b += 8 * per) {
-            double v[8];
+        for (; b + 15 * per < nparts; b += 16 * per) {
+            double v[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u * per) * k + k0 + t];
+            for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(b + u * per) * k + k0 + t];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += v[u];
+            for (int u = 0; u < 8; ++u) acc[u] += v[u] + v[u + 8];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (b + u * per < nparts) acc[u] += part[(int64_t)(b + u * per) * k + k0 + t];
+        for (int u = 0; u < 16; ++u)
+            if (b + u * per < nparts) acc[u & 7] += part[(int64_t)(b + u * per) * k + k0 + t];
     }
     const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     if (kb <= 64 && (kb & (kb - 1)) == 0) {

@@ -488,7 +488,7 @@ __device__ void block_partial_by_rhs(double val, int k, double* sh, double* out,
 }
 
 // res[t] = sum over the nparts partials, for t < k.  The 256 / k threads of
-// each t read 8 partials at a time (independent loads in flight) into 8
+// each t read 16 partials at a time (independent loads in flight) into 8
 // accumulators; accumulators and threads meet in a fixed-order tree.
 __device__ void sum_partials(const double* part, int nparts, int k, double* res, double* sh) {
     const int per = 256 / k;
@@ -497,17 +497,18 @@ __device__ void sum_partials(const double* part, int nparts, int k, double* res,
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = 0.0;
     if (ro < per) {
+        // 16 loads in flight per round, two per accumulator
         int b = ro;
-        for (; b + 7 * per < nparts; b += 8 * per) {
-            double v[8];
+        for (; b + 15 * per < nparts; b += 16 * per) {
+            double v[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u * per) * k + t];
+            for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(b + u * per) * k + t];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += v[u];
+            for (int u = 0; u < 8; ++u) acc[u] += v[u] + v[u + 8];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (b + u * per < nparts) acc[u] += part[(int64_t)(b + u * per) * k + t];
+        for (int u = 0; u < 16; ++u)
+            if (b + u * per < nparts) acc[u & 7] += part[(int64_t)(b + u * per) * k + t];
     }
     const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     if (k <= 64 && (k & (k - 1)) == 0) {
@@ -643,6 +644,7 @@ __global__ void __launch_bounds__(256) k_gather_seg(int k, int Y, const int32_t*
                                                     const double* __restrict__ seg_w,
                                                     const double* __restrict__ u, const double* __restrict__ r,
                                                     double* __restrict__ z, double* __restrict__ part) {
+    constexpr int kSB = 9;  // segments per round (a 2D full-stencil subdomain lies in 9 blocks)
     __shared__ double sh[256];
     const int j = blockIdx.x / Y, y = blockIdx.x % Y;
     const int L = (256 / k) * k;
@@ -653,14 +655,26 @@ __global__ void __launch_bounds__(256) k_gather_seg(int k, int Y, const int32_t*
     if (threadIdx.x < L) {
         const int64_t e0 = (int64_t)y * 4 * L + threadIdx.x;
         double zv[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t q = s0; q < s1; ++q) {
-            const double w = seg_w[q];
-            const double* us = u + seg_src[q] * k;
+        // the loads of a round's segments are all in flight together; the sums
+        // keep the segment order
+        for (int64_t q0 = s0; q0 < s1; q0 += kSB) {
+            const int nq = (int)((s1 - q0 < kSB) ? (s1 - q0) : kSB);
+            double w[kSB], uv[kSB][4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t e = e0 + (int64_t)L * v;
-                if (e < n) zv[v] += w * us[e];
+            for (int i = 0; i < kSB; ++i) {
+                const double* us = u + ((i < nq) ? seg_src[q0 + i] : 0) * k;
+                w[i] = (i < nq) ? seg_w[q0 + i] : 0.0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t e = e0 + (int64_t)L * v;
+                    uv[i][v] = (i < nq && e < n) ? us[e] : 0.0;
+                }
             }
+#pragma unroll
+            for (int i = 0; i < kSB; ++i)
+                if (i < nq)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) zv[v] += w[i] * uv[i][v];
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {

@@ -254,12 +254,13 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
     }
 }
 
-// Batched right-hand sides (KC = 16 or 32): the 16 slab rows of a task times
-// x (Q x KC) on the FP64 matrix cores.  Wave w takes the 64-column sweeps w,
-// w + 4, ...; lane l = 16 g + lr supplies row r0 + lr at columns c0 + 16 g + s
-// (A operand, K index 16 g + s at step s) and the x rows of the same columns
-// (B operand, read straight from global memory: within the task each x row
-// feeds one wave only).  The 4 waves' sums meet in LDS.
+// Batched right-hand sides (KC = 16 or 32): the kSlabRows slab rows of a task
+// (RB blocks of 16) times x (Q x KC) on the FP64 matrix cores.  Wave w takes
+// the 64-column sweeps w, w + 4, ...; lane l = 16 g + lr supplies rows
+// r0 + 16 b + lr at columns c0 + 16 g + s (A operands, K index 16 g + s at
+// step s) and the x rows of the same columns (B operand, read straight from
+// global memory once for the RB row blocks: within the task each x row feeds
+// one wave only).  The 4 waves' sums meet in LDS.
 template <int KC>
 __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks,
                                                   const int32_t* __restrict__ p,
@@ -272,8 +273,9 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
                                                   double* __restrict__ s, double* __restrict__ part,
                                                   PUpd pu) {
     constexpr int NB = KC / 16;
-    static_assert(kSlabRows == 16, "one 16-row MFMA block per task");
-    __shared__ double red[4][16][KC + 1];
+    constexpr int RB = kSlabRows / 16;
+    static_assert(kSlabRows % 16 == 0, "whole 16-row MFMA blocks per task");
+    __shared__ double red[4][kSlabRows][KC + 1];
     __shared__ double dsh[256];
     __shared__ double beta_s[KC], rz_s[KC], rr_s[KC];
     __shared__ int act_s[KC];
@@ -285,22 +287,30 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
     const int32_t* cols = N_cols + N_coff[j];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lr = lane & 15, g = lane >> 4;
-    const bool row_ok = r0 + lr < pj;
-    const double* Nr = N + N_off[j] + (int64_t)(row_ok ? r0 + lr : r0) * Q;
+    bool row_ok[RB];
+    const double* Nr[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        row_ok[b] = r0 + 16 * b + lr < pj;
+        Nr[b] = N + N_off[j] + (int64_t)(row_ok[b] ? r0 + 16 * b + lr : r0) * Q;
+    }
     typedef Mfma<double>::acc_t acc_t;
-    acc_t acc[NB];
+    acc_t acc[RB][NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+    for (int b = 0; b < RB; ++b)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[nb][e] = 0.0;
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[b][nb][e] = 0.0;
     for (int64_t c0 = 64 * w; c0 < Q; c0 += 256) {
         const int64_t cb = c0 + 16 * g;
-        double av[16];
+        double av[RB][16];
         int32_t ci[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const bool ok = cb + u < Q;
-            av[u] = (ok && row_ok) ? Nr[cb + u] : 0.0;
+#pragma unroll
+            for (int b = 0; b < RB; ++b) av[b][u] = (ok && row_ok[b]) ? Nr[b][cb + u] : 0.0;
             ci[u] = ok ? cols[cb + u] : -1;
         }
 #pragma unroll
@@ -312,17 +322,20 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
                     const int64_t gi = (int64_t)ci[u] * k + k0 + 16 * nb + lr;
                     bv = pu.pprev ? pupd_value(pu, gi, 16 * nb + lr, beta_s, act_s) : x[gi];
                 }
-                acc[nb] = Mfma<double>::mma(av[u], bv, acc[nb]);
+#pragma unroll
+                for (int b = 0; b < RB; ++b) acc[b][nb] = Mfma<double>::mma(av[b][u], bv, acc[b][nb]);
             }
     }
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+    for (int b = 0; b < RB; ++b)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) red[w][Mfma<double>::out_row(lane, e)][16 * nb + lr] = acc[nb][e];
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[w][16 * b + Mfma<double>::out_row(lane, e)][16 * nb + lr] = acc[b][nb][e];
     __syncthreads();
     const int t = threadIdx.x % KC;
     double dotv = 0.0;
-    for (int rr = threadIdx.x / KC; rr < 16; rr += 256 / KC) {
+    for (int rr = threadIdx.x / KC; rr < kSlabRows; rr += 256 / KC) {
         const double v = (red[0][rr][t] + red[1][rr][t]) + (red[2][rr][t] + red[3][rr][t]);
         if (r0 + rr < pj) {
             const int64_t gi = (col_off[j] + r0 + rr) * k + k0 + t;

@@ -461,12 +461,21 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
             for (int s = 0; s < 16; ++s) v[s] = T[s * kT];
         }
     };
-    auto load_x = [&](int b, double* xr) {
+    // the column indices of an x segment are loaded one step before its
+    // values, so that each step waits for one round of loads
+    auto load_cols = [&](int b, int32_t* ci) {
 #pragma unroll
         for (int m = 0; m < XPT; ++m) {
             const int e = threadIdx.x + 256 * m;
             const int64_t gc = (int64_t)b * kT + e / KC;
-            xr[m] = (gc < q) ? r[(int64_t)cols[gc] * k + k0 + e % KC] : 0.0;
+            ci[m] = (gc < q) ? cols[gc] : -1;
+        }
+    };
+    auto load_x = [&](const int32_t* ci, double* xr) {
+#pragma unroll
+        for (int m = 0; m < XPT; ++m) {
+            const int e = threadIdx.x + 256 * m;
+            xr[m] = (ci[m] >= 0) ? r[(int64_t)ci[m] * k + k0 + e % KC] : 0.0;
         }
     };
     auto put_x = [&](int buf, const double* xr) {
@@ -483,16 +492,20 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
 #pragma unroll
         for (int e = 0; e < 4; ++e) Z[nb][e] = 0.0;
     double v[16], xr[XPT];
+    int32_t ci[XPT], cn[XPT];
+    load_cols(0, ci);
     load_w(0, v);
-    load_x(0, xr);
+    load_x(ci, xr);
     put_x(0, xr);
+    if (nt > 1) load_cols(1, ci);
     __syncthreads();
     for (int b = 0; b < nt; ++b) {
         double vn[16];
         const bool more = b + 1 < nt;
         if (more) {
             load_w(b + 1, vn);
-            load_x(b + 1, xr);
+            load_x(ci, xr);
+            if (b + 2 < nt) load_cols(b + 2, cn);
         }
         const int buf = b & 1;
 #pragma unroll
@@ -503,6 +516,9 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
             put_x(buf ^ 1, xr);
 #pragma unroll
             for (int s = 0; s < 16; ++s) v[s] = vn[s];
+            if (b + 2 < nt)
+#pragma unroll
+                for (int m = 0; m < XPT; ++m) ci[m] = cn[m];
         }
         __syncthreads();
     }
@@ -1327,21 +1343,23 @@ int launch_precond_local(Handle& h, const ApplyPlan& pl, const double* r, int k,
         k0 += kb;
     }
     kt_.stop();
-    KTimer kr_(h.stream, "k_slot_reduce");
+    // the slot reduction runs (and is timed) only for right-hand sides past
+    // the matrix-core chunks
     const int kt = k - kv0;
-    const unsigned rgrid = (unsigned)((h.ub_total * kt + 255) / 256);
-    if (kt == 0) {
-    } else if (h.precision == RANN_MIXED) {
-        hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, kv0, kt, 0, 1, 0,
-                           h.d_ent_blk, h.d_ub_off, h.d_s_off, h.d_q, Rs, Cs, ub);
-    } else {
-        hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, kv0, kt, 1, 1, 1,
-                           h.d_ent_blk, h.d_ub_off, h.d_s_off, h.d_q, Rs, Cs, ub);
+    if (kt > 0) {
+        KTimer kr_(h.stream, "k_slot_reduce");
+        const unsigned rgrid = (unsigned)((h.ub_total * kt + 255) / 256);
+        if (h.precision == RANN_MIXED)
+            hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, kv0, kt, 0, 1, 0,
+                               h.d_ent_blk, h.d_ub_off, h.d_s_off, h.d_q, Rs, Cs, ub);
+        else
+            hipLaunchKernelGGL(k_slot_reduce, dim3(rgrid), dim3(256), 0, h.stream, h.ub_total, k, kv0, kt, 1, 1, 1,
+                               h.d_ent_blk, h.d_ub_off, h.d_s_off, h.d_q, Rs, Cs, ub);
+        kr_.stop();
     }
 #undef RDD_TA_KB
 #undef RDD_TR
 #undef RDD_TA
-    kr_.stop();
     RDD_HIP(hipGetLastError());
     return RANN_OK;
 }

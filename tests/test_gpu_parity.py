@@ -197,6 +197,38 @@ def test_preconditioner_batched_matches_oracle(case_small2d, stencil, kind, k):
         assert e < max(1e-9, 1e-15 * kappa), (t, e, kappa)
 
 
+@pytest.fixture(scope="module")
+def case_wide_blocks():
+    _need_gpu()
+    prob = wl.small2d(l=(4, 3), m=(150, 171, 133, 164, 148, 177), k=2)
+    ref = osolve.reference(prob, "rel_eig", 1e-10)
+    return prob, ref
+
+
+@pytest.mark.parametrize("kind", ["as", "ras", "sas"])
+@pytest.mark.parametrize("k", [16, 32, 37])
+def test_preconditioner_large_blocks_matches_oracle(case_wide_blocks, kind, k):
+    """Schwarz blocks of up to 9 tiles per edge (4x3 subdomains, full stencil,
+    q up to 563): the FP64 matrix-core local solves that stream the tiles of a
+    block one output tile per workgroup (k_rowcol_mfma64), against the
+    oracle's dense M^-1 column by column."""
+    prob, ref = case_wide_blocks
+    sysm, H = ref["sys"], ref["H"]
+    HtH = H.T @ H
+    M = osw.schwarz_dense(HtH, sysm.col_off, osw.stencil(prob, "full"), kind).dense()
+    s = binding.Solver(prob, device=DEV, stencil="full", precond=kind)
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    assert s.info.max_q > 6 * 64
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal((sysm.P, k))
+    z = s.apply_precond(torch.as_tensor(r, device=DEV)).cpu().numpy()
+    kappa = np.linalg.cond(HtH)
+    ref_z = M @ r
+    for t in range(k):
+        e = rel(z[:, t], ref_z[:, t])
+        assert e < max(1e-9, 1e-15 * kappa), (t, e, kappa)
+
+
 def test_mixed_batched_apply_close_to_fp64(case_small2d):
     """Mixed path against the FP64 oracle apply: one right-hand side at a time
     (FP64 arithmetic on the FP32 factor) and 32 at once (FP32 operands and
