@@ -302,16 +302,24 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[b][nb][e] = 0.0;
+    // the column indices of a sweep are loaded one sweep ahead, so that each
+    // sweep waits for one round of loads (slab entries and x together)
+    int32_t ci[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int64_t c = 64 * w + 16 * g + u;
+        ci[u] = c < Q ? cols[c] : -1;
+    }
     for (int64_t c0 = 64 * w; c0 < Q; c0 += 256) {
         const int64_t cb = c0 + 16 * g;
         double av[RB][16];
-        int32_t ci[16];
+        int32_t cn[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const bool ok = cb + u < Q;
 #pragma unroll
             for (int b = 0; b < RB; ++b) av[b][u] = (ok && row_ok[b]) ? Nr[b][cb + u] : 0.0;
-            ci[u] = ok ? cols[cb + u] : -1;
+            cn[u] = (cb + 256 + u < Q) ? cols[cb + 256 + u] : -1;
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u)
@@ -325,6 +333,8 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
 #pragma unroll
                 for (int b = 0; b < RB; ++b) acc[b][nb] = Mfma<double>::mma(av[b][u], bv, acc[b][nb]);
             }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) ci[u] = cn[u];
     }
 #pragma unroll
     for (int b = 0; b < RB; ++b)

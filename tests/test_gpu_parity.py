@@ -229,6 +229,27 @@ def test_preconditioner_large_blocks_matches_oracle(case_wide_blocks, kind, k):
         assert e < max(1e-9, 1e-15 * kappa), (t, e, kappa)
 
 
+@pytest.mark.parametrize("k", [16, 32])
+def test_solve_wide_block_rows_matches_qr(k):
+    """Block rows of about 60 columns and slabs of up to 563 (4x3 subdomains,
+    full stencil): the matrix-core normal-matrix product over several column
+    sweeps and the local solves of large blocks inside CG, against QR per
+    right-hand side."""
+    _need_gpu()
+    prob = wl.small2d(l=(4, 3), m=(150, 171, 133, 164, 148, 177), k=k)
+    ref = osolve.reference(prob, "rel_eig", 1e-10)
+    sysm = ref["sys"]
+    assert sysm.P / prob.J >= 48
+    s = binding.Solver(prob, device=DEV)
+    s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
+    # the normal residual's FP64 floor here is about 5e-13 (any k)
+    W, info = s.solve(torch.as_tensor(prob.F, device=DEV), tol=1e-12, maxiter=5000)
+    assert info["status"] == 0
+    Wn = W.cpu().numpy()
+    for t in range(k):
+        assert rel(Wn[:, t], ref["W"][:, t]) <= 1e-8, t
+
+
 def test_mixed_batched_apply_close_to_fp64(case_small2d):
     """Mixed path against the FP64 oracle apply: one right-hand side at a time
     (FP64 arithmetic on the FP32 factor) and 32 at once (FP32 operands and
