@@ -151,6 +151,12 @@ struct Handle {
     int32_t* d_N_cols = nullptr;
     int2* d_slab_tasks = nullptr;   // (subdomain, first row) per product workgroup
     int64_t n_slab_tasks = 0;
+    // the slabs again in matrix-core operand order, per 16-row task: quad c
+    // of columns 4c .. 4c + 3 as 64 doubles (entry 16 g + r: row r, column
+    // 4c + g; zero past the slab)
+    double* d_Nt = nullptr;
+    int64_t* d_Nt_off = nullptr;    // device J+1
+    int64_t Nt_elems = 0;
     std::vector<std::vector<std::pair<int, int>>> pair_tab;  // j -> (k >= j, pair id)
     double* d_G = nullptr;
     void* d_pair_blocks = nullptr;

@@ -350,6 +350,28 @@ __global__ void __launch_bounds__(256) k_assemble_slab(const int32_t* __restrict
     }
 }
 
+// the 16 rows of slab task (j, r0) in matrix-core operand order: quad c of
+// columns 4c .. 4c + 3 as 64 doubles, entry 16 g + r = N_j[r0 + r][4c + g]
+// (zero past the slab)
+__global__ void __launch_bounds__(256) k_tile_slab(const int2* __restrict__ tasks, const int32_t* __restrict__ p,
+                                                   const int64_t* __restrict__ N_off,
+                                                   const int64_t* __restrict__ N_coff,
+                                                   const double* __restrict__ N, const int64_t* __restrict__ Nt_off,
+                                                   double* __restrict__ Nt) {
+    const int2 tk = tasks[blockIdx.x];
+    const int j = tk.x, r0 = tk.y;
+    const int pj = p[j];
+    const int64_t Q = N_coff[j + 1] - N_coff[j];
+    const int64_t nq4 = (Q + 3) / 4;
+    double* out = Nt + Nt_off[j] + (int64_t)(r0 / 16) * nq4 * 64;
+    const double* Nj = N + N_off[j];
+    for (int64_t e = threadIdx.x; e < nq4 * 64; e += 256) {
+        const int64_t c = 4 * (e / 64) + (e % 64) / 16;
+        const int r = r0 + (int)(e % 16);
+        out[e] = (r < pj && c < Q) ? Nj[(int64_t)r * Q + c] : 0.0;
+    }
+}
+
 }  // namespace
 
 int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g_off) {
@@ -564,6 +586,22 @@ int normal_blocks(Handle& h) {
     h.n_slab_tasks = (int64_t)tasks.size();
     RDD_TRY(dev_alloc(h, &h.d_slab_tasks, tasks.size()));
     RDD_TRY(upload(h, h.d_slab_tasks, tasks.data(), sizeof(int2) * tasks.size()));
+    // the slabs in matrix-core operand order (the batched product reads them)
+    {
+        std::vector<int64_t> nt_off(J + 1, 0);
+        for (int j = 0; j < J; ++j) {
+            const int64_t nq4 = (h.N_coff[j + 1] - h.N_coff[j] + 3) / 4;
+            nt_off[j + 1] = nt_off[j] + (int64_t)((h.p[j] + kSlabRows - 1) / kSlabRows) * nq4 * 64;
+        }
+        h.Nt_elems = nt_off[J];
+        RDD_TRY(dev_alloc(h, &h.d_Nt_off, (size_t)J + 1));
+        RDD_TRY(dev_alloc(h, &h.d_Nt, (size_t)std::max<int64_t>(1, h.Nt_elems)));
+        RDD_TRY(upload(h, h.d_Nt_off, nt_off.data(), sizeof(int64_t) * (J + 1)));
+        if (h.n_slab_tasks)
+            hipLaunchKernelGGL(k_tile_slab, dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream, h.d_slab_tasks,
+                               h.d_p, h.d_N_off, h.d_N_coff, h.d_N, h.d_Nt_off, h.d_Nt);
+        RDD_HIP(hipGetLastError());
+    }
     RDD_HIP(hipStreamSynchronize(h.stream));
     for (void* ptr : {(void*)d_cnt, (void*)d_lj, (void*)d_lk, (void*)d_tiles, (void*)d_no, (void*)d_nf,
                       (void*)d_np, (void*)d_nc})

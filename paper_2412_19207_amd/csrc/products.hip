@@ -254,28 +254,29 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
     }
 }
 
-// Batched right-hand sides (KC = 16 or 32): the kSlabRows slab rows of a task
-// (RB blocks of 16) times x (Q x KC) on the FP64 matrix cores.  Wave w takes
-// the 64-column sweeps w, w + 4, ...; lane l = 16 g + lr supplies rows
-// r0 + 16 b + lr at columns c0 + 16 g + s (A operands, K index 16 g + s at
-// step s) and the x rows of the same columns (B operand, read straight from
-// global memory once for the RB row blocks: within the task each x row feeds
+// Batched right-hand sides (KC = 16 or 32): the 16 slab rows of a task times
+// x (Q x KC) on the FP64 matrix cores, from the slab in MFMA operand order
+// (Nt: per task, quad c of columns 4c .. 4c + 3 as 64 consecutive doubles,
+// entry l = 16 g + lr holding row r0 + lr, column 4c + g, zero past the slab),
+// so that each A operand is one coalesced 512-byte load.  Wave w takes the
+// 64-column sweeps w, w + 4, ...; at step u of a sweep lane (lr, g) supplies
+// quad c0 / 4 + u of the A operand and the x row of column c0 + 4u + g (B
+// operand, read straight from global memory: within the task each x row feeds
 // one wave only).  The 4 waves' sums meet in LDS.
 template <int KC>
 __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks,
                                                   const int32_t* __restrict__ p,
                                                   const int64_t* __restrict__ col_off,
-                                                  const int64_t* __restrict__ N_off,
+                                                  const int64_t* __restrict__ Nt_off,
                                                   const int64_t* __restrict__ N_coff,
                                                   const int32_t* __restrict__ N_cols,
-                                                  const double* __restrict__ N,
+                                                  const double* __restrict__ Nt,
                                                   const double* __restrict__ x, int k, int k0,
                                                   double* __restrict__ s, double* __restrict__ part,
                                                   PUpd pu) {
     constexpr int NB = KC / 16;
-    constexpr int RB = kSlabRows / 16;
-    static_assert(kSlabRows % 16 == 0, "whole 16-row MFMA blocks per task");
-    __shared__ double red[4][kSlabRows][KC + 1];
+    static_assert(kSlabRows == 16, "one 16-row MFMA block per task");
+    __shared__ double red[4][16][KC + 1];
     __shared__ double dsh[256];
     __shared__ double beta_s[KC], rz_s[KC], rr_s[KC];
     __shared__ int act_s[KC];
@@ -284,42 +285,34 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
     const int j = tk.x, r0 = tk.y;
     const int pj = p[j];
     const int64_t Q = N_coff[j + 1] - N_coff[j];
+    const int64_t nq4 = (Q + 3) / 4;
     const int32_t* cols = N_cols + N_coff[j];
+    const double* At = Nt + Nt_off[j] + (int64_t)(r0 / 16) * nq4 * 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lr = lane & 15, g = lane >> 4;
-    bool row_ok[RB];
-    const double* Nr[RB];
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-        row_ok[b] = r0 + 16 * b + lr < pj;
-        Nr[b] = N + N_off[j] + (int64_t)(row_ok[b] ? r0 + 16 * b + lr : r0) * Q;
-    }
     typedef Mfma<double>::acc_t acc_t;
-    acc_t acc[RB][NB];
+    acc_t acc[NB];
 #pragma unroll
-    for (int b = 0; b < RB; ++b)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc[b][nb][e] = 0.0;
+        for (int e = 0; e < 4; ++e) acc[nb][e] = 0.0;
     // the column indices of a sweep are loaded one sweep ahead, so that each
     // sweep waits for one round of loads (slab entries and x together)
     int32_t ci[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-        const int64_t c = 64 * w + 16 * g + u;
+        const int64_t c = 64 * w + 4 * u + g;
         ci[u] = c < Q ? cols[c] : -1;
     }
     for (int64_t c0 = 64 * w; c0 < Q; c0 += 256) {
-        const int64_t cb = c0 + 16 * g;
-        double av[RB][16];
+        const int64_t q0 = c0 / 4;
+        double av[16];
         int32_t cn[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const bool ok = cb + u < Q;
-#pragma unroll
-            for (int b = 0; b < RB; ++b) av[b][u] = (ok && row_ok[b]) ? Nr[b][cb + u] : 0.0;
-            cn[u] = (cb + 256 + u < Q) ? cols[cb + 256 + u] : -1;
+            av[u] = (q0 + u < nq4) ? At[(q0 + u) * 64 + lane] : 0.0;
+            const int64_t c = c0 + 256 + 4 * u + g;
+            cn[u] = c < Q ? cols[c] : -1;
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u)
@@ -330,22 +323,19 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
                     const int64_t gi = (int64_t)ci[u] * k + k0 + 16 * nb + lr;
                     bv = pu.pprev ? pupd_value(pu, gi, 16 * nb + lr, beta_s, act_s) : x[gi];
                 }
-#pragma unroll
-                for (int b = 0; b < RB; ++b) acc[b][nb] = Mfma<double>::mma(av[b][u], bv, acc[b][nb]);
+                acc[nb] = Mfma<double>::mma(av[u], bv, acc[nb]);
             }
 #pragma unroll
         for (int u = 0; u < 16; ++u) ci[u] = cn[u];
     }
 #pragma unroll
-    for (int b = 0; b < RB; ++b)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) red[w][16 * b + Mfma<double>::out_row(lane, e)][16 * nb + lr] = acc[b][nb][e];
+        for (int e = 0; e < 4; ++e) red[w][Mfma<double>::out_row(lane, e)][16 * nb + lr] = acc[nb][e];
     __syncthreads();
     const int t = threadIdx.x % KC;
     double dotv = 0.0;
-    for (int rr = threadIdx.x / KC; rr < kSlabRows; rr += 256 / KC) {
+    for (int rr = threadIdx.x / KC; rr < 16; rr += 256 / KC) {
         const double v = (red[0][rr][t] + red[1][rr][t]) + (red[2][rr][t] + red[3][rr][t]);
         if (r0 + rr < pj) {
             const int64_t gi = (col_off[j] + r0 + rr) * k + k0 + t;
@@ -509,12 +499,12 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part, co
             if (h.n_slab_tasks) {
                 if (kc == 32)
                     hipLaunchKernelGGL((k_nrm_mfma<32>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,
-                                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff, h.d_N_cols,
-                                       h.d_N, x, k, k0, s, part, pu);
+                                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_Nt_off, h.d_N_coff, h.d_N_cols,
+                                       h.d_Nt, x, k, k0, s, part, pu);
                 else
                     hipLaunchKernelGGL((k_nrm_mfma<16>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,
-                                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff, h.d_N_cols,
-                                       h.d_N, x, k, k0, s, part, pu);
+                                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_Nt_off, h.d_N_coff, h.d_N_cols,
+                                       h.d_Nt, x, k, k0, s, part, pu);
             }
             k0 += kc;
             continue;

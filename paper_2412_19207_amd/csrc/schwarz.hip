@@ -426,10 +426,11 @@ __global__ void __launch_bounds__(256) k_trirow_apply(const int2* __restrict__ t
 // over the stored tiles (a, b), b <= a, and the transposes of the tiles
 // (b, a), b > a.  Every tile off the diagonal is read by two workgroups.  Both
 // kinds of tile go straight from global memory into the A operand: lane
-// (lr, g) of wave w takes row 16 w + lr at the columns 16 g + s (K index
-// 16 g + s at step s) of a stored tile (a 16-element run), or the same K
-// entries of column 16 w + lr of a transposed one (16 rows 64 apart, each
-// load reading 16 consecutive entries across the lanes).  The x segment of
+// (lr, g) of wave w takes row 16 w + lr of a stored tile at the columns
+// 8 (s / 2) + 2 g + s % 2 (K index at step s; the four lanes of a row read 64
+// consecutive bytes per load), or column 16 w + lr of a transposed one at the
+// rows 16 g + s (16 rows 64 apart, each load reading 16 consecutive entries
+// across the lanes).  The x segment of
 // tile b is staged in one of two LDS buffers while tile b - 1 is multiplied
 // (one barrier per tile); the next tile is loaded meanwhile.
 template <int KC>
@@ -452,9 +453,20 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
     const int lr = lane & 15, g = lane >> 4;
     const double* Wi = W + t_off[i];
     const int32_t* cols = blk_cols + ub_off[i];
+    // a stored tile's row 16 w + lr is read as 8 pairs: at step s lane
+    // (lr, g) supplies K index 8 (s / 2) + 2 g + s % 2, so that the lanes of
+    // a row read 64 consecutive bytes per load; a transposed tile's K index is
+    // 16 g + s (16 consecutive entries across the lanes of each g)
     auto load_w = [&](int b, double* v) {
         if (b <= a) {
-            load16(Wi + ((int64_t)a * (a + 1) / 2 + b) * kTE + (16 * w + lr) * kT + 16 * g, v);
+            const double2* src = reinterpret_cast<const double2*>(
+                Wi + ((int64_t)a * (a + 1) / 2 + b) * kTE + (16 * w + lr) * kT + 2 * g);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const double2 t2 = src[4 * e];
+                v[2 * e] = t2.x;
+                v[2 * e + 1] = t2.y;
+            }
         } else {
             const double* T = Wi + ((int64_t)b * (b + 1) / 2 + a) * kTE + (16 * g) * kT + 16 * w + lr;
 #pragma unroll
@@ -508,10 +520,19 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
             if (b + 2 < nt) load_cols(b + 2, cn);
         }
         const int buf = b & 1;
+        if (b <= a) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s)
+            for (int s = 0; s < 16; ++s)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<double>::mma(v[s], xs[buf][16 * g + s][16 * nb + lr], Z[nb]);
+                for (int nb = 0; nb < NB; ++nb)
+                    Z[nb] = Mfma<double>::mma(v[s], xs[buf][8 * (s >> 1) + 2 * g + (s & 1)][16 * nb + lr], Z[nb]);
+        } else {
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    Z[nb] = Mfma<double>::mma(v[s], xs[buf][16 * g + s][16 * nb + lr], Z[nb]);
+        }
         if (more) {
             put_x(buf ^ 1, xr);
 #pragma unroll
