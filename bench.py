@@ -509,8 +509,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only: every GPU box here has one GPU, "
-                                   "so --gpus must be 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark measures one GPU only (the multi-GPU sharding is a "
+                                   "design, not built), so --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2412_19207_amd import binding
