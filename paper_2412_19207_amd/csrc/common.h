@@ -333,13 +333,16 @@ int64_t eig_scratch_elems(int m);
 int feature_rows(Handle& h);
 // several hidden layers (deep.hip): set-up from the descriptor, the value
 // matrices (slot kRecW) or probe values (slot kRecP0) of a point set into out
-// (n_j x m_j at d_out_off[j]), the operator rows H (and H32), and the probe
-// evaluation: y = per-pair values (x: raw coefficients, sum_m x k) or, with
-// transpose, y = raw-coefficient gradient (x: per point, M x k)
+// (n_j x m_j at d_out_off[j]), the operator rows H (and H32)
 int deep_setup(Handle& h, const rann_dd_desc* ds);
 int deep_values(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_off, double* out);
 int deep_feature_rows(Handle& h);
-int deep_eval(Handle& h, const PointSet& ps, const double* x, int k, double* y, bool transpose);
+// the same values for one or several hidden layers (gemm.hip)
+int values_matrix(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_off, double* out);
+// probe evaluation through the explicit probe values T_j and batched
+// products: y = per-pair values (x: raw coefficients, sum_m x k) or, with
+// transpose, y = raw-coefficient gradient (x: per point, M x k)
+int eval_explicit(Handle& h, const PointSet& ps, const double* x, int k, double* y, bool transpose);
 int build_schwarz(Handle& h);
 template <class T>
 int local_blocks(Handle& h, const T* H, T* A_out);

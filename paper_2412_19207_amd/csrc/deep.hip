@@ -17,8 +17,9 @@
 // The contractions with R_j are FP64 matrix-core products over K = w
 // (k_deep_rows; the value matrix of the PCA and the probe values take C0 only,
 // k_deep_values).  The explicit rows then multiply V_j like any other batched
-// product (k_seg_gemm), which also serves the probe values and their
-// transpose.
+// product (k_seg_gemm), which also serves the explicit probe evaluation and
+// its transpose (eval_explicit, for layered networks and for batched
+// right-hand sides of one-layer networks).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -445,7 +446,7 @@ int deep_feature_rows(Handle& h) {
     return RANN_OK;
 }
 
-int deep_eval(Handle& h, const PointSet& ps, const double* x, int k, double* y, bool transpose) {
+int eval_explicit(Handle& h, const PointSet& ps, const double* x, int k, double* y, bool transpose) {
     const int J = h.geo.J;
     std::vector<int64_t> t_off(J + 1, 0);
     for (int j = 0; j < J; ++j) t_off[j + 1] = t_off[j] + (ps.row_off[j + 1] - ps.row_off[j]) * h.m[j];
@@ -455,7 +456,7 @@ int deep_eval(Handle& h, const PointSet& ps, const double* x, int k, double* y, 
     RDD_TRY(dev_alloc(h, &T, (size_t)std::max<int64_t>(1, t_off[J])));
     RDD_TRY(upload(h, d_t_off, t_off.data(), sizeof(int64_t) * (J + 1)));
     // T_j[i][f] = L(x_i) w_j(x_i) phi_f(x_i) at the probe pairs
-    RDD_TRY(deep_values(h, ps, kRecP0, d_t_off, T));
+    RDD_TRY(values_matrix(h, ps, kRecP0, d_t_off, T));
     std::vector<SegDesc> segs(J);
     int rc = RANN_OK;
     if (!transpose) {

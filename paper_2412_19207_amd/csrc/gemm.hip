@@ -31,10 +31,11 @@ __device__ __forceinline__ double feature_z(const double* Rk, double bk, const d
     return z;
 }
 
-// Psi_j[i][f] = w_j(x_i) tanh(z_f(x_i)), row-major n_j x m_j, for the 16 pair
-// rows of workgroup (j, chunk); each value is computed once
+// Psi_j[i][f] = rec_i[slot] tanh(z_f(x_i)), row-major n_j x m_j, for the 16
+// pair rows of workgroup (j, chunk); each value is computed once.  slot: the
+// window (value matrix of the PCA) or L w_j (probe values)
 __global__ void __launch_bounds__(256) k_psi(Geo g, const int64_t* __restrict__ row_off,
-                                             const double* __restrict__ rec, const int32_t* __restrict__ m,
+                                             const double* __restrict__ rec, int slot, const int32_t* __restrict__ m,
                                              const int64_t* __restrict__ m_off, const double* __restrict__ Rf,
                                              const double* __restrict__ bf, const int64_t* __restrict__ psi_off,
                                              double* __restrict__ Psi) {
@@ -50,7 +51,7 @@ __global__ void __launch_bounds__(256) k_psi(Geo g, const int64_t* __restrict__ 
         if (i < n) {
             double xt[kMaxDim] = {0, 0, 0, 0};
             for (int q = 0; q < g.d; ++q) xt[q] = rj[i * kPairRec + kRecX + q];
-            const double w = rj[i * kPairRec + kRecW];
+            const double w = rj[i * kPairRec + slot];
             const int64_t gf = m_off[j] + f;
             out[i * mj + f] = w * tanh(feature_z(Rf + gf * 4, bf[gf], xt, g.d));
         }
@@ -374,6 +375,17 @@ __global__ void __launch_bounds__(256) k_tile_slab(const int2* __restrict__ task
 
 }  // namespace
 
+int values_matrix(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_off, double* out) {
+    if (h.deep.n > 0) return deep_values(h, ps, slot, d_out_off, out);
+    int64_t max_n = 0;
+    for (int j = 0; j < h.geo.J; ++j) max_n = std::max(max_n, ps.row_off[j + 1] - ps.row_off[j]);
+    if (max_n > 0)
+        hipLaunchKernelGGL(k_psi, dim3(h.geo.J, (unsigned)((max_n + 15) / 16)), dim3(256), 0, h.stream, h.geo,
+                           ps.d_row_off, ps.d_rec, slot, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, d_out_off, out);
+    RDD_HIP(hipGetLastError());
+    return RANN_OK;
+}
+
 int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g_off) {
     (void)g_off_host;
     std::vector<GramTile> tiles;
@@ -399,11 +411,9 @@ int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g
     RDD_TRY(dev_alloc(h, &d_psi_off, (size_t)J + 1));
     RDD_TRY(dev_alloc(h, &d_psi, (size_t)std::max<int64_t>(1, psi_off[J])));
     RDD_TRY(upload(h, d_psi_off, psi_off.data(), sizeof(int64_t) * (J + 1)));
-    if (h.deep.n > 0) RDD_TRY(deep_values(h, h.pts, kRecW, d_psi_off, d_psi));
+    (void)max_n;
     KTimer kt_(h.stream, "k_pca_gram");
-    if (max_n > 0 && h.deep.n == 0)
-        hipLaunchKernelGGL(k_psi, dim3(J, (unsigned)((max_n + 15) / 16)), dim3(256), 0, h.stream, h.geo,
-                           h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, d_psi_off, d_psi);
+    RDD_TRY(values_matrix(h, h.pts, kRecW, d_psi_off, d_psi));
     hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, d_t, h.pts.d_row_off,
                        h.d_m, d_psi_off, d_psi, d_g_off, G);
     kt_.stop();

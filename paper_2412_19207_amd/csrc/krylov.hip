@@ -1905,16 +1905,17 @@ int eval_points(Handle& h, const double* Xq, int64_t M, const double* Lq, const 
     double* val = nullptr;
     if (rc == RANN_OK) rc = dev_alloc(h, &cf, (size_t)h.sum_m * k);
     if (rc == RANN_OK && !transpose) rc = dev_alloc(h, &val, (size_t)ps.pairs * k);
-    if (rc == RANN_OK && h.deep.n > 0) {
-        // several hidden layers: explicit probe values times the coefficients
+    if (rc == RANN_OK && (h.deep.n > 0 || k >= 8)) {
+        // several hidden layers, or batched right-hand sides: the explicit
+        // probe values (once) times the coefficients on the matrix cores
         if (!transpose) {
             rc = coeffs_raw(h, W, k, cf, false);
-            if (rc == RANN_OK) rc = deep_eval(h, ps, cf, k, val, false);
+            if (rc == RANN_OK) rc = eval_explicit(h, ps, cf, k, val, false);
             if (rc == RANN_OK)
                 hipLaunchKernelGGL(k_point_sum, dim3(grid_for(M * k)), dim3(256), 0, h.stream, M, k,
                                    ps.d_cover_off, ps.d_cover, val, U);
         } else {
-            rc = deep_eval(h, ps, W, k, cf, true);
+            rc = eval_explicit(h, ps, W, k, cf, true);
             if (rc == RANN_OK) rc = coeffs_raw(h, cf, k, U, true);
         }
     } else if (rc == RANN_OK && !transpose) {

@@ -169,10 +169,11 @@ def test_cfg3_full_size_parity_batched():
     right-hand sides in one batched solve, FP64 and mixed."""
     _need_gpu()
     assert _prob("cfg3").F.shape[1] == 32
-    # to stagnation: the GPU's floor of the normal residual is about 2e-10 for
-    # the f = 1 column and 3e-11 to 1e-10 for the sine series (the oracle's
-    # refined PCG: 3e-11)
-    _full_size_parity("cfg3", ["fp64", "mixed"], {"fp64": 1e-8, "mixed": 1e-6}, gpu_tol=1e-11, floor=3e-10)
+    # to stagnation: the GPU's floor of the normal residual is 2e-10 to 4e-10
+    # for the f = 1 column (it moves with the summation order of the normal
+    # product's matrix-core sums) and 3e-11 to 1e-10 for the sine series (the
+    # oracle's refined PCG: 3e-11)
+    _full_size_parity("cfg3", ["fp64", "mixed"], {"fp64": 1e-8, "mixed": 1e-6}, gpu_tol=1e-11, floor=5e-10)
 
 
 def test_deep2d_full_size_parity():

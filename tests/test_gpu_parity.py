@@ -463,15 +463,19 @@ def test_cfg1_full_size_fp64():
 
 
 # ------------------------------------------------------------------ a10 adjoint, a11 eval
-def test_eval_and_transpose(case_small2d):
+@pytest.mark.parametrize("k", [3, 16])
+def test_eval_and_transpose(case_small2d, k):
+    """Probe values and their transpose against the oracle's probe matrix: per
+    pair (k = 3) and through the explicit probe values and batched products
+    (k = 16)."""
     prob, ref = case_small2d
     sysm = ref["sys"]
     s = binding.Solver(prob, device=DEV)
     s.pca(1e-10, p_force=sysm.p, V_force=vforce(sysm))
     Pm = oasm.probe_matrix(prob, sysm, prob.probes)
     rng = np.random.default_rng(2)
-    W = rng.standard_normal((sysm.P, 3))
-    dU = rng.standard_normal((prob.probes.shape[0], 3))
+    W = rng.standard_normal((sysm.P, k))
+    dU = rng.standard_normal((prob.probes.shape[0], k))
     Xq = torch.as_tensor(prob.probes, device=DEV)
     U = s.eval(Xq, torch.as_tensor(W, device=DEV)).cpu().numpy()
     dW = s.eval_T(Xq, torch.as_tensor(dU, device=DEV)).cpu().numpy()
