@@ -116,6 +116,8 @@ struct Handle {
     double* d_H = nullptr;         // nnz FP64
     float* d_H32 = nullptr;        // nnz FP32 (mixed precision with FP32 local Gram blocks only)
     float* d_G32 = nullptr;        // their Gram blocks (set-up only)
+    double* d_T = nullptr;         // tanh of every (pair, feature) from the PCA's value matrices,
+    int64_t* d_T_off = nullptr;    // n_j x m_j per subdomain, kept for the operator rows (set-up only)
 
     // Schwarz blocks
     std::vector<std::vector<int>> sten;  // stencil of each block (ascending)
@@ -338,7 +340,9 @@ int deep_setup(Handle& h, const rann_dd_desc* ds);
 int deep_values(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_off, double* out);
 int deep_feature_rows(Handle& h);
 // the same values for one or several hidden layers (gemm.hip)
-int values_matrix(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_off, double* out);
+// (with T and one hidden layer: the tanh values themselves into T as well)
+int values_matrix(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_off, double* out,
+                  double* T = nullptr);
 // probe evaluation through the explicit probe values T_j and batched
 // products: y = per-pair values (x: raw coefficients, sum_m x k) or, with
 // transpose, y = raw-coefficient gradient (x: per point, M x k)

@@ -5,7 +5,9 @@
 //                  evaluated once into scratch memory, then multiplied by tiles.
 //  * k_feat_rows : H_j = A_j V_j with A_j[i,k] = A[L w_j phi_k](x_i) generated
 //                  in the GEMM prologue from the pair coefficients (eqs. (sum),
-//                  (system_new)); FP64 output plus an FP32 copy in the mixed path.
+//                  (system_new)) and the tanh values the PCA's value matrices
+//                  kept (computed again when the PCA did not run); FP64
+//                  output plus an FP32 copy in the mixed path.
 //                  (Networks with several hidden layers take deep.hip instead,
 //                  for both products.)
 //  * k_local_gram: Gram blocks G_jk = H_j^T H_k over the rows the two supports
@@ -33,12 +35,13 @@ __device__ __forceinline__ double feature_z(const double* Rk, double bk, const d
 
 // Psi_j[i][f] = rec_i[slot] tanh(z_f(x_i)), row-major n_j x m_j, for the 16
 // pair rows of workgroup (j, chunk); each value is computed once.  slot: the
-// window (value matrix of the PCA) or L w_j (probe values)
+// window (value matrix of the PCA) or L w_j (probe values).  With T, the
+// tanh values themselves too (kept for the operator rows).
 __global__ void __launch_bounds__(256) k_psi(Geo g, const int64_t* __restrict__ row_off,
                                              const double* __restrict__ rec, int slot, const int32_t* __restrict__ m,
                                              const int64_t* __restrict__ m_off, const double* __restrict__ Rf,
                                              const double* __restrict__ bf, const int64_t* __restrict__ psi_off,
-                                             double* __restrict__ Psi) {
+                                             double* __restrict__ Psi, double* __restrict__ T) {
     const int j = blockIdx.x, mj = m[j];
     const int64_t n = row_off[j + 1] - row_off[j];
     const int64_t r0 = (int64_t)blockIdx.y * 16;
@@ -53,7 +56,9 @@ __global__ void __launch_bounds__(256) k_psi(Geo g, const int64_t* __restrict__ 
             for (int q = 0; q < g.d; ++q) xt[q] = rj[i * kPairRec + kRecX + q];
             const double w = rj[i * kPairRec + slot];
             const int64_t gf = m_off[j] + f;
-            out[i * mj + f] = w * tanh(feature_z(Rf + gf * 4, bf[gf], xt, g.d));
+            const double th = tanh(feature_z(Rf + gf * 4, bf[gf], xt, g.d));
+            out[i * mj + f] = w * th;
+            if (T) T[psi_off[j] + i * mj + f] = th;
         }
     }
 }
@@ -101,7 +106,9 @@ __global__ void __launch_bounds__(256) k_feat_rows(Geo g, const GramTile* __rest
                                                    const int64_t* __restrict__ v_off,
                                                    const double* __restrict__ V,
                                                    const int64_t* __restrict__ h_off,
-                                                   double* __restrict__ H, float* __restrict__ H32) {
+                                                   double* __restrict__ H, float* __restrict__ H32,
+                                                   const double* __restrict__ T,
+                                                   const int64_t* __restrict__ t_off) {
     __shared__ double As[kTK][kTM + kPad];
     __shared__ double Bs[kTK][kTN + kPad];
     const GramTile t = tiles[blockIdx.x];
@@ -133,7 +140,8 @@ __global__ void __launch_bounds__(256) k_feat_rows(Geo g, const GramTile* __rest
             if (rv && f < mj) {
                 int64_t gf = m_off[j] + f;
                 const double* Rk = Rf + gf * 4;
-                double th = tanh(feature_z(Rk, bf[gf], xt, g.d));
+                // the tanh values the PCA kept, when it ran
+                const double th = T ? T[t_off[j] + row * mj + f] : tanh(feature_z(Rk, bf[gf], xt, g.d));
                 double s = 1.0 - th * th;
                 double g1 = 0.0, g2 = 0.0;
                 for (int q = 0; q < g.d; ++q) {
@@ -375,13 +383,13 @@ __global__ void __launch_bounds__(256) k_tile_slab(const int2* __restrict__ task
 
 }  // namespace
 
-int values_matrix(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_off, double* out) {
+int values_matrix(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_off, double* out, double* T) {
     if (h.deep.n > 0) return deep_values(h, ps, slot, d_out_off, out);
     int64_t max_n = 0;
     for (int j = 0; j < h.geo.J; ++j) max_n = std::max(max_n, ps.row_off[j + 1] - ps.row_off[j]);
     if (max_n > 0)
         hipLaunchKernelGGL(k_psi, dim3(h.geo.J, (unsigned)((max_n + 15) / 16)), dim3(256), 0, h.stream, h.geo,
-                           ps.d_row_off, ps.d_rec, slot, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, d_out_off, out);
+                           ps.d_row_off, ps.d_rec, slot, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, d_out_off, out, T);
     RDD_HIP(hipGetLastError());
     return RANN_OK;
 }
@@ -412,8 +420,14 @@ int pca_gram(Handle& h, double* G, const int64_t* g_off_host, const int64_t* d_g
     RDD_TRY(dev_alloc(h, &d_psi, (size_t)std::max<int64_t>(1, psi_off[J])));
     RDD_TRY(upload(h, d_psi_off, psi_off.data(), sizeof(int64_t) * (J + 1)));
     (void)max_n;
+    // one hidden layer: the tanh values are kept for the operator rows
+    if (h.deep.n == 0 && !h.d_T) {
+        RDD_TRY(dev_alloc(h, &h.d_T_off, (size_t)J + 1));
+        RDD_TRY(dev_alloc(h, &h.d_T, (size_t)std::max<int64_t>(1, psi_off[J])));
+        RDD_TRY(upload(h, h.d_T_off, psi_off.data(), sizeof(int64_t) * (J + 1)));
+    }
     KTimer kt_(h.stream, "k_pca_gram");
-    RDD_TRY(values_matrix(h, h.pts, kRecW, d_psi_off, d_psi));
+    RDD_TRY(values_matrix(h, h.pts, kRecW, d_psi_off, d_psi, h.d_T));
     hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, d_t, h.pts.d_row_off,
                        h.d_m, d_psi_off, d_psi, d_g_off, G);
     kt_.stop();
@@ -441,11 +455,17 @@ int feature_rows(Handle& h) {
     KTimer kt_(h.stream, "k_feat_rows");
     hipLaunchKernelGGL(k_feat_rows, dim3((unsigned)tiles.size()), dim3(256), 0, h.stream, h.geo, d_t,
                        h.pts.d_row_off, h.pts.d_rec, h.d_m, h.d_m_off, h.d_Rf, h.d_bf, h.d_p,
-                       h.d_v_off, h.d_V, h.d_h_off, h.d_H, h.d_H32);
+                       h.d_v_off, h.d_V, h.d_h_off, h.d_H, h.d_H32, h.d_T, h.d_T_off);
     kt_.stop();
     RDD_HIP(hipGetLastError());
     RDD_HIP(hipStreamSynchronize(h.stream));
     dev_free(h, d_t);
+    if (h.d_T) {  // the tanh values of the PCA serve these rows only
+        dev_free(h, h.d_T);
+        dev_free(h, h.d_T_off);
+        h.d_T = nullptr;
+        h.d_T_off = nullptr;
+    }
     return RANN_OK;
 }
 

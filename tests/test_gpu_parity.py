@@ -120,6 +120,32 @@ def test_rows_match_oracle_with_forced_basis(name):
         assert np.max(np.abs(G - B)) <= 1e-11 * scale, j
 
 
+@pytest.mark.parametrize("name", ["small2d", "small3d"])
+def test_rows_with_own_pca_match_oracle_in_gpu_basis(name):
+    """Rows built after the library's own PCA (from the tanh values its value
+    matrices kept) against the oracle's rows in the library's basis."""
+    _need_gpu()
+    prob = make(name)
+    tol = prob.meta.get("pca_tol") or 1e-10
+    s = binding.Solver(prob, device=DEV)
+    p = s.pca(tol, "rel_eig")
+    blocks, V, _ = s.arrays()
+    blocks, V = blocks.cpu().numpy(), V.cpu().numpy()
+    Vg, off = [], 0
+    for j in range(prob.J):
+        m = int(prob.m[j])
+        Vg.append(V[off:off + m * p[j]].reshape(m, p[j]))
+        off += m * p[j]
+    sysg = oasm.assemble(prob, "rel_eig", tol, V_force=Vg)
+    scale = max(np.abs(b).max() for b in sysg.blocks)
+    o = 0
+    for j in range(prob.J):
+        B = sysg.blocks[j]
+        G = blocks[o:o + B.size].reshape(B.shape)
+        o += B.size
+        assert np.max(np.abs(G - B)) <= 1e-11 * scale, j
+
+
 def test_rows_raw_features_without_pca():
     _need_gpu()
     prob = wl.small2d()
