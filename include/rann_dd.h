@@ -212,7 +212,9 @@ RANN_API int rann_dd_assemble(const rann_dd_desc* desc, void* hip_stream, rann_d
  *            from p_force) or NULL: inject a PCA basis (requires p_force).
  *   p_out    host J or NULL: receives p_j.
  * Synchronous.  Returns RANN_WRANKTIE if an eigenvalue lies within relative
- * 1e-6 of the threshold. */
+ * 1e-6 of the threshold.  Device scratch during the call: the value matrices
+ * and, with one hidden layer, their tanh values for the operator rows
+ * (sum_j n_j m_j doubles each, n_j the points in support j). */
 RANN_API int rann_dd_pca(rann_dd_handle* h, double tol, int32_t mode, const int32_t* p_force,
                 const double* V_force, int32_t* p_out);
 
