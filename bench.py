@@ -505,6 +505,36 @@ def cpu_baseline(prob, tol, stencil, gpu_iters, sample_iters=10):
                 threads=threads, measured_s=t2 - t0)
 
 
+def cpu_reference_extras(wl):
+    """The oracle's dense path beside the sampled PCG baseline: assembly, PCA
+    and its own dense Householder QR least squares on the 1D Poisson workload
+    (full size) with every host thread and with one, and on the multiscale
+    workload scaled down to 4x4 subdomains (the dense H of the full size does
+    not fit the host)."""
+    from oracle import solve as osolve
+    out = {}
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # threadpoolctl missing: no one-thread run
+        threadpool_limits = None
+
+    def timed(prob):
+        t0 = time.perf_counter()
+        ref = osolve.reference(prob, "rel_eig", prob.meta["pca_tol"])
+        return time.perf_counter() - t0, int(ref["sys"].P), int(prob.N)
+
+    s, P, N = timed(wl.make("cfg1"))
+    out["poisson1d_l4_m50_dense_qr"] = {"seconds": s, "rows": N, "columns": P, "threads": "all"}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            s1, _, _ = timed(wl.make("cfg1"))
+        out["poisson1d_l4_m50_dense_qr_one_thread"] = {"seconds": s1, "rows": N, "columns": P, "threads": 1}
+    s, P, N = timed(wl.make("cfg3", l=[4, 4]))
+    out["multiscale2d_4x4_dense_qr"] = {"seconds": s, "rows": N, "columns": P, "threads": "all",
+                                        "right_hand_sides": 32}
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -651,6 +681,7 @@ def main():
                                          f"{int(info['iterations'])} iterations the GPU needed for {args.tol:g}",
                                "seconds_per_step": cb["total_s"], "seconds_measured": cb["measured_s"],
                                "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
+        out["cpu_baseline"]["dense_reference"] = cpu_reference_extras(wl)
     print(json.dumps(out))
 
 
