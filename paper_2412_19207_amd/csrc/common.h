@@ -347,6 +347,9 @@ int values_matrix(Handle& h, const PointSet& ps, int slot, const int64_t* d_out_
 // products: y = per-pair values (x: raw coefficients, sum_m x k) or, with
 // transpose, y = raw-coefficient gradient (x: per point, M x k)
 int eval_explicit(Handle& h, const PointSet& ps, const double* x, int k, double* y, bool transpose);
+// raw-neuron coefficients c_j = V_j W_j (or, with transpose, V_j^T c_j) as
+// batched matrix-core products
+int coeffs_batched(Handle& h, const double* x, int k, double* y, bool transpose);
 int build_schwarz(Handle& h);
 template <class T>
 int local_blocks(Handle& h, const T* H, T* A_out);

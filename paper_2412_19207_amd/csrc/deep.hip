@@ -446,6 +446,21 @@ int deep_feature_rows(Handle& h) {
     return RANN_OK;
 }
 
+int coeffs_batched(Handle& h, const double* x, int k, double* y, bool transpose) {
+    const int J = h.geo.J;
+    std::vector<SegDesc> segs(J);
+    bool empty = false;
+    for (int j = 0; j < J; ++j) {
+        empty |= h.p[j] == 0;
+        if (!transpose)  // c_j (m_j x k) = V_j (m_j x p_j) W_j (p_j x k)
+            segs[j] = SegDesc{h.v_off[j], h.col_off[j] * k, h.m_off[j] * k, h.m[j], h.p[j], k, h.p[j], k, k};
+        else  // W_j (p_j x k) = V_j^T c_j, V_j read as stored (m_j x p_j)
+            segs[j] = SegDesc{h.v_off[j], h.m_off[j] * k, h.col_off[j] * k, h.p[j], h.m[j], k, h.p[j], k, k};
+    }
+    if (empty && !transpose) RDD_HIP(hipMemsetAsync(y, 0, sizeof(double) * h.sum_m * k, h.stream));
+    return launch_seg(h, segs, transpose, h.d_V, x, y, nullptr);
+}
+
 int eval_explicit(Handle& h, const PointSet& ps, const double* x, int k, double* y, bool transpose) {
     const int J = h.geo.J;
     std::vector<int64_t> t_off(J + 1, 0);

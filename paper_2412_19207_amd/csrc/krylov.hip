@@ -1878,6 +1878,7 @@ int krylov_lanczos(Handle& h, const double* rhs, const double* Fs, int k, const 
 
 // ------------------------------------------------------------------ probes
 int coeffs_raw(Handle& h, const double* W, int k, double* c, bool transpose) {
+    if (k >= 8) return coeffs_batched(h, W, k, c, transpose);  // batched right-hand sides: matrix cores
     if (!transpose) {
         hipLaunchKernelGGL(k_coeffs, dim3((unsigned)((h.sum_m * k + 15) / 16)), dim3(256), 0, h.stream, h.sum_m, k,
                            h.d_feat_sub, h.d_m_off, h.d_p, h.d_v_off, h.d_col_off, h.d_V, W, c);
