@@ -12,28 +12,32 @@
 namespace rdd {
 
 // res[t] = sum over the nparts partials part[b * k + k0 + t], for t < kb:
-// the 256 / kb threads of each t read 16 partials at a time into 8
-// accumulators; accumulators and threads meet in a fixed-order tree
+// the 256 / kb threads of each t read 32 partials per round, all in flight
+// together (the last round's surplus loads re-read the last partial and are
+// discarded, so that no load waits behind a branch), into 8 accumulators;
+// accumulators and threads meet in a fixed-order tree
 __device__ inline void sum_partials_kb(const double* part, int nparts, int k, int k0, int kb, double* res,
                                        double* sh) {
+    constexpr int kR = 32;
     const int per = 256 / kb;
     const int t = threadIdx.x % kb, ro = threadIdx.x / kb;
     double acc[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = 0.0;
     if (ro < per) {
-        // 16 loads in flight per round, two per accumulator
-        int b = ro;
-        for (; b + 15 * per < nparts; b += 16 * per) {
-            double v[16];
+        for (int b = ro; b < nparts; b += kR * per) {
+            double v[kR];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(b + u * per) * k + k0 + t];
+            for (int u = 0; u < kR; ++u) {
+                const int bu = b + u * per;
+                v[u] = part[(int64_t)(bu < nparts ? bu : nparts - 1) * k + k0 + t];
+            }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += v[u] + v[u + 8];
+            for (int u = 0; u < kR; ++u)
+                if (b + u * per >= nparts) v[u] = 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += (v[u] + v[u + 8]) + (v[u + 16] + v[u + 24]);
         }
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            if (b + u * per < nparts) acc[u & 7] += part[(int64_t)(b + u * per) * k + k0 + t];
     }
     const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     if (kb <= 64 && (kb & (kb - 1)) == 0) {
@@ -81,24 +85,28 @@ struct PUpd {
 };
 
 // beta and activity for the right-hand sides k0 .. k0 + kb - 1 into
-// beta_s / act_s (shared); workgroup 0 also writes the bookkeeping
+// beta_s / act_s (shared); workgroup 0 also writes the bookkeeping.  The
+// per-right-hand-side state is loaded before the partials are added.
 __device__ inline void pupd_begin(const PUpd& u, int k, int k0, int kb, double* beta_s, int* act_s, double* rz_s,
                                   double* rr_s, double* sh) {
+    const bool lead = threadIdx.x < kb;
+    const int t = k0 + (lead ? (int)threadIdx.x : 0);
+    const int act = u.act_in[t];
+    const double rho = u.rho_in[t];
+    const double tl2 = u.tol2[t], b2 = u.bn2[t];
     sum_partials_kb(u.partC, u.nC, k, k0, kb, rz_s, sh);
     if (blockIdx.x == 0) sum_partials_kb(u.partB, u.nB, k, k0, kb, rr_s, sh);
-    if (threadIdx.x < kb) {
-        const int t = k0 + threadIdx.x;
-        const int act = u.act_in[t];
+    if (lead) {
         const double rz = rz_s[threadIdx.x];
-        beta_s[threadIdx.x] = act ? rz / u.rho_in[t] : 0.0;
+        beta_s[threadIdx.x] = act ? rz / rho : 0.0;
         act_s[threadIdx.x] = act;
         if (blockIdx.x == 0) {
             const double rr = rr_s[threadIdx.x];
-            u.rho_out[t] = act ? rz : u.rho_in[t];
-            u.act_out[t] = (act && !(rr <= u.tol2[t] * u.bn2[t])) ? 1 : 0;
+            u.rho_out[t] = act ? rz : rho;
+            u.act_out[t] = (act && !(rr <= tl2 * b2)) ? 1 : 0;
             if (act) {
                 u.iters[t] += 1;
-                u.rres[t] = sqrt(rr / u.bn2[t]);
+                u.rres[t] = sqrt(rr / b2);
             }
         }
     }

@@ -487,52 +487,9 @@ __device__ void block_partial_by_rhs(double val, int k, double* sh, double* out,
     __syncthreads();
 }
 
-// res[t] = sum over the nparts partials, for t < k.  The 256 / k threads of
-// each t read 16 partials at a time (independent loads in flight) into 8
-// accumulators; accumulators and threads meet in a fixed-order tree.
-__device__ void sum_partials(const double* part, int nparts, int k, double* res, double* sh) {
-    const int per = 256 / k;
-    const int t = threadIdx.x % k, ro = threadIdx.x / k;
-    double acc[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-    if (ro < per) {
-        // 16 loads in flight per round, two per accumulator
-        int b = ro;
-        for (; b + 15 * per < nparts; b += 16 * per) {
-            double v[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(b + u * per) * k + t];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += v[u] + v[u + 8];
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            if (b + u * per < nparts) acc[u & 7] += part[(int64_t)(b + u * per) * k + t];
-    }
-    const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    if (k <= 64 && (k & (k - 1)) == 0) {
-        // the lanes of a wave that share t differ in the bits from k up: a
-        // butterfly over those, then the four waves through LDS
-        double w = a;
-        for (int off = 32; off >= k; off >>= 1) w += __shfl_xor(w, off);
-        const int lane = threadIdx.x & 63;
-        if (lane < k) sh[(threadIdx.x >> 6) * k + lane] = w;
-        __syncthreads();
-        if (threadIdx.x < k)
-            res[threadIdx.x] = (sh[threadIdx.x] + sh[k + threadIdx.x]) +
-                               (sh[2 * k + threadIdx.x] + sh[3 * k + threadIdx.x]);
-        __syncthreads();
-        return;
-    }
-    sh[threadIdx.x] = (ro < per) ? a : 0.0;
-    __syncthreads();
-    for (int st = 1; st < per; st <<= 1) {
-        if (ro < per && (ro % (2 * st)) == 0 && ro + st < per) sh[threadIdx.x] += sh[threadIdx.x + st * k];
-        __syncthreads();
-    }
-    if (threadIdx.x < k) res[threadIdx.x] = sh[threadIdx.x];
-    __syncthreads();
+// res[t] = sum over the nparts partials part[b * k + t], for t < k
+__device__ inline void sum_partials(const double* part, int nparts, int k, double* res, double* sh) {
+    sum_partials_kb(part, nparts, k, 0, k, res, sh);
 }
 
 // Element-wise loop over idx = i0, i0 + stride, ... < n, four entries per
@@ -545,7 +502,9 @@ __device__ void sum_partials(const double* part, int nparts, int k, double* res,
         }                                                                              \
     }
 
-// alpha = rho / <p, s> (from nA partials); x += alpha p; r -= alpha s; partials of <r, r>
+// alpha = rho / <p, s> (from nA partials); x += alpha p; r -= alpha s; partials of <r, r>.
+// The operands of each thread's first four entries are loaded before the
+// partials are summed (their loads do not wait for alpha).
 __global__ void __launch_bounds__(256) k_cg_xr2(int64_t P, int k, int nA, const double* __restrict__ partA,
                                                 const double* __restrict__ rho_in,
                                                 const int32_t* __restrict__ active_in,
@@ -555,6 +514,20 @@ __global__ void __launch_bounds__(256) k_cg_xr2(int64_t P, int k, int nA, const 
                                                 int32_t* __restrict__ flags) {
     __shared__ double sh[256];
     __shared__ double al[256];
+    const int64_t stride = rhs_stride(k);
+    const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
+    const int64_t n = P * k;
+    const bool live = i0 < stride;
+    double pv[4], sv[4], xv[4], rv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t idx = i0 + u * stride;
+        const int64_t ic = (live && idx < n) ? idx : 0;
+        pv[u] = p[ic];
+        sv[u] = s[ic];
+        xv[u] = x[ic];
+        rv[u] = r[ic];
+    }
     sum_partials(partA, nA, k, al, sh);
     if (threadIdx.x < k) {
         const int t = threadIdx.x;
@@ -571,17 +544,24 @@ __global__ void __launch_bounds__(256) k_cg_xr2(int64_t P, int k, int nA, const 
         al[t] = a;
     }
     __syncthreads();
-    const int64_t stride = rhs_stride(k);
-    const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
-    const int64_t n = P * k;
     double acc = 0.0;
-    if (i0 < stride) {
+    if (live) {
         const double a = al[i0 % k];
-        RDD_EW_LOOP(i0, stride, n, {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t idx = i0 + u * stride;
+            if (idx < n) {
+                x[idx] = fma(a, pv[u], xv[u]);
+                const double rn = fma(-a, sv[u], rv[u]);
+                r[idx] = rn;
+                acc = fma(rn, rn, acc);
+            }
+        }
+        RDD_EW_LOOP(i0 + 4 * stride, stride, n, {
             x[idx] = fma(a, p[idx], x[idx]);
-            const double rv = fma(-a, s[idx], r[idx]);
-            r[idx] = rv;
-            acc = fma(rv, rv, acc);
+            const double rn = fma(-a, s[idx], r[idx]);
+            r[idx] = rn;
+            acc = fma(rn, rn, acc);
         })
     }
     block_partial_by_rhs(acc, k, sh, partB);

@@ -262,8 +262,13 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
 // 64-column sweeps w, w + 4, ...; at step u of a sweep lane (lr, g) supplies
 // quad c0 / 4 + u of the A operand and the x row of column c0 + 4u + g (B
 // operand, read straight from global memory: within the task each x row feeds
-// one wave only).  The 4 waves' sums meet in LDS.
-template <int KC>
+// one wave only).  The 4 waves' sums meet in LDS.  The loads that do not need
+// the direction update (column indices, A operands, the own rows' entries)
+// are issued before its partial sums are added, so that the chain of
+// dependent memory rounds is: those loads, then the x rows (all of a sweep's
+// in flight together: absent columns load row 0 and are discarded).  UPD: x
+// is the direction p_new = z + beta p_prev of the previous iteration.
+template <int KC, bool UPD>
 __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks,
                                                   const int32_t* __restrict__ p,
                                                   const int64_t* __restrict__ col_off,
@@ -275,12 +280,12 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
                                                   double* __restrict__ s, double* __restrict__ part,
                                                   PUpd pu) {
     constexpr int NB = KC / 16;
+    constexpr int kOwn = 16 * KC / 256;  // own-row entries per thread
     static_assert(kSlabRows == 16, "one 16-row MFMA block per task");
     __shared__ double red[4][16][KC + 1];
     __shared__ double dsh[256];
     __shared__ double beta_s[KC], rz_s[KC], rr_s[KC];
     __shared__ int act_s[KC];
-    if (pu.pprev) pupd_begin(pu, k, k0, KC, beta_s, act_s, rz_s, rr_s, dsh);
     const int2 tk = tasks[blockIdx.x];
     const int j = tk.x, r0 = tk.y;
     const int pj = p[j];
@@ -290,64 +295,98 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
     const double* At = Nt + Nt_off[j] + (int64_t)(r0 / 16) * nq4 * 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lr = lane & 15, g = lane >> 4;
+    // first round: column indices (this sweep and the next), A operands and
+    // the own rows' entries of x (or of p_prev and z)
+    int32_t ci[16], cn[16];
+    double av[16];
+    const int64_t c00 = 64 * w;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int64_t c = c00 + 4 * u + g;
+        ci[u] = c < Q ? cols[c] : -1;
+        const int64_t c2 = c + 256;
+        cn[u] = c2 < Q ? cols[c2] : -1;
+        av[u] = (c00 / 4 + u < nq4) ? At[(c00 / 4 + u) * 64 + lane] : 0.0;
+    }
+    const int t = threadIdx.x % KC;
+    double own_a[kOwn], own_b[kOwn];
+#pragma unroll
+    for (int v = 0; v < kOwn; ++v) {
+        const int rr = threadIdx.x / KC + (256 / KC) * v;
+        const int64_t gi = (col_off[j] + (r0 + rr < pj ? r0 + rr : pj - 1)) * k + k0 + t;
+        own_a[v] = UPD ? pu.pprev[gi] : x[gi];
+        own_b[v] = UPD ? pu.z[gi] : 0.0;
+    }
+    double bet[NB];
+    bool act[NB];
+    if (UPD) {
+        pupd_begin(pu, k, k0, KC, beta_s, act_s, rz_s, rr_s, dsh);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            bet[nb] = beta_s[16 * nb + lr];
+            act[nb] = act_s[16 * nb + lr] != 0;
+        }
+    }
+    const double* xa_src = UPD ? pu.pprev : x;
     typedef Mfma<double>::acc_t acc_t;
     acc_t acc[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[nb][e] = 0.0;
-    // the column indices of a sweep are loaded one sweep ahead, so that each
-    // sweep waits for one round of loads (slab entries and x together)
-    int32_t ci[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int64_t c = 64 * w + 4 * u + g;
-        ci[u] = c < Q ? cols[c] : -1;
-    }
-    for (int64_t c0 = 64 * w; c0 < Q; c0 += 256) {
-        const int64_t q0 = c0 / 4;
-        double av[16];
-        int32_t cn[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            av[u] = (q0 + u < nq4) ? At[(q0 + u) * 64 + lane] : 0.0;
-            const int64_t c = c0 + 256 + 4 * u + g;
-            cn[u] = c < Q ? cols[c] : -1;
-        }
+    for (int64_t c0 = c00; c0 < Q; c0 += 256) {
+        // the x rows of this sweep
+        double bv[16][NB], zb[UPD ? 16 : 1][NB];
 #pragma unroll
         for (int u = 0; u < 16; ++u)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                double bv = 0.0;
-                if (ci[u] >= 0) {
-                    const int64_t gi = (int64_t)ci[u] * k + k0 + 16 * nb + lr;
-                    bv = pu.pprev ? pupd_value(pu, gi, 16 * nb + lr, beta_s, act_s) : x[gi];
-                }
-                acc[nb] = Mfma<double>::mma(av[u], bv, acc[nb]);
+                const int64_t gi = (int64_t)(ci[u] >= 0 ? ci[u] : 0) * k + k0 + 16 * nb + lr;
+                bv[u][nb] = xa_src[gi];
+                if (UPD) zb[u][nb] = pu.z[gi];
             }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) ci[u] = cn[u];
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                double b = bv[u][nb];
+                if (UPD && act[nb]) b = fma(bet[nb], b, zb[u][nb]);
+                bv[u][nb] = ci[u] >= 0 ? b : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[nb] = Mfma<double>::mma(av[u], bv[u][nb], acc[nb]);
+        if (c0 + 256 < Q) {  // the next sweep's A operands and the column indices after it
+            const int64_t q0 = (c0 + 256) / 4;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                av[u] = (q0 + u < nq4) ? At[(q0 + u) * 64 + lane] : 0.0;
+                ci[u] = cn[u];
+                const int64_t c = c0 + 512 + 4 * u + g;
+                cn[u] = c < Q ? cols[c] : -1;
+            }
+        }
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) red[w][Mfma<double>::out_row(lane, e)][16 * nb + lr] = acc[nb][e];
     __syncthreads();
-    const int t = threadIdx.x % KC;
     double dotv = 0.0;
-    for (int rr = threadIdx.x / KC; rr < 16; rr += 256 / KC) {
-        const double v = (red[0][rr][t] + red[1][rr][t]) + (red[2][rr][t] + red[3][rr][t]);
+#pragma unroll
+    for (int v = 0; v < kOwn; ++v) {
+        const int rr = threadIdx.x / KC + (256 / KC) * v;
+        const double val = (red[0][rr][t] + red[1][rr][t]) + (red[2][rr][t] + red[3][rr][t]);
         if (r0 + rr < pj) {
             const int64_t gi = (col_off[j] + r0 + rr) * k + k0 + t;
-            s[gi] = v;
-            double xv;
-            if (pu.pprev) {
-                xv = pupd_value(pu, gi, t, beta_s, act_s);
+            s[gi] = val;
+            double xv = own_a[v];
+            if (UPD) {
+                xv = act_s[t] ? fma(beta_s[t], own_a[v], own_b[v]) : own_a[v];
                 pu.pcur[gi] = xv;
-            } else {
-                xv = x[gi];
             }
-            dotv = fma(v, xv, dotv);
+            dotv = fma(val, xv, dotv);
         }
     }
     if (part) {
@@ -497,14 +536,17 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part, co
         if (rem >= 16) {  // matrix cores, 32 or 16 right-hand sides per launch
             const int kc = rem >= 32 ? 32 : 16;
             if (h.n_slab_tasks) {
-                if (kc == 32)
-                    hipLaunchKernelGGL((k_nrm_mfma<32>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,
-                                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_Nt_off, h.d_N_coff, h.d_N_cols,
-                                       h.d_Nt, x, k, k0, s, part, pu);
-                else
-                    hipLaunchKernelGGL((k_nrm_mfma<16>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,
-                                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_Nt_off, h.d_N_coff, h.d_N_cols,
-                                       h.d_Nt, x, k, k0, s, part, pu);
+#define RDD_NM(KCV, UPDV)                                                                              \
+    hipLaunchKernelGGL((k_nrm_mfma<KCV, UPDV>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,     \
+                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_Nt_off, h.d_N_coff, h.d_N_cols, h.d_Nt, x, k, \
+                       k0, s, part, pu)
+                const bool upd = pu.pprev != nullptr;
+                if (kc == 32) {
+                    if (upd) RDD_NM(32, true); else RDD_NM(32, false);
+                } else {
+                    if (upd) RDD_NM(16, true); else RDD_NM(16, false);
+                }
+#undef RDD_NM
             }
             k0 += kc;
             continue;

@@ -563,6 +563,30 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
 // w / 4 + 2, ..., accumulating each in registers over b and storing it; the
 // next product's tile rows are loaded while the current one is multiplied.
 constexpr int kBlkNT = 6;
+
+// Stages x = r[cols[row]][k0 .. k0 + KC) of one block (rows < q; zero rows up
+// to kBlkNT tiles) into LDS with the workgroup's 512 threads: every column
+// index of a thread's rows first, then all of its loads in flight, then the
+// LDS stores.
+template <int KC, typename T>
+__device__ __forceinline__ void stage_block_x(T (*xs)[KC + 1], const int32_t* __restrict__ cols,
+                                              const double* __restrict__ r, int64_t q, int k, int k0) {
+    constexpr int kSE = kBlkNT * kT * KC / 512;
+    static_assert(kSE * 512 == kBlkNT * kT * KC, "whole rows per sweep");
+    const int tid = threadIdx.x, t = tid % KC;
+    int32_t c[kSE];
+#pragma unroll
+    for (int m = 0; m < kSE; ++m) {
+        const int row = (tid + 512 * m) / KC;
+        c[m] = (row < q) ? cols[row] : -1;
+    }
+    double x[kSE];
+#pragma unroll
+    for (int m = 0; m < kSE; ++m) x[m] = (c[m] >= 0) ? r[(int64_t)c[m] * k + k0 + t] : 0.0;
+#pragma unroll
+    for (int m = 0; m < kSE; ++m) xs[(tid + 512 * m) / KC][t] = (T)x[m];
+}
+
 template <int KC>
 __global__ void __launch_bounds__(512) k_blk_mfma64(const int32_t* __restrict__ blocks,
                                                     const int64_t* __restrict__ t_off,
@@ -582,10 +606,6 @@ __global__ void __launch_bounds__(512) k_blk_mfma64(const int32_t* __restrict__ 
     const int rg = w & 3, half = w >> 2;
     const double* Wi = W + t_off[i];
     const int32_t* cols = blk_cols + ub_off[i];
-    for (int e = tid; e < nt * kT * KC; e += 512) {
-        const int row = e / KC, t = e % KC;
-        xs[row][t] = (row < q) ? r[(int64_t)cols[row] * k + k0 + t] : 0.0;
-    }
     // this wave's products: (a, b) for a = half, half + 2, ..., b = 0 .. nt - 1
     const int na = (nt - half + 1) / 2;
     const int njobs = na * nt;
@@ -607,6 +627,7 @@ __global__ void __launch_bounds__(512) k_blk_mfma64(const int32_t* __restrict__ 
         for (int e = 0; e < 4; ++e) Z[nb][e] = 0.0;
     double v[16], vn[16];
     if (njobs > 0) load_job(0, v);
+    stage_block_x<KC>(xs, cols, r, q, k, k0);
     __syncthreads();  // x staged
     double* zi = z + ub_off[i] * k + k0;
     for (int jb = 0; jb < njobs; ++jb) {
@@ -660,10 +681,7 @@ __global__ void __launch_bounds__(512) k_blk_mfma32(const int32_t* __restrict__ 
     const int rg = w & 3, half = w >> 2;
     const float* Yi = Y + t_off[i];
     const int32_t* cols = blk_cols + ub_off[i];
-    for (int e = tid; e < nt * kT * KC; e += 512) {
-        const int row = e / KC, t = e % KC;
-        xs[row][t] = (row < q) ? (float)r[(int64_t)cols[row] * k + k0 + t] : 0.0f;
-    }
+    stage_block_x<KC>(xs, cols, r, q, k, k0);
     typedef Mfma<float>::acc_t acc_t;
     // pass 1 jobs (a, b), b <= a, for a = half, half + 2, ...; pass 2 jobs
     // (c, a), a >= c, for c = half, half + 2, ...  Job lists are walked by
