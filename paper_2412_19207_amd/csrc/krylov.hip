@@ -669,7 +669,9 @@ __global__ void __launch_bounds__(256) k_gather_seg(int k, int Y, const int32_t*
 }
 
 // beta = <r,z> / rho, rho and activity update (workgroup 0 writes the state of
-// the next iteration into the other buffer), p = z + beta p
+// the next iteration into the other buffer), p = z + beta p.  The state and
+// the operands of each thread's first four entries are loaded before the
+// partials are summed.
 __global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, int nB, int nC, const double* __restrict__ partB,
                                                const double* __restrict__ partC,
                                                const double* __restrict__ bn2,
@@ -683,31 +685,48 @@ __global__ void __launch_bounds__(256) k_cg_p2(int64_t P, int k, int nB, int nC,
     __shared__ double sh[256];
     __shared__ double rr[256];
     __shared__ double rz[256];
+    const int64_t stride = rhs_stride(k);
+    const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
+    const int64_t n = P * k;
+    const bool live = i0 < stride;
+    double pv[4], zv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t idx = i0 + u * stride;
+        const int64_t ic = (live && idx < n) ? idx : 0;
+        pv[u] = p[ic];
+        zv[u] = z[ic];
+    }
+    const int tl = threadIdx.x < k ? (int)threadIdx.x : 0;
+    const int act_l = active_in[tl];
+    const double rho_l = rho_in[tl], tol2_l = tol2[tl], bn2_l = bn2[tl];
     sum_partials(partB, nB, k, rr, sh);
     sum_partials(partC, nC, k, rz, sh);
     if (threadIdx.x < k) {
         const int t = threadIdx.x;
-        const int act = active_in[t];
-        const double b = act ? rz[t] / rho_in[t] : 0.0;
+        const double b = act_l ? rz[t] / rho_l : 0.0;
         if (blockIdx.x == 0) {
-            rho_out[t] = act ? rz[t] : rho_in[t];
-            active_out[t] = (act && !(rr[t] <= tol2[t] * bn2[t])) ? 1 : 0;
-            if (act) {
+            rho_out[t] = act_l ? rz[t] : rho_l;
+            active_out[t] = (act_l && !(rr[t] <= tol2_l * bn2_l)) ? 1 : 0;
+            if (act_l) {
                 iters[t] += 1;
-                rres[t] = sqrt(rr[t] / bn2[t]);
+                rres[t] = sqrt(rr[t] / bn2_l);
             }
         }
-        rz[t] = b;  // reuse as beta
+        rz[t] = act_l ? b : 0.0;  // reuse as beta
+        rr[t] = act_l ? 1.0 : 0.0;  // reuse as the activity
     }
     __syncthreads();
-    const int64_t stride = rhs_stride(k);
-    const int64_t i0 = blockIdx.x * 256LL + threadIdx.x;
-    const int64_t n = P * k;
-    if (i0 < stride) {
+    if (live) {
         const int t = (int)(i0 % k);
-        if (active_in[t]) {
+        if (rr[t] != 0.0) {
             const double b = rz[t];
-            RDD_EW_LOOP(i0, stride, n, { p[idx] = fma(b, p[idx], z[idx]); })
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t idx = i0 + u * stride;
+                if (idx < n) p[idx] = fma(b, pv[u], zv[u]);
+            }
+            RDD_EW_LOOP(i0 + 4 * stride, stride, n, { p[idx] = fma(b, p[idx], z[idx]); })
         }
     }
 }

@@ -144,8 +144,9 @@ __global__ void __launch_bounds__(256) k_HTy_chunk(const int32_t* __restrict__ c
 
 // s = N x from the slabs of N = H^T H: workgroup = kSlabRows rows of block row
 // j, each wave kSlabRows / 4 rows (loaded together), x gathered through the
-// slab's column list and staged in LDS; optional per-workgroup <x, s>.
-template <int KB>
+// slab's column list and staged in LDS; optional per-workgroup <x, s>.  UPD:
+// x is the direction p_new = z + beta p_prev of the previous iteration.
+template <int KB, bool UPD>
 __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks,
                                                   const int32_t* __restrict__ p,
                                                   const int64_t* __restrict__ col_off,
@@ -162,7 +163,7 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
     __shared__ double red[4][KB];
     __shared__ double beta_s[KB], rz_s[KB], rr_s[KB], psh[256];
     __shared__ int act_s[KB];
-    if (pu.pprev) pupd_begin(pu, k, k0, KB, beta_s, act_s, rz_s, rr_s, psh);
+    if (UPD) pupd_begin(pu, k, k0, KB, beta_s, act_s, rz_s, rr_s, psh);
     const int2 tk = tasks[blockIdx.x];
     const int j = tk.x, r0 = tk.y;
     const int pj = p[j];
@@ -182,18 +183,29 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
     for (int64_t c0 = 0; c0 < Q; c0 += kXS) {
         const int nc = (Q - c0 < kXS) ? (int)(Q - c0) : kXS;
         __syncthreads();
-        // 4 entries per thread and round, so that their loads are in flight together
+        // 4 entries per thread and round, so that their loads are in flight
+        // together (entries past the pass re-read its last one and are dropped)
+        const double* xa_src = UPD ? pu.pprev : x;
         for (int e0 = threadIdx.x; e0 < nc * KB; e0 += 4 * 256) {
             int64_t gi[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int e = e0 + v * 256;
-                gi[v] = (e < nc * KB) ? (int64_t)cols[c0 + e / KB] * k + k0 + e % KB : -1;
+                const int e = min(e0 + v * 256, nc * KB - 1);
+                gi[v] = (int64_t)cols[c0 + e / KB] * k + k0 + e % KB;
+            }
+            double xa[4], xb[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                xa[v] = xa_src[gi[v]];
+                xb[v] = UPD ? pu.z[gi[v]] : 0.0;
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int e = e0 + v * 256;
-                if (gi[v] >= 0) xs[e / KB][e % KB] = pu.pprev ? pupd_value(pu, gi[v], e % KB, beta_s, act_s) : x[gi[v]];
+                if (e < nc * KB) {
+                    const int t = e % KB;
+                    xs[e / KB][t] = (UPD && act_s[t]) ? fma(beta_s[t], xa[v], xb[v]) : xa[v];
+                }
             }
         }
         __syncthreads();
@@ -218,34 +230,38 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
             }
         }
     }
-    double dotv[KB];
-#pragma unroll
-    for (int t = 0; t < KB; ++t) dotv[t] = 0.0;
+    // the wave's kRW x KB results: lane l < kRW KB owns row u = l / KB,
+    // right-hand side t = l % KB; its entry of x (or of p_prev and z) is
+    // loaded before the sums are formed
+    static_assert(kRW * KB <= 64 && (KB & (KB - 1)) == 0, "one result per lane");
+    const int lu = lane / KB, lt = lane % KB;
+    const bool own = lane < kRW * KB && lu < nrow;
+    const int64_t go = (col_off[j] + (own ? r0 + wave + 4 * lu : pj - 1)) * k + k0 + lt;
+    const double oa = UPD ? pu.pprev[go] : x[go];
+    const double ob = UPD ? pu.z[go] : 0.0;
+    double mine = 0.0;
 #pragma unroll
     for (int u = 0; u < kRW; ++u) {
 #pragma unroll
-        for (int t = 0; t < KB; ++t)
+        for (int t = 0; t < KB; ++t) {
             for (int off = 32; off > 0; off >>= 1) acc[u][t] += __shfl_xor(acc[u][t], off);
-        if (lane == 0 && u < nrow) {
-            const int64_t g = (col_off[j] + r0 + wave + 4 * u) * k + k0;
-#pragma unroll
-            for (int t = 0; t < KB; ++t) {
-                s[g + t] = acc[u][t];
-                double xv;
-                if (pu.pprev) {
-                    xv = pupd_value(pu, g + t, t, beta_s, act_s);
-                    pu.pcur[g + t] = xv;
-                } else {
-                    xv = x[g + t];
-                }
-                dotv[t] = fma(acc[u][t], xv, dotv[t]);
-            }
+            if (lane == u * KB + t) mine = acc[u][t];
         }
     }
+    double d = 0.0;
+    if (own) {
+        s[go] = mine;
+        double xv = oa;
+        if (UPD) {
+            xv = act_s[lt] ? fma(beta_s[lt], oa, ob) : oa;
+            pu.pcur[go] = xv;
+        }
+        d = mine * xv;
+    }
+    // lanes t, t + KB, t + 2 KB, t + 3 KB hold the kRW rows of right-hand side t
+    for (int off = KB; off < kRW * KB; off <<= 1) d += __shfl_xor(d, off);
     if (part) {
-        if (lane == 0)
-#pragma unroll
-            for (int t = 0; t < KB; ++t) red[wave][t] = dotv[t];
+        if (lane < KB) red[wave][lane] = d;
         __syncthreads();
         if (threadIdx.x < KB) {
             const int t = threadIdx.x;
@@ -552,10 +568,17 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part, co
             continue;
         }
         const int kb = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
-#define RDD_NS(KBV)                                                                                 \
-    hipLaunchKernelGGL((k_nrm_slab<KBV>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,   \
-                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff, h.d_N_cols, h.d_N, \
-                       x, k, k0, s, part, pu)
+#define RDD_NS(KBV)                                                                                       \
+    do {                                                                                                  \
+        if (pu.pprev)                                                                                     \
+            hipLaunchKernelGGL((k_nrm_slab<KBV, true>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0,     \
+                               h.stream, h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff,       \
+                               h.d_N_cols, h.d_N, x, k, k0, s, part, pu);                                 \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_nrm_slab<KBV, false>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0,    \
+                               h.stream, h.d_slab_tasks, h.d_p, h.d_col_off, h.d_N_off, h.d_N_coff,       \
+                               h.d_N_cols, h.d_N, x, k, k0, s, part, pu);                                 \
+    } while (0)
         if (h.n_slab_tasks) {
             switch (kb) {
                 case 8: RDD_NS(8); break;

@@ -567,7 +567,8 @@ constexpr int kBlkNT = 6;
 // Stages x = r[cols[row]][k0 .. k0 + KC) of one block (rows < q; zero rows up
 // to kBlkNT tiles) into LDS with the workgroup's 512 threads: every column
 // index of a thread's rows first, then all of its loads in flight, then the
-// LDS stores.
+// LDS stores.  Rows past q re-read row q - 1 and store zero, so that no load
+// sits behind a branch.
 template <int KC, typename T>
 __device__ __forceinline__ void stage_block_x(T (*xs)[KC + 1], const int32_t* __restrict__ cols,
                                               const double* __restrict__ r, int64_t q, int k, int k0) {
@@ -577,14 +578,17 @@ __device__ __forceinline__ void stage_block_x(T (*xs)[KC + 1], const int32_t* __
     int32_t c[kSE];
 #pragma unroll
     for (int m = 0; m < kSE; ++m) {
-        const int row = (tid + 512 * m) / KC;
-        c[m] = (row < q) ? cols[row] : -1;
+        const int64_t row = (tid + 512 * m) / KC;
+        c[m] = cols[row < q ? row : q - 1];
     }
     double x[kSE];
 #pragma unroll
-    for (int m = 0; m < kSE; ++m) x[m] = (c[m] >= 0) ? r[(int64_t)c[m] * k + k0 + t] : 0.0;
+    for (int m = 0; m < kSE; ++m) x[m] = r[(int64_t)c[m] * k + k0 + t];
 #pragma unroll
-    for (int m = 0; m < kSE; ++m) xs[(tid + 512 * m) / KC][t] = (T)x[m];
+    for (int m = 0; m < kSE; ++m) {
+        const int row = (tid + 512 * m) / KC;
+        xs[row][t] = (row < q) ? (T)x[m] : (T)0;
+    }
 }
 
 template <int KC>
@@ -777,12 +781,18 @@ __global__ void __launch_bounds__(256) k_urow_mfma32(const int2* __restrict__ ta
     const int lr = lane & 15, g = lane >> 4;
     const float* Ya = Y + t_off[i] + (int64_t)a * (a + 1) / 2 * kTE + (16 * w + lr) * kT + 16 * g;
     const int32_t* cols = blk_cols + ub_off[i];
-    auto load_x = [&](int b, float* xr) {
+    auto load_x = [&](int b, float* xr) {  // rows past q re-read row q - 1 and are discarded
+        double xd[XPT];
 #pragma unroll
         for (int m = 0; m < XPT; ++m) {
             const int e = threadIdx.x + 256 * m;
             const int64_t gc = (int64_t)b * kT + e / KC;
-            xr[m] = (gc < q) ? (float)r[(int64_t)cols[gc] * k + k0 + e % KC] : 0.0f;
+            xd[m] = r[(int64_t)cols[gc < q ? gc : q - 1] * k + k0 + e % KC];
+        }
+#pragma unroll
+        for (int m = 0; m < XPT; ++m) {
+            const int64_t gc = (int64_t)b * kT + (threadIdx.x + 256 * m) / KC;
+            xr[m] = (gc < q) ? (float)xd[m] : 0.0f;
         }
     };
     typedef Mfma<float>::acc_t acc_t;
