@@ -23,6 +23,18 @@ constexpr double kEdge = 1.0 - 1e-12;  // strict support test factor
 // inner hidden layers of every subdomain network (paper eq. (net)); n = 0: one
 // hidden layer acting on the normalised input
 constexpr int kMaxInner = 3, kMaxInnerWidth = 64;
+
+// The command processor hands workgroup b of a launch to XCD b % 8 (each XCD
+// with its own L2).  xcd_task(b, n) numbers the n workgroups so that each XCD
+// takes one contiguous eighth of a task list: tasks of neighbouring
+// subdomains, which read the same rows of the vectors, then share an L2.  A
+// bijection of 0 .. n - 1.
+__device__ __forceinline__ int xcd_task(int b, int n) {
+    constexpr int kXcd = 8;
+    const int x = b % kXcd, l = b / kXcd;
+    const int per = n / kXcd, rem = n % kXcd;
+    return x * per + (x < rem ? x : rem) + l;
+}
 struct DeepNet {             // passed by value to kernels
     int n = 0;               // inner layers
     int w[kMaxInner + 1] = {0, 0, 0, 0};  // w[0] = d, then the inner widths

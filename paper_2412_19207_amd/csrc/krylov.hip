@@ -613,7 +613,7 @@ __global__ void __launch_bounds__(256) k_gather_dot(int64_t P, int k, int identi
 // The Schwarz sum by subdomain: the p_j k entries of z that belong to subdomain
 // j are the weighted sum of contiguous segments of the block results, one per
 // block that uses j (in block order, as the gather lists add them).
-// Workgroup (j, y) of a grid of J Y takes the entries [y E, (y + 1) E) of
+// Workgroup (j, y) of a grid of J Y (numbered by XCD) takes the entries [y E, (y + 1) E) of
 // subdomain j with E = 4 L, L = (256 / k) k: thread x < L the entries
 // y E + x + L v, v < 4, all of right-hand side x % k.  With part, the
 // workgroup's partials of <r, z> go to part[(j Y + y) k + t].
@@ -626,7 +626,8 @@ __global__ void __launch_bounds__(256) k_gather_seg(int k, int Y, const int32_t*
                                                     double* __restrict__ z, double* __restrict__ part) {
     constexpr int kSB = 9;  // segments per round (a 2D full-stencil subdomain lies in 9 blocks)
     __shared__ double sh[256];
-    const int j = blockIdx.x / Y, y = blockIdx.x % Y;
+    const int wb = xcd_task(blockIdx.x, gridDim.x);
+    const int j = wb / Y, y = wb % Y;
     const int L = (256 / k) * k;
     const int64_t n = (int64_t)pv[j] * k;
     const int64_t s0 = seg_off[j], s1 = seg_off[j + 1];

@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
     __shared__ double beta_s[KB], rz_s[KB], rr_s[KB], psh[256];
     __shared__ int act_s[KB];
     if (UPD) pupd_begin(pu, k, k0, KB, beta_s, act_s, rz_s, rr_s, psh);
-    const int2 tk = tasks[blockIdx.x];
+    const int2 tk = tasks[xcd_task(blockIdx.x, gridDim.x)];
     const int j = tk.x, r0 = tk.y;
     const int pj = p[j];
     const int64_t Q = N_coff[j + 1] - N_coff[j];
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
     __shared__ double dsh[256];
     __shared__ double beta_s[KC], rz_s[KC], rr_s[KC];
     __shared__ int act_s[KC];
-    const int2 tk = tasks[blockIdx.x];
+    const int2 tk = tasks[xcd_task(blockIdx.x, gridDim.x)];
     const int j = tk.x, r0 = tk.y;
     const int pj = p[j];
     const int64_t Q = N_coff[j + 1] - N_coff[j];

@@ -520,19 +520,25 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
             if (b + 2 < nt) load_cols(b + 2, cn);
         }
         const int buf = b & 1;
+        // the B operands from LDS first (K order of the stored tile or of its
+        // transpose), then the matrix-core chain
+        double xb[16][NB];
         if (b <= a) {
 #pragma unroll
             for (int s = 0; s < 16; ++s)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    Z[nb] = Mfma<double>::mma(v[s], xs[buf][8 * (s >> 1) + 2 * g + (s & 1)][16 * nb + lr], Z[nb]);
+                for (int nb = 0; nb < NB; ++nb) xb[s][nb] = xs[buf][8 * (s >> 1) + 2 * g + (s & 1)][16 * nb + lr];
         } else {
 #pragma unroll
             for (int s = 0; s < 16; ++s)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    Z[nb] = Mfma<double>::mma(v[s], xs[buf][16 * g + s][16 * nb + lr], Z[nb]);
+                for (int nb = 0; nb < NB; ++nb) xb[s][nb] = xs[buf][16 * g + s][16 * nb + lr];
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<double>::mma(v[s], xb[s][nb], Z[nb]);
         if (more) {
             put_x(buf ^ 1, xr);
 #pragma unroll
@@ -637,11 +643,18 @@ __global__ void __launch_bounds__(512) k_blk_mfma64(const int32_t* __restrict__ 
     for (int jb = 0; jb < njobs; ++jb) {
         const int a = half + 2 * (jb / nt), b = jb % nt;
         if (jb + 1 < njobs) load_job(jb + 1, vn);
+        // all of the product's B operands from LDS first, so that the
+        // matrix-core chain does not wait on each read
+        double xb[16][NB];
 #pragma unroll
         for (int s = 0; s < 16; ++s)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                Z[nb] = Mfma<double>::mma(v[s], xs[b * kT + 16 * g + s][16 * nb + lr], Z[nb]);
+            for (int nb = 0; nb < NB; ++nb) xb[s][nb] = xs[b * kT + 16 * g + s][16 * nb + lr];
+        __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the chain
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<double>::mma(v[s], xb[s][nb], Z[nb]);
         if (b == nt - 1) {  // output tile a complete
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
@@ -730,11 +743,16 @@ __global__ void __launch_bounds__(512) k_blk_mfma32(const int32_t* __restrict__ 
             int o2 = o, in2 = in;
             const bool more = next_job(pass, o2, in2);
             if (more) load(pass, o2, in2, vn);
+            float xb[16][NB];  // B operands from LDS first
 #pragma unroll
             for (int s = 0; s < 16; ++s)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    Acc[nb] = Mfma<float>::mma(v[s], src[in * kT + 16 * g + s][16 * nb + lr], Acc[nb]);
+                for (int nb = 0; nb < NB; ++nb) xb[s][nb] = src[in * kT + 16 * g + s][16 * nb + lr];
+            __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the chain
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) Acc[nb] = Mfma<float>::mma(v[s], xb[s][nb], Acc[nb]);
             const bool last = (pass == 1) ? (in == o) : (in == nt - 1);
             if (last) {  // output tile o complete
 #pragma unroll
@@ -817,10 +835,16 @@ __global__ void __launch_bounds__(256) k_urow_mfma32(const int2* __restrict__ ta
             load16(Ya + (int64_t)(b + 1) * kTE, vn);
             load_x(b + 1, xr);
         }
+        float bo[16][NB];  // B operands from LDS first
 #pragma unroll
         for (int s = 0; s < 16; ++s)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) U[nb] = Mfma<float>::mma(v[s], xb[16 * g + s][16 * nb + lr], U[nb]);
+            for (int nb = 0; nb < NB; ++nb) bo[s][nb] = xb[16 * g + s][16 * nb + lr];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) U[nb] = Mfma<float>::mma(v[s], bo[s][nb], U[nb]);
         if (b < a)
 #pragma unroll
             for (int s = 0; s < 16; ++s) v[s] = vn[s];
@@ -889,12 +913,18 @@ __global__ void __launch_bounds__(256) k_zcol_mfma32(const int2* __restrict__ ta
             load16(Yi + ((int64_t)(a + 1) * (a + 2) / 2 + c) * kTE, vn);
             load_u(a + 1, ur);
         }
+        float ao[16], bo[16][NB];  // operands from LDS first
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
-            const float av = ts[16 * g + s][16 * w + lr];
+            ao[s] = ts[16 * g + s][16 * w + lr];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<float>::mma(av, us[16 * g + s][16 * nb + lr], Z[nb]);
+            for (int nb = 0; nb < NB; ++nb) bo[s][nb] = us[16 * g + s][16 * nb + lr];
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<float>::mma(ao[s], bo[s][nb], Z[nb]);
         if (a + 1 < nt)
 #pragma unroll
             for (int s = 0; s < 16; ++s) v[s] = vn[s];
