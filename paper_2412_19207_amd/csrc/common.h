@@ -141,8 +141,9 @@ struct Handle {
     std::vector<int64_t> t_off;    // J+1 offsets of the packed lower tiles
     int64_t tile_elems = 0;        // sum nt_i (nt_i + 1) / 2 * 4096
     int64_t* d_t_off = nullptr;
-    double* d_M64 = nullptr;       // Y_i = L_i^{-1} D_i, packed tiles, FP64
-    float* d_M32 = nullptr;        // the same in FP32 (mixed)
+    double* d_M64 = nullptr;       // W_i = A_i^{-1}, packed lower tiles, FP64
+    float* d_M32 = nullptr;        // Y_i = L_i^{-1} D_i (A_i^{-1} = Y_i^T Y_i), packed tiles, FP32 (mixed)
+    float* d_W32 = nullptr;        // W_i in FP32 (mixed, blocks of at most 6 tiles per edge)
     ApplyPlan ap;                  // the preconditioner M^{-1}
     ApplyPlan apT;                 // RAS only: its transpose M^{-T} (masked input, full local results)
     int64_t slot_total = 0;        // row- or column-sum slots per right-hand side (sum nt(nt+1)/2 * 64)

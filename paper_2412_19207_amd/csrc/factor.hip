@@ -261,7 +261,8 @@ __global__ void k_make_Y(const TileTask* __restrict__ tasks, const int64_t* __re
 
 // packed tile (a, b), b <= a, of W = A^{-1} = D X^T X D: sum over the rows t >= a0
 // of X[t][a0 + r] X[t][b0 + c] (X is lower triangular), scaled by D on both
-// sides; a diagonal tile is written whole and exactly symmetric
+// sides, in FP64; a diagonal tile is written whole and exactly symmetric, as T
+template <class T>
 __global__ void __launch_bounds__(kFT) k_make_W(const TileTask* __restrict__ tasks,
                                                 const int64_t* __restrict__ f_off,
                                                 const int64_t* __restrict__ qv,
@@ -269,7 +270,7 @@ __global__ void __launch_bounds__(kFT) k_make_W(const TileTask* __restrict__ tas
                                                 const int64_t* __restrict__ t_off,
                                                 const double* __restrict__ Xall,
                                                 const double* __restrict__ Dall,
-                                                double* __restrict__ Wt) {
+                                                T* __restrict__ Wt) {
     __shared__ double As[kBK][kTM + kPad];
     __shared__ double Bs[kBK][kTN + kPad];
     __shared__ double Cs[kTM][kTM + kPad];
@@ -280,7 +281,7 @@ __global__ void __launch_bounds__(kFT) k_make_W(const TileTask* __restrict__ tas
     const int ab = tile_dim(q, a), bb = tile_dim(q, b);
     const double* X = Xall + f_off[i];
     const double* D = Dall + ub_off[i];
-    double* out = Wt + t_off[i] + ((int64_t)a * (a + 1) / 2 + b) * kTM * kTM;
+    T* out = Wt + t_off[i] + ((int64_t)a * (a + 1) / 2 + b) * kTM * kTM;
     TileAcc<double> acc;
     acc.zero();
     tile_gemm<double, true, true>(acc, As, Bs, X, q, a0, a0, ab, X, q, a0, b0, bb, (int)(q - a0));
@@ -290,7 +291,7 @@ __global__ void __launch_bounds__(kFT) k_make_W(const TileTask* __restrict__ tas
     __syncthreads();
     for (int e = threadIdx.x; e < kTM * kTM; e += kFT) {
         const int r = e / kTM, c = e % kTM;
-        out[e] = (a == b && c > r) ? Cs[c][r] : Cs[r][c];
+        out[e] = (T)((a == b && c > r) ? Cs[c][r] : Cs[r][c]);
     }
 }
 
@@ -438,7 +439,8 @@ int factor_tiles(Handle& h, double* A, double* W) {
                                    d_tasks + dist[t].off, h.d_f_off, h.d_q, W, A);
         RDD_HIP(hipGetLastError());
     }
-    // Y = X D (mixed, FP32) or W = Y^T Y (FP64) in packed lower tiles
+    // Y = X D (mixed, FP32; with W = Y^T Y in FP32 as well for blocks of at
+    // most 6 tiles) or W = Y^T Y (FP64) in packed lower tiles
     {
         std::vector<TileTask> tasks;
         for (int i = 0; i < J; ++i)
@@ -448,13 +450,17 @@ int factor_tiles(Handle& h, double* A, double* W) {
         RDD_TRY(upload_tasks(h, tasks, &d_tasks));
         task_bufs.push_back(d_tasks);
         if (!tasks.empty()) {
-            if (h.precision == RANN_MIXED)
+            if (h.precision == RANN_MIXED) {
                 hipLaunchKernelGGL(k_make_Y<float>, dim3((unsigned)tasks.size()), dim3(256), 0,
                                    h.stream, d_tasks, h.d_f_off, h.d_q, h.d_ub_off, h.d_t_off, A,
                                    d_D, h.d_M32);
-            else
-                hipLaunchKernelGGL(k_make_W, dim3((unsigned)tasks.size()), dim3(kFT), 0, h.stream,
+                if (h.d_W32)
+                    hipLaunchKernelGGL(k_make_W<float>, dim3((unsigned)tasks.size()), dim3(kFT), 0, h.stream,
+                                       d_tasks, h.d_f_off, h.d_q, h.d_ub_off, h.d_t_off, A, d_D, h.d_W32);
+            } else {
+                hipLaunchKernelGGL(k_make_W<double>, dim3((unsigned)tasks.size()), dim3(kFT), 0, h.stream,
                                    d_tasks, h.d_f_off, h.d_q, h.d_ub_off, h.d_t_off, A, d_D, h.d_M64);
+            }
         }
         RDD_HIP(hipGetLastError());
     }

@@ -559,15 +559,6 @@ __global__ void __launch_bounds__(256) k_rowcol_mfma64(const int2* __restrict__ 
         }
 }
 
-// FP64 symmetric W, one block per workgroup of eight waves (blocks of at most
-// kBlkNT tiles per edge): z = W x over the whole block, every stored tile read
-// from memory once per use inside the workgroup.  x (q x KC) is gathered into
-// LDS once.  Output tile a of the block takes the products with all nt input
-// tiles b: the stored tile (a, b) for b <= a, the transpose of (b, a) for
-// b > a (column runs straight into the A operand, as in k_rowcol_mfma64).
-// Wave w computes rows 16 (w % 4) .. + 15 of the output tiles a = w / 4,
-// w / 4 + 2, ..., accumulating each in registers over b and storing it; the
-// next product's tile rows are loaded while the current one is multiplied.
 constexpr int kBlkNT = 6;
 
 // Stages x = r[cols[row]][k0 .. k0 + KC) of one block (rows < q; zero rows up
@@ -597,45 +588,52 @@ __device__ __forceinline__ void stage_block_x(T (*xs)[KC + 1], const int32_t* __
     }
 }
 
-template <int KC>
-__global__ void __launch_bounds__(512) k_blk_mfma64(const int32_t* __restrict__ blocks,
-                                                    const int64_t* __restrict__ t_off,
-                                                    const int64_t* __restrict__ qv,
-                                                    const int64_t* __restrict__ ub_off,
-                                                    const int32_t* __restrict__ blk_cols,
-                                                    const double* __restrict__ W,
-                                                    const double* __restrict__ r, int k, int k0,
-                                                    double* __restrict__ z) {
+// Symmetric W (FP64, or its FP32 copy on the mixed path), one block per
+// workgroup of eight waves (blocks of at most kBlkNT tiles per edge): z = W x
+// over the whole block, every stored tile read from memory once per use
+// inside the workgroup.  x (q x KC) is gathered into LDS once.  Output tile a
+// of the block takes the products with all nt input tiles b: the stored tile
+// (a, b) for b <= a, the transpose of (b, a) for b > a (column runs straight
+// into the A operand, as in k_rowcol_mfma64).  Wave w computes rows
+// 16 (w % 4) .. + 15 of the output tiles a = w / 4, w / 4 + 2, ...,
+// accumulating each in registers over b and storing it; the next product's
+// tile rows are loaded while the current one is multiplied.  T is the type of
+// W, x in LDS and the matrix-core arithmetic; z is written in FP64.
+template <class T, int KC>
+__device__ __forceinline__ void blk_apply(T (*xs)[KC + 1], const int32_t* __restrict__ blocks,
+                                          const int64_t* __restrict__ t_off, const int64_t* __restrict__ qv,
+                                          const int64_t* __restrict__ ub_off, const int32_t* __restrict__ blk_cols,
+                                          const T* __restrict__ W, const double* __restrict__ r, int k, int k0,
+                                          double* __restrict__ z) {
     constexpr int NB = KC / 16;
-    __shared__ double xs[kBlkNT * kT][KC + 1];
     const int i = blocks[blockIdx.x];
     const int64_t q = qv[i];
     const int nt = (int)((q + kT - 1) / kT);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lr = lane & 15, g = lane >> 4;
     const int rg = w & 3, half = w >> 2;
-    const double* Wi = W + t_off[i];
+    const T* Wi = W + t_off[i];
     const int32_t* cols = blk_cols + ub_off[i];
     // this wave's products: (a, b) for a = half, half + 2, ..., b = 0 .. nt - 1
     const int na = (nt - half + 1) / 2;
     const int njobs = na * nt;
-    auto load_job = [&](int jb, double* v) {
+    auto load_job = [&](int jb, T* v) {
         const int a = half + 2 * (jb / nt), b = jb % nt;
         if (b <= a) {
             load16(Wi + ((int64_t)a * (a + 1) / 2 + b) * kTE + (16 * rg + lr) * kT + 16 * g, v);
         } else {
-            const double* T = Wi + ((int64_t)b * (b + 1) / 2 + a) * kTE + (16 * g) * kT + 16 * rg + lr;
+            const T* Tt = Wi + ((int64_t)b * (b + 1) / 2 + a) * kTE + (16 * g) * kT + 16 * rg + lr;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) v[s] = T[s * kT];
+            for (int s = 0; s < 16; ++s) v[s] = Tt[s * kT];
         }
     };
-    typedef Mfma<double>::acc_t acc_t;
+    typedef typename Mfma<T>::acc_t acc_t;
     acc_t Z[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) Z[nb][e] = 0.0;
-    double v[16], vn[16];
+        for (int e = 0; e < 4; ++e) Z[nb][e] = T(0);
+    T v[16], vn[16];
     if (njobs > 0) load_job(0, v);
     stage_block_x<KC>(xs, cols, r, q, k, k0);
     __syncthreads();  // x staged
@@ -645,7 +643,7 @@ __global__ void __launch_bounds__(512) k_blk_mfma64(const int32_t* __restrict__ 
         if (jb + 1 < njobs) load_job(jb + 1, vn);
         // all of the product's B operands from LDS first, so that the
         // matrix-core chain does not wait on each read
-        double xb[16][NB];
+        T xb[16][NB];
 #pragma unroll
         for (int s = 0; s < 16; ++s)
 #pragma unroll
@@ -654,20 +652,48 @@ __global__ void __launch_bounds__(512) k_blk_mfma64(const int32_t* __restrict__ 
 #pragma unroll
         for (int s = 0; s < 16; ++s)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<double>::mma(v[s], xb[s][nb], Z[nb]);
+            for (int nb = 0; nb < NB; ++nb) Z[nb] = Mfma<T>::mma(v[s], xb[s][nb], Z[nb]);
         if (b == nt - 1) {  // output tile a complete
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int64_t ga = (int64_t)a * kT + 16 * rg + Mfma<double>::out_row(lane, e);
-                    if (ga < q) zi[ga * k + 16 * nb + lr] = Z[nb][e];
-                    Z[nb][e] = 0.0;
+                    const int64_t ga = (int64_t)a * kT + 16 * rg + Mfma<T>::out_row(lane, e);
+                    if (ga < q) zi[ga * k + 16 * nb + lr] = (double)Z[nb][e];
+                    Z[nb][e] = T(0);
                 }
         }
 #pragma unroll
         for (int s = 0; s < 16; ++s) v[s] = vn[s];
     }
+}
+
+template <int KC>
+__global__ void __launch_bounds__(512) k_blk_mfma64(const int32_t* __restrict__ blocks,
+                                                    const int64_t* __restrict__ t_off,
+                                                    const int64_t* __restrict__ qv,
+                                                    const int64_t* __restrict__ ub_off,
+                                                    const int32_t* __restrict__ blk_cols,
+                                                    const double* __restrict__ W,
+                                                    const double* __restrict__ r, int k, int k0,
+                                                    double* __restrict__ z) {
+    __shared__ double xs[kBlkNT * kT][KC + 1];
+    blk_apply<double, KC>(xs, blocks, t_off, qv, ub_off, blk_cols, W, r, k, k0, z);
+}
+
+// The mixed path's single-pass local solves: the same product with the FP32
+// copy of W, FP32 operands and accumulation on the matrix cores.
+template <int KC>
+__global__ void __launch_bounds__(512) k_blk_w32(const int32_t* __restrict__ blocks,
+                                                 const int64_t* __restrict__ t_off,
+                                                 const int64_t* __restrict__ qv,
+                                                 const int64_t* __restrict__ ub_off,
+                                                 const int32_t* __restrict__ blk_cols,
+                                                 const float* __restrict__ W,
+                                                 const double* __restrict__ r, int k, int k0,
+                                                 double* __restrict__ z) {
+    __shared__ float xs[kBlkNT * kT][KC + 1];
+    blk_apply<float, KC>(xs, blocks, t_off, qv, ub_off, blk_cols, W, r, k, k0, z);
 }
 
 // FP32 triangular factor Y (mixed path), one block per workgroup of eight
@@ -1287,9 +1313,13 @@ int build_schwarz(Handle& h) {
     double *d_A = nullptr, *d_W = nullptr;
     RDD_TRY(dev_alloc(h, &d_A, (size_t)h.factor_elems));
     RDD_TRY(dev_alloc(h, &d_W, (size_t)h.factor_elems));
-    if (h.precision == RANN_MIXED)
+    if (h.precision == RANN_MIXED) {
         RDD_TRY(dev_alloc(h, &h.d_M32, (size_t)h.tile_elems));
-    else
+        int ntmax = 0;
+        for (int i = 0; i < J; ++i) ntmax = std::max(ntmax, (int)h.nt[i]);
+        // the single-pass FP32 local solves of narrow blocks apply W itself
+        if (ntmax <= kBlkNT) RDD_TRY(dev_alloc(h, &h.d_W32, (size_t)h.tile_elems));
+    } else
         RDD_TRY(dev_alloc(h, &h.d_M64, (size_t)h.tile_elems));
     if (h.d_G32) {
         // A_i from the FP32 Gram blocks, widened for the FP64 factorisation
@@ -1327,7 +1357,16 @@ int launch_precond_local(Handle& h, const ApplyPlan& pl, const double* r, int k,
         if (rem >= 16) {  // matrix cores, 32 or 16 right-hand sides per launch, no slots
             const int kc = rem >= 32 ? 32 : 16;
             float* u32 = reinterpret_cast<float*>(u1);
-            if (h.precision == RANN_MIXED && pl.max_nt <= kBlkNT && pl.n_blk_list > 0) {
+            if (h.precision == RANN_MIXED && h.d_W32 && pl.max_nt <= kBlkNT && pl.n_blk_list > 0) {
+                if (kc == 32)
+                    hipLaunchKernelGGL((k_blk_w32<32>), dim3((unsigned)pl.n_blk_list), dim3(512), 0, h.stream,
+                                       pl.d_blk_list, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_W32, r, k,
+                                       k0, ub);
+                else
+                    hipLaunchKernelGGL((k_blk_w32<16>), dim3((unsigned)pl.n_blk_list), dim3(512), 0, h.stream,
+                                       pl.d_blk_list, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_W32, r, k,
+                                       k0, ub);
+            } else if (h.precision == RANN_MIXED && pl.max_nt <= kBlkNT && pl.n_blk_list > 0) {
                 if (kc == 32)
                     hipLaunchKernelGGL((k_blk_mfma32<32>), dim3((unsigned)pl.n_blk_list), dim3(512), 0, h.stream,
                                        pl.d_blk_list, h.d_t_off, h.d_q, h.d_ub_off, pl.d_blk_cols, h.d_M32, r, k,
