@@ -928,16 +928,21 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
     double* rz = sc.take(k);
     double* rr = sc.take(k);
     double* bn2 = sc.take(k);
-    double* rres = sc.take(k);
     double* tol2v = sc.take(k);
     double* rhoB = sc.take(2 * (size_t)k);       // rho, double-buffered
     double* partA = sc.take((size_t)std::max<int64_t>(1, h.n_slab_tasks) * k);
     double* partB = sc.take((size_t)kRedMax * k);
     const int nC = (h.precond == RANN_PRECOND_NONE) ? 0 : gather_parts(h, k);  // 0: rgrid partials
     double* partC = sc.take((size_t)std::max(kRedMax, nC) * k);
-    int32_t* activeB = reinterpret_cast<int32_t*>(sc.take(2 * (size_t)k));  // activity, double-buffered
-    int32_t* iters = reinterpret_cast<int32_t*>(sc.take(k));
-    int32_t* flags = reinterpret_cast<int32_t*>(sc.take(4));
+    // the state the host reads after each window, in one block (one copy):
+    // recurrence residuals (k doubles), activity (2 k int32, double-buffered),
+    // iteration counts (k int32), flags (4 int32)
+    const size_t stat_doubles = 3 * (size_t)k + 4;
+    double* stat_dev = sc.take(stat_doubles);
+    double* rres = stat_dev;
+    int32_t* activeB = reinterpret_cast<int32_t*>(stat_dev + k);
+    int32_t* iters = reinterpret_cast<int32_t*>(stat_dev + 2 * (size_t)k);
+    int32_t* flags = reinterpret_cast<int32_t*>(stat_dev + 3 * (size_t)k);
     (void)rho; (void)pS; (void)alpha; (void)beta; (void)rz; (void)rr;
     int par = 0;
     int32_t* active = activeB;  // current buffer, follows par
@@ -1024,8 +1029,14 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
         return RANN_OK;
     };
     int window = 0;
+    // Window lengths: every iterations, shortened near the end to the
+    // iterations that the slowest active right-hand side still needs at the
+    // rate of its last window (plus one), so that few iterations run past
+    // convergence; windows shorter than every run eagerly.
+    std::vector<double> stat(stat_doubles), rprev(k, -1.0);
+    int next_nq = every, nq_prev = 0;
     while (true) {
-        const int nq = std::min(every, o.maxiter - it);
+        const int nq = std::min(next_nq, o.maxiter - it);
         // with the kernel timers on, one window in four runs eagerly with its
         // timers; the others run without timers (from the graph when allowed),
         // so that the timers' events do not slow the timed solve down
@@ -1089,10 +1100,33 @@ static int cg_core(Handle& h, const double* rhs, const double* Fs, int k, const 
         it += nq;
         active = activeB + (size_t)par * k;
         RDD_HIP(hipGetLastError());
-        int32_t fl[4];
-        RDD_TRY(download(h, act.data(), active, sizeof(int32_t) * k));
-        RDD_TRY(download(h, fl, flags, sizeof(fl)));
+        RDD_TRY(download(h, stat.data(), stat_dev, sizeof(double) * stat_doubles));
         RDD_HIP(hipStreamSynchronize(h.stream));
+        const int32_t* act_now = reinterpret_cast<const int32_t*>(stat.data() + k) + (size_t)par * k;
+        std::copy(act_now, act_now + k, act.begin());
+        const int32_t* fl = reinterpret_cast<const int32_t*>(stat.data() + 3 * (size_t)k);
+        {
+            int need = 0;
+            bool known = nq_prev > 0;
+            for (int t = 0; t < k && known; ++t) {
+                if (!act[t]) continue;
+                const double now = stat[t], before = rprev[t], tl = std::sqrt(tol2h[t]);
+                if (!(tl > 0.0 && now > tl && before > now)) {
+                    known = false;
+                    break;
+                }
+                const double rate = std::log(now / before) / nq_prev;  // per iteration, < 0
+                const double rem = std::ceil(std::log(tl / now) / rate);
+                if (!(rem < every)) {
+                    known = false;
+                    break;
+                }
+                need = std::max(need, (int)rem);
+            }
+            next_nq = known ? std::max(1, std::min(every, need + 1)) : every;
+            for (int t = 0; t < k; ++t) rprev[t] = stat[t];
+            nq_prev = nq;
+        }
         if (fl[1]) {
             set_error("NaN or Inf in the Krylov iteration");
             return RANN_ENAN;
