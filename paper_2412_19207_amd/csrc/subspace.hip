@@ -152,24 +152,34 @@ __global__ void __launch_bounds__(256) k_colscale(const int32_t* __restrict__ mv
 // memory); the shift is 11 (m s + s (s + 1)) u tr(S) when `shifted`.  Column k
 // is eliminated in one pass (each thread scales the pivot column's entries it
 // needs itself), one barrier per column.  A non-positive pivot sets flags[0].
+// L_true^{-1} comes from forward substitution organised by columns of L: once
+// rows 0 .. l of the inverse have all their updates, row l updates every
+// later row (a rank-one step over the whole lower triangle, one barrier per
+// column), and each row is divided by its pivot at the end.  Entries are
+// indexed by e = 64 r + c over the kSMax x kSMax square.
 __global__ void __launch_bounds__(kCT) k_chol_inv(const int32_t* __restrict__ mv, const int32_t* __restrict__ sv,
                                                   const int64_t* __restrict__ to, const double* __restrict__ S,
                                                   double* __restrict__ Rinv, int shifted, int32_t* __restrict__ flags) {
+    static_assert(kSMax == 64, "entries indexed by 64 r + c");
     __shared__ double L[kSMax][kSMax + 1];
+    __shared__ double X[kSMax][kSMax + 1];  // L_true^{-1}, lower
     __shared__ double red[kCT / 64];
     __shared__ double sdiag[kSMax];
-    __shared__ double sinv[kSMax];
     const int j = blockIdx.x;
     const int s = sv[j], m = mv[j];
     const double* Sj = S + to[j];
     double* Rj = Rinv + to[j];
     const int tid = threadIdx.x;
+    constexpr int kPer = kSMax * kSMax / kCT;  // entries per thread
     double tr = 0.0;
-    for (int e = tid; e < s * s; e += kCT) {
-        const int r = e / s, c = e % s;
-        const double v = Sj[e];
-        L[r][c] = v;
-        if (r == c) tr += v;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + kCT * u, r = e >> 6, c = e & 63;
+        if (r < s && c < s) {
+            const double v = Sj[r * s + c];
+            L[r][c] = v;
+            if (r == c) tr += v;
+        }
     }
     for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off);
     if ((tid & 63) == 0) red[tid >> 6] = tr;
@@ -186,38 +196,41 @@ __global__ void __launch_bounds__(kCT) k_chol_inv(const int32_t* __restrict__ mv
             dk = 1e-300;
         }
         const double inv = 1.0 / dk;  // L[r][c] -= L[r][k] L[c][k] / d_k
-        for (int e = tid; e < s * s; e += kCT) {
-            const int r = e / s, c = e % s;
-            if (c > k && c <= r) L[r][c] -= L[r][k] * L[c][k] * inv;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + kCT * u, r = e >> 6, c = e & 63;
+            if (c > k && c <= r && r < s) L[r][c] -= L[r][k] * L[c][k] * inv;
         }
         __syncthreads();
     }
     // the factor is L_true[r][k] = L[r][k] / sqrt(d_k), d_k = L[k][k]
     for (int k = tid; k < s; k += kCT) sdiag[k] = sqrt(L[k][k] > 0.0 ? L[k][k] : 1e-300);
     __syncthreads();
-    // the factor's entries L_true[r][c] = L[r][c] / sqrt(d_c), below the diagonal
-    for (int e = tid; e < s * s; e += kCT) {
-        const int r = e / s, c = e % s;
-        if (c < r) L[r][c] /= sdiag[c];
+    // the factor's entries L_true[r][c] = L[r][c] / sqrt(d_c) below the
+    // diagonal; X starts as the identity
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + kCT * u, r = e >> 6, c = e & 63;
+        if (r < s && c < r) L[r][c] /= sdiag[c];
+        X[r][c] = (r == c) ? 1.0 : 0.0;
     }
     __syncthreads();
-    // Rinv = L_true^{-T}: row c of Rinv is column c of L_true^{-1}.  Forward
-    // substitution row by row: step i finishes entry i of every column c <= i
-    // (one thread per column), the rows kept in the upper half of LDS rows
-    // (Linv[c][i] at Lt[c][i], i >= c, which the factor does not use)
-    for (int i = 0; i < s; ++i) {
-        for (int c = tid; c <= i; c += kCT) {
-            double acc = (i == c) ? 1.0 : 0.0;
-            for (int l = c; l < i; ++l) acc = fma(-L[i][l], (l == c ? sinv[c] : L[c][l]), acc);
-            const double v = acc / sdiag[i];
-            if (i == c) sinv[c] = v;
-            else L[c][i] = v;
+    // step l: row l of X is complete up to its division by the pivot; every
+    // row i > l takes X[i][c] -= L_true[i][l] X[l][c] / d_l for c <= l
+    for (int l = 0; l + 1 < s; ++l) {
+        const double invd = 1.0 / sdiag[l];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + kCT * u, i = e >> 6, c = e & 63;
+            if (i > l && i < s && c <= l) X[i][c] -= L[i][l] * (X[l][c] * invd);
         }
         __syncthreads();
     }
-    for (int e = tid; e < s * s; e += kCT) {
-        const int r = e / s, c = e % s;
-        Rj[e] = (c < r) ? 0.0 : (c == r ? sinv[r] : L[r][c]);
+    // Rinv = L_true^{-T}: Rinv[r][c] = X[c][r] / d_c for c >= r
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = tid + kCT * u, r = e >> 6, c = e & 63;
+        if (r < s && c < s) Rj[r * s + c] = (c < r) ? 0.0 : X[c][r] / sdiag[c];
     }
 }
 
