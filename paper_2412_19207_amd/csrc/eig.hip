@@ -568,14 +568,27 @@ __device__ bool chol_qr(const double* __restrict__ Zin, double* __restrict__ Zou
     }
     __syncthreads();
     if (fail) return false;
-    // X = L^{-1} (lower, diagonal included) into the lower triangle; column c per thread
-    for (int c = tid; c < p; c += kPT) {
-        Gs[c * ldg + c] = 1.0 / ldiag[c];
-        for (int r = c + 1; r < p; ++r) {
-            double sacc = 0.0;
-            for (int k = c; k < r; ++k) sacc = fma(Gs[k * ldg + r], Gs[k * ldg + c], sacc);  // L[r][k] X[k][c]
-            Gs[r * ldg + c] = -sacc / ldiag[r];
+    // X = L^{-1} (lower, diagonal included) into the lower triangle, by forward
+    // substitution organised by columns of L: once rows 0 .. l of X have all
+    // their updates, row l (divided by its pivot) updates every later row, one
+    // barrier per column; each row is divided by its pivot at the end
+    for (int e = tid; e < p * p; e += kPT) {
+        const int r = e / p, c = e % p;
+        if (c <= r) Gs[r * ldg + c] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int l = 0; l + 1 < p; ++l) {
+        const double il = 1.0 / ldiag[l];
+        const int w = l + 1, n = (p - 1 - l) * w;
+        for (int e = tid; e < n; e += kPT) {
+            const int i = l + 1 + e / w, c = e % w;
+            Gs[i * ldg + c] -= Gs[l * ldg + i] * (Gs[l * ldg + c] * il);  // L[i][l] X[l][c]
         }
+        __syncthreads();
+    }
+    for (int e = tid; e < p * p; e += kPT) {
+        const int r = e / p, c = e % p;
+        if (c <= r) Gs[r * ldg + c] /= ldiag[r];
     }
     __syncthreads();
     // Q = X Z, kStg columns at a time
