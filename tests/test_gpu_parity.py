@@ -565,6 +565,25 @@ def test_bitwise_repeatable(case_small2d):
     assert torch.equal(W1, W2)
 
 
+@pytest.mark.parametrize("k", [2, 32])
+def test_check_windows_do_not_change_the_iterates(k):
+    """The host's check cadence, and the windows it shortens near convergence,
+    decide only when the host looks at the recurrence: every cadence gives the
+    same iterates bit for bit and the same per-right-hand-side counts."""
+    _need_gpu()
+    prob = wl.small2d(k=k)
+    s = binding.Solver(prob, device=DEV)
+    s.pca(1e-10)
+    F = torch.as_tensor(prob.F, device=DEV)
+    runs = [s.solve(F, tol=1e-10, check_every=c) for c in (1, 7, 10)]
+    for _, info in runs:
+        assert info["status"] == 0
+    W0, i0 = runs[0]
+    for W, info in runs[1:]:
+        assert torch.equal(W, W0)
+        assert np.array_equal(info["rhs_iterations"], i0["rhs_iterations"])
+
+
 @pytest.mark.parametrize("method", ["cg", "bicg", "gmres"])
 @pytest.mark.parametrize("k", [4, 8, 64])
 def test_power_of_two_rhs_reductions(method, k):
