@@ -55,9 +55,12 @@ extern "C" {
  * H and the residual are FP64 in both) */
 #define RANN_FP64          0
 #define RANN_MIXED         1    /* the local inverses are stored as FP32 triangular
-                                   factors Y_i (A_i^{-1} = Y_i^T Y_i) and applied in
-                                   FP32 on the matrix cores for k >= 16 right-hand
-                                   sides (FP64 accumulation below that) */
+                                   factors Y_i (A_i^{-1} = Y_i^T Y_i) and, when no
+                                   block is wider than 6 tiles of 64, also as
+                                   A_i^{-1} rounded to FP32; for k >= 16 right-hand
+                                   sides they are applied in FP32 on the matrix
+                                   cores (A_i^{-1} in one pass where it is stored),
+                                   with FP64 accumulation below that */
 
 /* Schwarz blocks: which subdomains' columns block i selects (Sec. 3, R_i) */
 #define RANN_STENCIL_SELF  0    /* subdomain i only (block Jacobi) */
