@@ -283,9 +283,12 @@ __global__ void __launch_bounds__(256) k_nrm_slab(const int2* __restrict__ tasks
 // are issued before its partial sums are added, so that the chain of
 // dependent memory rounds is: those loads, then the x rows (all of a sweep's
 // in flight together: absent columns load row 0 and are discarded).  UPD: x
-// is the direction p_new = z + beta p_prev of the previous iteration.
-template <int KC, bool UPD>
-__global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks,
+// is the direction p_new = z + beta p_prev of the previous iteration.  P2
+// (KC = 32, k even): lane lr of the B operand takes the right-hand sides 2 lr
+// and 2 lr + 1 (one 16-byte load for both column blocks) instead of lr and
+// lr + 16.
+template <int KC, bool UPD, bool P2>
+__global__ void __launch_bounds__(256, 2) k_nrm_mfma(const int2* __restrict__ tasks,
                                                   const int32_t* __restrict__ p,
                                                   const int64_t* __restrict__ col_off,
                                                   const int64_t* __restrict__ Nt_off,
@@ -298,6 +301,9 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
     constexpr int NB = KC / 16;
     constexpr int kOwn = 16 * KC / 256;  // own-row entries per thread
     static_assert(kSlabRows == 16, "one 16-row MFMA block per task");
+    static_assert(!P2 || NB == 2, "paired columns need two column blocks");
+    // right-hand side (within the chunk) of column block nb, lane lr
+    auto colof = [](int nb, int lr) { return P2 ? NB * lr + nb : 16 * nb + lr; };
     __shared__ double red[4][16][KC + 1];
     __shared__ double dsh[256];
     __shared__ double beta_s[KC], rz_s[KC], rr_s[KC];
@@ -325,22 +331,14 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
         av[u] = (c00 / 4 + u < nq4) ? At[(c00 / 4 + u) * 64 + lane] : 0.0;
     }
     const int t = threadIdx.x % KC;
-    double own_a[kOwn], own_b[kOwn];
-#pragma unroll
-    for (int v = 0; v < kOwn; ++v) {
-        const int rr = threadIdx.x / KC + (256 / KC) * v;
-        const int64_t gi = (col_off[j] + (r0 + rr < pj ? r0 + rr : pj - 1)) * k + k0 + t;
-        own_a[v] = UPD ? pu.pprev[gi] : x[gi];
-        own_b[v] = UPD ? pu.z[gi] : 0.0;
-    }
     double bet[NB];
     bool act[NB];
     if (UPD) {
         pupd_begin(pu, k, k0, KC, beta_s, act_s, rz_s, rr_s, dsh);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            bet[nb] = beta_s[16 * nb + lr];
-            act[nb] = act_s[16 * nb + lr] != 0;
+            bet[nb] = beta_s[colof(nb, lr)];
+            act[nb] = act_s[colof(nb, lr)] != 0;
         }
     }
     const double* xa_src = UPD ? pu.pprev : x;
@@ -351,23 +349,41 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[nb][e] = 0.0;
     for (int64_t c0 = c00; c0 < Q; c0 += 256) {
-        // the x rows of this sweep
+        // the x rows of this sweep (absent columns: bit u of live clear)
+        uint32_t live = 0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) live |= (ci[u] >= 0 ? 1u : 0u) << u;
         double bv[16][NB], zb[UPD ? 16 : 1][NB];
+        if constexpr (P2) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const int64_t gi = (int64_t)(ci[u] >= 0 ? ci[u] : 0) * k + k0 + 16 * nb + lr;
-                bv[u][nb] = xa_src[gi];
-                if (UPD) zb[u][nb] = pu.z[gi];
+            for (int u = 0; u < 16; ++u) {
+                const int64_t gi = (int64_t)(ci[u] >= 0 ? ci[u] : 0) * k + k0 + 2 * lr;
+                const double2 va = *reinterpret_cast<const double2*>(xa_src + gi);
+                bv[u][0] = va.x;
+                bv[u][1] = va.y;
+                if (UPD) {
+                    const double2 vz = *reinterpret_cast<const double2*>(pu.z + gi);
+                    zb[u][0] = vz.x;
+                    zb[u][1] = vz.y;
+                }
             }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int64_t gi = (int64_t)(ci[u] >= 0 ? ci[u] : 0) * k + k0 + 16 * nb + lr;
+                    bv[u][nb] = xa_src[gi];
+                    if (UPD) zb[u][nb] = pu.z[gi];
+                }
+        }
 #pragma unroll
         for (int u = 0; u < 16; ++u)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 double b = bv[u][nb];
                 if (UPD && act[nb]) b = fma(bet[nb], b, zb[u][nb]);
-                bv[u][nb] = ci[u] >= 0 ? b : 0.0;
+                bv[u][nb] = ((live >> u) & 1u) ? b : 0.0;
             }
 #pragma unroll
         for (int u = 0; u < 16; ++u)
@@ -384,10 +400,20 @@ __global__ void __launch_bounds__(256) k_nrm_mfma(const int2* __restrict__ tasks
             }
         }
     }
+    // the own rows' entries of x (or of p_prev and z), loaded while the
+    // matrix-core chain runs
+    double own_a[kOwn], own_b[kOwn];
+#pragma unroll
+    for (int v = 0; v < kOwn; ++v) {
+        const int rr = threadIdx.x / KC + (256 / KC) * v;
+        const int64_t gi = (col_off[j] + (r0 + rr < pj ? r0 + rr : pj - 1)) * k + k0 + t;
+        own_a[v] = UPD ? pu.pprev[gi] : x[gi];
+        own_b[v] = UPD ? pu.z[gi] : 0.0;
+    }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) red[w][Mfma<double>::out_row(lane, e)][16 * nb + lr] = acc[nb][e];
+        for (int e = 0; e < 4; ++e) red[w][Mfma<double>::out_row(lane, e)][colof(nb, lr)] = acc[nb][e];
     __syncthreads();
     double dotv = 0.0;
 #pragma unroll
@@ -552,15 +578,17 @@ int launch_normal(Handle& h, const double* x, int k, double* s, double* part, co
         if (rem >= 16) {  // matrix cores, 32 or 16 right-hand sides per launch
             const int kc = rem >= 32 ? 32 : 16;
             if (h.n_slab_tasks) {
-#define RDD_NM(KCV, UPDV)                                                                              \
-    hipLaunchKernelGGL((k_nrm_mfma<KCV, UPDV>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream,     \
-                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_Nt_off, h.d_N_coff, h.d_N_cols, h.d_Nt, x, k, \
+#define RDD_NM(KCV, UPDV, P2V)                                                                         \
+    hipLaunchKernelGGL((k_nrm_mfma<KCV, UPDV, P2V>), dim3((unsigned)h.n_slab_tasks), dim3(256), 0, h.stream, \
+                       h.d_slab_tasks, h.d_p, h.d_col_off, h.d_Nt_off, h.d_N_coff, h.d_N_cols, h.d_Nt, x, k,  \
                        k0, s, part, pu)
                 const bool upd = pu.pprev != nullptr;
-                if (kc == 32) {
-                    if (upd) RDD_NM(32, true); else RDD_NM(32, false);
+                if (kc == 32 && k % 2 == 0) {  // 16-byte loads of right-hand-side pairs
+                    if (upd) RDD_NM(32, true, true); else RDD_NM(32, false, true);
+                } else if (kc == 32) {
+                    if (upd) RDD_NM(32, true, false); else RDD_NM(32, false, false);
                 } else {
-                    if (upd) RDD_NM(16, true); else RDD_NM(16, false);
+                    if (upd) RDD_NM(16, true, false); else RDD_NM(16, false, false);
                 }
 #undef RDD_NM
             }
