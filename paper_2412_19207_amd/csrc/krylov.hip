@@ -613,10 +613,10 @@ __global__ void __launch_bounds__(256) k_gather_dot(int64_t P, int k, int identi
 // The Schwarz sum by subdomain: the p_j k entries of z that belong to subdomain
 // j are the weighted sum of contiguous segments of the block results, one per
 // block that uses j (in block order, as the gather lists add them).
-// Workgroup (j, y) of a grid of J Y (numbered by XCD) takes the entries [y E, (y + 1) E) of
-// subdomain j with E = 4 L, L = (256 / k) k: thread x < L the entries
-// y E + x + L v, v < 4, all of right-hand side x % k.  With part, the
-// workgroup's partials of <r, z> go to part[(j Y + y) k + t].
+// Task (j, y) of J Y (tasks numbered by XCD, xcd_task) takes the entries
+// [y E, (y + 1) E) of subdomain j with E = 4 L, L = (256 / k) k: thread x < L
+// the entries y E + x + L v, v < 4, all of right-hand side x % k.  With part,
+// workgroup b's partials of <r, z> go to part[b k + t].
 __global__ void __launch_bounds__(256) k_gather_seg(int k, int Y, const int32_t* __restrict__ pv,
                                                     const int64_t* __restrict__ col_off,
                                                     const int64_t* __restrict__ seg_off,
